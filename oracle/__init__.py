@@ -1,0 +1,185 @@
+"""ctypes wrapper of the plain CPU oracle (``sba_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by
+the CPU-baseline leg of the benchmark -- never by the GPU library or its
+binding.  See the header of ``sba_oracle.c`` for the definitions it follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sba_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+_u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+_u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+
+
+def build(extra_flags=()) -> str:
+    """Compile the oracle with gcc (plain C, OpenMP)."""
+    cmd = ["gcc", "-O2", "-std=gnu11", "-Wall", "-Wextra", "-fopenmp", "-fPIC", "-shared",
+           *extra_flags, "-o", _LIB + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    L = C.CDLL(_LIB)
+    L.orc_cell_side.restype = C.c_int64
+    L.orc_cell_side.argtypes = [C.c_int64]
+    L.orc_raster_brute.restype = C.c_int
+    L.orc_raster_brute.argtypes = [C.c_int32, _i32p, _i64p, _i32p, C.c_int64, C.c_int64,
+                                   C.c_int64, C.c_int64, C.c_int64, _u8p]
+    L.orc_build.restype = C.c_void_p
+    L.orc_build.argtypes = [C.c_int32, _i32p, _i64p, _i32p, C.c_int64]
+    L.orc_free.restype = None
+    L.orc_free.argtypes = [C.c_void_p]
+    L.orc_cell_side_of.restype = C.c_int64
+    L.orc_cell_side_of.argtypes = [C.c_void_p]
+    L.orc_n_intervals.restype = C.c_int64
+    L.orc_n_intervals.argtypes = [C.c_void_p]
+    L.orc_export_intervals.restype = None
+    L.orc_export_intervals.argtypes = [C.c_void_p, _i32p, _i64p, _i64p, _i64p]
+    L.orc_cell_set.restype = C.c_int
+    L.orc_cell_set.argtypes = [C.c_void_p, C.c_int64, C.c_int64, _i32p, C.c_int]
+    for name in ("orc_aggregate", "orc_exact_join"):
+        f = getattr(L, name)
+        f.restype = C.c_int
+        f.argtypes = [C.c_void_p, _i32p, C.c_void_p, C.c_int64, _u64p, C.c_void_p, C.c_int]
+    L.orc_invariant.restype = C.c_int
+    L.orc_invariant.argtypes = [C.c_void_p, _i32p, C.c_int64, _i64p, C.c_int]
+    L.orc_invariant_all.restype = C.c_int
+    L.orc_invariant_all.argtypes = [C.c_void_p, _i32p, C.c_int64, _i64p]
+    L.orc_hilbert_d.restype = C.c_uint64
+    L.orc_hilbert_d.argtypes = [C.c_int, C.c_int64, C.c_int64]
+    L.orc_hilbert_runs.restype = C.c_int
+    L.orc_hilbert_runs.argtypes = [C.c_void_p, C.c_int, _u64p, _i64p, _i32p, C.c_int64,
+                                   C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    _lib = L
+    return L
+
+
+def _poly_arrays(polys):
+    return (np.ascontiguousarray(polys.ring_off, np.int32),
+            np.ascontiguousarray(polys.vert_off, np.int64),
+            np.ascontiguousarray(polys.xy, np.int32))
+
+
+def cell_side(eps: int) -> int:
+    """Largest s with 2 s^2 <= eps^2 (0 if eps is outside [2, 2^28])."""
+    return int(lib().orc_cell_side(int(eps)))
+
+
+def raster_brute(polys, s: int, i0: int, j0: int, nw: int, nh: int) -> np.ndarray:
+    """Per-polygon cell classes over a window: uint8 [P, nh, nw],
+    2 = boundary cell, 1 = interior cell, 0 = neither.  Definition form."""
+    ro, vo, xy = _poly_arrays(polys)
+    out = np.zeros(polys.n_polys * nh * nw, np.uint8)
+    rc = lib().orc_raster_brute(polys.n_polys, ro, vo, xy, s, i0, j0, nw, nh, out)
+    if rc:
+        raise ValueError("orc_raster_brute rejected its input")
+    return out.reshape(polys.n_polys, nh, nw)
+
+
+def hilbert_d(L: int, i: int, j: int) -> int:
+    return int(lib().orc_hilbert_d(L, int(i), int(j)))
+
+
+class Approx:
+    """The oracle's A(P) for every polygon, held as sorted row intervals."""
+
+    def __init__(self, polys, eps: int):
+        ro, vo, xy = _poly_arrays(polys)
+        self._keep = (ro, vo, xy)
+        self.n_polys = polys.n_polys
+        self.eps = int(eps)
+        self._h = lib().orc_build(polys.n_polys, ro, vo, xy, int(eps))
+        if not self._h:
+            raise ValueError("oracle rejected the polygons or eps")
+        self.s = int(lib().orc_cell_side_of(self._h))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_free(h)
+            self._h = None
+
+    def intervals(self):
+        """(poly, row, x0, x1): cells [x0, x1) of row `row` are in A(poly)."""
+        n = int(lib().orc_n_intervals(self._h))
+        p = np.zeros(n, np.int32)
+        r = np.zeros(n, np.int64)
+        a = np.zeros(n, np.int64)
+        b = np.zeros(n, np.int64)
+        lib().orc_export_intervals(self._h, p, r, a, b)
+        return p, r, a, b
+
+    def cell_set(self, i: int, j: int) -> list:
+        buf = np.zeros(max(1, self.n_polys), np.int32)
+        n = lib().orc_cell_set(self._h, int(i), int(j), buf, buf.shape[0])
+        return buf[:n].tolist()
+
+    def _agg(self, fn, xy, vals, nthreads):
+        xy = np.ascontiguousarray(xy, np.int32)
+        n = xy.shape[0] // 2
+        counts = np.zeros(max(1, self.n_polys), np.uint64)
+        sums = np.zeros(max(1, self.n_polys), np.int64)
+        vptr = None
+        if vals is not None:
+            vals = np.ascontiguousarray(vals, np.int64)
+            assert vals.shape[0] == n
+            vptr = vals.ctypes.data
+        rc = fn(self._h, xy, vptr, n, counts, sums.ctypes.data if vals is not None else None,
+                int(nthreads))
+        if rc < 0:
+            raise MemoryError("oracle aggregate failed")
+        self.threads_used = rc
+        return counts[:self.n_polys], (sums[:self.n_polys] if vals is not None else None)
+
+    def aggregate(self, xy, vals=None, nthreads: int = 0):
+        """Approximate per-polygon COUNT and SUM (the GPU parity target)."""
+        return self._agg(lib().orc_aggregate, xy, vals, nthreads)
+
+    def exact(self, xy, vals=None, nthreads: int = 0):
+        """Exact per-polygon COUNT and SUM by the crossing-number rule."""
+        return self._agg(lib().orc_exact_join, xy, vals, nthreads)
+
+    def invariant(self, xy, nthreads: int = 0, exhaustive: bool = False) -> dict:
+        xy = np.ascontiguousarray(xy, np.int32)
+        out = np.zeros(4, np.int64)
+        if exhaustive:
+            lib().orc_invariant_all(self._h, xy, xy.shape[0] // 2, out)
+        else:
+            lib().orc_invariant(self._h, xy, xy.shape[0] // 2, out, int(nthreads))
+        return {"differ": int(out[0]), "far": int(out[1]), "false_neg": int(out[2]),
+                "inside": int(out[3])}
+
+    def hilbert_runs(self, L: int):
+        """Maximal runs over [0, 4^L): (starts uint64, run_off int64, run_ids int32)."""
+        cap_r, cap_i = 1024, 1024
+        while True:
+            st = np.zeros(cap_r, np.uint64)
+            ro = np.zeros(cap_r + 1, np.int64)
+            ri = np.zeros(cap_i, np.int32)
+            nr, ni = C.c_int64(0), C.c_int64(0)
+            rc = lib().orc_hilbert_runs(self._h, L, st, ro, ri, cap_r, cap_i,
+                                        C.byref(nr), C.byref(ni))
+            if rc == 0:
+                return st[:nr.value], ro[:nr.value + 1], ri[:ni.value]
+            if rc < -1:
+                raise ValueError("orc_hilbert_runs: level out of range")
+            cap_r, cap_i = nr.value + 1, max(1, ni.value)

@@ -1,0 +1,360 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: hand-derived
+rasterisations (tests/golden), closed forms for rectangles and right
+triangles, the definition evaluated cell by cell (brute form), the
+eps-invariant of Sec. 2.2 checked with exact distances, the partition
+property, nested grids, and the Hilbert curve's defining properties.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+import yaml
+
+from gen import polygons_from_rings, star_polygons, voronoi_partition, uniform_points
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_examples.yaml")
+
+
+def lattice(lo, hi):
+    xs, ys = np.meshgrid(np.arange(lo, hi), np.arange(lo, hi))
+    return np.c_[xs.ravel(), ys.ravel()].astype(np.int32).ravel()
+
+
+def member_from_intervals(A, p, i0, j0, nw, nh):
+    m = np.zeros((nh, nw), bool)
+    P, R, X0, X1 = A.intervals()
+    sel = P == p
+    for r, a, b in zip(R[sel], X0[sel], X1[sel]):
+        if j0 <= r < j0 + nh:
+            a2, b2 = max(a, i0), min(b, i0 + nw)
+            if a2 < b2:
+                m[r - j0, a2 - i0:b2 - i0] = True
+    return m
+
+
+def cell_window(polys, s, pad=2):
+    xy = polys.xy.reshape(-1, 2).astype(np.int64)
+    i0 = int(np.floor(xy[:, 0].min() / s)) - pad
+    j0 = int(np.floor(xy[:, 1].min() / s)) - pad
+    i1 = int(np.floor(xy[:, 0].max() / s)) + pad
+    j1 = int(np.floor(xy[:, 1].max() / s)) + pad
+    return i0, j0, i1 - i0 + 1, j1 - j0 + 1
+
+
+# ---------------------------------------------------------------- cell side
+
+@pytest.mark.parametrize("eps,s", [(2, 1), (3, 2), (5, 3), (64, 45), (100, 70), (1000, 707),
+                                   (10000, 7071), (15000, 10606), (1 << 28, 189812531)])
+def test_cell_side_values(orc, eps, s):
+    assert orc.cell_side(eps) == s
+    # defining inequality: 2 s^2 <= eps^2 < 2 (s+1)^2
+    assert 2 * s * s <= eps * eps < 2 * (s + 1) * (s + 1)
+
+
+def test_cell_side_tiny_grid_matches_workload_text(orc):
+    # eps = 64 units over [0, 65536): a grid of about 1450^2 cells
+    s = orc.cell_side(64)
+    assert -(-65536 // s) == 1457
+
+
+def test_cell_side_rejects(orc):
+    assert orc.cell_side(1) == 0
+    assert orc.cell_side(0) == 0
+    assert orc.cell_side((1 << 28) + 1) == 0
+
+
+# ---------------------------------------------------------------- golden
+
+def _golden():
+    with open(GOLDEN) as f:
+        return yaml.safe_load(f)["examples"]
+
+
+@pytest.mark.parametrize("ex", _golden(), ids=lambda e: e["name"])
+def test_hand_examples(orc, ex):
+    polys = polygons_from_rings([[np.array(r) for r in ex["rings"]]])
+    s = orc.cell_side(ex["eps"])
+    assert s == ex["s"]
+    i0, j0, nw, nh = -3, -3, 12, 12
+    br = orc.raster_brute(polys, s, i0, j0, nw, nh)[0]
+    bset = {(i0 + i, j0 + j) for j, i in zip(*np.nonzero(br == 2))}
+    iset = {(i0 + i, j0 + j) for j, i in zip(*np.nonzero(br == 1))}
+    assert bset == {tuple(c) for c in ex["boundary"]}
+    assert iset == {tuple(c) for c in ex["interior"]}
+    A = orc.Approx(polys, ex["eps"])
+    m = member_from_intervals(A, 0, i0, j0, nw, nh)
+    assert {(i0 + i, j0 + j) for j, i in zip(*np.nonzero(m))} == bset | iset
+    xy = lattice(*ex["window"])
+    c, _ = A.aggregate(xy)
+    e, _ = A.exact(xy)
+    assert int(c[0]) == ex["approx_count"]
+    assert int(e[0]) == ex["exact_count"]
+
+
+# ---------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("s,a,b,c,d", [(5, 0, 35, 0, 40), (5, -15, 20, 10, 25), (3, 3, 6, -9, 30),
+                                       (7, 14, 70, 7, 21)])
+def test_rectangle_closed_form(orc, s, a, b, c, d):
+    # cell-aligned rectangle [a,b]x[c,d]: exact lattice count (b-a)(d-c) (half-open
+    # crossing rule keeps [a,b)x[c,d)); conservative raster adds one cell ring:
+    # (b-a+2s)(d-c+2s)
+    eps = {3: 5, 5: 8, 7: 10}[s]
+    assert orc.cell_side(eps) == s
+    polys = polygons_from_rings([[np.array([[a, c], [b, c], [b, d], [a, d]])]])
+    xy = lattice(min(a, c) - 3 * s, max(b, d) + 3 * s)
+    A = orc.Approx(polys, eps)
+    cnt, _ = A.aggregate(xy)
+    ex, _ = A.exact(xy)
+    assert int(ex[0]) == (b - a) * (d - c)
+    assert int(cnt[0]) == (b - a + 2 * s) * (d - c + 2 * s)
+
+
+@pytest.mark.parametrize("s,m,rot", [(5, 10, 0), (3, 7, 1), (4, 5, 2), (2, 9, 3)])
+def test_right_triangle_closed_form(orc, s, m, rot):
+    # legs L = m s at a cell-aligned corner: exact L(L+1)/2 for the corner at the
+    # origin with legs along +x,+y; approx s^2 [(m+1)(m+2)/2 + 2m + 3] (cells whose
+    # closed square meets the triangle).  Other orientations: the approximate count
+    # is invariant under the grid's symmetries that map cells to cells.
+    eps = {2: 3, 3: 5, 4: 6, 5: 8}[s]
+    assert orc.cell_side(eps) == s
+    L = m * s
+    tri = np.array([[0, 0], [L, 0], [0, L]])
+    R = [np.array([[1, 0], [0, 1]]), np.array([[0, -1], [1, 0]]),
+         np.array([[-1, 0], [0, -1]]), np.array([[0, 1], [-1, 0]])][rot]
+    v = tri @ R.T
+    polys = polygons_from_rings([[v]])
+    xy = lattice(-L - 3 * s, L + 3 * s)
+    A = orc.Approx(polys, eps)
+    cnt, _ = A.aggregate(xy)
+    assert int(cnt[0]) == s * s * ((m + 1) * (m + 2) // 2 + 2 * m + 3)
+    if rot == 0:
+        ex, _ = A.exact(xy)
+        assert int(ex[0]) == L * (L + 1) // 2
+
+
+# ---------------------------------------------------------------- brute vs scan
+
+def _hand_shapes():
+    S = []
+    S.append([[[0, 0], [30, 0], [30, 10], [10, 10], [10, 20], [30, 20], [30, 30], [0, 30]]])  # C
+    S.append([[[0, 0], [40, 0], [20, 1], [20, 30]]])                                      # spike
+    S.append([[[0, 0], [10, 0], [20, 0], [20, 10], [20, 20], [0, 20]]])                   # collinear
+    S.append([[[5, 5], [25, 5], [25, 5], [15, 25]]])                                      # repeated vertex
+    S.append([[[-17, -9], [12, -9], [12, 6], [-17, 6]]])                                  # negative coords
+    S.append([[[0, 0], [30, 0], [30, 30], [0, 30]], [[10, 10], [20, 10], [20, 20], [10, 20]]])  # hole
+    S.append([[[0, 0], [10, 0], [10, 10], [0, 10]], [[20, 0], [30, 0], [30, 10], [20, 10]]])    # two parts
+    S.append([[[3, 3], [3, 3], [9, 3]]])                                                  # degenerate (zero area)
+    S.append([[[0, 0], [24, 12], [0, 24], [12, 12]]])                                     # arrow, concave
+    S.append([[[1, 2], [2, 1], [3, 2], [2, 3]]])                                          # tiny diamond
+    return [[np.array(r) for r in p] for p in S]
+
+
+@pytest.mark.parametrize("eps", [2, 3, 5, 8, 9, 15])
+def test_scan_form_equals_definition_hand(orc, eps):
+    s = orc.cell_side(eps)
+    polys = polygons_from_rings(_hand_shapes())
+    i0, j0, nw, nh = cell_window(polys, s)
+    br = orc.raster_brute(polys, s, i0, j0, nw, nh)
+    A = orc.Approx(polys, eps)
+    for p in range(polys.n_polys):
+        np.testing.assert_array_equal(member_from_intervals(A, p, i0, j0, nw, nh), br[p] > 0,
+                                      err_msg=f"polygon {p}")
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_scan_form_equals_definition_random_stars(orc, seed):
+    rng = np.random.default_rng(seed)
+    polys = star_polygons(4, int(rng.integers(3, 12)), 5.0, 60.0, 200, 1000 + seed)
+    for eps in (2, 4, 7, 13):
+        s = orc.cell_side(eps)
+        i0, j0, nw, nh = cell_window(polys, s)
+        br = orc.raster_brute(polys, s, i0, j0, nw, nh)
+        A = orc.Approx(polys, eps)
+        for p in range(polys.n_polys):
+            np.testing.assert_array_equal(member_from_intervals(A, p, i0, j0, nw, nh), br[p] > 0)
+
+
+def test_scan_form_grid_aligned_edges(orc):
+    # vertices on cell corners and edges along grid lines, s = 4
+    eps = 6
+    s = orc.cell_side(eps)
+    assert s == 4
+    rings = [[np.array([[0, 0], [16, 0], [16, 8], [8, 8], [8, 16], [0, 16]])],
+             [np.array([[4, 4], [12, 12], [4, 12]])],
+             [np.array([[-8, 20], [8, 20], [0, 28]])]]
+    polys = polygons_from_rings(rings)
+    i0, j0, nw, nh = cell_window(polys, s)
+    br = orc.raster_brute(polys, s, i0, j0, nw, nh)
+    A = orc.Approx(polys, eps)
+    for p in range(polys.n_polys):
+        np.testing.assert_array_equal(member_from_intervals(A, p, i0, j0, nw, nh), br[p] > 0)
+
+
+# ---------------------------------------------------------------- aggregate
+
+def test_aggregate_equals_brute_membership(orc):
+    rng = np.random.default_rng(5)
+    polys = star_polygons(6, 9, 10.0, 70.0, 150, 77)
+    eps = 9
+    s = orc.cell_side(eps)
+    i0, j0, nw, nh = cell_window(polys, s)
+    br = orc.raster_brute(polys, s, i0, j0, nw, nh) > 0
+    xy = rng.integers(-30, 200, size=2 * 20000).astype(np.int32)
+    vals = rng.integers(-1000, 1000, size=20000).astype(np.int64)
+    A = orc.Approx(polys, eps)
+    cnt, sm = A.aggregate(xy, vals, nthreads=3)
+    ci = np.floor_divide(xy[0::2].astype(np.int64), s) - i0
+    cj = np.floor_divide(xy[1::2].astype(np.int64), s) - j0
+    ok = (ci >= 0) & (ci < nw) & (cj >= 0) & (cj < nh)
+    for p in range(polys.n_polys):
+        m = np.zeros(ci.shape, bool)
+        m[ok] = br[p][cj[ok], ci[ok]]
+        assert int(cnt[p]) == int(m.sum())
+        assert int(sm[p]) == int(vals[m].sum())
+
+
+def test_aggregate_thread_count_independent(orc):
+    rng = np.random.default_rng(1)
+    polys = star_polygons(10, 20, 50.0, 400.0, 2000, 9)
+    xy = rng.integers(0, 2000, size=2 * 100000).astype(np.int32)
+    vals = rng.integers(1, 10000, size=100000).astype(np.int64)
+    A = orc.Approx(polys, 20)
+    c1, s1 = A.aggregate(xy, vals, nthreads=1)
+    c4, s4 = A.aggregate(xy, vals, nthreads=4)
+    np.testing.assert_array_equal(c1, c4)
+    np.testing.assert_array_equal(s1, s4)
+
+
+def test_empty_inputs(orc):
+    polys = star_polygons(3, 8, 10.0, 50.0, 300, 2)
+    A = orc.Approx(polys, 10)
+    c, s = A.aggregate(np.zeros(0, np.int32), np.zeros(0, np.int64))
+    assert c.sum() == 0 and s.sum() == 0
+    empty = polygons_from_rings([])
+    A0 = orc.Approx(empty, 10)
+    c, _ = A0.aggregate(np.array([1, 2], np.int32))
+    assert c.shape == (0,)
+
+
+# ---------------------------------------------------------------- invariant
+
+@pytest.mark.parametrize("eps", [2, 6, 23, 64])
+def test_eps_invariant_stars(orc, eps):
+    rng = np.random.default_rng(eps)
+    polys = star_polygons(8, 16, 30.0, 300.0, 1000, 31 + eps)
+    xy = rng.integers(-300, 1300, size=2 * 60000).astype(np.int32)
+    A = orc.Approx(polys, eps)
+    inv = A.invariant(xy, exhaustive=True)
+    assert inv["far"] == 0
+    assert inv["false_neg"] == 0
+    assert inv["differ"] > 0
+    inv2 = A.invariant(xy)
+    assert inv2 == inv
+
+
+def test_invariant_detects_planted_far_point(orc):
+    # a point farther than eps from the boundary, counted by the approximation
+    # only if the raster were wrong: shrink the polygon by hand and check that
+    # the check flags the mismatch between the two sets
+    big = polygons_from_rings([[np.array([[0, 0], [100, 0], [100, 100], [0, 100]])]])
+    A = orc.Approx(big, 10)
+    far_in = np.array([50, 50], np.int32)
+    assert A.invariant(far_in, exhaustive=True) == {"differ": 0, "far": 0, "false_neg": 0, "inside": 1}
+    near_out = np.array([103, 50], np.int32)
+    inv = A.invariant(near_out, exhaustive=True)
+    assert inv["differ"] == 1 and inv["far"] == 0
+
+
+# ---------------------------------------------------------------- nested grids
+
+def test_nested_grids_monotone(orc):
+    rng = np.random.default_rng(3)
+    polys = star_polygons(6, 24, 200.0, 2000.0, 8000, 13)
+    xy = rng.integers(-2000, 10000, size=2 * 200000).astype(np.int32)
+    sides = [(8, 5), (15, 10), (29, 20), (57, 40)]   # eps -> s, each s twice the previous
+    prev = None
+    ex = None
+    for eps, s in sides:
+        assert orc.cell_side(eps) == s
+        A = orc.Approx(polys, eps)
+        c, _ = A.aggregate(xy)
+        if ex is None:
+            ex, _ = A.exact(xy)
+            assert np.all(ex <= c)
+        if prev is not None:
+            assert np.all(prev <= c)
+        prev = c
+
+
+# ---------------------------------------------------------------- partition
+
+def test_partition_property(orc):
+    polys = voronoi_partition(30, 200000, (3, 20), seed=3, jitter_seed=4)
+    pts = uniform_points(300000, 0, 200000, 11)
+    for eps in (100, 1500):
+        A = orc.Approx(polys, eps)
+        ex, _ = A.exact(pts)
+        ap, _ = A.aggregate(pts)
+        assert int(ex.sum()) == 300000          # each point in exactly one cell
+        assert int(ap.sum()) >= 300000
+        inv = A.invariant(pts)
+        assert inv["far"] == 0 and inv["false_neg"] == 0
+
+
+# ---------------------------------------------------------------- hilbert
+
+def test_hilbert_level1(orc):
+    assert [orc.hilbert_d(1, *c) for c in [(0, 0), (0, 1), (1, 1), (1, 0)]] == [0, 1, 2, 3]
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 5, 6])
+def test_hilbert_bijection_and_adjacency(orc, L):
+    n = 1 << L
+    inv = {}
+    for i in range(n):
+        for j in range(n):
+            inv[orc.hilbert_d(L, i, j)] = (i, j)
+    assert sorted(inv) == list(range(n * n))
+    for d in range(n * n - 1):
+        (a, b), (c, e) = inv[d], inv[d + 1]
+        assert abs(a - c) + abs(b - e) == 1
+    assert inv[0] == (0, 0)
+    assert inv[n * n - 1] == (n - 1, 0)
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 5])
+def test_hilbert_quadrant_blocks(orc, L):
+    # every aligned block of 4^k consecutive indices is an aligned 2^k square
+    n = 1 << L
+    inv = {orc.hilbert_d(L, i, j): (i, j) for i in range(n) for j in range(n)}
+    for k in range(1, L):
+        bs = 4 ** k
+        for start in range(0, n * n, bs):
+            cells = [inv[d] for d in range(start, start + bs)]
+            xs = {c[0] // (1 << k) for c in cells}
+            ys = {c[1] // (1 << k) for c in cells}
+            assert len(xs) == 1 and len(ys) == 1
+
+
+def test_hilbert_runs_against_brute(orc):
+    polys = star_polygons(5, 10, 10.0, 60.0, 120, 21)
+    eps = 5
+    s = orc.cell_side(eps)
+    L = 6
+    A = orc.Approx(polys, eps)
+    starts, off, ids = A.hilbert_runs(L)
+    assert starts[0] == 0 and np.all(np.diff(starts.astype(np.int64)) > 0)
+    sets = [tuple(ids[off[r]:off[r + 1]]) for r in range(len(starts))]
+    assert all(sets[r] != sets[r + 1] for r in range(len(sets) - 1))    # maximal
+    n = 1 << L
+    br = orc.raster_brute(polys, s, 0, 0, n, n) > 0
+    for i in range(n):
+        for j in range(n):
+            d = orc.hilbert_d(L, i, j)
+            r = int(np.searchsorted(starts, d, side="right")) - 1
+            want = tuple(int(p) for p in np.nonzero(br[:, j, i])[0])
+            assert sets[r] == want
