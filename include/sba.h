@@ -1,0 +1,188 @@
+/*
+ * sba.h -- C ABI of the distance-bounded spatial aggregation library for
+ * AMD MI355X (gfx950).
+ *
+ * The library answers the spatial aggregation query of Sec. 5 of
+ * Tzirita Zacharatou et al., "The Case for Distance-Bounded Spatial
+ * Approximations" (CIDR 2021):
+ *
+ *     SELECT COUNT(*), SUM(value) FROM points, polygons
+ *     WHERE point INSIDE polygon GROUP BY polygon.id
+ *
+ * without any point-in-polygon test: every polygon P is replaced by its
+ * conservative raster approximation A(P) (Sec. 2.2), a set of grid cells of
+ * side s = the largest integer with 2 s^2 <= eps^2 (cell diagonal <= eps).
+ * A cell belongs to A(P) when its closed square touches an edge of P
+ * (boundary cell) or when it touches no edge and its lower-left corner is
+ * inside P by the crossing-number rule (interior cell).  A point counts for
+ * every polygon whose approximation holds the point's cell, so every point
+ * that is counted wrongly lies within eps of that polygon's boundary, and no
+ * point inside a polygon is ever missed (false positives only).
+ *
+ * Conventions shared by every entry point:
+ *   - Coordinates are int32 fixed-point; the grid is anchored at (0,0) and
+ *     cell(p) = (floor(x/s), floor(y/s)).  Polygon vertex coordinates must
+ *     satisfy |c| < 2^30.  eps must lie in [2, 2^28].
+ *   - Every array argument is a DEVICE pointer (memory of the GPU that is
+ *     current when the call is made) unless the comment says "host".
+ *     The caller owns all of them; the library never frees them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are asynchronous on that stream except where noted.
+ *   - Return 0 on success or a negative SBA_E* code; nothing is thrown.
+ */
+#ifndef SBA_H
+#define SBA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SBA_OK        0
+#define SBA_EINVAL   (-1)  /* null pointer, negative size, bad offsets, eps out of range */
+#define SBA_ERANGE   (-2)  /* coordinate out of range (|c| >= 2^30, or < 0 for the Hilbert layout) */
+#define SBA_ENOMEM   (-3)  /* device allocation failed */
+#define SBA_EDEVICE  (-4)  /* a HIP call failed */
+#define SBA_ELIMIT   (-5)  /* a documented size limit is exceeded (see sba_build_approx) */
+
+/* Layouts of the approximation. */
+#define SBA_KIND_GRID     0  /* two-level tiled uniform grid of cell codes          */
+#define SBA_KIND_HILBERT  1  /* sorted Hilbert-key runs (adaptive quadtree cells)    */
+
+/* Search used by the Hilbert layout's probe. */
+#define SBA_SEARCH_BINARY   0  /* predecessor by binary search over all run starts   */
+#define SBA_SEARCH_LEARNED  1  /* two-level linear model + bounded search (+ fallback) */
+
+typedef struct sba_handle sba_handle;
+
+/* Polygons in CSR form, all DEVICE pointers.
+ *   ring_off[n_polys+1]  ring index range of polygon p: [ring_off[p], ring_off[p+1])
+ *   vert_off[n_rings+1]  vertex index range of ring r (rings are closed implicitly)
+ *   xy[2*n_verts]        x, y interleaved, int32
+ * A polygon with several rings is read even-odd (holes, multi-polygons).
+ * Polygons may overlap; a cell then belongs to every polygon that claims it. */
+typedef struct {
+    int32_t        n_polys;
+    const int32_t *ring_off;
+    const int64_t *vert_off;
+    const int32_t *xy;
+} sba_polygons;
+
+typedef struct {
+    int32_t kind;         /* SBA_KIND_GRID (default) or SBA_KIND_HILBERT                 */
+    int32_t search;       /* Hilbert only: SBA_SEARCH_BINARY (default) or _LEARNED       */
+    int32_t log2_leaves;  /* learned index: number of leaves = 2^log2_leaves (0 -> 16)   */
+    int32_t tile_log2;    /* grid: tile side 2^tile_log2 cells, 3..8 (0 -> chosen from
+                             the grid size)                                              */
+} sba_build_opts;
+
+typedef struct {
+    int32_t kind, search;
+    int32_t n_polys;
+    int32_t tile_log2;      /* grid */
+    int32_t level;          /* Hilbert: L, keys in [0, 4^L) */
+    int32_t log2_leaves;
+    int64_t eps, s;         /* distance bound and cell side */
+    int64_t gi0, gj0;       /* first cell of the stored box (grid) */
+    int64_t gw, gh;         /* stored box size in cells */
+    int64_t n_tiles, n_blocks;  /* grid: directory entries, mixed (fine) tiles */
+    int64_t n_sets, n_set_ids;  /* multi-polygon cell sets */
+    int64_t n_segments;     /* row segments of constant polygon set (build intermediate) */
+    int64_t n_boundary;     /* (edge, row strip) boundary intervals */
+    int64_t n_runs;         /* Hilbert runs */
+    int64_t max_leaf_err;   /* learned index: largest stored error */
+    int64_t bytes;          /* device bytes held by the handle */
+    double  build_ms;       /* wall time of the build, host clock (includes its syncs) */
+} sba_info_t;
+
+/*
+ * Build the approximation A(P) of every polygon for distance bound eps
+ * (Sec. 2.2: cell side eps/sqrt(2) at the boundary; conservative raster;
+ * Sec. 3: cells linearised on the Hilbert curve for the Hilbert layout).
+ *
+ *   polys   host struct of DEVICE arrays (see sba_polygons); read during the
+ *           call only.
+ *   eps     distance bound in coordinate units, 2 <= eps <= 2^28.
+ *   opts    host pointer or NULL for defaults.
+ *   stream  work is queued on it; the call synchronises it several times
+ *           (it reads sizes back) and returns once the handle is complete.
+ *   out     host pointer; receives the new handle (NULL on failure).
+ *
+ * Limits (SBA_ELIMIT): at most 2^21-1 polygons; the stored cell box at most
+ * 2^21 cells per side; a cell may belong to at most 32 polygons; Hilbert
+ * layout: all vertex coordinates >= 0 and level L <= 21.
+ * Errors: SBA_EINVAL (null/negative/non-monotone offsets, eps out of range),
+ * SBA_ERANGE, SBA_ENOMEM, SBA_EDEVICE, SBA_ELIMIT.
+ */
+int sba_build_approx(const sba_polygons *polys, int64_t eps, const sba_build_opts *opts,
+                     void *stream, sba_handle **out);
+
+/*
+ * Per-polygon COUNT and SUM over the points (Sec. 5: the aggregation query
+ * answered from the approximation alone, join and aggregation fused).
+ *
+ *   xy      [2n] int32 x,y interleaved.  16-byte alignment lets the probe use
+ *           128-bit loads (torch allocations are aligned).
+ *   values  [n] int64 or NULL (COUNT only; sums is then ignored).
+ *   n       number of points, >= 0.
+ *   counts  [n_polys] uint64, overwritten.
+ *   sums    [n_polys] int64, overwritten (may be NULL).
+ * A point whose cell lies in no approximation contributes nothing; one whose
+ * cell lies in k approximations contributes to all k.  With n == 0 both
+ * outputs are zeroed (sums if non-NULL).  Asynchronous on `stream`.  Sums
+ * wrap modulo 2^64 if they overflow (not checked).
+ */
+int sba_aggregate(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
+                  uint64_t *counts, int64_t *sums, void *stream);
+
+/* As sba_aggregate, with the Hilbert layout's search chosen per call
+ * (SBA_SEARCH_BINARY or SBA_SEARCH_LEARNED; learned needs a handle built with
+ * search = SBA_SEARCH_LEARNED).  Ignored for the grid layout. */
+int sba_aggregate_search(const int32_t *xy, const int64_t *values, int64_t n,
+                         const sba_handle *h, int32_t search, uint64_t *counts,
+                         int64_t *sums, void *stream);
+
+/*
+ * Cell lookup, for checking the approximation itself.
+ *   ij    [2n] int64 cell indices (i, j) interleaved.
+ *   ref   [n] int32 out: -1 = no polygon, p >= 0 = exactly polygon p,
+ *         <= -2 = the polygon set with index -2-ref (see sba_get_sets).
+ * Asynchronous on `stream`.
+ */
+int sba_lookup_cells(const sba_handle *h, const int64_t *ij, int64_t n, int32_t *ref,
+                     void *stream);
+
+/* Multi-polygon sets (host copies).  Pass NULL arrays to query sizes only.
+ *   n_sets, n_ids  host out: number of sets and of ids over all sets
+ *   off  host [n_sets+1], ids host [n_ids]: ids of set k (ascending) are
+ *        ids[off[k] .. off[k+1]).
+ * Synchronous. */
+int sba_get_sets(const sba_handle *h, int64_t *n_sets, int64_t *n_ids, int64_t *off,
+                 int32_t *ids);
+
+/* Hilbert layout: copy the runs into caller DEVICE buffers.
+ *   starts [n_runs] uint64: first key of each run (starts[0] = 0, ascending;
+ *          the runs partition [0, 4^L) and neighbours differ in their set)
+ *   ids    [n_runs] int32: ref of the run, encoded as in sba_lookup_cells.
+ * Asynchronous on `stream`. */
+int sba_get_runs(const sba_handle *h, uint64_t *starts, int32_t *ids, void *stream);
+
+/* Handle metadata (host struct). */
+int sba_info(const sba_handle *h, sba_info_t *info);
+
+/* Release the handle's device memory.  The caller must make sure no work
+ * using the handle is still queued (synchronise its streams first). */
+void sba_free(sba_handle *h);
+
+/* Static string describing an error code. */
+const char *sba_strerror(int code);
+
+/* Library version string. */
+const char *sba_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SBA_H */

@@ -1,0 +1,32 @@
+/*
+ * sba_debug.h -- host-only helpers of libsba for its own tests and tuning.
+ * They expose the integer arithmetic the kernels use, evaluated on the host,
+ * so that it can be checked without a GPU.  Not needed by applications.
+ */
+#ifndef SBA_DEBUG_H
+#define SBA_DEBUG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* q[k] = floor(n[k] / s) by the probes' multiply-shift division (Granlund and
+ * Montgomery, 1994, Thm. 4.2 with 31-bit dividends).  Host arrays of `count`
+ * entries; every n[k] must be < 2^31.  SBA_EINVAL if s is outside [1, 2^28]. */
+int sba_debug_celldiv(int64_t s, const uint32_t *n, int64_t count, uint32_t *q);
+
+/* Hilbert index of cell (i, j) at level L (Sec. 3 linearisation), and its
+ * inverse, exactly as the kernels compute them. */
+uint64_t sba_debug_hilbert(int L, uint32_t i, uint32_t j);
+void sba_debug_hilbert_cell(int L, uint64_t d, uint32_t *i, uint32_t *j);
+
+/* Workgroups per compute unit of the streaming probes (default 4, 1..64).
+ * Process-wide; for launch-shape sweeps. */
+int sba_debug_set_blocks_per_cu(int k);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,273 @@
+"""Python binding of libsba, the MI355X library for distance-bounded
+approximate point-in-polygon aggregation (Tzirita Zacharatou et al., "The
+Case for Distance-Bounded Spatial Approximations", CIDR 2021).
+
+Argument marshalling only: every step of the build and of the probe runs in
+the HIP kernels of ``libsba.so`` (sources in ``csrc/``).  PyTorch provides
+device memory and streams.  There is no CPU fallback: if the library is not
+built, or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+__all__ = ["Approx", "SbaError", "lib", "library_path", "celldiv", "hilbert", "hilbert_cell",
+           "KIND_GRID", "KIND_HILBERT", "SEARCH_BINARY", "SEARCH_LEARNED"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsba.so")
+_lib = None
+
+KIND_GRID, KIND_HILBERT = 0, 1
+SEARCH_BINARY, SEARCH_LEARNED = 0, 1
+
+
+class SbaError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        msg = lib().sba_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{what}: {msg} ({code})")
+
+
+class _Polys(C.Structure):
+    _fields_ = [("n_polys", C.c_int32), ("ring_off", C.c_void_p), ("vert_off", C.c_void_p),
+                ("xy", C.c_void_p)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("search", C.c_int32), ("log2_leaves", C.c_int32),
+                ("tile_log2", C.c_int32)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("search", C.c_int32), ("n_polys", C.c_int32),
+                ("tile_log2", C.c_int32), ("level", C.c_int32), ("log2_leaves", C.c_int32),
+                ("eps", C.c_int64), ("s", C.c_int64), ("gi0", C.c_int64), ("gj0", C.c_int64),
+                ("gw", C.c_int64), ("gh", C.c_int64), ("n_tiles", C.c_int64),
+                ("n_blocks", C.c_int64), ("n_sets", C.c_int64), ("n_set_ids", C.c_int64),
+                ("n_segments", C.c_int64), ("n_boundary", C.c_int64), ("n_runs", C.c_int64),
+                ("max_leaf_err", C.c_int64), ("bytes", C.c_int64), ("build_ms", C.c_double)]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libsba.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = C.CDLL(_LIB_PATH)
+    vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+    L.sba_build_approx.restype = C.c_int
+    L.sba_build_approx.argtypes = [C.POINTER(_Polys), i64, C.POINTER(_Opts), vp, C.POINTER(vp)]
+    L.sba_aggregate.restype = C.c_int
+    L.sba_aggregate.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+    L.sba_aggregate_search.restype = C.c_int
+    L.sba_aggregate_search.argtypes = [vp, vp, i64, vp, i32, vp, vp, vp]
+    L.sba_lookup_cells.restype = C.c_int
+    L.sba_lookup_cells.argtypes = [vp, vp, i64, vp, vp]
+    L.sba_get_sets.restype = C.c_int
+    L.sba_get_sets.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), vp, vp]
+    L.sba_get_runs.restype = C.c_int
+    L.sba_get_runs.argtypes = [vp, vp, vp, vp]
+    L.sba_info.restype = C.c_int
+    L.sba_info.argtypes = [vp, C.POINTER(_Info)]
+    L.sba_free.restype = None
+    L.sba_free.argtypes = [vp]
+    L.sba_strerror.restype = C.c_char_p
+    L.sba_strerror.argtypes = [C.c_int]
+    L.sba_version.restype = C.c_char_p
+    L.sba_version.argtypes = []
+    L.sba_debug_celldiv.restype = C.c_int
+    L.sba_debug_celldiv.argtypes = [i64, vp, i64, vp]
+    L.sba_debug_hilbert.restype = C.c_uint64
+    L.sba_debug_hilbert.argtypes = [C.c_int, C.c_uint32, C.c_uint32]
+    L.sba_debug_hilbert_cell.restype = None
+    L.sba_debug_hilbert_cell.argtypes = [C.c_int, C.c_uint64, C.POINTER(C.c_uint32),
+                                         C.POINTER(C.c_uint32)]
+    L.sba_debug_set_blocks_per_cu.restype = C.c_int
+    L.sba_debug_set_blocks_per_cu.argtypes = [C.c_int]
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise SbaError(rc, what)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtype, device):
+    torch = _torch()
+    if isinstance(t, np.ndarray):
+        t = torch.from_numpy(np.ascontiguousarray(t))
+    t = t.to(device=device, dtype=dtype).contiguous()
+    if t.device.type != "cuda":
+        raise ValueError("libsba works on GPU tensors only")
+    return t
+
+
+def celldiv(s: int, n) -> np.ndarray:
+    """floor(n / s) computed with the probes' multiply-shift (host copy)."""
+    n = np.ascontiguousarray(n, dtype=np.uint32)
+    q = np.zeros_like(n)
+    _check(lib().sba_debug_celldiv(int(s), n.ctypes.data, n.shape[0], q.ctypes.data), "celldiv")
+    return q
+
+
+def hilbert(L: int, i: int, j: int) -> int:
+    """Hilbert index of cell (i, j) as computed by the kernels (host copy)."""
+    return int(lib().sba_debug_hilbert(int(L), int(i), int(j)))
+
+
+def hilbert_cell(L: int, d: int):
+    i, j = C.c_uint32(0), C.c_uint32(0)
+    lib().sba_debug_hilbert_cell(int(L), int(d), C.byref(i), C.byref(j))
+    return int(i.value), int(j.value)
+
+
+class Approx:
+    """Handle of the approximation of a polygon set (``sba_build_approx``).
+
+    ring_off (int32 [P+1]), vert_off (int64 [R+1]) and xy (int32 [2V]) are the
+    polygons in CSR form (torch tensors or numpy arrays; copied to the GPU).
+    """
+
+    def __init__(self, ring_off, vert_off, xy, eps: int, kind: str = "grid",
+                 search: str = "binary", log2_leaves: int = 16, tile_log2: int = 0,
+                 device: str = "cuda", stream=None):
+        torch = _torch()
+        self._h = C.c_void_p(None)
+        self.device = torch.device(device)
+        ro = _dev(ring_off, torch.int32, self.device)
+        vo = _dev(vert_off, torch.int64, self.device)
+        pxy = _dev(xy, torch.int32, self.device)
+        self.n_polys = int(ro.shape[0] - 1)
+        polys = _Polys(self.n_polys, ro.data_ptr(), vo.data_ptr(), pxy.data_ptr())
+        opts = _Opts({"grid": KIND_GRID, "hilbert": KIND_HILBERT}[kind],
+                     {"binary": SEARCH_BINARY, "learned": SEARCH_LEARNED}[search],
+                     int(log2_leaves), int(tile_log2))
+        h = C.c_void_p(None)
+        with torch.cuda.device(self.device):
+            rc = lib().sba_build_approx(C.byref(polys), int(eps), C.byref(opts),
+                                        _stream_ptr(stream), C.byref(h))
+        _check(rc, "sba_build_approx")
+        self._h = h
+        self.eps = int(eps)
+        self.kind = kind
+        self.search = search
+
+    @classmethod
+    def from_polygons(cls, polys, eps: int, **kw) -> "Approx":
+        """polys: any object with numpy ring_off / vert_off / xy arrays."""
+        return cls(polys.ring_off, polys.vert_off, polys.xy, eps, **kw)
+
+    def close(self):
+        if self._h:
+            _torch().cuda.synchronize(self.device)
+            lib().sba_free(self._h)
+            self._h = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = _Info()
+        _check(lib().sba_info(self._h, C.byref(inf)), "sba_info")
+        return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+    def aggregate(self, xy, values=None, counts=None, sums=None, search: str | None = None,
+                  stream=None):
+        """Per-polygon (counts, sums) as int64 GPU tensors (sums None for COUNT).
+
+        xy: int32 GPU tensor [2n] (x, y interleaved); values: int64 [n] or None.
+        Asynchronous on the current (or given) stream.
+        """
+        torch = _torch()
+        if xy.dtype != torch.int32 or xy.device.type != "cuda" or not xy.is_contiguous():
+            raise ValueError("xy must be a contiguous int32 GPU tensor")
+        n = xy.numel() // 2
+        if values is not None:
+            if values.dtype != torch.int64 or values.numel() != n or not values.is_contiguous():
+                raise ValueError("values must be a contiguous int64 GPU tensor of n entries")
+        if counts is None:
+            counts = torch.empty(max(self.n_polys, 1), dtype=torch.int64, device=xy.device)
+        if values is not None and sums is None:
+            sums = torch.empty(max(self.n_polys, 1), dtype=torch.int64, device=xy.device)
+        vptr = values.data_ptr() if values is not None else None
+        sptr = sums.data_ptr() if (values is not None and sums is not None) else None
+        sp = _stream_ptr(stream)
+        if search is None:
+            rc = lib().sba_aggregate(xy.data_ptr(), vptr, n, self._h, counts.data_ptr(), sptr, sp)
+        else:
+            code = {"binary": SEARCH_BINARY, "learned": SEARCH_LEARNED}[search]
+            rc = lib().sba_aggregate_search(xy.data_ptr(), vptr, n, self._h, code,
+                                            counts.data_ptr(), sptr, sp)
+        _check(rc, "sba_aggregate")
+        return counts[:self.n_polys], (sums[:self.n_polys] if values is not None else None)
+
+    def lookup(self, ij, stream=None):
+        """Refs of cells (int64 GPU tensor [2n] of i,j): -1 none, p, or -2-set."""
+        torch = _torch()
+        ij = _dev(ij, torch.int64, self.device)
+        n = ij.numel() // 2
+        ref = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        _check(lib().sba_lookup_cells(self._h, ij.data_ptr(), n, ref.data_ptr(),
+                                      _stream_ptr(stream)), "sba_lookup_cells")
+        return ref[:n]
+
+    def sets(self):
+        """Multi-polygon sets: (off int64 [S+1], ids int32) numpy arrays."""
+        ns, ni = C.c_int64(0), C.c_int64(0)
+        _torch().cuda.synchronize(self.device)
+        _check(lib().sba_get_sets(self._h, C.byref(ns), C.byref(ni), None, None), "sba_get_sets")
+        off = np.zeros(ns.value + 1, np.int64)
+        ids = np.zeros(max(ni.value, 1), np.int32)
+        _check(lib().sba_get_sets(self._h, C.byref(ns), C.byref(ni), off.ctypes.data,
+                                  ids.ctypes.data), "sba_get_sets")
+        return off, ids[:ni.value]
+
+    def runs(self, stream=None):
+        """Hilbert runs: (starts as int64 tensor, refs int32 tensor) on the GPU."""
+        torch = _torch()
+        n = self.info()["n_runs"]
+        starts = torch.empty(max(n, 1), dtype=torch.int64, device=self.device)
+        ids = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        _check(lib().sba_get_runs(self._h, starts.data_ptr(), ids.data_ptr(), _stream_ptr(stream)),
+               "sba_get_runs")
+        return starts[:n], ids[:n]
+
+    def decode(self, refs) -> list:
+        """Turn refs into sorted polygon-id tuples."""
+        off, ids = self.sets()
+        out = []
+        for r in np.asarray(refs).tolist():
+            if r == -1:
+                out.append(())
+            elif r >= 0:
+                out.append((r,))
+            else:
+                k = -2 - r
+                out.append(tuple(int(v) for v in ids[off[k]:off[k + 1]]))
+        return out

@@ -1,0 +1,755 @@
+// build.hip -- construction of the conservative eps-approximation on the GPU.
+//
+// Sec. 2.2 of the paper defines the approximation: cells of side
+// eps/sqrt(2) along the boundary, every cell that touches the boundary kept
+// (conservative raster), interior cells kept whole.  In integers, cell (i,j)
+// is in A(P) when its closed square [is,(i+1)s]x[js,(j+1)s] meets an edge of
+// P, or when it meets none and its corner (is,js) is inside P by the
+// crossing-number rule.
+//
+// The build never visits a cell that is not on a boundary.  It works on
+// rows of cells:
+//   1. per edge and per row strip the edge touches: the closed x-range of the
+//      edge inside the strip gives one interval of boundary cells;
+//   2. per edge and per row line y = js it crosses (half-open rule): the
+//      crossing's cell index k = ceil(xc/s); sorted per (polygon, row), the
+//      crossings pair up into the intervals [k1,k2), [k3,k4) ... of cells
+//      whose corner is inside;
+//   3. all intervals become +p/-p events sorted by (row, x); one thread per
+//      row sweeps them and emits maximal row segments of constant polygon
+//      set;
+//   4. sets of two or more polygons are deduplicated into a set table;
+//   5. the segments are written into the chosen layout: a two-level tiled
+//      grid (uniform tiles stored once in a directory, mixed tiles as fine
+//      blocks) or, in hilbert.hip, the runs of the Hilbert order.
+#include <chrono>
+#include <vector>
+
+#include "sba_internal.h"
+#include "build_state.h"
+
+// ---------------------------------------------------------------- kernels
+
+__global__ void k_edges(const int32_t *ring_off, int32_t n_polys, const int64_t *vert_off,
+                        int32_t n_rings, const int32_t *xy, int64_t n_verts, int4 *edges,
+                        int32_t *epoly)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n_verts) return;
+    int lo = 0, hi = n_rings;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (vert_off[mid] <= v) lo = mid + 1; else hi = mid;
+    }
+    int r = lo - 1;
+    lo = 0;
+    hi = n_polys;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (ring_off[mid] <= r) lo = mid + 1; else hi = mid;
+    }
+    int p = lo - 1;
+    int64_t w = (v + 1 < vert_off[r + 1]) ? v + 1 : vert_off[r];
+    edges[v] = make_int4(xy[2 * v], xy[2 * v + 1], xy[2 * w], xy[2 * w + 1]);
+    epoly[v] = p;
+}
+
+// one wavefront per polygon: coordinate bounding box, range check
+__global__ void k_poly_bbox(const int32_t *ring_off, const int64_t *vert_off, const int32_t *xy,
+                            int32_t n_polys, int4 *bbox, int *err)
+{
+    int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    int lane = threadIdx.x & 63;
+    if (gw >= n_polys) return;
+    int p = (int)gw;
+    int64_t v0 = vert_off[ring_off[p]], v1 = vert_off[ring_off[p + 1]];
+    int xmin = INT32_MAX, ymin = INT32_MAX, xmax = INT32_MIN, ymax = INT32_MIN;
+    bool bad = false;
+    for (int64_t v = v0 + lane; v < v1; v += 64) {
+        int x = xy[2 * v], y = xy[2 * v + 1];
+        bad |= (x <= -(1 << 30)) | (x >= (1 << 30)) | (y <= -(1 << 30)) | (y >= (1 << 30));
+        xmin = min(xmin, x); ymin = min(ymin, y);
+        xmax = max(xmax, x); ymax = max(ymax, y);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        xmin = min(xmin, __shfl_xor(xmin, o, 64));
+        ymin = min(ymin, __shfl_xor(ymin, o, 64));
+        xmax = max(xmax, __shfl_xor(xmax, o, 64));
+        ymax = max(ymax, __shfl_xor(ymax, o, 64));
+    }
+    if (bad) atomicOr(err, 1);
+    if (lane == 0) bbox[p] = make_int4(xmin, ymin, xmax, ymax);
+}
+
+// per edge: number of boundary row strips and of row-line crossings
+__global__ void k_edge_counts(const int4 *edges, int64_t n_edges, int64_t s, int64_t *nb,
+                              int64_t *nc)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_edges) return;
+    int4 E = edges[e];
+    int64_t ey0 = min(E.y, E.w), ey1 = max(E.y, E.w);
+    nb[e] = floordiv64(ey1, s) - (ceildiv64(ey0, s) - 1) + 1;
+    nc[e] = (E.y != E.w) ? ceildiv64(ey1, s) - ceildiv64(ey0, s) : 0;
+}
+
+__device__ __forceinline__ int64_t upper_bound_i64(const int64_t *a, int64_t n, int64_t v)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] <= v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// boundary item t -> interval of cells [c0, c1] of row j touched by its edge,
+// written as a start and an end event
+__global__ void k_emit_boundary(const int4 *edges, const int32_t *epoly, int64_t n_edges,
+                                const int64_t *boff, int64_t nb_total, int64_t s, int64_t gi0,
+                                int64_t gj0, int xbits, uint64_t *evkey, uint32_t *evpay)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb_total) return;
+    int64_t e = upper_bound_i64(boff, n_edges, t) - 1;
+    int4 E = edges[e];
+    int64_t x1 = E.x, y1 = E.y, x2 = E.z, y2 = E.w;
+    int64_t ey0 = min(y1, y2), ey1 = max(y1, y2);
+    int64_t j = ceildiv64(ey0, s) - 1 + (t - boff[e]);
+    int64_t c0, c1;
+    if (y1 == y2) {
+        c0 = ceildiv64(min(x1, x2), s) - 1;
+        c1 = floordiv64(max(x1, x2), s);
+    } else {
+        int64_t ya = max(ey0, j * s), yb = min(ey1, (j + 1) * s);
+        int64_t den = y2 - y1;
+        // x(y) = (x1*den + (y - y1)*(x2 - x1)) / den ; |numerator| < 2^63
+        int64_t na = x1 * den + (ya - y1) * (x2 - x1);
+        int64_t nbv = x1 * den + (yb - y1) * (x2 - x1);
+        if (den < 0) { den = -den; na = -na; nbv = -nbv; }
+        int64_t lo = min(na, nbv), hi = max(na, nbv);
+        c0 = ceildiv64(lo, den * s) - 1;
+        c1 = floordiv64(hi, den * s);
+    }
+    uint64_t r = (uint64_t)(j - gj0);
+    uint32_t p = (uint32_t)epoly[e];
+    evkey[2 * t] = (r << xbits) | (uint64_t)(c0 - gi0);
+    evpay[2 * t] = p << 1;
+    evkey[2 * t + 1] = (r << xbits) | (uint64_t)(c1 + 1 - gi0);
+    evpay[2 * t + 1] = (p << 1) | 1u;
+}
+
+// crossing item t -> key (polygon, row, k) with k = ceil(xc / s)
+__global__ void k_emit_cross(const int4 *edges, const int32_t *epoly, int64_t n_edges,
+                             const int64_t *coff, int64_t nc_total, int64_t s, int64_t gi0,
+                             int64_t gj0, int xbits, int rbits, uint64_t *ckey)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nc_total) return;
+    int64_t e = upper_bound_i64(coff, n_edges, t) - 1;
+    int4 E = edges[e];
+    int64_t x1 = E.x, y1 = E.y, x2 = E.z, y2 = E.w;
+    int64_t ey0 = min(y1, y2);
+    int64_t j = ceildiv64(ey0, s) + (t - coff[e]);
+    int64_t den = y2 - y1;
+    int64_t num = x1 * den + (j * s - y1) * (x2 - x1);
+    if (den < 0) { den = -den; num = -num; }
+    int64_t k = ceildiv64(num, den * s);
+    ckey[t] = ((uint64_t)epoly[e] << (rbits + xbits)) | ((uint64_t)(j - gj0) << xbits) |
+              (uint64_t)(k - gi0);
+}
+
+// sorted crossings pair up within each (polygon, row): span [k1, k2)
+__global__ void k_spans(const uint64_t *ckey, int64_t npairs, int xbits, int rbits,
+                        uint64_t *evkey, uint32_t *evpay, int *err)
+{
+    int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= npairs) return;
+    uint64_t a = ckey[2 * m], b = ckey[2 * m + 1];
+    if ((a >> xbits) != (b >> xbits)) atomicOr(err, 2);
+    uint64_t xm = (1ull << xbits) - 1;
+    uint64_t rm = (1ull << rbits) - 1;
+    uint32_t p = (uint32_t)(a >> (xbits + rbits));
+    uint64_t r = (a >> xbits) & rm;
+    evkey[2 * m] = (r << xbits) | (a & xm);
+    evpay[2 * m] = p << 1;
+    evkey[2 * m + 1] = (r << xbits) | (b & xm);
+    evpay[2 * m + 1] = (p << 1) | 1u;
+}
+
+__global__ void k_row_off(const uint64_t *evkey, int64_t ne, int64_t gh, int xbits,
+                          int64_t *row_off)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > gh) return;
+    if (r == gh) { row_off[r] = ne; return; }
+    uint64_t v = (uint64_t)r << xbits;
+    int64_t lo = 0, hi = ne;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (evkey[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    row_off[r] = lo;
+}
+
+// One thread per row: sweep the row's events in x order, keep the multiset
+// of open polygons, emit a segment whenever the set of polygons changes.
+template <bool WRITE>
+__global__ __launch_bounds__(64) void k_sweep(const uint64_t *evkey, const uint32_t *evpay,
+                                              const int64_t *ev_row_off, int64_t gh, int xbits,
+                                              int64_t *cnt_seg, int64_t *cnt_multi,
+                                              int64_t *cnt_mem, const int64_t *off_seg,
+                                              const int64_t *off_multi, const int64_t *off_mem,
+                                              int32_t *seg_x0, int32_t *seg_x1, uint32_t *seg_code,
+                                              int64_t *multi_seg, int64_t *multi_mem,
+                                              int32_t *mem_ids, int *err)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= gh) return;
+    const uint64_t xmask = (1ull << xbits) - 1;
+    int ids[MAX_DEPTH], cnt[MAX_DEPTH], oid[MAX_DEPTH];
+    int na = 0, ona = 0;
+    uint32_t ox0 = 0;
+    int64_t nseg = 0, nmulti = 0, nmem = 0;
+    int64_t t = ev_row_off[r], te = ev_row_off[r + 1];
+    int bad = 0;
+    while (t < te) {
+        uint32_t x = (uint32_t)(evkey[t] & xmask);
+        while (t < te && (uint32_t)(evkey[t] & xmask) == x) {
+            uint32_t pay = evpay[t];
+            int p = (int)(pay >> 1);
+            int k = 0;
+            while (k < na && ids[k] < p) k++;
+            if (pay & 1u) {
+                if (k < na && ids[k] == p) cnt[k]--;
+                else bad |= 4;
+            } else if (k < na && ids[k] == p) {
+                cnt[k]++;
+            } else if (na == MAX_DEPTH) {
+                bad |= 8;
+            } else {
+                for (int q = na; q > k; q--) { ids[q] = ids[q - 1]; cnt[q] = cnt[q - 1]; }
+                ids[k] = p;
+                cnt[k] = 1;
+                na++;
+            }
+            t++;
+        }
+        int m = 0;
+        for (int k = 0; k < na; k++)
+            if (cnt[k] > 0) { ids[m] = ids[k]; cnt[m] = cnt[k]; m++; }
+        na = m;
+        bool same = (na == ona);
+        for (int k = 0; same && k < na; k++) same = (ids[k] == oid[k]);
+        if (!same) {
+            if (ona > 0) {
+                if (WRITE) {
+                    int64_t si = off_seg[r] + nseg;
+                    seg_x0[si] = (int32_t)ox0;
+                    seg_x1[si] = (int32_t)x;
+                    if (ona == 1) {
+                        seg_code[si] = (uint32_t)oid[0] + 1u;
+                    } else {
+                        int64_t mi = off_multi[r] + nmulti;
+                        int64_t mo = off_mem[r] + nmem;
+                        seg_code[si] = 0xffffffffu;
+                        multi_seg[mi] = si;
+                        multi_mem[mi] = mo;
+                        for (int k = 0; k < ona; k++) mem_ids[mo + k] = oid[k];
+                    }
+                }
+                nseg++;
+                if (ona > 1) { nmulti++; nmem += ona; }
+            }
+            for (int k = 0; k < na; k++) oid[k] = ids[k];
+            ona = na;
+            ox0 = x;
+        }
+    }
+    if (ona != 0) bad |= 16;
+    if (bad) atomicOr(err, bad);
+    if (!WRITE) {
+        cnt_seg[r] = nseg;
+        cnt_multi[r] = nmulti;
+        cnt_mem[r] = nmem;
+    }
+}
+
+// ------------------------------------------------ multi-polygon set dedup
+
+__global__ void k_multi_keys(const int64_t *multi_mem, int64_t n_multi, int64_t n_mem,
+                             const int32_t *mem_ids, uint64_t *key, uint32_t *val)
+{
+    int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n_multi) return;
+    int64_t a = multi_mem[m], b = (m + 1 < n_multi) ? multi_mem[m + 1] : n_mem;
+    uint64_t k = 0;
+    if (b - a <= 3) {
+        for (int64_t t = a; t < b; t++) k |= (uint64_t)(mem_ids[t] + 1) << (21 * (t - a));
+    } else {
+        k = (1ull << 63) | (uint64_t)m;  // not shared: a set of its own
+    }
+    key[m] = k;
+    val[m] = (uint32_t)m;
+}
+
+__global__ void k_flag_new(const uint64_t *key, int64_t n, int64_t *flag)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    flag[t] = (t == 0 || key[t] != key[t - 1]) ? 1 : 0;
+}
+
+__global__ void k_set_sizes(const uint64_t *key, const uint32_t *val, const int64_t *gexcl,
+                            int64_t n, const int64_t *multi_mem, int64_t n_multi, int64_t n_mem,
+                            int64_t *set_sz)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    if (t == 0 || key[t] != key[t - 1]) {
+        int64_t m = val[t];
+        int64_t a = multi_mem[m], b = (m + 1 < n_multi) ? multi_mem[m + 1] : n_mem;
+        set_sz[gexcl[t]] = b - a;
+    }
+}
+
+__global__ void k_set_fill(const uint64_t *key, const uint32_t *val, const int64_t *gexcl,
+                           int64_t n, const int64_t *multi_mem, int64_t n_multi, int64_t n_mem,
+                           const int32_t *mem_ids, const int64_t *set_off, int32_t *set_ids,
+                           const int64_t *multi_seg, uint32_t *seg_code)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    bool first = (t == 0 || key[t] != key[t - 1]);
+    int64_t g = gexcl[t] + (first ? 1 : 0) - 1;
+    int64_t m = val[t];
+    if (first) {
+        int64_t a = multi_mem[m], b = (m + 1 < n_multi) ? multi_mem[m + 1] : n_mem;
+        int64_t o = set_off[g];
+        for (int64_t q = a; q < b; q++) set_ids[o + (q - a)] = mem_ids[q];
+    }
+    seg_code[multi_seg[m]] = CODE_SET_BASE + (uint32_t)g;
+}
+
+// ------------------------------------------------ segment lookups
+
+__device__ __forceinline__ uint32_t seg_code_at(const int64_t *seg_row_off, const int32_t *seg_x0,
+                                                const int32_t *seg_x1, const uint32_t *seg_code,
+                                                int64_t r, int32_t x)
+{
+    int64_t lo = seg_row_off[r], hi = seg_row_off[r + 1];
+    int64_t a = lo;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (seg_x0[mid] <= x) lo = mid + 1; else hi = mid;
+    }
+    if (lo > a && x < seg_x1[lo - 1]) return seg_code[lo - 1];
+    return 0;
+}
+
+__global__ void k_lookup_ij(const int64_t *seg_row_off, const int32_t *seg_x0, const int32_t *seg_x1,
+                            const uint32_t *seg_code, int64_t gi0, int64_t gj0, int64_t gw, int64_t gh,
+                            const int64_t *ij, int64_t n, uint32_t *out)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    int64_t i = ij[2 * t] - gi0, j = ij[2 * t + 1] - gj0;
+    out[t] = (i < 0 || j < 0 || i >= gw || j >= gh)
+                 ? 0u
+                 : seg_code_at(seg_row_off, seg_x0, seg_x1, seg_code, j, (int32_t)i);
+}
+
+// ------------------------------------------------ tiled grid
+
+// one wavefront per tile: uniform code, or mixed
+__global__ void k_tile_classify(const int64_t *seg_row_off, const int32_t *seg_x0,
+                                const int32_t *seg_x1, const uint32_t *seg_code, int64_t gw,
+                                int64_t gh, int tl, int64_t tw, int64_t n_tiles, uint32_t *dir,
+                                int64_t *mixed)
+{
+    int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    int lane = threadIdx.x & 63;
+    if (tile >= n_tiles) return;
+    int64_t ti = tile % tw, tj = tile / tw;
+    int32_t x0 = (int32_t)(ti << tl);
+    int32_t x1 = (int32_t)min((int64_t)x0 + (1 << tl), gw);
+    int64_t r0 = tj << tl, r1 = min(r0 + (1 << tl), gh);
+    uint32_t lo_c = 0xffffffffu, hi_c = 0;
+    for (int64_t r = r0 + lane; r < r1; r += 64) {
+        int64_t a = seg_row_off[r], lo = a, hi = seg_row_off[r + 1], e = hi;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (seg_x0[mid] <= x0) lo = mid + 1; else hi = mid;
+        }
+        uint32_t c;
+        if (lo > a && x0 < seg_x1[lo - 1]) {
+            c = (seg_x1[lo - 1] >= x1) ? seg_code[lo - 1] : 0xffffffffu;
+        } else {
+            c = (lo >= e || seg_x0[lo] >= x1) ? 0u : 0xffffffffu;
+        }
+        lo_c = min(lo_c, c);
+        hi_c = max(hi_c, c);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        lo_c = min(lo_c, (uint32_t)__shfl_xor((int)lo_c, o, 64));
+        hi_c = max(hi_c, (uint32_t)__shfl_xor((int)hi_c, o, 64));
+    }
+    if (lane == 0) {
+        bool uni = (lo_c == hi_c) && (hi_c != 0xffffffffu);
+        dir[tile] = uni ? hi_c : 0xffffffffu;
+        mixed[tile] = uni ? 0 : 1;
+    }
+}
+
+// one block per tile; mixed tiles write their fine block, all tiles their
+// final directory entry
+__global__ __launch_bounds__(256) void k_tile_fill(const int64_t *seg_row_off, const int32_t *seg_x0,
+                                                   const int32_t *seg_x1, const uint32_t *seg_code,
+                                                   int64_t gw, int64_t gh, int tl, int64_t tw,
+                                                   uint32_t *dir, const int64_t *blk,
+                                                   uint32_t *blocks)
+{
+    int64_t tile = blockIdx.x;
+    uint32_t d = dir[tile];
+    if (d != 0xffffffffu) return;
+    int64_t b = blk[tile];
+    int64_t ti = tile % tw, tj = tile / tw;
+    int T = 1 << tl;
+    uint32_t *out = blocks + (b << (2 * tl));
+    for (int c = threadIdx.x; c < T * T; c += blockDim.x) {
+        int64_t r = (tj << tl) + (c >> tl);
+        int64_t x = (ti << tl) + (c & (T - 1));
+        out[c] = (r < gh && x < gw)
+                     ? seg_code_at(seg_row_off, seg_x0, seg_x1, seg_code, r, (int32_t)x)
+                     : 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) dir[tile] = TILE_MIXED | (uint32_t)b;
+}
+
+// ---------------------------------------------------------------- host side
+
+void magic_for(int64_t s, uint32_t *mag, int32_t *shift)
+{
+    int l = 0;
+    while (((int64_t)1 << l) < s) l++;  // l = ceil(log2 s)
+    // m = ceil(2^(31+l) / s)
+    unsigned __int128 num = (unsigned __int128)1 << (31 + l);
+    uint64_t m = (uint64_t)((num + (unsigned __int128)(s - 1)) / (unsigned __int128)s);
+    *mag = (uint32_t)m;  // < 2^32 (== 2^31 for s == 1)
+    *shift = 31 + l;
+}
+
+BuildState::~BuildState()
+{
+    if (!owned.empty()) (void)hipStreamSynchronize(st);
+    for (void *p : owned) (void)hipFree(p);
+}
+
+int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_handle *h,
+                   BuildState &B, bool need_boundary_cells)
+{
+    (void)need_boundary_cells;
+    const int32_t np = polys->n_polys;
+    int *err = nullptr;
+    RC(B.alloc(&err, 1));
+    HIP_OK(hipMemsetAsync(err, 0, sizeof(int), st));
+
+    // offsets to the host: sizes and validation
+    std::vector<int32_t> ring_off(np + 1);
+    HIP_OK(hipMemcpyAsync(ring_off.data(), polys->ring_off, sizeof(int32_t) * (np + 1),
+                          hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (ring_off[0] != 0) return SBA_EINVAL;
+    for (int32_t p = 0; p < np; p++)
+        if (ring_off[p + 1] < ring_off[p]) return SBA_EINVAL;
+    const int32_t nr = ring_off[np];
+    std::vector<int64_t> vert_off(nr + 1);
+    HIP_OK(hipMemcpyAsync(vert_off.data(), polys->vert_off, sizeof(int64_t) * (nr + 1),
+                          hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (vert_off[0] != 0) return SBA_EINVAL;
+    for (int32_t r = 0; r < nr; r++)
+        if (vert_off[r + 1] < vert_off[r]) return SBA_EINVAL;
+    for (int32_t p = 0; p < np; p++)
+        if (vert_off[ring_off[p + 1]] == vert_off[ring_off[p]]) return SBA_EINVAL;
+    const int64_t nv = vert_off[nr];
+    if (nv > ((int64_t)1 << 31) - 1) return SBA_ELIMIT;
+    B.n_edges = nv;
+
+    int4 *bbox = nullptr;
+    RC(B.alloc(&bbox, np));
+    RC(B.alloc(&B.edges, nv));
+    RC(B.alloc(&B.epoly, nv));
+    hipLaunchKernelGGL(k_poly_bbox, dim3(grid_for((int64_t)np * 64)), dim3(256), 0, st,
+                       polys->ring_off, polys->vert_off, polys->xy, np, bbox, err);
+    hipLaunchKernelGGL(k_edges, dim3(grid_for(nv)), dim3(256), 0, st, polys->ring_off, np,
+                       polys->vert_off, nr, polys->xy, nv, B.edges, B.epoly);
+    HIP_OK(hipGetLastError());
+    std::vector<int4> hb(np);
+    int herr = 0;
+    HIP_OK(hipMemcpyAsync(hb.data(), bbox, sizeof(int4) * np, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (herr) return SBA_ERANGE;
+
+    const int64_t s = h->s;
+    int64_t gi0 = INT64_MAX, gj0 = INT64_MAX, gi1 = INT64_MIN, gj1 = INT64_MIN;
+    int64_t cmin = INT64_MAX, cmax = INT64_MIN;
+    for (int32_t p = 0; p < np; p++) {
+        gi0 = std::min(gi0, ceildiv64(hb[p].x, s) - 1);
+        gj0 = std::min(gj0, ceildiv64(hb[p].y, s) - 1);
+        gi1 = std::max(gi1, floordiv64(hb[p].z, s));
+        gj1 = std::max(gj1, floordiv64(hb[p].w, s));
+        cmin = std::min<int64_t>(cmin, std::min(hb[p].x, hb[p].y));
+        cmax = std::max<int64_t>(cmax, std::max(hb[p].z, hb[p].w));
+    }
+    B.cmin = cmin;
+    B.cmax = cmax;
+    h->gi0 = gi0;
+    h->gj0 = gj0;
+    h->gw = gi1 - gi0 + 1;
+    h->gh = gj1 - gj0 + 1;
+    if (h->gw > MAX_GRID_SIDE || h->gh > MAX_GRID_SIDE) return SBA_ELIMIT;
+    if (h->gw * s >= ((int64_t)1 << 31) || h->gh * s >= ((int64_t)1 << 31)) return SBA_ELIMIT;
+    const int64_t gw = h->gw, gh = h->gh;
+    B.xbits = bits_for((uint64_t)gw);
+    B.rbits = bits_for((uint64_t)(gh - 1));
+    if (B.rbits < 1) B.rbits = 1;
+    const int pbits = bits_for((uint64_t)(np - 1)) < 1 ? 1 : bits_for((uint64_t)(np - 1));
+
+    // 1-2: boundary intervals and crossings per edge
+    int64_t *nb = nullptr, *nc = nullptr, *tot = nullptr;
+    RC(B.alloc(&nb, nv + 1));
+    RC(B.alloc(&nc, nv + 1));
+    RC(B.alloc(&tot, 2));
+    hipLaunchKernelGGL(k_edge_counts, dim3(grid_for(nv)), dim3(256), 0, st, B.edges, nv, s, nb, nc);
+    HIP_OK(hipGetLastError());
+    RC(scan_exclusive_i64(nb, nb, nv, tot, st));
+    RC(scan_exclusive_i64(nc, nc, nv, tot + 1, st));
+    int64_t ht[2];
+    HIP_OK(hipMemcpyAsync(ht, tot, sizeof(ht), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    const int64_t NB = ht[0], NC = ht[1];
+    if (NC % 2) return SBA_EDEVICE;
+    h->n_boundary = NB;
+    B.NB = NB;
+    const int64_t NE = 2 * NB + NC;
+    if (NE >= ((int64_t)1 << 32)) return SBA_ELIMIT;
+    RC(B.alloc(&B.evkey, NE));
+    RC(B.alloc(&B.evpay, NE));
+    if (NB)
+        hipLaunchKernelGGL(k_emit_boundary, dim3(grid_for(NB)), dim3(256), 0, st, B.edges, B.epoly,
+                           nv, nb, NB, s, gi0, gj0, B.xbits, B.evkey, B.evpay);
+    if (NC) {
+        uint64_t *ckey = nullptr;
+        RC(B.alloc(&ckey, NC));
+        hipLaunchKernelGGL(k_emit_cross, dim3(grid_for(NC)), dim3(256), 0, st, B.edges, B.epoly, nv,
+                           nc, NC, s, gi0, gj0, B.xbits, B.rbits, ckey);
+        HIP_OK(hipGetLastError());
+        RC(radix_sort_u64(ckey, nullptr, NC, pbits + B.rbits + B.xbits, st));
+        hipLaunchKernelGGL(k_spans, dim3(grid_for(NC / 2)), dim3(256), 0, st, ckey, NC / 2, B.xbits,
+                           B.rbits, B.evkey + 2 * NB, B.evpay + 2 * NB, err);
+        HIP_OK(hipGetLastError());
+        B.release(ckey);
+    }
+    HIP_OK(hipGetLastError());
+    B.release(nb);
+    B.release(nc);
+
+    // the Hilbert layout needs the boundary cells before the events are sorted
+    if (B.on_boundary_events) RC(B.on_boundary_events(B, h, st));
+
+    // 3: events by (row, x), sweep per row
+    RC(radix_sort_u64(B.evkey, B.evpay, NE, B.rbits + B.xbits, st));
+    int64_t *ev_row_off = nullptr;
+    RC(B.alloc(&ev_row_off, gh + 1));
+    hipLaunchKernelGGL(k_row_off, dim3(grid_for(gh + 1)), dim3(256), 0, st, B.evkey, NE, gh, B.xbits,
+                       ev_row_off);
+    int64_t *cs = nullptr, *cm = nullptr, *cme = nullptr;
+    RC(B.alloc(&cs, gh + 1));
+    RC(B.alloc(&cm, gh + 1));
+    RC(B.alloc(&cme, gh + 1));
+    hipLaunchKernelGGL(k_sweep<false>, dim3(grid_for(gh, 64)), dim3(64), 0, st, B.evkey, B.evpay,
+                       ev_row_off, gh, B.xbits, cs, cm, cme, (const int64_t *)nullptr,
+                       (const int64_t *)nullptr, (const int64_t *)nullptr, (int32_t *)nullptr,
+                       (int32_t *)nullptr, (uint32_t *)nullptr, (int64_t *)nullptr,
+                       (int64_t *)nullptr, (int32_t *)nullptr, err);
+    HIP_OK(hipGetLastError());
+    int64_t *tt = nullptr;
+    RC(B.alloc(&tt, 3));
+    RC(scan_exclusive_i64(cs, cs, gh, tt, st));
+    RC(scan_exclusive_i64(cm, cm, gh, tt + 1, st));
+    RC(scan_exclusive_i64(cme, cme, gh, tt + 2, st));
+    int64_t h3[3];
+    HIP_OK(hipMemcpyAsync(h3, tt, sizeof(h3), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (herr & 8) return SBA_ELIMIT;
+    if (herr) return SBA_EDEVICE;
+    const int64_t NS = h3[0], NM = h3[1], NMEM = h3[2];
+    if (NS >= ((int64_t)1 << 31)) return SBA_ELIMIT;
+    HIP_OK(hipMemcpyAsync(cs + gh, &NS, sizeof(int64_t), hipMemcpyHostToDevice, st));
+    h->n_segments = NS;
+    B.NS = NS;
+    B.seg_row_off = cs;
+    RC(B.alloc(&B.seg_x0, NS));
+    RC(B.alloc(&B.seg_x1, NS));
+    RC(B.alloc(&B.seg_code, NS));
+    int64_t *multi_seg = nullptr, *multi_mem = nullptr;
+    int32_t *mem_ids = nullptr;
+    RC(B.alloc(&multi_seg, NM));
+    RC(B.alloc(&multi_mem, NM));
+    RC(B.alloc(&mem_ids, NMEM));
+    hipLaunchKernelGGL(k_sweep<true>, dim3(grid_for(gh, 64)), dim3(64), 0, st, B.evkey, B.evpay,
+                       ev_row_off, gh, B.xbits, (int64_t *)nullptr, (int64_t *)nullptr,
+                       (int64_t *)nullptr, cs, cm, cme, B.seg_x0, B.seg_x1, B.seg_code, multi_seg,
+                       multi_mem, mem_ids, err);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(st));
+    B.release(B.evkey);
+    B.evkey = nullptr;
+    B.release(B.evpay);
+    B.evpay = nullptr;
+    B.release(ev_row_off);
+    B.release(cm);
+    B.release(cme);
+
+    // 4: deduplicate the sets of multi-polygon segments
+    h->n_sets = 0;
+    h->n_set_ids = 0;
+    if (NM > 0) {
+        uint64_t *mkey = nullptr;
+        uint32_t *mval = nullptr;
+        int64_t *g = nullptr, *set_sz = nullptr;
+        RC(B.alloc(&mkey, NM));
+        RC(B.alloc(&mval, NM));
+        RC(B.alloc(&g, NM + 1));
+        hipLaunchKernelGGL(k_multi_keys, dim3(grid_for(NM)), dim3(256), 0, st, multi_mem, NM, NMEM,
+                           mem_ids, mkey, mval);
+        HIP_OK(hipGetLastError());
+        RC(radix_sort_u64(mkey, mval, NM, 64, st));
+        hipLaunchKernelGGL(k_flag_new, dim3(grid_for(NM)), dim3(256), 0, st, mkey, NM, g);
+        HIP_OK(hipGetLastError());
+        RC(scan_exclusive_i64(g, g, NM, tot, st));
+        int64_t nsets = 0;
+        HIP_OK(hipMemcpyAsync(&nsets, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        RC(B.alloc(&set_sz, nsets + 1));
+        hipLaunchKernelGGL(k_set_sizes, dim3(grid_for(NM)), dim3(256), 0, st, mkey, mval, g, NM,
+                           multi_mem, NM, NMEM, set_sz);
+        HIP_OK(hipGetLastError());
+        RC(dev_alloc(&h->set_off, nsets + 1));
+        RC(scan_exclusive_i64(set_sz, h->set_off, nsets, h->set_off + nsets, st));
+        int64_t nids = 0;
+        HIP_OK(hipMemcpyAsync(&nids, h->set_off + nsets, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        RC(dev_alloc(&h->set_ids, nids));
+        hipLaunchKernelGGL(k_set_fill, dim3(grid_for(NM)), dim3(256), 0, st, mkey, mval, g, NM,
+                           multi_mem, NM, NMEM, mem_ids, h->set_off, h->set_ids, multi_seg,
+                           B.seg_code);
+        HIP_OK(hipGetLastError());
+        h->n_sets = nsets;
+        h->n_set_ids = nids;
+        h->bytes += (nsets + 1) * 8 + nids * 4;
+        HIP_OK(hipStreamSynchronize(st));
+        B.release(mkey);
+        B.release(mval);
+        B.release(g);
+        B.release(set_sz);
+    }
+    B.release(multi_seg);
+    B.release(multi_mem);
+    B.release(mem_ids);
+    if (h->n_sets >= (int64_t)(TILE_MIXED - CODE_SET_BASE)) return SBA_ELIMIT;
+    return 0;
+}
+
+int build_grid(sba_handle *h, BuildState &B, int tile_log2, hipStream_t st)
+{
+    int64_t side = std::max(h->gw, h->gh);
+    int tl = tile_log2;
+    if (tl == 0) {
+        tl = 3;
+        while (tl < 7 && (side >> tl) > 512) tl++;
+    }
+    if (tl < 3 || tl > 8) return SBA_EINVAL;
+    h->tile_log2 = tl;
+    h->tw = (h->gw + (1 << tl) - 1) >> tl;
+    h->th = (h->gh + (1 << tl) - 1) >> tl;
+    const int64_t nt = h->tw * h->th;
+    if (nt >= ((int64_t)1 << 31)) return SBA_ELIMIT;
+    RC(dev_alloc(&h->dir, nt));
+    h->bytes += nt * 4;
+    int64_t *mixed = nullptr, *tot = nullptr;
+    RC(B.alloc(&mixed, nt + 1));
+    RC(B.alloc(&tot, 1));
+    hipLaunchKernelGGL(k_tile_classify, dim3(grid_for(nt * 64)), dim3(256), 0, st, B.seg_row_off,
+                       B.seg_x0, B.seg_x1, B.seg_code, h->gw, h->gh, tl, h->tw, nt, h->dir, mixed);
+    HIP_OK(hipGetLastError());
+    RC(scan_exclusive_i64(mixed, mixed, nt, tot, st));
+    int64_t nblk = 0;
+    HIP_OK(hipMemcpyAsync(&nblk, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (nblk >= (int64_t)TILE_MIXED) return SBA_ELIMIT;
+    h->n_blocks = nblk;
+    RC(dev_alloc(&h->blocks, nblk << (2 * tl)));
+    h->bytes += (nblk << (2 * tl)) * 4;
+    hipLaunchKernelGGL(k_tile_fill, dim3((unsigned)nt), dim3(256), 0, st, B.seg_row_off, B.seg_x0,
+                       B.seg_x1, B.seg_code, h->gw, h->gh, tl, h->tw, h->dir, mixed, h->blocks);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(st));
+    return 0;
+}
+
+int segments_lookup(const BuildState &B, const sba_handle *h, const int64_t *ij, int64_t n,
+                    uint32_t *out, hipStream_t st)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_lookup_ij, dim3(grid_for(n)), dim3(256), 0, st, B.seg_row_off, B.seg_x0,
+                       B.seg_x1, B.seg_code, h->gi0, h->gj0, h->gw, h->gh, ij, n, out);
+    HIP_OK(hipGetLastError());
+    return 0;
+}
+
+int build_handle(const sba_polygons *polys, int64_t eps, const sba_build_opts *opts,
+                 hipStream_t st, sba_handle *h)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    sba_build_opts o = {SBA_KIND_GRID, SBA_SEARCH_BINARY, 16, 0};
+    if (opts) o = *opts;
+    if (o.log2_leaves == 0) o.log2_leaves = 16;
+    if (o.kind != SBA_KIND_GRID && o.kind != SBA_KIND_HILBERT) return SBA_EINVAL;
+    if (o.search != SBA_SEARCH_BINARY && o.search != SBA_SEARCH_LEARNED) return SBA_EINVAL;
+    if (o.log2_leaves < 1 || o.log2_leaves > 24) return SBA_EINVAL;
+    h->kind = o.kind;
+    h->search = o.search;
+    h->eps = eps;
+    int64_t t = eps * eps / 2, s = 0;
+    while ((s + 1) * (s + 1) <= t) {  // isqrt by bisection-free doubling + linear finish
+        int64_t step = 1;
+        while ((s + 2 * step) * (s + 2 * step) <= t) step *= 2;
+        s += step;
+    }
+    h->s = s;
+    magic_for(s, &h->mag, &h->shift);
+    h->n_polys = polys->n_polys;
+    if (polys->n_polys == 0) {
+        h->gw = h->gh = 0;
+        h->build_ms = 0;
+        return 0;
+    }
+    BuildState B;
+    B.st = st;
+    if (h->kind == SBA_KIND_HILBERT) RC(hilbert_prepare(B, h));
+    RC(build_segments(polys, eps, st, h, B, h->kind == SBA_KIND_HILBERT));
+    if (h->kind == SBA_KIND_GRID) {
+        RC(build_grid(h, B, o.tile_log2, st));
+    } else {
+        RC(hilbert_finish(B, h, o, st));
+    }
+    HIP_OK(hipStreamSynchronize(st));
+    auto t1 = std::chrono::steady_clock::now();
+    h->build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    return 0;
+}

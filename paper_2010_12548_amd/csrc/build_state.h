@@ -1,0 +1,54 @@
+// build_state.h -- temporaries shared by the build stages (build.hip,
+// hilbert.hip).  Not part of the public ABI.
+#pragma once
+
+#include <algorithm>
+#include <vector>
+
+#include "sba_internal.h"
+
+struct BuildState {
+    hipStream_t st = nullptr;
+    std::vector<void *> owned;
+
+    template <typename T>
+    int alloc(T **p, int64_t n)
+    {
+        int rc = dev_alloc(p, n);
+        if (!rc) owned.push_back((void *)*p);
+        return rc;
+    }
+    void release(void *p)
+    {
+        auto it = std::find(owned.begin(), owned.end(), p);
+        if (it == owned.end()) return;
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(p);
+        owned.erase(it);
+    }
+    ~BuildState();
+
+    // edges: (x1,y1,x2,y2) and polygon id, one per vertex
+    int4 *edges = nullptr;
+    int32_t *epoly = nullptr;
+    int64_t n_edges = 0;
+    int64_t cmin = 0, cmax = 0;  // smallest / largest vertex coordinate
+    int xbits = 0, rbits = 0;    // event key fields: row << xbits | x
+    int64_t NB = 0;              // boundary intervals (events [0, 2 NB) until sorted)
+    uint64_t *evkey = nullptr;
+    uint32_t *evpay = nullptr;
+    // row segments of constant polygon set
+    int64_t NS = 0;
+    int64_t *seg_row_off = nullptr;  // [gh+1]
+    int32_t *seg_x0 = nullptr, *seg_x1 = nullptr;
+    uint32_t *seg_code = nullptr;
+    // Hilbert layout: unique keys of boundary cells
+    int (*on_boundary_events)(BuildState &, sba_handle *, hipStream_t) = nullptr;
+    uint64_t *bkeys = nullptr;
+    int64_t nbkeys = 0;
+};
+
+int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_handle *h,
+                   BuildState &B, bool need_boundary_cells);
+int hilbert_prepare(BuildState &B, sba_handle *h);
+int hilbert_finish(BuildState &B, sba_handle *h, const sba_build_opts &o, hipStream_t st);

@@ -1,0 +1,380 @@
+// hilbert.hip -- the adaptive-quadtree layout: the approximation stored as
+// the maximal runs of consecutive Hilbert keys whose cells carry the same
+// polygon set (Sec. 3: cells linearised on a space-filling curve and kept in
+// a sorted array; a run of the curve is a union of aligned quadtree blocks,
+// so interior cells come out as large cells, Sec. 2.2), and the learned
+// index that predicts a key's run (Sec. 3, learned index over the sorted
+// cell array).
+//
+// Runs are found without visiting interior cells.  Consecutive Hilbert cells
+// share an edge; two edge-adjacent cells that are boundary cells of no
+// polygon have the same polygon set (a polygon boundary separating them
+// would touch both closed squares).  So the polygon set is constant on every
+// gap between consecutive boundary keys, and one lookup at the gap's first
+// cell gives it.
+#include "sba_internal.h"
+#include "build_state.h"
+
+__device__ __forceinline__ int64_t ub_i64(const int64_t *a, int64_t n, int64_t v)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] <= v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// cells of boundary interval t that lie in the key domain [0, side)^2
+__global__ void k_bcell_counts(const uint64_t *evkey, int64_t nb, int xbits, int64_t gi0,
+                               int64_t gj0, int64_t side, int64_t *cnt)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb) return;
+    uint64_t xm = (1ull << xbits) - 1;
+    int64_t j = gj0 + (int64_t)(evkey[2 * t] >> xbits);
+    int64_t i0 = gi0 + (int64_t)(evkey[2 * t] & xm), i1 = gi0 + (int64_t)(evkey[2 * t + 1] & xm);
+    i0 = max(i0, (int64_t)0);
+    i1 = min(i1, side);
+    cnt[t] = (j < 0 || j >= side || i1 <= i0) ? 0 : i1 - i0;
+}
+
+__global__ void k_bcell_keys(const uint64_t *evkey, int64_t nb, int xbits, int64_t gi0,
+                             int64_t gj0, const int64_t *off, int64_t ncells, int L,
+                             uint64_t *keys)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    int64_t t = ub_i64(off, nb, c) - 1;
+    uint64_t xm = (1ull << xbits) - 1;
+    int64_t j = gj0 + (int64_t)(evkey[2 * t] >> xbits);
+    int64_t i0 = max(gi0 + (int64_t)(evkey[2 * t] & xm), (int64_t)0);
+    int64_t i = i0 + (c - off[t]);
+    keys[c] = hilbert_index(L, (uint32_t)i, (uint32_t)j);
+}
+
+__global__ void k_flag_first(const uint64_t *keys, int64_t n, int64_t *flag)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    flag[t] = (t == 0 || keys[t] != keys[t - 1]) ? 1 : 0;
+}
+
+__global__ void k_compact_first(const uint64_t *keys, int64_t n, const int64_t *pos, uint64_t *out)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    if (t == 0 || keys[t] != keys[t - 1]) out[pos[t]] = keys[t];
+}
+
+static int hilbert_boundary_cells(BuildState &B, sba_handle *h, hipStream_t st)
+{
+    const int64_t side = (int64_t)1 << h->level;
+    const int64_t NB = B.NB;
+    if (NB == 0) return 0;
+    int64_t *cnt = nullptr, *tot = nullptr;
+    RC(B.alloc(&cnt, NB + 1));
+    RC(B.alloc(&tot, 1));
+    hipLaunchKernelGGL(k_bcell_counts, dim3(grid_for(NB)), dim3(256), 0, st, B.evkey, NB, B.xbits,
+                       h->gi0, h->gj0, side, cnt);
+    HIP_OK(hipGetLastError());
+    RC(scan_exclusive_i64(cnt, cnt, NB, tot, st));
+    int64_t nc = 0;
+    HIP_OK(hipMemcpyAsync(&nc, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (nc == 0) return 0;
+    uint64_t *keys = nullptr;
+    RC(B.alloc(&keys, nc));
+    hipLaunchKernelGGL(k_bcell_keys, dim3(grid_for(nc)), dim3(256), 0, st, B.evkey, NB, B.xbits,
+                       h->gi0, h->gj0, cnt, nc, h->level, keys);
+    HIP_OK(hipGetLastError());
+    B.release(cnt);
+    RC(radix_sort_u64(keys, nullptr, nc, 2 * h->level, st));
+    int64_t *flag = nullptr;
+    RC(B.alloc(&flag, nc + 1));
+    hipLaunchKernelGGL(k_flag_first, dim3(grid_for(nc)), dim3(256), 0, st, keys, nc, flag);
+    HIP_OK(hipGetLastError());
+    RC(scan_exclusive_i64(flag, flag, nc, tot, st));
+    int64_t nu = 0;
+    HIP_OK(hipMemcpyAsync(&nu, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    RC(B.alloc(&B.bkeys, nu));
+    hipLaunchKernelGGL(k_compact_first, dim3(grid_for(nc)), dim3(256), 0, st, keys, nc, flag,
+                       B.bkeys);
+    HIP_OK(hipGetLastError());
+    B.nbkeys = nu;
+    B.release(keys);
+    B.release(flag);
+    return 0;
+}
+
+int hilbert_prepare(BuildState &B, sba_handle *h)
+{
+    (void)h;
+    B.on_boundary_events = [](BuildState &b, sba_handle *hh, hipStream_t st) -> int {
+        if (b.cmin < 0) return SBA_ERANGE;
+        int L = 1;
+        while (L < 31 && (((int64_t)1 << L) * hh->s) <= b.cmax) L++;
+        if (L > 21) return SBA_ELIMIT;
+        hh->level = L;
+        return hilbert_boundary_cells(b, hh, st);
+    };
+    return 0;
+}
+
+// ---------------------------------------------------------------- runs
+
+__device__ __forceinline__ uint32_t code_of_cell(const int64_t *seg_row_off, const int32_t *seg_x0,
+                                                 const int32_t *seg_x1, const uint32_t *seg_code,
+                                                 int64_t gi0, int64_t gj0, int64_t gw, int64_t gh,
+                                                 int64_t i, int64_t j)
+{
+    int64_t x = i - gi0, r = j - gj0;
+    if (x < 0 || r < 0 || x >= gw || r >= gh) return 0;
+    int64_t lo = seg_row_off[r], hi = seg_row_off[r + 1], a = lo;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (seg_x0[mid] <= (int32_t)x) lo = mid + 1; else hi = mid;
+    }
+    if (lo > a && (int32_t)x < seg_x1[lo - 1]) return seg_code[lo - 1];
+    return 0;
+}
+
+struct SegView {
+    const int64_t *row_off;
+    const int32_t *x0, *x1;
+    const uint32_t *code;
+    int64_t gi0, gj0, gw, gh;
+};
+
+__device__ __forceinline__ uint32_t code_of_key(const SegView &S, int L, uint64_t key)
+{
+    uint32_t i, j;
+    hilbert_cell(L, key, &i, &j);
+    return code_of_cell(S.row_off, S.x0, S.x1, S.code, S.gi0, S.gj0, S.gw, S.gh, i, j);
+}
+
+// candidate run starts: every boundary key, the key after it when a gap
+// follows, and key 0 when the first boundary key is not 0
+__global__ void k_cand_counts(const uint64_t *bk, int64_t nb, uint64_t total, int64_t *cnt)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb) return;
+    uint64_t next = (t + 1 < nb) ? bk[t + 1] : total;
+    cnt[t] = 1 + ((next > bk[t] + 1) ? 1 : 0);
+}
+
+__global__ void k_cand_write(const uint64_t *bk, int64_t nb, uint64_t total, const int64_t *off,
+                             int64_t lead, SegView S, int L, uint64_t *ckey, uint32_t *ccode)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0 && lead) {
+        ckey[0] = 0;
+        ccode[0] = code_of_key(S, L, 0);
+    }
+    if (t >= nb) return;
+    int64_t o = lead + off[t];
+    uint64_t k = bk[t];
+    ckey[o] = k;
+    ccode[o] = code_of_key(S, L, k);
+    uint64_t next = (t + 1 < nb) ? bk[t + 1] : total;
+    if (next > k + 1) {
+        ckey[o + 1] = k + 1;
+        ccode[o + 1] = code_of_key(S, L, k + 1);
+    }
+}
+
+__global__ void k_run_flags(const uint32_t *ccode, int64_t n, int64_t *flag)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    flag[t] = (t == 0 || ccode[t] != ccode[t - 1]) ? 1 : 0;
+}
+
+__global__ void k_run_write(const uint64_t *ckey, const uint32_t *ccode, int64_t n,
+                            const int64_t *pos, uint64_t *starts, uint32_t *starts32,
+                            uint32_t *rcode)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    if (t == 0 || ccode[t] != ccode[t - 1]) {
+        int64_t g = pos[t];
+        starts[g] = ckey[t];
+        if (starts32) starts32[g] = (uint32_t)ckey[t];
+        rcode[g] = ccode[t];
+    }
+}
+
+// ---------------------------------------------------------------- learned index
+//
+// Two-level piecewise-linear model over the sorted run starts (the idea of a
+// learned index over a sorted cell array with a bounded last-mile search,
+// Sec. 3).  Root: leaf = floor(key * a) in fp32, clamped, monotone in key.
+// Leaf l covers the keys [K_l, K_{l+1}); it predicts the position of the run
+// holding a key as floor(slope * (key - K_l) + icpt) in fp32 (no fused
+// multiply-add, identical in the fit and in the probe), fitted by least
+// squares on the leaf's run starts.  Its stored error bounds |prediction -
+// answer| over EVERY key of [K_l, K_{l+1}), not only the stored ones: the
+// answer is a step function of the key and the prediction is monotone, so the
+// largest gap sits at an end of a step, and the fit evaluates exactly those
+// keys.  The probe still verifies the bracket and falls back to a full binary
+// search if it ever fails.
+
+// smallest key whose leaf is >= l (keys in [0, total])
+__device__ uint64_t leaf_first_key(uint32_t l, float a, uint32_t nl, uint64_t total)
+{
+    if (l == 0) return 0;
+    uint64_t lo = 0, hi = total;
+    while (lo < hi) {
+        uint64_t mid = lo + ((hi - lo) >> 1);
+        if (root_leaf(mid, a, nl) >= l) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int64_t lower_bound_u64(const uint64_t *a, int64_t n, uint64_t v)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// one wavefront per leaf: key range, least-squares fit, exact error bound
+__global__ void k_leaf_fit(const uint64_t *starts, int64_t n, float a, uint32_t nl, uint64_t total,
+                           uint64_t *kfirst, int4 *leaves, int64_t *max_err)
+{
+    int64_t l = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    int lane = threadIdx.x & 63;
+    if (l >= nl) return;
+    uint64_t K0 = leaf_first_key((uint32_t)l, a, nl, total);
+    uint64_t K1 = (l + 1 < nl) ? leaf_first_key((uint32_t)l + 1, a, nl, total) : total;
+    int64_t lo = lower_bound_u64(starts, n, K0), hi = lower_bound_u64(starts, n, K1);
+    // least squares of y = q - lo against x = starts[q] - K0 over q in [lo, hi)
+    double sx = 0, sy = 0, sxx = 0, sxy = 0;
+    for (int64_t q = lo + lane; q < hi; q += 64) {
+        double x = (double)(starts[q] - K0), y = (double)(q - lo);
+        sx += x; sy += y; sxx += x * x; sxy += x * y;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        sx += __shfl_xor(sx, o, 64);
+        sy += __shfl_xor(sy, o, 64);
+        sxx += __shfl_xor(sxx, o, 64);
+        sxy += __shfl_xor(sxy, o, 64);
+    }
+    double cnt = (double)(hi - lo);
+    float slope = 0.f, icpt;
+    if (hi - lo >= 2) {
+        double mx = sx / cnt, my = sy / cnt;
+        double var = sxx / cnt - mx * mx, cov = sxy / cnt - mx * my;
+        double sl = var > 0 ? cov / var : 0.0;
+        if (sl < 0) sl = 0;
+        slope = (float)sl;
+        icpt = (float)(my - sl * mx + (double)lo);
+    } else if (hi - lo == 1) {
+        icpt = (float)lo;
+    } else {
+        icpt = (float)(lo - 1);
+    }
+    // error over every key of [K0, K1): the answer is q on [max(starts[q],K0),
+    // min(starts[q+1],K1) - 1] for q in [lo-1, hi-1]; check both ends of each step
+    int64_t err = 0;
+    if (K1 > K0) {
+        for (int64_t q = lo - 1 + lane; q <= hi - 1; q += 64) {
+            if (q < 0) continue;  // keys before the first start do not occur (starts[0] = 0)
+            uint64_t ka = starts[q] > K0 ? starts[q] : K0;
+            uint64_t kb = (q + 1 < n && starts[q + 1] < K1) ? starts[q + 1] - 1 : K1 - 1;
+            if (ka > kb) continue;
+            int64_t pa = predict(K0, slope, icpt, ka), pb = predict(K0, slope, icpt, kb);
+            int64_t e1 = pa > q ? pa - q : q - pa, e2 = pb > q ? pb - q : q - pb;
+            err = max(err, max(e1, e2));
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        int64_t v = __shfl_xor(err, o, 64);
+        err = max(err, v);
+    }
+    if (lane == 0) {
+        kfirst[l] = K0;
+        leaves[l] = make_int4((int)(uint32_t)K0, __float_as_int(slope), __float_as_int(icpt),
+                              (int)err);
+        atomicMax((unsigned long long *)max_err, (unsigned long long)err);
+    }
+}
+
+int hilbert_finish(BuildState &B, sba_handle *h, const sba_build_opts &o, hipStream_t st)
+{
+    const int L = h->level;
+    const uint64_t total = (uint64_t)1 << (2 * L);
+    const int64_t nb = B.nbkeys;
+    const int64_t lead = 1;  // key 0 always opens a run (a boundary key 0 repeats it)
+    SegView S{B.seg_row_off, B.seg_x0, B.seg_x1, B.seg_code, h->gi0, h->gj0, h->gw, h->gh};
+    int64_t *cnt = nullptr, *tot = nullptr;
+    RC(B.alloc(&cnt, nb + 1));
+    RC(B.alloc(&tot, 1));
+    if (nb)
+        hipLaunchKernelGGL(k_cand_counts, dim3(grid_for(nb)), dim3(256), 0, st, B.bkeys, nb, total,
+                           cnt);
+    HIP_OK(hipGetLastError());
+    RC(scan_exclusive_i64(cnt, cnt, nb, tot, st));
+    int64_t nc = 0;
+    if (nb) {
+        HIP_OK(hipMemcpyAsync(&nc, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+    }
+    nc += lead;
+    uint64_t *ckey = nullptr;
+    uint32_t *ccode = nullptr;
+    RC(B.alloc(&ckey, nc));
+    RC(B.alloc(&ccode, nc));
+    // a boundary key equal to 0 writes over the leading candidate with the same values
+    hipLaunchKernelGGL(k_cand_write, dim3(grid_for(nb > 0 ? nb : 1)), dim3(256), 0, st, B.bkeys, nb,
+                       total, cnt, lead, S, L, ckey, ccode);
+    HIP_OK(hipGetLastError());
+    int64_t *flag = nullptr;
+    RC(B.alloc(&flag, nc + 1));
+    hipLaunchKernelGGL(k_run_flags, dim3(grid_for(nc)), dim3(256), 0, st, ccode, nc, flag);
+    HIP_OK(hipGetLastError());
+    RC(scan_exclusive_i64(flag, flag, nc, tot, st));
+    int64_t nr = 0;
+    HIP_OK(hipMemcpyAsync(&nr, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (nr >= ((int64_t)1 << 31)) return SBA_ELIMIT;
+    h->n_runs = nr;
+    RC(dev_alloc(&h->starts, nr));
+    RC(dev_alloc(&h->run_code, nr));
+    h->bytes += nr * 12;
+    if (2 * L <= 32) {
+        RC(dev_alloc(&h->starts32, nr));
+        h->bytes += nr * 4;
+    }
+    hipLaunchKernelGGL(k_run_write, dim3(grid_for(nc)), dim3(256), 0, st, ckey, ccode, nc, flag,
+                       h->starts, h->starts32, h->run_code);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(st));
+
+    if (o.search == SBA_SEARCH_LEARNED) {
+        if (2 * L > 32) return SBA_ELIMIT;  // leaves store 32-bit key bases
+        const uint32_t nl = 1u << o.log2_leaves;
+        h->log2_leaves = o.log2_leaves;
+        uint64_t last = 0;
+        HIP_OK(hipMemcpy(&last, h->starts + (nr - 1), sizeof(uint64_t), hipMemcpyDeviceToHost));
+        h->root_k0 = 0;
+        h->root_a = (float)nl / (float)(last + 1);
+        uint64_t *kfirst = nullptr;
+        int64_t *merr = nullptr;
+        RC(B.alloc(&kfirst, nl));
+        RC(B.alloc(&merr, 1));
+        HIP_OK(hipMemsetAsync(merr, 0, sizeof(int64_t), st));
+        RC(dev_alloc(&h->leaves, nl));
+        h->bytes += (int64_t)nl * 16;
+        hipLaunchKernelGGL(k_leaf_fit, dim3(grid_for((int64_t)nl * 64)), dim3(256), 0, st, h->starts,
+                           nr, h->root_a, nl, total, kfirst, h->leaves, merr);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpyAsync(&h->max_leaf_err, merr, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+    }
+    return 0;
+}

@@ -1,0 +1,294 @@
+// prims.hip -- device-wide exclusive scan and LSD radix sort used by the
+// approximation build.  Written for 64-lane wavefronts.
+#include "sba_internal.h"
+
+#define SCAN_BLOCK 256
+#define SCAN_ITEMS 8
+#define SCAN_TILE (SCAN_BLOCK * SCAN_ITEMS)
+
+// inclusive scan across a 64-lane wavefront
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// exclusive scan across the block (blockDim.x == 256); returns the block total
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T *excl)
+{
+    __shared__ T wsum[SCAN_BLOCK / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    T inc = wave_incl_scan(v);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    T off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_BLOCK / 64; k++) {
+        if (k < w) off += wsum[k];
+        tot += wsum[k];
+    }
+    __syncthreads();
+    *excl = off + inc - v;
+    return tot;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tiles(const int64_t *in, int64_t *out,
+                                                           int64_t n, int64_t *tile_sums)
+{
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int64_t v[SCAN_ITEMS];
+    int64_t run = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        int64_t idx = base + k;
+        v[k] = idx < n ? in[idx] : 0;
+        run += v[k];
+    }
+    int64_t excl;
+    int64_t tot = block_excl_scan<int64_t>(run, &excl);
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        int64_t idx = base + k;
+        if (idx < n) out[idx] = excl;
+        excl += v[k];
+    }
+    if (threadIdx.x == 0 && tile_sums) tile_sums[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_add(int64_t *out, int64_t n, const int64_t *tile_offs)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) out[idx] += tile_offs[idx / SCAN_TILE];
+}
+
+__global__ void k_scan_total(const int64_t *in, const int64_t *out, int64_t n, int64_t *total)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) total[0] = n > 0 ? out[n - 1] + in[n - 1] : 0;
+}
+
+// The last input element must be read before the scan overwrites it when
+// in == out; keep a copy.
+__global__ void k_copy_last(const int64_t *in, int64_t n, int64_t *dst)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = n > 0 ? in[n - 1] : 0;
+}
+
+__global__ void k_add_last(const int64_t *out, int64_t n, const int64_t *last, int64_t *total)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) total[0] = n > 0 ? out[n - 1] + last[0] : 0;
+}
+
+static int scan_rec(const int64_t *in, int64_t *out, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return 0;
+    int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (tiles == 1) {
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(SCAN_BLOCK), 0, st, in, out, n,
+                           (int64_t *)nullptr);
+        HIP_OK(hipGetLastError());
+        return 0;
+    }
+    int64_t *sums = nullptr;
+    RC(dev_alloc(&sums, tiles));
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, st, in, out, n,
+                       sums);
+    int rc = hipGetLastError() == hipSuccess ? 0 : SBA_EDEVICE;
+    if (!rc) rc = scan_rec(sums, sums, tiles, st);
+    if (!rc) {
+        hipLaunchKernelGGL(k_scan_add, dim3(grid_for(n)), dim3(256), 0, st, out, n, sums);
+        rc = hipGetLastError() == hipSuccess ? 0 : SBA_EDEVICE;
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(sums);
+    return rc;
+}
+
+int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t st)
+{
+    int64_t *last = nullptr;
+    if (total) {
+        RC(dev_alloc(&last, 1));
+        hipLaunchKernelGGL(k_copy_last, dim3(1), dim3(64), 0, st, in, n, last);
+    }
+    int rc = scan_rec(in, out, n, st);
+    if (!rc && total) {
+        hipLaunchKernelGGL(k_add_last, dim3(1), dim3(64), 0, st, out, n, last, total);
+        rc = hipGetLastError() == hipSuccess ? 0 : SBA_EDEVICE;
+    }
+    if (last) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(last);
+    }
+    return rc;
+}
+
+// ---------------------------------------------------------------- radix sort
+//
+// One pass per 8-bit digit, least significant first.  A block sorts a tile
+// of RS_TILE keys: each of its 4 waves owns a contiguous quarter and walks it
+// 64 keys at a time; lanes with equal digits find each other with 8 ballots,
+// so the rank of a key among equal digits before it is a popcount and the
+// pass is stable.  Keys are staged in LDS in digit order and written out in
+// runs, which keeps the global writes coalesced.
+
+#define RS_BLOCK 256
+#define RS_WAVES (RS_BLOCK / 64)
+#define RS_ROUNDS 16
+#define RS_TILE (RS_BLOCK * RS_ROUNDS)
+#define RS_RADIX 256
+
+__global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const uint64_t *keys, int64_t n, int shift,
+                                                      uint32_t *hist, int64_t nblocks)
+{
+    __shared__ uint32_t h[RS_RADIX];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int k = threadIdx.x; k < RS_TILE; k += RS_BLOCK) {
+        int64_t idx = base + k;
+        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 0xffu], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void k_u32_to_i64(const uint32_t *a, int64_t *b, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+template <bool HAS_VALS>
+__global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const uint64_t *keys, const uint32_t *vals,
+                                                         uint64_t *okeys, uint32_t *ovals,
+                                                         int64_t n, int shift,
+                                                         const int64_t *goff, int64_t nblocks)
+{
+    __shared__ uint32_t wcnt[RS_WAVES][RS_RADIX];
+    __shared__ uint32_t bdoff[RS_RADIX];
+    __shared__ uint64_t skeys[RS_TILE];
+    __shared__ uint32_t svals[HAS_VALS ? RS_TILE : 1];
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int k = threadIdx.x; k < RS_WAVES * RS_RADIX; k += RS_BLOCK) (&wcnt[0][0])[k] = 0;
+    __syncthreads();
+
+    const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t wbase = tbase + (int64_t)w * (64 * RS_ROUNDS);
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    uint64_t kk[RS_ROUNDS];
+    uint32_t vv[RS_ROUNDS];
+    uint32_t loc[RS_ROUNDS];
+#pragma unroll
+    for (int q = 0; q < RS_ROUNDS; q++) {
+        int64_t idx = wbase + q * 64 + lane;
+        bool valid = idx < n;
+        uint64_t key = valid ? keys[idx] : 0;
+        kk[q] = key;
+        if (HAS_VALS) vv[q] = valid ? vals[idx] : 0;
+        uint32_t d = (uint32_t)(key >> shift) & 0xffu;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            uint64_t bal = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        uint32_t old = wcnt[w][d];
+        uint32_t rank = (uint32_t)__popcll(peers & lt);
+        loc[q] = old + rank;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && (peers & lt) == 0) wcnt[w][d] = old + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // digit d = threadIdx.x: totals, wave prefixes, block-wide digit offsets
+    {
+        const int d = threadIdx.x;
+        uint32_t run = 0;
+#pragma unroll
+        for (int k = 0; k < RS_WAVES; k++) {
+            uint32_t c = wcnt[k][d];
+            wcnt[k][d] = run;
+            run += c;
+        }
+        uint32_t excl;
+        block_excl_scan<uint32_t>(run, &excl);
+        bdoff[d] = excl;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RS_ROUNDS; q++) {
+        int64_t idx = wbase + q * 64 + lane;
+        if (idx < n) {
+            uint32_t d = (uint32_t)(kk[q] >> shift) & 0xffu;
+            uint32_t p = bdoff[d] + wcnt[w][d] + loc[q];
+            skeys[p] = kk[q];
+            if (HAS_VALS) svals[p] = vv[q];
+        }
+    }
+    __syncthreads();
+    int64_t tn = n - tbase;
+    if (tn > RS_TILE) tn = RS_TILE;
+    for (int i = threadIdx.x; i < tn; i += RS_BLOCK) {
+        uint64_t key = skeys[i];
+        uint32_t d = (uint32_t)(key >> shift) & 0xffu;
+        int64_t g = goff[(int64_t)d * nblocks + blockIdx.x] + (i - (int64_t)bdoff[d]);
+        okeys[g] = key;
+        if (HAS_VALS) ovals[g] = svals[i];
+    }
+}
+
+int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st)
+{
+    if (n <= 1 || bits <= 0) return 0;
+    const int64_t nblocks = (n + RS_TILE - 1) / RS_TILE;
+    uint64_t *k2 = nullptr;
+    uint32_t *v2 = nullptr, *hist = nullptr;
+    int64_t *goff = nullptr;
+    int rc = dev_alloc(&k2, n);
+    if (!rc && vals) rc = dev_alloc(&v2, n);
+    if (!rc) rc = dev_alloc(&hist, nblocks * RS_RADIX);
+    if (!rc) rc = dev_alloc(&goff, nblocks * RS_RADIX);
+    uint64_t *ka = keys, *kb = k2;
+    uint32_t *va = vals, *vb = v2;
+    int passes = (bits + 7) / 8;
+    for (int p = 0; p < passes && !rc; p++) {
+        int shift = 8 * p;
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st, ka, n, shift,
+                           hist, nblocks);
+        hipLaunchKernelGGL(k_u32_to_i64, dim3(grid_for(nblocks * RS_RADIX)), dim3(256), 0, st, hist,
+                           goff, nblocks * RS_RADIX);
+        if (hipGetLastError() != hipSuccess) { rc = SBA_EDEVICE; break; }
+        rc = scan_exclusive_i64(goff, goff, nblocks * RS_RADIX, nullptr, st);
+        if (rc) break;
+        if (vals)
+            hipLaunchKernelGGL(k_rs_scatter<true>, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st, ka,
+                               va, kb, vb, n, shift, goff, nblocks);
+        else
+            hipLaunchKernelGGL(k_rs_scatter<false>, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st, ka,
+                               va, kb, vb, n, shift, goff, nblocks);
+        if (hipGetLastError() != hipSuccess) { rc = SBA_EDEVICE; break; }
+        uint64_t *tk = ka; ka = kb; kb = tk;
+        uint32_t *tv = va; va = vb; vb = tv;
+    }
+    if (!rc && ka != keys) {
+        if (hipMemcpyAsync(keys, ka, (size_t)n * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            rc = SBA_EDEVICE;
+        if (!rc && vals &&
+            hipMemcpyAsync(vals, va, (size_t)n * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            rc = SBA_EDEVICE;
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(k2);
+    (void)hipFree(v2);
+    (void)hipFree(hist);
+    (void)hipFree(goff);
+    return rc;
+}

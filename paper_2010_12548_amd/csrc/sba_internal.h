@@ -1,0 +1,223 @@
+// sba_internal.h -- types and device helpers shared by the HIP sources of
+// libsba (build, probe, primitives).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sba.h"
+
+// ---------------------------------------------------------------- codes
+//
+// A grid cell holds a 32-bit code:
+//   0                     no polygon
+//   1 .. 2^30-1           exactly polygon (code - 1)
+//   2^30 .. 2^31-1        the polygon set with index (code - 2^30)
+// A directory entry of the two-level grid holds either such a code (the
+// whole tile has it) or TILE_MIXED | block index (the tile's cells are
+// stored in a fine block).
+// The Hilbert layout and the lookup entry point use a signed "ref":
+//   -1 no polygon, p >= 0 exactly polygon p, -2-k the set with index k.
+#define CODE_SET_BASE 0x40000000u
+#define TILE_MIXED 0x80000000u
+#define MAX_POLYS ((1 << 21) - 1)
+#define MAX_DEPTH 32           // polygons per cell
+#define MAX_GRID_SIDE (1 << 21)
+
+__host__ __device__ inline int32_t code_to_ref(uint32_t c)
+{
+    if (c == 0) return -1;
+    if (c < CODE_SET_BASE) return (int32_t)(c - 1);
+    return -2 - (int32_t)(c - CODE_SET_BASE);
+}
+
+// ---------------------------------------------------------------- handle
+
+struct sba_handle {
+    int32_t kind, search;
+    int32_t n_polys;
+    int64_t eps, s;
+    // stored cell box
+    int64_t gi0, gj0, gw, gh;
+    // cell index from a coordinate: q = ((uint64)(c - origin) * mag) >> shift
+    uint32_t mag;
+    int32_t shift;
+    // grid layout
+    int32_t tile_log2;
+    int64_t tw, th;
+    uint32_t *dir;       // [tw*th]
+    uint32_t *blocks;    // [n_blocks << (2*tile_log2)]
+    int64_t n_blocks;
+    // polygon sets of multi-polygon cells
+    int64_t *set_off;    // [n_sets+1] (device)
+    int32_t *set_ids;    // [n_set_ids] (device)
+    int64_t n_sets, n_set_ids;
+    // Hilbert layout
+    int32_t level;
+    uint64_t *starts;    // [n_runs] run start keys
+    uint32_t *starts32;  // [n_runs] same keys when 2*level <= 32 (else NULL)
+    uint32_t *run_code;  // [n_runs] cell code of each run
+    int64_t n_runs;
+    // learned index over starts
+    int32_t log2_leaves;
+    float root_a;        // leaf = floor((float)(key - root_k0) * root_a)
+    uint64_t root_k0;
+    int4 *leaves;        // [2^log2_leaves] {key base (u32 bits), slope (f32 bits), icpt (f32 bits), err}
+    int64_t max_leaf_err;
+    // bookkeeping
+    int64_t n_segments, n_boundary;
+    int64_t bytes;
+    double build_ms;
+    int device;
+};
+
+// ---------------------------------------------------------------- helpers
+
+__host__ __device__ inline int64_t floordiv64(int64_t a, int64_t b)  // b > 0
+{
+    int64_t q = a / b;
+    return q - ((a % b != 0) & (a < 0));
+}
+
+__host__ __device__ inline int64_t ceildiv64(int64_t a, int64_t b)  // b > 0
+{
+    int64_t q = a / b;
+    return q + ((a % b != 0) & (a > 0));
+}
+
+// Division by the invariant cell side s for dividends 0 <= n < 2^31
+// (Granlund & Montgomery 1994, "Division by invariant integers using
+// multiplication", Thm. 4.2 with N = 31): with l = ceil(log2 s) and
+// m = ceil(2^(31+l) / s) < 2^32, floor(n / s) = (n * m) >> (31 + l).
+__host__ __device__ inline uint32_t divmagic(uint32_t n, uint32_t mag, int32_t shift)
+{
+    return (uint32_t)(((uint64_t)n * mag) >> shift);
+}
+
+void magic_for(int64_t s, uint32_t *mag, int32_t *shift);
+
+// Hilbert index d(i,j) of cell (i,j) on the 2^L x 2^L grid: quadrant order
+// (0,0),(0,1),(1,1),(1,0) at every level, sub-squares re-oriented so that
+// consecutive indices are edge-adjacent (Sec. 3, linearisation of cells).
+// Processed one level at a time from the top; the orientation state is kept
+// as a transpose flag and a reflection flag instead of rewriting i and j.
+__host__ __device__ inline uint64_t hilbert_index(int L, uint32_t i, uint32_t j)
+{
+    uint64_t d = 0;
+    uint32_t swap = 0, flip = 0;  // current frame: transpose, then complement
+    for (int lev = L - 1; lev >= 0; --lev) {
+        uint32_t bi = (i >> lev) & 1u, bj = (j >> lev) & 1u;
+        uint32_t x = (swap ? bj : bi) ^ flip;
+        uint32_t y = (swap ? bi : bj) ^ flip;
+        uint32_t q = (3u * x) ^ y;  // 0:(0,0) 1:(0,1) 2:(1,1) 3:(1,0)
+        d = (d << 2) | q;
+        if (y == 0) {             // lower quadrants are transposed,
+            if (x == 1) flip ^= 1u;  // the lower-right one also complemented
+            swap ^= 1u;
+        }
+    }
+    return d;
+}
+
+// Inverse of hilbert_index.
+__host__ __device__ inline void hilbert_cell(int L, uint64_t d, uint32_t *pi, uint32_t *pj)
+{
+    uint32_t i = 0, j = 0, swap = 0, flip = 0;
+    for (int lev = L - 1; lev >= 0; --lev) {
+        uint32_t q = (uint32_t)(d >> (2 * lev)) & 3u;
+        uint32_t x = (q >> 1) & 1u;            // q: 0->(0,0) 1->(0,1) 2->(1,1) 3->(1,0)
+        uint32_t y = (q == 1 || q == 2) ? 1u : 0u;
+        uint32_t fx = x ^ flip, fy = y ^ flip;  // undo the frame
+        uint32_t bi = swap ? fy : fx, bj = swap ? fx : fy;
+        i |= bi << lev;
+        j |= bj << lev;
+        if (y == 0) {
+            if (x == 1) flip ^= 1u;
+            swap ^= 1u;
+        }
+    }
+    *pi = i;
+    *pj = j;
+}
+
+// ---------------------------------------------------------------- learned index
+//
+// Root: leaf = floor(key * a) in fp32, clamped to [0, nl).  Leaf: predicted
+// run position floor(slope * (key - kbase) + icpt) in fp32 with separate
+// rounding of the product and the sum (no fused multiply-add), so the fit and
+// the probe compute bit-identical predictions.
+__device__ __forceinline__ uint32_t root_leaf(uint64_t key, float a, uint32_t nl)
+{
+    float f = __fmul_rn((float)key, a);
+    return (f >= (float)nl) ? nl - 1 : (uint32_t)f;
+}
+
+__device__ __forceinline__ int64_t predict(uint64_t kbase, float slope, float icpt, uint64_t key)
+{
+    float x = (float)(key - kbase);
+    float f = __fadd_rn(__fmul_rn(slope, x), icpt);
+    return (int64_t)floorf(f);
+}
+
+// ---------------------------------------------------------------- primitives (prims.hip)
+
+// Exclusive scan of n int64 values (in and out may alias).  If total is
+// non-null the grand total is written to total[0] (device).
+int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t st);
+
+// LSD radix sort by the low `bits` bits of keys (bits <= 64), stable,
+// carrying the optional 32-bit values.  On return keys/vals hold the sorted
+// data (the library ping-pongs through internal temporaries).
+int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st);
+
+// device allocation helper that records failures
+template <typename T>
+inline int dev_alloc(T **p, int64_t count)
+{
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    if (hipMalloc((void **)p, (size_t)count * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return SBA_ENOMEM;
+    }
+    return 0;
+}
+
+inline int bits_for(uint64_t maxval)  // bits needed to hold values in [0, maxval]
+{
+    int b = 0;
+    while (b < 64 && (maxval >> b) != 0) b++;
+    return b;
+}
+
+#define HIP_OK(x)                                   \
+    do {                                            \
+        if ((x) != hipSuccess) {                    \
+            (void)hipGetLastError();                \
+            return SBA_EDEVICE;                     \
+        }                                           \
+    } while (0)
+
+#define RC(x)                 \
+    do {                      \
+        int rc_ = (x);        \
+        if (rc_) return rc_;  \
+    } while (0)
+
+// Grid-size helper for element-wise kernels.
+inline unsigned grid_for(int64_t n, int block = 256)
+{
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+// Probe entry points (probe.hip).
+int probe_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
+                 int32_t search, uint64_t *counts, int64_t *sums, hipStream_t st);
+int lookup_launch(const sba_handle *h, const int64_t *ij, int64_t n, int32_t *ref, hipStream_t st);
+
+// Build entry point (build.hip).
+int build_handle(const sba_polygons *polys, int64_t eps, const sba_build_opts *opts,
+                 hipStream_t st, sba_handle *h);

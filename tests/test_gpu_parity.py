@@ -1,0 +1,275 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Per-cell polygon sets and per-polygon COUNT / SUM must be identical (integer
+work, bit-exact).  Sizes are chosen so that the oracle finishes in seconds
+while the GPU structures still span many tiles, blocks and ragged borders.
+"""
+import numpy as np
+import pytest
+
+from gen import (CITY_BOX, city_points, polygons_from_rings, star_polygons, tiny_workload,
+                 uniform_points, voronoi_partition)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sba():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2010_12548_amd as m
+    m.lib()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_agg(A, xy, vals=None, search=None):
+    c, s = A.aggregate(dev(xy), dev(vals) if vals is not None else None, search=search)
+    torch.cuda.synchronize()
+    return c.cpu().numpy().astype(np.uint64), (s.cpu().numpy() if s is not None else None)
+
+
+def expected_sets(orc_A, n_polys, i0, j0, nw, nh):
+    """Per-cell polygon tuples over a window, from the oracle's row intervals."""
+    m = np.zeros((n_polys, nh, nw), bool)
+    P, R, X0, X1 = orc_A.intervals()
+    for p, r, a, b in zip(P, R, X0, X1):
+        if j0 <= r < j0 + nh:
+            a2, b2 = max(a, i0), min(b, i0 + nw)
+            if a2 < b2:
+                m[p, r - j0, a2 - i0:b2 - i0] = True
+    out = {}
+    for j in range(nh):
+        for i in range(nw):
+            out[(i0 + i, j0 + j)] = tuple(int(p) for p in np.nonzero(m[:, j, i])[0])
+    return out
+
+
+def gpu_sets(A, cells):
+    ij = np.array(cells, dtype=np.int64).reshape(-1)
+    refs = A.lookup(dev(ij)).cpu().numpy()
+    return dict(zip(cells, A.decode(refs)))
+
+
+def window_of(polys, s, pad=3):
+    xy = polys.xy.reshape(-1, 2).astype(np.int64)
+    i0 = int(np.floor(xy[:, 0].min() / s)) - pad
+    j0 = int(np.floor(xy[:, 1].min() / s)) - pad
+    i1 = int(np.floor(xy[:, 0].max() / s)) + pad
+    j1 = int(np.floor(xy[:, 1].max() / s)) + pad
+    return i0, j0, i1 - i0 + 1, j1 - j0 + 1
+
+
+def shifted(polys, d):
+    return polygons_from_rings([[r + d for r in polys.rings_of(p)] for p in range(polys.n_polys)])
+
+
+# --------------------------------------------------------------- cell sets
+
+HAND = [
+    [[[1, 1], [7, 1], [1, 5]]],
+    [[[0, 0], [10, 0], [10, 10], [0, 10]], [[4, 4], [6, 4], [6, 6], [4, 6]]],
+    [[[0, 0], [30, 0], [30, 10], [10, 10], [10, 20], [30, 20], [30, 30], [0, 30]]],
+    [[[0, 0], [40, 0], [20, 1], [20, 30]]],
+    [[[5, 5], [25, 5], [25, 5], [15, 25]]],
+    [[[3, 3], [3, 3], [9, 3]]],
+    [[[-17, -9], [12, -9], [12, 6], [-17, 6]]],
+    [[[0, 0], [24, 12], [0, 24], [12, 12]]],
+]
+
+
+@pytest.mark.parametrize("eps", [2, 3, 5, 9, 15])
+def test_cell_sets_hand_shapes_grid(sba, orc, eps):
+    polys = polygons_from_rings([[np.array(r) for r in p] for p in HAND])
+    A = sba.Approx.from_polygons(polys, eps)
+    O = orc.Approx(polys, eps)
+    i0, j0, nw, nh = window_of(polys, O.s)
+    want = expected_sets(O, polys.n_polys, i0, j0, nw, nh)
+    got = gpu_sets(A, list(want.keys()))
+    assert got == want
+
+
+@pytest.mark.parametrize("seed,eps,tl", [(0, 4, 3), (1, 7, 4), (2, 13, 3), (3, 25, 5), (4, 3, 8)])
+def test_cell_sets_random_stars_grid(sba, orc, seed, eps, tl):
+    polys = star_polygons(12, 9 + seed, 20.0, 400.0, 1500, 500 + seed)
+    A = sba.Approx.from_polygons(polys, eps, tile_log2=tl)
+    O = orc.Approx(polys, eps)
+    i0, j0, nw, nh = window_of(polys, O.s)
+    want = expected_sets(O, polys.n_polys, i0, j0, nw, nh)
+    got = gpu_sets(A, list(want.keys()))
+    bad = [k for k in want if got[k] != want[k]]
+    assert not bad, (len(bad), bad[:5], [want[k] for k in bad[:5]], [got[k] for k in bad[:5]])
+    info = A.info()
+    assert info["n_blocks"] > 0 and info["n_tiles"] > info["n_blocks"]
+
+
+@pytest.mark.parametrize("seed,eps", [(0, 4), (1, 9), (2, 30)])
+def test_cell_sets_random_stars_hilbert(sba, orc, seed, eps):
+    polys = shifted(star_polygons(10, 11, 20.0, 300.0, 1200, 700 + seed), 400)
+    A = sba.Approx.from_polygons(polys, eps, kind="hilbert")
+    O = orc.Approx(polys, eps)
+    i0, j0, nw, nh = window_of(polys, O.s)
+    i0, j0 = max(i0, 0), max(j0, 0)
+    want = expected_sets(O, polys.n_polys, i0, j0, nw, nh)
+    got = gpu_sets(A, list(want.keys()))
+    bad = [k for k in want if got[k] != want[k]]
+    assert not bad, (len(bad), bad[:5])
+
+
+@pytest.mark.parametrize("seed,eps", [(0, 6), (1, 11), (2, 40)])
+def test_hilbert_runs_equal_oracle(sba, orc, seed, eps):
+    polys = shifted(star_polygons(6, 10, 10.0, 120.0, 500, 900 + seed), 150)
+    A = sba.Approx.from_polygons(polys, eps, kind="hilbert")
+    info = A.info()
+    L = info["level"]
+    O = orc.Approx(polys, eps)
+    st_o, off_o, ids_o = O.hilbert_runs(L)
+    st_g, ref_g = A.runs()
+    st_g = st_g.cpu().numpy().astype(np.uint64)
+    np.testing.assert_array_equal(st_g, st_o)
+    sets_o = [tuple(int(v) for v in ids_o[off_o[r]:off_o[r + 1]]) for r in range(len(st_o))]
+    assert A.decode(ref_g.cpu().numpy()) == sets_o
+
+
+# --------------------------------------------------------------- aggregates
+
+def test_tiny_workload_bit_exact(sba, orc):
+    xy, vals, polys = tiny_workload()
+    O = orc.Approx(polys, 64)
+    want_c, want_s = O.aggregate(xy, vals)
+    A = sba.Approx.from_polygons(polys, 64)
+    c, s = run_agg(A, xy, vals)
+    np.testing.assert_array_equal(c, want_c)
+    np.testing.assert_array_equal(s, want_s)
+    c2, s2 = run_agg(A, xy, None)
+    np.testing.assert_array_equal(c2, want_c)
+    assert s2 is None
+
+
+@pytest.mark.parametrize("tl", [3, 5, 8])
+def test_tiny_workload_tile_sizes(sba, orc, tl):
+    xy, vals, polys = tiny_workload(300_001)
+    want_c, want_s = orc.Approx(polys, 64).aggregate(xy, vals)
+    A = sba.Approx.from_polygons(polys, 64, tile_log2=tl)
+    c, s = run_agg(A, xy, vals)
+    np.testing.assert_array_equal(c, want_c)
+    np.testing.assert_array_equal(s, want_s)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 5, 255, 513])
+def test_small_and_ragged_n(sba, orc, n):
+    rng = np.random.default_rng(n)
+    polys = star_polygons(5, 12, 50.0, 400.0, 1000, 31)
+    xy = rng.integers(-100, 1100, size=2 * n).astype(np.int32)
+    vals = rng.integers(-10**6, 10**6, size=n).astype(np.int64)
+    O = orc.Approx(polys, 10)
+    want_c, want_s = O.aggregate(xy, vals)
+    A = sba.Approx.from_polygons(polys, 10)
+    c, s = run_agg(A, xy, vals)
+    np.testing.assert_array_equal(c, want_c)
+    np.testing.assert_array_equal(s, want_s)
+
+
+def test_extreme_point_coordinates(sba, orc):
+    polys = star_polygons(4, 10, 50.0, 400.0, 1000, 5)
+    ext = np.array([-2**31, -2**31, 2**31 - 1, 2**31 - 1, -2**31, 2**31 - 1, 0, 0, 500, 500,
+                    2**30, -2**30], dtype=np.int64).astype(np.int32)
+    vals = np.arange(6, dtype=np.int64) * 1000 + 7
+    want_c, want_s = orc.Approx(polys, 20).aggregate(ext, vals)
+    for kind in ("grid", "hilbert"):
+        P = polys if kind == "grid" else shifted(polys, 400)
+        X = ext if kind == "grid" else ext
+        want = orc.Approx(P, 20).aggregate(X, vals)
+        A = sba.Approx.from_polygons(P, 20, kind=kind)
+        c, s = run_agg(A, X, vals)
+        np.testing.assert_array_equal(c, want[0])
+        np.testing.assert_array_equal(s, want[1])
+    assert want_c.sum() >= 0
+
+
+def test_shuffle_invariance(sba):
+    xy, vals, polys = tiny_workload(400_000)
+    A = sba.Approx.from_polygons(polys, 64)
+    c1, s1 = run_agg(A, xy, vals)
+    perm = np.random.default_rng(9).permutation(400_000)
+    xy2 = xy.reshape(-1, 2)[perm].reshape(-1)
+    c2, s2 = run_agg(A, xy2, vals[perm])
+    np.testing.assert_array_equal(c1, c2)
+    np.testing.assert_array_equal(s1, s2)
+    c3, s3 = run_agg(A, xy, vals)
+    np.testing.assert_array_equal(c1, c3)
+    np.testing.assert_array_equal(s1, s3)
+
+
+@pytest.mark.parametrize("eps", [6, 40, 700, 6000])
+def test_partition_all_layouts(sba, orc, eps):
+    polys = voronoi_partition(40, 200_000, (3, 25), seed=3, jitter_seed=4)
+    xy = uniform_points(500_000, -1000, 201_000, 77)
+    vals = np.random.default_rng(1).integers(1, 10**7, size=500_000).astype(np.int64)
+    O = orc.Approx(polys, eps)
+    want_c, want_s = O.aggregate(xy, vals)
+    G = sba.Approx.from_polygons(polys, eps)
+    c, s = run_agg(G, xy, vals)
+    np.testing.assert_array_equal(c, want_c)
+    np.testing.assert_array_equal(s, want_s)
+    H = sba.Approx.from_polygons(polys, eps, kind="hilbert", search="learned", log2_leaves=8)
+    for search in ("binary", "learned"):
+        c, s = run_agg(H, xy, vals, search=search)
+        np.testing.assert_array_equal(c, want_c)
+        np.testing.assert_array_equal(s, want_s)
+
+
+def test_overlap_depth_and_limit(sba, orc):
+    rings = [[np.array([[-k, -k], [100 + k, -k], [100 + k, 100 + k], [-k, 100 + k]])] for k in range(20)]
+    polys = polygons_from_rings(rings)
+    xy = uniform_points(100_000, -40, 140, 3)
+    want_c, _ = orc.Approx(polys, 3).aggregate(xy)
+    A = sba.Approx.from_polygons(polys, 3)
+    c, _ = run_agg(A, xy)
+    np.testing.assert_array_equal(c, want_c)
+    deep = polygons_from_rings(rings + [[np.array([[-k, -k], [100 + k, -k], [100 + k, 100 + k],
+                                                    [-k, 100 + k]])] for k in range(20, 40)])
+    with pytest.raises(sba.SbaError) as e:
+        sba.Approx.from_polygons(deep, 3)
+    assert e.value.code == -5
+
+
+def test_error_codes(sba):
+    polys = star_polygons(3, 8, 50.0, 200.0, 1000, 2)
+    neg = polygons_from_rings([[np.array([[-5, 0], [10, 0], [10, 10]])]])
+    with pytest.raises(sba.SbaError) as e:
+        sba.Approx.from_polygons(neg, 10, kind="hilbert")
+    assert e.value.code == -2
+    big = polygons_from_rings([[np.array([[0, 0], [1 << 30, 0], [0, 5]])]])
+    with pytest.raises(sba.SbaError) as e:
+        sba.Approx.from_polygons(big, 10)
+    assert e.value.code == -2
+    A = sba.Approx.from_polygons(polys, 10)
+    buf = torch.zeros(9, dtype=torch.int32, device="cuda")
+    with pytest.raises(sba.SbaError):
+        A.aggregate(buf[1:5])        # not 16-byte aligned
+    empty = polygons_from_rings([])
+    E = sba.Approx.from_polygons(empty, 10)
+    c, _ = E.aggregate(dev(np.array([1, 2, 3, 4], np.int32)))
+    assert c.numel() == 0
+
+
+def test_city_partition_sampled(sba, orc):
+    """City-like partition (260 jittered Voronoi cells), 4M mixture points,
+    the three distance bounds; full oracle comparison."""
+    from gen import city_polygons
+    polys = city_polygons()
+    xy, vals = city_points(4_000_000)
+    for eps in (100, 1000, 10000):
+        O = orc.Approx(polys, eps)
+        want_c, want_s = O.aggregate(xy, vals)
+        A = sba.Approx.from_polygons(polys, eps)
+        c, s = run_agg(A, xy, vals)
+        np.testing.assert_array_equal(c, want_c)
+        np.testing.assert_array_equal(s, want_s)
+        assert int(c.sum()) >= 4_000_000
