@@ -42,7 +42,7 @@ extern "C" {
 
 #define SBA_OK        0
 #define SBA_EINVAL   (-1)  /* null pointer, negative size, bad offsets, eps out of range */
-#define SBA_ERANGE   (-2)  /* coordinate out of range (|c| >= 2^30, or < 0 for the Hilbert layout) */
+#define SBA_ERANGE   (-2)  /* vertex coordinate out of range (|c| >= 2^30) */
 #define SBA_ENOMEM   (-3)  /* device allocation failed */
 #define SBA_EDEVICE  (-4)  /* a HIP call failed */
 #define SBA_ELIMIT   (-5)  /* a documented size limit is exceeded (see sba_build_approx) */
@@ -110,9 +110,12 @@ typedef struct {
  *           (it reads sizes back) and returns once the handle is complete.
  *   out     host pointer; receives the new handle (NULL on failure).
  *
+ * The stored cell box is the union of the polygons' cell boxes; the grid
+ * layout tiles it, the Hilbert layout anchors its 2^L x 2^L key grid at its
+ * first cell (L = smallest level covering the box).
  * Limits (SBA_ELIMIT): at most 2^21-1 polygons; the stored cell box at most
- * 2^21 cells per side; a cell may belong to at most 32 polygons; Hilbert
- * layout: all vertex coordinates >= 0 and level L <= 21.
+ * 2^21 cells per side and less than 2^31 coordinate units per side; a cell
+ * may belong to at most 32 polygons; learned index: L <= 16.
  * Errors: SBA_EINVAL (null/negative/non-monotone offsets, eps out of range),
  * SBA_ERANGE, SBA_ENOMEM, SBA_EDEVICE, SBA_ELIMIT.
  */

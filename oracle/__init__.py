@@ -66,6 +66,10 @@ def lib():
     L.orc_invariant_all.argtypes = [C.c_void_p, _i32p, C.c_int64, _i64p]
     L.orc_hilbert_d.restype = C.c_uint64
     L.orc_hilbert_d.argtypes = [C.c_int, C.c_int64, C.c_int64]
+    L.orc_hilbert_level.restype = C.c_int
+    L.orc_hilbert_level.argtypes = [C.c_void_p]
+    L.orc_union_box.restype = None
+    L.orc_union_box.argtypes = [C.c_void_p, _i64p]
     L.orc_hilbert_runs.restype = C.c_int
     L.orc_hilbert_runs.argtypes = [C.c_void_p, C.c_int, _u64p, _i64p, _i32p, C.c_int64,
                                    C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
@@ -168,8 +172,18 @@ class Approx:
         return {"differ": int(out[0]), "far": int(out[1]), "false_neg": int(out[2]),
                 "inside": int(out[3])}
 
+    def union_box(self):
+        """(i0, j0, w, h): the cell box of the union of all approximations."""
+        out = np.zeros(4, np.int64)
+        lib().orc_union_box(self._h, out)
+        return tuple(int(v) for v in out)
+
+    def hilbert_level(self) -> int:
+        return int(lib().orc_hilbert_level(self._h))
+
     def hilbert_runs(self, L: int):
-        """Maximal runs over [0, 4^L): (starts uint64, run_off int64, run_ids int32)."""
+        """Maximal runs over [0, 4^L), key grid anchored at the union box:
+        (starts uint64, run_off int64, run_ids int32)."""
         cap_r, cap_i = 1024, 1024
         while True:
             st = np.zeros(cap_r, np.uint64)

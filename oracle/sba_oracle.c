@@ -728,12 +728,29 @@ uint64_t orc_hilbert_d(int L, int64_t x, int64_t y)
     return d;
 }
 
+/* Key grid of the Hilbert layout: the cell box of the union of the
+ * approximations, anchored at its first cell (ui0, uj0) and padded to
+ * 2^L x 2^L cells with L the smallest level >= 1 that covers it.  Every cell
+ * of every approximation then has a key. */
+int orc_hilbert_level(const orc_approx *a)
+{
+    int L = 1;
+    while (((int64_t)1 << L) < max64(a->uw, a->uh)) L++;
+    return L;
+}
+
+void orc_union_box(const orc_approx *a, int64_t *out)
+{
+    out[0] = a->ui0; out[1] = a->uj0; out[2] = a->uw; out[3] = a->uh;
+}
+
 /* Maximal runs of consecutive Hilbert indices in [0, 4^L) whose cells have
  * equal S(c) (the empty set included, so the runs partition the index
- * range).  By enumeration of every index: tiny L only.  Cells of the
- * domain are (i,j) in [0,2^L)^2.  Writes run starts, and per run the
- * ascending polygon ids as CSR (run_off[n_runs+1], run_ids).  Returns 0 if
- * everything fit, -1 otherwise; *n_runs / *n_ids get the sizes needed. */
+ * range); index d stands for cell (ui0 + x, uj0 + y) where (x, y) is the
+ * cell of d on the 2^L grid.  By enumeration of every index: tiny L only.
+ * Writes run starts, and per run the ascending polygon ids as CSR
+ * (run_off[n_runs+1], run_ids).  Returns 0 if everything fit, -1 otherwise;
+ * *n_runs / *n_ids get the sizes needed. */
 static int cmp_ids(const int32_t *a, int na, const int32_t *b, int nb)
 {
     if (na != nb) return 0;
@@ -763,7 +780,7 @@ int orc_hilbert_runs(const orc_approx *a, int L, uint64_t *starts, int64_t *run_
     int np = -1;
     int64_t nr = 0, ni = 0;
     for (uint64_t d = 0; d < total; d++) {
-        int n = orc_cell_set(a, cx[d], cy[d], cur, cap);
+        int n = orc_cell_set(a, a->ui0 + cx[d], a->uj0 + cy[d], cur, cap);
         if (np >= 0 && cmp_ids(cur, n, prev, np)) continue;
         if (nr < cap_runs) {
             starts[nr] = d;

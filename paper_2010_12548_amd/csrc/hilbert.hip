@@ -6,6 +6,9 @@
 // index that predicts a key's run (Sec. 3, learned index over the sorted
 // cell array).
 //
+// The key grid is anchored at the first cell of the stored box (the union of
+// the polygons' cell boxes), so every cell of every approximation has a key.
+//
 // Runs are found without visiting interior cells.  Consecutive Hilbert cells
 // share an edge; two edge-adjacent cells that are boundary cells of no
 // polygon have the same polygon set (a polygon boundary separating them
@@ -25,32 +28,26 @@ __device__ __forceinline__ int64_t ub_i64(const int64_t *a, int64_t n, int64_t v
     return lo;
 }
 
-// cells of boundary interval t that lie in the key domain [0, side)^2
-__global__ void k_bcell_counts(const uint64_t *evkey, int64_t nb, int xbits, int64_t gi0,
-                               int64_t gj0, int64_t side, int64_t *cnt)
+// cells of boundary interval t (relative to the stored box, which is also
+// the origin of the Hilbert key grid)
+__global__ void k_bcell_counts(const uint64_t *evkey, int64_t nb, int xbits, int64_t *cnt)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nb) return;
     uint64_t xm = (1ull << xbits) - 1;
-    int64_t j = gj0 + (int64_t)(evkey[2 * t] >> xbits);
-    int64_t i0 = gi0 + (int64_t)(evkey[2 * t] & xm), i1 = gi0 + (int64_t)(evkey[2 * t + 1] & xm);
-    i0 = max(i0, (int64_t)0);
-    i1 = min(i1, side);
-    cnt[t] = (j < 0 || j >= side || i1 <= i0) ? 0 : i1 - i0;
+    cnt[t] = (int64_t)(evkey[2 * t + 1] & xm) - (int64_t)(evkey[2 * t] & xm);
 }
 
-__global__ void k_bcell_keys(const uint64_t *evkey, int64_t nb, int xbits, int64_t gi0,
-                             int64_t gj0, const int64_t *off, int64_t ncells, int L,
-                             uint64_t *keys)
+__global__ void k_bcell_keys(const uint64_t *evkey, int64_t nb, int xbits, const int64_t *off,
+                             int64_t ncells, int L, uint64_t *keys)
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncells) return;
     int64_t t = ub_i64(off, nb, c) - 1;
     uint64_t xm = (1ull << xbits) - 1;
-    int64_t j = gj0 + (int64_t)(evkey[2 * t] >> xbits);
-    int64_t i0 = max(gi0 + (int64_t)(evkey[2 * t] & xm), (int64_t)0);
-    int64_t i = i0 + (c - off[t]);
-    keys[c] = hilbert_index(L, (uint32_t)i, (uint32_t)j);
+    uint32_t j = (uint32_t)(evkey[2 * t] >> xbits);
+    uint32_t i = (uint32_t)((evkey[2 * t] & xm) + (uint64_t)(c - off[t]));
+    keys[c] = hilbert_index(L, i, j);
 }
 
 __global__ void k_flag_first(const uint64_t *keys, int64_t n, int64_t *flag)
@@ -69,14 +66,13 @@ __global__ void k_compact_first(const uint64_t *keys, int64_t n, const int64_t *
 
 static int hilbert_boundary_cells(BuildState &B, sba_handle *h, hipStream_t st)
 {
-    const int64_t side = (int64_t)1 << h->level;
     const int64_t NB = B.NB;
     if (NB == 0) return 0;
     int64_t *cnt = nullptr, *tot = nullptr;
     RC(B.alloc(&cnt, NB + 1));
     RC(B.alloc(&tot, 1));
     hipLaunchKernelGGL(k_bcell_counts, dim3(grid_for(NB)), dim3(256), 0, st, B.evkey, NB, B.xbits,
-                       h->gi0, h->gj0, side, cnt);
+                       cnt);
     HIP_OK(hipGetLastError());
     RC(scan_exclusive_i64(cnt, cnt, NB, tot, st));
     int64_t nc = 0;
@@ -86,7 +82,7 @@ static int hilbert_boundary_cells(BuildState &B, sba_handle *h, hipStream_t st)
     uint64_t *keys = nullptr;
     RC(B.alloc(&keys, nc));
     hipLaunchKernelGGL(k_bcell_keys, dim3(grid_for(nc)), dim3(256), 0, st, B.evkey, NB, B.xbits,
-                       h->gi0, h->gj0, cnt, nc, h->level, keys);
+                       cnt, nc, h->level, keys);
     HIP_OK(hipGetLastError());
     B.release(cnt);
     RC(radix_sort_u64(keys, nullptr, nc, 2 * h->level, st));
@@ -112,9 +108,9 @@ int hilbert_prepare(BuildState &B, sba_handle *h)
 {
     (void)h;
     B.on_boundary_events = [](BuildState &b, sba_handle *hh, hipStream_t st) -> int {
-        if (b.cmin < 0) return SBA_ERANGE;
+        // key grid: the stored cell box, padded to 2^L x 2^L
         int L = 1;
-        while (L < 31 && (((int64_t)1 << L) * hh->s) <= b.cmax) L++;
+        while (((int64_t)1 << L) < std::max(hh->gw, hh->gh)) L++;
         if (L > 21) return SBA_ELIMIT;
         hh->level = L;
         return hilbert_boundary_cells(b, hh, st);
@@ -151,7 +147,8 @@ __device__ __forceinline__ uint32_t code_of_key(const SegView &S, int L, uint64_
 {
     uint32_t i, j;
     hilbert_cell(L, key, &i, &j);
-    return code_of_cell(S.row_off, S.x0, S.x1, S.code, S.gi0, S.gj0, S.gw, S.gh, i, j);
+    return code_of_cell(S.row_off, S.x0, S.x1, S.code, S.gi0, S.gj0, S.gw, S.gh, S.gi0 + i,
+                        S.gj0 + j);
 }
 
 // candidate run starts: every boundary key, the key after it when a gap

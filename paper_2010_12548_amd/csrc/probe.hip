@@ -33,7 +33,8 @@ struct GridView {
 };
 
 struct HilbView {
-    uint32_t ext;          // 2^L * s (< 2^31): points outside [0, ext)^2 have no cell
+    int64_t ox, oy;        // coordinate of the key grid's first cell (the stored box)
+    uint32_t extx, exty;   // stored box extent in coordinate units (< 2^31)
     uint32_t mag;
     int32_t shift;
     int32_t L;
@@ -94,9 +95,10 @@ __device__ __forceinline__ int64_t learned_search(const HilbView &v, const K *ke
 template <int SEARCH>
 __device__ __forceinline__ uint32_t hilbert_code(const HilbView &v, int32_t x, int32_t y)
 {
-    if ((uint32_t)x >= v.ext || (uint32_t)y >= v.ext) return 0;  // also rejects x < 0
-    uint32_t i = divmagic((uint32_t)x, v.mag, v.shift);
-    uint32_t j = divmagic((uint32_t)y, v.mag, v.shift);
+    int64_t dx = (int64_t)x - v.ox, dy = (int64_t)y - v.oy;
+    if ((uint64_t)dx >= v.extx || (uint64_t)dy >= v.exty) return 0;
+    uint32_t i = divmagic((uint32_t)dx, v.mag, v.shift);
+    uint32_t j = divmagic((uint32_t)dy, v.mag, v.shift);
     uint64_t key = hilbert_index(v.L, i, j);
     int64_t q;
     if (v.k32) {
@@ -289,9 +291,9 @@ __global__ void k_lookup(const int64_t *ij, int64_t n, GridView g, HilbView hv, 
             c = grid_code(g, (int32_t)(i * s), (int32_t)(j * s));
         }
     } else {
-        int64_t side = (int64_t)1 << hv.L;
-        if (i >= 0 && j >= 0 && i < side && j < side) {
-            uint64_t key = hilbert_index(hv.L, (uint32_t)i, (uint32_t)j);
+        int64_t x = i - gi0, y = j - gj0;
+        if (x >= 0 && y >= 0 && x < gw && y < gh) {
+            uint64_t key = hilbert_index(hv.L, (uint32_t)x, (uint32_t)y);
             int64_t q = hv.k32 ? pred_search<uint32_t>(hv.k32, 0, hv.n, (uint32_t)key)
                                : pred_search<uint64_t>(hv.k64, 0, hv.n, key);
             c = hv.code[q];
@@ -335,7 +337,10 @@ static void views(const sba_handle *h, GridView *g, HilbView *hv)
         g->dir = h->dir;
         g->blocks = h->blocks;
     } else {
-        hv->ext = (uint32_t)(((int64_t)1 << h->level) * h->s);
+        hv->ox = h->gi0 * h->s;
+        hv->oy = h->gj0 * h->s;
+        hv->extx = (uint32_t)(h->gw * h->s);
+        hv->exty = (uint32_t)(h->gh * h->s);
         hv->mag = h->mag;
         hv->shift = h->shift;
         hv->L = h->level;

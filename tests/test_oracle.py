@@ -344,17 +344,22 @@ def test_hilbert_runs_against_brute(orc):
     polys = star_polygons(5, 10, 10.0, 60.0, 120, 21)
     eps = 5
     s = orc.cell_side(eps)
-    L = 6
     A = orc.Approx(polys, eps)
+    i0, j0, w, h = A.union_box()
+    L = A.hilbert_level()
+    assert (1 << L) >= max(w, h) and (L == 1 or (1 << (L - 1)) < max(w, h))
     starts, off, ids = A.hilbert_runs(L)
     assert starts[0] == 0 and np.all(np.diff(starts.astype(np.int64)) > 0)
     sets = [tuple(ids[off[r]:off[r + 1]]) for r in range(len(starts))]
     assert all(sets[r] != sets[r + 1] for r in range(len(sets) - 1))    # maximal
     n = 1 << L
-    br = orc.raster_brute(polys, s, 0, 0, n, n) > 0
-    for i in range(n):
-        for j in range(n):
-            d = orc.hilbert_d(L, i, j)
+    br = orc.raster_brute(polys, s, i0, j0, n, n) > 0
+    for x in range(n):
+        for y in range(n):
+            d = orc.hilbert_d(L, x, y)
             r = int(np.searchsorted(starts, d, side="right")) - 1
-            want = tuple(int(p) for p in np.nonzero(br[:, j, i])[0])
+            want = tuple(int(p) for p in np.nonzero(br[:, y, x])[0])
             assert sets[r] == want
+    # every cell of every approximation lies inside the key grid
+    P, R, X0, X1 = A.intervals()
+    assert X0.min() >= i0 and X1.max() <= i0 + n and R.min() >= j0 and R.max() < j0 + n
