@@ -442,8 +442,28 @@ void magic_for(int64_t s, uint32_t *mag, int32_t *shift)
 
 BuildState::~BuildState()
 {
-    if (!owned.empty()) (void)hipStreamSynchronize(st);
-    for (void *p : owned) (void)hipFree(p);
+    for (void *p : owned) tmp_free(p, st);
+    (void)hipStreamSynchronize(st);
+}
+
+int pool_setup()
+{
+    static bool done[64] = {false};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return SBA_EDEVICE;
+    if (done[dev]) return 0;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return SBA_EDEVICE;
+    }
+    uint64_t keep = ~0ull;
+    if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
+        (void)hipGetLastError();
+        return SBA_EDEVICE;
+    }
+    done[dev] = true;
+    return 0;
 }
 
 int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_handle *h,

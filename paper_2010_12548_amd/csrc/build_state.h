@@ -14,7 +14,7 @@ struct BuildState {
     template <typename T>
     int alloc(T **p, int64_t n)
     {
-        int rc = dev_alloc(p, n);
+        int rc = tmp_alloc(p, n, st);
         if (!rc) owned.push_back((void *)*p);
         return rc;
     }
@@ -22,8 +22,7 @@ struct BuildState {
     {
         auto it = std::find(owned.begin(), owned.end(), p);
         if (it == owned.end()) return;
-        (void)hipStreamSynchronize(st);
-        (void)hipFree(p);
+        tmp_free(p, st);
         owned.erase(it);
     }
     ~BuildState();

@@ -96,7 +96,7 @@ static int scan_rec(const int64_t *in, int64_t *out, int64_t n, hipStream_t st)
         return 0;
     }
     int64_t *sums = nullptr;
-    RC(dev_alloc(&sums, tiles));
+    RC(tmp_alloc(&sums, tiles, st));
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, st, in, out, n,
                        sums);
     int rc = hipGetLastError() == hipSuccess ? 0 : SBA_EDEVICE;
@@ -105,8 +105,7 @@ static int scan_rec(const int64_t *in, int64_t *out, int64_t n, hipStream_t st)
         hipLaunchKernelGGL(k_scan_add, dim3(grid_for(n)), dim3(256), 0, st, out, n, sums);
         rc = hipGetLastError() == hipSuccess ? 0 : SBA_EDEVICE;
     }
-    (void)hipStreamSynchronize(st);
-    (void)hipFree(sums);
+    tmp_free(sums, st);
     return rc;
 }
 
@@ -114,7 +113,7 @@ int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tota
 {
     int64_t *last = nullptr;
     if (total) {
-        RC(dev_alloc(&last, 1));
+        RC(tmp_alloc(&last, 1, st));
         hipLaunchKernelGGL(k_copy_last, dim3(1), dim3(64), 0, st, in, n, last);
     }
     int rc = scan_rec(in, out, n, st);
@@ -122,10 +121,7 @@ int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tota
         hipLaunchKernelGGL(k_add_last, dim3(1), dim3(64), 0, st, out, n, last, total);
         rc = hipGetLastError() == hipSuccess ? 0 : SBA_EDEVICE;
     }
-    if (last) {
-        (void)hipStreamSynchronize(st);
-        (void)hipFree(last);
-    }
+    tmp_free(last, st);
     return rc;
 }
 
@@ -252,10 +248,10 @@ int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStrea
     uint64_t *k2 = nullptr;
     uint32_t *v2 = nullptr, *hist = nullptr;
     int64_t *goff = nullptr;
-    int rc = dev_alloc(&k2, n);
-    if (!rc && vals) rc = dev_alloc(&v2, n);
-    if (!rc) rc = dev_alloc(&hist, nblocks * RS_RADIX);
-    if (!rc) rc = dev_alloc(&goff, nblocks * RS_RADIX);
+    int rc = tmp_alloc(&k2, n, st);
+    if (!rc && vals) rc = tmp_alloc(&v2, n, st);
+    if (!rc) rc = tmp_alloc(&hist, nblocks * RS_RADIX, st);
+    if (!rc) rc = tmp_alloc(&goff, nblocks * RS_RADIX, st);
     uint64_t *ka = keys, *kb = k2;
     uint32_t *va = vals, *vb = v2;
     int passes = (bits + 7) / 8;
@@ -285,10 +281,9 @@ int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStrea
             hipMemcpyAsync(vals, va, (size_t)n * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
             rc = SBA_EDEVICE;
     }
-    (void)hipStreamSynchronize(st);
-    (void)hipFree(k2);
-    (void)hipFree(v2);
-    (void)hipFree(hist);
-    (void)hipFree(goff);
+    tmp_free(k2, st);
+    tmp_free(v2, st);
+    tmp_free(hist, st);
+    tmp_free(goff, st);
     return rc;
 }

@@ -378,11 +378,8 @@ static int launch_layout(const int32_t *xy, const int64_t *values, int64_t n, co
         uint32_t *pcnt = nullptr;
         unsigned long long *psum = nullptr;
         size_t bytes = (size_t)nb * np * (sizeof(uint32_t) + (vals ? 8 : 0));
-        void *scratch = nullptr;
-        if (hipMallocAsync(&scratch, bytes ? bytes : 8, st) != hipSuccess) {
-            (void)hipGetLastError();
-            return SBA_ENOMEM;
-        }
+        char *scratch = nullptr;
+        RC(tmp_alloc(&scratch, (int64_t)(bytes ? bytes : 8), st));
         psum = (unsigned long long *)scratch;
         pcnt = (uint32_t *)(vals ? (char *)scratch + (size_t)nb * np * 8 : (char *)scratch);
         size_t lds = (size_t)np * 12;
@@ -400,7 +397,7 @@ static int launch_layout(const int32_t *xy, const int64_t *values, int64_t n, co
             hipLaunchKernelGGL(k_reduce<false>, dim3((unsigned)np), dim3(256), 0, st, pcnt, psum, nb,
                                np, counts, sums);
         hipError_t e2 = hipGetLastError();
-        (void)hipFreeAsync(scratch, st);
+        tmp_free(scratch, st);
         if (e1 != hipSuccess || e2 != hipSuccess) return SBA_EDEVICE;
         return 0;
     }

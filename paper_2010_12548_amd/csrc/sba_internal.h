@@ -170,7 +170,7 @@ int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tota
 // data (the library ping-pongs through internal temporaries).
 int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st);
 
-// device allocation helper that records failures
+// device allocation helper (persistent arrays of a handle)
 template <typename T>
 inline int dev_alloc(T **p, int64_t count)
 {
@@ -182,6 +182,31 @@ inline int dev_alloc(T **p, int64_t count)
         return SBA_ENOMEM;
     }
     return 0;
+}
+
+// Stream-ordered temporaries from the device's default memory pool, which is
+// told to keep freed memory (pool_setup), so repeated builds and probes do
+// not go back to the driver and frees do not synchronise the device.
+int pool_setup();
+
+template <typename T>
+inline int tmp_alloc(T **p, int64_t count, hipStream_t st)
+{
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    int prc = pool_setup();
+    if (prc) return prc;
+    if (hipMallocAsync((void **)p, (size_t)count * sizeof(T), st) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return SBA_ENOMEM;
+    }
+    return 0;
+}
+
+inline void tmp_free(void *p, hipStream_t st)
+{
+    if (p) (void)hipFreeAsync(p, st);
 }
 
 inline int bits_for(uint64_t maxval)  // bits needed to hold values in [0, maxval]
