@@ -44,7 +44,42 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-sweep", action="store_true", help="skip the eps sweep")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--probe-only", action="store_true",
+                    help="build once, then run only --steps aggregate calls (for counter runs)")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="with --probe-only: first run a device-to-device copy of this many GiB "
+                         "(calibrates the memory counters against a kernel of known traffic)")
     return ap.parse_args()
+
+
+def probe_only(args, sba, torch, txy, tv, ro, vo, pxy, eps, layout, search, n):
+    if args.copy_gib > 0:
+        nb = int(args.copy_gib * 2**30)
+        src = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {nb} bytes read, {nb} bytes written")
+        del src, dst
+    a = sba.Approx(ro, vo, pxy, eps, kind=layout, search=search)
+    counts = torch.empty(a.n_polys, dtype=torch.int64, device="cuda")
+    sums = torch.empty(a.n_polys, dtype=torch.int64, device="cuda")
+    for _ in range(args.warmup):
+        a.aggregate(txy, tv, counts, sums)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        a.aggregate(txy, tv, counts, sums)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / args.steps
+    info = a.info()
+    log(f"[bench] probe-only: {args.steps} calls, {t:.4f} ms per call, "
+        f"{16.0 * n / (t * 1e-3) / 1e9:.1f} GB/s algorithmic; approx {json.dumps(info)}")
+    a.close()
 
 
 def workload(args):
@@ -104,6 +139,9 @@ def main():
     sums = torch.empty(polys.n_polys, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
     kw = dict(kind=layout, search=search)
+    if args.probe_only:
+        probe_only(args, sba, torch, txy, tv, ro, vo, pxy, eps, layout, search, n)
+        return
 
     def step(ev=None):
         a = sba.Approx(ro, vo, pxy, eps, **kw)

@@ -238,75 +238,77 @@ def voronoi_partition(n_sites: int, box: int, edge_verts=(10, 200), seed: int = 
                       np.c_[s[:, 0], -s[:, 1]], np.c_[s[:, 0], 2.0 * box - s[:, 1]]])
     vor = Voronoi(allp)
     vq = np.floor(vor.vertices + 0.5).astype(np.int64)
+    # vertices that coincide after rounding become one vertex
+    _, vcanon = np.unique(vq, axis=0, return_inverse=True)
+    vcanon = vcanon.reshape(-1)
+    first_of = np.full(vcanon.max() + 1, -1, np.int64)
+    for v in range(len(vcanon) - 1, -1, -1):
+        first_of[vcanon[v]] = v
+    vrep = first_of[vcanon]            # representative vertex index of each vertex
 
     # cyclic vertex order of each original cell, by angle about its site
     cells = []
     for i in range(n_sites):
-        reg = [v for v in vor.regions[vor.point_region[i]] if v >= 0]
+        reg = np.array([v for v in vor.regions[vor.point_region[i]] if v >= 0], np.int64)
         vv = vor.vertices[reg]
-        ang = np.arctan2(vv[:, 1] - s[i, 1], vv[:, 0] - s[i, 0])
-        order = np.argsort(ang)
-        ring = [reg[t] for t in order]
-        # drop consecutive duplicates created by rounding
-        ded = []
-        for v in ring:
-            if not ded or not np.array_equal(vq[ded[-1]], vq[v]):
-                ded.append(v)
-        if len(ded) > 1 and np.array_equal(vq[ded[0]], vq[ded[-1]]):
-            ded.pop()
-        cells.append(ded)
+        order = np.argsort(np.arctan2(vv[:, 1] - s[i, 1], vv[:, 0] - s[i, 0]))
+        ring = vrep[reg[order]]
+        keep = np.r_[True, ring[1:] != ring[:-1]]
+        ring = ring[keep]
+        if len(ring) > 1 and ring[0] == ring[-1]:
+            ring = ring[:-1]
+        cells.append(ring)
 
     # edges of every cell, keyed by the (min, max) vertex pair
-    edge_cells: dict = {}
-    for ci, ring in enumerate(cells):
-        m = len(ring)
-        for t in range(m):
-            a, b = ring[t], ring[(t + 1) % m]
-            edge_cells.setdefault((min(a, b), max(a, b)), []).append(ci)
-    keys = list(edge_cells.keys())
-    kidx = {k: e for e, k in enumerate(keys)}
-    E = len(keys)
-    ea = np.array([k[0] for k in keys], dtype=np.int64)
-    eb = np.array([k[1] for k in keys], dtype=np.int64)
+    ca = np.concatenate([c for c in cells])
+    cb = np.concatenate([np.roll(c, -1) for c in cells])
+    cid = np.concatenate([np.full(len(c), k) for k, c in enumerate(cells)])
+    lo_v, hi_v = np.minimum(ca, cb), np.maximum(ca, cb)
+    ekey = lo_v * (len(vq) + 1) + hi_v
+    ukey, eidx, ecount = np.unique(ekey, return_inverse=True, return_counts=True)
+    eidx = eidx.reshape(-1)
+    E = len(ukey)
+    ea = (ukey // (len(vq) + 1)).astype(np.int64)
+    eb = (ukey % (len(vq) + 1)).astype(np.int64)
     A = vq[ea].astype(np.float64)
     B = vq[eb].astype(np.float64)
-    shared = np.array([len(edge_cells[k]) == 2 for k in keys])
+    shared = ecount == 2
 
     # smallest angle between edges meeting at each vertex
-    inc: dict = {}
-    for e in range(E):
-        inc.setdefault(int(ea[e]), []).append((e, 0))
-        inc.setdefault(int(eb[e]), []).append((e, 1))
-    min_ang = {}
-    for v, lst in inc.items():
-        dirs = []
-        for e, end in lst:
-            d = (B[e] - A[e]) if end == 0 else (A[e] - B[e])
-            dirs.append(math.atan2(d[1], d[0]))
-        dirs.sort()
-        gaps = [dirs[t + 1] - dirs[t] for t in range(len(dirs) - 1)]
-        gaps.append(2 * math.pi - (dirs[-1] - dirs[0]))
-        min_ang[v] = max(1e-6, min(gaps)) if len(dirs) > 1 else math.pi
+    ends = np.r_[ea, eb]
+    dirs = np.r_[np.arctan2(B[:, 1] - A[:, 1], B[:, 0] - A[:, 0]),
+                 np.arctan2(A[:, 1] - B[:, 1], A[:, 0] - B[:, 0])]
+    order = np.lexsort((dirs, ends))
+    ends_s, dirs_s = ends[order], dirs[order]
+    same = np.r_[ends_s[1:] == ends_s[:-1], False]
+    gap = np.where(same, np.r_[dirs_s[1:] - dirs_s[:-1], 0.0], np.inf)
+    starts = np.r_[True, ends_s[1:] != ends_s[:-1]]
+    grp_first = np.maximum.accumulate(np.where(starts, np.arange(len(ends_s)), 0))
+    wrap = np.where(~same, 2 * np.pi - (dirs_s - dirs_s[grp_first]), np.inf)
+    cand = np.minimum(gap, wrap)
+    nv_all = len(vq)
+    min_ang = np.full(nv_all, np.inf)
+    np.minimum.at(min_ang, ends_s, cand)
+    single = np.bincount(ends_s, minlength=nv_all) <= 1
+    min_ang[single] = np.pi
+    min_ang = np.clip(min_ang, 1e-6, np.pi)
 
     # distance from each edge to the non-adjacent edges of its cells
     pa, pb = [], []
-    for ci, ring in enumerate(cells):
-        m = len(ring)
-        ids = [kidx[(min(ring[t], ring[(t + 1) % m]), max(ring[t], ring[(t + 1) % m]))]
-               for t in range(m)]
-        for x in range(m):
-            for y in range(m):
-                if x == y:
-                    continue
-                e, f = ids[x], ids[y]
-                if {int(ea[e]), int(eb[e])} & {int(ea[f]), int(eb[f])}:
-                    continue
-                pa.append(e)
-                pb.append(f)
+    off = 0
+    for c in cells:
+        m = len(c)
+        if m >= 4:
+            x, y = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+            d = (y - x) % m
+            sel = (d != 0) & (d != 1) & (d != m - 1)
+            pa.append(eidx[off + x[sel]])
+            pb.append(eidx[off + y[sel]])
+        off += m
     dsep = np.full(E, np.inf)
     if pa:
-        pa = np.asarray(pa)
-        pb = np.asarray(pb)
+        pa = np.concatenate(pa)
+        pb = np.concatenate(pb)
         d = np.minimum.reduce([
             _seg_point_dist(A[pb, 0], A[pb, 1], A[pa, 0], A[pa, 1], B[pa, 0], B[pa, 1]),
             _seg_point_dist(B[pb, 0], B[pb, 1], A[pa, 0], A[pa, 1], B[pa, 0], B[pa, 1]),
@@ -315,55 +317,65 @@ def voronoi_partition(n_sites: int, box: int, edge_verts=(10, 200), seed: int = 
         ])
         np.minimum.at(dsep, pa, d)
 
+    # jitter, all shared edges at once
     jr = np.random.default_rng(jitter_seed)
-    poly_of_edge = [None] * E
     lo, hi = edge_verts
-    for e in range(E):
-        if not shared[e]:
-            continue
-        a, b = A[e], B[e]
-        L = float(np.hypot(*(b - a)))
-        m = int(jr.integers(lo, hi + 1))
-        phA, phB = min_ang[int(ea[e])], min_ang[int(eb[e])]
-        hA = min(0.5, 0.4 * math.tan(phA / 2))
-        hB = min(0.5, 0.4 * math.tan(phB / 2))
-        # keep interior vertices away from the ends, where rounding could
-        # otherwise cross a neighbouring polyline meeting at a small angle
-        rA = 8.0 / max(math.sin(phA / 2), 1e-9)
-        rB = 8.0 / max(math.sin(phB / 2), 1e-9)
-        t_lo, t_hi = rA / L if L > 0 else 1.0, 1.0 - (rB / L if L > 0 else 1.0)
-        m = min(m, int(max(0.0, (t_hi - t_lo)) * L / 4.0))
-        if m <= 0 or t_hi <= t_lo:
-            continue
-        t = np.sort(jr.uniform(t_lo, t_hi, size=m))
-        tt = np.r_[0.0, t, 1.0]
-        spacing = np.minimum(tt[1:-1] - tt[:-2], tt[2:] - tt[1:-1]) * L
-        cap = np.minimum(np.minimum(hA * t, hB * (1.0 - t)) * L, 0.25 * spacing)
-        cap = np.minimum(cap, 0.3 * dsep[e])
-        u = jr.uniform(-1.0, 1.0, size=m) * cap
-        nrm = np.array([-(b - a)[1], (b - a)[0]]) / L
-        pts = a[None, :] + t[:, None] * (b - a)[None, :] + u[:, None] * nrm[None, :]
-        q = np.floor(pts + 0.5).astype(np.int64)
-        # drop points that coincide with their predecessor after rounding
-        keep = [0]
-        for k in range(1, m):
-            if not np.array_equal(q[k], q[keep[-1]]):
-                keep.append(k)
-        q = q[keep]
-        q = q[~(np.all(q == vq[ea[e]], axis=1) | np.all(q == vq[eb[e]], axis=1))]
-        poly_of_edge[e] = q
+    L = np.hypot(B[:, 0] - A[:, 0], B[:, 1] - A[:, 1])
+    m_want = jr.integers(lo, hi + 1, size=E)
+    phA, phB = min_ang[ea], min_ang[eb]
+    hA = np.minimum(0.5, 0.4 * np.tan(phA / 2))
+    hB = np.minimum(0.5, 0.4 * np.tan(phB / 2))
+    # keep interior vertices away from the ends, where rounding could
+    # otherwise cross a neighbouring polyline meeting at a small angle
+    rA = 8.0 / np.maximum(np.sin(phA / 2), 1e-9)
+    rB = 8.0 / np.maximum(np.sin(phB / 2), 1e-9)
+    Ls = np.where(L > 0, L, 1.0)
+    t_lo = np.where(L > 0, rA / Ls, 1.0)
+    t_hi = np.where(L > 0, 1.0 - rB / Ls, 0.0)
+    room = np.maximum(0.0, t_hi - t_lo) * L / 4.0
+    m = np.where(shared & (t_hi > t_lo), np.minimum(m_want, room.astype(np.int64)), 0)
+    tot = int(m.sum())
+    eid = np.repeat(np.arange(E), m)
+    t = t_lo[eid] + (t_hi[eid] - t_lo[eid]) * jr.random(tot)
+    order = np.lexsort((t, eid))
+    t = t[order]
+    seg_start = np.r_[0, np.cumsum(m)[:-1]]
+    first = np.zeros(tot, bool)
+    first[seg_start[m > 0]] = True
+    last = np.zeros(tot, bool)
+    last[(seg_start + m - 1)[m > 0]] = True
+    prev_t = np.where(first, 0.0, np.r_[0.0, t[:-1]])
+    next_t = np.where(last, 1.0, np.r_[t[1:], 1.0])
+    spacing = np.minimum(t - prev_t, next_t - t) * L[eid]
+    cap = np.minimum(np.minimum(hA[eid] * t, hB[eid] * (1.0 - t)) * L[eid], 0.25 * spacing)
+    cap = np.minimum(cap, 0.3 * dsep[eid])
+    u = jr.uniform(-1.0, 1.0, size=tot) * cap
+    dx, dy = (B[:, 0] - A[:, 0])[eid], (B[:, 1] - A[:, 1])[eid]
+    nx, ny = -dy / Ls[eid], dx / Ls[eid]
+    px = A[eid, 0] + t * dx + u * nx
+    py = A[eid, 1] + t * dy + u * ny
+    q = np.floor(np.c_[px, py] + 0.5).astype(np.int64)
+    # drop points equal to their predecessor on the same edge or to an endpoint
+    dup = np.r_[False, np.all(q[1:] == q[:-1], axis=1) & (eid[1:] == eid[:-1])]
+    endp = np.all(q == vq[ea[eid]], axis=1) | np.all(q == vq[eb[eid]], axis=1)
+    keep = ~(dup | endp)
+    q, eid_k = q[keep], eid[keep]
+    cnt = np.bincount(eid_k, minlength=E)
+    eoff = np.r_[0, np.cumsum(cnt)]
 
     polys = []
-    for ci, ring in enumerate(cells):
-        m = len(ring)
+    off = 0
+    for c in cells:
+        mm = len(c)
         out = []
-        for t in range(m):
-            a, b = ring[t], ring[(t + 1) % m]
+        for k in range(mm):
+            a, b = int(c[k]), int(c[(k + 1) % mm])
             out.append(vq[a][None, :])
-            e = kidx[(min(a, b), max(a, b))]
-            q = poly_of_edge[e]
-            if q is not None and len(q):
-                out.append(q if a < b else q[::-1])
+            e = int(eidx[off + k])
+            seg = q[eoff[e]:eoff[e + 1]]
+            if len(seg):
+                out.append(seg if a < b else seg[::-1])
+        off += mm
         polys.append([np.concatenate(out, axis=0)])
     return polygons_from_rings(polys)
 

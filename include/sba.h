@@ -76,6 +76,10 @@ typedef struct {
     int32_t log2_leaves;  /* learned index: number of leaves = 2^log2_leaves (0 -> 16)   */
     int32_t tile_log2;    /* grid: tile side 2^tile_log2 cells, 3..8 (0 -> chosen from
                              the grid size)                                              */
+    int32_t use_window;   /* 1: store only the cells that overlap the clip window        */
+    int32_t win_x0, win_y0, win_x1, win_y1;  /* clip window [x0,x1) x [y0,y1), coordinates;
+                             cells outside it are empty in the handle (for viewport
+                             queries: the answer inside the window is unchanged)         */
 } sba_build_opts;
 
 typedef struct {
@@ -146,6 +150,54 @@ int sba_aggregate(const int32_t *xy, const int64_t *values, int64_t n, const sba
 int sba_aggregate_search(const int32_t *xy, const int64_t *values, int64_t n,
                          const sba_handle *h, int32_t search, uint64_t *counts,
                          int64_t *sums, void *stream);
+
+/*
+ * One aggregation task of a batch (serving: viewport queries).
+ *   xy, values   the point table (as for sba_aggregate); the task reads the
+ *                points with index in [lo, hi).  values may be NULL (COUNT).
+ *   h            approximation handle; search: SBA_SEARCH_* for the Hilbert
+ *                layout (ignored for the grid).
+ *   vx, vy, vw, vh  viewport: only points with vx <= x < vx+vw and
+ *                vy <= y < vy+vh count; vw <= 0 or vh <= 0 means no filter.
+ *   counts, sums [h->n_polys] outputs (sums may be NULL).
+ */
+typedef struct {
+    const int32_t    *xy;
+    const int64_t    *values;
+    int64_t           lo, hi;
+    const sba_handle *h;
+    int32_t           search;
+    int32_t           vx, vy, vw, vh;
+    uint64_t         *counts;
+    int64_t          *sums;
+} sba_task;
+
+/*
+ * Answer n_tasks aggregation tasks with one persistent launch on `stream`
+ * (continuous batching of uneven queries; Sec. 1: interactive level-of-detail
+ * exploration).  The outputs of all tasks are zeroed first, then every task
+ * adds its points; tasks that name the same output buffers therefore
+ * accumulate into them (a query split into several point ranges).  Results
+ * are identical to running the tasks one by one.
+ *   tasks  HOST array of n_tasks descriptors (copied during the call).
+ * Asynchronous on `stream`.  Errors: SBA_EINVAL (null task fields, lo > hi,
+ * misaligned xy/values), SBA_ENOMEM, SBA_EDEVICE.
+ */
+int sba_aggregate_batch(const sba_task *tasks, int32_t n_tasks, void *stream);
+
+/*
+ * Reorder a point table into G x G buckets of `cell` x `cell` units,
+ * row-major, anchored at (x0, y0) (points outside the bucket grid go to the
+ * nearest border bucket), so that the points of a viewport are a few
+ * contiguous ranges (one per bucket row).  Serving preprocessing.
+ *   xy [2n], values [n] (may be NULL) in; out_xy [2n], out_values [n] out.
+ *   bucket_off [G*G+1] out: bucket b holds points [bucket_off[b], bucket_off[b+1]).
+ *   1 <= G <= 4096, cell >= 1.  Order inside a bucket is unspecified.
+ * Asynchronous on `stream`.
+ */
+int sba_bucket_points(const int32_t *xy, const int64_t *values, int64_t n, int32_t x0,
+                      int32_t y0, int32_t cell, int32_t G, int32_t *out_xy,
+                      int64_t *out_values, int64_t *bucket_off, void *stream);
 
 /*
  * Cell lookup, for checking the approximation itself.

@@ -15,6 +15,7 @@ import os
 import numpy as np
 
 __all__ = ["Approx", "SbaError", "lib", "library_path", "celldiv", "hilbert", "hilbert_cell",
+           "aggregate_batch", "bucket_points", "Task",
            "KIND_GRID", "KIND_HILBERT", "SEARCH_BINARY", "SEARCH_LEARNED"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,7 +40,15 @@ class _Polys(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("search", C.c_int32), ("log2_leaves", C.c_int32),
-                ("tile_log2", C.c_int32)]
+                ("tile_log2", C.c_int32), ("use_window", C.c_int32), ("win_x0", C.c_int32),
+                ("win_y0", C.c_int32), ("win_x1", C.c_int32), ("win_y1", C.c_int32)]
+
+
+class _Task(C.Structure):
+    _fields_ = [("xy", C.c_void_p), ("values", C.c_void_p), ("lo", C.c_int64), ("hi", C.c_int64),
+                ("h", C.c_void_p), ("search", C.c_int32), ("vx", C.c_int32), ("vy", C.c_int32),
+                ("vw", C.c_int32), ("vh", C.c_int32), ("counts", C.c_void_p),
+                ("sums", C.c_void_p)]
 
 
 class _Info(C.Structure):
@@ -71,6 +80,10 @@ def lib():
     L.sba_aggregate.argtypes = [vp, vp, i64, vp, vp, vp, vp]
     L.sba_aggregate_search.restype = C.c_int
     L.sba_aggregate_search.argtypes = [vp, vp, i64, vp, i32, vp, vp, vp]
+    L.sba_aggregate_batch.restype = C.c_int
+    L.sba_aggregate_batch.argtypes = [C.POINTER(_Task), i32, vp]
+    L.sba_bucket_points.restype = C.c_int
+    L.sba_bucket_points.argtypes = [vp, vp, i64, i32, i32, i32, i32, vp, vp, vp, vp]
     L.sba_lookup_cells.restype = C.c_int
     L.sba_lookup_cells.argtypes = [vp, vp, i64, vp, vp]
     L.sba_get_sets.restype = C.c_int
@@ -149,11 +162,12 @@ class Approx:
 
     ring_off (int32 [P+1]), vert_off (int64 [R+1]) and xy (int32 [2V]) are the
     polygons in CSR form (torch tensors or numpy arrays; copied to the GPU).
+    window: optional clip window (x0, y0, x1, y1), half-open, in coordinates.
     """
 
     def __init__(self, ring_off, vert_off, xy, eps: int, kind: str = "grid",
                  search: str = "binary", log2_leaves: int = 16, tile_log2: int = 0,
-                 device: str = "cuda", stream=None):
+                 window=None, device: str = "cuda", stream=None):
         torch = _torch()
         self._h = C.c_void_p(None)
         self.device = torch.device(device)
@@ -162,9 +176,10 @@ class Approx:
         pxy = _dev(xy, torch.int32, self.device)
         self.n_polys = int(ro.shape[0] - 1)
         polys = _Polys(self.n_polys, ro.data_ptr(), vo.data_ptr(), pxy.data_ptr())
+        win = (0, 0, 0, 0, 0) if window is None else (1, *[int(v) for v in window])
         opts = _Opts({"grid": KIND_GRID, "hilbert": KIND_HILBERT}[kind],
                      {"binary": SEARCH_BINARY, "learned": SEARCH_LEARNED}[search],
-                     int(log2_leaves), int(tile_log2))
+                     int(log2_leaves), int(tile_log2), *win)
         h = C.c_void_p(None)
         with torch.cuda.device(self.device):
             rc = lib().sba_build_approx(C.byref(polys), int(eps), C.byref(opts),
@@ -180,9 +195,12 @@ class Approx:
         """polys: any object with numpy ring_off / vert_off / xy arrays."""
         return cls(polys.ring_off, polys.vert_off, polys.xy, eps, **kw)
 
-    def close(self):
+    def close(self, sync: bool = True):
+        """Free the handle.  With sync=False the caller guarantees that no
+        queued GPU work still uses it (nothing is synchronised)."""
         if self._h:
-            _torch().cuda.synchronize(self.device)
+            if sync:
+                _torch().cuda.synchronize(self.device)
             lib().sba_free(self._h)
             self._h = C.c_void_p(None)
 
@@ -271,3 +289,55 @@ class Approx:
                 k = -2 - r
                 out.append(tuple(int(v) for v in ids[off[k]:off[k + 1]]))
         return out
+
+
+class Task:
+    """One task of ``aggregate_batch``: points [lo, hi) of (xy, values), a
+    handle, an optional viewport (vx, vy, vw, vh) and output tensors."""
+
+    def __init__(self, approx: "Approx", xy, values=None, lo: int = 0, hi: int | None = None,
+                 viewport=None, counts=None, sums=None, search: str = "binary"):
+        torch = _torch()
+        self.approx = approx
+        self.xy = xy
+        self.values = values
+        n = xy.numel() // 2
+        self.lo = int(lo)
+        self.hi = n if hi is None else int(hi)
+        self.viewport = viewport
+        self.search = search
+        np_ = max(approx.n_polys, 1)
+        self.counts = counts if counts is not None else torch.empty(np_, dtype=torch.int64,
+                                                                    device=xy.device)
+        if values is not None and sums is None:
+            sums = torch.empty(np_, dtype=torch.int64, device=xy.device)
+        self.sums = sums
+
+    def _c(self) -> _Task:
+        vx, vy, vw, vh = self.viewport if self.viewport is not None else (0, 0, 0, 0)
+        return _Task(self.xy.data_ptr(), self.values.data_ptr() if self.values is not None else None,
+                     self.lo, self.hi, self.approx._h,
+                     {"binary": SEARCH_BINARY, "learned": SEARCH_LEARNED}[self.search],
+                     int(vx), int(vy), int(vw), int(vh), self.counts.data_ptr(),
+                     self.sums.data_ptr() if self.sums is not None else None)
+
+
+def aggregate_batch(tasks, stream=None):
+    """Run ``sba_aggregate_batch`` over a list of Task objects (asynchronous)."""
+    arr = (_Task * max(len(tasks), 1))(*[t._c() for t in tasks])
+    _check(lib().sba_aggregate_batch(arr, len(tasks), _stream_ptr(stream)), "sba_aggregate_batch")
+    return tasks
+
+
+def bucket_points(xy, values, x0: int, y0: int, cell: int, G: int, stream=None):
+    """``sba_bucket_points``: returns (xy, values, bucket_off) GPU tensors."""
+    torch = _torch()
+    n = xy.numel() // 2
+    oxy = torch.empty_like(xy)
+    ov = torch.empty_like(values) if values is not None else None
+    off = torch.empty(G * G + 1, dtype=torch.int64, device=xy.device)
+    _check(lib().sba_bucket_points(xy.data_ptr(), values.data_ptr() if values is not None else None,
+                                   n, int(x0), int(y0), int(cell), int(G), oxy.data_ptr(),
+                                   ov.data_ptr() if ov is not None else None, off.data_ptr(),
+                                   _stream_ptr(stream)), "sba_bucket_points")
+    return oxy, ov, off

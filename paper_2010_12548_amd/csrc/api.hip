@@ -4,16 +4,14 @@
 
 #include "sba_internal.h"
 
+// The handle's arrays come from the device's stream-ordered pool; returning
+// them does not synchronise the device (the caller guarantees that no queued
+// work still reads the handle).
 static void handle_release(sba_handle *h)
 {
-    (void)hipFree(h->dir);
-    (void)hipFree(h->blocks);
-    (void)hipFree(h->set_off);
-    (void)hipFree(h->set_ids);
-    (void)hipFree(h->starts);
-    (void)hipFree(h->starts32);
-    (void)hipFree(h->run_code);
-    (void)hipFree(h->leaves);
+    void *arrs[] = {h->dir, h->blocks, h->set_off, h->set_ids, h->starts, h->starts32,
+                    h->run_code, h->leaves};
+    for (void *p : arrs) tmp_free(p, nullptr);
 }
 
 extern "C" int sba_build_approx(const sba_polygons *polys, int64_t eps, const sba_build_opts *opts,
@@ -64,6 +62,31 @@ extern "C" int sba_aggregate(const int32_t *xy, const int64_t *values, int64_t n
 {
     RC(check_probe_args(xy, values, n, h, counts));
     return probe_launch(xy, values, n, h, h->search, counts, sums, (hipStream_t)stream);
+}
+
+extern "C" int sba_aggregate_batch(const sba_task *tasks, int32_t n_tasks, void *stream)
+{
+    if (n_tasks < 0 || (n_tasks > 0 && !tasks)) return SBA_EINVAL;
+    for (int32_t k = 0; k < n_tasks; k++) {
+        const sba_task &t = tasks[k];
+        if (!t.h || t.lo < 0 || t.hi < t.lo) return SBA_EINVAL;
+        if (t.h->n_polys > 0 && !t.counts) return SBA_EINVAL;
+        if (t.hi > t.lo && !t.xy) return SBA_EINVAL;
+        if (((uintptr_t)t.xy & 15) != 0 || ((uintptr_t)t.values & 15) != 0) return SBA_EINVAL;
+        if (t.search == SBA_SEARCH_LEARNED && t.h->kind == SBA_KIND_HILBERT && !t.h->leaves)
+            return SBA_EINVAL;
+    }
+    return batch_launch(tasks, n_tasks, (hipStream_t)stream);
+}
+
+extern "C" int sba_bucket_points(const int32_t *xy, const int64_t *values, int64_t n, int32_t x0,
+                                 int32_t y0, int32_t cell, int32_t G, int32_t *out_xy,
+                                 int64_t *out_values, int64_t *bucket_off, void *stream)
+{
+    if (n < 0 || G < 1 || G > 4096 || cell < 1 || !bucket_off) return SBA_EINVAL;
+    if (n > 0 && (!xy || !out_xy || (values && !out_values))) return SBA_EINVAL;
+    return bucket_launch(xy, values, n, x0, y0, cell, G, out_xy, out_values, bucket_off,
+                         (hipStream_t)stream);
 }
 
 extern "C" int sba_lookup_cells(const sba_handle *h, const int64_t *ij, int64_t n, int32_t *ref,

@@ -81,16 +81,28 @@ __global__ void k_poly_bbox(const int32_t *ring_off, const int64_t *vert_off, co
     if (lane == 0) bbox[p] = make_int4(xmin, ymin, xmax, ymax);
 }
 
-// per edge: number of boundary row strips and of row-line crossings
-__global__ void k_edge_counts(const int4 *edges, int64_t n_edges, int64_t s, int64_t *nb,
-                              int64_t *nc)
+// per edge: number of boundary row strips and of row-line crossings inside
+// the stored box [gi0,gi1] x [gj0,gj1] (the box is the union of the cell
+// boxes, cut by the clip window if there is one); polygons whose cell box
+// misses the box in x contribute nothing inside it
+__global__ void k_edge_counts(const int4 *edges, const int32_t *epoly, const int4 *bbox,
+                              int64_t n_edges, int64_t s, int64_t gi0, int64_t gj0, int64_t gi1,
+                              int64_t gj1, int64_t *nb, int64_t *nc)
 {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_edges) return;
     int4 E = edges[e];
+    int4 bb = bbox[epoly[e]];
+    if (floordiv64(bb.z, s) < gi0 || ceildiv64(bb.x, s) - 1 > gi1) {
+        nb[e] = 0;
+        nc[e] = 0;
+        return;
+    }
     int64_t ey0 = min(E.y, E.w), ey1 = max(E.y, E.w);
-    nb[e] = floordiv64(ey1, s) - (ceildiv64(ey0, s) - 1) + 1;
-    nc[e] = (E.y != E.w) ? ceildiv64(ey1, s) - ceildiv64(ey0, s) : 0;
+    int64_t ja = max(ceildiv64(ey0, s) - 1, gj0), jb = min(floordiv64(ey1, s), gj1);
+    nb[e] = jb >= ja ? jb - ja + 1 : 0;
+    int64_t ka = max(ceildiv64(ey0, s), gj0), kb = min(ceildiv64(ey1, s) - 1, gj1);
+    nc[e] = (E.y != E.w && kb >= ka) ? kb - ka + 1 : 0;
 }
 
 __device__ __forceinline__ int64_t upper_bound_i64(const int64_t *a, int64_t n, int64_t v)
@@ -104,10 +116,12 @@ __device__ __forceinline__ int64_t upper_bound_i64(const int64_t *a, int64_t n, 
 }
 
 // boundary item t -> interval of cells [c0, c1] of row j touched by its edge,
-// written as a start and an end event
+// cut to the stored box, written as a start and an end event (an interval
+// cut away entirely becomes an empty start/end pair at x = 0)
 __global__ void k_emit_boundary(const int4 *edges, const int32_t *epoly, int64_t n_edges,
                                 const int64_t *boff, int64_t nb_total, int64_t s, int64_t gi0,
-                                int64_t gj0, int xbits, uint64_t *evkey, uint32_t *evpay)
+                                int64_t gj0, int64_t gi1, int xbits, uint64_t *evkey,
+                                uint32_t *evpay)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nb_total) return;
@@ -115,7 +129,7 @@ __global__ void k_emit_boundary(const int4 *edges, const int32_t *epoly, int64_t
     int4 E = edges[e];
     int64_t x1 = E.x, y1 = E.y, x2 = E.z, y2 = E.w;
     int64_t ey0 = min(y1, y2), ey1 = max(y1, y2);
-    int64_t j = ceildiv64(ey0, s) - 1 + (t - boff[e]);
+    int64_t j = max(ceildiv64(ey0, s) - 1, gj0) + (t - boff[e]);
     int64_t c0, c1;
     if (y1 == y2) {
         c0 = ceildiv64(min(x1, x2), s) - 1;
@@ -131,6 +145,9 @@ __global__ void k_emit_boundary(const int4 *edges, const int32_t *epoly, int64_t
         c0 = ceildiv64(lo, den * s) - 1;
         c1 = floordiv64(hi, den * s);
     }
+    c0 = max(c0, gi0);
+    c1 = min(c1, gi1);
+    if (c0 > c1) { c0 = gi0; c1 = gi0 - 1; }
     uint64_t r = (uint64_t)(j - gj0);
     uint32_t p = (uint32_t)epoly[e];
     evkey[2 * t] = (r << xbits) | (uint64_t)(c0 - gi0);
@@ -139,10 +156,11 @@ __global__ void k_emit_boundary(const int4 *edges, const int32_t *epoly, int64_t
     evpay[2 * t + 1] = (p << 1) | 1u;
 }
 
-// crossing item t -> key (polygon, row, k) with k = ceil(xc / s)
+// crossing item t -> key (polygon, row, k) with k = ceil(xc / s), k cut to
+// [gi0, gi1 + 1] (spans are then cut to the stored box)
 __global__ void k_emit_cross(const int4 *edges, const int32_t *epoly, int64_t n_edges,
                              const int64_t *coff, int64_t nc_total, int64_t s, int64_t gi0,
-                             int64_t gj0, int xbits, int rbits, uint64_t *ckey)
+                             int64_t gj0, int64_t gi1, int xbits, int rbits, uint64_t *ckey)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nc_total) return;
@@ -150,11 +168,12 @@ __global__ void k_emit_cross(const int4 *edges, const int32_t *epoly, int64_t n_
     int4 E = edges[e];
     int64_t x1 = E.x, y1 = E.y, x2 = E.z, y2 = E.w;
     int64_t ey0 = min(y1, y2);
-    int64_t j = ceildiv64(ey0, s) + (t - coff[e]);
+    int64_t j = max(ceildiv64(ey0, s), gj0) + (t - coff[e]);
     int64_t den = y2 - y1;
     int64_t num = x1 * den + (j * s - y1) * (x2 - x1);
     if (den < 0) { den = -den; num = -num; }
     int64_t k = ceildiv64(num, den * s);
+    k = min(max(k, gi0), gi1 + 1);
     ckey[t] = ((uint64_t)epoly[e] << (rbits + xbits)) | ((uint64_t)(j - gj0) << xbits) |
               (uint64_t)(k - gi0);
 }
@@ -194,53 +213,81 @@ __global__ void k_row_off(const uint64_t *evkey, int64_t ne, int64_t gh, int xbi
 
 // One thread per row: sweep the row's events in x order, keep the multiset
 // of open polygons, emit a segment whenever the set of polygons changes.
+// The per-thread sets live in LDS, laid out [slot][thread] so that lanes
+// touching the same slot hit different banks.
+#define SWEEP_BLOCK 64
 template <bool WRITE>
-__global__ __launch_bounds__(64) void k_sweep(const uint64_t *evkey, const uint32_t *evpay,
-                                              const int64_t *ev_row_off, int64_t gh, int xbits,
-                                              int64_t *cnt_seg, int64_t *cnt_multi,
-                                              int64_t *cnt_mem, const int64_t *off_seg,
-                                              const int64_t *off_multi, const int64_t *off_mem,
-                                              int32_t *seg_x0, int32_t *seg_x1, uint32_t *seg_code,
-                                              int64_t *multi_seg, int64_t *multi_mem,
-                                              int32_t *mem_ids, int *err)
+__global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(const uint64_t *evkey, const uint32_t *evpay,
+                                                       const int64_t *ev_row_off, int64_t gh,
+                                                       int xbits, int64_t *cnt_seg,
+                                                       int64_t *cnt_multi, int64_t *cnt_mem,
+                                                       const int64_t *off_seg,
+                                                       const int64_t *off_multi,
+                                                       const int64_t *off_mem, int32_t *seg_x0,
+                                                       int32_t *seg_x1, uint32_t *seg_code,
+                                                       int64_t *multi_seg, int64_t *multi_mem,
+                                                       int32_t *mem_ids, int *err)
 {
+    __shared__ int s_ids[MAX_DEPTH][SWEEP_BLOCK];
+    __shared__ int s_cnt[MAX_DEPTH][SWEEP_BLOCK];
+    __shared__ int s_oid[MAX_DEPTH][SWEEP_BLOCK];
+    const int tl = threadIdx.x;
+#define IDS(k) s_ids[k][tl]
+#define CNT(k) s_cnt[k][tl]
+#define OID(k) s_oid[k][tl]
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= gh) return;
     const uint64_t xmask = (1ull << xbits) - 1;
-    int ids[MAX_DEPTH], cnt[MAX_DEPTH], oid[MAX_DEPTH];
     int na = 0, ona = 0;
     uint32_t ox0 = 0;
     int64_t nseg = 0, nmulti = 0, nmem = 0;
     int64_t t = ev_row_off[r], te = ev_row_off[r + 1];
     int bad = 0;
+    uint64_t key = t < te ? evkey[t] : 0;
     while (t < te) {
-        uint32_t x = (uint32_t)(evkey[t] & xmask);
-        while (t < te && (uint32_t)(evkey[t] & xmask) == x) {
+        uint32_t x = (uint32_t)(key & xmask);
+        bool changed = false;
+        while (t < te && (uint32_t)(key & xmask) == x) {
             uint32_t pay = evpay[t];
+            t++;
+            key = t < te ? evkey[t] : 0;
             int p = (int)(pay >> 1);
             int k = 0;
-            while (k < na && ids[k] < p) k++;
+            while (k < na && IDS(k) < p) k++;
             if (pay & 1u) {
-                if (k < na && ids[k] == p) cnt[k]--;
-                else bad |= 4;
-            } else if (k < na && ids[k] == p) {
-                cnt[k]++;
+                if (k < na && IDS(k) == p) {
+                    int c = CNT(k) - 1;
+                    CNT(k) = c;
+                    changed |= (c == 0);
+                } else {
+                    bad |= 4;
+                }
+            } else if (k < na && IDS(k) == p) {
+                int c = CNT(k) + 1;
+                CNT(k) = c;
+                changed |= (c == 1);
             } else if (na == MAX_DEPTH) {
                 bad |= 8;
             } else {
-                for (int q = na; q > k; q--) { ids[q] = ids[q - 1]; cnt[q] = cnt[q - 1]; }
-                ids[k] = p;
-                cnt[k] = 1;
+                for (int q = na; q > k; q--) { IDS(q) = IDS(q - 1); CNT(q) = CNT(q - 1); }
+                IDS(k) = p;
+                CNT(k) = 1;
                 na++;
+                changed = true;
             }
-            t++;
         }
+        if (!changed) continue;  // counts moved, membership did not
         int m = 0;
-        for (int k = 0; k < na; k++)
-            if (cnt[k] > 0) { ids[m] = ids[k]; cnt[m] = cnt[k]; m++; }
+        for (int k = 0; k < na; k++) {
+            int c = CNT(k);
+            if (c > 0) {
+                if (m != k) { IDS(m) = IDS(k); CNT(m) = c; }
+                m++;
+            }
+        }
         na = m;
         bool same = (na == ona);
-        for (int k = 0; same && k < na; k++) same = (ids[k] == oid[k]);
+        for (int k = 0; same && k < na; k++) same = (IDS(k) == OID(k));
         if (!same) {
             if (ona > 0) {
                 if (WRITE) {
@@ -248,24 +295,27 @@ __global__ __launch_bounds__(64) void k_sweep(const uint64_t *evkey, const uint3
                     seg_x0[si] = (int32_t)ox0;
                     seg_x1[si] = (int32_t)x;
                     if (ona == 1) {
-                        seg_code[si] = (uint32_t)oid[0] + 1u;
+                        seg_code[si] = (uint32_t)OID(0) + 1u;
                     } else {
                         int64_t mi = off_multi[r] + nmulti;
                         int64_t mo = off_mem[r] + nmem;
                         seg_code[si] = 0xffffffffu;
                         multi_seg[mi] = si;
                         multi_mem[mi] = mo;
-                        for (int k = 0; k < ona; k++) mem_ids[mo + k] = oid[k];
+                        for (int k = 0; k < ona; k++) mem_ids[mo + k] = OID(k);
                     }
                 }
                 nseg++;
                 if (ona > 1) { nmulti++; nmem += ona; }
             }
-            for (int k = 0; k < na; k++) oid[k] = ids[k];
+            for (int k = 0; k < na; k++) OID(k) = IDS(k);
             ona = na;
             ox0 = x;
         }
     }
+#undef IDS
+#undef CNT
+#undef OID
     if (ona != 0) bad |= 16;
     if (bad) atomicOr(err, bad);
     if (!WRITE) {
@@ -277,17 +327,19 @@ __global__ __launch_bounds__(64) void k_sweep(const uint64_t *evkey, const uint3
 
 // ------------------------------------------------ multi-polygon set dedup
 
+// Sets of 2 or 3 polygons are packed exactly into fb-bit fields (fb bits hold
+// id+1); larger sets get a key of their own above that range (not shared).
 __global__ void k_multi_keys(const int64_t *multi_mem, int64_t n_multi, int64_t n_mem,
-                             const int32_t *mem_ids, uint64_t *key, uint32_t *val)
+                             const int32_t *mem_ids, int fb, uint64_t *key, uint32_t *val)
 {
     int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n_multi) return;
     int64_t a = multi_mem[m], b = (m + 1 < n_multi) ? multi_mem[m + 1] : n_mem;
     uint64_t k = 0;
     if (b - a <= 3) {
-        for (int64_t t = a; t < b; t++) k |= (uint64_t)(mem_ids[t] + 1) << (21 * (t - a));
+        for (int64_t t = a; t < b; t++) k |= (uint64_t)(mem_ids[t] + 1) << (fb * (t - a));
     } else {
-        k = (1ull << 63) | (uint64_t)m;  // not shared: a set of its own
+        k = (1ull << (3 * fb)) | (uint64_t)m;
     }
     key[m] = k;
     val[m] = (uint32_t)m;
@@ -526,6 +578,18 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     }
     B.cmin = cmin;
     B.cmax = cmax;
+    if (B.window) {
+        gi0 = std::max(gi0, floordiv64(B.wx0, s));
+        gj0 = std::max(gj0, floordiv64(B.wy0, s));
+        gi1 = std::min(gi1, floordiv64(B.wx1 - 1, s));
+        gj1 = std::min(gj1, floordiv64(B.wy1 - 1, s));
+        if (gi0 > gi1 || gj0 > gj1) {  // nothing of any polygon inside the window
+            h->gi0 = h->gj0 = 0;
+            h->gw = h->gh = 0;
+            B.empty = true;
+            return 0;
+        }
+    }
     h->gi0 = gi0;
     h->gj0 = gj0;
     h->gw = gi1 - gi0 + 1;
@@ -543,7 +607,8 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     RC(B.alloc(&nb, nv + 1));
     RC(B.alloc(&nc, nv + 1));
     RC(B.alloc(&tot, 2));
-    hipLaunchKernelGGL(k_edge_counts, dim3(grid_for(nv)), dim3(256), 0, st, B.edges, nv, s, nb, nc);
+    hipLaunchKernelGGL(k_edge_counts, dim3(grid_for(nv)), dim3(256), 0, st, B.edges, B.epoly, bbox,
+                       nv, s, gi0, gj0, gi1, gj1, nb, nc);
     HIP_OK(hipGetLastError());
     RC(scan_exclusive_i64(nb, nb, nv, tot, st));
     RC(scan_exclusive_i64(nc, nc, nv, tot + 1, st));
@@ -560,12 +625,12 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     RC(B.alloc(&B.evpay, NE));
     if (NB)
         hipLaunchKernelGGL(k_emit_boundary, dim3(grid_for(NB)), dim3(256), 0, st, B.edges, B.epoly,
-                           nv, nb, NB, s, gi0, gj0, B.xbits, B.evkey, B.evpay);
+                           nv, nb, NB, s, gi0, gj0, gi1, B.xbits, B.evkey, B.evpay);
     if (NC) {
         uint64_t *ckey = nullptr;
         RC(B.alloc(&ckey, NC));
         hipLaunchKernelGGL(k_emit_cross, dim3(grid_for(NC)), dim3(256), 0, st, B.edges, B.epoly, nv,
-                           nc, NC, s, gi0, gj0, B.xbits, B.rbits, ckey);
+                           nc, NC, s, gi0, gj0, gi1, B.xbits, B.rbits, ckey);
         HIP_OK(hipGetLastError());
         RC(radix_sort_u64(ckey, nullptr, NC, pbits + B.rbits + B.xbits, st));
         hipLaunchKernelGGL(k_spans, dim3(grid_for(NC / 2)), dim3(256), 0, st, ckey, NC / 2, B.xbits,
@@ -590,7 +655,7 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     RC(B.alloc(&cs, gh + 1));
     RC(B.alloc(&cm, gh + 1));
     RC(B.alloc(&cme, gh + 1));
-    hipLaunchKernelGGL(k_sweep<false>, dim3(grid_for(gh, 64)), dim3(64), 0, st, B.evkey, B.evpay,
+    hipLaunchKernelGGL(k_sweep<false>, dim3(grid_for(gh, SWEEP_BLOCK)), dim3(SWEEP_BLOCK), 0, st, B.evkey, B.evpay,
                        ev_row_off, gh, B.xbits, cs, cm, cme, (const int64_t *)nullptr,
                        (const int64_t *)nullptr, (const int64_t *)nullptr, (int32_t *)nullptr,
                        (int32_t *)nullptr, (uint32_t *)nullptr, (int64_t *)nullptr,
@@ -621,7 +686,7 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     RC(B.alloc(&multi_seg, NM));
     RC(B.alloc(&multi_mem, NM));
     RC(B.alloc(&mem_ids, NMEM));
-    hipLaunchKernelGGL(k_sweep<true>, dim3(grid_for(gh, 64)), dim3(64), 0, st, B.evkey, B.evpay,
+    hipLaunchKernelGGL(k_sweep<true>, dim3(grid_for(gh, SWEEP_BLOCK)), dim3(SWEEP_BLOCK), 0, st, B.evkey, B.evpay,
                        ev_row_off, gh, B.xbits, (int64_t *)nullptr, (int64_t *)nullptr,
                        (int64_t *)nullptr, cs, cm, cme, B.seg_x0, B.seg_x1, B.seg_code, multi_seg,
                        multi_mem, mem_ids, err);
@@ -645,10 +710,13 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
         RC(B.alloc(&mkey, NM));
         RC(B.alloc(&mval, NM));
         RC(B.alloc(&g, NM + 1));
+        const int fb = std::min(pbits + 1, 21);  // ids + 1 < 2^21
+        const int kbits = std::max(3 * fb + 1, bits_for(((uint64_t)1 << (3 * fb)) | (uint64_t)NM));
+        if (kbits > 64) return SBA_ELIMIT;
         hipLaunchKernelGGL(k_multi_keys, dim3(grid_for(NM)), dim3(256), 0, st, multi_mem, NM, NMEM,
-                           mem_ids, mkey, mval);
+                           mem_ids, fb, mkey, mval);
         HIP_OK(hipGetLastError());
-        RC(radix_sort_u64(mkey, mval, NM, 64, st));
+        RC(radix_sort_u64(mkey, mval, NM, kbits, st));
         hipLaunchKernelGGL(k_flag_new, dim3(grid_for(NM)), dim3(256), 0, st, mkey, NM, g);
         HIP_OK(hipGetLastError());
         RC(scan_exclusive_i64(g, g, NM, tot, st));
@@ -659,12 +727,12 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
         hipLaunchKernelGGL(k_set_sizes, dim3(grid_for(NM)), dim3(256), 0, st, mkey, mval, g, NM,
                            multi_mem, NM, NMEM, set_sz);
         HIP_OK(hipGetLastError());
-        RC(dev_alloc(&h->set_off, nsets + 1));
+        RC(tmp_alloc(&h->set_off, nsets + 1, st));
         RC(scan_exclusive_i64(set_sz, h->set_off, nsets, h->set_off + nsets, st));
         int64_t nids = 0;
         HIP_OK(hipMemcpyAsync(&nids, h->set_off + nsets, sizeof(int64_t), hipMemcpyDeviceToHost, st));
         HIP_OK(hipStreamSynchronize(st));
-        RC(dev_alloc(&h->set_ids, nids));
+        RC(tmp_alloc(&h->set_ids, nids, st));
         hipLaunchKernelGGL(k_set_fill, dim3(grid_for(NM)), dim3(256), 0, st, mkey, mval, g, NM,
                            multi_mem, NM, NMEM, mem_ids, h->set_off, h->set_ids, multi_seg,
                            B.seg_code);
@@ -699,7 +767,7 @@ int build_grid(sba_handle *h, BuildState &B, int tile_log2, hipStream_t st)
     h->th = (h->gh + (1 << tl) - 1) >> tl;
     const int64_t nt = h->tw * h->th;
     if (nt >= ((int64_t)1 << 31)) return SBA_ELIMIT;
-    RC(dev_alloc(&h->dir, nt));
+    RC(tmp_alloc(&h->dir, nt, st));
     h->bytes += nt * 4;
     int64_t *mixed = nullptr, *tot = nullptr;
     RC(B.alloc(&mixed, nt + 1));
@@ -713,7 +781,7 @@ int build_grid(sba_handle *h, BuildState &B, int tile_log2, hipStream_t st)
     HIP_OK(hipStreamSynchronize(st));
     if (nblk >= (int64_t)TILE_MIXED) return SBA_ELIMIT;
     h->n_blocks = nblk;
-    RC(dev_alloc(&h->blocks, nblk << (2 * tl)));
+    RC(tmp_alloc(&h->blocks, nblk << (2 * tl), st));
     h->bytes += (nblk << (2 * tl)) * 4;
     hipLaunchKernelGGL(k_tile_fill, dim3((unsigned)nt), dim3(256), 0, st, B.seg_row_off, B.seg_x0,
                        B.seg_x1, B.seg_code, h->gw, h->gh, tl, h->tw, h->dir, mixed, h->blocks);
@@ -736,8 +804,9 @@ int build_handle(const sba_polygons *polys, int64_t eps, const sba_build_opts *o
                  hipStream_t st, sba_handle *h)
 {
     auto t0 = std::chrono::steady_clock::now();
-    sba_build_opts o = {SBA_KIND_GRID, SBA_SEARCH_BINARY, 16, 0};
+    sba_build_opts o = {SBA_KIND_GRID, SBA_SEARCH_BINARY, 16, 0, 0, 0, 0, 0, 0};
     if (opts) o = *opts;
+    if (o.use_window && (o.win_x1 <= o.win_x0 || o.win_y1 <= o.win_y0)) return SBA_EINVAL;
     if (o.log2_leaves == 0) o.log2_leaves = 16;
     if (o.kind != SBA_KIND_GRID && o.kind != SBA_KIND_HILBERT) return SBA_EINVAL;
     if (o.search != SBA_SEARCH_BINARY && o.search != SBA_SEARCH_LEARNED) return SBA_EINVAL;
@@ -761,8 +830,19 @@ int build_handle(const sba_polygons *polys, int64_t eps, const sba_build_opts *o
     }
     BuildState B;
     B.st = st;
+    B.window = o.use_window != 0;
+    B.wx0 = o.win_x0;
+    B.wy0 = o.win_y0;
+    B.wx1 = o.win_x1;
+    B.wy1 = o.win_y1;
     if (h->kind == SBA_KIND_HILBERT) RC(hilbert_prepare(B, h));
     RC(build_segments(polys, eps, st, h, B, h->kind == SBA_KIND_HILBERT));
+    if (B.empty) {
+        HIP_OK(hipStreamSynchronize(st));
+        h->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                          .count();
+        return 0;
+    }
     if (h->kind == SBA_KIND_GRID) {
         RC(build_grid(h, B, o.tile_log2, st));
     } else {

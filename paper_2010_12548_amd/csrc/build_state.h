@@ -27,6 +27,10 @@ struct BuildState {
     }
     ~BuildState();
 
+    // clip window in coordinates, [wx0, wx1) x [wy0, wy1)
+    bool window = false;
+    int64_t wx0 = 0, wy0 = 0, wx1 = 0, wy1 = 0;
+    bool empty = false;  // the window holds no cell of any polygon
     // edges: (x1,y1,x2,y2) and polygon id, one per vertex
     int4 *edges = nullptr;
     int32_t *epoly = nullptr;

@@ -340,11 +340,11 @@ int hilbert_finish(BuildState &B, sba_handle *h, const sba_build_opts &o, hipStr
     HIP_OK(hipStreamSynchronize(st));
     if (nr >= ((int64_t)1 << 31)) return SBA_ELIMIT;
     h->n_runs = nr;
-    RC(dev_alloc(&h->starts, nr));
-    RC(dev_alloc(&h->run_code, nr));
+    RC(tmp_alloc(&h->starts, nr, st));
+    RC(tmp_alloc(&h->run_code, nr, st));
     h->bytes += nr * 12;
     if (2 * L <= 32) {
-        RC(dev_alloc(&h->starts32, nr));
+        RC(tmp_alloc(&h->starts32, nr, st));
         h->bytes += nr * 4;
     }
     hipLaunchKernelGGL(k_run_write, dim3(grid_for(nc)), dim3(256), 0, st, ckey, ccode, nc, flag,
@@ -365,7 +365,7 @@ int hilbert_finish(BuildState &B, sba_handle *h, const sba_build_opts &o, hipStr
         RC(B.alloc(&kfirst, nl));
         RC(B.alloc(&merr, 1));
         HIP_OK(hipMemsetAsync(merr, 0, sizeof(int64_t), st));
-        RC(dev_alloc(&h->leaves, nl));
+        RC(tmp_alloc(&h->leaves, nl, st));
         h->bytes += (int64_t)nl * 16;
         hipLaunchKernelGGL(k_leaf_fit, dim3(grid_for((int64_t)nl * 64)), dim3(256), 0, st, h->starts,
                            nr, h->root_a, nl, total, kfirst, h->leaves, merr);

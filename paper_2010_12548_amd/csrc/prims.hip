@@ -39,8 +39,57 @@ __device__ __forceinline__ T block_excl_scan(T v, T *excl)
     return tot;
 }
 
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tiles(const int64_t *in, int64_t *out,
-                                                           int64_t n, int64_t *tile_sums)
+// Small arrays (n <= SCAN_SMALL): one workgroup, one launch.
+#define SCAN_SMALL_ITEMS 32
+#define SCAN_SMALL (SCAN_BLOCK * SCAN_SMALL_ITEMS)
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_small(const int64_t *in, int64_t *out,
+                                                           int64_t n, int64_t *total)
+{
+    const int64_t base = (int64_t)threadIdx.x * SCAN_SMALL_ITEMS;
+    int64_t v[SCAN_SMALL_ITEMS];
+    int64_t run = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_SMALL_ITEMS; k++) {
+        int64_t idx = base + k;
+        v[k] = idx < n ? in[idx] : 0;
+        run += v[k];
+    }
+    int64_t excl;
+    int64_t tot = block_excl_scan<int64_t>(run, &excl);
+#pragma unroll
+    for (int k = 0; k < SCAN_SMALL_ITEMS; k++) {
+        int64_t idx = base + k;
+        if (idx < n) out[idx] = excl;
+        excl += v[k];
+    }
+    if (threadIdx.x == 0 && total) total[0] = tot;
+}
+
+// Large arrays: per-tile sums, scan of the sums, then each tile scanned with
+// its offset (reads the input twice, writes once; in may alias out).
+__global__ __launch_bounds__(SCAN_BLOCK) void k_tile_sums(const int64_t *in, int64_t n,
+                                                          int64_t *sums)
+{
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    int64_t run = 0;
+    for (int k = threadIdx.x; k < SCAN_TILE; k += SCAN_BLOCK) {
+        int64_t idx = base + k;
+        if (idx < n) run += in[idx];
+    }
+    for (int o = 32; o > 0; o >>= 1) run += __shfl_xor(run, o, 64);
+    __shared__ int64_t ws[SCAN_BLOCK / 64];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = run;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int k = 0; k < SCAN_BLOCK / 64; k++) t += ws[k];
+        sums[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_tile_scan(const int64_t *in, int64_t *out,
+                                                          int64_t n, const int64_t *offs)
 {
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
     int64_t v[SCAN_ITEMS];
@@ -52,76 +101,39 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tiles(const int64_t *in, in
         run += v[k];
     }
     int64_t excl;
-    int64_t tot = block_excl_scan<int64_t>(run, &excl);
+    block_excl_scan<int64_t>(run, &excl);
+    excl += offs[blockIdx.x];
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; k++) {
         int64_t idx = base + k;
         if (idx < n) out[idx] = excl;
         excl += v[k];
     }
-    if (threadIdx.x == 0 && tile_sums) tile_sums[blockIdx.x] = tot;
-}
-
-__global__ void k_scan_add(int64_t *out, int64_t n, const int64_t *tile_offs)
-{
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx < n) out[idx] += tile_offs[idx / SCAN_TILE];
-}
-
-__global__ void k_scan_total(const int64_t *in, const int64_t *out, int64_t n, int64_t *total)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) total[0] = n > 0 ? out[n - 1] + in[n - 1] : 0;
-}
-
-// The last input element must be read before the scan overwrites it when
-// in == out; keep a copy.
-__global__ void k_copy_last(const int64_t *in, int64_t n, int64_t *dst)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = n > 0 ? in[n - 1] : 0;
-}
-
-__global__ void k_add_last(const int64_t *out, int64_t n, const int64_t *last, int64_t *total)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) total[0] = n > 0 ? out[n - 1] + last[0] : 0;
-}
-
-static int scan_rec(const int64_t *in, int64_t *out, int64_t n, hipStream_t st)
-{
-    if (n <= 0) return 0;
-    int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
-    if (tiles == 1) {
-        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(SCAN_BLOCK), 0, st, in, out, n,
-                           (int64_t *)nullptr);
-        HIP_OK(hipGetLastError());
-        return 0;
-    }
-    int64_t *sums = nullptr;
-    RC(tmp_alloc(&sums, tiles, st));
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, st, in, out, n,
-                       sums);
-    int rc = hipGetLastError() == hipSuccess ? 0 : SBA_EDEVICE;
-    if (!rc) rc = scan_rec(sums, sums, tiles, st);
-    if (!rc) {
-        hipLaunchKernelGGL(k_scan_add, dim3(grid_for(n)), dim3(256), 0, st, out, n, sums);
-        rc = hipGetLastError() == hipSuccess ? 0 : SBA_EDEVICE;
-    }
-    tmp_free(sums, st);
-    return rc;
 }
 
 int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t st)
 {
-    int64_t *last = nullptr;
-    if (total) {
-        RC(tmp_alloc(&last, 1, st));
-        hipLaunchKernelGGL(k_copy_last, dim3(1), dim3(64), 0, st, in, n, last);
+    if (n <= 0) {
+        if (total) HIP_OK(hipMemsetAsync(total, 0, sizeof(int64_t), st));
+        return 0;
     }
-    int rc = scan_rec(in, out, n, st);
-    if (!rc && total) {
-        hipLaunchKernelGGL(k_add_last, dim3(1), dim3(64), 0, st, out, n, last, total);
+    if (n <= SCAN_SMALL) {
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(SCAN_BLOCK), 0, st, in, out, n, total);
+        HIP_OK(hipGetLastError());
+        return 0;
+    }
+    const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    int64_t *sums = nullptr;
+    RC(tmp_alloc(&sums, tiles, st));
+    hipLaunchKernelGGL(k_tile_sums, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, st, in, n, sums);
+    int rc = hipGetLastError() == hipSuccess ? 0 : SBA_EDEVICE;
+    if (!rc) rc = scan_exclusive_i64(sums, sums, tiles, total, st);
+    if (!rc) {
+        hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, st, in, out, n,
+                           sums);
         rc = hipGetLastError() == hipSuccess ? 0 : SBA_EDEVICE;
     }
-    tmp_free(last, st);
+    tmp_free(sums, st);
     return rc;
 }
 
@@ -141,7 +153,7 @@ int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tota
 #define RS_RADIX 256
 
 __global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const uint64_t *keys, int64_t n, int shift,
-                                                      uint32_t *hist, int64_t nblocks)
+                                                      int64_t *hist, int64_t nblocks)
 {
     __shared__ uint32_t h[RS_RADIX];
     h[threadIdx.x] = 0;
@@ -153,12 +165,6 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const uint64_t *keys, int6
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
-}
-
-__global__ void k_u32_to_i64(const uint32_t *a, int64_t *b, int64_t n)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) b[i] = a[i];
 }
 
 template <bool HAS_VALS>
@@ -246,11 +252,10 @@ int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStrea
     if (n <= 1 || bits <= 0) return 0;
     const int64_t nblocks = (n + RS_TILE - 1) / RS_TILE;
     uint64_t *k2 = nullptr;
-    uint32_t *v2 = nullptr, *hist = nullptr;
+    uint32_t *v2 = nullptr;
     int64_t *goff = nullptr;
     int rc = tmp_alloc(&k2, n, st);
     if (!rc && vals) rc = tmp_alloc(&v2, n, st);
-    if (!rc) rc = tmp_alloc(&hist, nblocks * RS_RADIX, st);
     if (!rc) rc = tmp_alloc(&goff, nblocks * RS_RADIX, st);
     uint64_t *ka = keys, *kb = k2;
     uint32_t *va = vals, *vb = v2;
@@ -258,9 +263,7 @@ int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStrea
     for (int p = 0; p < passes && !rc; p++) {
         int shift = 8 * p;
         hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st, ka, n, shift,
-                           hist, nblocks);
-        hipLaunchKernelGGL(k_u32_to_i64, dim3(grid_for(nblocks * RS_RADIX)), dim3(256), 0, st, hist,
-                           goff, nblocks * RS_RADIX);
+                           goff, nblocks);
         if (hipGetLastError() != hipSuccess) { rc = SBA_EDEVICE; break; }
         rc = scan_exclusive_i64(goff, goff, nblocks * RS_RADIX, nullptr, st);
         if (rc) break;
@@ -283,7 +286,6 @@ int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStrea
     }
     tmp_free(k2, st);
     tmp_free(v2, st);
-    tmp_free(hist, st);
     tmp_free(goff, st);
     return rc;
 }

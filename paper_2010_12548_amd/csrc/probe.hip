@@ -15,9 +15,13 @@
 //            L2), and for mixed tiles one more load from the tile's block;
 //   hilbert  Hilbert key of the cell, then the run holding it: binary search
 //            over the run starts, or the learned index's bounded search.
+#include <algorithm>
+#include <vector>
+
 #include "sba_internal.h"
 
 #define PROBE_BLOCK 256
+#define PROBE_UNROLL 4
 #define LDS_MAX_POLYS 4096
 
 struct GridView {
@@ -191,13 +195,29 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_probe_lds(const int4 *__restric
     __syncthreads();
     const int64_t npairs = n >> 1;
     const int64_t stride = (int64_t)gridDim.x * PROBE_BLOCK;
-    for (int64_t t = (int64_t)blockIdx.x * PROBE_BLOCK + threadIdx.x; t < npairs; t += stride) {
-        int4 q = xy4[t];
-        longlong2 vv = VALS ? v2[t] : make_longlong2(0, 0);
-        uint32_t c0 = code_of<LAYOUT>(g, hv, q.x, q.y);
-        uint32_t c1 = code_of<LAYOUT>(g, hv, q.z, q.w);
-        add_lds<VALS>(c0, vv.x, A, lcnt, lsum);
-        add_lds<VALS>(c1, vv.y, A, lcnt, lsum);
+    // PROBE_UNROLL pairs per lane per trip: all stream loads are issued before
+    // the first cell lookup, so each lane keeps several 128-bit loads in flight
+    for (int64_t t0 = (int64_t)blockIdx.x * PROBE_BLOCK + threadIdx.x; t0 < npairs;
+         t0 += stride * PROBE_UNROLL) {
+        int4 q[PROBE_UNROLL];
+        longlong2 vv[PROBE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; u++) {
+            int64_t t = t0 + (int64_t)u * stride;
+            q[u] = t < npairs ? xy4[t] : make_int4(INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN);
+            vv[u] = (VALS && t < npairs) ? v2[t] : make_longlong2(0, 0);
+        }
+        uint32_t c[2 * PROBE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; u++) {
+            c[2 * u] = code_of<LAYOUT>(g, hv, q[u].x, q[u].y);
+            c[2 * u + 1] = code_of<LAYOUT>(g, hv, q[u].z, q[u].w);
+        }
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; u++) {
+            add_lds<VALS>(c[2 * u], vv[u].x, A, lcnt, lsum);
+            add_lds<VALS>(c[2 * u + 1], vv[u].y, A, lcnt, lsum);
+        }
     }
     if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
         int64_t k = n - 1;
@@ -456,4 +476,194 @@ extern "C" int sba_debug_set_blocks_per_cu(int k)
     if (k < 1 || k > 64) return SBA_EINVAL;
     g_blocks_per_cu = k;
     return 0;
+}
+
+// ---------------------------------------------------------------- batches
+//
+// Serving: many aggregation tasks (each: a point range, a handle, an optional
+// viewport, outputs) answered by one persistent launch.  The tasks' point
+// ranges are cut into items of at most BATCH_ITEM points; workgroups pull
+// items from a device counter until none is left, so uneven tasks balance
+// across the chip.  An item aggregates into LDS (when its polygon count
+// fits) and adds its non-zero bins to the task's outputs with global atomics;
+// tasks that share outputs therefore accumulate into them.
+
+#define BATCH_ITEM (1 << 18)
+
+struct TaskDev {
+    GridView g;
+    HilbView hv;
+    Agg A;
+    int32_t layout;        // 0 grid, 1 hilbert + binary, 2 hilbert + learned
+    int32_t np;
+    const int32_t *xy;
+    const int64_t *vals;
+    int32_t filt;
+    int64_t vx0, vy0, vx1, vy1;  // viewport [vx0, vx1) x [vy0, vy1)
+    unsigned long long *counts;
+    unsigned long long *sums;
+};
+
+struct ItemDev {
+    int64_t lo, hi;
+    int32_t task;
+    int32_t pad;
+};
+
+__device__ __forceinline__ bool in_view(const TaskDev &T, int32_t x, int32_t y)
+{
+    return !T.filt || (x >= T.vx0 && x < T.vx1 && y >= T.vy0 && y < T.vy1);
+}
+
+template <int LAYOUT, bool USE_LDS>
+__device__ __forceinline__ void batch_item(const TaskDev &T, int64_t lo, int64_t hi, uint32_t *lcnt,
+                                           unsigned long long *lsum)
+{
+    const bool vals = T.vals != nullptr && T.sums != nullptr;
+    auto one = [&](int32_t x, int32_t y, int64_t v) {
+        if (!in_view(T, x, y)) return;
+        uint32_t c = code_of<LAYOUT>(T.g, T.hv, x, y);
+        if (USE_LDS) {
+            if (vals) add_lds<true>(c, v, T.A, lcnt, lsum);
+            else add_lds<false>(c, 0, T.A, lcnt, lsum);
+        } else {
+            if (vals) add_global<true>(c, v, T.A, T.counts, T.sums);
+            else add_global<false>(c, 0, T.A, T.counts, T.sums);
+        }
+    };
+    // ragged ends one point at a time, the aligned middle two points per load
+    int64_t a = lo, b = hi;
+    if ((a & 1) && a < b) {
+        if (threadIdx.x == 0) one(T.xy[2 * a], T.xy[2 * a + 1], vals ? T.vals[a] : 0);
+        a++;
+    }
+    if ((b & 1) && b > a) {
+        if (threadIdx.x == 0) one(T.xy[2 * (b - 1)], T.xy[2 * (b - 1) + 1], vals ? T.vals[b - 1] : 0);
+        b--;
+    }
+    const int4 *xy4 = (const int4 *)T.xy;
+    const longlong2 *v2 = (const longlong2 *)T.vals;
+    for (int64_t t = (a >> 1) + threadIdx.x; t < (b >> 1); t += PROBE_BLOCK) {
+        int4 q = xy4[t];
+        longlong2 vv = vals ? v2[t] : make_longlong2(0, 0);
+        one(q.x, q.y, vv.x);
+        one(q.z, q.w, vv.y);
+    }
+}
+
+__global__ __launch_bounds__(PROBE_BLOCK) void k_batch(const TaskDev *__restrict__ tasks,
+                                                       const ItemDev *__restrict__ items,
+                                                       int32_t n_items, int32_t lds_np,
+                                                       int *__restrict__ next)
+{
+    extern __shared__ unsigned long long smem[];
+    unsigned long long *lsum = smem;
+    uint32_t *lcnt = (uint32_t *)(smem + lds_np);
+    __shared__ int s_item;
+    while (true) {
+        if (threadIdx.x == 0) s_item = atomicAdd(next, 1);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= n_items) break;  // every wave of the workgroup leaves here together
+        const ItemDev I = items[it];
+        const TaskDev T = tasks[I.task];
+        const int np = T.np;
+        const bool use_lds = np <= lds_np;
+        if (use_lds) {
+            for (int p = threadIdx.x; p < np; p += PROBE_BLOCK) {
+                lcnt[p] = 0;
+                lsum[p] = 0;
+            }
+            __syncthreads();
+        }
+        switch (T.layout * 2 + (use_lds ? 1 : 0)) {
+        case 0: batch_item<0, false>(T, I.lo, I.hi, lcnt, lsum); break;
+        case 1: batch_item<0, true>(T, I.lo, I.hi, lcnt, lsum); break;
+        case 2: batch_item<1, false>(T, I.lo, I.hi, lcnt, lsum); break;
+        case 3: batch_item<1, true>(T, I.lo, I.hi, lcnt, lsum); break;
+        case 4: batch_item<2, false>(T, I.lo, I.hi, lcnt, lsum); break;
+        default: batch_item<2, true>(T, I.lo, I.hi, lcnt, lsum); break;
+        }
+        if (use_lds) {
+            __syncthreads();
+            const bool vals = T.vals != nullptr && T.sums != nullptr;
+            for (int p = threadIdx.x; p < np; p += PROBE_BLOCK) {
+                uint32_t c = lcnt[p];
+                if (c) {
+                    atomicAdd(&T.counts[p], (unsigned long long)c);
+                    if (vals) atomicAdd(&T.sums[p], lsum[p]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_batch_zero(const TaskDev *__restrict__ tasks, int32_t n_tasks, int *next)
+{
+    const int t = blockIdx.x;
+    if (t == 0 && threadIdx.x == 0) *next = 0;
+    if (t >= n_tasks) return;
+    const TaskDev &T = tasks[t];
+    for (int p = threadIdx.x; p < T.np; p += blockDim.x) {
+        T.counts[p] = 0;
+        if (T.sums) T.sums[p] = 0;
+    }
+}
+
+int batch_launch(const sba_task *tasks, int32_t n_tasks, hipStream_t st)
+{
+    if (n_tasks <= 0) return 0;
+    std::vector<TaskDev> td(n_tasks);
+    std::vector<ItemDev> items;
+    int32_t lds_np = 0;
+    for (int32_t k = 0; k < n_tasks; k++) {
+        const sba_task &q = tasks[k];
+        const sba_handle *h = q.h;
+        TaskDev &T = td[k];
+        T = TaskDev{};
+        views(h, &T.g, &T.hv);
+        T.A = Agg{h->set_off, h->set_ids, (uint32_t)h->n_polys, (uint32_t)h->n_sets};
+        T.layout = h->kind == SBA_KIND_GRID ? 0 : (q.search == SBA_SEARCH_LEARNED ? 2 : 1);
+        T.np = h->n_polys;
+        T.xy = q.xy;
+        T.vals = q.values;
+        T.filt = (q.vw > 0 && q.vh > 0) ? 1 : 0;
+        T.vx0 = q.vx;
+        T.vy0 = q.vy;
+        T.vx1 = (int64_t)q.vx + q.vw;
+        T.vy1 = (int64_t)q.vy + q.vh;
+        T.counts = (unsigned long long *)q.counts;
+        T.sums = (unsigned long long *)q.sums;
+        if (T.np <= LDS_MAX_POLYS) lds_np = std::max(lds_np, T.np);
+        for (int64_t a = q.lo; a < q.hi; a += BATCH_ITEM)
+            items.push_back(ItemDev{a, std::min<int64_t>(q.hi, a + BATCH_ITEM), k, 0});
+    }
+    const int32_t n_items = (int32_t)items.size();
+    const size_t tbytes = sizeof(TaskDev) * n_tasks, ibytes = sizeof(ItemDev) * (n_items + 1);
+    char *buf = nullptr;
+    RC(tmp_alloc(&buf, (int64_t)(tbytes + ibytes + 64), st));
+    TaskDev *dtasks = (TaskDev *)buf;
+    ItemDev *ditems = (ItemDev *)(buf + tbytes);
+    int *next = (int *)(buf + tbytes + ibytes);
+    int rc = 0;
+    if (hipMemcpyAsync(dtasks, td.data(), tbytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+        (n_items && hipMemcpyAsync(ditems, items.data(), sizeof(ItemDev) * n_items,
+                                   hipMemcpyHostToDevice, st) != hipSuccess))
+        rc = SBA_EDEVICE;
+    if (!rc) {
+        hipLaunchKernelGGL(k_batch_zero, dim3((unsigned)n_tasks), dim3(256), 0, st, dtasks, n_tasks,
+                           next);
+        if (hipGetLastError() != hipSuccess) rc = SBA_EDEVICE;
+    }
+    if (!rc && n_items) {
+        int64_t nb = std::min<int64_t>(n_items, (int64_t)cu_count() * g_blocks_per_cu);
+        size_t lds = (size_t)lds_np * 12;
+        hipLaunchKernelGGL(k_batch, dim3((unsigned)nb), dim3(PROBE_BLOCK), lds, st, dtasks, ditems,
+                           n_items, lds_np, next);
+        if (hipGetLastError() != hipSuccess) rc = SBA_EDEVICE;
+    }
+    tmp_free(buf, st);
+    return rc;
 }
