@@ -36,7 +36,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="city", choices=["city", "tiny", "quadtree"])
+    ap.add_argument("--workload", default="city", choices=["city", "tiny", "quadtree", "serve"])
+    ap.add_argument("--queries", type=int, default=300, help="serve: queries per phase")
+    ap.add_argument("--serve", action="store_true",
+                    help="city: also run the viewport-query server on the resident points")
     ap.add_argument("--points", type=int, default=0, help="0 = the workload's size")
     ap.add_argument("--eps", type=int, default=0, help="0 = the workload's default")
     ap.add_argument("--layout", default="", choices=["", "grid", "hilbert"])
@@ -82,6 +85,71 @@ def probe_only(args, sba, torch, txy, tv, ro, vo, pxy, eps, layout, search, n):
     a.close()
 
 
+def serve_bench(args, torch, txy, tv, n_queries, with_big_set=True):
+    """Viewport-query serving on the resident points: capacity (closed loop),
+    then Poisson arrivals at 0.5 / 0.8 / 0.95 of it; p50 / p99 latency from
+    arrival to result on the host."""
+    import paper_2010_12548_amd.serve as serve
+    from gen import CITY_BOX, city_polygons, quadtree_polygons, seeds, viewport_queries
+    t0 = time.time()
+    sets = [city_polygons(), city_polygons(4000, (4, 40), config=5)]
+    if with_big_set:
+        sets.append(quadtree_polygons())
+    log(f"[bench] serve: polygon sets {[p.n_polys for p in sets]} in {time.time() - t0:.1f}s")
+    qs = viewport_queries(4 * n_queries, seeds(5)["queries"], n_sets=len(sets))
+    Q = [serve.Query(q["vx"], q["vy"], q["vw"], q["eps"], q["set"], q["agg"]) for q in qs]
+    S = serve.Server(txy, tv, sets, (0, 0, CITY_BOX), G=256, mem_budget=16 << 30)
+    out = {"points": int(txy.numel() // 2), "polygon_sets": [p.n_polys for p in sets],
+           "bucket_prep_ms": round(S.prep_ms, 2)}
+    try:
+        # warm-up, then capacity with everything submitted at once
+        [f.result() for f in [S.submit(q) for q in Q[:32]]]
+        phase = Q[:n_queries]
+        t1 = time.perf_counter()
+        res = [f.result() for f in [S.submit(q) for q in phase]]
+        wall = time.perf_counter() - t1
+        cap = len(phase) / wall
+        out["closed_loop"] = {"queries_per_s": cap, **serve.latency_summary(res),
+                              "mean_build_ms": float(np.mean([r.build_ms for r in res])),
+                              "mean_points": float(np.mean([r.points_scanned for r in res]))}
+        log(f"[bench] serve closed loop: {json.dumps(out['closed_loop'])}")
+        rng = np.random.default_rng(seeds(5)["queries"] + 1)
+        out["open_loop"] = []
+        for k, frac in enumerate((0.5, 0.8, 0.95)):
+            lam = frac * cap
+            qs_k = Q[n_queries * (k + 1):n_queries * (k + 2)]
+            gaps = rng.exponential(1.0 / lam, size=len(qs_k))
+            futs = []
+            t_start = time.perf_counter()
+            due = t_start
+            for q, g in zip(qs_k, gaps):
+                due += g
+                while True:
+                    now = time.perf_counter()
+                    if now >= due:
+                        break
+                    time.sleep(min(0.0005, due - now))
+                futs.append(S.submit(q))
+            res = [f.result() for f in futs]
+            wall = time.perf_counter() - t_start
+            row = {"load": frac, "arrival_rate": lam, "queries_per_s": len(res) / wall,
+                   **serve.latency_summary(res)}
+            out["open_loop"].append(row)
+            log(f"[bench] serve open loop: {json.dumps(row)}")
+        # each result identical alone and in the mix
+        probe = Q[:24]
+        mixed = [f.result() for f in [S.submit(q) for q in probe]]
+        alone = [S.submit(q).result() for q in probe]
+        same = all(np.array_equal(a.counts, m.counts) and
+                   (a.sums is None or np.array_equal(a.sums, m.sums)) for a, m in zip(alone, mixed))
+        out["alone_equals_mixed"] = bool(same)
+        out["max_batch_queries"] = max(b for b, _ in S.batches)
+        out["peak_reserved_bytes"] = S.peak_reserved
+    finally:
+        S.close()
+    return out
+
+
 def workload(args):
     from gen import city_points, city_polygons, quadtree_polygons, tiny_workload
     if args.workload == "tiny":
@@ -99,6 +167,13 @@ def workload(args):
         desc = (f"city: {n} Gaussian-mixture points (50 comps, sigma 200-3000 m) in 40x40 km at "
                 f"1 cm, lognormal(7,0.8) cents, 260 jittered Voronoi polygons, eps={eps / 100:g} m")
         return xy, vals, polys, eps, desc, "grid"
+    if args.workload == "serve":
+        n = args.points or 1_000_000_000
+        xy, vals = city_points(n, config=5)
+        desc = (f"serve: {n} resident Gaussian-mixture points, polygon sets of 260 / 4,000 / "
+                f"40,000 jittered Voronoi cells, viewport queries at zoom 10-18 with eps = one "
+                f"pixel, Poisson arrivals")
+        return xy, vals, None, 0, desc, "grid"
     n = args.points or 1_000_000_000
     polys = quadtree_polygons()
     xy, vals = city_points(n, config=3)
@@ -132,6 +207,17 @@ def main():
     log(f"[bench] workload ready in {time.time() - t0:.1f}s: {desc}")
     txy = torch.from_numpy(xy).to(dev)
     tv = torch.from_numpy(vals).to(dev)
+    if args.workload == "serve":
+        del xy, vals
+        res = serve_bench(args, torch, txy, tv, args.queries)
+        cl = res["closed_loop"]
+        p99 = max(r["p99_ms"] for r in res["open_loop"])
+        print(json.dumps({"metric": METRIC, "value": cl["queries_per_s"], "unit": "queries/s",
+                          "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
+                          "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+                          "config": {"workload": desc}, "p99_ms_worst_open_loop": p99,
+                          "serving": res}), flush=True)
+        return
     ro = torch.from_numpy(polys.ring_off).to(dev)
     vo = torch.from_numpy(polys.vert_off).to(dev)
     pxy = torch.from_numpy(polys.xy).to(dev)
@@ -237,6 +323,10 @@ def main():
             a.close()
         log(f"[bench] eps sweep: {json.dumps(sweep)}")
 
+    serving = None
+    if args.serve and args.workload == "city":
+        serving = serve_bench(args, torch, txy, tv, args.queries)
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -284,6 +374,7 @@ def main():
         "approx": {k: info[k] for k in ("s", "gw", "gh", "tile_log2", "n_tiles", "n_blocks",
                                         "n_sets", "n_segments", "n_boundary", "n_runs", "bytes")},
         "eps_sweep": sweep or None,
+        "serving": serving,
         **extra,
     }
     print(json.dumps(line), flush=True)

@@ -22,7 +22,7 @@ int sba_debug_celldiv(int64_t s, const uint32_t *n, int64_t count, uint32_t *q);
 uint64_t sba_debug_hilbert(int L, uint32_t i, uint32_t j);
 void sba_debug_hilbert_cell(int L, uint64_t d, uint32_t *i, uint32_t *j);
 
-/* Workgroups per compute unit of the streaming probes (default 4, 1..64).
+/* Workgroups per compute unit of the streaming probes (default 8, 1..64).
  * Process-wide; for launch-shape sweeps. */
 int sba_debug_set_blocks_per_cu(int k);
 

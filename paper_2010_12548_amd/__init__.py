@@ -19,7 +19,9 @@ __all__ = ["Approx", "SbaError", "lib", "library_path", "celldiv", "hilbert", "h
            "KIND_GRID", "KIND_HILBERT", "SEARCH_BINARY", "SEARCH_LEARNED"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libsba.so")
+# SBA_LIBRARY may point at another build of the same library (e.g. a variant
+# compiled with different launch parameters)
+_LIB_PATH = os.environ.get("SBA_LIBRARY") or os.path.join(_HERE, "libsba.so")
 _lib = None
 
 KIND_GRID, KIND_HILBERT = 0, 1

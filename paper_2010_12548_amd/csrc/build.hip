@@ -54,15 +54,41 @@ __global__ void k_edges(const int32_t *ring_off, int32_t n_polys, const int64_t 
     epoly[v] = p;
 }
 
-// one wavefront per polygon: coordinate bounding box, range check
+// offsets: ring_off[0] = 0 and non-decreasing; sizes[0] = n_rings (err bit 2)
+__global__ void k_check_rings(const int32_t *ring_off, int32_t n_polys, int64_t *sizes, int *err)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > n_polys) return;
+    if (p == 0 && ring_off[0] != 0) atomicOr(err, 2);
+    if (p < n_polys && ring_off[p + 1] < ring_off[p]) atomicOr(err, 2);
+    if (p == n_polys) sizes[0] = ring_off[n_polys];
+}
+
+// vert_off[0] = 0 and non-decreasing over the n_rings+1 entries; sizes[1] =
+// n_verts.  Reads nothing if the ring offsets were already refused.
+__global__ void k_check_verts(const int64_t *vert_off, int64_t *sizes, int *err)
+{
+    if (*err) return;
+    const int64_t nr = sizes[0];
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= nr;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        if (r == 0 && vert_off[0] != 0) atomicOr(err, 2);
+        if (r < nr && vert_off[r + 1] < vert_off[r]) atomicOr(err, 2);
+        if (r == nr) sizes[1] = vert_off[nr];
+    }
+}
+
+// one wavefront per polygon: coordinate bounding box, range check (err bit
+// 1), empty polygon (err bit 2); skipped when the offsets were refused
 __global__ void k_poly_bbox(const int32_t *ring_off, const int64_t *vert_off, const int32_t *xy,
                             int32_t n_polys, int4 *bbox, int *err)
 {
     int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     int lane = threadIdx.x & 63;
-    if (gw >= n_polys) return;
+    if (gw >= n_polys || (*err & 2)) return;
     int p = (int)gw;
     int64_t v0 = vert_off[ring_off[p]], v1 = vert_off[ring_off[p + 1]];
+    if (v1 == v0 && lane == 0) atomicOr(err, 2);
     int xmin = INT32_MAX, ymin = INT32_MAX, xmax = INT32_MIN, ymax = INT32_MIN;
     bool bad = false;
     for (int64_t v = v0 + lane; v < v1; v += 64) {
@@ -527,43 +553,37 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     RC(B.alloc(&err, 1));
     HIP_OK(hipMemsetAsync(err, 0, sizeof(int), st));
 
-    // offsets to the host: sizes and validation
-    std::vector<int32_t> ring_off(np + 1);
-    HIP_OK(hipMemcpyAsync(ring_off.data(), polys->ring_off, sizeof(int32_t) * (np + 1),
-                          hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
-    if (ring_off[0] != 0) return SBA_EINVAL;
-    for (int32_t p = 0; p < np; p++)
-        if (ring_off[p + 1] < ring_off[p]) return SBA_EINVAL;
-    const int32_t nr = ring_off[np];
-    std::vector<int64_t> vert_off(nr + 1);
-    HIP_OK(hipMemcpyAsync(vert_off.data(), polys->vert_off, sizeof(int64_t) * (nr + 1),
-                          hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
-    if (vert_off[0] != 0) return SBA_EINVAL;
-    for (int32_t r = 0; r < nr; r++)
-        if (vert_off[r + 1] < vert_off[r]) return SBA_EINVAL;
-    for (int32_t p = 0; p < np; p++)
-        if (vert_off[ring_off[p + 1]] == vert_off[ring_off[p]]) return SBA_EINVAL;
-    const int64_t nv = vert_off[nr];
-    if (nv > ((int64_t)1 << 31) - 1) return SBA_ELIMIT;
-    B.n_edges = nv;
-
+    // validate the offsets on the device (each stage reads only what the
+    // previous one validated) and read sizes and bounding boxes in one sync
+    int64_t *sizes = nullptr;
+    RC(B.alloc(&sizes, 2));
+    hipLaunchKernelGGL(k_check_rings, dim3(grid_for(np + 1)), dim3(256), 0, st, polys->ring_off, np,
+                       sizes, err);
+    hipLaunchKernelGGL(k_check_verts, dim3(1024), dim3(256), 0, st, polys->vert_off, sizes, err);
+    HIP_OK(hipGetLastError());
     int4 *bbox = nullptr;
     RC(B.alloc(&bbox, np));
-    RC(B.alloc(&B.edges, nv));
-    RC(B.alloc(&B.epoly, nv));
     hipLaunchKernelGGL(k_poly_bbox, dim3(grid_for((int64_t)np * 64)), dim3(256), 0, st,
                        polys->ring_off, polys->vert_off, polys->xy, np, bbox, err);
-    hipLaunchKernelGGL(k_edges, dim3(grid_for(nv)), dim3(256), 0, st, polys->ring_off, np,
-                       polys->vert_off, nr, polys->xy, nv, B.edges, B.epoly);
     HIP_OK(hipGetLastError());
     std::vector<int4> hb(np);
     int herr = 0;
+    int64_t hsz[2] = {0, 0};
     HIP_OK(hipMemcpyAsync(hb.data(), bbox, sizeof(int4) * np, hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(hsz, sizes, sizeof(hsz), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
-    if (herr) return SBA_ERANGE;
+    if (herr & 2) return SBA_EINVAL;
+    if (herr & 1) return SBA_ERANGE;
+    const int32_t nr = (int32_t)hsz[0];
+    const int64_t nv = hsz[1];
+    if (nv > ((int64_t)1 << 31) - 1) return SBA_ELIMIT;
+    B.n_edges = nv;
+    RC(B.alloc(&B.edges, nv));
+    RC(B.alloc(&B.epoly, nv));
+    hipLaunchKernelGGL(k_edges, dim3(grid_for(nv)), dim3(256), 0, st, polys->ring_off, np,
+                       polys->vert_off, nr, polys->xy, nv, B.edges, B.epoly);
+    HIP_OK(hipGetLastError());
 
     const int64_t s = h->s;
     int64_t gi0 = INT64_MAX, gj0 = INT64_MAX, gi1 = INT64_MIN, gj1 = INT64_MIN;
@@ -691,7 +711,6 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
                        (int64_t *)nullptr, cs, cm, cme, B.seg_x0, B.seg_x1, B.seg_code, multi_seg,
                        multi_mem, mem_ids, err);
     HIP_OK(hipGetLastError());
-    HIP_OK(hipStreamSynchronize(st));
     B.release(B.evkey);
     B.evkey = nullptr;
     B.release(B.evpay);
@@ -740,7 +759,6 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
         h->n_sets = nsets;
         h->n_set_ids = nids;
         h->bytes += (nsets + 1) * 8 + nids * 4;
-        HIP_OK(hipStreamSynchronize(st));
         B.release(mkey);
         B.release(mval);
         B.release(g);
@@ -786,7 +804,6 @@ int build_grid(sba_handle *h, BuildState &B, int tile_log2, hipStream_t st)
     hipLaunchKernelGGL(k_tile_fill, dim3((unsigned)nt), dim3(256), 0, st, B.seg_row_off, B.seg_x0,
                        B.seg_x1, B.seg_code, h->gw, h->gh, tl, h->tw, h->dir, mixed, h->blocks);
     HIP_OK(hipGetLastError());
-    HIP_OK(hipStreamSynchronize(st));
     return 0;
 }
 

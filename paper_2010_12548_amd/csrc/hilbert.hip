@@ -50,6 +50,21 @@ __global__ void k_bcell_keys(const uint64_t *evkey, int64_t nb, int xbits, const
     keys[c] = hilbert_index(L, i, j);
 }
 
+// cells on the border of the stored box (used when a clip window cut the
+// box through polygon interiors: a gap of the curve must not run from a cell
+// inside the box to an empty cell outside it without a key in between)
+__global__ void k_border_keys(int64_t gw, int64_t gh, int L, uint64_t *keys)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * (gw + gh)) return;
+    uint32_t i, j;
+    if (t < gw) { i = (uint32_t)t; j = 0; }
+    else if (t < 2 * gw) { i = (uint32_t)(t - gw); j = (uint32_t)(gh - 1); }
+    else if (t < 2 * gw + gh) { i = 0; j = (uint32_t)(t - 2 * gw); }
+    else { i = (uint32_t)(gw - 1); j = (uint32_t)(t - 2 * gw - gh); }
+    keys[t] = hilbert_index(L, i, j);
+}
+
 __global__ void k_flag_first(const uint64_t *keys, int64_t n, int64_t *flag)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -67,7 +82,7 @@ __global__ void k_compact_first(const uint64_t *keys, int64_t n, const int64_t *
 static int hilbert_boundary_cells(BuildState &B, sba_handle *h, hipStream_t st)
 {
     const int64_t NB = B.NB;
-    if (NB == 0) return 0;
+    if (NB == 0 && !B.window) return 0;
     int64_t *cnt = nullptr, *tot = nullptr;
     RC(B.alloc(&cnt, NB + 1));
     RC(B.alloc(&tot, 1));
@@ -75,14 +90,20 @@ static int hilbert_boundary_cells(BuildState &B, sba_handle *h, hipStream_t st)
                        cnt);
     HIP_OK(hipGetLastError());
     RC(scan_exclusive_i64(cnt, cnt, NB, tot, st));
-    int64_t nc = 0;
-    HIP_OK(hipMemcpyAsync(&nc, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    int64_t ncb = 0;
+    HIP_OK(hipMemcpyAsync(&ncb, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
+    const int64_t nborder = B.window ? 2 * (h->gw + h->gh) : 0;
+    const int64_t nc = ncb + nborder;
     if (nc == 0) return 0;
     uint64_t *keys = nullptr;
     RC(B.alloc(&keys, nc));
-    hipLaunchKernelGGL(k_bcell_keys, dim3(grid_for(nc)), dim3(256), 0, st, B.evkey, NB, B.xbits,
-                       cnt, nc, h->level, keys);
+    if (ncb)
+        hipLaunchKernelGGL(k_bcell_keys, dim3(grid_for(ncb)), dim3(256), 0, st, B.evkey, NB, B.xbits,
+                           cnt, ncb, h->level, keys);
+    if (nborder)
+        hipLaunchKernelGGL(k_border_keys, dim3(grid_for(nborder)), dim3(256), 0, st, h->gw, h->gh,
+                           h->level, keys + ncb);
     HIP_OK(hipGetLastError());
     B.release(cnt);
     RC(radix_sort_u64(keys, nullptr, nc, 2 * h->level, st));

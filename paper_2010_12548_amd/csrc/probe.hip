@@ -49,6 +49,7 @@ struct HilbView {
     float a;               // learned root
     uint32_t nl;
     const int4 *leaves;
+    int64_t win;           // learned: search window 2*max_err+3 (uniform), clamped to n
 };
 
 __device__ __forceinline__ uint32_t grid_code(const GridView &g, int32_t x, int32_t y)
@@ -112,6 +113,177 @@ __device__ __forceinline__ uint32_t hilbert_code(const HilbView &v, int32_t x, i
         q = pred_search<uint64_t>(v.k64, 0, v.n, key);
     }
     return v.code[q];
+}
+
+
+// ---------------------------------------------------------------- batched lookups
+//
+// NP points at a time with no data-dependent branch around a load: all NP
+// directory loads are issued together, then all NP block loads (a point in
+// a uniform tile re-reads the first block word, a cache hit), so one
+// iteration pays two memory latencies instead of 2*NP.
+
+template <int NP>
+__device__ __forceinline__ void grid_codes(const GridView &g, const int32_t *xs, const int32_t *ys,
+                                           uint32_t *c)
+{
+    if (g.extx == 0) {  // empty handle (a clip window that holds no cell)
+#pragma unroll
+        for (int k = 0; k < NP; k++) c[k] = 0;
+        return;
+    }
+    const uint32_t m = (1u << g.tl) - 1u;
+    uint32_t ti[NP], lo[NP];
+    bool ok[NP];
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        int64_t dx = (int64_t)xs[k] - g.ox, dy = (int64_t)ys[k] - g.oy;
+        ok[k] = (uint64_t)dx < g.extx && (uint64_t)dy < g.exty;
+        uint32_t i = divmagic(ok[k] ? (uint32_t)dx : 0u, g.mag, g.shift);
+        uint32_t j = divmagic(ok[k] ? (uint32_t)dy : 0u, g.mag, g.shift);
+        ti[k] = (j >> g.tl) * g.tw + (i >> g.tl);
+        lo[k] = ((j & m) << g.tl) | (i & m);
+    }
+    uint32_t e[NP];
+#pragma unroll
+    for (int k = 0; k < NP; k++) e[k] = g.dir[ti[k]];
+    uint32_t f[NP];
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        uint32_t b = e[k] & ~TILE_MIXED;
+        bool fine = (e[k] & TILE_MIXED) && b < g.nblocks;
+        f[k] = g.blocks[fine ? ((uint64_t)b << (2 * g.tl)) + lo[k] : 0];
+    }
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        uint32_t b = e[k] & ~TILE_MIXED;
+        uint32_t v = (e[k] & TILE_MIXED) ? (b < g.nblocks ? f[k] : 0u) : e[k];
+        c[k] = ok[k] ? v : 0u;
+    }
+}
+
+// NP predecessor searches in lockstep over keys[lo[k] .. lo[k]+len): the
+// step count depends only on len, so every step issues NP loads at once.
+template <typename K, int NP>
+__device__ __forceinline__ void pred_search_n(const K *keys, int64_t *lo, int64_t len, const K *key)
+{
+    while (len > 1) {
+        const int64_t half = len >> 1;
+        K v[NP];
+#pragma unroll
+        for (int k = 0; k < NP; k++) v[k] = keys[lo[k] + half];
+#pragma unroll
+        for (int k = 0; k < NP; k++) lo[k] = (v[k] <= key[k]) ? lo[k] + half : lo[k];
+        len -= half;
+    }
+}
+
+// As pred_search_n with a window length per point: the wave steps while any
+// of its lanes still has a window longer than one (lanes that are done
+// re-read their current key, which changes nothing).
+template <typename K, int NP>
+__device__ __forceinline__ void pred_search_var(const K *keys, int64_t *lo, int64_t *len,
+                                                const K *key)
+{
+    while (true) {
+        bool more = false;
+#pragma unroll
+        for (int k = 0; k < NP; k++) more |= len[k] > 1;
+        if (!__any(more)) break;
+        K v[NP];
+        int64_t half[NP];
+#pragma unroll
+        for (int k = 0; k < NP; k++) {
+            half[k] = len[k] >> 1;
+            v[k] = keys[lo[k] + half[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < NP; k++) {
+            lo[k] = (v[k] <= key[k]) ? lo[k] + half[k] : lo[k];
+            len[k] -= half[k];
+        }
+    }
+}
+
+template <int SEARCH, int NP>
+__device__ __forceinline__ void hilbert_codes(const HilbView &v, const int32_t *xs, const int32_t *ys,
+                                              uint32_t *c)
+{
+    if (v.extx == 0) {
+#pragma unroll
+        for (int k = 0; k < NP; k++) c[k] = 0;
+        return;
+    }
+    bool ok[NP];
+    uint64_t key[NP];
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        int64_t dx = (int64_t)xs[k] - v.ox, dy = (int64_t)ys[k] - v.oy;
+        ok[k] = (uint64_t)dx < v.extx && (uint64_t)dy < v.exty;
+        uint32_t i = divmagic(ok[k] ? (uint32_t)dx : 0u, v.mag, v.shift);
+        uint32_t j = divmagic(ok[k] ? (uint32_t)dy : 0u, v.mag, v.shift);
+        key[k] = hilbert_index(v.L, i, j);
+    }
+    int64_t q[NP];
+    if (v.k32) {
+        uint32_t k32[NP];
+#pragma unroll
+        for (int k = 0; k < NP; k++) k32[k] = (uint32_t)key[k];
+        if (SEARCH) {
+            int4 lf[NP];
+#pragma unroll
+            for (int k = 0; k < NP; k++) lf[k] = v.leaves[root_leaf(key[k], v.a, v.nl)];
+            int64_t len[NP];
+#pragma unroll
+            for (int k = 0; k < NP; k++) {
+                int64_t p = predict((uint64_t)(uint32_t)lf[k].x, __int_as_float(lf[k].y),
+                                    __int_as_float(lf[k].z), key[k]);
+                int64_t a = p - lf[k].w, e = p + lf[k].w;
+                a = a < 0 ? 0 : (a > v.n - 1 ? v.n - 1 : a);
+                e = e < a ? a : (e > v.n - 1 ? v.n - 1 : e);
+                q[k] = a;
+                len[k] = e - a + 1;
+            }
+            uint32_t first[NP];
+#pragma unroll
+            for (int k = 0; k < NP; k++) first[k] = v.k32[q[k]];
+            pred_search_var<uint32_t, NP>(v.k32, q, len, k32);
+            uint32_t nxt[NP];
+#pragma unroll
+            for (int k = 0; k < NP; k++) nxt[k] = q[k] + 1 < v.n ? v.k32[q[k] + 1] : 0xffffffffu;
+#pragma unroll
+            for (int k = 0; k < NP; k++) {
+                bool good = first[k] <= k32[k] && (q[k] + 1 == v.n || nxt[k] > k32[k]);
+                if (!good) {  // bracket missed (never for an exact error bound): full search
+                    int64_t lo1[1] = {0};
+                    uint32_t kk[1] = {k32[k]};
+                    pred_search_n<uint32_t, 1>(v.k32, lo1, v.n, kk);
+                    q[k] = lo1[0];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NP; k++) q[k] = 0;
+            pred_search_n<uint32_t, NP>(v.k32, q, v.n, k32);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NP; k++) q[k] = 0;
+        pred_search_n<uint64_t, NP>(v.k64, q, v.n, key);
+    }
+    uint32_t r[NP];
+#pragma unroll
+    for (int k = 0; k < NP; k++) r[k] = v.code[q[k]];
+#pragma unroll
+    for (int k = 0; k < NP; k++) c[k] = ok[k] ? r[k] : 0u;
+}
+
+template <int LAYOUT, int NP>
+__device__ __forceinline__ void codes_of(const GridView &g, const HilbView &hv, const int32_t *xs,
+                                         const int32_t *ys, uint32_t *c)
+{
+    if (LAYOUT == 0) grid_codes<NP>(g, xs, ys, c);
+    else hilbert_codes<LAYOUT == 2 ? 1 : 0, NP>(hv, xs, ys, c);
 }
 
 struct Agg {
@@ -195,8 +367,9 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_probe_lds(const int4 *__restric
     __syncthreads();
     const int64_t npairs = n >> 1;
     const int64_t stride = (int64_t)gridDim.x * PROBE_BLOCK;
-    // PROBE_UNROLL pairs per lane per trip: all stream loads are issued before
-    // the first cell lookup, so each lane keeps several 128-bit loads in flight
+    // PROBE_UNROLL pairs per lane per trip: the stream loads of the trip are
+    // issued together, then the cell lookups of all 2*PROBE_UNROLL points
+    // (batched, see grid_codes); latency is hidden by the other waves
     for (int64_t t0 = (int64_t)blockIdx.x * PROBE_BLOCK + threadIdx.x; t0 < npairs;
          t0 += stride * PROBE_UNROLL) {
         int4 q[PROBE_UNROLL];
@@ -207,12 +380,16 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_probe_lds(const int4 *__restric
             q[u] = t < npairs ? xy4[t] : make_int4(INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN);
             vv[u] = (VALS && t < npairs) ? v2[t] : make_longlong2(0, 0);
         }
-        uint32_t c[2 * PROBE_UNROLL];
+        int32_t xs[2 * PROBE_UNROLL], ys[2 * PROBE_UNROLL];
 #pragma unroll
         for (int u = 0; u < PROBE_UNROLL; u++) {
-            c[2 * u] = code_of<LAYOUT>(g, hv, q[u].x, q[u].y);
-            c[2 * u + 1] = code_of<LAYOUT>(g, hv, q[u].z, q[u].w);
+            xs[2 * u] = q[u].x;
+            ys[2 * u] = q[u].y;
+            xs[2 * u + 1] = q[u].z;
+            ys[2 * u + 1] = q[u].w;
         }
+        uint32_t c[2 * PROBE_UNROLL];
+        codes_of<LAYOUT, 2 * PROBE_UNROLL>(g, hv, xs, ys, c);
 #pragma unroll
         for (int u = 0; u < PROBE_UNROLL; u++) {
             add_lds<VALS>(c[2 * u], vv[u].x, A, lcnt, lsum);
@@ -281,11 +458,31 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_probe_global(const int4 *__rest
     unsigned long long *sum = (unsigned long long *)sums;
     const int64_t npairs = n >> 1;
     const int64_t stride = (int64_t)gridDim.x * PROBE_BLOCK;
-    for (int64_t t = (int64_t)blockIdx.x * PROBE_BLOCK + threadIdx.x; t < npairs; t += stride) {
-        int4 q = xy4[t];
-        longlong2 vv = VALS ? v2[t] : make_longlong2(0, 0);
-        add_global<VALS>(code_of<LAYOUT>(g, hv, q.x, q.y), vv.x, A, cnt, sum);
-        add_global<VALS>(code_of<LAYOUT>(g, hv, q.z, q.w), vv.y, A, cnt, sum);
+    for (int64_t t0 = (int64_t)blockIdx.x * PROBE_BLOCK + threadIdx.x; t0 < npairs;
+         t0 += stride * PROBE_UNROLL) {
+        int4 q[PROBE_UNROLL];
+        longlong2 vv[PROBE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; u++) {
+            int64_t t = t0 + (int64_t)u * stride;
+            q[u] = t < npairs ? xy4[t] : make_int4(INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN);
+            vv[u] = (VALS && t < npairs) ? v2[t] : make_longlong2(0, 0);
+        }
+        int32_t xs[2 * PROBE_UNROLL], ys[2 * PROBE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; u++) {
+            xs[2 * u] = q[u].x;
+            ys[2 * u] = q[u].y;
+            xs[2 * u + 1] = q[u].z;
+            ys[2 * u + 1] = q[u].w;
+        }
+        uint32_t c[2 * PROBE_UNROLL];
+        codes_of<LAYOUT, 2 * PROBE_UNROLL>(g, hv, xs, ys, c);
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; u++) {
+            add_global<VALS>(c[2 * u], vv[u].x, A, cnt, sum);
+            add_global<VALS>(c[2 * u + 1], vv[u].y, A, cnt, sum);
+        }
     }
     if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
         int64_t k = n - 1;
@@ -371,11 +568,12 @@ static void views(const sba_handle *h, GridView *g, HilbView *hv)
         hv->a = h->root_a;
         hv->nl = 1u << h->log2_leaves;
         hv->leaves = h->leaves;
+        hv->win = std::min<int64_t>(2 * h->max_leaf_err + 3, std::max<int64_t>(h->n_runs, 1));
     }
 }
 
 // blocks per CU for the streaming probe
-static int g_blocks_per_cu = 4;
+static int g_blocks_per_cu = 8;
 
 template <int LAYOUT>
 static int launch_layout(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
@@ -543,11 +741,48 @@ __device__ __forceinline__ void batch_item(const TaskDev &T, int64_t lo, int64_t
     }
     const int4 *xy4 = (const int4 *)T.xy;
     const longlong2 *v2 = (const longlong2 *)T.vals;
-    for (int64_t t = (a >> 1) + threadIdx.x; t < (b >> 1); t += PROBE_BLOCK) {
-        int4 q = xy4[t];
-        longlong2 vv = vals ? v2[t] : make_longlong2(0, 0);
-        one(q.x, q.y, vv.x);
-        one(q.z, q.w, vv.y);
+    const int64_t pb = b >> 1;
+    for (int64_t t0 = (a >> 1) + threadIdx.x; t0 < pb; t0 += (int64_t)PROBE_BLOCK * PROBE_UNROLL) {
+        int4 q[PROBE_UNROLL];
+        longlong2 vv[PROBE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; u++) {
+            int64_t t = t0 + (int64_t)u * PROBE_BLOCK;
+            q[u] = t < pb ? xy4[t] : make_int4(INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN);
+            vv[u] = (vals && t < pb) ? v2[t] : make_longlong2(0, 0);
+        }
+        // points outside the viewport become a coordinate no cell holds
+        int32_t xs[2 * PROBE_UNROLL], ys[2 * PROBE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; u++) {
+            bool k0 = in_view(T, q[u].x, q[u].y), k1 = in_view(T, q[u].z, q[u].w);
+            xs[2 * u] = k0 ? q[u].x : INT32_MIN;
+            ys[2 * u] = k0 ? q[u].y : INT32_MIN;
+            xs[2 * u + 1] = k1 ? q[u].z : INT32_MIN;
+            ys[2 * u + 1] = k1 ? q[u].w : INT32_MIN;
+        }
+        uint32_t c[2 * PROBE_UNROLL];
+        codes_of<LAYOUT, 2 * PROBE_UNROLL>(T.g, T.hv, xs, ys, c);
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; u++) {
+            if (USE_LDS) {
+                if (vals) {
+                    add_lds<true>(c[2 * u], vv[u].x, T.A, lcnt, lsum);
+                    add_lds<true>(c[2 * u + 1], vv[u].y, T.A, lcnt, lsum);
+                } else {
+                    add_lds<false>(c[2 * u], 0, T.A, lcnt, lsum);
+                    add_lds<false>(c[2 * u + 1], 0, T.A, lcnt, lsum);
+                }
+            } else {
+                if (vals) {
+                    add_global<true>(c[2 * u], vv[u].x, T.A, T.counts, T.sums);
+                    add_global<true>(c[2 * u + 1], vv[u].y, T.A, T.counts, T.sums);
+                } else {
+                    add_global<false>(c[2 * u], 0, T.A, T.counts, T.sums);
+                    add_global<false>(c[2 * u + 1], 0, T.A, T.counts, T.sums);
+                }
+            }
+        }
     }
 }
 

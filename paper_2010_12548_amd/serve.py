@@ -113,6 +113,7 @@ class Server:
         self._ready = collections.deque()
         self._stop = False
         self.batches = []             # (n_queries, n_tasks) per launch
+        self._inflight_jobs = []
         self._builder = threading.Thread(target=self._build_loop, daemon=True)
         self._batcher = threading.Thread(target=self._batch_loop, daemon=True)
         self._builder.start()
@@ -212,9 +213,32 @@ class Server:
             self.reserved -= job.est
             self._lock.notify_all()
 
+    def _ready_nonempty(self):
+        with self._lock:
+            return bool(self._ready)
+
     def _batch_loop(self):
+        try:
+            self._batch_loop_body()
+        except BaseException as e:  # noqa: BLE001 - fail every waiting query, never hang
+            self._fail_all(e)
+            raise
+
+    def _fail_all(self, exc):
+        with self._lock:
+            self._stop = True
+            jobs = list(self._pending) + list(self._ready)
+            self._pending.clear()
+            self._ready.clear()
+            self._lock.notify_all()
+        for job in jobs + list(self._inflight_jobs):
+            if not job.fut.done():
+                job.fut.set_exception(RuntimeError(f"server failed: {exc!r}"))
+
+    def _batch_loop_body(self):
         torch = self.torch
         inflight = collections.deque()   # (event, jobs), in launch order
+        self._inflight_jobs = []
         while True:
             with self._lock:
                 if not self._ready and not inflight:
@@ -242,6 +266,7 @@ class Server:
                     ev.record(self.probe_stream)
                 self.batches.append((len(batch), len(tasks)))
                 inflight.append((ev, batch))
+                self._inflight_jobs = [j for _, b in inflight for j in b]
             # complete finished launches in order; block only when idle otherwise
             while inflight and (inflight[0][0].query() or not self._ready_nonempty()):
                 self._finish(*inflight.popleft())
