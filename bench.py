@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-sweep", action="store_true", help="skip the eps sweep")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--force-wide", action="store_true",
+                    help="grid probe: 32-bit directory in global memory instead of the LDS copy")
     ap.add_argument("--probe-only", action="store_true",
                     help="build once, then run only --steps aggregate calls (for counter runs)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
@@ -198,6 +200,8 @@ def main():
         sys.exit(1)
     if args.blocks_per_cu:
         sba.lib().sba_debug_set_blocks_per_cu(args.blocks_per_cu)
+    if args.force_wide:
+        sba.lib().sba_debug_force_wide_grid(1)
     dev = torch.device("cuda:0")
     t0 = time.time()
     xy, vals, polys, eps, desc, layout = workload(args)
@@ -296,6 +300,7 @@ def main():
         extra["learned_vs_binary"] = {**out, "identical": bool(same),
                                       "speedup": out["binary"]["probe_ms"] / out["learned"]["probe_ms"],
                                       "n_runs": ai["n_runs"], "max_leaf_err": ai["max_leaf_err"],
+                                      "mean_leaf_err": ai["mean_leaf_err"],
                                       "leaves": 1 << ai["log2_leaves"]}
         a.close()
 

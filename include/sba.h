@@ -97,6 +97,7 @@ typedef struct {
     int64_t n_boundary;     /* (edge, row strip) boundary intervals */
     int64_t n_runs;         /* Hilbert runs */
     int64_t max_leaf_err;   /* learned index: largest stored error */
+    double  mean_leaf_err;  /* learned index: mean stored error over the leaves */
     int64_t bytes;          /* device bytes held by the handle */
     double  build_ms;       /* wall time of the build, host clock (includes its syncs) */
 } sba_info_t;

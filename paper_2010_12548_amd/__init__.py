@@ -60,7 +60,8 @@ class _Info(C.Structure):
                 ("gw", C.c_int64), ("gh", C.c_int64), ("n_tiles", C.c_int64),
                 ("n_blocks", C.c_int64), ("n_sets", C.c_int64), ("n_set_ids", C.c_int64),
                 ("n_segments", C.c_int64), ("n_boundary", C.c_int64), ("n_runs", C.c_int64),
-                ("max_leaf_err", C.c_int64), ("bytes", C.c_int64), ("build_ms", C.c_double)]
+                ("max_leaf_err", C.c_int64), ("mean_leaf_err", C.c_double), ("bytes", C.c_int64),
+                ("build_ms", C.c_double)]
 
 
 def library_path() -> str:
@@ -107,6 +108,8 @@ def lib():
     L.sba_debug_hilbert_cell.restype = None
     L.sba_debug_hilbert_cell.argtypes = [C.c_int, C.c_uint64, C.POINTER(C.c_uint32),
                                          C.POINTER(C.c_uint32)]
+    L.sba_debug_force_wide_grid.restype = C.c_int
+    L.sba_debug_force_wide_grid.argtypes = [C.c_int]
     L.sba_debug_set_blocks_per_cu.restype = C.c_int
     L.sba_debug_set_blocks_per_cu.argtypes = [C.c_int]
     _lib = L

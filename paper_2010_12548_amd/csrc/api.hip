@@ -9,8 +9,8 @@
 // work still reads the handle).
 static void handle_release(sba_handle *h)
 {
-    void *arrs[] = {h->dir, h->blocks, h->set_off, h->set_ids, h->starts, h->starts32,
-                    h->run_code, h->leaves};
+    void *arrs[] = {h->dir, h->blocks, h->dir16, h->blocks16, h->set_off, h->set_ids, h->starts,
+                    h->starts32, h->run_code, h->leaves, h->leaf_lo};
     for (void *p : arrs) tmp_free(p, nullptr);
 }
 
@@ -157,6 +157,7 @@ extern "C" int sba_info(const sba_handle *h, sba_info_t *info)
     o.n_boundary = h->n_boundary;
     o.n_runs = h->n_runs;
     o.max_leaf_err = h->max_leaf_err;
+    o.mean_leaf_err = h->mean_leaf_err;
     o.bytes = h->bytes;
     o.build_ms = h->build_ms;
     *info = o;

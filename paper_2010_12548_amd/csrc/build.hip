@@ -479,8 +479,9 @@ __global__ void k_tile_classify(const int64_t *seg_row_off, const int32_t *seg_x
     }
 }
 
-// one block per tile; mixed tiles write their fine block, all tiles their
-// final directory entry
+// one block per tile; mixed tiles write their fine block (one wavefront per
+// row: one binary search for the first cell, then a walk along the row's
+// segments), all tiles their final directory entry
 __global__ __launch_bounds__(256) void k_tile_fill(const int64_t *seg_row_off, const int32_t *seg_x0,
                                                    const int32_t *seg_x1, const uint32_t *seg_code,
                                                    int64_t gw, int64_t gh, int tl, int64_t tw,
@@ -492,17 +493,54 @@ __global__ __launch_bounds__(256) void k_tile_fill(const int64_t *seg_row_off, c
     if (d != 0xffffffffu) return;
     int64_t b = blk[tile];
     int64_t ti = tile % tw, tj = tile / tw;
-    int T = 1 << tl;
+    const int T = 1 << tl;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t *out = blocks + (b << (2 * tl));
-    for (int c = threadIdx.x; c < T * T; c += blockDim.x) {
-        int64_t r = (tj << tl) + (c >> tl);
-        int64_t x = (ti << tl) + (c & (T - 1));
-        out[c] = (r < gh && x < gw)
-                     ? seg_code_at(seg_row_off, seg_x0, seg_x1, seg_code, r, (int32_t)x)
-                     : 0u;
+    const int32_t x0 = (int32_t)(ti << tl);
+    for (int row = w; row < T; row += 4) {
+        int64_t r = (tj << tl) + row;
+        uint32_t *orow = out + ((int64_t)row << tl);
+        if (r >= gh) {
+            for (int cx = lane; cx < T; cx += 64) orow[cx] = 0;
+            continue;
+        }
+        const int64_t lo = seg_row_off[r], hi = seg_row_off[r + 1];
+        int64_t k;
+        {
+            int32_t x = x0 + lane;
+            int64_t a = lo, e = hi;
+            while (a < e) {
+                int64_t mid = (a + e) >> 1;
+                if (seg_x0[mid] <= x) a = mid + 1; else e = mid;
+            }
+            k = a - 1;  // last segment starting at or before x (lo-1 if none)
+        }
+        for (int cx = lane; cx < T; cx += 64) {
+            int32_t x = x0 + cx;
+            while (k + 1 < hi && seg_x0[k + 1] <= x) k++;
+            uint32_t c = 0;
+            if (x < gw && k >= lo && x < seg_x1[k]) c = seg_code[k];
+            orow[cx] = c;
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) dir[tile] = TILE_MIXED | (uint32_t)b;
+}
+
+// 32-bit codes / directory entries -> 16-bit ones (see build_grid)
+__global__ void k_compact16(const uint32_t *in, int64_t n, int64_t n_pad, uint32_t np, bool is_dir,
+                            uint16_t *out)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_pad) return;
+    if (t >= n) { out[t] = 0; return; }
+    uint32_t c = in[t];
+    uint32_t v;
+    if (is_dir && (c & TILE_MIXED)) v = 0x8000u | (c & ~TILE_MIXED);
+    else if (c == 0) v = 0;
+    else if (c < CODE_SET_BASE) v = c;                       // polygon c-1 -> c
+    else v = np + 1 + (c - CODE_SET_BASE);                   // set k -> np+1+k
+    out[t] = (uint16_t)v;
 }
 
 // ---------------------------------------------------------------- host side
@@ -773,13 +811,14 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
 
 int build_grid(sba_handle *h, BuildState &B, int tile_log2, hipStream_t st)
 {
-    int64_t side = std::max(h->gw, h->gh);
     int tl = tile_log2;
-    if (tl == 0) {
+    if (tl == 0) {  // smallest tile whose 16-bit directory fits 64 KB of LDS
         tl = 3;
-        while (tl < 7 && (side >> tl) > 512) tl++;
+        while (tl < 10 && ((h->gw + (1 << tl) - 1) >> tl) * ((h->gh + (1 << tl) - 1) >> tl) >
+                              COMPACT_DIR_TILES)
+            tl++;
     }
-    if (tl < 3 || tl > 8) return SBA_EINVAL;
+    if (tl < 3 || tl > 10) return SBA_EINVAL;
     h->tile_log2 = tl;
     h->tw = (h->gw + (1 << tl) - 1) >> tl;
     h->th = (h->gh + (1 << tl) - 1) >> tl;
@@ -804,6 +843,22 @@ int build_grid(sba_handle *h, BuildState &B, int tile_log2, hipStream_t st)
     hipLaunchKernelGGL(k_tile_fill, dim3((unsigned)nt), dim3(256), 0, st, B.seg_row_off, B.seg_x0,
                        B.seg_x1, B.seg_code, h->gw, h->gh, tl, h->tw, h->dir, mixed, h->blocks);
     HIP_OK(hipGetLastError());
+    // 16-bit copy for the streaming probe, whose workgroups keep the whole
+    // directory in LDS: entries < 0x8000 are short codes (0 none, p+1 polygon
+    // p, n_polys+1+k set k), 0x8000|b is fine block b
+    if ((int64_t)h->n_polys + h->n_sets < 0x8000 && nblk < 0x8000 && nt <= COMPACT_DIR_TILES_MAX) {
+        const int64_t nt16 = (nt + 7) & ~(int64_t)7;  // LDS copies move 16 bytes at a time
+        RC(tmp_alloc(&h->dir16, nt16, st));
+        RC(tmp_alloc(&h->blocks16, std::max<int64_t>(nblk << (2 * tl), 1), st));
+        h->bytes += nt16 * 2 + (nblk << (2 * tl)) * 2;
+        hipLaunchKernelGGL(k_compact16, dim3(grid_for(nt16)), dim3(256), 0, st, h->dir, nt, nt16,
+                           (uint32_t)h->n_polys, true, h->dir16);
+        if (nblk)
+            hipLaunchKernelGGL(k_compact16, dim3(grid_for(nblk << (2 * tl))), dim3(256), 0, st,
+                               h->blocks, nblk << (2 * tl), nblk << (2 * tl), (uint32_t)h->n_polys,
+                               false, h->blocks16);
+        HIP_OK(hipGetLastError());
+    }
     return 0;
 }
 

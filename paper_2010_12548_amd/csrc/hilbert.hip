@@ -262,7 +262,7 @@ __device__ __forceinline__ int64_t lower_bound_u64(const uint64_t *a, int64_t n,
 
 // one wavefront per leaf: key range, least-squares fit, exact error bound
 __global__ void k_leaf_fit(const uint64_t *starts, int64_t n, float a, uint32_t nl, uint64_t total,
-                           uint64_t *kfirst, int4 *leaves, int64_t *max_err)
+                           int4 *leaves, int32_t *leaf_lo, unsigned long long *err_stats)
 {
     int64_t l = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     int lane = threadIdx.x & 63;
@@ -296,8 +296,10 @@ __global__ void k_leaf_fit(const uint64_t *starts, int64_t n, float a, uint32_t 
     } else {
         icpt = (float)(lo - 1);
     }
+    const int4 lf = make_int4((int)(uint32_t)K0, __float_as_int(slope), __float_as_int(icpt), 0);
     // error over every key of [K0, K1): the answer is q on [max(starts[q],K0),
-    // min(starts[q+1],K1) - 1] for q in [lo-1, hi-1]; check both ends of each step
+    // min(starts[q+1],K1) - 1] for q in [lo-1, hi-1]; the clamped prediction is
+    // monotone, so both ends of each step bound it
     int64_t err = 0;
     if (K1 > K0) {
         for (int64_t q = lo - 1 + lane; q <= hi - 1; q += 64) {
@@ -305,7 +307,7 @@ __global__ void k_leaf_fit(const uint64_t *starts, int64_t n, float a, uint32_t 
             uint64_t ka = starts[q] > K0 ? starts[q] : K0;
             uint64_t kb = (q + 1 < n && starts[q + 1] < K1) ? starts[q + 1] - 1 : K1 - 1;
             if (ka > kb) continue;
-            int64_t pa = predict(K0, slope, icpt, ka), pb = predict(K0, slope, icpt, kb);
+            int64_t pa = predict_in_leaf(lf, lo, hi, ka), pb = predict_in_leaf(lf, lo, hi, kb);
             int64_t e1 = pa > q ? pa - q : q - pa, e2 = pb > q ? pb - q : q - pb;
             err = max(err, max(e1, e2));
         }
@@ -315,10 +317,11 @@ __global__ void k_leaf_fit(const uint64_t *starts, int64_t n, float a, uint32_t 
         err = max(err, v);
     }
     if (lane == 0) {
-        kfirst[l] = K0;
-        leaves[l] = make_int4((int)(uint32_t)K0, __float_as_int(slope), __float_as_int(icpt),
-                              (int)err);
-        atomicMax((unsigned long long *)max_err, (unsigned long long)err);
+        leaves[l] = make_int4(lf.x, lf.y, lf.z, (int)err);
+        leaf_lo[l] = (int32_t)lo;
+        if (l == nl - 1) leaf_lo[nl] = (int32_t)n;
+        atomicMax(&err_stats[0], (unsigned long long)err);
+        atomicAdd(&err_stats[1], (unsigned long long)err);
     }
 }
 
@@ -381,18 +384,20 @@ int hilbert_finish(BuildState &B, sba_handle *h, const sba_build_opts &o, hipStr
         HIP_OK(hipMemcpy(&last, h->starts + (nr - 1), sizeof(uint64_t), hipMemcpyDeviceToHost));
         h->root_k0 = 0;
         h->root_a = (float)nl / (float)(last + 1);
-        uint64_t *kfirst = nullptr;
-        int64_t *merr = nullptr;
-        RC(B.alloc(&kfirst, nl));
-        RC(B.alloc(&merr, 1));
-        HIP_OK(hipMemsetAsync(merr, 0, sizeof(int64_t), st));
+        unsigned long long *stats = nullptr;
+        RC(B.alloc(&stats, 2));
+        HIP_OK(hipMemsetAsync(stats, 0, 2 * sizeof(unsigned long long), st));
         RC(tmp_alloc(&h->leaves, nl, st));
-        h->bytes += (int64_t)nl * 16;
+        RC(tmp_alloc(&h->leaf_lo, (int64_t)nl + 1, st));
+        h->bytes += (int64_t)nl * 16 + ((int64_t)nl + 1) * 4;
         hipLaunchKernelGGL(k_leaf_fit, dim3(grid_for((int64_t)nl * 64)), dim3(256), 0, st, h->starts,
-                           nr, h->root_a, nl, total, kfirst, h->leaves, merr);
+                           nr, h->root_a, nl, total, h->leaves, h->leaf_lo, stats);
         HIP_OK(hipGetLastError());
-        HIP_OK(hipMemcpyAsync(&h->max_leaf_err, merr, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        unsigned long long hs[2];
+        HIP_OK(hipMemcpyAsync(hs, stats, sizeof(hs), hipMemcpyDeviceToHost, st));
         HIP_OK(hipStreamSynchronize(st));
+        h->max_leaf_err = (int64_t)hs[0];
+        h->mean_leaf_err = (double)hs[1] / (double)nl;
     }
     return 0;
 }

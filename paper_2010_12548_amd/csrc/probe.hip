@@ -49,7 +49,7 @@ struct HilbView {
     float a;               // learned root
     uint32_t nl;
     const int4 *leaves;
-    int64_t win;           // learned: search window 2*max_err+3 (uniform), clamped to n
+    const int32_t *leaf_lo;
 };
 
 __device__ __forceinline__ uint32_t grid_code(const GridView &g, int32_t x, int32_t y)
@@ -85,11 +85,13 @@ __device__ __forceinline__ int64_t learned_search(const HilbView &v, const K *ke
 {
     uint32_t l = root_leaf((uint64_t)key, v.a, v.nl);
     int4 lf = v.leaves[l];
-    int64_t p = predict((uint64_t)(uint32_t)lf.x, __int_as_float(lf.y), __int_as_float(lf.z),
-                        (uint64_t)key);
+    int64_t llo = v.leaf_lo[l], lhi = v.leaf_lo[l + 1];
+    int64_t p = predict_in_leaf(lf, llo, lhi, (uint64_t)key);
+    int64_t ra, rb;
+    leaf_range(llo, lhi, &ra, &rb);
     int64_t lo = p - lf.w, hi = p + lf.w;
-    lo = lo < 0 ? 0 : lo;
-    hi = hi > v.n - 1 ? v.n - 1 : hi;
+    lo = lo < ra ? ra : lo;
+    hi = hi > rb ? rb : hi;
     if (lo <= hi && keys[lo] <= key) {
         int64_t q = pred_search<K>(keys, lo, hi - lo + 1, key);
         if (q == v.n - 1 || keys[q + 1] > key) return q;
@@ -231,16 +233,23 @@ __device__ __forceinline__ void hilbert_codes(const HilbView &v, const int32_t *
         for (int k = 0; k < NP; k++) k32[k] = (uint32_t)key[k];
         if (SEARCH) {
             int4 lf[NP];
+            int64_t llo[NP], lhi[NP];
 #pragma unroll
-            for (int k = 0; k < NP; k++) lf[k] = v.leaves[root_leaf(key[k], v.a, v.nl)];
+            for (int k = 0; k < NP; k++) {
+                uint32_t l = root_leaf(key[k], v.a, v.nl);
+                lf[k] = v.leaves[l];
+                llo[k] = v.leaf_lo[l];
+                lhi[k] = v.leaf_lo[l + 1];
+            }
             int64_t len[NP];
 #pragma unroll
             for (int k = 0; k < NP; k++) {
-                int64_t p = predict((uint64_t)(uint32_t)lf[k].x, __int_as_float(lf[k].y),
-                                    __int_as_float(lf[k].z), key[k]);
+                int64_t p = predict_in_leaf(lf[k], llo[k], lhi[k], key[k]);
+                int64_t ra, rb;
+                leaf_range(llo[k], lhi[k], &ra, &rb);
                 int64_t a = p - lf[k].w, e = p + lf[k].w;
-                a = a < 0 ? 0 : (a > v.n - 1 ? v.n - 1 : a);
-                e = e < a ? a : (e > v.n - 1 ? v.n - 1 : e);
+                a = a < ra ? ra : a;
+                e = e > rb ? rb : e;
                 q[k] = a;
                 len[k] = e - a + 1;
             }
@@ -568,12 +577,14 @@ static void views(const sba_handle *h, GridView *g, HilbView *hv)
         hv->a = h->root_a;
         hv->nl = 1u << h->log2_leaves;
         hv->leaves = h->leaves;
-        hv->win = std::min<int64_t>(2 * h->max_leaf_err + 3, std::max<int64_t>(h->n_runs, 1));
+        hv->leaf_lo = h->leaf_lo;
     }
 }
 
 // blocks per CU for the streaming probe
 static int g_blocks_per_cu = 8;
+// force the 32-bit global directory (comparison runs)
+static bool g_force_wide = false;
 
 template <int LAYOUT>
 static int launch_layout(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
@@ -631,6 +642,201 @@ static int launch_layout(const int32_t *xy, const int64_t *values, int64_t n, co
     return 0;
 }
 
+
+// ---------------------------------------------------------------- grid probe, LDS directory
+//
+// The 16-bit directory (<= 128 KB) is copied into LDS once per workgroup;
+// a point in a uniform tile then costs one LDS read instead of a random
+// global gather (1e8 scattered 4-byte gathers are bounded by the L2 request
+// rate, not by bytes).  Points in mixed tiles read their cell's 16-bit code
+// from the fine blocks in global memory, batched 8 points at a time.  The
+// point stream uses non-temporal loads, so it does not evict the blocks.
+
+#define GRID16_BLOCK 512
+
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef long long v2l_t __attribute__((ext_vector_type(2)));
+
+struct Grid16 {
+    int64_t ox, oy;
+    uint32_t extx, exty;
+    uint32_t mag;
+    int32_t shift;
+    int32_t tl;
+    uint32_t tw;
+    uint32_t nt16;                // directory entries, a multiple of 8
+    const uint16_t *dir16;
+    const uint16_t *blocks16;
+    uint32_t np;                  // short codes: p+1 polygon p, > np set (code - np - 1)
+};
+
+template <bool VALS>
+__device__ __forceinline__ void add_short(uint32_t sc, int64_t v, const Agg &A, uint32_t np,
+                                          uint32_t *lcnt, unsigned long long *lsum)
+{
+    if (sc == 0) return;
+    if (sc <= np) {
+        atomicAdd(&lcnt[sc - 1], 1u);
+        if (VALS) atomicAdd(&lsum[sc - 1], (unsigned long long)v);
+    } else {
+        uint32_t k = sc - np - 1;
+        if (k >= A.n_sets) return;
+        for (int64_t t = A.set_off[k], e = A.set_off[k + 1]; t < e; t++) {
+            uint32_t p = (uint32_t)A.set_ids[t];
+            if (p >= np) continue;
+            atomicAdd(&lcnt[p], 1u);
+            if (VALS) atomicAdd(&lsum[p], (unsigned long long)v);
+        }
+    }
+}
+
+template <bool VALS>
+__global__ __launch_bounds__(GRID16_BLOCK) void k_probe_grid16(const int4 *__restrict__ xy4,
+                                                              const longlong2 *__restrict__ v2,
+                                                              const int32_t *__restrict__ xy,
+                                                              const int64_t *__restrict__ vals,
+                                                              int64_t n, Grid16 g, Agg A,
+                                                              uint32_t *__restrict__ pcnt,
+                                                              unsigned long long *__restrict__ psum)
+{
+    extern __shared__ unsigned long long smem[];
+    const uint32_t np = g.np;
+    unsigned long long *lsum = smem;
+    uint32_t *lcnt = (uint32_t *)(smem + np);
+    uint16_t *ldir = (uint16_t *)(((uintptr_t)(lcnt + np) + 15) & ~(uintptr_t)15);
+    {
+        const uint4 *src = (const uint4 *)g.dir16;
+        uint4 *dst = (uint4 *)ldir;
+        for (uint32_t q = threadIdx.x; q < g.nt16 / 8; q += GRID16_BLOCK) dst[q] = src[q];
+        for (uint32_t p = threadIdx.x; p < np; p += GRID16_BLOCK) {
+            lcnt[p] = 0;
+            lsum[p] = 0;
+        }
+    }
+    __syncthreads();
+    const uint32_t m = (1u << g.tl) - 1u;
+    const int64_t npairs = n >> 1;
+    const int64_t stride = (int64_t)gridDim.x * GRID16_BLOCK;
+    for (int64_t t0 = (int64_t)blockIdx.x * GRID16_BLOCK + threadIdx.x; t0 < npairs;
+         t0 += stride * PROBE_UNROLL) {
+        v4i_t q[PROBE_UNROLL];
+        v2l_t vv[PROBE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; u++) {
+            int64_t t = t0 + (int64_t)u * stride;
+            if (t < npairs) {
+                q[u] = __builtin_nontemporal_load((const v4i_t *)(xy4 + t));
+                if (VALS) vv[u] = __builtin_nontemporal_load((const v2l_t *)(v2 + t));
+                else vv[u] = v2l_t{0, 0};
+            } else {
+                q[u] = v4i_t{INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN};
+                vv[u] = v2l_t{0, 0};
+            }
+        }
+        uint32_t e[2 * PROBE_UNROLL], lo[2 * PROBE_UNROLL];
+        bool ok[2 * PROBE_UNROLL];
+#pragma unroll
+        for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
+            int32_t x = (k & 1) ? q[k >> 1].z : q[k >> 1].x;
+            int32_t y = (k & 1) ? q[k >> 1].w : q[k >> 1].y;
+            int64_t dx = (int64_t)x - g.ox, dy = (int64_t)y - g.oy;
+            ok[k] = (uint64_t)dx < g.extx && (uint64_t)dy < g.exty;
+            uint32_t i = divmagic(ok[k] ? (uint32_t)dx : 0u, g.mag, g.shift);
+            uint32_t j = divmagic(ok[k] ? (uint32_t)dy : 0u, g.mag, g.shift);
+            e[k] = ldir[(j >> g.tl) * g.tw + (i >> g.tl)];
+            lo[k] = ((j & m) << g.tl) | (i & m);
+        }
+        uint32_t f[2 * PROBE_UNROLL];
+#pragma unroll
+        for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
+            bool fine = ok[k] && (e[k] & 0x8000u);
+            f[k] = g.blocks16[fine ? ((uint64_t)(e[k] & 0x7fffu) << (2 * g.tl)) + lo[k] : 0];
+        }
+#pragma unroll
+        for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
+            uint32_t sc = !ok[k] ? 0u : ((e[k] & 0x8000u) ? f[k] : e[k]);
+            add_short<VALS>(sc, (k & 1) ? vv[k >> 1].y : vv[k >> 1].x, A, np, lcnt, lsum);
+        }
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        int64_t k = n - 1;
+        int32_t x = xy[2 * k], y = xy[2 * k + 1];
+        int64_t dx = (int64_t)x - g.ox, dy = (int64_t)y - g.oy;
+        if ((uint64_t)dx < g.extx && (uint64_t)dy < g.exty) {
+            uint32_t i = divmagic((uint32_t)dx, g.mag, g.shift);
+            uint32_t j = divmagic((uint32_t)dy, g.mag, g.shift);
+            uint32_t ee = ldir[(j >> g.tl) * g.tw + (i >> g.tl)];
+            uint32_t sc = (ee & 0x8000u)
+                              ? g.blocks16[((uint64_t)(ee & 0x7fffu) << (2 * g.tl)) +
+                                           (((j & m) << g.tl) | (i & m))]
+                              : ee;
+            add_short<VALS>(sc, VALS ? vals[k] : 0, A, np, lcnt, lsum);
+        }
+    }
+    __syncthreads();
+    uint32_t *oc = pcnt + (int64_t)blockIdx.x * np;
+    unsigned long long *os = psum + (int64_t)blockIdx.x * np;
+    for (uint32_t p = threadIdx.x; p < np; p += GRID16_BLOCK) {
+        oc[p] = lcnt[p];
+        if (VALS) os[p] = lsum[p];
+    }
+}
+
+static int launch_grid16(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
+                         uint64_t *counts, int64_t *sums, hipStream_t st)
+{
+    Grid16 g{};
+    g.ox = h->gi0 * h->s;
+    g.oy = h->gj0 * h->s;
+    g.extx = (uint32_t)(h->gw * h->s);
+    g.exty = (uint32_t)(h->gh * h->s);
+    g.mag = h->mag;
+    g.shift = h->shift;
+    g.tl = h->tile_log2;
+    g.tw = (uint32_t)h->tw;
+    g.nt16 = (uint32_t)(((h->tw * h->th) + 7) & ~(int64_t)7);
+    g.dir16 = h->dir16;
+    g.blocks16 = h->blocks16;
+    g.np = (uint32_t)h->n_polys;
+    Agg A{h->set_off, h->set_ids, (uint32_t)h->n_polys, (uint32_t)h->n_sets};
+    const int32_t np = h->n_polys;
+    const bool vals = values != nullptr && sums != nullptr;
+    const size_t lds = (size_t)np * 12 + 16 + (size_t)g.nt16 * 2;
+    const int per_cu = lds <= 72 * 1024 ? 2 : 1;
+    const int64_t npairs = n >> 1;
+    int64_t nb = std::min<int64_t>((npairs + GRID16_BLOCK - 1) / GRID16_BLOCK,
+                                   (int64_t)cu_count() * per_cu);
+    if (nb < 1) nb = 1;
+    char *scratch = nullptr;
+    RC(tmp_alloc(&scratch, (int64_t)nb * np * (4 + (vals ? 8 : 0)) + 8, st));
+    unsigned long long *psum = (unsigned long long *)scratch;
+    uint32_t *pcnt = (uint32_t *)(vals ? scratch + (size_t)nb * np * 8 : scratch);
+    // dynamic LDS above 64 KB has to be allowed explicitly
+    (void)hipFuncSetAttribute((const void *)k_probe_grid16<true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void *)k_probe_grid16<false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipGetLastError();
+    if (vals)
+        hipLaunchKernelGGL(k_probe_grid16<true>, dim3((unsigned)nb), dim3(GRID16_BLOCK), lds, st,
+                           (const int4 *)xy, (const longlong2 *)values, xy, values, n, g, A, pcnt,
+                           psum);
+    else
+        hipLaunchKernelGGL(k_probe_grid16<false>, dim3((unsigned)nb), dim3(GRID16_BLOCK), lds, st,
+                           (const int4 *)xy, (const longlong2 *)values, xy, values, n, g, A, pcnt,
+                           psum);
+    hipError_t e1 = hipGetLastError();
+    if (vals)
+        hipLaunchKernelGGL(k_reduce<true>, dim3((unsigned)np), dim3(256), 0, st, pcnt, psum, nb, np,
+                           counts, sums);
+    else
+        hipLaunchKernelGGL(k_reduce<false>, dim3((unsigned)np), dim3(256), 0, st, pcnt, psum, nb, np,
+                           counts, sums);
+    hipError_t e2 = hipGetLastError();
+    tmp_free(scratch, st);
+    return (e1 != hipSuccess || e2 != hipSuccess) ? SBA_EDEVICE : 0;
+}
+
 int probe_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
                  int32_t search, uint64_t *counts, int64_t *sums, hipStream_t st)
 {
@@ -641,7 +847,10 @@ int probe_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_
         HIP_OK(hipGetLastError());
         return 0;
     }
-    if (h->kind == SBA_KIND_GRID) return launch_layout<0>(xy, values, n, h, counts, sums, st);
+    if (h->kind == SBA_KIND_GRID) {
+        if (h->dir16 && !g_force_wide) return launch_grid16(xy, values, n, h, counts, sums, st);
+        return launch_layout<0>(xy, values, n, h, counts, sums, st);
+    }
     if (search == SBA_SEARCH_LEARNED) {
         if (!h->leaves) return SBA_EINVAL;
         return launch_layout<2>(xy, values, n, h, counts, sums, st);
@@ -901,4 +1110,10 @@ int batch_launch(const sba_task *tasks, int32_t n_tasks, hipStream_t st)
     }
     tmp_free(buf, st);
     return rc;
+}
+
+extern "C" int sba_debug_force_wide_grid(int on)
+{
+    g_force_wide = on != 0;
+    return 0;
 }

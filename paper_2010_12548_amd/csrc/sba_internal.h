@@ -25,6 +25,8 @@
 #define MAX_POLYS ((1 << 21) - 1)
 #define MAX_DEPTH 32           // polygons per cell
 #define MAX_GRID_SIDE (1 << 21)
+#define COMPACT_DIR_TILES 32768       // default tile size: directory <= 64 KB at 16 bits
+#define COMPACT_DIR_TILES_MAX 65536   // 16-bit directory still staged in LDS up to 128 KB
 
 __host__ __device__ inline int32_t code_to_ref(uint32_t c)
 {
@@ -50,6 +52,8 @@ struct sba_handle {
     uint32_t *dir;       // [tw*th]
     uint32_t *blocks;    // [n_blocks << (2*tile_log2)]
     int64_t n_blocks;
+    uint16_t *dir16;     // 16-bit directory (LDS-staged by the probe) or NULL
+    uint16_t *blocks16;  // 16-bit fine blocks (with dir16)
     // polygon sets of multi-polygon cells
     int64_t *set_off;    // [n_sets+1] (device)
     int32_t *set_ids;    // [n_set_ids] (device)
@@ -65,7 +69,9 @@ struct sba_handle {
     float root_a;        // leaf = floor((float)(key - root_k0) * root_a)
     uint64_t root_k0;
     int4 *leaves;        // [2^log2_leaves] {key base (u32 bits), slope (f32 bits), icpt (f32 bits), err}
+    int32_t *leaf_lo;    // [2^log2_leaves + 1] first run position of each leaf's key range
     int64_t max_leaf_err;
+    double mean_leaf_err;
     // bookkeeping
     int64_t n_segments, n_boundary;
     int64_t bytes;
@@ -159,6 +165,24 @@ __device__ __forceinline__ int64_t predict(uint64_t kbase, float slope, float ic
     float x = (float)(key - kbase);
     float f = __fadd_rn(__fmul_rn(slope, x), icpt);
     return (int64_t)floorf(f);
+}
+
+// The run holding a key of leaf l is one of lo-1 .. hi-1, where [lo, hi) are
+// the positions of the run starts inside the leaf's key range: clamp the
+// prediction into that range (fit and probe alike), so no leaf's error can
+// exceed its own size.
+__device__ __forceinline__ void leaf_range(int64_t lo, int64_t hi, int64_t *a, int64_t *b)
+{
+    *a = lo > 0 ? lo - 1 : 0;
+    *b = hi - 1 > *a ? hi - 1 : *a;
+}
+
+__device__ __forceinline__ int64_t predict_in_leaf(int4 lf, int64_t lo, int64_t hi, uint64_t key)
+{
+    int64_t a, b;
+    leaf_range(lo, hi, &a, &b);
+    int64_t p = predict((uint64_t)(uint32_t)lf.x, __int_as_float(lf.y), __int_as_float(lf.z), key);
+    return p < a ? a : (p > b ? b : p);
 }
 
 // ---------------------------------------------------------------- primitives (prims.hip)

@@ -80,7 +80,8 @@ class Server:
     """
 
     def __init__(self, xy, values, polygon_sets, box, G: int = 256, mem_budget: int = 8 << 30,
-                 max_batch: int = 256, kind: str = "grid"):
+                 max_batch: int = 256, kind: str = "grid", builders: int = 4,
+                 max_inflight: int = 1):
         import torch
         self.torch = torch
         self.dev = xy.device
@@ -89,7 +90,7 @@ class Server:
         self.G = G
         self.cell = max(1, -(-int(side) // G))
         self.probe_stream = torch.cuda.Stream(device=self.dev)
-        self.build_stream = torch.cuda.Stream(device=self.dev)
+        self.build_streams = [torch.cuda.Stream(device=self.dev) for _ in range(max(1, builders))]
         t0 = time.perf_counter()
         with torch.cuda.stream(self.probe_stream):
             self.xy, self.values, off = bucket_points(xy, values, x0, y0, self.cell, G,
@@ -113,10 +114,14 @@ class Server:
         self._ready = collections.deque()
         self._stop = False
         self.batches = []             # (n_queries, n_tasks) per launch
+        self.max_inflight = max(1, max_inflight)
+        self._paused = False
         self._inflight_jobs = []
-        self._builder = threading.Thread(target=self._build_loop, daemon=True)
+        self._builders = [threading.Thread(target=self._build_loop, args=(st,), daemon=True)
+                          for st in self.build_streams]
         self._batcher = threading.Thread(target=self._batch_loop, daemon=True)
-        self._builder.start()
+        for t in self._builders:
+            t.start()
         self._batcher.start()
 
     # ------------------------------------------------------------ helpers
@@ -161,15 +166,34 @@ class Server:
             self._lock.notify_all()
         return fut
 
+    def pause(self):
+        """Stop launching batches (admission and builds go on)."""
+        with self._lock:
+            self._paused = True
+
+    def resume(self):
+        with self._lock:
+            self._paused = False
+            self._lock.notify_all()
+
+    def n_ready(self) -> int:
+        with self._lock:
+            return len(self._ready)
+
+    def _builders_alive(self):
+        return any(t.is_alive() for t in self._builders)
+
     def close(self):
+        self.resume()
         with self._lock:
             self._stop = True
             self._lock.notify_all()
-        self._builder.join()
+        for t in self._builders:
+            t.join()
         self._batcher.join()
 
     # ------------------------------------------------------------ threads
-    def _build_loop(self):
+    def _build_loop(self, stream):
         torch = self.torch
         while True:
             with self._lock:
@@ -193,9 +217,9 @@ class Server:
                 ro, vo, pxy, np_, _ = self.sets[q.set_id]
                 win = (q.vx, q.vy, q.vx + q.vw, q.vy + q.vw)
                 t0 = time.perf_counter()
-                with torch.cuda.stream(self.build_stream):
+                with torch.cuda.stream(stream):
                     job.approx = Approx(ro, vo, pxy, q.eps, kind=self.kind, window=win,
-                                        stream=self.build_stream)
+                                        stream=stream)
                 job.build_ms = 1000.0 * (time.perf_counter() - t0)
                 job.ranges = self.ranges_of(q)
                 job.npts = sum(b - a for a, b in job.ranges)
@@ -240,38 +264,41 @@ class Server:
         inflight = collections.deque()   # (event, jobs), in launch order
         self._inflight_jobs = []
         while True:
+            # complete finished launches, in order
+            while inflight and inflight[0][0].query():
+                self._finish(*inflight.popleft())
+                self._inflight_jobs = [j for _, b in inflight for j in b]
             with self._lock:
-                if not self._ready and not inflight:
-                    if self._stop and not self._pending and not self._builder.is_alive():
+                can_launch = (self._ready and not self._paused
+                              and (len(inflight) < self.max_inflight
+                                   or len(self._ready) >= self.max_batch))
+                if not can_launch:
+                    if (self._stop and not inflight and not self._ready and not self._pending
+                            and not self._builders_alive()):
                         return
-                    self._lock.wait(0.002)
+                    self._lock.wait(0.0002 if inflight else 0.002)
+                    continue
                 batch = []
                 while self._ready and len(batch) < self.max_batch:
                     batch.append(self._ready.popleft())
-            if batch:
-                tasks = []
-                for job in batch:
-                    np_ = max(job.approx.n_polys, 1)
-                    job.counts = torch.empty(np_, dtype=torch.int64, device=self.dev)
-                    job.sums = (torch.empty(np_, dtype=torch.int64, device=self.dev)
-                                if job.q.agg == "sum" else None)
-                    vals = self.values if job.q.agg == "sum" else None
-                    view = (job.q.vx, job.q.vy, job.q.vw, job.q.vw)
-                    for a, b in (job.ranges or [(0, 0)]):
-                        tasks.append(Task(job.approx, self.xy, vals, a, b, view, job.counts,
-                                          job.sums))
-                with torch.cuda.stream(self.probe_stream):
-                    aggregate_batch(tasks, stream=self.probe_stream)
-                    ev = torch.cuda.Event()
-                    ev.record(self.probe_stream)
-                self.batches.append((len(batch), len(tasks)))
-                inflight.append((ev, batch))
-                self._inflight_jobs = [j for _, b in inflight for j in b]
-            # complete finished launches in order; block only when idle otherwise
-            while inflight and (inflight[0][0].query() or not self._ready_nonempty()):
-                self._finish(*inflight.popleft())
-                if self._ready_nonempty():
-                    break
+            tasks = []
+            for job in batch:
+                np_ = max(job.approx.n_polys, 1)
+                job.counts = torch.empty(np_, dtype=torch.int64, device=self.dev)
+                job.sums = (torch.empty(np_, dtype=torch.int64, device=self.dev)
+                            if job.q.agg == "sum" else None)
+                vals = self.values if job.q.agg == "sum" else None
+                view = (job.q.vx, job.q.vy, job.q.vw, job.q.vw)
+                for a, b in (job.ranges or [(0, 0)]):
+                    tasks.append(Task(job.approx, self.xy, vals, a, b, view, job.counts,
+                                      job.sums))
+            with torch.cuda.stream(self.probe_stream):
+                aggregate_batch(tasks, stream=self.probe_stream)
+                ev = torch.cuda.Event()
+                ev.record(self.probe_stream)
+            self.batches.append((len(batch), len(tasks)))
+            inflight.append((ev, batch))
+            self._inflight_jobs = [j for _, b in inflight for j in b]
 
     def _finish(self, ev, jobs):
         ev.synchronize()

@@ -266,3 +266,24 @@ def test_city_partition_sampled(sba, orc):
         np.testing.assert_array_equal(c, want_c)
         np.testing.assert_array_equal(s, want_s)
         assert int(c.sum()) >= 4_000_000
+
+
+@pytest.mark.parametrize("eps", [100, 1000, 10000])
+def test_lds_directory_and_global_directory_agree(sba, orc, eps):
+    """The grid probe with the 16-bit LDS-staged directory and the one with
+    the 32-bit directory in global memory give the oracle's answer."""
+    from gen import city_polygons
+    polys = city_polygons()
+    xy, vals = city_points(1_000_000)
+    want_c, want_s = orc.Approx(polys, eps).aggregate(xy, vals)
+    A = sba.Approx.from_polygons(polys, eps)
+    try:
+        for wide in (0, 1):
+            sba.lib().sba_debug_force_wide_grid(wide)
+            c, s = run_agg(A, xy, vals)
+            np.testing.assert_array_equal(c, want_c)
+            np.testing.assert_array_equal(s, want_s)
+            c, _ = run_agg(A, xy, None)
+            np.testing.assert_array_equal(c, want_c)
+    finally:
+        sba.lib().sba_debug_force_wide_grid(0)

@@ -200,11 +200,19 @@ def test_server_results_alone_mixed_and_oracle(sba, orc, city_small):
     Q = _queries(serve, qs)
     try:
         alone = [S.submit(q).result(timeout=60) for q in Q]        # one at a time
-        futs = [S.submit(q) for q in Q]                            # all in flight together
+        n_alone = len(S.batches)
+        S.pause()                                                  # let every query get built,
+        futs = [S.submit(q) for q in Q]                            # then one mixed launch
+        import time
+        t0 = time.time()
+        while S.n_ready() < len(Q) and time.time() - t0 < 60:
+            time.sleep(0.01)
+        S.resume()
         mixed = [f.result(timeout=60) for f in futs]
     finally:
         S.close()
-    assert max(n for n, _ in S.batches) > 1                       # batching happened
+    assert all(n == 1 for n, _ in S.batches[:n_alone])
+    assert S.batches[n_alone][0] == len(Q)                        # all in one batch
     for q, a, m in zip(Q, alone, mixed):
         np.testing.assert_array_equal(a.counts, m.counts)
         if q.agg == "sum":

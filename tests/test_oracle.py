@@ -363,3 +363,32 @@ def test_hilbert_runs_against_brute(orc):
     # every cell of every approximation lies inside the key grid
     P, R, X0, X1 = A.intervals()
     assert X0.min() >= i0 and X1.max() <= i0 + n and R.min() >= j0 and R.max() < j0 + n
+
+
+# ---------------------------------------------------------------- workloads
+
+def test_invariant_every_point_tiny_workload(orc):
+    """Tiny workload (1M points, 16 overlapping stars, eps = 64): every point
+    on which the approximation and the exact join differ lies within eps of
+    the polygon's boundary, and no point inside a polygon is missed."""
+    from gen import tiny_workload
+    xy, vals, polys = tiny_workload()
+    A = orc.Approx(polys, 64)
+    inv = A.invariant(xy)
+    assert inv["far"] == 0 and inv["false_neg"] == 0 and inv["differ"] > 0
+    ap, _ = A.aggregate(xy)
+    ex, _ = A.exact(xy)
+    assert np.all(ex <= ap)
+
+
+@pytest.mark.parametrize("eps", [100, 1000, 10000])
+def test_invariant_city_sample(orc, eps):
+    """City partition (260 jittered Voronoi cells), 2M mixture points."""
+    from gen import city_points, city_polygons
+    polys = city_polygons()
+    xy, _ = city_points(2_000_000)
+    A = orc.Approx(polys, eps)
+    inv = A.invariant(xy)
+    assert inv["far"] == 0 and inv["false_neg"] == 0
+    ex, _ = A.exact(xy)
+    assert int(ex.sum()) == 2_000_000           # a partition of the box
