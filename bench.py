@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-sweep", action="store_true", help="skip the eps sweep")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--log2-leaves", type=int, default=16, help="learned index leaves (log2)")
     ap.add_argument("--force-wide", action="store_true",
                     help="grid probe: 32-bit directory in global memory instead of the LDS copy")
     ap.add_argument("--probe-only", action="store_true",
@@ -68,7 +69,7 @@ def probe_only(args, sba, torch, txy, tv, ro, vo, pxy, eps, layout, search, n):
         torch.cuda.synchronize()
         log(f"[bench] calibration copy: {nb} bytes read, {nb} bytes written")
         del src, dst
-    a = sba.Approx(ro, vo, pxy, eps, kind=layout, search=search)
+    a = sba.Approx(ro, vo, pxy, eps, kind=layout, search=search, log2_leaves=args.log2_leaves)
     counts = torch.empty(a.n_polys, dtype=torch.int64, device="cuda")
     sums = torch.empty(a.n_polys, dtype=torch.int64, device="cuda")
     for _ in range(args.warmup):
@@ -228,7 +229,7 @@ def main():
     counts = torch.empty(polys.n_polys, dtype=torch.int64, device=dev)
     sums = torch.empty(polys.n_polys, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
-    kw = dict(kind=layout, search=search)
+    kw = dict(kind=layout, search=search, log2_leaves=args.log2_leaves)
     if args.probe_only:
         probe_only(args, sba, torch, txy, tv, ro, vo, pxy, eps, layout, search, n)
         return
@@ -273,7 +274,8 @@ def main():
     extra = {}
     if layout == "hilbert":
         # binary and learned probe on the same handle, identical results required
-        a = sba.Approx(ro, vo, pxy, eps, kind="hilbert", search="learned")
+        a = sba.Approx(ro, vo, pxy, eps, kind="hilbert", search="learned",
+                       log2_leaves=args.log2_leaves)
         out = {}
         for srch in ("binary", "learned"):
             cc = torch.empty_like(counts)

@@ -74,8 +74,8 @@ typedef struct {
     int32_t kind;         /* SBA_KIND_GRID (default) or SBA_KIND_HILBERT                 */
     int32_t search;       /* Hilbert only: SBA_SEARCH_BINARY (default) or _LEARNED       */
     int32_t log2_leaves;  /* learned index: number of leaves = 2^log2_leaves (0 -> 16)   */
-    int32_t tile_log2;    /* grid: tile side 2^tile_log2 cells, 3..8 (0 -> chosen from
-                             the grid size)                                              */
+    int32_t tile_log2;    /* grid: tile side 2^tile_log2 cells, 2..10 (0 -> the smallest
+                             tile whose 16-bit directory fits 64 KB)                      */
     int32_t use_window;   /* 1: store only the cells that overlap the clip window        */
     int32_t win_x0, win_y0, win_x1, win_y1;  /* clip window [x0,x1) x [y0,y1), coordinates;
                              cells outside it are empty in the handle (for viewport

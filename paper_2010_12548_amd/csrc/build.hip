@@ -813,12 +813,12 @@ int build_grid(sba_handle *h, BuildState &B, int tile_log2, hipStream_t st)
 {
     int tl = tile_log2;
     if (tl == 0) {  // smallest tile whose 16-bit directory fits 64 KB of LDS
-        tl = 3;
+        tl = 2;
         while (tl < 10 && ((h->gw + (1 << tl) - 1) >> tl) * ((h->gh + (1 << tl) - 1) >> tl) >
                               COMPACT_DIR_TILES)
             tl++;
     }
-    if (tl < 3 || tl > 10) return SBA_EINVAL;
+    if (tl < 2 || tl > 10) return SBA_EINVAL;
     h->tile_log2 = tl;
     h->tw = (h->gw + (1 << tl) - 1) >> tl;
     h->th = (h->gh + (1 << tl) - 1) >> tl;
