@@ -12,14 +12,17 @@
 //   1. per edge and per row strip the edge touches: the closed x-range of the
 //      edge inside the strip gives one interval of boundary cells;
 //   2. per edge and per row line y = js it crosses (half-open rule): the
-//      crossing's cell index k = ceil(xc/s); sorted per (polygon, row), the
+//      crossing's cell index k = ceil(xc/s); in order per (polygon, row), the
 //      crossings pair up into the intervals [k1,k2), [k3,k4) ... of cells
 //      whose corner is inside;
-//   3. all intervals become +p/-p events sorted by (row, x); one thread per
-//      row sweeps them and emits maximal row segments of constant polygon
-//      set;
-//   4. sets of two or more polygons are deduplicated into a set table;
-//   5. the segments are written into the chosen layout: a two-level tiled
+//   3. boundary intervals and crossings become events keyed (polygon, row,
+//      x); one scan over them in key order yields each polygon's coverage
+//      count, whose changes give its maximal covered intervals per row;
+//   4. the distinct interval ends of a row cut it into pieces; each covered
+//      interval adds its polygon to the pieces it spans, and the non-empty
+//      pieces are the maximal row segments of constant polygon set;
+//   5. sets of two or more polygons are deduplicated into a set table;
+//   6. the segments are written into the chosen layout: a two-level tiled
 //      grid (uniform tiles stored once in a directory, mixed tiles as fine
 //      blocks) or, in hilbert.hip, the runs of the Hilbert order.
 #include <chrono>
@@ -29,6 +32,11 @@
 #include "build_state.h"
 
 // ---------------------------------------------------------------- kernels
+
+// event kinds (payload of the (polygon, row, x) event keys)
+#define EV_OPEN 0u   // first cell of a boundary interval
+#define EV_CLOSE 1u  // one past the last cell of a boundary interval
+#define EV_CROSS 2u  // crossing of the row line y = j s
 
 __global__ void k_edges(const int32_t *ring_off, int32_t n_polys, const int64_t *vert_off,
                         int32_t n_rings, const int32_t *xy, int64_t n_verts, int4 *edges,
@@ -142,11 +150,12 @@ __device__ __forceinline__ int64_t upper_bound_i64(const int64_t *a, int64_t n, 
 }
 
 // boundary item t -> interval of cells [c0, c1] of row j touched by its edge,
-// cut to the stored box, written as a start and an end event (an interval
-// cut away entirely becomes an empty start/end pair at x = 0)
+// cut to the stored box, written as a start and an end event keyed
+// (polygon, row, x) (an interval cut away entirely becomes an empty
+// start/end pair at x = 0)
 __global__ void k_emit_boundary(const int4 *edges, const int32_t *epoly, int64_t n_edges,
                                 const int64_t *boff, int64_t nb_total, int64_t s, int64_t gi0,
-                                int64_t gj0, int64_t gi1, int xbits, uint64_t *evkey,
+                                int64_t gj0, int64_t gi1, int xbits, int rbits, uint64_t *evkey,
                                 uint32_t *evpay)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -174,19 +183,19 @@ __global__ void k_emit_boundary(const int4 *edges, const int32_t *epoly, int64_t
     c0 = max(c0, gi0);
     c1 = min(c1, gi1);
     if (c0 > c1) { c0 = gi0; c1 = gi0 - 1; }
-    uint64_t r = (uint64_t)(j - gj0);
-    uint32_t p = (uint32_t)epoly[e];
-    evkey[2 * t] = (r << xbits) | (uint64_t)(c0 - gi0);
-    evpay[2 * t] = p << 1;
-    evkey[2 * t + 1] = (r << xbits) | (uint64_t)(c1 + 1 - gi0);
-    evpay[2 * t + 1] = (p << 1) | 1u;
+    uint64_t pr = ((uint64_t)epoly[e] << (rbits + xbits)) | ((uint64_t)(j - gj0) << xbits);
+    evkey[2 * t] = pr | (uint64_t)(c0 - gi0);
+    evpay[2 * t] = EV_OPEN;
+    evkey[2 * t + 1] = pr | (uint64_t)(c1 + 1 - gi0);
+    evpay[2 * t + 1] = EV_CLOSE;
 }
 
-// crossing item t -> key (polygon, row, k) with k = ceil(xc / s), k cut to
-// [gi0, gi1 + 1] (spans are then cut to the stored box)
+// crossing item t -> event (polygon, row, k) with k = ceil(xc / s), k cut to
+// [gi0, gi1 + 1] (inside spans are then cut to the stored box)
 __global__ void k_emit_cross(const int4 *edges, const int32_t *epoly, int64_t n_edges,
                              const int64_t *coff, int64_t nc_total, int64_t s, int64_t gi0,
-                             int64_t gj0, int64_t gi1, int xbits, int rbits, uint64_t *ckey)
+                             int64_t gj0, int64_t gi1, int xbits, int rbits, uint64_t *evkey,
+                             uint32_t *evpay)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nc_total) return;
@@ -200,155 +209,196 @@ __global__ void k_emit_cross(const int4 *edges, const int32_t *epoly, int64_t n_
     if (den < 0) { den = -den; num = -num; }
     int64_t k = ceildiv64(num, den * s);
     k = min(max(k, gi0), gi1 + 1);
-    ckey[t] = ((uint64_t)epoly[e] << (rbits + xbits)) | ((uint64_t)(j - gj0) << xbits) |
-              (uint64_t)(k - gi0);
+    evkey[t] = ((uint64_t)epoly[e] << (rbits + xbits)) | ((uint64_t)(j - gj0) << xbits) |
+               (uint64_t)(k - gi0);
+    evpay[t] = EV_CROSS;
 }
 
-// sorted crossings pair up within each (polygon, row): span [k1, k2)
-__global__ void k_spans(const uint64_t *ckey, int64_t npairs, int xbits, int rbits,
-                        uint64_t *evkey, uint32_t *evpay, int *err)
+// ------------------------------------------------ coverage of each row
+//
+// Events carry the key (polygon, row, x) and one of three kinds: the start
+// of a boundary interval, one past its end, or a crossing of the row line.
+// Sorted by key, each (polygon, row) group holds matched starts and ends and
+// an even number of crossings; cells from the 2m-th to the (2m+1)-th
+// crossing have their corner inside (Sec. 2.2, crossing-number rule).  The
+// polygon covers x when a boundary interval is open there or the crossings
+// seen so far are odd in number.  One global scan gives both counts at every
+// event: starts and ends add +1/-1 to the low 32 bits, crossings add 1 to
+// the high bits.  Groups before the current one are balanced, so the prefix
+// equals the prefix within the group.
+__device__ __forceinline__ int64_t ev_value(uint32_t kind)
+{
+    return kind == EV_CROSS ? ((int64_t)1 << 32) : (kind == EV_OPEN ? 1 : -1);
+}
+
+// coverage count of the event's polygon just after event t (cex = exclusive
+// scan of ev_value); the low part never goes negative because the sort is
+// stable and every interval's start precedes its end
+__device__ __forceinline__ int64_t cov_after(const int64_t *cex, const uint32_t *kind, int64_t t)
+{
+    int64_t S = cex[t] + ev_value(kind[t]);
+    return (S & 0xffffffffll) + ((S >> 32) & 1);
+}
+
+__global__ void k_ev_values(const uint32_t *kind, int64_t n, int64_t *v)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) v[t] = ev_value(kind[t]);
+}
+
+// flag[t] = 1 when t is the last event of its (polygon, row, x) group and
+// the polygon's membership at x differs from its membership just before x
+// (a toggle).  Toggles of one (polygon, row) alternate on/off, starting with
+// on, so consecutive pairs are the maximal covered intervals [a, b).
+__global__ void k_toggle_flags(const uint64_t *key, const uint32_t *kind, const int64_t *cex,
+                               int64_t n, int xbits, int64_t *flag, int *err)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    uint64_t k = key[t];
+    int64_t f = 0;
+    if (t + 1 == n || key[t + 1] != k) {
+        int64_t a = t;
+        while (a > 0 && key[a - 1] == k) a--;
+        uint64_t g = k >> xbits;
+        int64_t before = (a > 0 && (key[a - 1] >> xbits) == g) ? cov_after(cex, kind, a - 1) : 0;
+        int64_t after = cov_after(cex, kind, t);
+        f = (before > 0) != (after > 0);
+        if ((t + 1 == n || (key[t + 1] >> xbits) != g) && after != 0) atomicOr(err, 2);
+    }
+    flag[t] = f;
+}
+
+__global__ void k_toggle_emit(const uint64_t *key, const int64_t *toff, int64_t n, int64_t nt,
+                              int rxbits, uint64_t *tkey, int32_t *tpoly)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    int64_t o = toff[t];
+    int64_t o1 = t + 1 < n ? toff[t + 1] : nt;
+    if (o1 == o) return;
+    uint64_t k = key[t];
+    tkey[o] = k & ((1ull << rxbits) - 1);
+    tpoly[o] = (int32_t)(k >> rxbits);
+}
+
+__global__ void k_unique_emit(const uint64_t *keys, int64_t n, const int64_t *pos, uint64_t *out)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    if (t == 0 || keys[t] != keys[t - 1]) out[pos[t]] = keys[t];
+}
+
+__device__ __forceinline__ int64_t lower_bound_key(const uint64_t *a, int64_t n, uint64_t v)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// The sorted distinct toggle positions E (row << xbits | x) cut every row
+// into elementary pieces [E[k], E[k+1]) of constant polygon set.  Covered
+// interval m spans pieces [ka, kb); the depth of piece k is the number of
+// intervals spanning it (difference array, scanned later).
+__global__ void k_interval_span(const uint64_t *tkey, int64_t nint, const uint64_t *E,
+                                const int64_t *nE, int64_t *ika, int64_t *cnt, int64_t *diff)
 {
     int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= npairs) return;
-    uint64_t a = ckey[2 * m], b = ckey[2 * m + 1];
-    if ((a >> xbits) != (b >> xbits)) atomicOr(err, 2);
-    uint64_t xm = (1ull << xbits) - 1;
-    uint64_t rm = (1ull << rbits) - 1;
-    uint32_t p = (uint32_t)(a >> (xbits + rbits));
-    uint64_t r = (a >> xbits) & rm;
-    evkey[2 * m] = (r << xbits) | (a & xm);
-    evpay[2 * m] = p << 1;
-    evkey[2 * m + 1] = (r << xbits) | (b & xm);
-    evpay[2 * m + 1] = (p << 1) | 1u;
+    if (m >= nint) return;
+    int64_t ne = *nE;
+    int64_t ka = lower_bound_key(E, ne, tkey[2 * m]);
+    int64_t kb = lower_bound_key(E, ne, tkey[2 * m + 1]);
+    ika[m] = ka;
+    cnt[m] = kb - ka;
+    atomicAdd((unsigned long long *)&diff[ka], 1ull);
+    atomicAdd((unsigned long long *)&diff[kb], ~0ull);
 }
 
-__global__ void k_row_off(const uint64_t *evkey, int64_t ne, int64_t gh, int xbits,
-                          int64_t *row_off)
+// per piece: packed counters (non-empty << 32 | multi) and multi member count
+__global__ void k_piece_classify(const int64_t *dex, const int64_t *diff, int64_t n, int64_t *segc,
+                                 int64_t *mm, int *err)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int64_t d = dex[k] + diff[k];
+    if (d > MAX_DEPTH) atomicOr(err, 8);
+    segc[k] = (d >= 1 ? ((int64_t)1 << 32) : 0) | (d >= 2 ? 1 : 0);
+    mm[k] = d >= 2 ? d : 0;
+}
+
+// one thread per (interval, piece) pair: record the interval's polygon in
+// the piece (a piece of depth 1 keeps its polygon directly)
+__global__ void k_piece_members(const int64_t *xoff, int64_t nint, int64_t nx, const int64_t *ika,
+                                const int32_t *tpoly, const int64_t *dex, const int64_t *diff,
+                                const int64_t *mmoff, int32_t *sid, int32_t *fill, int32_t *mem_ids)
+{
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= nx) return;
+    int64_t lo = 0, hi = nint;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (xoff[mid] <= u) lo = mid + 1; else hi = mid;
+    }
+    int64_t m = lo - 1;
+    int64_t k = ika[m] + (u - xoff[m]);
+    int32_t p = tpoly[2 * m];
+    if (dex[k] + diff[k] == 1) {
+        sid[k] = p;
+    } else {
+        int32_t r = atomicAdd(&fill[k], 1);
+        mem_ids[mmoff[k] + r] = p;
+    }
+}
+
+// non-empty pieces become the row segments; members of multi-polygon
+// segments are put in ascending order (the set's canonical form)
+__global__ void k_piece_emit(const uint64_t *E, int64_t n, const int64_t *dex, const int64_t *diff,
+                             const int64_t *segc, const int64_t *mmoff, const int32_t *sid,
+                             int xbits, int32_t *seg_x0, int32_t *seg_x1, uint32_t *seg_code,
+                             uint32_t *seg_row, int64_t *multi_seg, int64_t *multi_mem,
+                             int32_t *mem_ids)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int64_t d = dex[k] + diff[k];
+    if (d < 1) return;
+    const uint64_t xm = (1ull << xbits) - 1;
+    int64_t sc = segc[k];
+    int64_t o = sc >> 32;
+    uint64_t e0 = E[k], e1 = E[k + 1];
+    seg_x0[o] = (int32_t)(e0 & xm);
+    seg_x1[o] = (int32_t)(e1 & xm);
+    seg_row[o] = (uint32_t)(e0 >> xbits);
+    if (d == 1) {
+        seg_code[o] = (uint32_t)sid[k] + 1u;
+        return;
+    }
+    int64_t a = mmoff[k];
+    for (int64_t i = a + 1; i < a + d; i++) {
+        int32_t v = mem_ids[i];
+        int64_t j = i;
+        while (j > a && mem_ids[j - 1] > v) { mem_ids[j] = mem_ids[j - 1]; j--; }
+        mem_ids[j] = v;
+    }
+    int64_t mi = sc & 0xffffffffll;
+    multi_seg[mi] = o;
+    multi_mem[mi] = a;
+    seg_code[o] = 0xffffffffu;
+}
+
+__global__ void k_seg_row_off(const uint32_t *seg_row, int64_t ns, int64_t gh, int64_t *row_off)
 {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r > gh) return;
-    if (r == gh) { row_off[r] = ne; return; }
-    uint64_t v = (uint64_t)r << xbits;
-    int64_t lo = 0, hi = ne;
+    int64_t lo = 0, hi = ns;
     while (lo < hi) {
         int64_t mid = (lo + hi) >> 1;
-        if (evkey[mid] < v) lo = mid + 1; else hi = mid;
+        if ((int64_t)seg_row[mid] < r) lo = mid + 1; else hi = mid;
     }
     row_off[r] = lo;
-}
-
-// One thread per row: sweep the row's events in x order, keep the multiset
-// of open polygons, emit a segment whenever the set of polygons changes.
-// The per-thread sets live in LDS, laid out [slot][thread] so that lanes
-// touching the same slot hit different banks.
-#define SWEEP_BLOCK 64
-template <bool WRITE>
-__global__ __launch_bounds__(SWEEP_BLOCK) void k_sweep(const uint64_t *evkey, const uint32_t *evpay,
-                                                       const int64_t *ev_row_off, int64_t gh,
-                                                       int xbits, int64_t *cnt_seg,
-                                                       int64_t *cnt_multi, int64_t *cnt_mem,
-                                                       const int64_t *off_seg,
-                                                       const int64_t *off_multi,
-                                                       const int64_t *off_mem, int32_t *seg_x0,
-                                                       int32_t *seg_x1, uint32_t *seg_code,
-                                                       int64_t *multi_seg, int64_t *multi_mem,
-                                                       int32_t *mem_ids, int *err)
-{
-    __shared__ int s_ids[MAX_DEPTH][SWEEP_BLOCK];
-    __shared__ int s_cnt[MAX_DEPTH][SWEEP_BLOCK];
-    __shared__ int s_oid[MAX_DEPTH][SWEEP_BLOCK];
-    const int tl = threadIdx.x;
-#define IDS(k) s_ids[k][tl]
-#define CNT(k) s_cnt[k][tl]
-#define OID(k) s_oid[k][tl]
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= gh) return;
-    const uint64_t xmask = (1ull << xbits) - 1;
-    int na = 0, ona = 0;
-    uint32_t ox0 = 0;
-    int64_t nseg = 0, nmulti = 0, nmem = 0;
-    int64_t t = ev_row_off[r], te = ev_row_off[r + 1];
-    int bad = 0;
-    uint64_t key = t < te ? evkey[t] : 0;
-    while (t < te) {
-        uint32_t x = (uint32_t)(key & xmask);
-        bool changed = false;
-        while (t < te && (uint32_t)(key & xmask) == x) {
-            uint32_t pay = evpay[t];
-            t++;
-            key = t < te ? evkey[t] : 0;
-            int p = (int)(pay >> 1);
-            int k = 0;
-            while (k < na && IDS(k) < p) k++;
-            if (pay & 1u) {
-                if (k < na && IDS(k) == p) {
-                    int c = CNT(k) - 1;
-                    CNT(k) = c;
-                    changed |= (c == 0);
-                } else {
-                    bad |= 4;
-                }
-            } else if (k < na && IDS(k) == p) {
-                int c = CNT(k) + 1;
-                CNT(k) = c;
-                changed |= (c == 1);
-            } else if (na == MAX_DEPTH) {
-                bad |= 8;
-            } else {
-                for (int q = na; q > k; q--) { IDS(q) = IDS(q - 1); CNT(q) = CNT(q - 1); }
-                IDS(k) = p;
-                CNT(k) = 1;
-                na++;
-                changed = true;
-            }
-        }
-        if (!changed) continue;  // counts moved, membership did not
-        int m = 0;
-        for (int k = 0; k < na; k++) {
-            int c = CNT(k);
-            if (c > 0) {
-                if (m != k) { IDS(m) = IDS(k); CNT(m) = c; }
-                m++;
-            }
-        }
-        na = m;
-        bool same = (na == ona);
-        for (int k = 0; same && k < na; k++) same = (IDS(k) == OID(k));
-        if (!same) {
-            if (ona > 0) {
-                if (WRITE) {
-                    int64_t si = off_seg[r] + nseg;
-                    seg_x0[si] = (int32_t)ox0;
-                    seg_x1[si] = (int32_t)x;
-                    if (ona == 1) {
-                        seg_code[si] = (uint32_t)OID(0) + 1u;
-                    } else {
-                        int64_t mi = off_multi[r] + nmulti;
-                        int64_t mo = off_mem[r] + nmem;
-                        seg_code[si] = 0xffffffffu;
-                        multi_seg[mi] = si;
-                        multi_mem[mi] = mo;
-                        for (int k = 0; k < ona; k++) mem_ids[mo + k] = OID(k);
-                    }
-                }
-                nseg++;
-                if (ona > 1) { nmulti++; nmem += ona; }
-            }
-            for (int k = 0; k < na; k++) OID(k) = IDS(k);
-            ona = na;
-            ox0 = x;
-        }
-    }
-#undef IDS
-#undef CNT
-#undef OID
-    if (ona != 0) bad |= 16;
-    if (bad) atomicOr(err, bad);
-    if (!WRITE) {
-        cnt_seg[r] = nseg;
-        cnt_multi[r] = nmulti;
-        cnt_mem[r] = nmem;
-    }
 }
 
 // ------------------------------------------------ multi-polygon set dedup
@@ -664,7 +714,7 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     int64_t *nb = nullptr, *nc = nullptr, *tot = nullptr;
     RC(B.alloc(&nb, nv + 1));
     RC(B.alloc(&nc, nv + 1));
-    RC(B.alloc(&tot, 2));
+    RC(B.alloc(&tot, 6));
     hipLaunchKernelGGL(k_edge_counts, dim3(grid_for(nv)), dim3(256), 0, st, B.edges, B.epoly, bbox,
                        nv, s, gi0, gj0, gi1, gj1, nb, nc);
     HIP_OK(hipGetLastError());
@@ -683,19 +733,11 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     RC(B.alloc(&B.evpay, NE));
     if (NB)
         hipLaunchKernelGGL(k_emit_boundary, dim3(grid_for(NB)), dim3(256), 0, st, B.edges, B.epoly,
-                           nv, nb, NB, s, gi0, gj0, gi1, B.xbits, B.evkey, B.evpay);
-    if (NC) {
-        uint64_t *ckey = nullptr;
-        RC(B.alloc(&ckey, NC));
+                           nv, nb, NB, s, gi0, gj0, gi1, B.xbits, B.rbits, B.evkey, B.evpay);
+    if (NC)
         hipLaunchKernelGGL(k_emit_cross, dim3(grid_for(NC)), dim3(256), 0, st, B.edges, B.epoly, nv,
-                           nc, NC, s, gi0, gj0, gi1, B.xbits, B.rbits, ckey);
-        HIP_OK(hipGetLastError());
-        RC(radix_sort_u64(ckey, nullptr, NC, pbits + B.rbits + B.xbits, st));
-        hipLaunchKernelGGL(k_spans, dim3(grid_for(NC / 2)), dim3(256), 0, st, ckey, NC / 2, B.xbits,
-                           B.rbits, B.evkey + 2 * NB, B.evpay + 2 * NB, err);
-        HIP_OK(hipGetLastError());
-        B.release(ckey);
-    }
+                           nc, NC, s, gi0, gj0, gi1, B.xbits, B.rbits, B.evkey + 2 * NB,
+                           B.evpay + 2 * NB);
     HIP_OK(hipGetLastError());
     B.release(nb);
     B.release(nc);
@@ -703,61 +745,123 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     // the Hilbert layout needs the boundary cells before the events are sorted
     if (B.on_boundary_events) RC(B.on_boundary_events(B, h, st));
 
-    // 3: events by (row, x), sweep per row
-    RC(radix_sort_u64(B.evkey, B.evpay, NE, B.rbits + B.xbits, st));
-    int64_t *ev_row_off = nullptr;
-    RC(B.alloc(&ev_row_off, gh + 1));
-    hipLaunchKernelGGL(k_row_off, dim3(grid_for(gh + 1)), dim3(256), 0, st, B.evkey, NE, gh, B.xbits,
-                       ev_row_off);
-    int64_t *cs = nullptr, *cm = nullptr, *cme = nullptr;
-    RC(B.alloc(&cs, gh + 1));
-    RC(B.alloc(&cm, gh + 1));
-    RC(B.alloc(&cme, gh + 1));
-    hipLaunchKernelGGL(k_sweep<false>, dim3(grid_for(gh, SWEEP_BLOCK)), dim3(SWEEP_BLOCK), 0, st, B.evkey, B.evpay,
-                       ev_row_off, gh, B.xbits, cs, cm, cme, (const int64_t *)nullptr,
-                       (const int64_t *)nullptr, (const int64_t *)nullptr, (int32_t *)nullptr,
-                       (int32_t *)nullptr, (uint32_t *)nullptr, (int64_t *)nullptr,
-                       (int64_t *)nullptr, (int32_t *)nullptr, err);
+    // 3: coverage.  Events by (polygon, row, x); one scan gives every
+    // polygon's coverage count at every event, whose changes (toggles) are
+    // the maximal covered intervals of each polygon in each row.
+    const int rxbits = B.rbits + B.xbits;
+    RC(radix_sort_u64(B.evkey, B.evpay, NE, pbits + rxbits, st));
+    int64_t *cex = nullptr, *tf = nullptr;
+    RC(B.alloc(&cex, NE));
+    RC(B.alloc(&tf, NE));
+    hipLaunchKernelGGL(k_ev_values, dim3(grid_for(NE)), dim3(256), 0, st, B.evpay, NE, cex);
     HIP_OK(hipGetLastError());
-    int64_t *tt = nullptr;
-    RC(B.alloc(&tt, 3));
-    RC(scan_exclusive_i64(cs, cs, gh, tt, st));
-    RC(scan_exclusive_i64(cm, cm, gh, tt + 1, st));
-    RC(scan_exclusive_i64(cme, cme, gh, tt + 2, st));
-    int64_t h3[3];
-    HIP_OK(hipMemcpyAsync(h3, tt, sizeof(h3), hipMemcpyDeviceToHost, st));
+    RC(scan_exclusive_i64(cex, cex, NE, tot, st));
+    hipLaunchKernelGGL(k_toggle_flags, dim3(grid_for(NE)), dim3(256), 0, st, B.evkey, B.evpay, cex,
+                       NE, B.xbits, tf, err);
+    HIP_OK(hipGetLastError());
+    RC(scan_exclusive_i64(tf, tf, NE, tot, st));
+    int64_t NT = 0;
+    HIP_OK(hipMemcpyAsync(&NT, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
-    if (herr & 8) return SBA_ELIMIT;
-    if (herr) return SBA_EDEVICE;
-    const int64_t NS = h3[0], NM = h3[1], NMEM = h3[2];
-    if (NS >= ((int64_t)1 << 31)) return SBA_ELIMIT;
-    HIP_OK(hipMemcpyAsync(cs + gh, &NS, sizeof(int64_t), hipMemcpyHostToDevice, st));
-    h->n_segments = NS;
-    B.NS = NS;
-    B.seg_row_off = cs;
-    RC(B.alloc(&B.seg_x0, NS));
-    RC(B.alloc(&B.seg_x1, NS));
-    RC(B.alloc(&B.seg_code, NS));
-    int64_t *multi_seg = nullptr, *multi_mem = nullptr;
-    int32_t *mem_ids = nullptr;
-    RC(B.alloc(&multi_seg, NM));
-    RC(B.alloc(&multi_mem, NM));
-    RC(B.alloc(&mem_ids, NMEM));
-    hipLaunchKernelGGL(k_sweep<true>, dim3(grid_for(gh, SWEEP_BLOCK)), dim3(SWEEP_BLOCK), 0, st, B.evkey, B.evpay,
-                       ev_row_off, gh, B.xbits, (int64_t *)nullptr, (int64_t *)nullptr,
-                       (int64_t *)nullptr, cs, cm, cme, B.seg_x0, B.seg_x1, B.seg_code, multi_seg,
-                       multi_mem, mem_ids, err);
+    if (herr || (NT & 1)) return SBA_EDEVICE;
+    B.release(cex);
+    uint64_t *tkey = nullptr, *E = nullptr;
+    int32_t *tpoly = nullptr;
+    RC(B.alloc(&tkey, std::max<int64_t>(NT, 1)));
+    RC(B.alloc(&tpoly, std::max<int64_t>(NT, 1)));
+    hipLaunchKernelGGL(k_toggle_emit, dim3(grid_for(NE)), dim3(256), 0, st, B.evkey, tf, NE, NT,
+                       rxbits, tkey, tpoly);
     HIP_OK(hipGetLastError());
+    B.release(tf);
     B.release(B.evkey);
     B.evkey = nullptr;
     B.release(B.evpay);
     B.evpay = nullptr;
-    B.release(ev_row_off);
-    B.release(cm);
-    B.release(cme);
 
-    // 4: deduplicate the sets of multi-polygon segments
+    // 4: elementary pieces between distinct toggle positions of a row, their
+    // depth, and the polygons of each piece
+    const int64_t NI = NT / 2;                     // covered intervals
+    const int64_t NP = std::max<int64_t>(NT, 1);   // pieces (upper bound)
+    int64_t *pos = nullptr, *ika = nullptr, *xoff = nullptr, *diff = nullptr, *dex = nullptr;
+    int64_t *segc = nullptr, *mm = nullptr;
+    RC(B.alloc(&E, NP));
+    RC(B.alloc(&pos, NP));
+    RC(B.alloc(&ika, std::max<int64_t>(NI, 1)));
+    RC(B.alloc(&xoff, std::max<int64_t>(NI, 1)));
+    RC(B.alloc(&diff, NP + 1));
+    RC(B.alloc(&dex, NP));
+    RC(B.alloc(&segc, NP));
+    RC(B.alloc(&mm, NP));
+    HIP_OK(hipMemsetAsync(diff, 0, sizeof(int64_t) * (NP + 1), st));
+    if (NT) {
+        HIP_OK(hipMemcpyAsync(E, tkey, sizeof(uint64_t) * NT, hipMemcpyDeviceToDevice, st));
+        RC(radix_sort_u64(E, nullptr, NT, rxbits, st));
+        hipLaunchKernelGGL(k_flag_new, dim3(grid_for(NT)), dim3(256), 0, st, E, NT, pos);
+        HIP_OK(hipGetLastError());
+        RC(scan_exclusive_i64(pos, pos, NT, tot + 1, st));
+        uint64_t *Eu = nullptr;
+        RC(B.alloc(&Eu, NT));
+        hipLaunchKernelGGL(k_unique_emit, dim3(grid_for(NT)), dim3(256), 0, st, E, NT, pos, Eu);
+        HIP_OK(hipGetLastError());
+        B.release(E);
+        E = Eu;
+        hipLaunchKernelGGL(k_interval_span, dim3(grid_for(NI)), dim3(256), 0, st, tkey, NI, E,
+                           tot + 1, ika, xoff, diff);
+        HIP_OK(hipGetLastError());
+    }
+    B.release(pos);
+    RC(scan_exclusive_i64(diff, dex, NP, tot + 2, st));
+    hipLaunchKernelGGL(k_piece_classify, dim3(grid_for(NP)), dim3(256), 0, st, dex, diff, NP, segc,
+                       mm, err);
+    HIP_OK(hipGetLastError());
+    RC(scan_exclusive_i64(segc, segc, NP, tot + 3, st));
+    RC(scan_exclusive_i64(mm, mm, NP, tot + 4, st));
+    RC(scan_exclusive_i64(xoff, xoff, std::max<int64_t>(NI, 1), tot + 5, st));
+    int64_t h6[6];
+    HIP_OK(hipMemcpyAsync(h6, tot, sizeof(h6), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (herr & 8) return SBA_ELIMIT;
+    if (herr) return SBA_EDEVICE;
+    const int64_t NS = h6[3] >> 32, NM = h6[3] & 0xffffffffll, NMEM = h6[4];
+    const int64_t NX = NI ? h6[5] : 0;
+    if (NS >= ((int64_t)1 << 31)) return SBA_ELIMIT;
+    h->n_segments = NS;
+    B.NS = NS;
+    int64_t *cs = nullptr;
+    uint32_t *seg_row = nullptr;
+    int32_t *sid = nullptr, *fill = nullptr;
+    RC(B.alloc(&cs, gh + 1));
+    RC(B.alloc(&B.seg_x0, std::max<int64_t>(NS, 1)));
+    RC(B.alloc(&B.seg_x1, std::max<int64_t>(NS, 1)));
+    RC(B.alloc(&B.seg_code, std::max<int64_t>(NS, 1)));
+    RC(B.alloc(&seg_row, std::max<int64_t>(NS, 1)));
+    RC(B.alloc(&sid, NP));
+    RC(B.alloc(&fill, NP));
+    int64_t *multi_seg = nullptr, *multi_mem = nullptr;
+    int32_t *mem_ids = nullptr;
+    RC(B.alloc(&multi_seg, std::max<int64_t>(NM, 1)));
+    RC(B.alloc(&multi_mem, std::max<int64_t>(NM, 1)));
+    RC(B.alloc(&mem_ids, std::max<int64_t>(NMEM, 1)));
+    HIP_OK(hipMemsetAsync(fill, 0, sizeof(int32_t) * NP, st));
+    if (NX)
+        hipLaunchKernelGGL(k_piece_members, dim3(grid_for(NX)), dim3(256), 0, st, xoff, NI, NX,
+                           ika, tpoly, dex, diff, mm, sid, fill, mem_ids);
+    if (NT)
+        hipLaunchKernelGGL(k_piece_emit, dim3(grid_for(NT)), dim3(256), 0, st, E, NT, dex, diff,
+                           segc, mm, sid, B.xbits, B.seg_x0, B.seg_x1, B.seg_code, seg_row,
+                           multi_seg, multi_mem, mem_ids);
+    hipLaunchKernelGGL(k_seg_row_off, dim3(grid_for(gh + 1)), dim3(256), 0, st, seg_row, NS, gh,
+                       cs);
+    HIP_OK(hipGetLastError());
+    B.seg_row_off = cs;
+    for (void *p : {(void *)tkey, (void *)tpoly, (void *)E, (void *)ika, (void *)xoff,
+                    (void *)diff, (void *)dex, (void *)segc, (void *)mm, (void *)seg_row,
+                    (void *)sid, (void *)fill})
+        B.release(p);
+
+    // 5: deduplicate the sets of multi-polygon segments
     h->n_sets = 0;
     h->n_set_ids = 0;
     if (NM > 0) {

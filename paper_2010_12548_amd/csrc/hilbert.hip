@@ -29,7 +29,7 @@ __device__ __forceinline__ int64_t ub_i64(const int64_t *a, int64_t n, int64_t v
 }
 
 // cells of boundary interval t (relative to the stored box, which is also
-// the origin of the Hilbert key grid)
+// the origin of the Hilbert key grid); event keys are (polygon, row, x)
 __global__ void k_bcell_counts(const uint64_t *evkey, int64_t nb, int xbits, int64_t *cnt)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -38,14 +38,14 @@ __global__ void k_bcell_counts(const uint64_t *evkey, int64_t nb, int xbits, int
     cnt[t] = (int64_t)(evkey[2 * t + 1] & xm) - (int64_t)(evkey[2 * t] & xm);
 }
 
-__global__ void k_bcell_keys(const uint64_t *evkey, int64_t nb, int xbits, const int64_t *off,
-                             int64_t ncells, int L, uint64_t *keys)
+__global__ void k_bcell_keys(const uint64_t *evkey, int64_t nb, int xbits, int rbits,
+                             const int64_t *off, int64_t ncells, int L, uint64_t *keys)
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncells) return;
     int64_t t = ub_i64(off, nb, c) - 1;
     uint64_t xm = (1ull << xbits) - 1;
-    uint32_t j = (uint32_t)(evkey[2 * t] >> xbits);
+    uint32_t j = (uint32_t)((evkey[2 * t] >> xbits) & ((1ull << rbits) - 1));
     uint32_t i = (uint32_t)((evkey[2 * t] & xm) + (uint64_t)(c - off[t]));
     keys[c] = hilbert_index(L, i, j);
 }
@@ -100,7 +100,7 @@ static int hilbert_boundary_cells(BuildState &B, sba_handle *h, hipStream_t st)
     RC(B.alloc(&keys, nc));
     if (ncb)
         hipLaunchKernelGGL(k_bcell_keys, dim3(grid_for(ncb)), dim3(256), 0, st, B.evkey, NB, B.xbits,
-                           cnt, ncb, h->level, keys);
+                           B.rbits, cnt, ncb, h->level, keys);
     if (nborder)
         hipLaunchKernelGGL(k_border_keys, dim3(grid_for(nborder)), dim3(256), 0, st, h->gw, h->gh,
                            h->level, keys + ncb);
