@@ -80,6 +80,9 @@ typedef struct {
     int32_t win_x0, win_y0, win_x1, win_y1;  /* clip window [x0,x1) x [y0,y1), coordinates;
                              cells outside it are empty in the handle (for viewport
                              queries: the answer inside the window is unchanged)         */
+    int32_t sub_log2;     /* grid: sub-tile side 2^sub_log2 cells inside mixed tiles,
+                             2..tile_log2; == tile_log2: mixed tiles are stored cell by
+                             cell (0 -> 4 for tiles of 64 cells or more, else tile_log2) */
 } sba_build_opts;
 
 typedef struct {
@@ -91,7 +94,7 @@ typedef struct {
     int64_t eps, s;         /* distance bound and cell side */
     int64_t gi0, gj0;       /* first cell of the stored box (grid) */
     int64_t gw, gh;         /* stored box size in cells */
-    int64_t n_tiles, n_blocks;  /* grid: directory entries, mixed (fine) tiles */
+    int64_t n_tiles, n_blocks;  /* grid: directory entries, mixed tiles */
     int64_t n_sets, n_set_ids;  /* multi-polygon cell sets */
     int64_t n_segments;     /* row segments of constant polygon set (build intermediate) */
     int64_t n_boundary;     /* (edge, row strip) boundary intervals */
@@ -100,6 +103,9 @@ typedef struct {
     double  mean_leaf_err;  /* learned index: mean stored error over the leaves */
     int64_t bytes;          /* device bytes held by the handle */
     double  build_ms;       /* wall time of the build, host clock (includes its syncs) */
+    int64_t n_sub;          /* grid: mixed sub-tiles (stored cell by cell) */
+    int32_t sub_log2;       /* grid: sub-tile side log2 (== tile_log2: no sub level) */
+    int32_t compact;        /* grid: 1 = 16-bit codes (directory staged in LDS), 0 = 32-bit */
 } sba_info_t;
 
 /*

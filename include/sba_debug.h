@@ -26,8 +26,9 @@ void sba_debug_hilbert_cell(int L, uint64_t d, uint32_t *i, uint32_t *j);
  * Process-wide; for launch-shape sweeps. */
 int sba_debug_set_blocks_per_cu(int k);
 
-/* 1: grid probes read the 32-bit directory from global memory even where the
- * handle also holds the 16-bit LDS-staged copy (comparison runs); 0: default. */
+/* 1: grid builds store the 32-bit format (directory read from global memory
+ * by the probes) even where the 16-bit LDS-staged format would fit
+ * (comparison runs); 0: default.  Process-wide, read at build time. */
 int sba_debug_force_wide_grid(int on);
 
 #ifdef __cplusplus

@@ -43,7 +43,8 @@ class _Polys(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("search", C.c_int32), ("log2_leaves", C.c_int32),
                 ("tile_log2", C.c_int32), ("use_window", C.c_int32), ("win_x0", C.c_int32),
-                ("win_y0", C.c_int32), ("win_x1", C.c_int32), ("win_y1", C.c_int32)]
+                ("win_y0", C.c_int32), ("win_x1", C.c_int32), ("win_y1", C.c_int32),
+                ("sub_log2", C.c_int32)]
 
 
 class _Task(C.Structure):
@@ -61,7 +62,8 @@ class _Info(C.Structure):
                 ("n_blocks", C.c_int64), ("n_sets", C.c_int64), ("n_set_ids", C.c_int64),
                 ("n_segments", C.c_int64), ("n_boundary", C.c_int64), ("n_runs", C.c_int64),
                 ("max_leaf_err", C.c_int64), ("mean_leaf_err", C.c_double), ("bytes", C.c_int64),
-                ("build_ms", C.c_double)]
+                ("build_ms", C.c_double), ("n_sub", C.c_int64), ("sub_log2", C.c_int32),
+                ("compact", C.c_int32)]
 
 
 def library_path() -> str:
@@ -172,7 +174,7 @@ class Approx:
 
     def __init__(self, ring_off, vert_off, xy, eps: int, kind: str = "grid",
                  search: str = "binary", log2_leaves: int = 16, tile_log2: int = 0,
-                 window=None, device: str = "cuda", stream=None):
+                 window=None, device: str = "cuda", stream=None, sub_log2: int = 0):
         torch = _torch()
         self._h = C.c_void_p(None)
         self.device = torch.device(device)
@@ -184,7 +186,7 @@ class Approx:
         win = (0, 0, 0, 0, 0) if window is None else (1, *[int(v) for v in window])
         opts = _Opts({"grid": KIND_GRID, "hilbert": KIND_HILBERT}[kind],
                      {"binary": SEARCH_BINARY, "learned": SEARCH_LEARNED}[search],
-                     int(log2_leaves), int(tile_log2), *win)
+                     int(log2_leaves), int(tile_log2), *win, int(sub_log2))
         h = C.c_void_p(None)
         with torch.cuda.device(self.device):
             rc = lib().sba_build_approx(C.byref(polys), int(eps), C.byref(opts),

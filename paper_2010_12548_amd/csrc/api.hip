@@ -9,7 +9,7 @@
 // work still reads the handle).
 static void handle_release(sba_handle *h)
 {
-    void *arrs[] = {h->dir, h->blocks, h->dir16, h->blocks16, h->set_off, h->set_ids, h->starts,
+    void *arrs[] = {h->dir, h->sub, h->blocks, h->dir16, h->blocks16, h->set_off, h->set_ids, h->starts,
                     h->starts32, h->run_code, h->leaves, h->leaf_lo};
     for (void *p : arrs) tmp_free(p, nullptr);
 }
@@ -151,6 +151,9 @@ extern "C" int sba_info(const sba_handle *h, sba_info_t *info)
     o.gh = h->gh;
     o.n_tiles = h->tw * h->th;
     o.n_blocks = h->n_blocks;
+    o.n_sub = h->n_sub;
+    o.sub_log2 = h->sub_log2;
+    o.compact = h->compact ? 1 : 0;
     o.n_sets = h->n_sets;
     o.n_set_ids = h->n_set_ids;
     o.n_segments = h->n_segments;

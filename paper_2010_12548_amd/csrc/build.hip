@@ -488,22 +488,57 @@ __global__ void k_lookup_ij(const int64_t *seg_row_off, const int32_t *seg_x0, c
 }
 
 // ------------------------------------------------ tiled grid
+//
+// The grid is stored in up to three levels: a directory of tiles of 2^tl
+// cells a side, for mixed tiles a sub-directory of sub-tiles of 2^sl cells a
+// side (sl < tl), and for mixed sub-tiles (or mixed tiles when sl == tl) a
+// fine block of one code per cell.  A uniform square stores its code once.
 
-// one wavefront per tile: uniform code, or mixed
-__global__ void k_tile_classify(const int64_t *seg_row_off, const int32_t *seg_x0,
-                                const int32_t *seg_x1, const uint32_t *seg_code, int64_t gw,
-                                int64_t gh, int tl, int64_t tw, int64_t n_tiles, uint32_t *dir,
-                                int64_t *mixed)
+// 16-bit short code of a cell code: 0 none, p+1 polygon p, np+1+k set k
+__device__ __forceinline__ uint32_t short_code(uint32_t c, uint32_t np)
 {
-    int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    int lane = threadIdx.x & 63;
-    if (tile >= n_tiles) return;
-    int64_t ti = tile % tw, tj = tile / tw;
-    int32_t x0 = (int32_t)(ti << tl);
-    int32_t x1 = (int32_t)min((int64_t)x0 + (1 << tl), gw);
-    int64_t r0 = tj << tl, r1 = min(r0 + (1 << tl), gh);
+    return c < CODE_SET_BASE ? c : np + 1 + (c - CODE_SET_BASE);
+}
+
+// origin (first column, first row) of square u: a tile (mt == NULL), or
+// sub-tile u % Q of mixed tile mt[u / Q]
+__device__ __forceinline__ void square_origin(int64_t u, const int64_t *mt, int tl, int sl,
+                                              int64_t tw, int32_t *x0, int64_t *r0)
+{
+    if (!mt) {
+        *x0 = (int32_t)((u % tw) << tl);
+        *r0 = (u / tw) << tl;
+        return;
+    }
+    const int qs = tl - sl;  // sub-tiles per tile side: 2^qs
+    int64_t q = u & (((int64_t)1 << (2 * qs)) - 1);
+    int64_t tile = mt[u >> (2 * qs)];
+    *x0 = (int32_t)(((tile % tw) << tl) + ((q & (((int64_t)1 << qs) - 1)) << sl));
+    *r0 = ((tile / tw) << tl) + ((q >> qs) << sl);
+}
+
+// G lanes per square (G = min(side, 64)): uniform code of the square, or
+// 0xffffffff and mixed[u] = 1
+template <int G>
+__global__ void k_square_classify(const int64_t *seg_row_off, const int32_t *seg_x0,
+                                  const int32_t *seg_x1, const uint32_t *seg_code, int64_t gw,
+                                  int64_t gh, const int64_t *mt, int tl, int sl, int64_t tw,
+                                  int64_t n_sq, uint32_t *code, int64_t *mixed)
+{
+    int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    int lane = threadIdx.x & (G - 1);
+    if (u >= n_sq) return;  // whole groups leave together (G divides the block)
+    const int side_log2 = mt ? sl : tl;
+    int32_t x0;
+    int64_t r0;
+    square_origin(u, mt, tl, sl, tw, &x0, &r0);
+    int32_t x1 = (int32_t)min((int64_t)x0 + (1 << side_log2), gw);
+    int64_t r1 = min(r0 + (1 << side_log2), gh);
     uint32_t lo_c = 0xffffffffu, hi_c = 0;
-    for (int64_t r = r0 + lane; r < r1; r += 64) {
+    if (x0 >= gw || r0 >= gh) {  // square wholly outside the stored box
+        lo_c = hi_c = 0;
+    }
+    for (int64_t r = r0 + lane; r < r1 && x0 < gw; r += G) {
         int64_t a = seg_row_off[r], lo = a, hi = seg_row_off[r + 1], e = hi;
         while (lo < hi) {
             int64_t mid = (lo + hi) >> 1;
@@ -518,79 +553,88 @@ __global__ void k_tile_classify(const int64_t *seg_row_off, const int32_t *seg_x
         lo_c = min(lo_c, c);
         hi_c = max(hi_c, c);
     }
-    for (int o = 32; o > 0; o >>= 1) {
+    // a square cut by the edge of the box is uniform only if its stored part
+    // is; cells beyond the box read as 0 through the probe's range test
+    for (int o = G / 2; o > 0; o >>= 1) {
         lo_c = min(lo_c, (uint32_t)__shfl_xor((int)lo_c, o, 64));
         hi_c = max(hi_c, (uint32_t)__shfl_xor((int)hi_c, o, 64));
     }
     if (lane == 0) {
         bool uni = (lo_c == hi_c) && (hi_c != 0xffffffffu);
-        dir[tile] = uni ? hi_c : 0xffffffffu;
-        mixed[tile] = uni ? 0 : 1;
+        code[u] = uni ? hi_c : 0xffffffffu;
+        mixed[u] = uni ? 0 : 1;
     }
 }
 
-// one block per tile; mixed tiles write their fine block (one wavefront per
-// row: one binary search for the first cell, then a walk along the row's
-// segments), all tiles their final directory entry
-__global__ __launch_bounds__(256) void k_tile_fill(const int64_t *seg_row_off, const int32_t *seg_x0,
-                                                   const int32_t *seg_x1, const uint32_t *seg_code,
-                                                   int64_t gw, int64_t gh, int tl, int64_t tw,
-                                                   uint32_t *dir, const int64_t *blk,
-                                                   uint32_t *blocks)
+// list[pos[u]] = u for every flagged u (pos = exclusive scan of the flags)
+__global__ void k_flag_list(const int64_t *pos, int64_t n, int64_t total, int64_t *list)
 {
-    int64_t tile = blockIdx.x;
-    uint32_t d = dir[tile];
-    if (d != 0xffffffffu) return;
-    int64_t b = blk[tile];
-    int64_t ti = tile % tw, tj = tile / tw;
-    const int T = 1 << tl;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint32_t *out = blocks + (b << (2 * tl));
-    const int32_t x0 = (int32_t)(ti << tl);
-    for (int row = w; row < T; row += 4) {
-        int64_t r = (tj << tl) + row;
-        uint32_t *orow = out + ((int64_t)row << tl);
-        if (r >= gh) {
-            for (int cx = lane; cx < T; cx += 64) orow[cx] = 0;
-            continue;
-        }
-        const int64_t lo = seg_row_off[r], hi = seg_row_off[r + 1];
-        int64_t k;
-        {
-            int32_t x = x0 + lane;
-            int64_t a = lo, e = hi;
-            while (a < e) {
-                int64_t mid = (a + e) >> 1;
-                if (seg_x0[mid] <= x) a = mid + 1; else e = mid;
-            }
-            k = a - 1;  // last segment starting at or before x (lo-1 if none)
-        }
-        for (int cx = lane; cx < T; cx += 64) {
-            int32_t x = x0 + cx;
-            while (k + 1 < hi && seg_x0[k + 1] <= x) k++;
-            uint32_t c = 0;
-            if (x < gw && k >= lo && x < seg_x1[k]) c = seg_code[k];
-            orow[cx] = c;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) dir[tile] = TILE_MIXED | (uint32_t)b;
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    int64_t o = pos[u], o1 = u + 1 < n ? pos[u + 1] : total;
+    if (o1 != o) list[o] = u;
 }
 
-// 32-bit codes / directory entries -> 16-bit ones (see build_grid)
-__global__ void k_compact16(const uint32_t *in, int64_t n, int64_t n_pad, uint32_t np, bool is_dir,
-                            uint16_t *out)
+// Fine blocks: one thread per (block, row, run of up to 16 cells): one
+// binary search for the run's first cell, then a walk along the row's
+// segments.  Block k holds square sq[k] of side 2^side_log2 (sq indexes the
+// squares of k_square_classify).  OUT = uint32_t full codes or uint16_t
+// short codes.
+template <typename OUT>
+__global__ void k_block_fill(const int64_t *seg_row_off, const int32_t *seg_x0,
+                             const int32_t *seg_x1, const uint32_t *seg_code, int64_t gw,
+                             int64_t gh, const int64_t *sq, int64_t nblk, const int64_t *mt,
+                             int tl, int sl, int64_t tw, int side_log2, uint32_t np, OUT *blocks)
 {
+    const int side = 1 << side_log2;
+    const int runs = side > 16 ? side >> 4 : 1;
+    const int rlen = side > 16 ? 16 : side;
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_pad) return;
-    if (t >= n) { out[t] = 0; return; }
-    uint32_t c = in[t];
-    uint32_t v;
-    if (is_dir && (c & TILE_MIXED)) v = 0x8000u | (c & ~TILE_MIXED);
-    else if (c == 0) v = 0;
-    else if (c < CODE_SET_BASE) v = c;                       // polygon c-1 -> c
-    else v = np + 1 + (c - CODE_SET_BASE);                   // set k -> np+1+k
-    out[t] = (uint16_t)v;
+    if (t >= nblk * side * runs) return;
+    int64_t k = t / ((int64_t)side * runs);
+    int rem = (int)(t - k * side * runs);
+    int row = rem / runs, run = rem - row * runs;
+    int32_t x0;
+    int64_t r0;
+    square_origin(sq[k], mt, tl, sl, tw, &x0, &r0);
+    OUT *out = blocks + (k << (2 * side_log2)) + ((int64_t)row << side_log2) + run * rlen;
+    int64_t r = r0 + row;
+    int32_t xa = x0 + run * rlen;
+    if (r >= gh) {
+        for (int c = 0; c < rlen; c++) out[c] = 0;
+        return;
+    }
+    const int64_t lo = seg_row_off[r], hi = seg_row_off[r + 1];
+    int64_t a = lo, e = hi;
+    while (a < e) {
+        int64_t mid = (a + e) >> 1;
+        if (seg_x0[mid] <= xa) a = mid + 1; else e = mid;
+    }
+    int64_t q = a - 1;  // last segment starting at or before xa (lo-1 if none)
+    for (int c = 0; c < rlen; c++) {
+        int32_t x = xa + c;
+        while (q + 1 < hi && seg_x0[q + 1] <= x) q++;
+        uint32_t v = 0;
+        if (x < gw && q >= lo && x < seg_x1[q]) v = seg_code[q];
+        out[c] = sizeof(OUT) == 2 ? (OUT)short_code(v, np) : (OUT)v;
+    }
+}
+
+// final directory / sub-directory entries: the square's code (short codes
+// in the compact format), or TILE_MIXED | index of its fine block or
+// sub-directory.  Compact directory entries are 16-bit: 0x8000 | index.
+__global__ void k_entries(const uint32_t *code, const int64_t *pos, int64_t n, int64_t n_pad,
+                          uint32_t np, int mode, uint32_t *out32, uint16_t *out16)
+{
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n_pad) return;
+    if (u >= n) { out16[u] = 0; return; }  // padding exists only in mode 2
+    uint32_t c = code[u];
+    bool mixed = c == 0xffffffffu;
+    uint32_t idx = (uint32_t)pos[u];
+    if (mode == 0) out32[u] = mixed ? (TILE_MIXED | idx) : c;                   // wide
+    else if (mode == 1) out32[u] = mixed ? (TILE_MIXED | idx) : short_code(c, np);  // compact sub
+    else out16[u] = (uint16_t)(mixed ? (0x8000u | idx) : short_code(c, np));   // compact dir
 }
 
 // ---------------------------------------------------------------- host side
@@ -913,7 +957,31 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     return 0;
 }
 
-int build_grid(sba_handle *h, BuildState &B, int tile_log2, hipStream_t st)
+// debug switch: store the grid in the 32-bit format even where the compact
+// one would fit
+bool g_build_wide = false;
+
+template <int G>
+static void launch_classify(const BuildState &B, const sba_handle *h, const int64_t *mt, int tl,
+                            int sl, int64_t n_sq, uint32_t *code, int64_t *mixed, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_square_classify<G>, dim3(grid_for(n_sq * G)), dim3(256), 0, st,
+                       B.seg_row_off, B.seg_x0, B.seg_x1, B.seg_code, h->gw, h->gh, mt, tl, sl,
+                       h->tw, n_sq, code, mixed);
+}
+
+static void classify(const BuildState &B, const sba_handle *h, const int64_t *mt, int tl, int sl,
+                     int64_t n_sq, uint32_t *code, int64_t *mixed, hipStream_t st)
+{
+    int side_log2 = mt ? sl : tl;
+    if (side_log2 >= 6) launch_classify<64>(B, h, mt, tl, sl, n_sq, code, mixed, st);
+    else if (side_log2 == 5) launch_classify<32>(B, h, mt, tl, sl, n_sq, code, mixed, st);
+    else if (side_log2 == 4) launch_classify<16>(B, h, mt, tl, sl, n_sq, code, mixed, st);
+    else if (side_log2 == 3) launch_classify<8>(B, h, mt, tl, sl, n_sq, code, mixed, st);
+    else launch_classify<4>(B, h, mt, tl, sl, n_sq, code, mixed, st);
+}
+
+int build_grid(sba_handle *h, BuildState &B, int tile_log2, int sub_log2, hipStream_t st)
 {
     int tl = tile_log2;
     if (tl == 0) {  // smallest tile whose 16-bit directory fits 64 KB of LDS
@@ -923,46 +991,120 @@ int build_grid(sba_handle *h, BuildState &B, int tile_log2, hipStream_t st)
             tl++;
     }
     if (tl < 2 || tl > 10) return SBA_EINVAL;
+    int sl = sub_log2 ? sub_log2 : (tl >= 6 ? 4 : tl);  // sub-tiles of 16 x 16 under big tiles
+    if (sl < 2 || sl > tl) return SBA_EINVAL;
     h->tile_log2 = tl;
+    h->sub_log2 = sl;
     h->tw = (h->gw + (1 << tl) - 1) >> tl;
     h->th = (h->gh + (1 << tl) - 1) >> tl;
     const int64_t nt = h->tw * h->th;
     if (nt >= ((int64_t)1 << 31)) return SBA_ELIMIT;
-    RC(tmp_alloc(&h->dir, nt, st));
-    h->bytes += nt * 4;
-    int64_t *mixed = nullptr, *tot = nullptr;
-    RC(B.alloc(&mixed, nt + 1));
-    RC(B.alloc(&tot, 1));
-    hipLaunchKernelGGL(k_tile_classify, dim3(grid_for(nt * 64)), dim3(256), 0, st, B.seg_row_off,
-                       B.seg_x0, B.seg_x1, B.seg_code, h->gw, h->gh, tl, h->tw, nt, h->dir, mixed);
+    const uint32_t np = (uint32_t)h->n_polys;
+    uint32_t *tcode = nullptr;
+    int64_t *tpos = nullptr, *tot = nullptr;
+    RC(B.alloc(&tcode, nt));
+    RC(B.alloc(&tpos, nt + 1));
+    RC(B.alloc(&tot, 2));
+    classify(B, h, nullptr, tl, sl, nt, tcode, tpos, st);
     HIP_OK(hipGetLastError());
-    RC(scan_exclusive_i64(mixed, mixed, nt, tot, st));
+    RC(scan_exclusive_i64(tpos, tpos, nt, tot, st));
     int64_t nblk = 0;
     HIP_OK(hipMemcpyAsync(&nblk, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     if (nblk >= (int64_t)TILE_MIXED) return SBA_ELIMIT;
     h->n_blocks = nblk;
-    RC(tmp_alloc(&h->blocks, nblk << (2 * tl), st));
-    h->bytes += (nblk << (2 * tl)) * 4;
-    hipLaunchKernelGGL(k_tile_fill, dim3((unsigned)nt), dim3(256), 0, st, B.seg_row_off, B.seg_x0,
-                       B.seg_x1, B.seg_code, h->gw, h->gh, tl, h->tw, h->dir, mixed, h->blocks);
-    HIP_OK(hipGetLastError());
-    // 16-bit copy for the streaming probe, whose workgroups keep the whole
-    // directory in LDS: entries < 0x8000 are short codes (0 none, p+1 polygon
-    // p, n_polys+1+k set k), 0x8000|b is fine block b
-    if ((int64_t)h->n_polys + h->n_sets < 0x8000 && nblk < 0x8000 && nt <= COMPACT_DIR_TILES_MAX) {
+    const bool compact = !g_build_wide && (int64_t)np + h->n_sets < 0x8000 && nblk < 0x8000 &&
+                         nt <= COMPACT_DIR_TILES_MAX;
+    h->compact = compact;
+
+    // directory
+    if (compact) {
         const int64_t nt16 = (nt + 7) & ~(int64_t)7;  // LDS copies move 16 bytes at a time
         RC(tmp_alloc(&h->dir16, nt16, st));
-        RC(tmp_alloc(&h->blocks16, std::max<int64_t>(nblk << (2 * tl), 1), st));
-        h->bytes += nt16 * 2 + (nblk << (2 * tl)) * 2;
-        hipLaunchKernelGGL(k_compact16, dim3(grid_for(nt16)), dim3(256), 0, st, h->dir, nt, nt16,
-                           (uint32_t)h->n_polys, true, h->dir16);
-        if (nblk)
-            hipLaunchKernelGGL(k_compact16, dim3(grid_for(nblk << (2 * tl))), dim3(256), 0, st,
-                               h->blocks, nblk << (2 * tl), nblk << (2 * tl), (uint32_t)h->n_polys,
-                               false, h->blocks16);
-        HIP_OK(hipGetLastError());
+        h->bytes += nt16 * 2;
+        hipLaunchKernelGGL(k_entries, dim3(grid_for(nt16)), dim3(256), 0, st, tcode, tpos, nt, nt16,
+                           np, 2, (uint32_t *)nullptr, h->dir16);
+    } else {
+        RC(tmp_alloc(&h->dir, nt, st));
+        h->bytes += nt * 4;
+        hipLaunchKernelGGL(k_entries, dim3(grid_for(nt)), dim3(256), 0, st, tcode, tpos, nt, nt, np,
+                           0, h->dir, (uint16_t *)nullptr);
     }
+    HIP_OK(hipGetLastError());
+    if (nblk == 0) {
+        // one-element placeholders: the batched lookups read element 0 of
+        // the lower levels for points that need nothing from them
+        if (sl < tl) {
+            RC(tmp_alloc(&h->sub, 1, st));
+            HIP_OK(hipMemsetAsync(h->sub, 0, 4, st));
+        }
+        if (compact) {
+            RC(tmp_alloc(&h->blocks16, 1, st));
+            HIP_OK(hipMemsetAsync(h->blocks16, 0, 2, st));
+        } else {
+            RC(tmp_alloc(&h->blocks, 1, st));
+            HIP_OK(hipMemsetAsync(h->blocks, 0, 4, st));
+        }
+        return 0;
+    }
+    int64_t *mt = nullptr;  // mixed tiles in order
+    RC(B.alloc(&mt, nblk));
+    hipLaunchKernelGGL(k_flag_list, dim3(grid_for(nt)), dim3(256), 0, st, tpos, nt, nblk, mt);
+    HIP_OK(hipGetLastError());
+
+    // sub-directories of the mixed tiles
+    const int64_t *fine_sq = mt;        // squares stored as fine blocks
+    const int64_t *fine_mt = nullptr;   // their tile list (sub-tiles) or NULL (tiles)
+    int64_t nfine = nblk;
+    int fine_log2 = tl;
+    if (sl < tl) {
+        const int64_t nq = nblk << (2 * (tl - sl));
+        uint32_t *scode = nullptr;
+        int64_t *spos = nullptr, *ms = nullptr;
+        RC(B.alloc(&scode, nq));
+        RC(B.alloc(&spos, nq + 1));
+        classify(B, h, mt, tl, sl, nq, scode, spos, st);
+        HIP_OK(hipGetLastError());
+        RC(scan_exclusive_i64(spos, spos, nq, tot + 1, st));
+        int64_t nsub = 0;
+        HIP_OK(hipMemcpyAsync(&nsub, tot + 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        if (nsub >= (int64_t)TILE_MIXED) return SBA_ELIMIT;
+        h->n_sub = nsub;
+        RC(tmp_alloc(&h->sub, nq, st));
+        h->bytes += nq * 4;
+        hipLaunchKernelGGL(k_entries, dim3(grid_for(nq)), dim3(256), 0, st, scode, spos, nq, nq, np,
+                           compact ? 1 : 0, h->sub, (uint16_t *)nullptr);
+        HIP_OK(hipGetLastError());
+        RC(B.alloc(&ms, std::max<int64_t>(nsub, 1)));
+        hipLaunchKernelGGL(k_flag_list, dim3(grid_for(nq)), dim3(256), 0, st, spos, nq, nsub, ms);
+        HIP_OK(hipGetLastError());
+        fine_sq = ms;
+        fine_mt = mt;
+        nfine = nsub;
+        fine_log2 = sl;
+    }
+
+    // fine blocks
+    const int64_t cells = nfine << (2 * fine_log2);
+    const int side = 1 << fine_log2;
+    const int64_t threads = nfine * side * (side > 16 ? side >> 4 : 1);
+    if (compact) {
+        RC(tmp_alloc(&h->blocks16, std::max<int64_t>(cells, 1), st));
+        h->bytes += cells * 2;
+        if (nfine)
+            hipLaunchKernelGGL(k_block_fill<uint16_t>, dim3(grid_for(threads)), dim3(256), 0, st,
+                               B.seg_row_off, B.seg_x0, B.seg_x1, B.seg_code, h->gw, h->gh, fine_sq,
+                               nfine, fine_mt, tl, sl, h->tw, fine_log2, np, h->blocks16);
+    } else {
+        RC(tmp_alloc(&h->blocks, std::max<int64_t>(cells, 1), st));
+        h->bytes += cells * 4;
+        if (nfine)
+            hipLaunchKernelGGL(k_block_fill<uint32_t>, dim3(grid_for(threads)), dim3(256), 0, st,
+                               B.seg_row_off, B.seg_x0, B.seg_x1, B.seg_code, h->gw, h->gh, fine_sq,
+                               nfine, fine_mt, tl, sl, h->tw, fine_log2, np, h->blocks);
+    }
+    HIP_OK(hipGetLastError());
     return 0;
 }
 
@@ -980,7 +1122,7 @@ int build_handle(const sba_polygons *polys, int64_t eps, const sba_build_opts *o
                  hipStream_t st, sba_handle *h)
 {
     auto t0 = std::chrono::steady_clock::now();
-    sba_build_opts o = {SBA_KIND_GRID, SBA_SEARCH_BINARY, 16, 0, 0, 0, 0, 0, 0};
+    sba_build_opts o = {SBA_KIND_GRID, SBA_SEARCH_BINARY, 16, 0, 0, 0, 0, 0, 0, 0};
     if (opts) o = *opts;
     if (o.use_window && (o.win_x1 <= o.win_x0 || o.win_y1 <= o.win_y0)) return SBA_EINVAL;
     if (o.log2_leaves == 0) o.log2_leaves = 16;
@@ -1020,7 +1162,7 @@ int build_handle(const sba_polygons *polys, int64_t eps, const sba_build_opts *o
         return 0;
     }
     if (h->kind == SBA_KIND_GRID) {
-        RC(build_grid(h, B, o.tile_log2, st));
+        RC(build_grid(h, B, o.tile_log2, o.sub_log2, st));
     } else {
         RC(hilbert_finish(B, h, o, st));
     }

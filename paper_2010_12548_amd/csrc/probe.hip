@@ -29,11 +29,17 @@ struct GridView {
     uint32_t extx, exty;   // box extent in coordinate units (< 2^31)
     uint32_t mag;
     int32_t shift;
-    int32_t tl;
+    int32_t tl, sl;        // tile and sub-tile side log2 (sl == tl: no sub level)
     uint32_t tw;
-    uint32_t nblocks;
+    uint32_t nblocks;      // mixed tiles
+    uint32_t nfine;        // fine blocks
+    uint32_t np;           // compact format: short codes above np are sets
+    int32_t compact;       // 1: dir16 / sub / blocks16, 0: dir / sub / blocks
     const uint32_t *dir;
+    const uint16_t *dir16;
+    const uint32_t *sub;
     const uint32_t *blocks;
+    const uint16_t *blocks16;
 };
 
 struct HilbView {
@@ -52,20 +58,46 @@ struct HilbView {
     const int32_t *leaf_lo;
 };
 
+// short code (compact format) -> cell code
+__device__ __forceinline__ uint32_t full_code(uint32_t sc, uint32_t np)
+{
+    return sc <= np ? sc : CODE_SET_BASE + (sc - np - 1);
+}
+
 __device__ __forceinline__ uint32_t grid_code(const GridView &g, int32_t x, int32_t y)
 {
     int64_t dx = (int64_t)x - g.ox, dy = (int64_t)y - g.oy;
     if ((uint64_t)dx >= g.extx || (uint64_t)dy >= g.exty) return 0;
     uint32_t i = divmagic((uint32_t)dx, g.mag, g.shift);
     uint32_t j = divmagic((uint32_t)dy, g.mag, g.shift);
-    uint32_t e = g.dir[(uint64_t)(j >> g.tl) * g.tw + (i >> g.tl)];
-    if (e & TILE_MIXED) {
-        uint32_t b = e & ~TILE_MIXED;
-        if (b >= g.nblocks) return 0;  // never taken for a well-formed handle
-        uint32_t m = (1u << g.tl) - 1u;
-        e = g.blocks[((uint64_t)b << (2 * g.tl)) + ((j & m) << g.tl) + (i & m)];
+    uint32_t ti = (j >> g.tl) * g.tw + (i >> g.tl);
+    uint32_t e, b;
+    bool mixed;
+    if (g.compact) {
+        e = g.dir16[ti];
+        mixed = (e & 0x8000u) != 0;
+        b = e & 0x7fffu;
+    } else {
+        e = g.dir[ti];
+        mixed = (e & TILE_MIXED) != 0;
+        b = e & ~TILE_MIXED;
     }
-    return e;
+    if (!mixed) return g.compact ? full_code(e, g.np) : e;
+    if (b >= g.nblocks) return 0;  // never taken for a well-formed handle
+    int fl = g.tl;
+    if (g.sl < g.tl) {
+        const int qs = g.tl - g.sl;
+        const uint32_t mq = (1u << qs) - 1u;
+        uint32_t se = g.sub[((uint64_t)b << (2 * qs)) + ((((j >> g.sl) & mq) << qs) |
+                                                           ((i >> g.sl) & mq))];
+        if (!(se & TILE_MIXED)) return g.compact ? full_code(se, g.np) : se;
+        b = se & ~TILE_MIXED;
+        fl = g.sl;
+    }
+    if (b >= g.nfine) return 0;
+    const uint32_t m = (1u << fl) - 1u;
+    uint64_t idx = ((uint64_t)b << (2 * fl)) + ((j & m) << fl) + (i & m);
+    return g.compact ? full_code(g.blocks16[idx], g.np) : g.blocks[idx];
 }
 
 // last q with keys[q] <= key; keys[0] == 0 <= key
@@ -134,8 +166,11 @@ __device__ __forceinline__ void grid_codes(const GridView &g, const int32_t *xs,
         for (int k = 0; k < NP; k++) c[k] = 0;
         return;
     }
-    const uint32_t m = (1u << g.tl) - 1u;
-    uint32_t ti[NP], lo[NP];
+    const bool two = g.sl < g.tl;
+    const int qs = g.tl - g.sl;
+    const int fl = two ? g.sl : g.tl;
+    const uint32_t m = (1u << fl) - 1u, mq = (1u << qs) - 1u;
+    uint32_t ti[NP], lo[NP], sq[NP];
     bool ok[NP];
 #pragma unroll
     for (int k = 0; k < NP; k++) {
@@ -144,24 +179,47 @@ __device__ __forceinline__ void grid_codes(const GridView &g, const int32_t *xs,
         uint32_t i = divmagic(ok[k] ? (uint32_t)dx : 0u, g.mag, g.shift);
         uint32_t j = divmagic(ok[k] ? (uint32_t)dy : 0u, g.mag, g.shift);
         ti[k] = (j >> g.tl) * g.tw + (i >> g.tl);
-        lo[k] = ((j & m) << g.tl) | (i & m);
+        lo[k] = ((j & m) << fl) | (i & m);
+        sq[k] = (((j >> g.sl) & mq) << qs) | ((i >> g.sl) & mq);
     }
-    uint32_t e[NP];
+    // level 1: directory entry -> (uniform code | mixed tile b)
+    uint32_t v[NP], b[NP];
+    bool mix[NP];
 #pragma unroll
-    for (int k = 0; k < NP; k++) e[k] = g.dir[ti[k]];
+    for (int k = 0; k < NP; k++) {
+        uint32_t e = g.compact ? (uint32_t)g.dir16[ti[k]] : g.dir[ti[k]];
+        mix[k] = g.compact ? (e & 0x8000u) != 0 : (e & TILE_MIXED) != 0;
+        b[k] = g.compact ? (e & 0x7fffu) : (e & ~TILE_MIXED);
+        mix[k] = mix[k] && b[k] < g.nblocks;
+        v[k] = mix[k] ? 0u : (g.compact ? full_code(e, g.np) : e);
+        if (!ok[k]) { mix[k] = false; v[k] = 0; }
+    }
+    // level 2: sub-directory entry of mixed tiles
+    if (two) {
+        uint32_t se[NP];
+#pragma unroll
+        for (int k = 0; k < NP; k++) se[k] = g.sub[mix[k] ? ((uint64_t)b[k] << (2 * qs)) + sq[k] : 0];
+#pragma unroll
+        for (int k = 0; k < NP; k++) {
+            if (!mix[k]) continue;
+            if (se[k] & TILE_MIXED) {
+                b[k] = se[k] & ~TILE_MIXED;
+                mix[k] = b[k] < g.nfine;
+            } else {
+                v[k] = g.compact ? full_code(se[k], g.np) : se[k];
+                mix[k] = false;
+            }
+        }
+    }
+    // level 3: fine block cell
     uint32_t f[NP];
 #pragma unroll
     for (int k = 0; k < NP; k++) {
-        uint32_t b = e[k] & ~TILE_MIXED;
-        bool fine = (e[k] & TILE_MIXED) && b < g.nblocks;
-        f[k] = g.blocks[fine ? ((uint64_t)b << (2 * g.tl)) + lo[k] : 0];
+        uint64_t idx = mix[k] ? ((uint64_t)b[k] << (2 * fl)) + lo[k] : 0;
+        f[k] = g.compact ? (uint32_t)g.blocks16[idx] : g.blocks[idx];
     }
 #pragma unroll
-    for (int k = 0; k < NP; k++) {
-        uint32_t b = e[k] & ~TILE_MIXED;
-        uint32_t v = (e[k] & TILE_MIXED) ? (b < g.nblocks ? f[k] : 0u) : e[k];
-        c[k] = ok[k] ? v : 0u;
-    }
+    for (int k = 0; k < NP; k++) c[k] = mix[k] ? (g.compact ? full_code(f[k], g.np) : f[k]) : v[k];
 }
 
 // NP predecessor searches in lockstep over keys[lo[k] .. lo[k]+len): the
@@ -558,10 +616,17 @@ static void views(const sba_handle *h, GridView *g, HilbView *hv)
         g->mag = h->mag;
         g->shift = h->shift;
         g->tl = h->tile_log2;
+        g->sl = h->sub_log2;
         g->tw = (uint32_t)h->tw;
         g->nblocks = (uint32_t)h->n_blocks;
+        g->nfine = (uint32_t)(h->sub_log2 < h->tile_log2 ? h->n_sub : h->n_blocks);
+        g->np = (uint32_t)h->n_polys;
+        g->compact = h->compact ? 1 : 0;
         g->dir = h->dir;
+        g->dir16 = h->dir16;
+        g->sub = h->sub;
         g->blocks = h->blocks;
+        g->blocks16 = h->blocks16;
     } else {
         hv->ox = h->gi0 * h->s;
         hv->oy = h->gj0 * h->s;
@@ -583,8 +648,6 @@ static void views(const sba_handle *h, GridView *g, HilbView *hv)
 
 // blocks per CU for the streaming probe
 static int g_blocks_per_cu = 8;
-// force the 32-bit global directory (comparison runs)
-static bool g_force_wide = false;
 
 template <int LAYOUT>
 static int launch_layout(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
@@ -662,10 +725,11 @@ struct Grid16 {
     uint32_t extx, exty;
     uint32_t mag;
     int32_t shift;
-    int32_t tl;
+    int32_t tl, sl;               // tile / sub-tile side log2
     uint32_t tw;
     uint32_t nt16;                // directory entries, a multiple of 8
     const uint16_t *dir16;
+    const uint32_t *sub;          // short code or TILE_MIXED | fine block (SUB kernels)
     const uint16_t *blocks16;
     uint32_t np;                  // short codes: p+1 polygon p, > np set (code - np - 1)
 };
@@ -690,7 +754,33 @@ __device__ __forceinline__ void add_short(uint32_t sc, int64_t v, const Agg &A, 
     }
 }
 
-template <bool VALS>
+// short code of one point (the odd last point, the batched loop's tail)
+template <bool SUB>
+__device__ __forceinline__ uint32_t grid16_code(const Grid16 &g, const uint16_t *ldir, int32_t x,
+                                                int32_t y)
+{
+    int64_t dx = (int64_t)x - g.ox, dy = (int64_t)y - g.oy;
+    if ((uint64_t)dx >= g.extx || (uint64_t)dy >= g.exty) return 0;
+    uint32_t i = divmagic((uint32_t)dx, g.mag, g.shift);
+    uint32_t j = divmagic((uint32_t)dy, g.mag, g.shift);
+    uint32_t e = ldir[(j >> g.tl) * g.tw + (i >> g.tl)];
+    if (!(e & 0x8000u)) return e;
+    uint32_t b = e & 0x7fffu;
+    int fl = g.tl;
+    if (SUB) {
+        const int qs = g.tl - g.sl;
+        const uint32_t mq = (1u << qs) - 1u;
+        uint32_t se = g.sub[((uint64_t)b << (2 * qs)) + ((((j >> g.sl) & mq) << qs) |
+                                                           ((i >> g.sl) & mq))];
+        if (!(se & TILE_MIXED)) return se;
+        b = se & ~TILE_MIXED;
+        fl = g.sl;
+    }
+    const uint32_t m = (1u << fl) - 1u;
+    return g.blocks16[((uint64_t)b << (2 * fl)) + (((j & m) << fl) | (i & m))];
+}
+
+template <bool VALS, bool SUB>
 __global__ __launch_bounds__(GRID16_BLOCK) void k_probe_grid16(const int4 *__restrict__ xy4,
                                                               const longlong2 *__restrict__ v2,
                                                               const int32_t *__restrict__ xy,
@@ -714,7 +804,9 @@ __global__ __launch_bounds__(GRID16_BLOCK) void k_probe_grid16(const int4 *__res
         }
     }
     __syncthreads();
-    const uint32_t m = (1u << g.tl) - 1u;
+    const int qs = g.tl - g.sl;
+    const int fl = SUB ? g.sl : g.tl;
+    const uint32_t m = (1u << fl) - 1u, mq = (1u << qs) - 1u;
     const int64_t npairs = n >> 1;
     const int64_t stride = (int64_t)gridDim.x * GRID16_BLOCK;
     for (int64_t t0 = (int64_t)blockIdx.x * GRID16_BLOCK + threadIdx.x; t0 < npairs;
@@ -733,7 +825,9 @@ __global__ __launch_bounds__(GRID16_BLOCK) void k_probe_grid16(const int4 *__res
                 vv[u] = v2l_t{0, 0};
             }
         }
-        uint32_t e[2 * PROBE_UNROLL], lo[2 * PROBE_UNROLL];
+        // level 1 from LDS; levels 2 and 3 as batched global loads (a point
+        // that needs no load there re-reads element 0, a cache hit)
+        uint32_t e[2 * PROBE_UNROLL], lo[2 * PROBE_UNROLL], sq[2 * PROBE_UNROLL];
         bool ok[2 * PROBE_UNROLL];
 #pragma unroll
         for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
@@ -744,34 +838,45 @@ __global__ __launch_bounds__(GRID16_BLOCK) void k_probe_grid16(const int4 *__res
             uint32_t i = divmagic(ok[k] ? (uint32_t)dx : 0u, g.mag, g.shift);
             uint32_t j = divmagic(ok[k] ? (uint32_t)dy : 0u, g.mag, g.shift);
             e[k] = ldir[(j >> g.tl) * g.tw + (i >> g.tl)];
-            lo[k] = ((j & m) << g.tl) | (i & m);
+            lo[k] = ((j & m) << fl) | (i & m);
+            if (SUB) sq[k] = (((j >> g.sl) & mq) << qs) | ((i >> g.sl) & mq);
+            if (!ok[k]) e[k] = 0;
+        }
+        uint32_t fb[2 * PROBE_UNROLL];  // fine block of the point, or ~0u
+        uint32_t v[2 * PROBE_UNROLL];   // short code when no fine block is needed
+#pragma unroll
+        for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
+            bool mixed = (e[k] & 0x8000u) != 0;
+            fb[k] = mixed ? (e[k] & 0x7fffu) : ~0u;
+            v[k] = mixed ? 0u : e[k];
+        }
+        if (SUB) {
+            uint32_t se[2 * PROBE_UNROLL];
+#pragma unroll
+            for (int k = 0; k < 2 * PROBE_UNROLL; k++)
+                se[k] = g.sub[fb[k] != ~0u ? ((uint64_t)fb[k] << (2 * qs)) + sq[k] : 0];
+#pragma unroll
+            for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
+                if (fb[k] == ~0u) continue;
+                bool mixed = (se[k] & TILE_MIXED) != 0;
+                v[k] = mixed ? 0u : se[k];
+                fb[k] = mixed ? (se[k] & ~TILE_MIXED) : ~0u;
+            }
         }
         uint32_t f[2 * PROBE_UNROLL];
 #pragma unroll
-        for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
-            bool fine = ok[k] && (e[k] & 0x8000u);
-            f[k] = g.blocks16[fine ? ((uint64_t)(e[k] & 0x7fffu) << (2 * g.tl)) + lo[k] : 0];
-        }
+        for (int k = 0; k < 2 * PROBE_UNROLL; k++)
+            f[k] = g.blocks16[fb[k] != ~0u ? ((uint64_t)fb[k] << (2 * fl)) + lo[k] : 0];
 #pragma unroll
         for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
-            uint32_t sc = !ok[k] ? 0u : ((e[k] & 0x8000u) ? f[k] : e[k]);
+            uint32_t sc = fb[k] != ~0u ? f[k] : v[k];
             add_short<VALS>(sc, (k & 1) ? vv[k >> 1].y : vv[k >> 1].x, A, np, lcnt, lsum);
         }
     }
     if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
         int64_t k = n - 1;
-        int32_t x = xy[2 * k], y = xy[2 * k + 1];
-        int64_t dx = (int64_t)x - g.ox, dy = (int64_t)y - g.oy;
-        if ((uint64_t)dx < g.extx && (uint64_t)dy < g.exty) {
-            uint32_t i = divmagic((uint32_t)dx, g.mag, g.shift);
-            uint32_t j = divmagic((uint32_t)dy, g.mag, g.shift);
-            uint32_t ee = ldir[(j >> g.tl) * g.tw + (i >> g.tl)];
-            uint32_t sc = (ee & 0x8000u)
-                              ? g.blocks16[((uint64_t)(ee & 0x7fffu) << (2 * g.tl)) +
-                                           (((j & m) << g.tl) | (i & m))]
-                              : ee;
-            add_short<VALS>(sc, VALS ? vals[k] : 0, A, np, lcnt, lsum);
-        }
+        uint32_t sc = grid16_code<SUB>(g, ldir, xy[2 * k], xy[2 * k + 1]);
+        add_short<VALS>(sc, VALS ? vals[k] : 0, A, np, lcnt, lsum);
     }
     __syncthreads();
     uint32_t *oc = pcnt + (int64_t)blockIdx.x * np;
@@ -780,6 +885,20 @@ __global__ __launch_bounds__(GRID16_BLOCK) void k_probe_grid16(const int4 *__res
         oc[p] = lcnt[p];
         if (VALS) os[p] = lsum[p];
     }
+}
+
+// LDS of the grid probe: histograms (12 B per polygon) + the 16-bit directory
+static size_t grid16_lds(const sba_handle *h)
+{
+    const size_t nt16 = (size_t)(((h->tw * h->th) + 7) & ~(int64_t)7);
+    return (size_t)h->n_polys * 12 + 16 + nt16 * 2;
+}
+#define GRID16_LDS_MAX (160 * 1024)
+
+template <bool SUB>
+static void grid16_kernels(bool vals, const void **k)
+{
+    *k = vals ? (const void *)k_probe_grid16<true, SUB> : (const void *)k_probe_grid16<false, SUB>;
 }
 
 static int launch_grid16(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
@@ -793,15 +912,18 @@ static int launch_grid16(const int32_t *xy, const int64_t *values, int64_t n, co
     g.mag = h->mag;
     g.shift = h->shift;
     g.tl = h->tile_log2;
+    g.sl = h->sub_log2;
     g.tw = (uint32_t)h->tw;
     g.nt16 = (uint32_t)(((h->tw * h->th) + 7) & ~(int64_t)7);
     g.dir16 = h->dir16;
+    g.sub = h->sub;
     g.blocks16 = h->blocks16;
     g.np = (uint32_t)h->n_polys;
     Agg A{h->set_off, h->set_ids, (uint32_t)h->n_polys, (uint32_t)h->n_sets};
     const int32_t np = h->n_polys;
     const bool vals = values != nullptr && sums != nullptr;
-    const size_t lds = (size_t)np * 12 + 16 + (size_t)g.nt16 * 2;
+    const bool sub = h->sub_log2 < h->tile_log2;
+    const size_t lds = grid16_lds(h);
     const int per_cu = lds <= 72 * 1024 ? 2 : 1;
     const int64_t npairs = n >> 1;
     int64_t nb = std::min<int64_t>((npairs + GRID16_BLOCK - 1) / GRID16_BLOCK,
@@ -811,20 +933,28 @@ static int launch_grid16(const int32_t *xy, const int64_t *values, int64_t n, co
     RC(tmp_alloc(&scratch, (int64_t)nb * np * (4 + (vals ? 8 : 0)) + 8, st));
     unsigned long long *psum = (unsigned long long *)scratch;
     uint32_t *pcnt = (uint32_t *)(vals ? scratch + (size_t)nb * np * 8 : scratch);
+    const void *kern = nullptr;
+    if (sub) grid16_kernels<true>(vals, &kern);
+    else grid16_kernels<false>(vals, &kern);
     // dynamic LDS above 64 KB has to be allowed explicitly
-    (void)hipFuncSetAttribute((const void *)k_probe_grid16<true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipFuncSetAttribute((const void *)k_probe_grid16<false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipGetLastError();
-    if (vals)
-        hipLaunchKernelGGL(k_probe_grid16<true>, dim3((unsigned)nb), dim3(GRID16_BLOCK), lds, st,
-                           (const int4 *)xy, (const longlong2 *)values, xy, values, n, g, A, pcnt,
-                           psum);
+    if (sub && vals)
+        hipLaunchKernelGGL((k_probe_grid16<true, true>), dim3((unsigned)nb), dim3(GRID16_BLOCK),
+                           lds, st, (const int4 *)xy, (const longlong2 *)values, xy, values, n, g,
+                           A, pcnt, psum);
+    else if (sub)
+        hipLaunchKernelGGL((k_probe_grid16<false, true>), dim3((unsigned)nb), dim3(GRID16_BLOCK),
+                           lds, st, (const int4 *)xy, (const longlong2 *)values, xy, values, n, g,
+                           A, pcnt, psum);
+    else if (vals)
+        hipLaunchKernelGGL((k_probe_grid16<true, false>), dim3((unsigned)nb), dim3(GRID16_BLOCK),
+                           lds, st, (const int4 *)xy, (const longlong2 *)values, xy, values, n, g,
+                           A, pcnt, psum);
     else
-        hipLaunchKernelGGL(k_probe_grid16<false>, dim3((unsigned)nb), dim3(GRID16_BLOCK), lds, st,
-                           (const int4 *)xy, (const longlong2 *)values, xy, values, n, g, A, pcnt,
-                           psum);
+        hipLaunchKernelGGL((k_probe_grid16<false, false>), dim3((unsigned)nb), dim3(GRID16_BLOCK),
+                           lds, st, (const int4 *)xy, (const longlong2 *)values, xy, values, n, g,
+                           A, pcnt, psum);
     hipError_t e1 = hipGetLastError();
     if (vals)
         hipLaunchKernelGGL(k_reduce<true>, dim3((unsigned)np), dim3(256), 0, st, pcnt, psum, nb, np,
@@ -848,7 +978,8 @@ int probe_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_
         return 0;
     }
     if (h->kind == SBA_KIND_GRID) {
-        if (h->dir16 && !g_force_wide) return launch_grid16(xy, values, n, h, counts, sums, st);
+        if (h->compact && grid16_lds(h) <= GRID16_LDS_MAX)
+            return launch_grid16(xy, values, n, h, counts, sums, st);
         return launch_layout<0>(xy, values, n, h, counts, sums, st);
     }
     if (search == SBA_SEARCH_LEARNED) {
@@ -1114,6 +1245,6 @@ int batch_launch(const sba_task *tasks, int32_t n_tasks, hipStream_t st)
 
 extern "C" int sba_debug_force_wide_grid(int on)
 {
-    g_force_wide = on != 0;
+    g_build_wide = on != 0;
     return 0;
 }

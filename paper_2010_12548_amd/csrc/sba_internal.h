@@ -46,14 +46,25 @@ struct sba_handle {
     // cell index from a coordinate: q = ((uint64)(c - origin) * mag) >> shift
     uint32_t mag;
     int32_t shift;
-    // grid layout
-    int32_t tile_log2;
+    // grid layout: tiles of 2^tile_log2 cells a side; a mixed tile has a
+    // sub-directory of sub-tiles of 2^sub_log2 cells (sub_log2 < tile_log2)
+    // or is itself a fine block (sub_log2 == tile_log2); fine blocks hold one
+    // code per cell.  One of two formats:
+    //   wide     dir, sub, blocks: 32-bit codes, TILE_MIXED | index
+    //   compact  dir16: 16-bit short codes (0 none, p+1 polygon p,
+    //            n_polys+1+k set k) or 0x8000 | index, staged in LDS by the
+    //            probe; sub: 32-bit, short code or TILE_MIXED | index;
+    //            blocks16: 16-bit short codes
+    int32_t tile_log2, sub_log2;
     int64_t tw, th;
-    uint32_t *dir;       // [tw*th]
-    uint32_t *blocks;    // [n_blocks << (2*tile_log2)]
-    int64_t n_blocks;
-    uint16_t *dir16;     // 16-bit directory (LDS-staged by the probe) or NULL
-    uint16_t *blocks16;  // 16-bit fine blocks (with dir16)
+    bool compact;
+    uint32_t *dir;       // wide: [tw*th]
+    uint16_t *dir16;     // compact: [tw*th rounded up to 8]
+    uint32_t *sub;       // [n_blocks << 2*(tile_log2-sub_log2)] when sub_log2 < tile_log2
+    uint32_t *blocks;    // wide: [n_fine << 2*fine_log2]
+    uint16_t *blocks16;  // compact: same shape
+    int64_t n_blocks;    // mixed tiles
+    int64_t n_sub;       // mixed sub-tiles
     // polygon sets of multi-polygon cells
     int64_t *set_off;    // [n_sets+1] (device)
     int32_t *set_ids;    // [n_set_ids] (device)
@@ -274,5 +285,6 @@ int bucket_launch(const int32_t *xy, const int64_t *values, int64_t n, int32_t x
                   hipStream_t st);
 
 // Build entry point (build.hip).
+extern bool g_build_wide;
 int build_handle(const sba_polygons *polys, int64_t eps, const sba_build_opts *opts,
                  hipStream_t st, sba_handle *h);

@@ -269,21 +269,66 @@ def test_city_partition_sampled(sba, orc):
 
 
 @pytest.mark.parametrize("eps", [100, 1000, 10000])
-def test_lds_directory_and_global_directory_agree(sba, orc, eps):
-    """The grid probe with the 16-bit LDS-staged directory and the one with
-    the 32-bit directory in global memory give the oracle's answer."""
+def test_compact_and_wide_formats_agree(sba, orc, eps):
+    """The grid stored with 16-bit codes (directory staged in LDS by the
+    probe) and with 32-bit codes (directory read from global memory) give
+    the oracle's answer and the oracle's cell sets."""
     from gen import city_polygons
     polys = city_polygons()
     xy, vals = city_points(1_000_000)
-    want_c, want_s = orc.Approx(polys, eps).aggregate(xy, vals)
-    A = sba.Approx.from_polygons(polys, eps)
+    O = orc.Approx(polys, eps)
+    want_c, want_s = O.aggregate(xy, vals)
+    for wide in (0, 1):
+        sba.lib().sba_debug_force_wide_grid(wide)
+        try:
+            A = sba.Approx.from_polygons(polys, eps)
+        finally:
+            sba.lib().sba_debug_force_wide_grid(0)
+        assert A.info()["compact"] == 1 - wide
+        c, s = run_agg(A, xy, vals)
+        np.testing.assert_array_equal(c, want_c)
+        np.testing.assert_array_equal(s, want_s)
+        c, _ = run_agg(A, xy, None)
+        np.testing.assert_array_equal(c, want_c)
+        A.close()
+
+
+@pytest.mark.parametrize("tl,sl", [(6, 2), (6, 3), (6, 4), (6, 6), (8, 4), (8, 5), (10, 4)])
+@pytest.mark.parametrize("wide", [0, 1])
+def test_sub_tile_levels(sba, orc, tl, sl, wide):
+    """Every tile / sub-tile split, in both formats, stores the oracle's cell
+    sets and gives its aggregates (overlapping stars: multi-polygon sets in
+    fine blocks, sub-tiles cut by the edge of the stored box)."""
+    polys = star_polygons(12, 9, 20.0, 400.0, 1500, 77)
+    eps = 5
+    O = orc.Approx(polys, eps)
+    sba.lib().sba_debug_force_wide_grid(wide)
     try:
-        for wide in (0, 1):
-            sba.lib().sba_debug_force_wide_grid(wide)
-            c, s = run_agg(A, xy, vals)
-            np.testing.assert_array_equal(c, want_c)
-            np.testing.assert_array_equal(s, want_s)
-            c, _ = run_agg(A, xy, None)
-            np.testing.assert_array_equal(c, want_c)
+        A = sba.Approx.from_polygons(polys, eps, tile_log2=tl, sub_log2=sl)
     finally:
         sba.lib().sba_debug_force_wide_grid(0)
+    info = A.info()
+    assert (info["tile_log2"], info["sub_log2"], info["compact"]) == (tl, sl, 1 - wide)
+    assert info["n_blocks"] > 0
+    if sl < tl:
+        assert info["n_sub"] > 0
+    i0, j0, nw, nh = window_of(polys, O.s)
+    want = expected_sets(O, polys.n_polys, i0, j0, nw, nh)
+    got = gpu_sets(A, list(want.keys()))
+    bad = [k for k in want if got[k] != want[k]]
+    assert not bad, (len(bad), bad[:5])
+    rng = np.random.default_rng(tl * 16 + sl)
+    n = 200_001
+    xy = rng.integers(-50, 1600, size=2 * n).astype(np.int32)
+    vals = rng.integers(100, 10000, size=n).astype(np.int64)
+    want_c, want_s = O.aggregate(xy, vals)
+    c, s = run_agg(A, xy, vals)
+    np.testing.assert_array_equal(c, want_c)
+    np.testing.assert_array_equal(s, want_s)
+
+
+def test_sub_level_rejects_bad_split(sba):
+    polys = star_polygons(3, 9, 20.0, 400.0, 1500, 78)
+    for tl, sl in ((5, 6), (6, 1)):
+        with pytest.raises(RuntimeError):
+            sba.Approx.from_polygons(polys, 5, tile_log2=tl, sub_log2=sl)
