@@ -4,15 +4,9 @@
 
 #include "sba_internal.h"
 
-// The handle's arrays come from the device's stream-ordered pool; returning
-// them does not synchronise the device (the caller guarantees that no queued
-// work still reads the handle).
-static void handle_release(sba_handle *h)
-{
-    void *arrs[] = {h->dir, h->sub, h->blocks, h->dir16, h->blocks16, h->set_off, h->set_ids, h->starts,
-                    h->starts32, h->run_code, h->leaves, h->leaf_lo};
-    for (void *p : arrs) tmp_free(p, nullptr);
-}
+// The handle's arrays go back to the device's block cache; nothing is
+// synchronised (the caller guarantees that no queued work still reads them).
+static void handle_release(sba_handle *h) { handle_put_all(h); }
 
 extern "C" int sba_build_approx(const sba_polygons *polys, int64_t eps, const sba_build_opts *opts,
                                 void *stream, sba_handle **out)

@@ -115,6 +115,42 @@ __global__ void k_poly_bbox(const int32_t *ring_off, const int64_t *vert_off, co
     if (lane == 0) bbox[p] = make_int4(xmin, ymin, xmax, ymax);
 }
 
+// union of the polygons' cell boxes (one workgroup): box = {min over p of
+// ceil(xmin/s) - 1, same for y, max over p of floor(xmax/s), same for y}
+#define BOX_BLOCK 1024
+__global__ __launch_bounds__(BOX_BLOCK) void k_union_box(const int4 *bbox, int32_t n_polys,
+                                                         int64_t s, int64_t *box)
+{
+    __shared__ int64_t red[4][BOX_BLOCK / 64];
+    int64_t v[4] = {INT64_MAX, INT64_MAX, INT64_MIN, INT64_MIN};
+    for (int p = threadIdx.x; p < n_polys; p += BOX_BLOCK) {
+        int4 b = bbox[p];
+        v[0] = min(v[0], ceildiv64(b.x, s) - 1);
+        v[1] = min(v[1], ceildiv64(b.y, s) - 1);
+        v[2] = max(v[2], floordiv64(b.z, s));
+        v[3] = max(v[3], floordiv64(b.w, s));
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        v[0] = min(v[0], (int64_t)__shfl_xor(v[0], o, 64));
+        v[1] = min(v[1], (int64_t)__shfl_xor(v[1], o, 64));
+        v[2] = max(v[2], (int64_t)__shfl_xor(v[2], o, 64));
+        v[3] = max(v[3], (int64_t)__shfl_xor(v[3], o, 64));
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 4; k++) red[k][w] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < BOX_BLOCK / 64; q++) {
+            v[0] = min(v[0], red[0][q]);
+            v[1] = min(v[1], red[1][q]);
+            v[2] = max(v[2], red[2][q]);
+            v[3] = max(v[3], red[3][q]);
+        }
+        for (int k = 0; k < 4; k++) box[k] = v[k];
+    }
+}
+
 // per edge: number of boundary row strips and of row-line crossings inside
 // the stored box [gi0,gi1] x [gj0,gj1] (the box is the union of the cell
 // boxes, cut by the clip window if there is one); polygons whose cell box
@@ -650,12 +686,6 @@ void magic_for(int64_t s, uint32_t *mag, int32_t *shift)
     *shift = 31 + l;
 }
 
-BuildState::~BuildState()
-{
-    for (void *p : owned) tmp_free(p, st);
-    (void)hipStreamSynchronize(st);
-}
-
 int pool_setup()
 {
     static bool done[64] = {false};
@@ -698,13 +728,16 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     hipLaunchKernelGGL(k_poly_bbox, dim3(grid_for((int64_t)np * 64)), dim3(256), 0, st,
                        polys->ring_off, polys->vert_off, polys->xy, np, bbox, err);
     HIP_OK(hipGetLastError());
-    std::vector<int4> hb(np);
+    int64_t *dbox = nullptr;
+    RC(B.alloc(&dbox, 4));
+    hipLaunchKernelGGL(k_union_box, dim3(1), dim3(BOX_BLOCK), 0, st, bbox, np, h->s, dbox);
+    HIP_OK(hipGetLastError());
     int herr = 0;
-    int64_t hsz[2] = {0, 0};
-    HIP_OK(hipMemcpyAsync(hb.data(), bbox, sizeof(int4) * np, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(hsz, sizes, sizeof(hsz), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
+    int64_t hsz[2] = {0, 0}, hbox[4] = {0, 0, 0, 0};
+    RC(B.ws.read(&herr, err, sizeof(int)));
+    RC(B.ws.read(hsz, sizes, sizeof(hsz)));
+    RC(B.ws.read(hbox, dbox, sizeof(hbox)));
+    RC(B.ws.sync());
     if (herr & 2) return SBA_EINVAL;
     if (herr & 1) return SBA_ERANGE;
     const int32_t nr = (int32_t)hsz[0];
@@ -718,18 +751,7 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     HIP_OK(hipGetLastError());
 
     const int64_t s = h->s;
-    int64_t gi0 = INT64_MAX, gj0 = INT64_MAX, gi1 = INT64_MIN, gj1 = INT64_MIN;
-    int64_t cmin = INT64_MAX, cmax = INT64_MIN;
-    for (int32_t p = 0; p < np; p++) {
-        gi0 = std::min(gi0, ceildiv64(hb[p].x, s) - 1);
-        gj0 = std::min(gj0, ceildiv64(hb[p].y, s) - 1);
-        gi1 = std::max(gi1, floordiv64(hb[p].z, s));
-        gj1 = std::max(gj1, floordiv64(hb[p].w, s));
-        cmin = std::min<int64_t>(cmin, std::min(hb[p].x, hb[p].y));
-        cmax = std::max<int64_t>(cmax, std::max(hb[p].z, hb[p].w));
-    }
-    B.cmin = cmin;
-    B.cmax = cmax;
+    int64_t gi0 = hbox[0], gj0 = hbox[1], gi1 = hbox[2], gj1 = hbox[3];
     if (B.window) {
         gi0 = std::max(gi0, floordiv64(B.wx0, s));
         gj0 = std::max(gj0, floordiv64(B.wy0, s));
@@ -762,11 +784,11 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     hipLaunchKernelGGL(k_edge_counts, dim3(grid_for(nv)), dim3(256), 0, st, B.edges, B.epoly, bbox,
                        nv, s, gi0, gj0, gi1, gj1, nb, nc);
     HIP_OK(hipGetLastError());
-    RC(scan_exclusive_i64(nb, nb, nv, tot, st));
-    RC(scan_exclusive_i64(nc, nc, nv, tot + 1, st));
+    RC(scan_exclusive_i64(nb, nb, nv, tot, st, &B.ws));
+    RC(scan_exclusive_i64(nc, nc, nv, tot + 1, st, &B.ws));
     int64_t ht[2];
-    HIP_OK(hipMemcpyAsync(ht, tot, sizeof(ht), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
+    RC(B.ws.read(ht, tot, sizeof(ht)));
+    RC(B.ws.sync());
     const int64_t NB = ht[0], NC = ht[1];
     if (NC % 2) return SBA_EDEVICE;
     h->n_boundary = NB;
@@ -793,21 +815,21 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     // polygon's coverage count at every event, whose changes (toggles) are
     // the maximal covered intervals of each polygon in each row.
     const int rxbits = B.rbits + B.xbits;
-    RC(radix_sort_u64(B.evkey, B.evpay, NE, pbits + rxbits, st));
+    RC(radix_sort_u64(B.evkey, B.evpay, NE, pbits + rxbits, st, &B.ws));
     int64_t *cex = nullptr, *tf = nullptr;
     RC(B.alloc(&cex, NE));
     RC(B.alloc(&tf, NE));
     hipLaunchKernelGGL(k_ev_values, dim3(grid_for(NE)), dim3(256), 0, st, B.evpay, NE, cex);
     HIP_OK(hipGetLastError());
-    RC(scan_exclusive_i64(cex, cex, NE, tot, st));
+    RC(scan_exclusive_i64(cex, cex, NE, tot, st, &B.ws));
     hipLaunchKernelGGL(k_toggle_flags, dim3(grid_for(NE)), dim3(256), 0, st, B.evkey, B.evpay, cex,
                        NE, B.xbits, tf, err);
     HIP_OK(hipGetLastError());
-    RC(scan_exclusive_i64(tf, tf, NE, tot, st));
+    RC(scan_exclusive_i64(tf, tf, NE, tot, st, &B.ws));
     int64_t NT = 0;
-    HIP_OK(hipMemcpyAsync(&NT, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
+    RC(B.ws.read(&NT, tot, sizeof(int64_t)));
+    RC(B.ws.read(&herr, err, sizeof(int)));
+    RC(B.ws.sync());
     if (herr || (NT & 1)) return SBA_EDEVICE;
     B.release(cex);
     uint64_t *tkey = nullptr, *E = nullptr;
@@ -840,10 +862,10 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     HIP_OK(hipMemsetAsync(diff, 0, sizeof(int64_t) * (NP + 1), st));
     if (NT) {
         HIP_OK(hipMemcpyAsync(E, tkey, sizeof(uint64_t) * NT, hipMemcpyDeviceToDevice, st));
-        RC(radix_sort_u64(E, nullptr, NT, rxbits, st));
+        RC(radix_sort_u64(E, nullptr, NT, rxbits, st, &B.ws));
         hipLaunchKernelGGL(k_flag_new, dim3(grid_for(NT)), dim3(256), 0, st, E, NT, pos);
         HIP_OK(hipGetLastError());
-        RC(scan_exclusive_i64(pos, pos, NT, tot + 1, st));
+        RC(scan_exclusive_i64(pos, pos, NT, tot + 1, st, &B.ws));
         uint64_t *Eu = nullptr;
         RC(B.alloc(&Eu, NT));
         hipLaunchKernelGGL(k_unique_emit, dim3(grid_for(NT)), dim3(256), 0, st, E, NT, pos, Eu);
@@ -855,17 +877,17 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
         HIP_OK(hipGetLastError());
     }
     B.release(pos);
-    RC(scan_exclusive_i64(diff, dex, NP, tot + 2, st));
+    RC(scan_exclusive_i64(diff, dex, NP, tot + 2, st, &B.ws));
     hipLaunchKernelGGL(k_piece_classify, dim3(grid_for(NP)), dim3(256), 0, st, dex, diff, NP, segc,
                        mm, err);
     HIP_OK(hipGetLastError());
-    RC(scan_exclusive_i64(segc, segc, NP, tot + 3, st));
-    RC(scan_exclusive_i64(mm, mm, NP, tot + 4, st));
-    RC(scan_exclusive_i64(xoff, xoff, std::max<int64_t>(NI, 1), tot + 5, st));
+    RC(scan_exclusive_i64(segc, segc, NP, tot + 3, st, &B.ws));
+    RC(scan_exclusive_i64(mm, mm, NP, tot + 4, st, &B.ws));
+    RC(scan_exclusive_i64(xoff, xoff, std::max<int64_t>(NI, 1), tot + 5, st, &B.ws));
     int64_t h6[6];
-    HIP_OK(hipMemcpyAsync(h6, tot, sizeof(h6), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
+    RC(B.ws.read(h6, tot, sizeof(h6)));
+    RC(B.ws.read(&herr, err, sizeof(int)));
+    RC(B.ws.sync());
     if (herr & 8) return SBA_ELIMIT;
     if (herr) return SBA_EDEVICE;
     const int64_t NS = h6[3] >> 32, NM = h6[3] & 0xffffffffll, NMEM = h6[4];
@@ -921,30 +943,30 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
         hipLaunchKernelGGL(k_multi_keys, dim3(grid_for(NM)), dim3(256), 0, st, multi_mem, NM, NMEM,
                            mem_ids, fb, mkey, mval);
         HIP_OK(hipGetLastError());
-        RC(radix_sort_u64(mkey, mval, NM, kbits, st));
+        RC(radix_sort_u64(mkey, mval, NM, kbits, st, &B.ws));
         hipLaunchKernelGGL(k_flag_new, dim3(grid_for(NM)), dim3(256), 0, st, mkey, NM, g);
         HIP_OK(hipGetLastError());
-        RC(scan_exclusive_i64(g, g, NM, tot, st));
-        int64_t nsets = 0;
-        HIP_OK(hipMemcpyAsync(&nsets, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
-        RC(B.alloc(&set_sz, nsets + 1));
+        RC(scan_exclusive_i64(g, g, NM, tot, st, &B.ws));
+        // sizes are bounded by the multi segments (NM sets, NMEM ids), so the
+        // set table is laid out before its counts reach the host
+        RC(B.alloc(&set_sz, NM + 1));
+        HIP_OK(hipMemsetAsync(set_sz, 0, sizeof(int64_t) * (NM + 1), st));
         hipLaunchKernelGGL(k_set_sizes, dim3(grid_for(NM)), dim3(256), 0, st, mkey, mval, g, NM,
                            multi_mem, NM, NMEM, set_sz);
         HIP_OK(hipGetLastError());
-        RC(tmp_alloc(&h->set_off, nsets + 1, st));
-        RC(scan_exclusive_i64(set_sz, h->set_off, nsets, h->set_off + nsets, st));
-        int64_t nids = 0;
-        HIP_OK(hipMemcpyAsync(&nids, h->set_off + nsets, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
-        RC(tmp_alloc(&h->set_ids, nids, st));
+        RC(handle_alloc(h, &h->set_off, NM + 1));
+        RC(scan_exclusive_i64(set_sz, h->set_off, NM, h->set_off + NM, st, &B.ws));
+        RC(handle_alloc(h, &h->set_ids, NMEM));
         hipLaunchKernelGGL(k_set_fill, dim3(grid_for(NM)), dim3(256), 0, st, mkey, mval, g, NM,
                            multi_mem, NM, NMEM, mem_ids, h->set_off, h->set_ids, multi_seg,
                            B.seg_code);
         HIP_OK(hipGetLastError());
+        int64_t nsets = 0, nids = 0;
+        RC(B.ws.read(&nsets, tot, sizeof(int64_t)));
+        RC(B.ws.read(&nids, h->set_off + NM, sizeof(int64_t)));
+        RC(B.ws.sync());
         h->n_sets = nsets;
         h->n_set_ids = nids;
-        h->bytes += (nsets + 1) * 8 + nids * 4;
         B.release(mkey);
         B.release(mval);
         B.release(g);
@@ -1007,10 +1029,10 @@ int build_grid(sba_handle *h, BuildState &B, int tile_log2, int sub_log2, hipStr
     RC(B.alloc(&tot, 2));
     classify(B, h, nullptr, tl, sl, nt, tcode, tpos, st);
     HIP_OK(hipGetLastError());
-    RC(scan_exclusive_i64(tpos, tpos, nt, tot, st));
+    RC(scan_exclusive_i64(tpos, tpos, nt, tot, st, &B.ws));
     int64_t nblk = 0;
-    HIP_OK(hipMemcpyAsync(&nblk, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
+    RC(B.ws.read(&nblk, tot, sizeof(int64_t)));
+    RC(B.ws.sync());
     if (nblk >= (int64_t)TILE_MIXED) return SBA_ELIMIT;
     h->n_blocks = nblk;
     const bool compact = !g_build_wide && (int64_t)np + h->n_sets < 0x8000 && nblk < 0x8000 &&
@@ -1020,13 +1042,11 @@ int build_grid(sba_handle *h, BuildState &B, int tile_log2, int sub_log2, hipStr
     // directory
     if (compact) {
         const int64_t nt16 = (nt + 7) & ~(int64_t)7;  // LDS copies move 16 bytes at a time
-        RC(tmp_alloc(&h->dir16, nt16, st));
-        h->bytes += nt16 * 2;
+        RC(handle_alloc(h, &h->dir16, nt16));
         hipLaunchKernelGGL(k_entries, dim3(grid_for(nt16)), dim3(256), 0, st, tcode, tpos, nt, nt16,
                            np, 2, (uint32_t *)nullptr, h->dir16);
     } else {
-        RC(tmp_alloc(&h->dir, nt, st));
-        h->bytes += nt * 4;
+        RC(handle_alloc(h, &h->dir, nt));
         hipLaunchKernelGGL(k_entries, dim3(grid_for(nt)), dim3(256), 0, st, tcode, tpos, nt, nt, np,
                            0, h->dir, (uint16_t *)nullptr);
     }
@@ -1035,14 +1055,14 @@ int build_grid(sba_handle *h, BuildState &B, int tile_log2, int sub_log2, hipStr
         // one-element placeholders: the batched lookups read element 0 of
         // the lower levels for points that need nothing from them
         if (sl < tl) {
-            RC(tmp_alloc(&h->sub, 1, st));
+            RC(handle_alloc(h, &h->sub, 1));
             HIP_OK(hipMemsetAsync(h->sub, 0, 4, st));
         }
         if (compact) {
-            RC(tmp_alloc(&h->blocks16, 1, st));
+            RC(handle_alloc(h, &h->blocks16, 1));
             HIP_OK(hipMemsetAsync(h->blocks16, 0, 2, st));
         } else {
-            RC(tmp_alloc(&h->blocks, 1, st));
+            RC(handle_alloc(h, &h->blocks, 1));
             HIP_OK(hipMemsetAsync(h->blocks, 0, 4, st));
         }
         return 0;
@@ -1065,14 +1085,13 @@ int build_grid(sba_handle *h, BuildState &B, int tile_log2, int sub_log2, hipStr
         RC(B.alloc(&spos, nq + 1));
         classify(B, h, mt, tl, sl, nq, scode, spos, st);
         HIP_OK(hipGetLastError());
-        RC(scan_exclusive_i64(spos, spos, nq, tot + 1, st));
+        RC(scan_exclusive_i64(spos, spos, nq, tot + 1, st, &B.ws));
         int64_t nsub = 0;
-        HIP_OK(hipMemcpyAsync(&nsub, tot + 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
+        RC(B.ws.read(&nsub, tot + 1, sizeof(int64_t)));
+        RC(B.ws.sync());
         if (nsub >= (int64_t)TILE_MIXED) return SBA_ELIMIT;
         h->n_sub = nsub;
-        RC(tmp_alloc(&h->sub, nq, st));
-        h->bytes += nq * 4;
+        RC(handle_alloc(h, &h->sub, nq));
         hipLaunchKernelGGL(k_entries, dim3(grid_for(nq)), dim3(256), 0, st, scode, spos, nq, nq, np,
                            compact ? 1 : 0, h->sub, (uint16_t *)nullptr);
         HIP_OK(hipGetLastError());
@@ -1090,15 +1109,13 @@ int build_grid(sba_handle *h, BuildState &B, int tile_log2, int sub_log2, hipStr
     const int side = 1 << fine_log2;
     const int64_t threads = nfine * side * (side > 16 ? side >> 4 : 1);
     if (compact) {
-        RC(tmp_alloc(&h->blocks16, std::max<int64_t>(cells, 1), st));
-        h->bytes += cells * 2;
+        RC(handle_alloc(h, &h->blocks16, std::max<int64_t>(cells, 1)));
         if (nfine)
             hipLaunchKernelGGL(k_block_fill<uint16_t>, dim3(grid_for(threads)), dim3(256), 0, st,
                                B.seg_row_off, B.seg_x0, B.seg_x1, B.seg_code, h->gw, h->gh, fine_sq,
                                nfine, fine_mt, tl, sl, h->tw, fine_log2, np, h->blocks16);
     } else {
-        RC(tmp_alloc(&h->blocks, std::max<int64_t>(cells, 1), st));
-        h->bytes += cells * 4;
+        RC(handle_alloc(h, &h->blocks, std::max<int64_t>(cells, 1)));
         if (nfine)
             hipLaunchKernelGGL(k_block_fill<uint32_t>, dim3(grid_for(threads)), dim3(256), 0, st,
                                B.seg_row_off, B.seg_x0, B.seg_x1, B.seg_code, h->gw, h->gh, fine_sq,
@@ -1146,8 +1163,7 @@ int build_handle(const sba_polygons *polys, int64_t eps, const sba_build_opts *o
         h->build_ms = 0;
         return 0;
     }
-    BuildState B;
-    B.st = st;
+    BuildState B(st);
     B.window = o.use_window != 0;
     B.wx0 = o.win_x0;
     B.wy0 = o.win_y0;

@@ -8,24 +8,16 @@
 #include "sba_internal.h"
 
 struct BuildState {
-    hipStream_t st = nullptr;
-    std::vector<void *> owned;
+    explicit BuildState(hipStream_t s) : st(s), ws(s) {}
+    hipStream_t st;
+    Workspace ws;  // temporaries; returned (after a sync) when the build ends
 
     template <typename T>
     int alloc(T **p, int64_t n)
     {
-        int rc = tmp_alloc(p, n, st);
-        if (!rc) owned.push_back((void *)*p);
-        return rc;
+        return ws.alloc(p, n);
     }
-    void release(void *p)
-    {
-        auto it = std::find(owned.begin(), owned.end(), p);
-        if (it == owned.end()) return;
-        tmp_free(p, st);
-        owned.erase(it);
-    }
-    ~BuildState();
+    void release(void *p) { ws.put(p); }
 
     // clip window in coordinates, [wx0, wx1) x [wy0, wy1)
     bool window = false;
@@ -35,7 +27,6 @@ struct BuildState {
     int4 *edges = nullptr;
     int32_t *epoly = nullptr;
     int64_t n_edges = 0;
-    int64_t cmin = 0, cmax = 0;  // smallest / largest vertex coordinate
     int xbits = 0, rbits = 0;    // event key fields: row << xbits | x
     int64_t NB = 0;              // boundary intervals (events [0, 2 NB) until sorted)
     uint64_t *evkey = nullptr;

@@ -89,10 +89,10 @@ static int hilbert_boundary_cells(BuildState &B, sba_handle *h, hipStream_t st)
     hipLaunchKernelGGL(k_bcell_counts, dim3(grid_for(NB)), dim3(256), 0, st, B.evkey, NB, B.xbits,
                        cnt);
     HIP_OK(hipGetLastError());
-    RC(scan_exclusive_i64(cnt, cnt, NB, tot, st));
+    RC(scan_exclusive_i64(cnt, cnt, NB, tot, st, &B.ws));
     int64_t ncb = 0;
-    HIP_OK(hipMemcpyAsync(&ncb, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
+    RC(B.ws.read(&ncb, tot, sizeof(int64_t)));
+    RC(B.ws.sync());
     const int64_t nborder = B.window ? 2 * (h->gw + h->gh) : 0;
     const int64_t nc = ncb + nborder;
     if (nc == 0) return 0;
@@ -106,15 +106,15 @@ static int hilbert_boundary_cells(BuildState &B, sba_handle *h, hipStream_t st)
                            h->level, keys + ncb);
     HIP_OK(hipGetLastError());
     B.release(cnt);
-    RC(radix_sort_u64(keys, nullptr, nc, 2 * h->level, st));
+    RC(radix_sort_u64(keys, nullptr, nc, 2 * h->level, st, &B.ws));
     int64_t *flag = nullptr;
     RC(B.alloc(&flag, nc + 1));
     hipLaunchKernelGGL(k_flag_first, dim3(grid_for(nc)), dim3(256), 0, st, keys, nc, flag);
     HIP_OK(hipGetLastError());
-    RC(scan_exclusive_i64(flag, flag, nc, tot, st));
+    RC(scan_exclusive_i64(flag, flag, nc, tot, st, &B.ws));
     int64_t nu = 0;
-    HIP_OK(hipMemcpyAsync(&nu, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
+    RC(B.ws.read(&nu, tot, sizeof(int64_t)));
+    RC(B.ws.sync());
     RC(B.alloc(&B.bkeys, nu));
     hipLaunchKernelGGL(k_compact_first, dim3(grid_for(nc)), dim3(256), 0, st, keys, nc, flag,
                        B.bkeys);
@@ -339,11 +339,11 @@ int hilbert_finish(BuildState &B, sba_handle *h, const sba_build_opts &o, hipStr
         hipLaunchKernelGGL(k_cand_counts, dim3(grid_for(nb)), dim3(256), 0, st, B.bkeys, nb, total,
                            cnt);
     HIP_OK(hipGetLastError());
-    RC(scan_exclusive_i64(cnt, cnt, nb, tot, st));
+    RC(scan_exclusive_i64(cnt, cnt, nb, tot, st, &B.ws));
     int64_t nc = 0;
     if (nb) {
-        HIP_OK(hipMemcpyAsync(&nc, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
+        RC(B.ws.read(&nc, tot, sizeof(int64_t)));
+        RC(B.ws.sync());
     }
     nc += lead;
     uint64_t *ckey = nullptr;
@@ -358,44 +358,41 @@ int hilbert_finish(BuildState &B, sba_handle *h, const sba_build_opts &o, hipStr
     RC(B.alloc(&flag, nc + 1));
     hipLaunchKernelGGL(k_run_flags, dim3(grid_for(nc)), dim3(256), 0, st, ccode, nc, flag);
     HIP_OK(hipGetLastError());
-    RC(scan_exclusive_i64(flag, flag, nc, tot, st));
+    RC(scan_exclusive_i64(flag, flag, nc, tot, st, &B.ws));
     int64_t nr = 0;
-    HIP_OK(hipMemcpyAsync(&nr, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
+    RC(B.ws.read(&nr, tot, sizeof(int64_t)));
+    RC(B.ws.sync());
     if (nr >= ((int64_t)1 << 31)) return SBA_ELIMIT;
     h->n_runs = nr;
-    RC(tmp_alloc(&h->starts, nr, st));
-    RC(tmp_alloc(&h->run_code, nr, st));
-    h->bytes += nr * 12;
+    RC(handle_alloc(h, &h->starts, nr));
+    RC(handle_alloc(h, &h->run_code, nr));
     if (2 * L <= 32) {
-        RC(tmp_alloc(&h->starts32, nr, st));
-        h->bytes += nr * 4;
+        RC(handle_alloc(h, &h->starts32, nr));
     }
     hipLaunchKernelGGL(k_run_write, dim3(grid_for(nc)), dim3(256), 0, st, ckey, ccode, nc, flag,
                        h->starts, h->starts32, h->run_code);
     HIP_OK(hipGetLastError());
-    HIP_OK(hipStreamSynchronize(st));
 
     if (o.search == SBA_SEARCH_LEARNED) {
         if (2 * L > 32) return SBA_ELIMIT;  // leaves store 32-bit key bases
         const uint32_t nl = 1u << o.log2_leaves;
         h->log2_leaves = o.log2_leaves;
         uint64_t last = 0;
-        HIP_OK(hipMemcpy(&last, h->starts + (nr - 1), sizeof(uint64_t), hipMemcpyDeviceToHost));
+        RC(B.ws.read(&last, h->starts + (nr - 1), sizeof(uint64_t)));
+        RC(B.ws.sync());
         h->root_k0 = 0;
         h->root_a = (float)nl / (float)(last + 1);
         unsigned long long *stats = nullptr;
         RC(B.alloc(&stats, 2));
         HIP_OK(hipMemsetAsync(stats, 0, 2 * sizeof(unsigned long long), st));
-        RC(tmp_alloc(&h->leaves, nl, st));
-        RC(tmp_alloc(&h->leaf_lo, (int64_t)nl + 1, st));
-        h->bytes += (int64_t)nl * 16 + ((int64_t)nl + 1) * 4;
+        RC(handle_alloc(h, &h->leaves, nl));
+        RC(handle_alloc(h, &h->leaf_lo, (int64_t)nl + 1));
         hipLaunchKernelGGL(k_leaf_fit, dim3(grid_for((int64_t)nl * 64)), dim3(256), 0, st, h->starts,
                            nr, h->root_a, nl, total, h->leaves, h->leaf_lo, stats);
         HIP_OK(hipGetLastError());
         unsigned long long hs[2];
-        HIP_OK(hipMemcpyAsync(hs, stats, sizeof(hs), hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
+        RC(B.ws.read(hs, stats, sizeof(hs)));
+        RC(B.ws.sync());
         h->max_leaf_err = (int64_t)hs[0];
         h->mean_leaf_err = (double)hs[1] / (double)nl;
     }

@@ -111,7 +111,20 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_tile_scan(const int64_t *in, int
     }
 }
 
-int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t st)
+template <typename T>
+static int tmp_get(Workspace *ws, T **p, int64_t n, hipStream_t st)
+{
+    return ws ? ws->alloc(p, n) : tmp_alloc(p, n, st);
+}
+
+static void tmp_put(Workspace *ws, void *p, hipStream_t st)
+{
+    if (ws) ws->put(p);
+    else tmp_free(p, st);
+}
+
+int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t st,
+                       Workspace *ws)
 {
     if (n <= 0) {
         if (total) HIP_OK(hipMemsetAsync(total, 0, sizeof(int64_t), st));
@@ -124,16 +137,16 @@ int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tota
     }
     const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
     int64_t *sums = nullptr;
-    RC(tmp_alloc(&sums, tiles, st));
+    RC(tmp_get(ws, &sums, tiles, st));
     hipLaunchKernelGGL(k_tile_sums, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, st, in, n, sums);
     int rc = hipGetLastError() == hipSuccess ? 0 : SBA_EDEVICE;
-    if (!rc) rc = scan_exclusive_i64(sums, sums, tiles, total, st);
+    if (!rc) rc = scan_exclusive_i64(sums, sums, tiles, total, st, ws);
     if (!rc) {
         hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, st, in, out, n,
                            sums);
         rc = hipGetLastError() == hipSuccess ? 0 : SBA_EDEVICE;
     }
-    tmp_free(sums, st);
+    tmp_put(ws, sums, st);
     return rc;
 }
 
@@ -247,16 +260,17 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const uint64_t *keys, c
     }
 }
 
-int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st)
+int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st,
+                   Workspace *ws)
 {
     if (n <= 1 || bits <= 0) return 0;
     const int64_t nblocks = (n + RS_TILE - 1) / RS_TILE;
     uint64_t *k2 = nullptr;
     uint32_t *v2 = nullptr;
     int64_t *goff = nullptr;
-    int rc = tmp_alloc(&k2, n, st);
-    if (!rc && vals) rc = tmp_alloc(&v2, n, st);
-    if (!rc) rc = tmp_alloc(&goff, nblocks * RS_RADIX, st);
+    int rc = tmp_get(ws, &k2, n, st);
+    if (!rc && vals) rc = tmp_get(ws, &v2, n, st);
+    if (!rc) rc = tmp_get(ws, &goff, nblocks * RS_RADIX, st);
     uint64_t *ka = keys, *kb = k2;
     uint32_t *va = vals, *vb = v2;
     int passes = (bits + 7) / 8;
@@ -265,7 +279,7 @@ int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStrea
         hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st, ka, n, shift,
                            goff, nblocks);
         if (hipGetLastError() != hipSuccess) { rc = SBA_EDEVICE; break; }
-        rc = scan_exclusive_i64(goff, goff, nblocks * RS_RADIX, nullptr, st);
+        rc = scan_exclusive_i64(goff, goff, nblocks * RS_RADIX, nullptr, st, ws);
         if (rc) break;
         if (vals)
             hipLaunchKernelGGL(k_rs_scatter<true>, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st, ka,
@@ -284,8 +298,8 @@ int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStrea
             hipMemcpyAsync(vals, va, (size_t)n * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
             rc = SBA_EDEVICE;
     }
-    tmp_free(k2, st);
-    tmp_free(v2, st);
-    tmp_free(goff, st);
+    tmp_put(ws, k2, st);
+    tmp_put(ws, v2, st);
+    tmp_put(ws, goff, st);
     return rc;
 }

@@ -6,13 +6,15 @@
 // pairs, one 128-bit load of two int64 values), maps each point to its cell
 // with a multiply-shift division by the cell side, looks up the cell's code
 // and adds the point to a per-workgroup histogram in LDS.  At the end every
-// workgroup writes its histogram once; a second small kernel sums the
-// workgroup histograms into the caller's outputs (no global atomics on the
-// hot path).  Polygon counts too large for LDS fall back to global atomics.
+// workgroup adds its non-empty bins to the caller's outputs (zeroed by a
+// small kernel before the probe) with one global atomic per bin; no global
+// atomics per point.  Polygon counts too large for LDS fall back to global
+// atomics per point.  A call allocates nothing.
 //
 // Cell lookup per layout:
-//   grid     directory entry of the cell's tile (a few hundred KB, stays in
-//            L2), and for mixed tiles one more load from the tile's block;
+//   grid     directory entry of the cell's tile (staged in LDS in the
+//            16-bit format), for mixed tiles the sub-tile's entry, for mixed
+//            sub-tiles the cell's code in a fine block;
 //   hilbert  Hilbert key of the cell, then the run holding it: binary search
 //            over the run starts, or the learned index's bounded search.
 #include <algorithm>
@@ -413,7 +415,23 @@ __device__ __forceinline__ uint32_t code_of(const GridView &g, const HilbView &h
     return hilbert_code<LAYOUT == 2 ? 1 : 0>(hv, x, y);
 }
 
-// LDS-privatised histograms; partial[b] = {count u32 [np], sum u64 [np]}
+// A workgroup's LDS histogram into the outputs (zeroed before the launch):
+// one global atomic per non-empty bin.  Integer addition is associative, so
+// the result does not depend on the order of the workgroups.
+template <bool VALS>
+__device__ __forceinline__ void flush_bins(const uint32_t *lcnt, const unsigned long long *lsum,
+                                           uint32_t np, uint32_t nthreads, uint64_t *counts,
+                                           int64_t *sums)
+{
+    for (uint32_t p = threadIdx.x; p < np; p += nthreads) {
+        uint32_t c = lcnt[p];
+        if (c == 0) continue;
+        atomicAdd((unsigned long long *)&counts[p], (unsigned long long)c);
+        if (VALS && lsum[p] != 0) atomicAdd((unsigned long long *)&sums[p], lsum[p]);
+    }
+}
+
+// LDS-privatised histograms, added to the outputs once per workgroup
 template <int LAYOUT, bool VALS>
 __global__ __launch_bounds__(PROBE_BLOCK) void k_probe_lds(const int4 *__restrict__ xy4,
                                                            const longlong2 *__restrict__ v2,
@@ -421,8 +439,8 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_probe_lds(const int4 *__restric
                                                            const int64_t *__restrict__ vals,
                                                            int64_t n, GridView g, HilbView hv,
                                                            Agg A, int32_t np,
-                                                           uint32_t *__restrict__ pcnt,
-                                                           unsigned long long *__restrict__ psum)
+                                                           uint64_t *__restrict__ counts,
+                                                           int64_t *__restrict__ sums)
 {
     extern __shared__ unsigned long long smem[];
     unsigned long long *lsum = smem;
@@ -469,42 +487,10 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_probe_lds(const int4 *__restric
         add_lds<VALS>(c, VALS ? vals[k] : 0, A, lcnt, lsum);
     }
     __syncthreads();
-    uint32_t *oc = pcnt + (int64_t)blockIdx.x * np;
-    unsigned long long *os = psum + (int64_t)blockIdx.x * np;
-    for (int p = threadIdx.x; p < np; p += PROBE_BLOCK) {
-        oc[p] = lcnt[p];
-        if (VALS) os[p] = lsum[p];
-    }
+    flush_bins<VALS>(lcnt, lsum, np, PROBE_BLOCK, counts, sums);
 }
 
 // one block per polygon: sum the workgroup histograms, overwrite the outputs
-template <bool VALS>
-__global__ __launch_bounds__(256) void k_reduce(const uint32_t *pcnt, const unsigned long long *psum,
-                                                int64_t nblocks, int32_t np, uint64_t *counts,
-                                                int64_t *sums)
-{
-    const int p = blockIdx.x;
-    unsigned long long c = 0, s = 0;
-    for (int64_t b = threadIdx.x; b < nblocks; b += 256) {
-        c += pcnt[b * np + p];
-        if (VALS) s += psum[b * np + p];
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        c += __shfl_xor(c, o, 64);
-        s += __shfl_xor(s, o, 64);
-    }
-    __shared__ unsigned long long wc[4], ws[4];
-    if ((threadIdx.x & 63) == 0) {
-        wc[threadIdx.x >> 6] = c;
-        ws[threadIdx.x >> 6] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        counts[p] = wc[0] + wc[1] + wc[2] + wc[3];
-        if (VALS) sums[p] = (int64_t)(ws[0] + ws[1] + ws[2] + ws[3]);
-    }
-}
-
 __global__ void k_zero_out(uint64_t *counts, int64_t *sums, int32_t np)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -667,30 +653,16 @@ static int launch_layout(const int32_t *xy, const int64_t *values, int64_t n, co
     const int4 *xy4 = (const int4 *)xy;
     const longlong2 *v2 = (const longlong2 *)values;
     if (np <= LDS_MAX_POLYS) {
-        uint32_t *pcnt = nullptr;
-        unsigned long long *psum = nullptr;
-        size_t bytes = (size_t)nb * np * (sizeof(uint32_t) + (vals ? 8 : 0));
-        char *scratch = nullptr;
-        RC(tmp_alloc(&scratch, (int64_t)(bytes ? bytes : 8), st));
-        psum = (unsigned long long *)scratch;
-        pcnt = (uint32_t *)(vals ? (char *)scratch + (size_t)nb * np * 8 : (char *)scratch);
+        hipLaunchKernelGGL(k_zero_out, dim3(grid_for(np)), dim3(256), 0, st, counts,
+                           vals ? sums : nullptr, np);
         size_t lds = (size_t)np * 12;
         if (vals)
             hipLaunchKernelGGL((k_probe_lds<LAYOUT, true>), dim3((unsigned)nb), dim3(PROBE_BLOCK), lds,
-                               st, xy4, v2, xy, values, n, g, hv, A, np, pcnt, psum);
+                               st, xy4, v2, xy, values, n, g, hv, A, np, counts, sums);
         else
             hipLaunchKernelGGL((k_probe_lds<LAYOUT, false>), dim3((unsigned)nb), dim3(PROBE_BLOCK), lds,
-                               st, xy4, v2, xy, values, n, g, hv, A, np, pcnt, psum);
-        hipError_t e1 = hipGetLastError();
-        if (vals)
-            hipLaunchKernelGGL(k_reduce<true>, dim3((unsigned)np), dim3(256), 0, st, pcnt, psum, nb, np,
-                               counts, sums);
-        else
-            hipLaunchKernelGGL(k_reduce<false>, dim3((unsigned)np), dim3(256), 0, st, pcnt, psum, nb,
-                               np, counts, sums);
-        hipError_t e2 = hipGetLastError();
-        tmp_free(scratch, st);
-        if (e1 != hipSuccess || e2 != hipSuccess) return SBA_EDEVICE;
+                               st, xy4, v2, xy, values, n, g, hv, A, np, counts, sums);
+        HIP_OK(hipGetLastError());
         return 0;
     }
     hipLaunchKernelGGL(k_zero_out, dim3(grid_for(np)), dim3(256), 0, st, counts, vals ? sums : nullptr,
@@ -786,8 +758,8 @@ __global__ __launch_bounds__(GRID16_BLOCK) void k_probe_grid16(const int4 *__res
                                                               const int32_t *__restrict__ xy,
                                                               const int64_t *__restrict__ vals,
                                                               int64_t n, Grid16 g, Agg A,
-                                                              uint32_t *__restrict__ pcnt,
-                                                              unsigned long long *__restrict__ psum)
+                                                              uint64_t *__restrict__ counts,
+                                                              int64_t *__restrict__ sums)
 {
     extern __shared__ unsigned long long smem[];
     const uint32_t np = g.np;
@@ -879,12 +851,7 @@ __global__ __launch_bounds__(GRID16_BLOCK) void k_probe_grid16(const int4 *__res
         add_short<VALS>(sc, VALS ? vals[k] : 0, A, np, lcnt, lsum);
     }
     __syncthreads();
-    uint32_t *oc = pcnt + (int64_t)blockIdx.x * np;
-    unsigned long long *os = psum + (int64_t)blockIdx.x * np;
-    for (uint32_t p = threadIdx.x; p < np; p += GRID16_BLOCK) {
-        oc[p] = lcnt[p];
-        if (VALS) os[p] = lsum[p];
-    }
+    flush_bins<VALS>(lcnt, lsum, np, GRID16_BLOCK, counts, sums);
 }
 
 // LDS of the grid probe: histograms (12 B per polygon) + the 16-bit directory
@@ -929,42 +896,31 @@ static int launch_grid16(const int32_t *xy, const int64_t *values, int64_t n, co
     int64_t nb = std::min<int64_t>((npairs + GRID16_BLOCK - 1) / GRID16_BLOCK,
                                    (int64_t)cu_count() * per_cu);
     if (nb < 1) nb = 1;
-    char *scratch = nullptr;
-    RC(tmp_alloc(&scratch, (int64_t)nb * np * (4 + (vals ? 8 : 0)) + 8, st));
-    unsigned long long *psum = (unsigned long long *)scratch;
-    uint32_t *pcnt = (uint32_t *)(vals ? scratch + (size_t)nb * np * 8 : scratch);
     const void *kern = nullptr;
     if (sub) grid16_kernels<true>(vals, &kern);
     else grid16_kernels<false>(vals, &kern);
     // dynamic LDS above 64 KB has to be allowed explicitly
     (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipGetLastError();
+    hipLaunchKernelGGL(k_zero_out, dim3(grid_for(np)), dim3(256), 0, st, counts,
+                       vals ? sums : nullptr, np);
     if (sub && vals)
         hipLaunchKernelGGL((k_probe_grid16<true, true>), dim3((unsigned)nb), dim3(GRID16_BLOCK),
                            lds, st, (const int4 *)xy, (const longlong2 *)values, xy, values, n, g,
-                           A, pcnt, psum);
+                           A, counts, sums);
     else if (sub)
         hipLaunchKernelGGL((k_probe_grid16<false, true>), dim3((unsigned)nb), dim3(GRID16_BLOCK),
                            lds, st, (const int4 *)xy, (const longlong2 *)values, xy, values, n, g,
-                           A, pcnt, psum);
+                           A, counts, sums);
     else if (vals)
         hipLaunchKernelGGL((k_probe_grid16<true, false>), dim3((unsigned)nb), dim3(GRID16_BLOCK),
                            lds, st, (const int4 *)xy, (const longlong2 *)values, xy, values, n, g,
-                           A, pcnt, psum);
+                           A, counts, sums);
     else
         hipLaunchKernelGGL((k_probe_grid16<false, false>), dim3((unsigned)nb), dim3(GRID16_BLOCK),
                            lds, st, (const int4 *)xy, (const longlong2 *)values, xy, values, n, g,
-                           A, pcnt, psum);
-    hipError_t e1 = hipGetLastError();
-    if (vals)
-        hipLaunchKernelGGL(k_reduce<true>, dim3((unsigned)np), dim3(256), 0, st, pcnt, psum, nb, np,
-                           counts, sums);
-    else
-        hipLaunchKernelGGL(k_reduce<false>, dim3((unsigned)np), dim3(256), 0, st, pcnt, psum, nb, np,
-                           counts, sums);
-    hipError_t e2 = hipGetLastError();
-    tmp_free(scratch, st);
-    return (e1 != hipSuccess || e2 != hipSuccess) ? SBA_EDEVICE : 0;
+                           A, counts, sums);
+    return hipGetLastError() != hipSuccess ? SBA_EDEVICE : 0;
 }
 
 int probe_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,

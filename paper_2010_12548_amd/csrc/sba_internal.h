@@ -5,9 +5,60 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string.h>
+
 #include <algorithm>
+#include <vector>
 
 #include "../../include/sba.h"
+
+// ---------------------------------------------------------------- device memory (alloc.hip)
+
+struct DevBlock {
+    void *p;
+    size_t cls;  // size of the block (its size class)
+    int dev;
+};
+
+int cache_get(size_t bytes, DevBlock *out);
+void cache_put(const DevBlock &b);
+
+// Temporaries of one stream-ordered job; the destructor synchronises the
+// stream and returns every block to the device's cache.
+class Workspace {
+public:
+    explicit Workspace(hipStream_t st);
+    ~Workspace();
+    Workspace(const Workspace &) = delete;
+    Workspace &operator=(const Workspace &) = delete;
+    int get(void **p, size_t bytes);
+    void put(void *p);  // reusable by later requests of this job
+    template <typename T>
+    int alloc(T **p, int64_t n)
+    {
+        void *q = nullptr;
+        int rc = get(&q, (size_t)(n > 0 ? n : 1) * sizeof(T));
+        *p = (T *)q;
+        return rc;
+    }
+    // queue a copy of `bytes` (<= a few KB in all) device bytes for the host;
+    // the host copies are filled by sync()
+    int read(void *host, const void *dev, size_t bytes);
+    int sync();
+    hipStream_t stream() const { return st_; }
+
+private:
+    struct Read {
+        void *host;
+        size_t off, bytes;
+    };
+    hipStream_t st_;
+    int dev_ = -1;
+    std::vector<DevBlock> live_, spare_;
+    std::vector<Read> reads_;
+    char *pinned_ = nullptr;
+    size_t staged_ = 0;
+};
 
 // ---------------------------------------------------------------- codes
 //
@@ -88,7 +139,20 @@ struct sba_handle {
     int64_t bytes;
     double build_ms;
     int device;
+    std::vector<DevBlock> blocks_owned;  // every device array above
 };
+
+// device array of a handle (counted in h->bytes, released by handle_put_all)
+int handle_get(sba_handle *h, void **p, size_t bytes);
+void handle_put_all(sba_handle *h);
+template <typename T>
+inline int handle_alloc(sba_handle *h, T **p, int64_t n)
+{
+    void *q = nullptr;
+    int rc = handle_get(h, &q, (size_t)(n > 0 ? n : 1) * sizeof(T));
+    *p = (T *)q;
+    return rc;
+}
 
 // ---------------------------------------------------------------- helpers
 
@@ -200,12 +264,15 @@ __device__ __forceinline__ int64_t predict_in_leaf(int4 lf, int64_t lo, int64_t 
 
 // Exclusive scan of n int64 values (in and out may alias).  If total is
 // non-null the grand total is written to total[0] (device).
-int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t st);
+// Temporaries come from ws when given, else from the stream-ordered pool.
+int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t st,
+                       Workspace *ws = nullptr);
 
 // LSD radix sort by the low `bits` bits of keys (bits <= 64), stable,
 // carrying the optional 32-bit values.  On return keys/vals hold the sorted
 // data (the library ping-pongs through internal temporaries).
-int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st);
+int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st,
+                   Workspace *ws = nullptr);
 
 // device allocation helper (persistent arrays of a handle)
 template <typename T>
