@@ -31,6 +31,33 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# HBM bytes per launch of the probe, from rocprofv3 counter runs of this
+# kernel version (FETCH_SIZE and WRITE_SIZE per dispatch, KiB, each scaled by
+# what the counter reads for a device copy of known size); keyed by the
+# workload it was taken on.  Re-measure after any change to the kernel.
+TRAFFIC = {
+}
+
+
+def probe_kernel(layout, search, info):
+    if layout == "grid":
+        if info.get("compact"):
+            sub = info.get("sub_log2", 0) < info.get("tile_log2", 0)
+            return f"k_probe_grid16<true, {'true' if sub else 'false'}>"
+        return "k_probe_lds<0, true>" if info["n_polys"] <= 4096 else "k_probe_global<0, true>"
+    lay = 2 if search == "learned" else 1
+    return (f"k_probe_lds<{lay}, true>" if info["n_polys"] <= 4096
+            else f"k_probe_global<{lay}, true>")
+
+
+def traffic_of(args, layout, eps, n, info):
+    key = (args.workload, layout, int(eps), int(n), probe_kernel(layout, args.search or
+                                                                   ("learned" if layout == "hilbert"
+                                                                    else "binary"), info))
+    t = TRAFFIC.get(key)
+    return None if t is None else t["fetch_bytes"] + t["write_bytes"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -47,7 +74,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-sweep", action="store_true", help="skip the eps sweep")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--grid16-per-cu", type=int, default=0,
+                    help="cap on workgroups per CU of the LDS-directory grid probe (0 = none)")
     ap.add_argument("--log2-leaves", type=int, default=16, help="learned index leaves (log2)")
+    ap.add_argument("--tile-log2", type=int, default=0, help="grid tile side log2 (0 = auto)")
+    ap.add_argument("--sub-log2", type=int, default=0, help="grid sub-tile side log2 (0 = auto)")
     ap.add_argument("--force-wide", action="store_true",
                     help="grid probe: 32-bit directory in global memory instead of the LDS copy")
     ap.add_argument("--probe-only", action="store_true",
@@ -69,7 +100,8 @@ def probe_only(args, sba, torch, txy, tv, ro, vo, pxy, eps, layout, search, n):
         torch.cuda.synchronize()
         log(f"[bench] calibration copy: {nb} bytes read, {nb} bytes written")
         del src, dst
-    a = sba.Approx(ro, vo, pxy, eps, kind=layout, search=search, log2_leaves=args.log2_leaves)
+    a = sba.Approx(ro, vo, pxy, eps, kind=layout, search=search, log2_leaves=args.log2_leaves,
+                   tile_log2=args.tile_log2, sub_log2=args.sub_log2)
     counts = torch.empty(a.n_polys, dtype=torch.int64, device="cuda")
     sums = torch.empty(a.n_polys, dtype=torch.int64, device="cuda")
     for _ in range(args.warmup):
@@ -201,6 +233,8 @@ def main():
         sys.exit(1)
     if args.blocks_per_cu:
         sba.lib().sba_debug_set_blocks_per_cu(args.blocks_per_cu)
+    if args.grid16_per_cu:
+        sba.lib().sba_debug_set_grid16_per_cu(args.grid16_per_cu)
     if args.force_wide:
         sba.lib().sba_debug_force_wide_grid(1)
     dev = torch.device("cuda:0")
@@ -229,7 +263,8 @@ def main():
     counts = torch.empty(polys.n_polys, dtype=torch.int64, device=dev)
     sums = torch.empty(polys.n_polys, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
-    kw = dict(kind=layout, search=search, log2_leaves=args.log2_leaves)
+    kw = dict(kind=layout, search=search, log2_leaves=args.log2_leaves, tile_log2=args.tile_log2,
+              sub_log2=args.sub_log2)
     if args.probe_only:
         probe_only(args, sba, torch, txy, tv, ro, vo, pxy, eps, layout, search, n)
         return
@@ -371,8 +406,9 @@ def main():
                    "layout": layout, "search": search if layout == "hilbert" else None,
                    "step": "sba_build_approx + sba_aggregate (COUNT+SUM)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_probe_lds (+ k_reduce)",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_of(args, layout, eps, n, info),
+                     "kernel": probe_kernel(layout, search, info),
                      "algorithmic_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
         "probe_ms": probe_avg,

@@ -26,6 +26,17 @@ void sba_debug_hilbert_cell(int L, uint64_t d, uint32_t *i, uint32_t *j);
  * Process-wide; for launch-shape sweeps. */
 int sba_debug_set_blocks_per_cu(int k);
 
+/* Cap on workgroups per compute unit of the grid probe with the LDS-staged
+ * directory (0: as many as LDS and wave slots allow, the default; 1..4).
+ * Process-wide; for launch-shape sweeps. */
+int sba_debug_set_grid16_per_cu(int k);
+
+/* How the LDS-directory grid probe adds points of multi-polygon cells:
+ * -1 automatic (default), 0 walk the global set table, 1 walk a copy staged
+ * in LDS, 2 one LDS bin per set, expanded once per workgroup.  A mode that
+ * does not fit the LDS falls back to the next one down.  Process-wide. */
+int sba_debug_grid16_sets(int mode);
+
 /* 1: grid builds store the 32-bit format (directory read from global memory
  * by the probes) even where the 16-bit LDS-staged format would fit
  * (comparison runs); 0: default.  Process-wide, read at build time. */

@@ -110,6 +110,10 @@ def lib():
     L.sba_debug_hilbert_cell.restype = None
     L.sba_debug_hilbert_cell.argtypes = [C.c_int, C.c_uint64, C.POINTER(C.c_uint32),
                                          C.POINTER(C.c_uint32)]
+    L.sba_debug_grid16_sets.restype = C.c_int
+    L.sba_debug_grid16_sets.argtypes = [C.c_int]
+    L.sba_debug_set_grid16_per_cu.restype = C.c_int
+    L.sba_debug_set_grid16_per_cu.argtypes = [C.c_int]
     L.sba_debug_force_wide_grid.restype = C.c_int
     L.sba_debug_force_wide_grid.argtypes = [C.c_int]
     L.sba_debug_set_blocks_per_cu.restype = C.c_int

@@ -634,6 +634,8 @@ static void views(const sba_handle *h, GridView *g, HilbView *hv)
 
 // blocks per CU for the streaming probe
 static int g_blocks_per_cu = 8;
+// cap on workgroups per CU of the LDS-directory grid probe (0: none)
+static int g_grid16_per_cu = 0;
 
 template <int LAYOUT>
 static int launch_layout(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
@@ -687,10 +689,13 @@ static int launch_layout(const int32_t *xy, const int64_t *values, int64_t n, co
 // from the fine blocks in global memory, batched 8 points at a time.  The
 // point stream uses non-temporal loads, so it does not evict the blocks.
 
-#define GRID16_BLOCK 512
-
 typedef int v4i_t __attribute__((ext_vector_type(4)));
 typedef long long v2l_t __attribute__((ext_vector_type(2)));
+
+// How a workgroup of the grid probe handles multi-polygon cells:
+#define SETS_GLOBAL 0  // walk the set's members in the global set table
+#define SETS_LDS 1     // walk them in a 16-bit copy of the table staged in LDS
+#define SETS_BINS 2    // one histogram bin per set; expanded once per workgroup
 
 struct Grid16 {
     int64_t ox, oy;
@@ -704,29 +709,51 @@ struct Grid16 {
     const uint32_t *sub;          // short code or TILE_MIXED | fine block (SUB kernels)
     const uint16_t *blocks16;
     uint32_t np;                  // short codes: p+1 polygon p, > np set (code - np - 1)
+    uint32_t sets;                // SETS_*
+    uint32_t n_ids;               // set table ids
+};
+
+// Workgroup-private state of the grid probe in LDS.
+struct Lds16 {
+    const uint16_t *dir;
+    uint32_t *cnt;                // [np] or [np + n_sets] with SETS_BINS
+    unsigned long long *sum;
+    const uint16_t *soff, *sids;  // SETS_LDS
 };
 
 template <bool VALS>
+__device__ __forceinline__ void add_member(uint32_t p, int64_t v, uint32_t np, const Lds16 &L)
+{
+    if (p >= np) return;
+    atomicAdd(&L.cnt[p], 1u);
+    if (VALS) atomicAdd(&L.sum[p], (unsigned long long)v);
+}
+
+template <bool VALS, int SETS>
 __device__ __forceinline__ void add_short(uint32_t sc, int64_t v, const Agg &A, uint32_t np,
-                                          uint32_t *lcnt, unsigned long long *lsum)
+                                          const Lds16 &L)
 {
     if (sc == 0) return;
     if (sc <= np) {
-        atomicAdd(&lcnt[sc - 1], 1u);
-        if (VALS) atomicAdd(&lsum[sc - 1], (unsigned long long)v);
+        atomicAdd(&L.cnt[sc - 1], 1u);
+        if (VALS) atomicAdd(&L.sum[sc - 1], (unsigned long long)v);
+        return;
+    }
+    uint32_t k = sc - np - 1;
+    if (k >= A.n_sets) return;
+    if (SETS == SETS_BINS) {
+        atomicAdd(&L.cnt[np + k], 1u);
+        if (VALS) atomicAdd(&L.sum[np + k], (unsigned long long)v);
+    } else if (SETS == SETS_LDS) {
+        for (uint32_t t = L.soff[k], e = L.soff[k + 1]; t < e; t++)
+            add_member<VALS>(L.sids[t], v, np, L);
     } else {
-        uint32_t k = sc - np - 1;
-        if (k >= A.n_sets) return;
-        for (int64_t t = A.set_off[k], e = A.set_off[k + 1]; t < e; t++) {
-            uint32_t p = (uint32_t)A.set_ids[t];
-            if (p >= np) continue;
-            atomicAdd(&lcnt[p], 1u);
-            if (VALS) atomicAdd(&lsum[p], (unsigned long long)v);
-        }
+        for (int64_t t = A.set_off[k], e = A.set_off[k + 1]; t < e; t++)
+            add_member<VALS>((uint32_t)A.set_ids[t], v, np, L);
     }
 }
 
-// short code of one point (the odd last point, the batched loop's tail)
+// short code of one point (the odd last point)
 template <bool SUB>
 __device__ __forceinline__ uint32_t grid16_code(const Grid16 &g, const uint16_t *ldir, int32_t x,
                                                 int32_t y)
@@ -752,27 +779,43 @@ __device__ __forceinline__ uint32_t grid16_code(const Grid16 &g, const uint16_t 
     return g.blocks16[((uint64_t)b << (2 * fl)) + (((j & m) << fl) | (i & m))];
 }
 
-template <bool VALS, bool SUB>
-__global__ __launch_bounds__(GRID16_BLOCK) void k_probe_grid16(const int4 *__restrict__ xy4,
-                                                              const longlong2 *__restrict__ v2,
-                                                              const int32_t *__restrict__ xy,
-                                                              const int64_t *__restrict__ vals,
-                                                              int64_t n, Grid16 g, Agg A,
-                                                              uint64_t *__restrict__ counts,
-                                                              int64_t *__restrict__ sums)
+template <bool VALS, bool SUB, int SETS, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_probe_grid16(const int4 *__restrict__ xy4,
+                                                        const longlong2 *__restrict__ v2,
+                                                        const int32_t *__restrict__ xy,
+                                                        const int64_t *__restrict__ vals,
+                                                        int64_t n, Grid16 g, Agg A,
+                                                        uint64_t *__restrict__ counts,
+                                                        int64_t *__restrict__ sums)
 {
+    // LDS: directory (nt16 entries, a multiple of 8), sums (u64 [nb]), counts
+    // (u32 [nb]) with nb = np (+ n_sets with SETS_BINS), then with SETS_LDS
+    // the set table (u16 [n_sets + 1], u16 [n_ids]).  Every pointer is formed
+    // by pointer arithmetic on the shared array, so the compiler keeps LDS
+    // instructions for all of them.
     extern __shared__ unsigned long long smem[];
     const uint32_t np = g.np;
-    unsigned long long *lsum = smem;
-    uint32_t *lcnt = (uint32_t *)(smem + np);
-    uint16_t *ldir = (uint16_t *)(((uintptr_t)(lcnt + np) + 15) & ~(uintptr_t)15);
+    const uint32_t nbins = np + (SETS == SETS_BINS ? A.n_sets : 0u);
+    Lds16 L;
+    uint16_t *ldir = (uint16_t *)smem;
+    L.dir = ldir;
+    L.sum = smem + g.nt16 / 4;
+    L.cnt = (uint32_t *)(L.sum + nbins);
+    L.soff = (const uint16_t *)(L.cnt + nbins);
+    L.sids = L.soff + A.n_sets + 1;
     {
         const uint4 *src = (const uint4 *)g.dir16;
         uint4 *dst = (uint4 *)ldir;
-        for (uint32_t q = threadIdx.x; q < g.nt16 / 8; q += GRID16_BLOCK) dst[q] = src[q];
-        for (uint32_t p = threadIdx.x; p < np; p += GRID16_BLOCK) {
-            lcnt[p] = 0;
-            lsum[p] = 0;
+        for (uint32_t q = threadIdx.x; q < g.nt16 / 8; q += BLOCK) dst[q] = src[q];
+        for (uint32_t p = threadIdx.x; p < nbins; p += BLOCK) {
+            L.cnt[p] = 0;
+            L.sum[p] = 0;
+        }
+        if (SETS == SETS_LDS) {
+            uint16_t *so = (uint16_t *)L.soff, *si = (uint16_t *)L.sids;
+            for (uint32_t k = threadIdx.x; k <= A.n_sets; k += BLOCK)
+                so[k] = (uint16_t)A.set_off[k];
+            for (uint32_t t = threadIdx.x; t < g.n_ids; t += BLOCK) si[t] = (uint16_t)A.set_ids[t];
         }
     }
     __syncthreads();
@@ -780,8 +823,8 @@ __global__ __launch_bounds__(GRID16_BLOCK) void k_probe_grid16(const int4 *__res
     const int fl = SUB ? g.sl : g.tl;
     const uint32_t m = (1u << fl) - 1u, mq = (1u << qs) - 1u;
     const int64_t npairs = n >> 1;
-    const int64_t stride = (int64_t)gridDim.x * GRID16_BLOCK;
-    for (int64_t t0 = (int64_t)blockIdx.x * GRID16_BLOCK + threadIdx.x; t0 < npairs;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    for (int64_t t0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t0 < npairs;
          t0 += stride * PROBE_UNROLL) {
         v4i_t q[PROBE_UNROLL];
         v2l_t vv[PROBE_UNROLL];
@@ -842,30 +885,89 @@ __global__ __launch_bounds__(GRID16_BLOCK) void k_probe_grid16(const int4 *__res
 #pragma unroll
         for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
             uint32_t sc = fb[k] != ~0u ? f[k] : v[k];
-            add_short<VALS>(sc, (k & 1) ? vv[k >> 1].y : vv[k >> 1].x, A, np, lcnt, lsum);
+            add_short<VALS, SETS>(sc, (k & 1) ? vv[k >> 1].y : vv[k >> 1].x, A, np, L);
         }
     }
     if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
         int64_t k = n - 1;
         uint32_t sc = grid16_code<SUB>(g, ldir, xy[2 * k], xy[2 * k + 1]);
-        add_short<VALS>(sc, VALS ? vals[k] : 0, A, np, lcnt, lsum);
+        add_short<VALS, SETS>(sc, VALS ? vals[k] : 0, A, np, L);
     }
     __syncthreads();
-    flush_bins<VALS>(lcnt, lsum, np, GRID16_BLOCK, counts, sums);
+    if (SETS == SETS_BINS) {
+        // each set's bin goes to its members' bins
+        for (uint32_t k = threadIdx.x; k < A.n_sets; k += BLOCK) {
+            uint32_t c = L.cnt[np + k];
+            if (c == 0) continue;
+            unsigned long long sv = VALS ? L.sum[np + k] : 0ull;
+            for (int64_t t = A.set_off[k], e = A.set_off[k + 1]; t < e; t++) {
+                uint32_t p = (uint32_t)A.set_ids[t];
+                if (p >= np) continue;
+                atomicAdd(&L.cnt[p], c);
+                if (VALS) atomicAdd(&L.sum[p], sv);
+            }
+        }
+        __syncthreads();
+    }
+    flush_bins<VALS>(L.cnt, L.sum, np, BLOCK, counts, sums);
 }
 
-// LDS of the grid probe: histograms (12 B per polygon) + the 16-bit directory
+#define GRID16_LDS_MAX (160 * 1024)
+#define GRID16_SETS_MAX (16 * 1024)  // largest set table staged in LDS (bytes)
+
+static size_t grid16_dir_lds(const sba_handle *h)
+{
+    return (size_t)(((h->tw * h->th) + 7) & ~(int64_t)7) * 2;
+}
+
+// set handling and LDS bytes of the grid probe for a handle: bins when
+// directory + (polygons + sets) bins fit, else the staged table when it
+// fits, else the global table
+static int g_grid16_sets = -1;  // forced SETS_* mode (when it fits), -1: automatic
+
+static int grid16_mode(const sba_handle *h, size_t *lds)
+{
+    const size_t dir = grid16_dir_lds(h), np = (size_t)h->n_polys, ns = (size_t)h->n_sets;
+    const int want = g_grid16_sets;
+    if ((want < 0 || want == SETS_BINS) && ns > 0 && dir + (np + ns) * 12 <= GRID16_LDS_MAX) {
+        *lds = dir + (np + ns) * 12;
+        return SETS_BINS;
+    }
+    const size_t table = (ns + 1 + (size_t)h->n_set_ids) * 2;
+    if ((want < 0 || want == SETS_LDS) && ns > 0 && h->n_set_ids < 0xffff &&
+        table <= GRID16_SETS_MAX && dir + np * 12 + table <= GRID16_LDS_MAX) {
+        *lds = dir + np * 12 + table;
+        return SETS_LDS;
+    }
+    *lds = dir + np * 12;
+    return SETS_GLOBAL;
+}
+
 static size_t grid16_lds(const sba_handle *h)
 {
-    const size_t nt16 = (size_t)(((h->tw * h->th) + 7) & ~(int64_t)7);
-    return (size_t)h->n_polys * 12 + 16 + nt16 * 2;
+    size_t lds = 0;
+    (void)grid16_mode(h, &lds);
+    return lds;
 }
-#define GRID16_LDS_MAX (160 * 1024)
 
-template <bool SUB>
-static void grid16_kernels(bool vals, const void **k)
+typedef void (*grid16_fn)(const int4 *, const longlong2 *, const int32_t *, const int64_t *,
+                          int64_t, Grid16, Agg, uint64_t *, int64_t *);
+
+template <bool VALS, bool SUB, int BLOCK>
+static grid16_fn grid16_pick_sets(int sets)
 {
-    *k = vals ? (const void *)k_probe_grid16<true, SUB> : (const void *)k_probe_grid16<false, SUB>;
+    if (sets == SETS_BINS) return k_probe_grid16<VALS, SUB, SETS_BINS, BLOCK>;
+    if (sets == SETS_LDS) return k_probe_grid16<VALS, SUB, SETS_LDS, BLOCK>;
+    return k_probe_grid16<VALS, SUB, SETS_GLOBAL, BLOCK>;
+}
+
+template <int BLOCK>
+static grid16_fn grid16_pick(bool vals, bool sub, int sets)
+{
+    if (vals) return sub ? grid16_pick_sets<true, true, BLOCK>(sets)
+                         : grid16_pick_sets<true, false, BLOCK>(sets);
+    return sub ? grid16_pick_sets<false, true, BLOCK>(sets)
+               : grid16_pick_sets<false, false, BLOCK>(sets);
 }
 
 static int launch_grid16(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
@@ -886,40 +988,36 @@ static int launch_grid16(const int32_t *xy, const int64_t *values, int64_t n, co
     g.sub = h->sub;
     g.blocks16 = h->blocks16;
     g.np = (uint32_t)h->n_polys;
+    size_t lds = 0;
+    g.sets = (uint32_t)grid16_mode(h, &lds);
+    g.n_ids = (uint32_t)h->n_set_ids;
     Agg A{h->set_off, h->set_ids, (uint32_t)h->n_polys, (uint32_t)h->n_sets};
     const int32_t np = h->n_polys;
     const bool vals = values != nullptr && sums != nullptr;
     const bool sub = h->sub_log2 < h->tile_log2;
-    const size_t lds = grid16_lds(h);
-    const int per_cu = lds <= 72 * 1024 ? 2 : 1;
+    // 16 or more waves per CU: workgroups of 512 threads when two fit in the
+    // LDS (up to four, as LDS and the 32 wave slots allow), else one of 1024
+    // threads per CU
+    int block = 512;
+    int per_cu = (int)std::min<size_t>((size_t)GRID16_LDS_MAX / lds, 4);
+    if (g_grid16_per_cu > 0) per_cu = std::min(per_cu, g_grid16_per_cu);
+    if (per_cu < 2) {
+        block = 1024;
+        per_cu = 1;
+    }
     const int64_t npairs = n >> 1;
-    int64_t nb = std::min<int64_t>((npairs + GRID16_BLOCK - 1) / GRID16_BLOCK,
-                                   (int64_t)cu_count() * per_cu);
+    int64_t nb = std::min<int64_t>((npairs + block - 1) / block, (int64_t)cu_count() * per_cu);
     if (nb < 1) nb = 1;
-    const void *kern = nullptr;
-    if (sub) grid16_kernels<true>(vals, &kern);
-    else grid16_kernels<false>(vals, &kern);
+    grid16_fn kern = block == 512 ? grid16_pick<512>(vals, sub, (int)g.sets)
+                                  : grid16_pick<1024>(vals, sub, (int)g.sets);
     // dynamic LDS above 64 KB has to be allowed explicitly
-    (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_zero_out, dim3(grid_for(np)), dim3(256), 0, st, counts,
                        vals ? sums : nullptr, np);
-    if (sub && vals)
-        hipLaunchKernelGGL((k_probe_grid16<true, true>), dim3((unsigned)nb), dim3(GRID16_BLOCK),
-                           lds, st, (const int4 *)xy, (const longlong2 *)values, xy, values, n, g,
-                           A, counts, sums);
-    else if (sub)
-        hipLaunchKernelGGL((k_probe_grid16<false, true>), dim3((unsigned)nb), dim3(GRID16_BLOCK),
-                           lds, st, (const int4 *)xy, (const longlong2 *)values, xy, values, n, g,
-                           A, counts, sums);
-    else if (vals)
-        hipLaunchKernelGGL((k_probe_grid16<true, false>), dim3((unsigned)nb), dim3(GRID16_BLOCK),
-                           lds, st, (const int4 *)xy, (const longlong2 *)values, xy, values, n, g,
-                           A, counts, sums);
-    else
-        hipLaunchKernelGGL((k_probe_grid16<false, false>), dim3((unsigned)nb), dim3(GRID16_BLOCK),
-                           lds, st, (const int4 *)xy, (const longlong2 *)values, xy, values, n, g,
-                           A, counts, sums);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(block), lds, st, (const int4 *)xy,
+                       (const longlong2 *)values, xy, values, n, g, A, counts, sums);
     return hipGetLastError() != hipSuccess ? SBA_EDEVICE : 0;
 }
 
@@ -962,6 +1060,20 @@ int lookup_launch(const sba_handle *h, const int64_t *ij, int64_t n, int32_t *re
         hipLaunchKernelGGL(k_lookup<1>, dim3(grid_for(n)), dim3(256), 0, st, ij, n, g, hv, h->gi0,
                            h->gj0, h->gw, h->gh, h->s, ref);
     HIP_OK(hipGetLastError());
+    return 0;
+}
+
+extern "C" int sba_debug_grid16_sets(int mode)
+{
+    if (mode < -1 || mode > SETS_BINS) return SBA_EINVAL;
+    g_grid16_sets = mode;
+    return 0;
+}
+
+extern "C" int sba_debug_set_grid16_per_cu(int k)
+{
+    if (k < 0 || k > 4) return SBA_EINVAL;
+    g_grid16_per_cu = k;
     return 0;
 }
 

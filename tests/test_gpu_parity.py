@@ -332,3 +332,26 @@ def test_sub_level_rejects_bad_split(sba):
     for tl, sl in ((5, 6), (6, 1)):
         with pytest.raises(RuntimeError):
             sba.Approx.from_polygons(polys, 5, tile_log2=tl, sub_log2=sl)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("eps,tl,sl", [(1000, 5, 5), (1000, 5, 3), (100, 0, 0)])
+def test_set_modes_of_grid_probe(sba, orc, mode, eps, tl, sl):
+    """Points in multi-polygon cells are added the same way whether the probe
+    walks the global set table, a copy in LDS, or keeps one bin per set (at
+    1 m the bins do not fit and every mode falls back)."""
+    from gen import city_polygons
+    polys = city_polygons()
+    xy, vals = city_points(1_000_001)
+    want_c, want_s = orc.Approx(polys, eps).aggregate(xy, vals)
+    A = sba.Approx.from_polygons(polys, eps, tile_log2=tl, sub_log2=sl)
+    assert A.info()["n_sets"] > 0
+    sba.lib().sba_debug_grid16_sets(mode)
+    try:
+        c, s = run_agg(A, xy, vals)
+        c2, _ = run_agg(A, xy, None)
+    finally:
+        sba.lib().sba_debug_grid16_sets(-1)
+    np.testing.assert_array_equal(c, want_c)
+    np.testing.assert_array_equal(s, want_s)
+    np.testing.assert_array_equal(c2, want_c)
