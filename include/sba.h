@@ -75,14 +75,16 @@ typedef struct {
     int32_t search;       /* Hilbert only: SBA_SEARCH_BINARY (default) or _LEARNED       */
     int32_t log2_leaves;  /* learned index: number of leaves = 2^log2_leaves (0 -> 16)   */
     int32_t tile_log2;    /* grid: tile side 2^tile_log2 cells, 2..10 (0 -> the smallest
-                             tile whose 16-bit directory fits 64 KB)                      */
+                             tile whose 16-bit directory, with 12 B per polygon and per
+                             polygon set, fits the 160 KB LDS of a compute unit)          */
     int32_t use_window;   /* 1: store only the cells that overlap the clip window        */
     int32_t win_x0, win_y0, win_x1, win_y1;  /* clip window [x0,x1) x [y0,y1), coordinates;
                              cells outside it are empty in the handle (for viewport
                              queries: the answer inside the window is unchanged)         */
     int32_t sub_log2;     /* grid: sub-tile side 2^sub_log2 cells inside mixed tiles,
                              2..tile_log2; == tile_log2: mixed tiles are stored cell by
-                             cell (0 -> 4 for tiles of 64 cells or more, else tile_log2) */
+                             cell (0 -> 4 for tiles of 64 cells or more, 3 for tiles of
+                             32 cells, else tile_log2)                                   */
 } sba_build_opts;
 
 typedef struct {

@@ -1006,14 +1006,32 @@ static void classify(const BuildState &B, const sba_handle *h, const int64_t *mt
 int build_grid(sba_handle *h, BuildState &B, int tile_log2, int sub_log2, hipStream_t st)
 {
     int tl = tile_log2;
-    if (tl == 0) {  // smallest tile whose 16-bit directory fits 64 KB of LDS
+    if (tl == 0) {
+        // the smallest tile whose 16-bit directory, with the probe's LDS bins
+        // (12 B per polygon and per set), fits the LDS of a compute unit: the
+        // finer the directory, the fewer points need a lookup in global memory
+        auto tiles = [&](int t) {
+            return ((h->gw + (1 << t) - 1) >> t) * ((h->gh + (1 << t) - 1) >> t);
+        };
+        auto fits = [&](int t, int64_t bins) {
+            int64_t nt16 = (tiles(t) + 7) & ~(int64_t)7;
+            return tiles(t) <= COMPACT_DIR_TILES_MAX && nt16 * 2 + bins * 12 <= PROBE_LDS_BYTES;
+        };
+        const int64_t all = (int64_t)h->n_polys + h->n_sets;
         tl = 2;
-        while (tl < 10 && ((h->gw + (1 << tl) - 1) >> tl) * ((h->gh + (1 << tl) - 1) >> tl) >
-                              COMPACT_DIR_TILES)
-            tl++;
+        while (tl < 10 && !fits(tl, all)) tl++;
+        if (!fits(tl, all)) {  // set bins never fit: directory and polygon bins
+            tl = 2;
+            while (tl < 10 && !fits(tl, h->n_polys)) tl++;
+            if (!fits(tl, h->n_polys)) {  // polygon bins do not fit either
+                tl = 2;
+                while (tl < 10 && tiles(tl) > COMPACT_DIR_TILES) tl++;
+            }
+        }
     }
     if (tl < 2 || tl > 10) return SBA_EINVAL;
-    int sl = sub_log2 ? sub_log2 : (tl >= 6 ? 4 : tl);  // sub-tiles of 16 x 16 under big tiles
+    // sub-tiles of 16 x 16 cells under big tiles, of 8 x 8 under tiles of 32
+    int sl = sub_log2 ? sub_log2 : (tl >= 6 ? 4 : (tl == 5 ? 3 : tl));
     if (sl < 2 || sl > tl) return SBA_EINVAL;
     h->tile_log2 = tl;
     h->sub_log2 = sl;

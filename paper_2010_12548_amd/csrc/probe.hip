@@ -912,7 +912,7 @@ __global__ __launch_bounds__(BLOCK) void k_probe_grid16(const int4 *__restrict__
     flush_bins<VALS>(L.cnt, L.sum, np, BLOCK, counts, sums);
 }
 
-#define GRID16_LDS_MAX (160 * 1024)
+#define GRID16_LDS_MAX PROBE_LDS_BYTES
 #define GRID16_SETS_MAX (16 * 1024)  // largest set table staged in LDS (bytes)
 
 static size_t grid16_dir_lds(const sba_handle *h)

@@ -76,8 +76,9 @@ private:
 #define MAX_POLYS ((1 << 21) - 1)
 #define MAX_DEPTH 32           // polygons per cell
 #define MAX_GRID_SIDE (1 << 21)
-#define COMPACT_DIR_TILES 32768       // default tile size: directory <= 64 KB at 16 bits
+#define COMPACT_DIR_TILES 32768       // directory <= 64 KB at 16 bits
 #define COMPACT_DIR_TILES_MAX 65536   // 16-bit directory still staged in LDS up to 128 KB
+#define PROBE_LDS_BYTES (160 * 1024)  // LDS of one compute unit (gfx950)
 
 __host__ __device__ inline int32_t code_to_ref(uint32_t c)
 {
