@@ -702,6 +702,8 @@ struct Grid16 {
     uint32_t extx, exty;
     uint32_t mag;
     int32_t shift;
+    // floor(n / s) = mul_hi(n << pre, mag) >> post (see grid16_div)
+    uint32_t pre, post;
     int32_t tl, sl;               // tile / sub-tile side log2
     uint32_t tw;
     uint32_t nt16;                // directory entries, a multiple of 8
@@ -824,21 +826,22 @@ __global__ __launch_bounds__(BLOCK) void k_probe_grid16(const int4 *__restrict__
     const uint32_t m = (1u << fl) - 1u, mq = (1u << qs) - 1u;
     const int64_t npairs = n >> 1;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    const int64_t tlast = npairs - 1;
+    const uint32_t ox = (uint32_t)g.ox, oy = (uint32_t)g.oy;
     for (int64_t t0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t0 < npairs;
          t0 += stride * PROBE_UNROLL) {
+        // loads without branches: a lane past the end re-reads the last pair
+        // (in bounds, as t0 < npairs) and drops it below
         v4i_t q[PROBE_UNROLL];
         v2l_t vv[PROBE_UNROLL];
+        bool in[PROBE_UNROLL];
 #pragma unroll
         for (int u = 0; u < PROBE_UNROLL; u++) {
             int64_t t = t0 + (int64_t)u * stride;
-            if (t < npairs) {
-                q[u] = __builtin_nontemporal_load((const v4i_t *)(xy4 + t));
-                if (VALS) vv[u] = __builtin_nontemporal_load((const v2l_t *)(v2 + t));
-                else vv[u] = v2l_t{0, 0};
-            } else {
-                q[u] = v4i_t{INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN};
-                vv[u] = v2l_t{0, 0};
-            }
+            in[u] = t < npairs;
+            int64_t tc = in[u] ? t : tlast;
+            q[u] = __builtin_nontemporal_load((const v4i_t *)(xy4 + tc));
+            vv[u] = VALS ? __builtin_nontemporal_load((const v2l_t *)(v2 + tc)) : v2l_t{0, 0};
         }
         // level 1 from LDS; levels 2 and 3 as batched global loads (a point
         // that needs no load there re-reads element 0, a cache hit)
@@ -848,10 +851,15 @@ __global__ __launch_bounds__(BLOCK) void k_probe_grid16(const int4 *__restrict__
         for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
             int32_t x = (k & 1) ? q[k >> 1].z : q[k >> 1].x;
             int32_t y = (k & 1) ? q[k >> 1].w : q[k >> 1].y;
-            int64_t dx = (int64_t)x - g.ox, dy = (int64_t)y - g.oy;
-            ok[k] = (uint64_t)dx < g.extx && (uint64_t)dy < g.exty;
-            uint32_t i = divmagic(ok[k] ? (uint32_t)dx : 0u, g.mag, g.shift);
-            uint32_t j = divmagic(ok[k] ? (uint32_t)dy : 0u, g.mag, g.shift);
+            // offsets from the box origin modulo 2^32: the stored box lies
+            // inside (-2^30 - 2^29, 2^30 + 2^28) (polygon coordinates below
+            // 2^30 in magnitude, cells below 2^28), so no int32 point is 2^32
+            // away from a position in the box, and the wrapped offset is
+            // below ext exactly when the point is in the box
+            uint32_t dx = (uint32_t)x - ox, dy = (uint32_t)y - oy;
+            ok[k] = in[k >> 1] && dx < g.extx && dy < g.exty;
+            uint32_t i = __umulhi((ok[k] ? dx : 0u) << g.pre, g.mag) >> g.post;
+            uint32_t j = __umulhi((ok[k] ? dy : 0u) << g.pre, g.mag) >> g.post;
             e[k] = ldir[(j >> g.tl) * g.tw + (i >> g.tl)];
             lo[k] = ((j & m) << fl) | (i & m);
             if (SUB) sq[k] = (((j >> g.sl) & mq) << qs) | ((i >> g.sl) & mq);
@@ -980,6 +988,10 @@ static int launch_grid16(const int32_t *xy, const int64_t *values, int64_t n, co
     g.exty = (uint32_t)(h->gh * h->s);
     g.mag = h->mag;
     g.shift = h->shift;
+    // shift >= 32 (s >= 2): floor(floor(n m / 2^32) / 2^(shift-32)); shift 31
+    // (s = 1, m = 2^31): mul_hi(2n, 2^31) = n
+    g.pre = h->shift >= 32 ? 0u : 1u;
+    g.post = h->shift >= 32 ? (uint32_t)(h->shift - 32) : 0u;
     g.tl = h->tile_log2;
     g.sl = h->sub_log2;
     g.tw = (uint32_t)h->tw;

@@ -173,9 +173,13 @@ __host__ __device__ inline int64_t ceildiv64(int64_t a, int64_t b)  // b > 0
 // (Granlund & Montgomery 1994, "Division by invariant integers using
 // multiplication", Thm. 4.2 with N = 31): with l = ceil(log2 s) and
 // m = ceil(2^(31+l) / s) < 2^32, floor(n / s) = (n * m) >> (31 + l).
+// Since floor(floor(a / 2^32) / 2^k) = floor(a / 2^(32+k)), a shift of 32 or
+// more is a high-half multiply and a short shift; shift 31 only occurs for
+// s = 1.
 __host__ __device__ inline uint32_t divmagic(uint32_t n, uint32_t mag, int32_t shift)
 {
-    return (uint32_t)(((uint64_t)n * mag) >> shift);
+    if (shift < 32) return (uint32_t)(((uint64_t)n * mag) >> shift);
+    return (uint32_t)(((uint64_t)n * mag) >> 32) >> (shift - 32);
 }
 
 void magic_for(int64_t s, uint32_t *mag, int32_t *shift);

@@ -355,3 +355,21 @@ def test_set_modes_of_grid_probe(sba, orc, mode, eps, tl, sl):
     np.testing.assert_array_equal(c, want_c)
     np.testing.assert_array_equal(s, want_s)
     np.testing.assert_array_equal(c2, want_c)
+
+
+@pytest.mark.parametrize("eps", [2, 3, 4])
+def test_unit_and_small_cells_aggregate(sba, orc, eps):
+    """Cell side 1 (eps = 2: the probe's division by one) and side 2 (eps 3
+    and 4): the aggregates equal the oracle's."""
+    polys = star_polygons(8, 10, 5.0, 60.0, 300, 41)
+    rng = np.random.default_rng(eps)
+    n = 100_003
+    xy = rng.integers(-20, 330, size=2 * n).astype(np.int32)
+    vals = rng.integers(-1000, 1000, size=n).astype(np.int64)
+    O = orc.Approx(polys, eps)
+    A = sba.Approx.from_polygons(polys, eps)
+    assert A.info()["s"] == O.s
+    want_c, want_s = O.aggregate(xy, vals)
+    c, s = run_agg(A, xy, vals)
+    np.testing.assert_array_equal(c, want_c)
+    np.testing.assert_array_equal(s, want_s)
