@@ -36,25 +36,15 @@ def log(*a):
 # what the counter reads for a device copy of known size); keyed by the
 # workload it was taken on.  Re-measure after any change to the kernel.
 TRAFFIC = {
+    # profiles/city_eps10m_probe_counters.md: FETCH_SIZE 800568.97 KiB (x 1.99993: a 1 GiB
+    # device copy reads 524306.5 KiB), WRITE_SIZE 2080 KiB (x 1.00000)
+    ("city", 1000, 100_000_000, "k_probe_grid16<true, true, 2, 512>"):
+        {"fetch_bytes": 1639507396, "write_bytes": 2129920},
 }
 
 
-def probe_kernel(layout, search, info):
-    if layout == "grid":
-        if info.get("compact"):
-            sub = info.get("sub_log2", 0) < info.get("tile_log2", 0)
-            return f"k_probe_grid16<true, {'true' if sub else 'false'}>"
-        return "k_probe_lds<0, true>" if info["n_polys"] <= 4096 else "k_probe_global<0, true>"
-    lay = 2 if search == "learned" else 1
-    return (f"k_probe_lds<{lay}, true>" if info["n_polys"] <= 4096
-            else f"k_probe_global<{lay}, true>")
-
-
-def traffic_of(args, layout, eps, n, info):
-    key = (args.workload, layout, int(eps), int(n), probe_kernel(layout, args.search or
-                                                                   ("learned" if layout == "hilbert"
-                                                                    else "binary"), info))
-    t = TRAFFIC.get(key)
+def traffic_of(workload, eps, n, kernel):
+    t = TRAFFIC.get((workload, int(eps), int(n), kernel))
     return None if t is None else t["fetch_bytes"] + t["write_bytes"]
 
 
@@ -292,17 +282,39 @@ def main():
     t_total = time.perf_counter() - t_start
     probe_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
     info = handles[-1].info()
-    build_ms = [h.info()["build_ms"] for h in handles]
+    kernel = handles[-1].probe_kernel(True)
+    ms_step = 1000.0 * t_total / args.steps
+    probe_in_step = float(np.mean(probe_ms))
+    alg_bytes = 16.0 * n          # 8 B x,y + 8 B value per point
+    # the probe kernel's own time: back-to-back calls on the current stream
+    # between one pair of events (the per-step events above also hold the
+    # launch gaps of a step); each call is a zeroing kernel of the outputs
+    # (a few microseconds) and the probe kernel
+    last = handles[-1]
+    reps = max(args.steps, 10)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        last.aggregate(txy, tv, counts, sums)
+    e1.record()
+    torch.cuda.synchronize()
+    probe_avg = e0.elapsed_time(e1) / reps
+    achieved = alg_bytes / (probe_avg * 1e-3) / 1e9
+    # build time on its own (inside the step loop a build's first wait also
+    # covers the previous step's probe)
+    iso = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a = sba.Approx(ro, vo, pxy, eps, **kw)
+        iso.append(1000.0 * (time.perf_counter() - t0))
+        a.close()
+    build_iso = float(np.median(iso))
+    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, probe in step {probe_in_step:.4f} ms, "
+        f"probe back-to-back {probe_avg:.4f} ms, build alone median {build_iso:.3f} ms")
+
     for h in handles:
         h.close()
-    ms_step = 1000.0 * t_total / args.steps
-    probe_avg = float(np.mean(probe_ms))
-    probe_med = float(np.median(probe_ms))
-    alg_bytes = 16.0 * n          # 8 B x,y + 8 B value per point
-    achieved = alg_bytes / (probe_avg * 1e-3) / 1e9
-    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, probe avg {probe_avg:.4f} ms "
-        f"(median {probe_med:.4f}), build median {np.median(build_ms):.3f} ms")
-
     res_c = counts.cpu().numpy().astype(np.uint64)
     res_s = sums.cpu().numpy()
 
@@ -407,13 +419,14 @@ def main():
                    "step": "sba_build_approx + sba_aggregate (COUNT+SUM)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic_of(args, layout, eps, n, info),
-                     "kernel": probe_kernel(layout, search, info),
+                     "traffic": traffic_of(args.workload, eps, n, kernel),
+                     "kernel": kernel,
                      "algorithmic_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
         "probe_ms": probe_avg,
+        "probe_ms_in_step": probe_in_step,
         "probe_points_per_s": n / (probe_avg * 1e-3),
-        "build_ms_median": float(np.median(build_ms)),
+        "build_ms_median": build_iso,
         "approx": {k: info[k] for k in ("s", "gw", "gh", "tile_log2", "n_tiles", "n_blocks",
                                         "n_sets", "n_segments", "n_boundary", "n_runs", "bytes")},
         "eps_sweep": sweep or None,

@@ -236,6 +236,13 @@ int sba_get_runs(const sba_handle *h, uint64_t *starts, int32_t *ids, void *stre
 /* Handle metadata (host struct). */
 int sba_info(const sba_handle *h, sba_info_t *info);
 
+/* Name of the probe kernel that sba_aggregate launches for h, with values
+ * (with_values != 0) or counts only, as profilers list it (template
+ * arguments, no parameters).  Static per-thread storage, valid until the
+ * next call on the same thread; "" for a null handle or one without
+ * polygons. */
+const char *sba_probe_kernel(const sba_handle *h, int with_values);
+
 /* Release the handle's device memory.  The caller must make sure no work
  * using the handle is still queued (synchronise its streams first). */
 void sba_free(sba_handle *h);

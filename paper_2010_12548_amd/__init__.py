@@ -110,6 +110,8 @@ def lib():
     L.sba_debug_hilbert_cell.restype = None
     L.sba_debug_hilbert_cell.argtypes = [C.c_int, C.c_uint64, C.POINTER(C.c_uint32),
                                          C.POINTER(C.c_uint32)]
+    L.sba_probe_kernel.restype = C.c_char_p
+    L.sba_probe_kernel.argtypes = [C.c_void_p, C.c_int]
     L.sba_debug_grid16_sets.restype = C.c_int
     L.sba_debug_grid16_sets.argtypes = [C.c_int]
     L.sba_debug_set_grid16_per_cu.restype = C.c_int
@@ -220,6 +222,10 @@ class Approx:
             self.close()
         except Exception:
             pass
+
+    def probe_kernel(self, with_values: bool = True) -> str:
+        """Name of the kernel aggregate() launches (as profilers list it)."""
+        return lib().sba_probe_kernel(self._h, 1 if with_values else 0).decode()
 
     def info(self) -> dict:
         inf = _Info()

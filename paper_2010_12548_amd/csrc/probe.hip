@@ -17,6 +17,8 @@
 //            sub-tiles the cell's code in a fine block;
 //   hilbert  Hilbert key of the cell, then the run holding it: binary search
 //            over the run starts, or the learned index's bounded search.
+#include <stdio.h>
+
 #include <algorithm>
 #include <vector>
 
@@ -634,8 +636,7 @@ static void views(const sba_handle *h, GridView *g, HilbView *hv)
 
 // blocks per CU for the streaming probe
 static int g_blocks_per_cu = 8;
-// cap on workgroups per CU of the LDS-directory grid probe (0: none)
-static int g_grid16_per_cu = 0;
+
 
 template <int LAYOUT>
 static int launch_layout(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
@@ -921,6 +922,8 @@ __global__ __launch_bounds__(BLOCK) void k_probe_grid16(const int4 *__restrict__
 }
 
 #define GRID16_LDS_MAX PROBE_LDS_BYTES
+// cap on workgroups per CU of the LDS-directory grid probe (0: none)
+static int g_grid16_per_cu = 0;
 #define GRID16_SETS_MAX (16 * 1024)  // largest set table staged in LDS (bytes)
 
 static size_t grid16_dir_lds(const sba_handle *h)
@@ -956,6 +959,17 @@ static size_t grid16_lds(const sba_handle *h)
     size_t lds = 0;
     (void)grid16_mode(h, &lds);
     return lds;
+}
+
+// 16 or more waves per CU: workgroups of 512 threads when two fit in the LDS
+// (up to four, as LDS and the 32 wave slots allow), else one of 1024 threads
+// per CU
+static void grid16_shape(size_t lds, int *block, int *per_cu)
+{
+    int k = (int)std::min<size_t>((size_t)GRID16_LDS_MAX / lds, 4);
+    if (g_grid16_per_cu > 0) k = std::min(k, g_grid16_per_cu);
+    *block = k < 2 ? 1024 : 512;
+    *per_cu = k < 2 ? 1 : k;
 }
 
 typedef void (*grid16_fn)(const int4 *, const longlong2 *, const int32_t *, const int64_t *,
@@ -1007,16 +1021,8 @@ static int launch_grid16(const int32_t *xy, const int64_t *values, int64_t n, co
     const int32_t np = h->n_polys;
     const bool vals = values != nullptr && sums != nullptr;
     const bool sub = h->sub_log2 < h->tile_log2;
-    // 16 or more waves per CU: workgroups of 512 threads when two fit in the
-    // LDS (up to four, as LDS and the 32 wave slots allow), else one of 1024
-    // threads per CU
-    int block = 512;
-    int per_cu = (int)std::min<size_t>((size_t)GRID16_LDS_MAX / lds, 4);
-    if (g_grid16_per_cu > 0) per_cu = std::min(per_cu, g_grid16_per_cu);
-    if (per_cu < 2) {
-        block = 1024;
-        per_cu = 1;
-    }
+    int block = 0, per_cu = 0;
+    grid16_shape(lds, &block, &per_cu);
     const int64_t npairs = n >> 1;
     int64_t nb = std::min<int64_t>((npairs + block - 1) / block, (int64_t)cu_count() * per_cu);
     if (nb < 1) nb = 1;
@@ -1073,6 +1079,27 @@ int lookup_launch(const sba_handle *h, const int64_t *ij, int64_t n, int32_t *re
                            h->gj0, h->gw, h->gh, h->s, ref);
     HIP_OK(hipGetLastError());
     return 0;
+}
+
+// Name of the kernel an aggregate call on h launches (as profilers print it,
+// without arguments).
+extern "C" const char *sba_probe_kernel(const sba_handle *h, int with_values)
+{
+    static thread_local char buf[96];
+    if (!h || h->n_polys == 0) return "";
+    const char *v = with_values ? "true" : "false";
+    if (h->kind == SBA_KIND_GRID && h->compact && grid16_lds(h) <= GRID16_LDS_MAX) {
+        size_t lds = 0;
+        int sets = grid16_mode(h, &lds), block = 0, per_cu = 0;
+        grid16_shape(lds, &block, &per_cu);
+        snprintf(buf, sizeof(buf), "k_probe_grid16<%s, %s, %d, %d>", v,
+                 h->sub_log2 < h->tile_log2 ? "true" : "false", sets, block);
+        return buf;
+    }
+    int layout = h->kind == SBA_KIND_GRID ? 0 : (h->search == SBA_SEARCH_LEARNED ? 2 : 1);
+    snprintf(buf, sizeof(buf), "%s<%d, %s>",
+             h->n_polys <= LDS_MAX_POLYS ? "k_probe_lds" : "k_probe_global", layout, v);
+    return buf;
 }
 
 extern "C" int sba_debug_grid16_sets(int mode)
