@@ -269,6 +269,111 @@ __device__ __forceinline__ void pred_search_var(const K *keys, int64_t *lo, int6
     }
 }
 
+// 4-ary predecessor search with a window per point: each step issues three
+// independent loads at the window's quarter points and keeps one quarter, so
+// a window of W keys costs about log4(W) dependent round trips instead of
+// log2(W) (the lookups are bound by such round trips); windows shorter than
+// four take binary steps.  Lanes whose windows are done re-read their
+// current key, which changes nothing.
+template <int NP>
+__device__ __forceinline__ void pred_search_var4(const uint32_t *keys, int32_t *lo, int32_t *len,
+                                                 const uint32_t *key)
+{
+    while (true) {
+        bool more = false;
+#pragma unroll
+        for (int k = 0; k < NP; k++) more |= len[k] > 1;
+        if (!__any(more)) break;
+        int32_t c1[NP], c2[NP], c3[NP];
+#pragma unroll
+        for (int k = 0; k < NP; k++) {
+            const int32_t L = len[k];
+            if (L >= 4) {
+                c1[k] = lo[k] + (L >> 2);
+                c2[k] = lo[k] + (L >> 1);
+                c3[k] = lo[k] + (int32_t)(((int64_t)3 * L) >> 2);
+            } else {
+                c1[k] = c2[k] = c3[k] = lo[k] + (L > 1 ? (L >> 1) : 0);
+            }
+        }
+        uint32_t v1[NP], v2[NP], v3[NP];
+#pragma unroll
+        for (int k = 0; k < NP; k++) {
+            v1[k] = keys[c1[k]];
+            v2[k] = keys[c2[k]];
+            v3[k] = keys[c3[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < NP; k++) {
+            if (len[k] <= 1) continue;
+            int32_t end = lo[k] + len[k];
+            if (v3[k] <= key[k]) {
+                lo[k] = c3[k];
+            } else if (v2[k] <= key[k]) {
+                lo[k] = c2[k];
+                end = c3[k];
+            } else if (v1[k] <= key[k]) {
+                lo[k] = c1[k];
+                end = c2[k];
+            } else {
+                end = c1[k];
+            }
+            len[k] = end - lo[k];
+        }
+    }
+}
+
+// NP learned-index lookups in lockstep.  The leaf's model predicts p (clamped
+// into the leaf's run range); the answer lies within the leaf's stored error
+// of p, and a bounded 4-ary predecessor search over that window finds it.
+// The bracket is verified; a full binary search is the fallback (never taken
+// for an exact error bound).
+template <int NP>
+__device__ __forceinline__ void learned_search_n(const HilbView &v, const uint32_t *kk,
+                                                 const uint64_t *key, int64_t *q)
+{
+    const uint32_t *keys = v.k32;
+    int4 lf[NP];
+    int64_t llo[NP], lhi[NP];
+    int32_t lo32[NP], len[NP];  // positions fit 31 bits (runs < 2^31)
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        uint32_t l = root_leaf(key[k], v.a, v.nl);
+        lf[k] = v.leaves[l];
+        llo[k] = v.leaf_lo[l];
+        lhi[k] = v.leaf_lo[l + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        int64_t ra, rb;
+        leaf_range(llo[k], lhi[k], &ra, &rb);
+        int64_t p = predict_in_leaf(lf[k], llo[k], lhi[k], key[k]);
+        int64_t a = p - lf[k].w < ra ? ra : p - lf[k].w;
+        int64_t e = p + lf[k].w > rb ? rb : p + lf[k].w;
+        lo32[k] = (int32_t)a;
+        len[k] = (int32_t)(e - a + 1);
+    }
+    uint32_t first[NP];
+#pragma unroll
+    for (int k = 0; k < NP; k++) first[k] = keys[lo32[k]];
+    pred_search_var4<NP>(keys, lo32, len, kk);
+#pragma unroll
+    for (int k = 0; k < NP; k++) q[k] = lo32[k];
+    uint32_t nxt[NP];
+#pragma unroll
+    for (int k = 0; k < NP; k++) nxt[k] = q[k] + 1 < v.n ? keys[q[k] + 1] : 0xffffffffu;
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        bool good = first[k] <= kk[k] && (q[k] + 1 == v.n || nxt[k] > kk[k]);
+        if (!good) {  // bracket missed (never for an exact error bound): full search
+            int64_t lo1[1] = {0};
+            uint32_t k1[1] = {kk[k]};
+            pred_search_n<uint32_t, 1>(keys, lo1, v.n, k1);
+            q[k] = lo1[0];
+        }
+    }
+}
+
 template <int SEARCH, int NP>
 __device__ __forceinline__ void hilbert_codes(const HilbView &v, const int32_t *xs, const int32_t *ys,
                                               uint32_t *c)
@@ -294,44 +399,7 @@ __device__ __forceinline__ void hilbert_codes(const HilbView &v, const int32_t *
 #pragma unroll
         for (int k = 0; k < NP; k++) k32[k] = (uint32_t)key[k];
         if (SEARCH) {
-            int4 lf[NP];
-            int64_t llo[NP], lhi[NP];
-#pragma unroll
-            for (int k = 0; k < NP; k++) {
-                uint32_t l = root_leaf(key[k], v.a, v.nl);
-                lf[k] = v.leaves[l];
-                llo[k] = v.leaf_lo[l];
-                lhi[k] = v.leaf_lo[l + 1];
-            }
-            int64_t len[NP];
-#pragma unroll
-            for (int k = 0; k < NP; k++) {
-                int64_t p = predict_in_leaf(lf[k], llo[k], lhi[k], key[k]);
-                int64_t ra, rb;
-                leaf_range(llo[k], lhi[k], &ra, &rb);
-                int64_t a = p - lf[k].w, e = p + lf[k].w;
-                a = a < ra ? ra : a;
-                e = e > rb ? rb : e;
-                q[k] = a;
-                len[k] = e - a + 1;
-            }
-            uint32_t first[NP];
-#pragma unroll
-            for (int k = 0; k < NP; k++) first[k] = v.k32[q[k]];
-            pred_search_var<uint32_t, NP>(v.k32, q, len, k32);
-            uint32_t nxt[NP];
-#pragma unroll
-            for (int k = 0; k < NP; k++) nxt[k] = q[k] + 1 < v.n ? v.k32[q[k] + 1] : 0xffffffffu;
-#pragma unroll
-            for (int k = 0; k < NP; k++) {
-                bool good = first[k] <= k32[k] && (q[k] + 1 == v.n || nxt[k] > k32[k]);
-                if (!good) {  // bracket missed (never for an exact error bound): full search
-                    int64_t lo1[1] = {0};
-                    uint32_t kk[1] = {k32[k]};
-                    pred_search_n<uint32_t, 1>(v.k32, lo1, v.n, kk);
-                    q[k] = lo1[0];
-                }
-            }
+            learned_search_n<NP>(v, k32, key, q);
         } else {
 #pragma unroll
             for (int k = 0; k < NP; k++) q[k] = 0;
