@@ -815,7 +815,7 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     // polygon's coverage count at every event, whose changes (toggles) are
     // the maximal covered intervals of each polygon in each row.
     const int rxbits = B.rbits + B.xbits;
-    RC(radix_sort_u64(B.evkey, B.evpay, NE, pbits + rxbits, st, &B.ws));
+    RC(radix_sort_u64_ws(&B.evkey, &B.evpay, NE, pbits + rxbits, B.ws));
     int64_t *cex = nullptr, *tf = nullptr;
     RC(B.alloc(&cex, NE));
     RC(B.alloc(&tf, NE));
@@ -862,7 +862,7 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     HIP_OK(hipMemsetAsync(diff, 0, sizeof(int64_t) * (NP + 1), st));
     if (NT) {
         HIP_OK(hipMemcpyAsync(E, tkey, sizeof(uint64_t) * NT, hipMemcpyDeviceToDevice, st));
-        RC(radix_sort_u64(E, nullptr, NT, rxbits, st, &B.ws));
+        RC(radix_sort_u64_ws(&E, nullptr, NT, rxbits, B.ws));
         hipLaunchKernelGGL(k_flag_new, dim3(grid_for(NT)), dim3(256), 0, st, E, NT, pos);
         HIP_OK(hipGetLastError());
         RC(scan_exclusive_i64(pos, pos, NT, tot + 1, st, &B.ws));
@@ -943,7 +943,7 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
         hipLaunchKernelGGL(k_multi_keys, dim3(grid_for(NM)), dim3(256), 0, st, multi_mem, NM, NMEM,
                            mem_ids, fb, mkey, mval);
         HIP_OK(hipGetLastError());
-        RC(radix_sort_u64(mkey, mval, NM, kbits, st, &B.ws));
+        RC(radix_sort_u64_ws(&mkey, &mval, NM, kbits, B.ws));
         hipLaunchKernelGGL(k_flag_new, dim3(grid_for(NM)), dim3(256), 0, st, mkey, NM, g);
         HIP_OK(hipGetLastError());
         RC(scan_exclusive_i64(g, g, NM, tot, st, &B.ws));

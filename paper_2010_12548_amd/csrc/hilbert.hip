@@ -106,7 +106,7 @@ static int hilbert_boundary_cells(BuildState &B, sba_handle *h, hipStream_t st)
                            h->level, keys + ncb);
     HIP_OK(hipGetLastError());
     B.release(cnt);
-    RC(radix_sort_u64(keys, nullptr, nc, 2 * h->level, st, &B.ws));
+    RC(radix_sort_u64_ws(&keys, nullptr, nc, 2 * h->level, B.ws));
     int64_t *flag = nullptr;
     RC(B.alloc(&flag, nc + 1));
     hipLaunchKernelGGL(k_flag_first, dim3(grid_for(nc)), dim3(256), 0, st, keys, nc, flag);

@@ -123,6 +123,45 @@ static void tmp_put(Workspace *ws, void *p, hipStream_t st)
     else tmp_free(p, st);
 }
 
+// Tiles <= SCAN_TILES_DIRECT: the second pass finds each tile's offset by
+// summing the sums of the tiles before it (at most SCAN_TILES_DIRECT reads
+// per block), so the scan takes two launches; the last tile writes the total.
+#define SCAN_TILES_DIRECT 1024
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_tile_scan_direct(const int64_t *in, int64_t *out,
+                                                                 int64_t n, const int64_t *sums,
+                                                                 int64_t tiles, int64_t *total)
+{
+    int64_t before = 0;
+    for (int64_t t = threadIdx.x; t < blockIdx.x; t += SCAN_BLOCK) before += sums[t];
+    for (int o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o, 64);
+    __shared__ int64_t wb[SCAN_BLOCK / 64];
+    if ((threadIdx.x & 63) == 0) wb[threadIdx.x >> 6] = before;
+    __syncthreads();
+    int64_t off = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_BLOCK / 64; k++) off += wb[k];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int64_t v[SCAN_ITEMS];
+    int64_t run = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        int64_t idx = base + k;
+        v[k] = idx < n ? in[idx] : 0;
+        run += v[k];
+    }
+    int64_t excl;
+    const int64_t tot = block_excl_scan<int64_t>(run, &excl);
+    excl += off;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+        int64_t idx = base + k;
+        if (idx < n) out[idx] = excl;
+        excl += v[k];
+    }
+    if (total && blockIdx.x == tiles - 1 && threadIdx.x == 0) total[0] = off + tot;
+}
+
 int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t st,
                        Workspace *ws)
 {
@@ -140,6 +179,13 @@ int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tota
     RC(tmp_get(ws, &sums, tiles, st));
     hipLaunchKernelGGL(k_tile_sums, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, st, in, n, sums);
     int rc = hipGetLastError() == hipSuccess ? 0 : SBA_EDEVICE;
+    if (!rc && tiles <= SCAN_TILES_DIRECT) {
+        hipLaunchKernelGGL(k_tile_scan_direct, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, st, in,
+                           out, n, sums, tiles, total);
+        rc = hipGetLastError() == hipSuccess ? 0 : SBA_EDEVICE;
+        tmp_put(ws, sums, st);
+        return rc;
+    }
     if (!rc) rc = scan_exclusive_i64(sums, sums, tiles, total, st, ws);
     if (!rc) {
         hipLaunchKernelGGL(k_tile_scan, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, st, in, out, n,
@@ -165,8 +211,11 @@ int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tota
 #define RS_TILE (RS_BLOCK * RS_ROUNDS)
 #define RS_RADIX 256
 
+// per block and digit: count, laid out digit-major (hist[d * nblocks + b]);
+// the digit totals are summed into dtot (zeroed before the pass)
 __global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const uint64_t *keys, int64_t n, int shift,
-                                                      int64_t *hist, int64_t nblocks)
+                                                      int64_t *hist, int64_t nblocks,
+                                                      unsigned long long *dtot)
 {
     __shared__ uint32_t h[RS_RADIX];
     h[threadIdx.x] = 0;
@@ -177,7 +226,45 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const uint64_t *keys, int6
         if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 0xffu], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    const uint32_t c = h[threadIdx.x];
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = c;
+    if (c) atomicAdd(&dtot[threadIdx.x], (unsigned long long)c);
+}
+
+// Scatter offsets in place, one workgroup per digit d: the keys of all lower
+// digits (a sum over dtot) plus the exclusive scan of digit d's block counts.
+__global__ __launch_bounds__(RS_BLOCK) void k_rs_offsets(int64_t *hist, int64_t nblocks,
+                                                         const unsigned long long *dtot)
+{
+    const int d = blockIdx.x;
+    int64_t below = 0;
+    for (int e = threadIdx.x; e < d; e += RS_BLOCK) below += (int64_t)dtot[e];
+    for (int o = 32; o > 0; o >>= 1) below += __shfl_xor(below, o, 64);
+    __shared__ int64_t wb[RS_BLOCK / 64];
+    if ((threadIdx.x & 63) == 0) wb[threadIdx.x >> 6] = below;
+    __syncthreads();
+    int64_t carry = 0;
+    for (int k = 0; k < RS_BLOCK / 64; k++) carry += wb[k];
+    int64_t *row = hist + (int64_t)d * nblocks;
+    for (int64_t c0 = 0; c0 < nblocks; c0 += RS_BLOCK * SCAN_ITEMS) {
+        const int64_t b0 = c0 + (int64_t)threadIdx.x * SCAN_ITEMS;
+        int64_t v[SCAN_ITEMS];
+        int64_t run = 0;
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; k++) {
+            v[k] = b0 + k < nblocks ? row[b0 + k] : 0;
+            run += v[k];
+        }
+        int64_t excl;
+        const int64_t tot = block_excl_scan<int64_t>(run, &excl);
+        excl += carry;
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; k++) {
+            if (b0 + k < nblocks) row[b0 + k] = excl;
+            excl += v[k];
+        }
+        carry += tot;
+    }
 }
 
 template <bool HAS_VALS>
@@ -271,16 +358,20 @@ int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStrea
     int rc = tmp_get(ws, &k2, n, st);
     if (!rc && vals) rc = tmp_get(ws, &v2, n, st);
     if (!rc) rc = tmp_get(ws, &goff, nblocks * RS_RADIX, st);
+    int passes = (bits + 7) / 8;
+    unsigned long long *dtot = nullptr;
+    if (!rc) rc = tmp_get(ws, &dtot, (int64_t)passes * RS_RADIX, st);
+    if (!rc && hipMemsetAsync(dtot, 0, sizeof(unsigned long long) * passes * RS_RADIX, st) != hipSuccess)
+        rc = SBA_EDEVICE;
     uint64_t *ka = keys, *kb = k2;
     uint32_t *va = vals, *vb = v2;
-    int passes = (bits + 7) / 8;
     for (int p = 0; p < passes && !rc; p++) {
         int shift = 8 * p;
         hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st, ka, n, shift,
-                           goff, nblocks);
+                           goff, nblocks, dtot + RS_RADIX * p);
+        hipLaunchKernelGGL(k_rs_offsets, dim3(RS_RADIX), dim3(RS_BLOCK), 0, st, goff, nblocks,
+                           dtot + RS_RADIX * p);
         if (hipGetLastError() != hipSuccess) { rc = SBA_EDEVICE; break; }
-        rc = scan_exclusive_i64(goff, goff, nblocks * RS_RADIX, nullptr, st, ws);
-        if (rc) break;
         if (vals)
             hipLaunchKernelGGL(k_rs_scatter<true>, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st, ka,
                                va, kb, vb, n, shift, goff, nblocks);
@@ -301,5 +392,51 @@ int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStrea
     tmp_put(ws, k2, st);
     tmp_put(ws, v2, st);
     tmp_put(ws, goff, st);
+    tmp_put(ws, dtot, st);
     return rc;
+}
+
+int radix_sort_u64_ws(uint64_t **keys, uint32_t **vals, int64_t n, int bits, Workspace &ws)
+{
+    if (n <= 1 || bits <= 0) return 0;
+    hipStream_t st = ws.stream();
+    const int64_t nblocks = (n + RS_TILE - 1) / RS_TILE;
+    uint64_t *k2 = nullptr;
+    uint32_t *v2 = nullptr;
+    int64_t *goff = nullptr;
+    RC(ws.alloc(&k2, n));
+    if (vals && *vals) RC(ws.alloc(&v2, n));
+    RC(ws.alloc(&goff, nblocks * RS_RADIX));
+    const int passes = (bits + 7) / 8;
+    unsigned long long *dtot = nullptr;
+    RC(ws.alloc(&dtot, (int64_t)passes * RS_RADIX));
+    HIP_OK(hipMemsetAsync(dtot, 0, sizeof(unsigned long long) * passes * RS_RADIX, st));
+    uint64_t *ka = *keys, *kb = k2;
+    uint32_t *va = vals ? *vals : nullptr, *vb = v2;
+    for (int p = 0; p < passes; p++) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st, ka, n, shift,
+                           goff, nblocks, dtot + RS_RADIX * p);
+        hipLaunchKernelGGL(k_rs_offsets, dim3(RS_RADIX), dim3(RS_BLOCK), 0, st, goff, nblocks,
+                           dtot + RS_RADIX * p);
+        HIP_OK(hipGetLastError());
+        if (va)
+            hipLaunchKernelGGL(k_rs_scatter<true>, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st, ka,
+                               va, kb, vb, n, shift, goff, nblocks);
+        else
+            hipLaunchKernelGGL(k_rs_scatter<false>, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st, ka,
+                               va, kb, vb, n, shift, goff, nblocks);
+        HIP_OK(hipGetLastError());
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    // the sorted data stays where the last pass wrote it; the other buffers
+    // go back to the workspace
+    ws.put(kb);
+    if (vb) ws.put(vb);
+    ws.put(goff);
+    ws.put(dtot);
+    *keys = ka;
+    if (vals && *vals) *vals = va;
+    return 0;
 }

@@ -279,6 +279,11 @@ int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tota
 int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st,
                    Workspace *ws = nullptr);
 
+// The same with the temporaries of ws, on its stream; the sorted keys/values
+// are left in whichever buffer the last pass wrote: *keys / *vals are updated
+// to it and the other buffer goes back to ws (so both must come from ws).
+int radix_sort_u64_ws(uint64_t **keys, uint32_t **vals, int64_t n, int bits, Workspace &ws);
+
 // device allocation helper (persistent arrays of a handle)
 template <typename T>
 inline int dev_alloc(T **p, int64_t count)
