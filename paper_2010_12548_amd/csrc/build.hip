@@ -711,14 +711,21 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
 {
     (void)need_boundary_cells;
     const int32_t np = polys->n_polys;
-    int *err = nullptr;
-    RC(B.alloc(&err, 1));
-    HIP_OK(hipMemsetAsync(err, 0, sizeof(int), st));
+    // device scalars read back together (one copy per synchronisation):
+    // [0] error bits (int), [1..2] ring and vertex counts, [3..6] union cell
+    // box, [8..13] totals of the scans
+    RC(B.alloc(&B.sc, SC_SLOTS));
+    HIP_OK(hipMemsetAsync(B.sc, 0, sizeof(int64_t) * SC_SLOTS, st));
+    int *err = (int *)B.sc;
+    int64_t *sizes = B.sc + 1, *dbox = B.sc + 3, *tot = B.sc + 8;
+    int64_t hsc[SC_READ];
+    auto fetch = [&]() -> int {
+        RC(B.ws.read(hsc, B.sc, sizeof(hsc)));
+        return B.ws.sync();
+    };
 
     // validate the offsets on the device (each stage reads only what the
     // previous one validated) and read sizes and bounding boxes in one sync
-    int64_t *sizes = nullptr;
-    RC(B.alloc(&sizes, 2));
     hipLaunchKernelGGL(k_check_rings, dim3(grid_for(np + 1)), dim3(256), 0, st, polys->ring_off, np,
                        sizes, err);
     hipLaunchKernelGGL(k_check_verts, dim3(1024), dim3(256), 0, st, polys->vert_off, sizes, err);
@@ -728,20 +735,14 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     hipLaunchKernelGGL(k_poly_bbox, dim3(grid_for((int64_t)np * 64)), dim3(256), 0, st,
                        polys->ring_off, polys->vert_off, polys->xy, np, bbox, err);
     HIP_OK(hipGetLastError());
-    int64_t *dbox = nullptr;
-    RC(B.alloc(&dbox, 4));
     hipLaunchKernelGGL(k_union_box, dim3(1), dim3(BOX_BLOCK), 0, st, bbox, np, h->s, dbox);
     HIP_OK(hipGetLastError());
-    int herr = 0;
-    int64_t hsz[2] = {0, 0}, hbox[4] = {0, 0, 0, 0};
-    RC(B.ws.read(&herr, err, sizeof(int)));
-    RC(B.ws.read(hsz, sizes, sizeof(hsz)));
-    RC(B.ws.read(hbox, dbox, sizeof(hbox)));
-    RC(B.ws.sync());
+    RC(fetch());
+    int herr = (int)(uint32_t)hsc[0];
     if (herr & 2) return SBA_EINVAL;
     if (herr & 1) return SBA_ERANGE;
-    const int32_t nr = (int32_t)hsz[0];
-    const int64_t nv = hsz[1];
+    const int32_t nr = (int32_t)hsc[1];
+    const int64_t nv = hsc[2];
     if (nv > ((int64_t)1 << 31) - 1) return SBA_ELIMIT;
     B.n_edges = nv;
     RC(B.alloc(&B.edges, nv));
@@ -751,7 +752,7 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     HIP_OK(hipGetLastError());
 
     const int64_t s = h->s;
-    int64_t gi0 = hbox[0], gj0 = hbox[1], gi1 = hbox[2], gj1 = hbox[3];
+    int64_t gi0 = hsc[3], gj0 = hsc[4], gi1 = hsc[5], gj1 = hsc[6];
     if (B.window) {
         gi0 = std::max(gi0, floordiv64(B.wx0, s));
         gj0 = std::max(gj0, floordiv64(B.wy0, s));
@@ -777,19 +778,16 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     const int pbits = bits_for((uint64_t)(np - 1)) < 1 ? 1 : bits_for((uint64_t)(np - 1));
 
     // 1-2: boundary intervals and crossings per edge
-    int64_t *nb = nullptr, *nc = nullptr, *tot = nullptr;
+    int64_t *nb = nullptr, *nc = nullptr;
     RC(B.alloc(&nb, nv + 1));
     RC(B.alloc(&nc, nv + 1));
-    RC(B.alloc(&tot, 6));
     hipLaunchKernelGGL(k_edge_counts, dim3(grid_for(nv)), dim3(256), 0, st, B.edges, B.epoly, bbox,
                        nv, s, gi0, gj0, gi1, gj1, nb, nc);
     HIP_OK(hipGetLastError());
     RC(scan_exclusive_i64(nb, nb, nv, tot, st, &B.ws));
     RC(scan_exclusive_i64(nc, nc, nv, tot + 1, st, &B.ws));
-    int64_t ht[2];
-    RC(B.ws.read(ht, tot, sizeof(ht)));
-    RC(B.ws.sync());
-    const int64_t NB = ht[0], NC = ht[1];
+    RC(fetch());
+    const int64_t NB = hsc[8], NC = hsc[9];
     if (NC % 2) return SBA_EDEVICE;
     h->n_boundary = NB;
     B.NB = NB;
@@ -826,10 +824,9 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
                        NE, B.xbits, tf, err);
     HIP_OK(hipGetLastError());
     RC(scan_exclusive_i64(tf, tf, NE, tot, st, &B.ws));
-    int64_t NT = 0;
-    RC(B.ws.read(&NT, tot, sizeof(int64_t)));
-    RC(B.ws.read(&herr, err, sizeof(int)));
-    RC(B.ws.sync());
+    RC(fetch());
+    const int64_t NT = hsc[8];
+    herr = (int)(uint32_t)hsc[0];
     if (herr || (NT & 1)) return SBA_EDEVICE;
     B.release(cex);
     uint64_t *tkey = nullptr, *E = nullptr;
@@ -884,10 +881,9 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     RC(scan_exclusive_i64(segc, segc, NP, tot + 3, st, &B.ws));
     RC(scan_exclusive_i64(mm, mm, NP, tot + 4, st, &B.ws));
     RC(scan_exclusive_i64(xoff, xoff, std::max<int64_t>(NI, 1), tot + 5, st, &B.ws));
-    int64_t h6[6];
-    RC(B.ws.read(h6, tot, sizeof(h6)));
-    RC(B.ws.read(&herr, err, sizeof(int)));
-    RC(B.ws.sync());
+    RC(fetch());
+    const int64_t *h6 = hsc + 8;
+    herr = (int)(uint32_t)hsc[0];
     if (herr & 8) return SBA_ELIMIT;
     if (herr) return SBA_EDEVICE;
     const int64_t NS = h6[3] >> 32, NM = h6[3] & 0xffffffffll, NMEM = h6[4];
@@ -961,10 +957,11 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
                            multi_mem, NM, NMEM, mem_ids, h->set_off, h->set_ids, multi_seg,
                            B.seg_code);
         HIP_OK(hipGetLastError());
-        int64_t nsets = 0, nids = 0;
-        RC(B.ws.read(&nsets, tot, sizeof(int64_t)));
+        int64_t nids = 0;
+        RC(B.ws.read(hsc, B.sc, sizeof(hsc)));
         RC(B.ws.read(&nids, h->set_off + NM, sizeof(int64_t)));
         RC(B.ws.sync());
+        const int64_t nsets = hsc[8];
         h->n_sets = nsets;
         h->n_set_ids = nids;
         B.release(mkey);
@@ -1041,16 +1038,16 @@ int build_grid(sba_handle *h, BuildState &B, int tile_log2, int sub_log2, hipStr
     if (nt >= ((int64_t)1 << 31)) return SBA_ELIMIT;
     const uint32_t np = (uint32_t)h->n_polys;
     uint32_t *tcode = nullptr;
-    int64_t *tpos = nullptr, *tot = nullptr;
+    int64_t *tpos = nullptr, *tot = B.sc + 16;
+    int64_t hsc[SC_READ];
     RC(B.alloc(&tcode, nt));
     RC(B.alloc(&tpos, nt + 1));
-    RC(B.alloc(&tot, 2));
     classify(B, h, nullptr, tl, sl, nt, tcode, tpos, st);
     HIP_OK(hipGetLastError());
     RC(scan_exclusive_i64(tpos, tpos, nt, tot, st, &B.ws));
-    int64_t nblk = 0;
-    RC(B.ws.read(&nblk, tot, sizeof(int64_t)));
+    RC(B.ws.read(hsc, B.sc, sizeof(hsc)));
     RC(B.ws.sync());
+    const int64_t nblk = hsc[16];
     if (nblk >= (int64_t)TILE_MIXED) return SBA_ELIMIT;
     h->n_blocks = nblk;
     const bool compact = !g_build_wide && (int64_t)np + h->n_sets < 0x8000 && nblk < 0x8000 &&
@@ -1104,9 +1101,9 @@ int build_grid(sba_handle *h, BuildState &B, int tile_log2, int sub_log2, hipStr
         classify(B, h, mt, tl, sl, nq, scode, spos, st);
         HIP_OK(hipGetLastError());
         RC(scan_exclusive_i64(spos, spos, nq, tot + 1, st, &B.ws));
-        int64_t nsub = 0;
-        RC(B.ws.read(&nsub, tot + 1, sizeof(int64_t)));
+        RC(B.ws.read(hsc, B.sc, sizeof(hsc)));
         RC(B.ws.sync());
+        const int64_t nsub = hsc[17];
         if (nsub >= (int64_t)TILE_MIXED) return SBA_ELIMIT;
         h->n_sub = nsub;
         RC(handle_alloc(h, &h->sub, nq));

@@ -7,6 +7,9 @@
 
 #include "sba_internal.h"
 
+#define SC_SLOTS 32
+#define SC_READ 20
+
 struct BuildState {
     explicit BuildState(hipStream_t s) : st(s), ws(s) {}
     hipStream_t st;
@@ -18,6 +21,10 @@ struct BuildState {
         return ws.alloc(p, n);
     }
     void release(void *p) { ws.put(p); }
+
+    // device scalars of the build (error bits, sizes, scan totals) that are
+    // read back together: slots [0, SC_READ) in one copy
+    int64_t *sc = nullptr;
 
     // clip window in coordinates, [wx0, wx1) x [wy0, wy1)
     bool window = false;
