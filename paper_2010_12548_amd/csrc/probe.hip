@@ -1197,9 +1197,10 @@ extern "C" int sba_debug_set_blocks_per_cu(int k)
 // viewport, outputs) answered by one persistent launch.  The tasks' point
 // ranges are cut into items of at most BATCH_ITEM points; workgroups pull
 // items from a device counter until none is left, so uneven tasks balance
-// across the chip.  An item aggregates into LDS (when its polygon count
-// fits) and adds its non-zero bins to the task's outputs with global atomics;
-// tasks that share outputs therefore accumulate into them.
+// across the chip.  An item aggregates into a table of the cell codes it
+// meets in LDS and adds the table to the task's outputs with global atomics
+// (a polygon set to each member); tasks that share outputs therefore
+// accumulate into them.
 
 #define BATCH_ITEM (1 << 18)
 
@@ -1228,30 +1229,55 @@ __device__ __forceinline__ bool in_view(const TaskDev &T, int32_t x, int32_t y)
     return !T.filt || (x >= T.vx0 && x < T.vx1 && y >= T.vy0 && y < T.vy1);
 }
 
-template <int LAYOUT, bool USE_LDS>
-__device__ __forceinline__ void batch_item(const TaskDev &T, int64_t lo, int64_t hi, uint32_t *lcnt,
-                                           unsigned long long *lsum)
+// Per-workgroup table of the codes an item meets (polygon or polygon set,
+// open addressing in LDS): the serving loop keeps its points bucketed, so the
+// points of one item come from a small area and meet few codes; a code that
+// finds no free slot within BATCH_PROBES steps goes to the outputs directly.
+#define BATCH_SLOTS 2048
+#define BATCH_PROBES 16
+#define BATCH_EMPTY 0xffffffffu
+
+struct CodeTable {
+    uint32_t *key;                 // [BATCH_SLOTS] code or BATCH_EMPTY
+    uint32_t *cnt;                 // [BATCH_SLOTS]
+    unsigned long long *sum;       // [BATCH_SLOTS]
+};
+
+template <bool VALS>
+__device__ __forceinline__ void table_add(const CodeTable &H, uint32_t code, int64_t v,
+                                          const TaskDev &T)
 {
-    const bool vals = T.vals != nullptr && T.sums != nullptr;
+    if (code == 0) return;
+    uint32_t h = (code * 2654435761u) >> (32 - 11);  // BATCH_SLOTS = 2^11
+    for (int k = 0; k < BATCH_PROBES; k++) {
+        uint32_t old = H.key[h];
+        if (old == BATCH_EMPTY) old = atomicCAS(&H.key[h], BATCH_EMPTY, code);
+        if (old == BATCH_EMPTY || old == code) {
+            atomicAdd(&H.cnt[h], 1u);
+            if (VALS) atomicAdd(&H.sum[h], (unsigned long long)v);
+            return;
+        }
+        h = (h + 1) & (BATCH_SLOTS - 1);
+    }
+    add_global<VALS>(code, v, T.A, T.counts, T.sums);
+}
+
+template <int LAYOUT, bool VALS>
+__device__ __forceinline__ void batch_item(const TaskDev &T, int64_t lo, int64_t hi,
+                                           const CodeTable &H)
+{
     auto one = [&](int32_t x, int32_t y, int64_t v) {
         if (!in_view(T, x, y)) return;
-        uint32_t c = code_of<LAYOUT>(T.g, T.hv, x, y);
-        if (USE_LDS) {
-            if (vals) add_lds<true>(c, v, T.A, lcnt, lsum);
-            else add_lds<false>(c, 0, T.A, lcnt, lsum);
-        } else {
-            if (vals) add_global<true>(c, v, T.A, T.counts, T.sums);
-            else add_global<false>(c, 0, T.A, T.counts, T.sums);
-        }
+        table_add<VALS>(H, code_of<LAYOUT>(T.g, T.hv, x, y), v, T);
     };
     // ragged ends one point at a time, the aligned middle two points per load
     int64_t a = lo, b = hi;
     if ((a & 1) && a < b) {
-        if (threadIdx.x == 0) one(T.xy[2 * a], T.xy[2 * a + 1], vals ? T.vals[a] : 0);
+        if (threadIdx.x == 0) one(T.xy[2 * a], T.xy[2 * a + 1], VALS ? T.vals[a] : 0);
         a++;
     }
     if ((b & 1) && b > a) {
-        if (threadIdx.x == 0) one(T.xy[2 * (b - 1)], T.xy[2 * (b - 1) + 1], vals ? T.vals[b - 1] : 0);
+        if (threadIdx.x == 0) one(T.xy[2 * (b - 1)], T.xy[2 * (b - 1) + 1], VALS ? T.vals[b - 1] : 0);
         b--;
     }
     const int4 *xy4 = (const int4 *)T.xy;
@@ -1264,7 +1290,7 @@ __device__ __forceinline__ void batch_item(const TaskDev &T, int64_t lo, int64_t
         for (int u = 0; u < PROBE_UNROLL; u++) {
             int64_t t = t0 + (int64_t)u * PROBE_BLOCK;
             q[u] = t < pb ? xy4[t] : make_int4(INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN);
-            vv[u] = (vals && t < pb) ? v2[t] : make_longlong2(0, 0);
+            vv[u] = (VALS && t < pb) ? v2[t] : make_longlong2(0, 0);
         }
         // points outside the viewport become a coordinate no cell holds
         int32_t xs[2 * PROBE_UNROLL], ys[2 * PROBE_UNROLL];
@@ -1280,36 +1306,26 @@ __device__ __forceinline__ void batch_item(const TaskDev &T, int64_t lo, int64_t
         codes_of<LAYOUT, 2 * PROBE_UNROLL>(T.g, T.hv, xs, ys, c);
 #pragma unroll
         for (int u = 0; u < PROBE_UNROLL; u++) {
-            if (USE_LDS) {
-                if (vals) {
-                    add_lds<true>(c[2 * u], vv[u].x, T.A, lcnt, lsum);
-                    add_lds<true>(c[2 * u + 1], vv[u].y, T.A, lcnt, lsum);
-                } else {
-                    add_lds<false>(c[2 * u], 0, T.A, lcnt, lsum);
-                    add_lds<false>(c[2 * u + 1], 0, T.A, lcnt, lsum);
-                }
-            } else {
-                if (vals) {
-                    add_global<true>(c[2 * u], vv[u].x, T.A, T.counts, T.sums);
-                    add_global<true>(c[2 * u + 1], vv[u].y, T.A, T.counts, T.sums);
-                } else {
-                    add_global<false>(c[2 * u], 0, T.A, T.counts, T.sums);
-                    add_global<false>(c[2 * u + 1], 0, T.A, T.counts, T.sums);
-                }
-            }
+            table_add<VALS>(H, c[2 * u], vv[u].x, T);
+            table_add<VALS>(H, c[2 * u + 1], vv[u].y, T);
         }
     }
 }
 
 __global__ __launch_bounds__(PROBE_BLOCK) void k_batch(const TaskDev *__restrict__ tasks,
                                                        const ItemDev *__restrict__ items,
-                                                       int32_t n_items, int32_t lds_np,
-                                                       int *__restrict__ next)
+                                                       int32_t n_items, int *__restrict__ next)
 {
-    extern __shared__ unsigned long long smem[];
-    unsigned long long *lsum = smem;
-    uint32_t *lcnt = (uint32_t *)(smem + lds_np);
+    __shared__ uint32_t s_key[BATCH_SLOTS];
+    __shared__ uint32_t s_cnt[BATCH_SLOTS];
+    __shared__ unsigned long long s_sum[BATCH_SLOTS];
     __shared__ int s_item;
+    const CodeTable H{s_key, s_cnt, s_sum};
+    for (int k = threadIdx.x; k < BATCH_SLOTS; k += PROBE_BLOCK) {
+        s_key[k] = BATCH_EMPTY;
+        s_cnt[k] = 0;
+        s_sum[k] = 0;
+    }
     while (true) {
         if (threadIdx.x == 0) s_item = atomicAdd(next, 1);
         __syncthreads();
@@ -1318,31 +1334,39 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_batch(const TaskDev *__restrict
         if (it >= n_items) break;  // every wave of the workgroup leaves here together
         const ItemDev I = items[it];
         const TaskDev T = tasks[I.task];
-        const int np = T.np;
-        const bool use_lds = np <= lds_np;
-        if (use_lds) {
-            for (int p = threadIdx.x; p < np; p += PROBE_BLOCK) {
-                lcnt[p] = 0;
-                lsum[p] = 0;
-            }
-            __syncthreads();
+        const bool vals = T.vals != nullptr && T.sums != nullptr;
+        switch (T.layout * 2 + (vals ? 1 : 0)) {
+        case 0: batch_item<0, false>(T, I.lo, I.hi, H); break;
+        case 1: batch_item<0, true>(T, I.lo, I.hi, H); break;
+        case 2: batch_item<1, false>(T, I.lo, I.hi, H); break;
+        case 3: batch_item<1, true>(T, I.lo, I.hi, H); break;
+        case 4: batch_item<2, false>(T, I.lo, I.hi, H); break;
+        default: batch_item<2, true>(T, I.lo, I.hi, H); break;
         }
-        switch (T.layout * 2 + (use_lds ? 1 : 0)) {
-        case 0: batch_item<0, false>(T, I.lo, I.hi, lcnt, lsum); break;
-        case 1: batch_item<0, true>(T, I.lo, I.hi, lcnt, lsum); break;
-        case 2: batch_item<1, false>(T, I.lo, I.hi, lcnt, lsum); break;
-        case 3: batch_item<1, true>(T, I.lo, I.hi, lcnt, lsum); break;
-        case 4: batch_item<2, false>(T, I.lo, I.hi, lcnt, lsum); break;
-        default: batch_item<2, true>(T, I.lo, I.hi, lcnt, lsum); break;
-        }
-        if (use_lds) {
-            __syncthreads();
-            const bool vals = T.vals != nullptr && T.sums != nullptr;
-            for (int p = threadIdx.x; p < np; p += PROBE_BLOCK) {
-                uint32_t c = lcnt[p];
-                if (c) {
-                    atomicAdd(&T.counts[p], (unsigned long long)c);
-                    if (vals) atomicAdd(&T.sums[p], lsum[p]);
+        __syncthreads();
+        // the item's codes to the task's outputs (sets to each member), and
+        // the table back to empty
+        for (int k = threadIdx.x; k < BATCH_SLOTS; k += PROBE_BLOCK) {
+            const uint32_t code = s_key[k];
+            if (code == BATCH_EMPTY) continue;
+            const unsigned long long c = s_cnt[k], sv = s_sum[k];
+            s_key[k] = BATCH_EMPTY;
+            s_cnt[k] = 0;
+            s_sum[k] = 0;
+            if (c == 0) continue;
+            if (code < CODE_SET_BASE) {
+                const uint32_t p = code - 1u;
+                if (p >= T.A.np) continue;
+                atomicAdd(&T.counts[p], c);
+                if (vals) atomicAdd(&T.sums[p], sv);
+            } else {
+                const uint32_t ks = code - CODE_SET_BASE;
+                if (ks >= T.A.n_sets) continue;
+                for (int64_t t = T.A.set_off[ks], e = T.A.set_off[ks + 1]; t < e; t++) {
+                    const uint32_t p = (uint32_t)T.A.set_ids[t];
+                    if (p >= T.A.np) continue;
+                    atomicAdd(&T.counts[p], c);
+                    if (vals) atomicAdd(&T.sums[p], sv);
                 }
             }
         }
@@ -1367,7 +1391,6 @@ int batch_launch(const sba_task *tasks, int32_t n_tasks, hipStream_t st)
     if (n_tasks <= 0) return 0;
     std::vector<TaskDev> td(n_tasks);
     std::vector<ItemDev> items;
-    int32_t lds_np = 0;
     for (int32_t k = 0; k < n_tasks; k++) {
         const sba_task &q = tasks[k];
         const sba_handle *h = q.h;
@@ -1386,7 +1409,6 @@ int batch_launch(const sba_task *tasks, int32_t n_tasks, hipStream_t st)
         T.vy1 = (int64_t)q.vy + q.vh;
         T.counts = (unsigned long long *)q.counts;
         T.sums = (unsigned long long *)q.sums;
-        if (T.np <= LDS_MAX_POLYS) lds_np = std::max(lds_np, T.np);
         for (int64_t a = q.lo; a < q.hi; a += BATCH_ITEM)
             items.push_back(ItemDev{a, std::min<int64_t>(q.hi, a + BATCH_ITEM), k, 0});
     }
@@ -1409,9 +1431,8 @@ int batch_launch(const sba_task *tasks, int32_t n_tasks, hipStream_t st)
     }
     if (!rc && n_items) {
         int64_t nb = std::min<int64_t>(n_items, (int64_t)cu_count() * g_blocks_per_cu);
-        size_t lds = (size_t)lds_np * 12;
-        hipLaunchKernelGGL(k_batch, dim3((unsigned)nb), dim3(PROBE_BLOCK), lds, st, dtasks, ditems,
-                           n_items, lds_np, next);
+        hipLaunchKernelGGL(k_batch, dim3((unsigned)nb), dim3(PROBE_BLOCK), 0, st, dtasks, ditems,
+                           n_items, next);
         if (hipGetLastError() != hipSuccess) rc = SBA_EDEVICE;
     }
     tmp_free(buf, st);
