@@ -647,12 +647,26 @@ __global__ void k_block_fill(const int64_t *seg_row_off, const int32_t *seg_x0,
         if (seg_x0[mid] <= xa) a = mid + 1; else e = mid;
     }
     int64_t q = a - 1;  // last segment starting at or before xa (lo-1 if none)
-    for (int c = 0; c < rlen; c++) {
+    // the run's codes go to registers first and leave in 16-byte stores (a
+    // run starts at a multiple of 16 bytes: blocks and rows are multiples of
+    // 8 bytes long and runs of 16 codes are 32 or 64 bytes)
+    OUT buf[16] __attribute__((aligned(16)));
+#pragma unroll
+    for (int c = 0; c < 16; c++) {
+        if (c >= rlen) break;
         int32_t x = xa + c;
         while (q + 1 < hi && seg_x0[q + 1] <= x) q++;
         uint32_t v = 0;
         if (x < gw && q >= lo && x < seg_x1[q]) v = seg_code[q];
-        out[c] = sizeof(OUT) == 2 ? (OUT)short_code(v, np) : (OUT)v;
+        buf[c] = sizeof(OUT) == 2 ? (OUT)short_code(v, np) : (OUT)v;
+    }
+    const int bytes = rlen * (int)sizeof(OUT);
+    if (bytes % 16 == 0) {
+        uint4 *o4 = (uint4 *)out;
+        const uint4 *b4 = (const uint4 *)buf;
+        for (int k = 0; k < bytes / 16; k++) o4[k] = b4[k];
+    } else {
+        for (int c = 0; c < rlen; c++) out[c] = buf[c];
     }
 }
 
