@@ -175,6 +175,36 @@ def serve_bench(args, torch, txy, tv, n_queries, with_big_set=True):
     return out
 
 
+def hilbert_sorted(torch, txy, tv, info):
+    """The points reordered by the Hilbert index of their cell on the handle's
+    key grid (input preparation for a comparison run, in torch)."""
+    L, s = info["level"], info["s"]
+    x = txy[0::2].to(torch.int64) - info["gi0"] * s
+    y = txy[1::2].to(torch.int64) - info["gj0"] * s
+    top = (1 << L) - 1
+    i = torch.clamp(torch.div(x, s, rounding_mode="floor"), 0, top)
+    j = torch.clamp(torch.div(y, s, rounding_mode="floor"), 0, top)
+    del x, y
+    d = torch.zeros_like(i)
+    swap = torch.zeros_like(i)
+    flip = torch.zeros_like(i)
+    for lev in range(L - 1, -1, -1):
+        bi = (i >> lev) & 1
+        bj = (j >> lev) & 1
+        xx = torch.where(swap == 1, bj, bi) ^ flip
+        yy = torch.where(swap == 1, bi, bj) ^ flip
+        d = (d << 2) | ((3 * xx) ^ yy)
+        low = yy == 0
+        flip = torch.where(low & (xx == 1), flip ^ 1, flip)
+        swap = torch.where(low, swap ^ 1, swap)
+    del i, j, swap, flip
+    order = torch.argsort(d)
+    del d
+    sx = txy.view(-1, 2)[order].reshape(-1).contiguous()
+    sv = tv[order].contiguous()
+    return sx, sv
+
+
 def workload(args):
     from gen import city_points, city_polygons, quadtree_polygons, tiny_workload
     if args.workload == "tiny":
@@ -346,12 +376,78 @@ def main():
         for v in out.values():
             v.pop("_res")
         ai = a.info()
+        # the same probes over the points in Hilbert order of their cells (a
+        # resident layout a serving system would keep): lookups of neighbouring
+        # points share cache lines; results must not change
+        sx, sv = hilbert_sorted(torch, txy, tv, ai)
+        srt = {}
+        for srch in ("binary", "learned"):
+            cc = torch.empty_like(counts)
+            ss = torch.empty_like(sums)
+            a.aggregate(sx, sv, cc, ss, search=srch)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(3):
+                a.aggregate(sx, sv, cc, ss, search=srch)
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / 3
+            srt[srch] = {"probe_ms": round(t, 4), "points_per_s": n / (t * 1e-3),
+                         "gbps": alg_bytes / (t * 1e-3) / 1e9,
+                         "same_as_unsorted": bool(np.array_equal(cc.cpu().numpy(), res_c.astype(np.int64))
+                                                  and np.array_equal(ss.cpu().numpy(), res_s))}
+            # the batch entry point over the same range: workgroups take
+            # contiguous items and count them in an LDS table of cell codes,
+            # which sorted points keep small
+            task = sba.Task(a, sx, sv, 0, n, None, cc, ss, search=srch)
+            sba.aggregate_batch([task])
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(3):
+                sba.aggregate_batch([task])
+            e1.record()
+            torch.cuda.synchronize()
+            tb = e0.elapsed_time(e1) / 3
+            srt[srch]["batch_probe_ms"] = round(tb, 4)
+            srt[srch]["batch_points_per_s"] = n / (tb * 1e-3)
+            srt[srch]["batch_same"] = bool(np.array_equal(cc.cpu().numpy(), res_c.astype(np.int64))
+                                           and np.array_equal(ss.cpu().numpy(), res_s))
+        del sx, sv
+        extra["hilbert_sorted_points"] = srt
         extra["learned_vs_binary"] = {**out, "identical": bool(same),
                                       "speedup": out["binary"]["probe_ms"] / out["learned"]["probe_ms"],
                                       "n_runs": ai["n_runs"], "max_leaf_err": ai["max_leaf_err"],
                                       "mean_leaf_err": ai["mean_leaf_err"],
                                       "leaves": 1 << ai["log2_leaves"]}
         a.close()
+
+    if args.workload == "city":
+        # result range [alpha - beta, alpha] (Sec. 6): beta from a
+        # boundary-only approximation over the same points
+        t0 = time.perf_counter()
+        bh = sba.Approx(ro, vo, pxy, eps, boundary_only=True, tile_log2=args.tile_log2,
+                        sub_log2=args.sub_log2)
+        t_bb = 1000.0 * (time.perf_counter() - t0)
+        bc = torch.empty_like(counts)
+        bs = torch.empty_like(sums)
+        bh.aggregate(txy, tv, bc, bs)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            bh.aggregate(txy, tv, bc, bs)
+        e1.record()
+        torch.cuda.synchronize()
+        beta = bc.cpu().numpy().astype(np.float64)
+        alpha = res_c.astype(np.float64)
+        extra["result_range"] = {
+            "beta_build_ms": round(t_bb, 3), "beta_probe_ms": round(e0.elapsed_time(e1) / 10, 4),
+            "beta_over_alpha_total": float(beta.sum() / max(alpha.sum(), 1.0)),
+            "beta_over_alpha_median_polygon": float(np.median(beta / np.maximum(alpha, 1.0))),
+            "kernel": bh.probe_kernel(True)}
+        bh.close()
+        log(f"[bench] result range: {json.dumps(extra['result_range'])}")
 
     sweep = {}
     if args.workload == "city" and not args.no_sweep:

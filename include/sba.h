@@ -85,6 +85,12 @@ typedef struct {
                              2..tile_log2; == tile_log2: mixed tiles are stored cell by
                              cell (0 -> 4 for tiles of 64 cells or more, 3 for tiles of
                              32 cells, else tile_log2)                                   */
+    int32_t boundary_only; /* 1: store only the boundary cells B(P) of every polygon
+                             (no interior cells).  sba_aggregate over such a handle gives
+                             the partial count beta (and sum) over the boundary cells, so
+                             the exact answer lies in [alpha - beta, alpha] for the full
+                             approximation's alpha (Sec. 6, result range estimation;
+                             sums: for non-negative values)                             */
 } sba_build_opts;
 
 typedef struct {
@@ -108,6 +114,7 @@ typedef struct {
     int64_t n_sub;          /* grid: mixed sub-tiles (stored cell by cell) */
     int32_t sub_log2;       /* grid: sub-tile side log2 (== tile_log2: no sub level) */
     int32_t compact;        /* grid: 1 = 16-bit codes (directory staged in LDS), 0 = 32-bit */
+    int32_t boundary_only;  /* built with sba_build_opts.boundary_only */
 } sba_info_t;
 
 /*

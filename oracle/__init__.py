@@ -46,6 +46,8 @@ def lib():
                                    C.c_int64, C.c_int64, C.c_int64, _u8p]
     L.orc_build.restype = C.c_void_p
     L.orc_build.argtypes = [C.c_int32, _i32p, _i64p, _i32p, C.c_int64]
+    L.orc_build_mode.restype = C.c_void_p
+    L.orc_build_mode.argtypes = [C.c_int32, _i32p, _i64p, _i32p, C.c_int64, C.c_int]
     L.orc_free.restype = None
     L.orc_free.argtypes = [C.c_void_p]
     L.orc_cell_side_of.restype = C.c_int64
@@ -104,14 +106,21 @@ def hilbert_d(L: int, i: int, j: int) -> int:
 
 
 class Approx:
-    """The oracle's A(P) for every polygon, held as sorted row intervals."""
+    """The oracle's A(P) for every polygon, held as sorted row intervals.
 
-    def __init__(self, polys, eps: int):
+    boundary_only=True holds B(P) instead: the boundary cells alone, over
+    which the partial count of the result range [alpha - beta, alpha]
+    (Sec. 6, result range estimation) is taken.
+    """
+
+    def __init__(self, polys, eps: int, boundary_only: bool = False):
         ro, vo, xy = _poly_arrays(polys)
         self._keep = (ro, vo, xy)
         self.n_polys = polys.n_polys
         self.eps = int(eps)
-        self._h = lib().orc_build(polys.n_polys, ro, vo, xy, int(eps))
+        self.boundary_only = bool(boundary_only)
+        self._h = lib().orc_build_mode(polys.n_polys, ro, vo, xy, int(eps),
+                                       1 if boundary_only else 0)
         if not self._h:
             raise ValueError("oracle rejected the polygons or eps")
         self.s = int(lib().orc_cell_side_of(self._h))

@@ -307,7 +307,7 @@ typedef struct {
  *
  *  A(P) = B(P) u I(P) = B(P) u {cells whose corner is inside}, since the
  *  second set differs from I(P) only by cells of B(P). */
-static int build_rows(const polyset *ps, int32_t p, int64_t s, prows *out)
+static int build_rows(const polyset *ps, int32_t p, int64_t s, int with_interior, prows *out)
 {
     int64_t xmin, ymin, xmax, ymax;
     poly_bbox(ps, p, &xmin, &ymin, &xmax, &ymax);
@@ -360,7 +360,7 @@ static int build_rows(const polyset *ps, int32_t p, int64_t s, prows *out)
         /* each row line meets a closed ring an even number of times */
         for (int64_t t = 0; t + 1 < cr.n && !err; t += 2) {
             if (cr.a[t].row != cr.a[t + 1].row) { err = 2; break; }
-            if (cr.a[t].x0 < cr.a[t + 1].x0)
+            if (with_interior && cr.a[t].x0 < cr.a[t + 1].x0)
                 if (ivec_push(&iv, cr.a[t].row, cr.a[t].x0, cr.a[t + 1].x0)) err = 1;
         }
         if (cr.n % 2) err = 2;
@@ -435,8 +435,11 @@ void orc_free(orc_approx *a)
     free(a);
 }
 
-orc_approx *orc_build(int32_t n_polys, const int32_t *ring_off, const int64_t *vert_off,
-                      const int32_t *xy, int64_t eps)
+/* boundary_only = 1: only the boundary cells B(P) of every polygon (the
+ * cells over which the partial count of Sec. 6's result range is taken);
+ * 0: A(P) = B(P) u I(P). */
+orc_approx *orc_build_mode(int32_t n_polys, const int32_t *ring_off, const int64_t *vert_off,
+                           const int32_t *xy, int64_t eps, int boundary_only)
 {
     int64_t s = orc_cell_side(eps);
     polyset in = {n_polys, ring_off, vert_off, xy};
@@ -460,7 +463,7 @@ orc_approx *orc_build(int32_t n_polys, const int32_t *ring_off, const int64_t *v
     int fail = 0;
     #pragma omp parallel for schedule(dynamic, 1) reduction(|:fail)
     for (int32_t p = 0; p < n_polys; p++)
-        if (build_rows(&a->ps, p, s, &a->rows[p])) fail = 1;
+        if (build_rows(&a->ps, p, s, !boundary_only, &a->rows[p])) fail = 1;
     if (fail) { orc_free(a); return NULL; }
 
     /* bucket filter */
@@ -504,6 +507,12 @@ orc_approx *orc_build(int32_t n_polys, const int32_t *ring_off, const int64_t *v
         free(fill);
     }
     return a;
+}
+
+orc_approx *orc_build(int32_t n_polys, const int32_t *ring_off, const int64_t *vert_off,
+                      const int32_t *xy, int64_t eps)
+{
+    return orc_build_mode(n_polys, ring_off, vert_off, xy, eps, 0);
 }
 
 int64_t orc_cell_side_of(const orc_approx *a) { return a->s; }

@@ -44,7 +44,7 @@ class _Opts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("search", C.c_int32), ("log2_leaves", C.c_int32),
                 ("tile_log2", C.c_int32), ("use_window", C.c_int32), ("win_x0", C.c_int32),
                 ("win_y0", C.c_int32), ("win_x1", C.c_int32), ("win_y1", C.c_int32),
-                ("sub_log2", C.c_int32)]
+                ("sub_log2", C.c_int32), ("boundary_only", C.c_int32)]
 
 
 class _Task(C.Structure):
@@ -63,7 +63,7 @@ class _Info(C.Structure):
                 ("n_segments", C.c_int64), ("n_boundary", C.c_int64), ("n_runs", C.c_int64),
                 ("max_leaf_err", C.c_int64), ("mean_leaf_err", C.c_double), ("bytes", C.c_int64),
                 ("build_ms", C.c_double), ("n_sub", C.c_int64), ("sub_log2", C.c_int32),
-                ("compact", C.c_int32)]
+                ("compact", C.c_int32), ("boundary_only", C.c_int32)]
 
 
 def library_path() -> str:
@@ -176,11 +176,14 @@ class Approx:
     ring_off (int32 [P+1]), vert_off (int64 [R+1]) and xy (int32 [2V]) are the
     polygons in CSR form (torch tensors or numpy arrays; copied to the GPU).
     window: optional clip window (x0, y0, x1, y1), half-open, in coordinates.
+    boundary_only: store only the boundary cells; aggregate() then returns the
+    partial counts and sums beta of the result range [alpha - beta, alpha].
     """
 
     def __init__(self, ring_off, vert_off, xy, eps: int, kind: str = "grid",
                  search: str = "binary", log2_leaves: int = 16, tile_log2: int = 0,
-                 window=None, device: str = "cuda", stream=None, sub_log2: int = 0):
+                 window=None, device: str = "cuda", stream=None, sub_log2: int = 0,
+                 boundary_only: bool = False):
         torch = _torch()
         self._h = C.c_void_p(None)
         self.device = torch.device(device)
@@ -192,7 +195,8 @@ class Approx:
         win = (0, 0, 0, 0, 0) if window is None else (1, *[int(v) for v in window])
         opts = _Opts({"grid": KIND_GRID, "hilbert": KIND_HILBERT}[kind],
                      {"binary": SEARCH_BINARY, "learned": SEARCH_LEARNED}[search],
-                     int(log2_leaves), int(tile_log2), *win, int(sub_log2))
+                     int(log2_leaves), int(tile_log2), *win, int(sub_log2),
+                     1 if boundary_only else 0)
         h = C.c_void_p(None)
         with torch.cuda.device(self.device):
             rc = lib().sba_build_approx(C.byref(polys), int(eps), C.byref(opts),

@@ -801,7 +801,8 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     RC(scan_exclusive_i64(nb, nb, nv, tot, st, &B.ws));
     RC(scan_exclusive_i64(nc, nc, nv, tot + 1, st, &B.ws));
     RC(fetch());
-    const int64_t NB = hsc[8], NC = hsc[9];
+    // boundary-only approximations take no row-line crossings (no interior spans)
+    const int64_t NB = hsc[8], NC = B.boundary_only ? 0 : hsc[9];
     if (NC % 2) return SBA_EDEVICE;
     h->n_boundary = NB;
     B.NB = NB;
@@ -1168,7 +1169,7 @@ int build_handle(const sba_polygons *polys, int64_t eps, const sba_build_opts *o
                  hipStream_t st, sba_handle *h)
 {
     auto t0 = std::chrono::steady_clock::now();
-    sba_build_opts o = {SBA_KIND_GRID, SBA_SEARCH_BINARY, 16, 0, 0, 0, 0, 0, 0, 0};
+    sba_build_opts o = {SBA_KIND_GRID, SBA_SEARCH_BINARY, 16, 0, 0, 0, 0, 0, 0, 0, 0};
     if (opts) o = *opts;
     if (o.use_window && (o.win_x1 <= o.win_x0 || o.win_y1 <= o.win_y0)) return SBA_EINVAL;
     if (o.log2_leaves == 0) o.log2_leaves = 16;
@@ -1193,6 +1194,8 @@ int build_handle(const sba_polygons *polys, int64_t eps, const sba_build_opts *o
         return 0;
     }
     BuildState B(st);
+    B.boundary_only = o.boundary_only != 0;
+    h->boundary_only = o.boundary_only != 0;
     B.window = o.use_window != 0;
     B.wx0 = o.win_x0;
     B.wy0 = o.win_y0;

@@ -26,6 +26,8 @@ struct BuildState {
     // read back together: slots [0, SC_READ) in one copy
     int64_t *sc = nullptr;
 
+    bool boundary_only = false;  // no interior spans: B(P) only
+
     // clip window in coordinates, [wx0, wx1) x [wy0, wy1)
     bool window = false;
     int64_t wx0 = 0, wy0 = 0, wx1 = 0, wy1 = 0;

@@ -373,3 +373,53 @@ def test_unit_and_small_cells_aggregate(sba, orc, eps):
     c, s = run_agg(A, xy, vals)
     np.testing.assert_array_equal(c, want_c)
     np.testing.assert_array_equal(s, want_s)
+
+
+# --------------------------------------------------------------- result range (Sec. 6)
+
+@pytest.mark.parametrize("kind,search", [("grid", None), ("hilbert", "binary"),
+                                         ("hilbert", "learned")])
+@pytest.mark.parametrize("seed,eps", [(0, 4), (1, 9), (2, 30)])
+def test_boundary_only_cells_and_aggregates(sba, orc, kind, search, seed, eps):
+    """A boundary-only handle stores the oracle's boundary cells B(P) and its
+    aggregate is the oracle's partial count and sum over them."""
+    polys = star_polygons(10, 11, 20.0, 300.0, 1200, 900 + seed)
+    OB = orc.Approx(polys, eps, boundary_only=True)
+    kw = {"kind": kind, "boundary_only": True}
+    if search:
+        kw["search"] = search
+    A = sba.Approx.from_polygons(polys, eps, **kw)
+    assert A.info()["boundary_only"] == 1
+    i0, j0, nw, nh = window_of(polys, OB.s)
+    want = expected_sets(OB, polys.n_polys, i0, j0, nw, nh)
+    got = gpu_sets(A, list(want.keys()))
+    bad = [k for k in want if got[k] != want[k]]
+    assert not bad, (len(bad), bad[:5])
+    rng = np.random.default_rng(seed)
+    n = 150_001
+    xy = rng.integers(-100, 1300, size=2 * n).astype(np.int32)
+    vals = rng.integers(0, 10000, size=n).astype(np.int64)
+    want_c, want_s = OB.aggregate(xy, vals)
+    c, s = run_agg(A, xy, vals)
+    np.testing.assert_array_equal(c, want_c)
+    np.testing.assert_array_equal(s, want_s)
+
+
+@pytest.mark.parametrize("eps", [100, 1000, 10000])
+def test_city_result_range_contains_exact(sba, orc, eps):
+    """GPU alpha and beta on the city partition: beta equals the oracle's, and
+    alpha - beta <= exact <= alpha for every polygon (counts and sums)."""
+    from gen import city_polygons
+    polys = city_polygons()
+    xy, vals = city_points(1_000_000)
+    A = sba.Approx.from_polygons(polys, eps)
+    Bh = sba.Approx.from_polygons(polys, eps, boundary_only=True)
+    ac, asum = run_agg(A, xy, vals)
+    bc, bsum = run_agg(Bh, xy, vals)
+    wb_c, wb_s = orc.Approx(polys, eps, boundary_only=True).aggregate(xy, vals)
+    np.testing.assert_array_equal(bc, wb_c)
+    np.testing.assert_array_equal(bsum, wb_s)
+    ec, esum = orc.Approx(polys, eps).exact(xy, vals)
+    ac, bc, ec = ac.astype(np.int64), bc.astype(np.int64), ec.astype(np.int64)
+    assert np.all(ac - bc <= ec) and np.all(ec <= ac)
+    assert np.all(asum - bsum <= esum) and np.all(esum <= asum)

@@ -392,3 +392,71 @@ def test_invariant_city_sample(orc, eps):
     assert inv["far"] == 0 and inv["false_neg"] == 0
     ex, _ = A.exact(xy)
     assert int(ex.sum()) == 2_000_000           # a partition of the box
+
+
+# ---------------------------------------------------------------- result range (Sec. 6)
+#
+# beta = the partial count over the boundary cells B(P); with the conservative
+# approximation every wrong point lies in a boundary cell, so the exact count
+# lies in [alpha - beta, alpha].
+
+@pytest.mark.parametrize("eps", [2, 3, 5, 8, 9, 15])
+def test_boundary_only_equals_definition_hand(orc, eps):
+    s = orc.cell_side(eps)
+    polys = polygons_from_rings(_hand_shapes())
+    i0, j0, nw, nh = cell_window(polys, s)
+    br = orc.raster_brute(polys, s, i0, j0, nw, nh)
+    B = orc.Approx(polys, eps, boundary_only=True)
+    for p in range(polys.n_polys):
+        np.testing.assert_array_equal(member_from_intervals(B, p, i0, j0, nw, nh), br[p] == 2,
+                                      err_msg=f"polygon {p}")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_boundary_only_equals_definition_random_stars(orc, seed):
+    rng = np.random.default_rng(seed)
+    polys = star_polygons(4, int(rng.integers(3, 12)), 5.0, 60.0, 200, 2000 + seed)
+    for eps in (2, 4, 7, 13):
+        s = orc.cell_side(eps)
+        i0, j0, nw, nh = cell_window(polys, s)
+        br = orc.raster_brute(polys, s, i0, j0, nw, nh)
+        B = orc.Approx(polys, eps, boundary_only=True)
+        for p in range(polys.n_polys):
+            np.testing.assert_array_equal(member_from_intervals(B, p, i0, j0, nw, nh), br[p] == 2)
+
+
+@pytest.mark.parametrize("s,a,b,c,d", [(5, 0, 35, 0, 40), (5, -15, 20, 10, 25), (3, 3, 12, -9, 30),
+                                       (7, 14, 70, 7, 35)])
+def test_rectangle_result_range_closed_form(orc, s, a, b, c, d):
+    # cell-aligned rectangle: the boundary cells are two cells thick along every
+    # side (cells i with is <= a <= (i+1)s touch x = a), the interior cells
+    # cover (b-a-2s)(d-c-2s) lattice points, so beta = (b-a+2s)(d-c+2s) -
+    # (b-a-2s)(d-c-2s); the exact (b-a)(d-c) lies in [alpha - beta, alpha]
+    eps = {3: 5, 5: 8, 7: 10}[s]
+    polys = polygons_from_rings([[np.array([[a, c], [b, c], [b, d], [a, d]])]])
+    xy = lattice(min(a, c) - 3 * s, max(b, d) + 3 * s)
+    alpha, _ = orc.Approx(polys, eps).aggregate(xy)
+    beta, _ = orc.Approx(polys, eps, boundary_only=True).aggregate(xy)
+    inner = max(b - a - 2 * s, 0) * max(d - c - 2 * s, 0)
+    assert int(alpha[0]) == (b - a + 2 * s) * (d - c + 2 * s)
+    assert int(beta[0]) == int(alpha[0]) - inner
+    assert int(alpha[0]) - int(beta[0]) <= (b - a) * (d - c) <= int(alpha[0])
+
+
+@pytest.mark.parametrize("eps", [2, 6, 23, 64])
+def test_result_range_contains_exact(orc, eps):
+    # counts and (non-negative) sums: alpha - beta <= exact <= alpha, for every
+    # polygon; overlapping stars, points on and off the polygons
+    rng = np.random.default_rng(100 + eps)
+    polys = star_polygons(8, 16, 30.0, 300.0, 1000, 131 + eps)
+    xy = rng.integers(-300, 1300, size=2 * 60000).astype(np.int32)
+    vals = rng.integers(0, 10000, size=60000).astype(np.int64)
+    A = orc.Approx(polys, eps)
+    ac, asum = A.aggregate(xy, vals)
+    bc, bsum = orc.Approx(polys, eps, boundary_only=True).aggregate(xy, vals)
+    ec, esum = A.exact(xy, vals)
+    ac, bc, ec = ac.astype(np.int64), bc.astype(np.int64), ec.astype(np.int64)
+    assert np.all(bc <= ac)
+    assert np.all(ac - bc <= ec) and np.all(ec <= ac)
+    assert np.all(asum - bsum <= esum) and np.all(esum <= asum)
+    assert np.any(ac - bc < ec) and np.any(ec < ac)   # the bounds are not trivially tight
