@@ -8,8 +8,9 @@
 // and adds the point to a per-workgroup histogram in LDS.  At the end every
 // workgroup adds its non-empty bins to the caller's outputs (zeroed by a
 // small kernel before the probe) with one global atomic per bin; no global
-// atomics per point.  Polygon counts too large for LDS fall back to global
-// atomics per point.  A call allocates nothing.
+// atomics per point.  Polygon counts too large for per-polygon bins use a
+// per-workgroup LDS table of the cell codes met in a contiguous item of
+// points instead.  A call allocates nothing.
 //
 // Cell lookup per layout:
 //   grid     directory entry of the cell's tile (staged in LDS in the
@@ -569,51 +570,6 @@ __global__ void k_zero_out(uint64_t *counts, int64_t *sums, int32_t np)
     if (sums) sums[p] = 0;
 }
 
-template <int LAYOUT, bool VALS>
-__global__ __launch_bounds__(PROBE_BLOCK) void k_probe_global(const int4 *__restrict__ xy4,
-                                                              const longlong2 *__restrict__ v2,
-                                                              const int32_t *__restrict__ xy,
-                                                              const int64_t *__restrict__ vals,
-                                                              int64_t n, GridView g, HilbView hv,
-                                                              Agg A, uint64_t *counts, int64_t *sums)
-{
-    unsigned long long *cnt = (unsigned long long *)counts;
-    unsigned long long *sum = (unsigned long long *)sums;
-    const int64_t npairs = n >> 1;
-    const int64_t stride = (int64_t)gridDim.x * PROBE_BLOCK;
-    for (int64_t t0 = (int64_t)blockIdx.x * PROBE_BLOCK + threadIdx.x; t0 < npairs;
-         t0 += stride * PROBE_UNROLL) {
-        int4 q[PROBE_UNROLL];
-        longlong2 vv[PROBE_UNROLL];
-#pragma unroll
-        for (int u = 0; u < PROBE_UNROLL; u++) {
-            int64_t t = t0 + (int64_t)u * stride;
-            q[u] = t < npairs ? xy4[t] : make_int4(INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN);
-            vv[u] = (VALS && t < npairs) ? v2[t] : make_longlong2(0, 0);
-        }
-        int32_t xs[2 * PROBE_UNROLL], ys[2 * PROBE_UNROLL];
-#pragma unroll
-        for (int u = 0; u < PROBE_UNROLL; u++) {
-            xs[2 * u] = q[u].x;
-            ys[2 * u] = q[u].y;
-            xs[2 * u + 1] = q[u].z;
-            ys[2 * u + 1] = q[u].w;
-        }
-        uint32_t c[2 * PROBE_UNROLL];
-        codes_of<LAYOUT, 2 * PROBE_UNROLL>(g, hv, xs, ys, c);
-#pragma unroll
-        for (int u = 0; u < PROBE_UNROLL; u++) {
-            add_global<VALS>(c[2 * u], vv[u].x, A, cnt, sum);
-            add_global<VALS>(c[2 * u + 1], vv[u].y, A, cnt, sum);
-        }
-    }
-    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
-        int64_t k = n - 1;
-        add_global<VALS>(code_of<LAYOUT>(g, hv, xy[2 * k], xy[2 * k + 1]), VALS ? vals[k] : 0, A,
-                         cnt, sum);
-    }
-}
-
 // ---------------------------------------------------------------- lookups
 
 template <int LAYOUT>
@@ -705,6 +661,9 @@ static void views(const sba_handle *h, GridView *g, HilbView *hv)
 // blocks per CU for the streaming probe
 static int g_blocks_per_cu = 8;
 
+static int launch_items(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
+                        int layout, uint64_t *counts, int64_t *sums, hipStream_t st);
+
 
 template <int LAYOUT>
 static int launch_layout(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
@@ -736,16 +695,7 @@ static int launch_layout(const int32_t *xy, const int64_t *values, int64_t n, co
         HIP_OK(hipGetLastError());
         return 0;
     }
-    hipLaunchKernelGGL(k_zero_out, dim3(grid_for(np)), dim3(256), 0, st, counts, vals ? sums : nullptr,
-                       np);
-    if (vals)
-        hipLaunchKernelGGL((k_probe_global<LAYOUT, true>), dim3((unsigned)nb), dim3(PROBE_BLOCK), 0, st,
-                           xy4, v2, xy, values, n, g, hv, A, counts, sums);
-    else
-        hipLaunchKernelGGL((k_probe_global<LAYOUT, false>), dim3((unsigned)nb), dim3(PROBE_BLOCK), 0,
-                           st, xy4, v2, xy, values, n, g, hv, A, counts, sums);
-    HIP_OK(hipGetLastError());
-    return 0;
+    return launch_items(xy, values, n, h, LAYOUT, counts, sums, st);
 }
 
 
@@ -1166,7 +1116,7 @@ extern "C" const char *sba_probe_kernel(const sba_handle *h, int with_values)
     }
     int layout = h->kind == SBA_KIND_GRID ? 0 : (h->search == SBA_SEARCH_LEARNED ? 2 : 1);
     snprintf(buf, sizeof(buf), "%s<%d, %s>",
-             h->n_polys <= LDS_MAX_POLYS ? "k_probe_lds" : "k_probe_global", layout, v);
+             h->n_polys <= LDS_MAX_POLYS ? "k_probe_lds" : "k_probe_items", layout, v);
     return buf;
 }
 
@@ -1203,6 +1153,8 @@ extern "C" int sba_debug_set_blocks_per_cu(int k)
 // accumulate into them.
 
 #define BATCH_ITEM (1 << 18)
+#define ITEM_MIN 4096
+#define ITEMS_PER_WG 8
 
 struct TaskDev {
     GridView g;
@@ -1210,6 +1162,7 @@ struct TaskDev {
     Agg A;
     int32_t layout;        // 0 grid, 1 hilbert + binary, 2 hilbert + learned
     int32_t np;
+    int64_t n;             // points (the items kernel's range is [0, n))
     const int32_t *xy;
     const int64_t *vals;
     int32_t filt;
@@ -1241,6 +1194,9 @@ struct CodeTable {
     uint32_t *key;                 // [BATCH_SLOTS] code or BATCH_EMPTY
     uint32_t *cnt;                 // [BATCH_SLOTS]
     unsigned long long *sum;       // [BATCH_SLOTS]
+    int *full;                     // set once a code found no slot: later codes
+                                   // look at one slot only (points in no
+                                   // spatial order meet more codes than fit)
 };
 
 template <bool VALS>
@@ -1249,7 +1205,8 @@ __device__ __forceinline__ void table_add(const CodeTable &H, uint32_t code, int
 {
     if (code == 0) return;
     uint32_t h = (code * 2654435761u) >> (32 - 11);  // BATCH_SLOTS = 2^11
-    for (int k = 0; k < BATCH_PROBES; k++) {
+    const int probes = *H.full ? 1 : BATCH_PROBES;
+    for (int k = 0; k < probes; k++) {
         uint32_t old = H.key[h];
         if (old == BATCH_EMPTY) old = atomicCAS(&H.key[h], BATCH_EMPTY, code);
         if (old == BATCH_EMPTY || old == code) {
@@ -1259,6 +1216,7 @@ __device__ __forceinline__ void table_add(const CodeTable &H, uint32_t code, int
         }
         h = (h + 1) & (BATCH_SLOTS - 1);
     }
+    if (probes > 1) *H.full = 1;
     add_global<VALS>(code, v, T.A, T.counts, T.sums);
 }
 
@@ -1312,6 +1270,104 @@ __device__ __forceinline__ void batch_item(const TaskDev &T, int64_t lo, int64_t
     }
 }
 
+// the item's codes to the task's outputs (sets to each member), and the
+// table back to empty
+__device__ __forceinline__ void table_flush(const CodeTable &H, const TaskDev &T, bool vals)
+{
+    for (int k = threadIdx.x; k < BATCH_SLOTS; k += PROBE_BLOCK) {
+        const uint32_t code = H.key[k];
+        if (code == BATCH_EMPTY) continue;
+        const unsigned long long c = H.cnt[k], sv = H.sum[k];
+        H.key[k] = BATCH_EMPTY;
+        H.cnt[k] = 0;
+        H.sum[k] = 0;
+        if (c == 0) continue;
+        if (code < CODE_SET_BASE) {
+            const uint32_t p = code - 1u;
+            if (p >= T.A.np) continue;
+            atomicAdd(&T.counts[p], c);
+            if (vals) atomicAdd(&T.sums[p], sv);
+        } else {
+            const uint32_t ks = code - CODE_SET_BASE;
+            if (ks >= T.A.n_sets) continue;
+            for (int64_t t = T.A.set_off[ks], e = T.A.set_off[ks + 1]; t < e; t++) {
+                const uint32_t p = (uint32_t)T.A.set_ids[t];
+                if (p >= T.A.np) continue;
+                atomicAdd(&T.counts[p], c);
+                if (vals) atomicAdd(&T.sums[p], sv);
+            }
+        }
+    }
+    if (threadIdx.x == 0) *H.full = 0;
+}
+
+// One aggregate over all points when the polygon count is too large for
+// per-polygon LDS bins: workgroups take contiguous items (round robin, so
+// no counter is needed) and count each in the LDS table of cell codes; points
+// in spatial order (bucketed, Hilbert-sorted) meet few codes per item and
+// almost never reach global memory, points in no order fall back to a global
+// atomic per point once the table is full.
+template <int LAYOUT, bool VALS>
+__global__ __launch_bounds__(PROBE_BLOCK) void k_probe_items(const TaskDev T, int64_t item,
+                                                             int64_t n_items)
+{
+    __shared__ uint32_t s_key[BATCH_SLOTS];
+    __shared__ uint32_t s_cnt[BATCH_SLOTS];
+    __shared__ unsigned long long s_sum[BATCH_SLOTS];
+    __shared__ int s_full;
+    const CodeTable H{s_key, s_cnt, s_sum, &s_full};
+    for (int k = threadIdx.x; k < BATCH_SLOTS; k += PROBE_BLOCK) {
+        s_key[k] = BATCH_EMPTY;
+        s_cnt[k] = 0;
+        s_sum[k] = 0;
+    }
+    if (threadIdx.x == 0) s_full = 0;
+    __syncthreads();
+    for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int64_t lo = it * item, hi = min(lo + item, T.n);
+        batch_item<LAYOUT, VALS>(T, lo, hi, H);
+        __syncthreads();
+        table_flush(H, T, VALS);
+        __syncthreads();
+    }
+}
+
+static int launch_items(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
+                        int layout, uint64_t *counts, int64_t *sums, hipStream_t st)
+{
+    const bool vals = values != nullptr && sums != nullptr;
+    TaskDev T{};
+    views(h, &T.g, &T.hv);
+    T.A = Agg{h->set_off, h->set_ids, (uint32_t)h->n_polys, (uint32_t)h->n_sets};
+    T.layout = layout;
+    T.np = h->n_polys;
+    T.n = n;
+    T.xy = xy;
+    T.vals = vals ? values : nullptr;
+    T.counts = (unsigned long long *)counts;
+    T.sums = vals ? (unsigned long long *)sums : nullptr;
+    // about ITEMS_PER_WG items per workgroup (even sizes keep the pairs
+    // aligned), so the round robin ends evenly
+    const int64_t nb = std::max<int64_t>(
+        1, std::min<int64_t>((n + ITEM_MIN - 1) / ITEM_MIN, (int64_t)cu_count() * g_blocks_per_cu));
+    int64_t item = (n + nb * ITEMS_PER_WG - 1) / (nb * ITEMS_PER_WG);
+    item = std::max<int64_t>(ITEM_MIN, (item + 1) & ~(int64_t)1);
+    const int64_t n_items = (n + item - 1) / item;
+    hipLaunchKernelGGL(k_zero_out, dim3(grid_for(h->n_polys)), dim3(256), 0, st, counts,
+                       vals ? sums : nullptr, h->n_polys);
+    const dim3 grid((unsigned)std::min(nb, n_items));
+    switch (layout * 2 + (vals ? 1 : 0)) {
+    case 0: hipLaunchKernelGGL((k_probe_items<0, false>), grid, dim3(PROBE_BLOCK), 0, st, T, item, n_items); break;
+    case 1: hipLaunchKernelGGL((k_probe_items<0, true>), grid, dim3(PROBE_BLOCK), 0, st, T, item, n_items); break;
+    case 2: hipLaunchKernelGGL((k_probe_items<1, false>), grid, dim3(PROBE_BLOCK), 0, st, T, item, n_items); break;
+    case 3: hipLaunchKernelGGL((k_probe_items<1, true>), grid, dim3(PROBE_BLOCK), 0, st, T, item, n_items); break;
+    case 4: hipLaunchKernelGGL((k_probe_items<2, false>), grid, dim3(PROBE_BLOCK), 0, st, T, item, n_items); break;
+    default: hipLaunchKernelGGL((k_probe_items<2, true>), grid, dim3(PROBE_BLOCK), 0, st, T, item, n_items); break;
+    }
+    HIP_OK(hipGetLastError());
+    return 0;
+}
+
 __global__ __launch_bounds__(PROBE_BLOCK) void k_batch(const TaskDev *__restrict__ tasks,
                                                        const ItemDev *__restrict__ items,
                                                        int32_t n_items, int *__restrict__ next)
@@ -1319,13 +1375,14 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_batch(const TaskDev *__restrict
     __shared__ uint32_t s_key[BATCH_SLOTS];
     __shared__ uint32_t s_cnt[BATCH_SLOTS];
     __shared__ unsigned long long s_sum[BATCH_SLOTS];
-    __shared__ int s_item;
-    const CodeTable H{s_key, s_cnt, s_sum};
+    __shared__ int s_item, s_full;
+    const CodeTable H{s_key, s_cnt, s_sum, &s_full};
     for (int k = threadIdx.x; k < BATCH_SLOTS; k += PROBE_BLOCK) {
         s_key[k] = BATCH_EMPTY;
         s_cnt[k] = 0;
         s_sum[k] = 0;
     }
+    if (threadIdx.x == 0) s_full = 0;
     while (true) {
         if (threadIdx.x == 0) s_item = atomicAdd(next, 1);
         __syncthreads();
@@ -1344,32 +1401,7 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_batch(const TaskDev *__restrict
         default: batch_item<2, true>(T, I.lo, I.hi, H); break;
         }
         __syncthreads();
-        // the item's codes to the task's outputs (sets to each member), and
-        // the table back to empty
-        for (int k = threadIdx.x; k < BATCH_SLOTS; k += PROBE_BLOCK) {
-            const uint32_t code = s_key[k];
-            if (code == BATCH_EMPTY) continue;
-            const unsigned long long c = s_cnt[k], sv = s_sum[k];
-            s_key[k] = BATCH_EMPTY;
-            s_cnt[k] = 0;
-            s_sum[k] = 0;
-            if (c == 0) continue;
-            if (code < CODE_SET_BASE) {
-                const uint32_t p = code - 1u;
-                if (p >= T.A.np) continue;
-                atomicAdd(&T.counts[p], c);
-                if (vals) atomicAdd(&T.sums[p], sv);
-            } else {
-                const uint32_t ks = code - CODE_SET_BASE;
-                if (ks >= T.A.n_sets) continue;
-                for (int64_t t = T.A.set_off[ks], e = T.A.set_off[ks + 1]; t < e; t++) {
-                    const uint32_t p = (uint32_t)T.A.set_ids[t];
-                    if (p >= T.A.np) continue;
-                    atomicAdd(&T.counts[p], c);
-                    if (vals) atomicAdd(&T.sums[p], sv);
-                }
-            }
-        }
+        table_flush(H, T, vals);
         __syncthreads();
     }
 }

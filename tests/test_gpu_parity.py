@@ -375,6 +375,42 @@ def test_unit_and_small_cells_aggregate(sba, orc, eps):
     np.testing.assert_array_equal(s, want_s)
 
 
+@pytest.mark.parametrize("eps", [300, 3000])
+def test_many_polygons_item_probe(sba, orc, eps):
+    """More polygons than per-polygon LDS bins hold: the probe counts each
+    item of points in an LDS table of cell codes.  Points in no order (the
+    table fills and later codes go to global atomics) and in row-band order
+    (few codes per item) give the oracle's aggregates on every layout."""
+    polys = voronoi_partition(6000, 1_000_000, (2, 6), seed=31, jitter_seed=32)
+    n = 600_001
+    xy = uniform_points(n, -2000, 1_002_000, 5)
+    vals = np.random.default_rng(2).integers(0, 10**6, size=n).astype(np.int64)
+    pts = xy.reshape(-1, 2)
+    order = np.lexsort((pts[:, 0], pts[:, 1] // 5000))
+    xy_sorted = np.ascontiguousarray(pts[order]).reshape(-1)
+    vals_sorted = vals[order]
+    O = orc.Approx(polys, eps)
+    want_c, want_s = O.aggregate(xy, vals)
+    handles = []
+    sba.lib().sba_debug_force_wide_grid(1)
+    try:
+        handles.append(sba.Approx.from_polygons(polys, eps))
+    finally:
+        sba.lib().sba_debug_force_wide_grid(0)
+    handles.append(sba.Approx.from_polygons(polys, eps, kind="hilbert", search="binary"))
+    handles.append(sba.Approx.from_polygons(polys, eps, kind="hilbert", search="learned",
+                                            log2_leaves=10))
+    for A in handles:
+        assert A.probe_kernel(True).startswith("k_probe_items")
+        for p, v in ((xy, vals), (xy_sorted, vals_sorted)):
+            c, s = run_agg(A, p, v)
+            np.testing.assert_array_equal(c, want_c)
+            np.testing.assert_array_equal(s, want_s)
+            c, _ = run_agg(A, p, None)
+            np.testing.assert_array_equal(c, want_c)
+        A.close()
+
+
 # --------------------------------------------------------------- result range (Sec. 6)
 
 @pytest.mark.parametrize("kind,search", [("grid", None), ("hilbert", "binary"),
