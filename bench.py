@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--search", default="", choices=["", "binary", "learned"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-sweep", action="store_true", help="skip the eps sweep")
+    ap.add_argument("--no-pindex", action="store_true",
+                    help="skip the point-index (pre-aggregated points) measurement")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--grid16-per-cu", type=int, default=0,
                     help="cap on workgroups per CU of the LDS-directory grid probe (0 = none)")
@@ -203,6 +205,49 @@ def hilbert_sorted(torch, txy, tv, info):
     sx = txy.view(-1, 2)[order].reshape(-1).contiguous()
     sv = tv[order].contiguous()
     return sx, sv
+
+
+def pindex_bench(sba, torch, txy, tv, ro, vo, pxy, eps, res_c, res_s, scan_ms):
+    """Point-side pre-aggregation (Sec. 3, point indexing): build the point
+    index once, then answer the same query from the runs of a Hilbert handle
+    on the index's key grid with binary searches and with the RadixSpline.
+    The answer must equal the scan's."""
+    n = txy.numel() // 2
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ix = sba.PointIndex(txy, tv, eps)
+    t_ix = 1000.0 * (time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    a = sba.Approx(ro, vo, pxy, eps, kind="hilbert", key_grid=ix)
+    t_h = 1000.0 * (time.perf_counter() - t0)
+    ii, ai = ix.info(), a.info()
+    out = {"index_build_ms": round(t_ix, 3), "handle_build_ms": round(t_h, 3),
+           "n_runs": ai["n_runs"], "key_level": ii["key_level"], "n_distinct": ii["n_distinct"],
+           "n_knots": ii["n_knots"], "radix_bits": ii["radix_bits"],
+           "spline_err": ii["spline_err"], "index_MB": round(ii["bytes"] / 2**20, 1),
+           "scan_probe_ms": round(scan_ms, 4)}
+    counts = torch.empty(max(a.n_polys, 1), dtype=torch.int64, device=txy.device)
+    sums = torch.empty_like(counts)
+    for srch in ("binary", "learned"):
+        for _ in range(2):
+            ix.aggregate(a, srch, counts, sums)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
+            ix.aggregate(a, srch, counts, sums)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / reps
+        same = bool(np.array_equal(counts[:a.n_polys].cpu().numpy().astype(np.uint64), res_c)
+                    and np.array_equal(sums[:a.n_polys].cpu().numpy(), res_s))
+        out[srch] = {"query_ms": round(t, 4), "points_per_s_equiv": n / (t * 1e-3),
+                     "speedup_vs_scan": round(scan_ms / t, 2), "same_as_scan": same}
+    a.close()
+    ix.close()
+    log(f"[bench] point index: {json.dumps(out)}")
+    return out
 
 
 def workload(args):
@@ -448,6 +493,10 @@ def main():
             "kernel": bh.probe_kernel(True)}
         bh.close()
         log(f"[bench] result range: {json.dumps(extra['result_range'])}")
+
+    if args.workload in ("city", "quadtree") and not args.no_pindex:
+        extra["point_index"] = pindex_bench(sba, torch, txy, tv, ro, vo, pxy, eps, res_c, res_s,
+                                            probe_avg)
 
     sweep = {}
     if args.workload == "city" and not args.no_sweep:

@@ -91,6 +91,12 @@ typedef struct {
                              the exact answer lies in [alpha - beta, alpha] for the full
                              approximation's alpha (Sec. 6, result range estimation;
                              sums: for non-negative values)                             */
+    int32_t key_level;    /* Hilbert only: > 0 anchors the 2^key_level x 2^key_level key
+                             grid at cell (key_i0, key_j0) instead of the stored box's
+                             first cell (the key grid of a point index, sba_pindex_info,
+                             so that sba_pindex_aggregate can answer from the handle's
+                             runs); cells outside that grid are not stored.  1..21     */
+    int64_t key_i0, key_j0;
 } sba_build_opts;
 
 typedef struct {
@@ -253,6 +259,78 @@ const char *sba_probe_kernel(const sba_handle *h, int with_values);
 /* Release the handle's device memory.  The caller must make sure no work
  * using the handle is still queued (synchronise its streams first). */
 void sba_free(sba_handle *h);
+
+/* ------------------------------------------------------------ point index
+ *
+ * Point-side pre-aggregation (Sec. 3, point indexing): the points are
+ * linearised to the Hilbert keys of their cells and kept as a sorted key
+ * array with a prefix-sum array of their values.  A polygon query then costs
+ * a lower-bound search at both ends of each query cell instead of a pass over
+ * the points: the query cells are the runs of a Hilbert handle built on the
+ * index's key grid (each run is a contiguous key range and a union of aligned
+ * quadtree cells), COUNT of a run = ub - lb, SUM = prefix[ub] - prefix[lb].
+ * The searches are binary searches or a RadixSpline (Sec. 3: spline knots
+ * with a bounded error plus a radix table over the key prefixes).  The
+ * answer is the one sba_aggregate gives over the same points and handle.
+ */
+typedef struct sba_pindex sba_pindex;
+
+typedef struct {
+    int32_t radix_bits;   /* RadixSpline radix table: 2^radix_bits + 2 entries over the top
+                             bits of the key (0 -> 20; 1..28, capped at 2L)             */
+    int32_t spline_err;   /* RadixSpline error bound in positions (0 -> 32; 1..2^20)     */
+} sba_pindex_opts;
+
+typedef struct {
+    int64_t n;            /* points indexed */
+    int64_t eps, s;       /* distance bound and cell side (as for a handle)           */
+    int64_t key_i0, key_j0;  /* key grid origin, in cells                              */
+    int32_t key_level;    /* key grid side 2^key_level cells                          */
+    int32_t has_values;   /* prefix sums stored                                        */
+    int64_t n_distinct;   /* distinct cell keys                                        */
+    int64_t n_knots;      /* RadixSpline knots                                         */
+    int32_t radix_bits, spline_err;
+    int64_t bytes;        /* device bytes held by the index                           */
+    double  build_ms;     /* wall time of the build, host clock                       */
+} sba_pindex_info_t;
+
+/*
+ * Build the point index of n points for cell side s(eps) (the same cells as
+ * a handle built with eps).
+ *   xy      [2n] int32 x,y interleaved (DEVICE), read during the call only.
+ *   values  [n] int64 (DEVICE) or NULL (COUNT only).
+ *   eps     2 <= eps <= 2^28.   opts: host pointer or NULL for defaults.
+ *   stream  work is queued on it; the call synchronises it (it reads the
+ *           point box and sizes back) and returns once the index is complete.
+ * The key grid is anchored at the first cell of the points' cell box, L =
+ * smallest level covering it.  Limits (SBA_ELIMIT): n < 2^31; the points'
+ * cell box at most 2^21 cells and less than 2^31 coordinate units per side.
+ * Errors: SBA_EINVAL, SBA_ENOMEM, SBA_EDEVICE, SBA_ELIMIT.
+ */
+int sba_pindex_build(const int32_t *xy, const int64_t *values, int64_t n, int64_t eps,
+                     const sba_pindex_opts *opts, void *stream, sba_pindex **out);
+
+/* Index metadata (host struct). */
+int sba_pindex_info(const sba_pindex *ix, sba_pindex_info_t *info);
+
+/*
+ * Per-polygon COUNT and SUM of the indexed points over the approximation h.
+ *   h       a Hilbert handle whose cell side and key grid are the index's
+ *           (built with opts.key_level / key_i0 / key_j0 from sba_pindex_info
+ *           and the same eps), else SBA_EINVAL.  A handle without polygons
+ *           or with no cell in the key grid gives zero outputs.
+ *   search  SBA_SEARCH_BINARY (binary searches over the keys) or
+ *           SBA_SEARCH_LEARNED (RadixSpline estimate, bounded search, full
+ *           binary search if the bound ever fails).
+ *   counts  [n_polys] uint64, overwritten.  sums [n_polys] int64, overwritten
+ *           (may be NULL; SBA_EINVAL if non-NULL and the index has no values).
+ * Asynchronous on `stream`; allocates nothing.  Sums wrap modulo 2^64.
+ */
+int sba_pindex_aggregate(const sba_pindex *ix, const sba_handle *h, int32_t search,
+                         uint64_t *counts, int64_t *sums, void *stream);
+
+/* Release the index's device memory (no work using it may still be queued). */
+void sba_pindex_free(sba_pindex *ix);
 
 /* Static string describing an error code. */
 const char *sba_strerror(int code);

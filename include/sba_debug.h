@@ -42,6 +42,16 @@ int sba_debug_grid16_sets(int mode);
  * (comparison runs); 0: default.  Process-wide, read at build time. */
 int sba_debug_force_wide_grid(int on);
 
+/* Lower bounds in a point index: out[k] = number of indexed points whose cell
+ * key is below v[k] (0 <= v[k] <= 4^L), by binary search (search 0) or the
+ * RadixSpline (search 1).  v and out are DEVICE arrays of n entries; the host
+ * *fallbacks receives how many RadixSpline windows failed their check and
+ * needed the full search (the spline's error bound makes that 0).
+ * Synchronous (synchronises `stream`).  Test support. */
+struct sba_pindex;
+int sba_debug_pindex_lb(const struct sba_pindex *ix, const uint64_t *v, int64_t n, int32_t search,
+                        int64_t *out, int64_t *fallbacks, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

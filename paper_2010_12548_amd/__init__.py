@@ -14,7 +14,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Approx", "SbaError", "lib", "library_path", "celldiv", "hilbert", "hilbert_cell",
+__all__ = ["Approx", "PointIndex", "SbaError", "lib", "library_path", "celldiv", "hilbert", "hilbert_cell",
            "aggregate_batch", "bucket_points", "Task",
            "KIND_GRID", "KIND_HILBERT", "SEARCH_BINARY", "SEARCH_LEARNED"]
 
@@ -44,7 +44,19 @@ class _Opts(C.Structure):
     _fields_ = [("kind", C.c_int32), ("search", C.c_int32), ("log2_leaves", C.c_int32),
                 ("tile_log2", C.c_int32), ("use_window", C.c_int32), ("win_x0", C.c_int32),
                 ("win_y0", C.c_int32), ("win_x1", C.c_int32), ("win_y1", C.c_int32),
-                ("sub_log2", C.c_int32), ("boundary_only", C.c_int32)]
+                ("sub_log2", C.c_int32), ("boundary_only", C.c_int32),
+                ("key_level", C.c_int32), ("key_i0", C.c_int64), ("key_j0", C.c_int64)]
+
+
+class _PiOpts(C.Structure):
+    _fields_ = [("radix_bits", C.c_int32), ("spline_err", C.c_int32)]
+
+
+class _PiInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("eps", C.c_int64), ("s", C.c_int64), ("key_i0", C.c_int64),
+                ("key_j0", C.c_int64), ("key_level", C.c_int32), ("has_values", C.c_int32),
+                ("n_distinct", C.c_int64), ("n_knots", C.c_int64), ("radix_bits", C.c_int32),
+                ("spline_err", C.c_int32), ("bytes", C.c_int64), ("build_ms", C.c_double)]
 
 
 class _Task(C.Structure):
@@ -120,6 +132,16 @@ def lib():
     L.sba_debug_force_wide_grid.argtypes = [C.c_int]
     L.sba_debug_set_blocks_per_cu.restype = C.c_int
     L.sba_debug_set_blocks_per_cu.argtypes = [C.c_int]
+    L.sba_pindex_build.restype = C.c_int
+    L.sba_pindex_build.argtypes = [vp, vp, i64, i64, C.POINTER(_PiOpts), vp, C.POINTER(vp)]
+    L.sba_pindex_info.restype = C.c_int
+    L.sba_pindex_info.argtypes = [vp, C.POINTER(_PiInfo)]
+    L.sba_pindex_aggregate.restype = C.c_int
+    L.sba_pindex_aggregate.argtypes = [vp, vp, i32, vp, vp, vp]
+    L.sba_pindex_free.restype = None
+    L.sba_pindex_free.argtypes = [vp]
+    L.sba_debug_pindex_lb.restype = C.c_int
+    L.sba_debug_pindex_lb.argtypes = [vp, vp, i64, i32, vp, C.POINTER(i64), vp]
     _lib = L
     return L
 
@@ -178,12 +200,14 @@ class Approx:
     window: optional clip window (x0, y0, x1, y1), half-open, in coordinates.
     boundary_only: store only the boundary cells; aggregate() then returns the
     partial counts and sums beta of the result range [alpha - beta, alpha].
+    key_grid: Hilbert only; a PointIndex (or its (level, i0, j0)) whose key
+    grid the runs are built on, so that PointIndex.aggregate can answer them.
     """
 
     def __init__(self, ring_off, vert_off, xy, eps: int, kind: str = "grid",
                  search: str = "binary", log2_leaves: int = 16, tile_log2: int = 0,
                  window=None, device: str = "cuda", stream=None, sub_log2: int = 0,
-                 boundary_only: bool = False):
+                 boundary_only: bool = False, key_grid=None):
         torch = _torch()
         self._h = C.c_void_p(None)
         self.device = torch.device(device)
@@ -196,7 +220,7 @@ class Approx:
         opts = _Opts({"grid": KIND_GRID, "hilbert": KIND_HILBERT}[kind],
                      {"binary": SEARCH_BINARY, "learned": SEARCH_LEARNED}[search],
                      int(log2_leaves), int(tile_log2), *win, int(sub_log2),
-                     1 if boundary_only else 0)
+                     1 if boundary_only else 0, *_key_grid(key_grid))
         h = C.c_void_p(None)
         with torch.cuda.device(self.device):
             rc = lib().sba_build_approx(C.byref(polys), int(eps), C.byref(opts),
@@ -310,6 +334,97 @@ class Approx:
                 k = -2 - r
                 out.append(tuple(int(v) for v in ids[off[k]:off[k + 1]]))
         return out
+
+
+def _key_grid(g):
+    if g is None:
+        return (0, 0, 0)
+    if isinstance(g, PointIndex):
+        return g.key_grid()
+    level, i0, j0 = g
+    return (int(level), int(i0), int(j0))
+
+
+class PointIndex:
+    """Point-side pre-aggregation (``sba_pindex_build``): the points' cell keys
+    on the Hilbert curve, sorted, with prefix sums of the values and a
+    RadixSpline over the keys.  xy: int32 GPU tensor [2n]; values: int64 [n]
+    or None.  A query (aggregate) takes a Hilbert Approx built with
+    key_grid=this index and the same eps."""
+
+    def __init__(self, xy, values, eps: int, radix_bits: int = 0, spline_err: int = 0,
+                 device: str = "cuda", stream=None):
+        torch = _torch()
+        self._ix = C.c_void_p(None)
+        self.device = torch.device(device)
+        xy = _dev(xy, torch.int32, self.device)
+        vals = _dev(values, torch.int64, self.device) if values is not None else None
+        n = xy.numel() // 2
+        opts = _PiOpts(int(radix_bits), int(spline_err))
+        ix = C.c_void_p(None)
+        with torch.cuda.device(self.device):
+            rc = lib().sba_pindex_build(xy.data_ptr(), vals.data_ptr() if vals is not None else None,
+                                        n, int(eps), C.byref(opts), _stream_ptr(stream),
+                                        C.byref(ix))
+        _check(rc, "sba_pindex_build")
+        self._ix = ix
+        self.eps = int(eps)
+        self.has_values = values is not None
+
+    def info(self) -> dict:
+        inf = _PiInfo()
+        _check(lib().sba_pindex_info(self._ix, C.byref(inf)), "sba_pindex_info")
+        return {k: getattr(inf, k) for k, _ in _PiInfo._fields_}
+
+    def key_grid(self):
+        i = self.info()
+        return (i["key_level"], i["key_i0"], i["key_j0"])
+
+    def aggregate(self, approx: "Approx", search: str = "binary", counts=None, sums=None,
+                  with_values: bool | None = None, stream=None):
+        """Per-polygon (counts, sums) of the indexed points over approx's
+        runs, as int64 GPU tensors (sums None for COUNT)."""
+        torch = _torch()
+        if with_values is None:
+            with_values = self.has_values
+        np_ = max(approx.n_polys, 1)
+        if counts is None:
+            counts = torch.empty(np_, dtype=torch.int64, device=self.device)
+        if with_values and sums is None:
+            sums = torch.empty(np_, dtype=torch.int64, device=self.device)
+        code = {"binary": SEARCH_BINARY, "learned": SEARCH_LEARNED}[search]
+        rc = lib().sba_pindex_aggregate(self._ix, approx._h, code, counts.data_ptr(),
+                                        sums.data_ptr() if with_values else None,
+                                        _stream_ptr(stream))
+        _check(rc, "sba_pindex_aggregate")
+        n = approx.n_polys
+        return counts[:n], (sums[:n] if with_values else None)
+
+    def lower_bounds(self, v, search: str = "learned", stream=None):
+        """Test support: (number of indexed keys below each v as an int64 GPU
+        tensor, RadixSpline windows that needed the full search)."""
+        torch = _torch()
+        v = _dev(v, torch.int64, self.device)
+        n = v.numel()
+        out = torch.empty(max(n, 1), dtype=torch.int64, device=self.device)
+        fb = C.c_int64(0)
+        code = {"binary": SEARCH_BINARY, "learned": SEARCH_LEARNED}[search]
+        _check(lib().sba_debug_pindex_lb(self._ix, v.data_ptr(), n, code, out.data_ptr(),
+                                         C.byref(fb), _stream_ptr(stream)), "sba_debug_pindex_lb")
+        return out[:n], int(fb.value)
+
+    def close(self, sync: bool = True):
+        if self._ix:
+            if sync:
+                _torch().cuda.synchronize(self.device)
+            lib().sba_pindex_free(self._ix)
+            self._ix = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Task:

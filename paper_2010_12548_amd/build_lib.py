@@ -5,7 +5,8 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["alloc.hip", "prims.hip", "build.hip", "hilbert.hip", "probe.hip", "serve.hip", "api.hip"]
+SOURCES = ["alloc.hip", "prims.hip", "build.hip", "hilbert.hip", "probe.hip", "serve.hip", "pindex.hip",
+           "api.hip"]
 OUT = os.path.join(HERE, "libsba.so")
 
 FLAGS = [

@@ -779,6 +779,24 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
             return 0;
         }
     }
+    if (B.key_level > 0) {
+        // a given key grid: cells outside it are cut off (at the grid's own
+        // edges, which the curve never crosses, so no border keys are
+        // needed), and the stored box starts at the grid's first cell
+        const int64_t side = (int64_t)1 << B.key_level;
+        gi0 = std::max(gi0, B.key_i0);
+        gj0 = std::max(gj0, B.key_j0);
+        gi1 = std::min(gi1, B.key_i0 + side - 1);
+        gj1 = std::min(gj1, B.key_j0 + side - 1);
+        if (gi0 > gi1 || gj0 > gj1) {
+            h->gi0 = h->gj0 = 0;
+            h->gw = h->gh = 0;
+            B.empty = true;
+            return 0;
+        }
+        gi0 = B.key_i0;
+        gj0 = B.key_j0;
+    }
     h->gi0 = gi0;
     h->gj0 = gj0;
     h->gw = gi1 - gi0 + 1;
@@ -1176,15 +1194,15 @@ int build_handle(const sba_polygons *polys, int64_t eps, const sba_build_opts *o
     if (o.kind != SBA_KIND_GRID && o.kind != SBA_KIND_HILBERT) return SBA_EINVAL;
     if (o.search != SBA_SEARCH_BINARY && o.search != SBA_SEARCH_LEARNED) return SBA_EINVAL;
     if (o.log2_leaves < 1 || o.log2_leaves > 24) return SBA_EINVAL;
+    if (o.key_level < 0 || o.key_level > 21 || (o.key_level > 0 && o.kind != SBA_KIND_HILBERT))
+        return SBA_EINVAL;
+    if (o.key_level > 0 && (o.key_i0 < -((int64_t)1 << 31) || o.key_i0 >= ((int64_t)1 << 31) ||
+                            o.key_j0 < -((int64_t)1 << 31) || o.key_j0 >= ((int64_t)1 << 31)))
+        return SBA_EINVAL;
     h->kind = o.kind;
     h->search = o.search;
     h->eps = eps;
-    int64_t t = eps * eps / 2, s = 0;
-    while ((s + 1) * (s + 1) <= t) {  // isqrt by bisection-free doubling + linear finish
-        int64_t step = 1;
-        while ((s + 2 * step) * (s + 2 * step) <= t) step *= 2;
-        s += step;
-    }
+    const int64_t s = cell_side(eps);
     h->s = s;
     magic_for(s, &h->mag, &h->shift);
     h->n_polys = polys->n_polys;
@@ -1201,6 +1219,9 @@ int build_handle(const sba_polygons *polys, int64_t eps, const sba_build_opts *o
     B.wy0 = o.win_y0;
     B.wx1 = o.win_x1;
     B.wy1 = o.win_y1;
+    B.key_level = o.key_level;
+    B.key_i0 = o.key_i0;
+    B.key_j0 = o.key_j0;
     if (h->kind == SBA_KIND_HILBERT) RC(hilbert_prepare(B, h));
     RC(build_segments(polys, eps, st, h, B, h->kind == SBA_KIND_HILBERT));
     if (B.empty) {

@@ -32,6 +32,9 @@ struct BuildState {
     bool window = false;
     int64_t wx0 = 0, wy0 = 0, wx1 = 0, wy1 = 0;
     bool empty = false;  // the window holds no cell of any polygon
+    // Hilbert key grid given by the caller (key_level 0: the stored box's own)
+    int32_t key_level = 0;
+    int64_t key_i0 = 0, key_j0 = 0;
     // edges: (x1,y1,x2,y2) and polygon id, one per vertex
     int4 *edges = nullptr;
     int32_t *epoly = nullptr;

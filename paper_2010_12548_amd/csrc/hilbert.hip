@@ -7,7 +7,8 @@
 // cell array).
 //
 // The key grid is anchored at the first cell of the stored box (the union of
-// the polygons' cell boxes), so every cell of every approximation has a key.
+// the polygons' cell boxes), so every cell of every approximation has a key;
+// or at a grid the caller gives (a point index's), the box cut to it.
 //
 // Runs are found without visiting interior cells.  Consecutive Hilbert cells
 // share an edge; two edge-adjacent cells that are boundary cells of no
@@ -132,6 +133,7 @@ int hilbert_prepare(BuildState &B, sba_handle *h)
         // key grid: the stored cell box, padded to 2^L x 2^L
         int L = 1;
         while (((int64_t)1 << L) < std::max(hh->gw, hh->gh)) L++;
+        if (b.key_level > 0) L = b.key_level;  // the box was cut to fit it
         if (L > 21) return SBA_ELIMIT;
         hh->level = L;
         return hilbert_boundary_cells(b, hh, st);

@@ -185,6 +185,20 @@ __host__ __device__ inline uint32_t divmagic(uint32_t n, uint32_t mag, int32_t s
 
 void magic_for(int64_t s, uint32_t *mag, int32_t *shift);
 
+// Cell side for distance bound eps (Sec. 2.2): the largest integer s with
+// 2 s^2 <= eps^2, i.e. isqrt(floor(eps^2 / 2)), found by doubling steps.
+inline int64_t cell_side(int64_t eps)
+{
+    const int64_t t = eps * eps / 2;
+    int64_t s = 0;
+    while ((s + 1) * (s + 1) <= t) {
+        int64_t step = 1;
+        while ((s + 2 * step) * (s + 2 * step) <= t) step *= 2;
+        s += step;
+    }
+    return s;
+}
+
 // Hilbert index d(i,j) of cell (i,j) on the 2^L x 2^L grid: quadrant order
 // (0,0),(0,1),(1,1),(1,0) at every level, sub-squares re-oriented so that
 // consecutive indices are edge-adjacent (Sec. 3, linearisation of cells).
