@@ -22,10 +22,11 @@
 // uses): F is a step function, so it is enough to bound the error at the two
 // ends of every step: for distinct keys D_0 < ... < D_{M-1} with first
 // positions P_m, the corners (D_{m-1} + 1, P_m) and (D_m, P_m) (D_{-1} + 1 =
-// 0), then (D_{M-1} + 1, n) and (4^L, n).  The corners are cut into chunks;
-// one thread runs the greedy corridor over each chunk from its first to its
-// last corner (both become knots).  Two consecutive corners are exact on
-// every integer key between them, so the chunk seams add no error.
+// 0), then (D_{M-1} + 1, n) and (4^L, n).  The distinct keys are cut into
+// chunks; one thread runs the greedy corridor over the corners of each chunk
+// from its first to its last corner (both become knots).  Two consecutive
+// corners are exact on every integer key between them, so the chunk seams add
+// no error.
 #include <chrono>
 #include <new>
 #include <vector>
@@ -154,32 +155,20 @@ struct Corners {
     uint64_t total;
 };
 
-// corner j of the step function F (0 <= j < 2M + 2); equal keys come with
-// equal positions, keys are non-decreasing in j
-__device__ __forceinline__ void corner(const Corners &C, int64_t j, uint64_t *x, int64_t *y)
-{
-    const int64_t m = j >> 1;
-    if (m < C.M) {
-        *y = C.P[m];
-        *x = (j & 1) ? C.D[m] : (m == 0 ? 0 : C.D[m - 1] + 1);
-    } else {
-        *y = C.n;
-        *x = (j & 1) ? C.total : C.D[C.M - 1] + 1;
-    }
-}
-
-// Greedy corridor over the corners [c*CH, min((c+1)*CH, NC)): the knot moves
-// to the previous corner as soon as a corner's slope from the knot leaves the
-// band of slopes that keeps every corner since the knot within E.  Pass 1
-// counts the knots, pass 2 writes them at off[c] (off[nch] = total).
+// Greedy corridor over the corners of the distinct keys [c*CHM, min((c+1)*CHM,
+// M)) (the last chunk also takes the two corners after the last key): the
+// knot moves to the previous corner as soon as a corner's slope from the knot
+// leaves the band of slopes that keeps every corner since the knot within E.
+// Slopes are compared as cross products (no divisions; positive run lengths).
+// Pass 1 counts the knots, pass 2 writes them at off[c] (off[nch] = total).
 template <bool WRITE>
-__global__ void k_spline(Corners C, int64_t NC, int64_t CH, double E, int64_t *cnt,
-                         const int64_t *off, uint64_t *kx, int64_t *ky)
+__global__ void k_spline(Corners C, int64_t CHM, double E, int64_t *cnt, const int64_t *off,
+                         uint64_t *kx, int64_t *ky)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t a = c * CH;
-    if (a >= NC) return;
-    const int64_t b = min(a + CH, NC);
+    const int64_t a = c * CHM;
+    if (a >= C.M) return;
+    const int64_t b = min(a + CHM, C.M);
     int64_t k = 0;
     const int64_t base = WRITE ? off[c] : 0, lim = WRITE ? off[c + 1] - base : 0;
     auto emit = [&](uint64_t x, int64_t y) {
@@ -189,34 +178,48 @@ __global__ void k_spline(Corners C, int64_t NC, int64_t CH, double E, int64_t *c
         }
         k++;
     };
-    uint64_t x0, lx;
-    int64_t y0, ly;
-    corner(C, a, &x0, &y0);
+    uint64_t x0 = a == 0 ? 0 : C.D[a - 1] + 1, lx;
+    int64_t y0 = C.P[a], ly;
     emit(x0, y0);
     lx = x0;
     ly = y0;
-    double up = INFINITY, lo = -INFINITY;
-    for (int64_t j = a + 1; j < b; j++) {
-        uint64_t x;
-        int64_t y;
-        corner(C, j, &x, &y);
-        if (x == lx) continue;  // the same corner again
+    double un = 0, ud = 1, ln = 0, ld = 1;  // band: slopes in [ln/ld, un/ud]
+    bool band = false;
+    auto feed = [&](uint64_t x, int64_t y) {
+        if (x == lx) return;  // the same corner again (equal keys, equal positions)
         double dx = (double)(x - x0), dy = (double)(y - y0);
-        const double sl = dy / dx;
-        if (sl > up || sl < lo) {
+        if (band && (dy * ud > un * dx || dy * ld < ln * dx)) {
             emit(lx, ly);
             x0 = lx;
             y0 = ly;
             dx = (double)(x - x0);
             dy = (double)(y - y0);
-            up = (dy + E) / dx;
-            lo = (dy - E) / dx;
-        } else {
-            up = fmin(up, (dy + E) / dx);
-            lo = fmax(lo, (dy - E) / dx);
+            band = false;
         }
+        if (!band || (dy + E) * ud < un * dx) {
+            un = dy + E;
+            ud = dx;
+        }
+        if (!band || (dy - E) * ld > ln * dx) {
+            ln = dy - E;
+            ld = dx;
+        }
+        band = true;
         lx = x;
         ly = y;
+    };
+    uint64_t prev = C.D[a];
+    feed(prev, y0);
+    for (int64_t m = a + 1; m < b; m++) {
+        const uint64_t d = C.D[m];
+        const int64_t p = C.P[m];
+        feed(prev + 1, p);
+        feed(d, p);
+        prev = d;
+    }
+    if (b == C.M) {
+        feed(prev + 1, C.n);
+        feed(C.total, C.n);
     }
     if (lx != x0) emit(lx, ly);
     if (!WRITE) cnt[c] = k;
@@ -448,10 +451,10 @@ static int pindex_build(const int32_t *xy, const int64_t *values, int64_t n, sba
 
     // RadixSpline knots over the corners of F, then the radix table
     const Corners C{D, P, M, n, total};
-    const int64_t NC = 2 * M + 2, CH = 2048, nch = (NC + CH - 1) / CH;
+    const int64_t CHM = 1024, nch = (M + CHM - 1) / CHM;
     int64_t *cnt = nullptr;
     RC(ws.alloc(&cnt, nch + 1));
-    hipLaunchKernelGGL(k_spline<false>, dim3(grid_for(nch)), dim3(256), 0, st, C, NC, CH,
+    hipLaunchKernelGGL(k_spline<false>, dim3(grid_for(nch)), dim3(256), 0, st, C, CHM,
                        (double)ix->spline_err, cnt, (const int64_t *)nullptr, (uint64_t *)nullptr,
                        (int64_t *)nullptr);
     HIP_OK(hipGetLastError());
@@ -462,7 +465,7 @@ static int pindex_build(const int32_t *xy, const int64_t *values, int64_t n, sba
     ix->n_knots = nk;
     RC(ix_alloc(ix, &ix->kx, nk));
     RC(ix_alloc(ix, &ix->ky, nk));
-    hipLaunchKernelGGL(k_spline<true>, dim3(grid_for(nch)), dim3(256), 0, st, C, NC, CH,
+    hipLaunchKernelGGL(k_spline<true>, dim3(grid_for(nch)), dim3(256), 0, st, C, CHM,
                        (double)ix->spline_err, (int64_t *)nullptr, (const int64_t *)cnt, ix->kx,
                        ix->ky);
     HIP_OK(hipGetLastError());
