@@ -44,6 +44,9 @@ def lib():
     L.orc_raster_brute.restype = C.c_int
     L.orc_raster_brute.argtypes = [C.c_int32, _i32p, _i64p, _i32p, C.c_int64, C.c_int64,
                                    C.c_int64, C.c_int64, C.c_int64, _u8p]
+    L.orc_centre_brute.restype = C.c_int
+    L.orc_centre_brute.argtypes = [C.c_int32, _i32p, _i64p, _i32p, C.c_int64, C.c_int64,
+                                   C.c_int64, C.c_int64, C.c_int64, _u8p]
     L.orc_build.restype = C.c_void_p
     L.orc_build.argtypes = [C.c_int32, _i32p, _i64p, _i32p, C.c_int64]
     L.orc_build_mode.restype = C.c_void_p
@@ -101,6 +104,18 @@ def raster_brute(polys, s: int, i0: int, j0: int, nw: int, nh: int) -> np.ndarra
     return out.reshape(polys.n_polys, nh, nw)
 
 
+def centre_brute(polys, s: int, i0: int, j0: int, nw: int, nh: int) -> np.ndarray:
+    """Per-polygon membership of the centre-sampled approximation over a
+    window: uint8 [P, nh, nw], 1 if the cell's centre is inside P.
+    Definition form (Sec. 2.2, non-conservative raster)."""
+    ro, vo, xy = _poly_arrays(polys)
+    out = np.zeros(polys.n_polys * nh * nw, np.uint8)
+    rc = lib().orc_centre_brute(polys.n_polys, ro, vo, xy, s, i0, j0, nw, nh, out)
+    if rc:
+        raise ValueError("orc_centre_brute rejected its input")
+    return out.reshape(polys.n_polys, nh, nw)
+
+
 def hilbert_d(L: int, i: int, j: int) -> int:
     return int(lib().orc_hilbert_d(L, int(i), int(j)))
 
@@ -110,17 +125,22 @@ class Approx:
 
     boundary_only=True holds B(P) instead: the boundary cells alone, over
     which the partial count of the result range [alpha - beta, alpha]
-    (Sec. 6, result range estimation) is taken.
+    (Sec. 6, result range estimation) is taken.  centre=True holds the
+    centre-sampled approximation C(P) (Sec. 2.2, non-conservative): the cells
+    whose centre is inside P.
     """
 
-    def __init__(self, polys, eps: int, boundary_only: bool = False):
+    def __init__(self, polys, eps: int, boundary_only: bool = False, centre: bool = False):
         ro, vo, xy = _poly_arrays(polys)
         self._keep = (ro, vo, xy)
         self.n_polys = polys.n_polys
         self.eps = int(eps)
         self.boundary_only = bool(boundary_only)
+        if boundary_only and centre:
+            raise ValueError("boundary_only and centre exclude each other")
+        self.centre = bool(centre)
         self._h = lib().orc_build_mode(polys.n_polys, ro, vo, xy, int(eps),
-                                       1 if boundary_only else 0)
+                                       1 if boundary_only else (2 if centre else 0))
         if not self._h:
             raise ValueError("oracle rejected the polygons or eps")
         self.s = int(lib().orc_cell_side_of(self._h))

@@ -43,6 +43,12 @@
  *          the approximate and the exact predicate differ has p within
  *          distance eps of the boundary of P, and no point inside P is
  *          missed (conservative raster: false positives only).
+ *   C(P)   Centre-sampled approximation (Sec. 2.2, non-conservative raster:
+ *          cells with little overlap may be left out, so false negatives are
+ *          allowed): the cells whose centre ((i+1/2)s, (j+1/2)s) is inside P
+ *          by the crossing-number rule.  A point whose membership differs
+ *          from its cell centre's is separated from the centre by the
+ *          boundary, so it lies within half a diagonal, eps/2, of it.
  *   hilbert (Sec. 3, linearisation of cells by a space-filling curve): the
  *          Hilbert index d(i,j) at level L with (0,0)->0, (0,1)->1,
  *          (1,1)->2, (1,0)->3 at level 1, and the maximal runs of
@@ -162,6 +168,16 @@ static int point_in_poly(const polyset *ps, int32_t p, int64_t px, int64_t py)
     return odd;
 }
 
+/* point_in_poly at a point given in doubled coordinates (2px, 2py): the
+ * polygon is doubled with it, which changes no incidence */
+static int point_in_poly2(const polyset *ps, int32_t p, int64_t px2, int64_t py2)
+{
+    int odd = 0;
+    FOR_EACH_EDGE(ps, p, x1, y1, x2, y2,
+                  { odd ^= edge_crosses_ray(px2, py2, 2 * x1, 2 * y1, 2 * x2, 2 * y2); })
+    return odd;
+}
+
 static int cell_in_boundary(const polyset *ps, int32_t p, int64_t s, int64_t i, int64_t j)
 {
     int64_t qx0 = i * s, qy0 = j * s, qx1 = qx0 + s, qy1 = qy0 + s;
@@ -192,6 +208,17 @@ static int near_boundary(const polyset *ps, int32_t p, int64_t px, int64_t py, i
     i128 e2 = (i128)eps * eps;
     FOR_EACH_EDGE(ps, p, x1, y1, x2, y2, {
         if (seg_within(px, py, x1, y1, x2, y2, e2)) return 1;
+    })
+    return 0;
+}
+
+/* within eps/2 of the boundary: distance of the doubled point to the doubled
+ * polygon within eps */
+static int near_boundary_half(const polyset *ps, int32_t p, int64_t px, int64_t py, int64_t eps)
+{
+    i128 e2 = (i128)eps * eps;
+    FOR_EACH_EDGE(ps, p, x1, y1, x2, y2, {
+        if (seg_within(2 * px, 2 * py, 2 * x1, 2 * y1, 2 * x2, 2 * y2, e2)) return 1;
     })
     return 0;
 }
@@ -254,6 +281,23 @@ int orc_raster_brute(int32_t n_polys, const int32_t *ring_off, const int64_t *ve
     return 0;
 }
 
+/* The centre-sampled approximation by its definition, cell by cell:
+ * out[(p*nh + (j-j0))*nw + (i-i0)] = 1 if the centre of cell (i,j) is inside
+ * P, else 0.  For tiny inputs only. */
+int orc_centre_brute(int32_t n_polys, const int32_t *ring_off, const int64_t *vert_off,
+                     const int32_t *xy, int64_t s, int64_t i0, int64_t j0,
+                     int64_t nw, int64_t nh, uint8_t *out)
+{
+    polyset ps = {n_polys, ring_off, vert_off, xy};
+    if (s < 1 || nw < 0 || nh < 0 || polys_ok(&ps)) return -1;
+    for (int32_t p = 0; p < n_polys; p++)
+        for (int64_t j = j0; j < j0 + nh; j++)
+            for (int64_t i = i0; i < i0 + nw; i++)
+                out[((int64_t)p * nh + (j - j0)) * nw + (i - i0)] =
+                    (uint8_t)point_in_poly2(&ps, p, (2 * i + 1) * s, (2 * j + 1) * s);
+    return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* scanline raster: A(P) as sorted, disjoint row intervals             */
 /* ------------------------------------------------------------------ */
@@ -306,9 +350,20 @@ typedef struct {
  *  number of k exceed i, i.e. i in [k1,k2) u [k3,k4) u ...
  *
  *  A(P) = B(P) u I(P) = B(P) u {cells whose corner is inside}, since the
- *  second set differs from I(P) only by cells of B(P). */
-static int build_rows(const polyset *ps, int32_t p, int64_t s, int with_interior, prows *out)
+ *  second set differs from I(P) only by cells of B(P).
+ *
+ *  centre-sampled (mode ORC_CENTRE) -- no boundary part; the row line is the
+ *  line of the centres, y = (j+1/2)s, crossed by the edges with
+ *  2 ymin <= (2j+1)s < 2 ymax.  With 2xc = N/D (D = y2-y1 > 0 after a sign
+ *  change) the centre of cell i lies left of the crossing iff
+ *  (2i+1) s D < N, i.e. i < ceil((N - sD) / (2sD)); spans as above.
+ *
+ *  mode: ORC_FULL A(P), ORC_BOUNDARY B(P) only, ORC_CENTRE C(P). */
+enum { ORC_FULL = 0, ORC_BOUNDARY = 1, ORC_CENTRE = 2 };
+
+static int build_rows(const polyset *ps, int32_t p, int64_t s, int mode, prows *out)
 {
+    const int with_interior = mode != ORC_BOUNDARY, with_boundary = mode != ORC_CENTRE;
     int64_t xmin, ymin, xmax, ymax;
     poly_bbox(ps, p, &xmin, &ymin, &xmax, &ymax);
     out->ci0 = (int64_t)cdiv(xmin, s) - 1;
@@ -324,6 +379,7 @@ static int build_rows(const polyset *ps, int32_t p, int64_t s, int with_interior
         int64_t ey0 = min64(y1, y2), ey1 = max64(y1, y2);
         /* boundary strips */
         int64_t ja = (int64_t)cdiv(ey0, s) - 1, jb = (int64_t)fdiv(ey1, s);
+        if (!with_boundary) jb = ja - 1;
         for (int64_t j = ja; j <= jb && !err; j++) {
             int64_t c0, c1;
             if (y1 == y2) {
@@ -343,8 +399,19 @@ static int build_rows(const polyset *ps, int32_t p, int64_t s, int with_interior
             }
             if (ivec_push(&iv, j, c0, c1 + 1)) err = 1;
         }
+        /* crossings of centre lines y = (j+1/2)s with (2j+1)s in [2 ey0, 2 ey1) */
+        if (y1 != y2 && mode == ORC_CENTRE) {
+            int64_t ka = (int64_t)cdiv(2 * ey0 - s, 2 * s), kb = (int64_t)cdiv(2 * ey1 - s, 2 * s) - 1;
+            for (int64_t j = ka; j <= kb && !err; j++) {
+                i128 den = (i128)(y2 - y1);
+                i128 num = (i128)2 * x1 * den + ((i128)(2 * j + 1) * s - 2 * y1) * (x2 - x1);
+                if (den < 0) { den = -den; num = -num; }
+                int64_t k = (int64_t)cdiv(num - s * den, 2 * s * den);
+                if (ivec_push(&cr, j, k, 0)) err = 1;
+            }
+        }
         /* crossings of row lines y = js with js in [ey0, ey1) */
-        if (y1 != y2) {
+        if (y1 != y2 && mode != ORC_CENTRE) {
             int64_t ka = (int64_t)cdiv(ey0, s), kb = (int64_t)cdiv(ey1, s) - 1;
             for (int64_t j = ka; j <= kb && !err; j++) {
                 i128 den = (i128)(y2 - y1);
@@ -410,6 +477,7 @@ static int prows_contains(const prows *pr, int64_t i, int64_t j)
 
 typedef struct {
     int64_t eps, s;
+    int mode;                     /* ORC_FULL, ORC_BOUNDARY or ORC_CENTRE */
     int32_t n_polys;
     int32_t *ring_off; int64_t *vert_off; int32_t *xy;   /* own copy */
     polyset ps;
@@ -435,18 +503,18 @@ void orc_free(orc_approx *a)
     free(a);
 }
 
-/* boundary_only = 1: only the boundary cells B(P) of every polygon (the
- * cells over which the partial count of Sec. 6's result range is taken);
- * 0: A(P) = B(P) u I(P). */
+/* mode 1: only the boundary cells B(P) of every polygon (the cells over
+ * which the partial count of Sec. 6's result range is taken); 2: the
+ * centre-sampled C(P); 0: A(P) = B(P) u I(P). */
 orc_approx *orc_build_mode(int32_t n_polys, const int32_t *ring_off, const int64_t *vert_off,
-                           const int32_t *xy, int64_t eps, int boundary_only)
+                           const int32_t *xy, int64_t eps, int mode)
 {
     int64_t s = orc_cell_side(eps);
     polyset in = {n_polys, ring_off, vert_off, xy};
-    if (s < 1 || n_polys < 0 || polys_ok(&in)) return NULL;
+    if (s < 1 || n_polys < 0 || polys_ok(&in) || mode < 0 || mode > 2) return NULL;
     orc_approx *a = (orc_approx *)calloc(1, sizeof(orc_approx));
     if (!a) return NULL;
-    a->eps = eps; a->s = s; a->n_polys = n_polys;
+    a->eps = eps; a->s = s; a->n_polys = n_polys; a->mode = mode;
     int32_t nr = ring_off[n_polys];
     int64_t nv = vert_off[nr];
     a->ring_off = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n_polys + 1));
@@ -463,7 +531,7 @@ orc_approx *orc_build_mode(int32_t n_polys, const int32_t *ring_off, const int64
     int fail = 0;
     #pragma omp parallel for schedule(dynamic, 1) reduction(|:fail)
     for (int32_t p = 0; p < n_polys; p++)
-        if (build_rows(&a->ps, p, s, !boundary_only, &a->rows[p])) fail = 1;
+        if (build_rows(&a->ps, p, s, mode, &a->rows[p])) fail = 1;
     if (fail) { orc_free(a); return NULL; }
 
     /* bucket filter */
@@ -660,9 +728,10 @@ int orc_exact_join(const orc_approx *a, const int32_t *xy, const int64_t *vals, 
 
 /* Invariant check over the given points.  out[0] = (point, polygon) pairs
  * where approximate and exact membership differ; out[1] = such pairs farther
- * than eps from the boundary of P (must be 0); out[2] = false negatives,
- * i.e. p inside P with cell(p) not in A(P) (must be 0); out[3] = pairs
- * inside P (exact). */
+ * than eps (centre-sampled: eps/2) from the boundary of P (must be 0);
+ * out[2] = false negatives, i.e. p inside P with cell(p) not in the
+ * approximation (must be 0 unless centre-sampled); out[3] = pairs inside P
+ * (exact). */
 int orc_invariant(const orc_approx *a, const int32_t *xy, int64_t n, int64_t *out, int nthreads)
 {
     int nt = nthreads_of(nthreads);
@@ -680,7 +749,9 @@ int orc_invariant(const orc_approx *a, const int32_t *xy, int64_t n, int64_t *ou
             ins += ex;
             if (ap != ex) {
                 diff++;
-                if (!near_boundary(&a->ps, p, px, py, a->eps)) far++;
+                if (a->mode == ORC_CENTRE ? !near_boundary_half(&a->ps, p, px, py, a->eps)
+                                          : !near_boundary(&a->ps, p, px, py, a->eps))
+                    far++;
                 if (ex && !ap) fneg++;
             }
         }
@@ -702,7 +773,9 @@ int orc_invariant_all(const orc_approx *a, const int32_t *xy, int64_t n, int64_t
             ins += ex;
             if (ap != ex) {
                 diff++;
-                if (!near_boundary(&a->ps, p, px, py, a->eps)) far++;
+                if (a->mode == ORC_CENTRE ? !near_boundary_half(&a->ps, p, px, py, a->eps)
+                                          : !near_boundary(&a->ps, p, px, py, a->eps))
+                    far++;
                 if (ex && !ap) fneg++;
             }
         }

@@ -460,3 +460,118 @@ def test_result_range_contains_exact(orc, eps):
     assert np.all(ac - bc <= ec) and np.all(ec <= ac)
     assert np.all(asum - bsum <= esum) and np.all(esum <= asum)
     assert np.any(ac - bc < ec) and np.any(ec < ac)   # the bounds are not trivially tight
+
+
+# ---------------------------------------------------------------- centre-sampled cells
+#
+# The non-conservative raster (Sec. 2.2): a cell belongs to P when its centre
+# is inside P.  Pinned by the per-cell definition, closed forms on rectangles
+# and right triangles (ties on edges decided by the half-open crossing rule),
+# the eps/2 bound on every misclassified point, and the partition property.
+
+def _centre_cells_1d(a, b, s):
+    # number of integers i with a <= (i + 1/2) s < b
+    return max(0, -(-(2 * b - s) // (2 * s)) - (-(-(2 * a - s) // (2 * s))))
+
+
+@pytest.mark.parametrize("eps", [2, 3, 5, 8, 9, 15])
+def test_centre_equals_definition_hand(orc, eps):
+    s = orc.cell_side(eps)
+    polys = polygons_from_rings(_hand_shapes())
+    i0, j0, nw, nh = cell_window(polys, s)
+    br = orc.centre_brute(polys, s, i0, j0, nw, nh)
+    C = orc.Approx(polys, eps, centre=True)
+    for p in range(polys.n_polys):
+        np.testing.assert_array_equal(member_from_intervals(C, p, i0, j0, nw, nh), br[p] == 1,
+                                      err_msg=f"polygon {p}")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_centre_equals_definition_random_stars(orc, seed):
+    rng = np.random.default_rng(seed)
+    polys = star_polygons(4, int(rng.integers(3, 12)), 5.0, 60.0, 200, 3000 + seed)
+    for eps in (2, 3, 4, 7, 13):
+        s = orc.cell_side(eps)
+        i0, j0, nw, nh = cell_window(polys, s)
+        br = orc.centre_brute(polys, s, i0, j0, nw, nh)
+        C = orc.Approx(polys, eps, centre=True)
+        for p in range(polys.n_polys):
+            np.testing.assert_array_equal(member_from_intervals(C, p, i0, j0, nw, nh), br[p] == 1)
+
+
+@pytest.mark.parametrize("s,a,b,c,d", [(5, 0, 35, 0, 40), (5, -15, 20, 10, 25), (4, 2, 18, 6, 22),
+                                       (4, -3, 13, 1, 30), (7, 3, 40, -11, 17), (1, -4, 9, 2, 5)])
+def test_centre_rectangle_closed_form(orc, s, a, b, c, d):
+    # the cells whose centre lies in [a,b) x [c,d) (left and bottom edges
+    # inclusive by the half-open crossing rule); on the full lattice each cell
+    # holds s^2 points.  Cell-aligned rectangles give exactly the exact count.
+    eps = {1: 2, 4: 6, 5: 8, 7: 10}[s]
+    assert orc.cell_side(eps) == s
+    polys = polygons_from_rings([[np.array([[a, c], [b, c], [b, d], [a, d]])]])
+    lo = (min(a, c) // s - 3) * s
+    hi = (max(b, d) // s + 4) * s
+    xy = lattice(lo, hi)
+    C = orc.Approx(polys, eps, centre=True)
+    cnt, _ = C.aggregate(xy)
+    assert int(cnt[0]) == s * s * _centre_cells_1d(a, b, s) * _centre_cells_1d(c, d, s)
+    if a % s == 0 and b % s == 0 and c % s == 0 and d % s == 0:
+        ex, _ = C.exact(xy)
+        assert int(cnt[0]) == int(ex[0]) == (b - a) * (d - c)
+
+
+@pytest.mark.parametrize("s,m", [(5, 10), (3, 7), (4, 5), (1, 9)])
+def test_centre_right_triangle_closed_form(orc, s, m):
+    # legs L = m s.  Triangle (0,0),(L,0),(0,L): centres with i + j = m - 1 lie
+    # on the hypotenuse, where the crossing rule puts them outside: m(m-1)/2
+    # cells, fewer lattice points than the exact L(L+1)/2 (false negatives).
+    # Triangle (0,0),(L,0),(L,L): the diagonal centres (i = j) lie on the
+    # hypotenuse with the right edge to their right, inside: m(m+1)/2 cells.
+    eps = {1: 2, 3: 5, 4: 6, 5: 8}[s]
+    assert orc.cell_side(eps) == s
+    L = m * s
+    xy = lattice(-2 * s, L + 2 * s)
+    lo = orc.Approx(polygons_from_rings([[np.array([[0, 0], [L, 0], [0, L]])]]), eps, centre=True)
+    cnt, _ = lo.aggregate(xy)
+    ex, _ = lo.exact(xy)
+    assert int(cnt[0]) == s * s * m * (m - 1) // 2
+    assert int(ex[0]) == L * (L + 1) // 2
+    up = orc.Approx(polygons_from_rings([[np.array([[0, 0], [L, 0], [L, L]])]]), eps, centre=True)
+    cnt, _ = up.aggregate(xy)
+    assert int(cnt[0]) == s * s * m * (m + 1) // 2
+
+
+@pytest.mark.parametrize("eps", [2, 6, 23, 64])
+def test_centre_within_half_eps(orc, eps):
+    # every point whose membership differs from its cell centre's lies within
+    # eps/2 of the boundary (checked exactly); false negatives do occur
+    rng = np.random.default_rng(200 + eps)
+    polys = star_polygons(8, 16, 30.0, 300.0, 1000, 231 + eps)
+    xy = rng.integers(-300, 1300, size=2 * 60000).astype(np.int32)
+    C = orc.Approx(polys, eps, centre=True)
+    inv = C.invariant(xy, exhaustive=True)
+    assert inv["far"] == 0
+    assert inv["differ"] > 0 and inv["false_neg"] > 0
+    assert C.invariant(xy) == inv
+    # the conservative approximation of the same polygons is further off: its
+    # misclassified points are not all within eps/2 (so the bound is a pin)
+    A = orc.Approx(polys, eps)
+    assert A.invariant(xy, exhaustive=True)["differ"] > inv["differ"]
+
+
+def test_centre_partition_counts_each_point_once(orc):
+    # on a partition of the box every cell centre inside the box lies in
+    # exactly one polygon, so the counts add up to the number of points whose
+    # cell centre is inside the box (no double counting on shared boundaries)
+    B = 200000
+    polys = voronoi_partition(30, B, (3, 20), seed=3, jitter_seed=4)
+    pts = uniform_points(300000, 0, B, 11)
+    for eps in (100, 1500, 7777):
+        s = orc.cell_side(eps)
+        C = orc.Approx(polys, eps, centre=True)
+        cnt, _ = C.aggregate(pts)
+        p = pts.reshape(-1, 2).astype(np.int64)
+        cx, cy = (2 * (p[:, 0] // s) + 1) * s, (2 * (p[:, 1] // s) + 1) * s
+        inside = int(np.count_nonzero((cx < 2 * B) & (cy < 2 * B)))
+        assert int(cnt.sum()) == inside
+        inv = C.invariant(pts)
+        assert inv["far"] == 0
