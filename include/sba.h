@@ -97,6 +97,13 @@ typedef struct {
                              so that sba_pindex_aggregate can answer from the handle's
                              runs); cells outside that grid are not stored.  1..21     */
     int64_t key_i0, key_j0;
+    int32_t centre_sampled; /* 1: the non-conservative approximation C(P) (Sec. 2.2: cells
+                             with little overlap may be left out): a cell belongs to P
+                             when its centre ((i+1/2)s, (j+1/2)s) is inside P by the
+                             crossing-number rule.  False negatives as well as false
+                             positives, every misclassified point within eps/2 of P's
+                             boundary; on a partition every point counts once.  Not with
+                             boundary_only.                                             */
 } sba_build_opts;
 
 typedef struct {
@@ -121,6 +128,7 @@ typedef struct {
     int32_t sub_log2;       /* grid: sub-tile side log2 (== tile_log2: no sub level) */
     int32_t compact;        /* grid: 1 = 16-bit codes (directory staged in LDS), 0 = 32-bit */
     int32_t boundary_only;  /* built with sba_build_opts.boundary_only */
+    int32_t centre_sampled; /* built with sba_build_opts.centre_sampled */
 } sba_info_t;
 
 /*

@@ -45,7 +45,8 @@ class _Opts(C.Structure):
                 ("tile_log2", C.c_int32), ("use_window", C.c_int32), ("win_x0", C.c_int32),
                 ("win_y0", C.c_int32), ("win_x1", C.c_int32), ("win_y1", C.c_int32),
                 ("sub_log2", C.c_int32), ("boundary_only", C.c_int32),
-                ("key_level", C.c_int32), ("key_i0", C.c_int64), ("key_j0", C.c_int64)]
+                ("key_level", C.c_int32), ("key_i0", C.c_int64), ("key_j0", C.c_int64),
+                ("centre_sampled", C.c_int32)]
 
 
 class _PiOpts(C.Structure):
@@ -75,7 +76,8 @@ class _Info(C.Structure):
                 ("n_segments", C.c_int64), ("n_boundary", C.c_int64), ("n_runs", C.c_int64),
                 ("max_leaf_err", C.c_int64), ("mean_leaf_err", C.c_double), ("bytes", C.c_int64),
                 ("build_ms", C.c_double), ("n_sub", C.c_int64), ("sub_log2", C.c_int32),
-                ("compact", C.c_int32), ("boundary_only", C.c_int32)]
+                ("compact", C.c_int32), ("boundary_only", C.c_int32),
+                ("centre_sampled", C.c_int32)]
 
 
 def library_path() -> str:
@@ -202,12 +204,14 @@ class Approx:
     partial counts and sums beta of the result range [alpha - beta, alpha].
     key_grid: Hilbert only; a PointIndex (or its (level, i0, j0)) whose key
     grid the runs are built on, so that PointIndex.aggregate can answer them.
+    centre_sampled: the non-conservative approximation (cells whose centre is
+    inside the polygon; misclassified points within eps/2 of the boundary).
     """
 
     def __init__(self, ring_off, vert_off, xy, eps: int, kind: str = "grid",
                  search: str = "binary", log2_leaves: int = 16, tile_log2: int = 0,
                  window=None, device: str = "cuda", stream=None, sub_log2: int = 0,
-                 boundary_only: bool = False, key_grid=None):
+                 boundary_only: bool = False, key_grid=None, centre_sampled: bool = False):
         torch = _torch()
         self._h = C.c_void_p(None)
         self.device = torch.device(device)
@@ -220,7 +224,8 @@ class Approx:
         opts = _Opts({"grid": KIND_GRID, "hilbert": KIND_HILBERT}[kind],
                      {"binary": SEARCH_BINARY, "learned": SEARCH_LEARNED}[search],
                      int(log2_leaves), int(tile_log2), *win, int(sub_log2),
-                     1 if boundary_only else 0, *_key_grid(key_grid))
+                     1 if boundary_only else 0, *_key_grid(key_grid),
+                     1 if centre_sampled else 0)
         h = C.c_void_p(None)
         with torch.cuda.device(self.device):
             rc = lib().sba_build_approx(C.byref(polys), int(eps), C.byref(opts),

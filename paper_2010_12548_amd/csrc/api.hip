@@ -149,6 +149,7 @@ extern "C" int sba_info(const sba_handle *h, sba_info_t *info)
     o.sub_log2 = h->sub_log2;
     o.compact = h->compact ? 1 : 0;
     o.boundary_only = h->boundary_only;
+    o.centre_sampled = h->centre_sampled;
     o.n_sets = h->n_sets;
     o.n_set_ids = h->n_set_ids;
     o.n_segments = h->n_segments;

@@ -157,7 +157,7 @@ __global__ __launch_bounds__(BOX_BLOCK) void k_union_box(const int4 *bbox, int32
 // misses the box in x contribute nothing inside it
 __global__ void k_edge_counts(const int4 *edges, const int32_t *epoly, const int4 *bbox,
                               int64_t n_edges, int64_t s, int64_t gi0, int64_t gj0, int64_t gi1,
-                              int64_t gj1, int64_t *nb, int64_t *nc)
+                              int64_t gj1, int centre, int64_t *nb, int64_t *nc)
 {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_edges) return;
@@ -171,7 +171,16 @@ __global__ void k_edge_counts(const int4 *edges, const int32_t *epoly, const int
     int64_t ey0 = min(E.y, E.w), ey1 = max(E.y, E.w);
     int64_t ja = max(ceildiv64(ey0, s) - 1, gj0), jb = min(floordiv64(ey1, s), gj1);
     nb[e] = jb >= ja ? jb - ja + 1 : 0;
-    int64_t ka = max(ceildiv64(ey0, s), gj0), kb = min(ceildiv64(ey1, s) - 1, gj1);
+    // row lines y = js (corners) or y = (j+1/2)s (centres) crossed under the
+    // half-open rule: ey0 <= y < ey1
+    int64_t ka, kb;
+    if (centre) {
+        ka = max(ceildiv64(2 * ey0 - s, 2 * s), gj0);
+        kb = min(ceildiv64(2 * ey1 - s, 2 * s) - 1, gj1);
+    } else {
+        ka = max(ceildiv64(ey0, s), gj0);
+        kb = min(ceildiv64(ey1, s) - 1, gj1);
+    }
     nc[e] = (E.y != E.w && kb >= ka) ? kb - ka + 1 : 0;
 }
 
@@ -230,8 +239,8 @@ __global__ void k_emit_boundary(const int4 *edges, const int32_t *epoly, int64_t
 // [gi0, gi1 + 1] (inside spans are then cut to the stored box)
 __global__ void k_emit_cross(const int4 *edges, const int32_t *epoly, int64_t n_edges,
                              const int64_t *coff, int64_t nc_total, int64_t s, int64_t gi0,
-                             int64_t gj0, int64_t gi1, int xbits, int rbits, uint64_t *evkey,
-                             uint32_t *evpay)
+                             int64_t gj0, int64_t gi1, int centre, int xbits, int rbits,
+                             uint64_t *evkey, uint32_t *evpay)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nc_total) return;
@@ -239,11 +248,25 @@ __global__ void k_emit_cross(const int4 *edges, const int32_t *epoly, int64_t n_
     int4 E = edges[e];
     int64_t x1 = E.x, y1 = E.y, x2 = E.z, y2 = E.w;
     int64_t ey0 = min(y1, y2);
+    int64_t den = y2 - y1, k;
+    if (centre) {
+        // centre line y = (j+1/2)s; with 2 xc = num / den the centre of cell i
+        // lies left of the crossing iff (2i+1) s den < num (den > 0).  The
+        // terms stay below 2^63 for coordinates under 2^30 in magnitude.
+        int64_t j = max(ceildiv64(2 * ey0 - s, 2 * s), gj0) + (t - coff[e]);
+        int64_t num = 2 * x1 * den + ((2 * j + 1) * s - 2 * y1) * (x2 - x1);
+        if (den < 0) { den = -den; num = -num; }
+        k = ceildiv64(num - s * den, 2 * s * den);
+        k = min(max(k, gi0), gi1 + 1);
+        evkey[t] = ((uint64_t)epoly[e] << (rbits + xbits)) | ((uint64_t)(j - gj0) << xbits) |
+                   (uint64_t)(k - gi0);
+        evpay[t] = EV_CROSS;
+        return;
+    }
     int64_t j = max(ceildiv64(ey0, s), gj0) + (t - coff[e]);
-    int64_t den = y2 - y1;
     int64_t num = x1 * den + (j * s - y1) * (x2 - x1);
     if (den < 0) { den = -den; num = -num; }
-    int64_t k = ceildiv64(num, den * s);
+    k = ceildiv64(num, den * s);
     k = min(max(k, gi0), gi1 + 1);
     evkey[t] = ((uint64_t)epoly[e] << (rbits + xbits)) | ((uint64_t)(j - gj0) << xbits) |
                (uint64_t)(k - gi0);
@@ -814,34 +837,50 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     RC(B.alloc(&nb, nv + 1));
     RC(B.alloc(&nc, nv + 1));
     hipLaunchKernelGGL(k_edge_counts, dim3(grid_for(nv)), dim3(256), 0, st, B.edges, B.epoly, bbox,
-                       nv, s, gi0, gj0, gi1, gj1, nb, nc);
+                       nv, s, gi0, gj0, gi1, gj1, B.centre ? 1 : 0, nb, nc);
     HIP_OK(hipGetLastError());
     RC(scan_exclusive_i64(nb, nb, nv, tot, st, &B.ws));
     RC(scan_exclusive_i64(nc, nc, nv, tot + 1, st, &B.ws));
     RC(fetch());
-    // boundary-only approximations take no row-line crossings (no interior spans)
-    const int64_t NB = hsc[8], NC = B.boundary_only ? 0 : hsc[9];
+    // boundary-only approximations take no row-line crossings (no interior
+    // spans); centre-sampled ones no boundary cells, except as the Hilbert
+    // layout's candidate keys (where the cell sets can change along the curve)
+    const bool need_b = !B.centre || B.on_boundary_events;
+    const int64_t NB = need_b ? hsc[8] : 0, NC = B.boundary_only ? 0 : hsc[9];
     if (NC % 2) return SBA_EDEVICE;
     h->n_boundary = NB;
     B.NB = NB;
-    const int64_t NE = 2 * NB + NC;
+    const int64_t NB_cov = B.centre ? 0 : NB;  // boundary intervals in the coverage
+    int64_t NE = 2 * NB + NC;
     if (NE >= ((int64_t)1 << 32)) return SBA_ELIMIT;
     RC(B.alloc(&B.evkey, NE));
     RC(B.alloc(&B.evpay, NE));
+    uint64_t *ckey = B.evkey + 2 * NB;
+    uint32_t *cpay = B.evpay + 2 * NB;
+    if (B.centre && NB) {  // crossings in arrays of their own, coverage input alone
+        RC(B.alloc(&ckey, std::max<int64_t>(NC, 1)));
+        RC(B.alloc(&cpay, std::max<int64_t>(NC, 1)));
+    }
     if (NB)
         hipLaunchKernelGGL(k_emit_boundary, dim3(grid_for(NB)), dim3(256), 0, st, B.edges, B.epoly,
                            nv, nb, NB, s, gi0, gj0, gi1, B.xbits, B.rbits, B.evkey, B.evpay);
     if (NC)
         hipLaunchKernelGGL(k_emit_cross, dim3(grid_for(NC)), dim3(256), 0, st, B.edges, B.epoly, nv,
-                           nc, NC, s, gi0, gj0, gi1, B.xbits, B.rbits, B.evkey + 2 * NB,
-                           B.evpay + 2 * NB);
+                           nc, NC, s, gi0, gj0, gi1, B.centre ? 1 : 0, B.xbits, B.rbits, ckey,
+                           cpay);
     HIP_OK(hipGetLastError());
     B.release(nb);
     B.release(nc);
 
     // the Hilbert layout needs the boundary cells before the events are sorted
     if (B.on_boundary_events) RC(B.on_boundary_events(B, h, st));
-
+    if (B.centre && NB) {
+        B.release(B.evkey);
+        B.release(B.evpay);
+        B.evkey = ckey;
+        B.evpay = cpay;
+    }
+    NE = 2 * NB_cov + NC;
     // 3: coverage.  Events by (polygon, row, x); one scan gives every
     // polygon's coverage count at every event, whose changes (toggles) are
     // the maximal covered intervals of each polygon in each row.
@@ -1196,6 +1235,8 @@ int build_handle(const sba_polygons *polys, int64_t eps, const sba_build_opts *o
     if (o.log2_leaves < 1 || o.log2_leaves > 24) return SBA_EINVAL;
     if (o.key_level < 0 || o.key_level > 21 || (o.key_level > 0 && o.kind != SBA_KIND_HILBERT))
         return SBA_EINVAL;
+    if (o.centre_sampled != 0 && o.centre_sampled != 1) return SBA_EINVAL;
+    if (o.centre_sampled && o.boundary_only) return SBA_EINVAL;
     if (o.key_level > 0 && (o.key_i0 < -((int64_t)1 << 31) || o.key_i0 >= ((int64_t)1 << 31) ||
                             o.key_j0 < -((int64_t)1 << 31) || o.key_j0 >= ((int64_t)1 << 31)))
         return SBA_EINVAL;
@@ -1214,6 +1255,8 @@ int build_handle(const sba_polygons *polys, int64_t eps, const sba_build_opts *o
     BuildState B(st);
     B.boundary_only = o.boundary_only != 0;
     h->boundary_only = o.boundary_only != 0;
+    B.centre = o.centre_sampled != 0;
+    h->centre_sampled = o.centre_sampled != 0;
     B.window = o.use_window != 0;
     B.wx0 = o.win_x0;
     B.wy0 = o.win_y0;

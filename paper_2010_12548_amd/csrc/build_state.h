@@ -27,6 +27,7 @@ struct BuildState {
     int64_t *sc = nullptr;
 
     bool boundary_only = false;  // no interior spans: B(P) only
+    bool centre = false;         // centre-sampled cells: crossings of the centre lines only
 
     // clip window in coordinates, [wx0, wx1) x [wy0, wy1)
     bool window = false;

@@ -92,6 +92,7 @@ __host__ __device__ inline int32_t code_to_ref(uint32_t c)
 struct sba_handle {
     int32_t kind, search;
     int32_t boundary_only;  // only the boundary cells B(P) are stored
+    int32_t centre_sampled; // cells whose centre is inside (non-conservative)
     int32_t n_polys;
     int64_t eps, s;
     // stored cell box

@@ -459,3 +459,80 @@ def test_city_result_range_contains_exact(sba, orc, eps):
     ac, bc, ec = ac.astype(np.int64), bc.astype(np.int64), ec.astype(np.int64)
     assert np.all(ac - bc <= ec) and np.all(ec <= ac)
     assert np.all(asum - bsum <= esum) and np.all(esum <= asum)
+
+
+# --------------------------------------------------------------- centre-sampled cells (Sec. 2.2)
+
+@pytest.mark.parametrize("kind,search", [("grid", None), ("hilbert", "binary"),
+                                         ("hilbert", "learned")])
+@pytest.mark.parametrize("seed,eps", [(0, 2), (1, 4), (2, 9), (3, 30)])
+def test_centre_sampled_cells_and_aggregates(sba, orc, kind, search, seed, eps):
+    """A centre-sampled handle stores the oracle's C(P) (cells whose centre is
+    inside) in every layout, and aggregates like the oracle."""
+    polys = star_polygons(10, 11, 20.0, 300.0, 1200, 700 + seed)
+    OC = orc.Approx(polys, eps, centre=True)
+    kw = {"kind": kind, "centre_sampled": True}
+    if search:
+        kw["search"] = search
+    A = sba.Approx.from_polygons(polys, eps, **kw)
+    assert A.info()["centre_sampled"] == 1
+    i0, j0, nw, nh = window_of(polys, OC.s)
+    want = expected_sets(OC, polys.n_polys, i0, j0, nw, nh)
+    got = gpu_sets(A, list(want.keys()))
+    bad = [k for k in want if got[k] != want[k]]
+    assert not bad, (len(bad), bad[:5])
+    rng = np.random.default_rng(seed)
+    n = 150_001
+    xy = rng.integers(-100, 1300, size=2 * n).astype(np.int32)
+    vals = rng.integers(-5000, 10000, size=n).astype(np.int64)
+    want_c, want_s = OC.aggregate(xy, vals)
+    c, s = run_agg(A, xy, vals)
+    np.testing.assert_array_equal(c, want_c)
+    np.testing.assert_array_equal(s, want_s)
+
+
+@pytest.mark.parametrize("tl,sl", [(6, 3), (8, 4), (5, 5)])
+@pytest.mark.parametrize("wide", [0, 1])
+def test_centre_sampled_grid_levels(sba, orc, tl, sl, wide):
+    polys = star_polygons(12, 9, 20.0, 400.0, 1500, 77)
+    eps = 5
+    OC = orc.Approx(polys, eps, centre=True)
+    sba.lib().sba_debug_force_wide_grid(wide)
+    try:
+        A = sba.Approx.from_polygons(polys, eps, tile_log2=tl, sub_log2=sl, centre_sampled=True)
+    finally:
+        sba.lib().sba_debug_force_wide_grid(0)
+    rng = np.random.default_rng(tl * 16 + sl)
+    n = 200_001
+    xy = rng.integers(-50, 1600, size=2 * n).astype(np.int32)
+    vals = rng.integers(100, 10000, size=n).astype(np.int64)
+    want_c, want_s = OC.aggregate(xy, vals)
+    c, s = run_agg(A, xy, vals)
+    np.testing.assert_array_equal(c, want_c)
+    np.testing.assert_array_equal(s, want_s)
+
+
+def test_centre_sampled_city_partition(sba, orc):
+    """City partition: the oracle's centre-sampled aggregates, and every point
+    whose cell centre lies in the box is counted exactly once."""
+    from gen import city_polygons
+    polys = city_polygons()
+    xy, vals = city_points(2_000_000)
+    B = CITY_BOX
+    p = xy.reshape(-1, 2).astype(np.int64)
+    for eps in (100, 1000, 10000):
+        OC = orc.Approx(polys, eps, centre=True)
+        want_c, want_s = OC.aggregate(xy, vals)
+        A = sba.Approx.from_polygons(polys, eps, centre_sampled=True)
+        c, s = run_agg(A, xy, vals)
+        np.testing.assert_array_equal(c, want_c)
+        np.testing.assert_array_equal(s, want_s)
+        sc = OC.s
+        cx, cy = (2 * (p[:, 0] // sc) + 1) * sc, (2 * (p[:, 1] // sc) + 1) * sc
+        assert int(c.sum()) == int(np.count_nonzero((cx < 2 * B) & (cy < 2 * B)))
+
+
+def test_centre_sampled_rejects_boundary_only(sba):
+    polys = star_polygons(3, 8, 50.0, 200.0, 1000, 2)
+    with pytest.raises(sba.SbaError):
+        sba.Approx.from_polygons(polys, 10, centre_sampled=True, boundary_only=True)

@@ -214,3 +214,21 @@ def test_spline_error_bound(sba, orc, eps, radix_bits, spline_err):
         got, fb = ix.lower_bounds(dev(q), search)
         np.testing.assert_array_equal(got.cpu().numpy(), want)
         assert fb == 0
+
+
+@pytest.mark.parametrize("eps", [4, 40])
+def test_centre_sampled_handle(sba, orc, eps):
+    """The point index answers a centre-sampled Hilbert handle on its key grid
+    like the oracle's centre-sampled aggregate."""
+    polys = star_polygons(12, 9, 20.0, 400.0, 1500, 303)
+    rng = np.random.default_rng(eps)
+    n = 150_001
+    xy = rng.integers(-100, 1600, size=2 * n).astype(np.int32)
+    vals = rng.integers(0, 10000, size=n).astype(np.int64)
+    want_c, want_s = orc.Approx(polys, eps, centre=True).aggregate(xy, vals)
+    ix = sba.PointIndex(dev(xy), dev(vals), eps)
+    A = sba.Approx.from_polygons(polys, eps, kind="hilbert", key_grid=ix, centre_sampled=True)
+    for search in ("binary", "learned"):
+        c, s = pindex_agg(ix, A, search)
+        np.testing.assert_array_equal(c, want_c)
+        np.testing.assert_array_equal(s, want_s)
