@@ -47,6 +47,8 @@ def lib():
     L.orc_centre_brute.restype = C.c_int
     L.orc_centre_brute.argtypes = [C.c_int32, _i32p, _i64p, _i32p, C.c_int64, C.c_int64,
                                    C.c_int64, C.c_int64, C.c_int64, _u8p]
+    L.orc_join_pairs.restype = C.c_int64
+    L.orc_join_pairs.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, _i32p, _i32p, _i64p]
     L.orc_build.restype = C.c_void_p
     L.orc_build.argtypes = [C.c_int32, _i32p, _i64p, _i32p, C.c_int64]
     L.orc_build_mode.restype = C.c_void_p
@@ -114,6 +116,20 @@ def centre_brute(polys, s: int, i0: int, j0: int, nw: int, nh: int) -> np.ndarra
     if rc:
         raise ValueError("orc_centre_brute rejected its input")
     return out.reshape(polys.n_polys, nh, nw)
+
+
+def join_pairs(a: "Approx", b: "Approx"):
+    """Polygon pairs (p of a, q of b) whose approximations share cells, with
+    the number of shared cells: (pa int32, pb int32, cells int64) in (p, q)
+    order (Sec. 4: blend of two rasterized canvases, mask of the cells that
+    hold both)."""
+    z32, z64 = np.zeros(1, np.int32), np.zeros(1, np.int64)
+    n = int(lib().orc_join_pairs(a._h, b._h, 0, z32, z32, z64))
+    if n < 0:
+        raise ValueError("the approximations have different cell sides")
+    pa, pb, cells = np.zeros(max(n, 1), np.int32), np.zeros(max(n, 1), np.int32), np.zeros(max(n, 1), np.int64)
+    lib().orc_join_pairs(a._h, b._h, n, pa, pb, cells)
+    return pa[:n], pb[:n], cells[:n]
 
 
 def hilbert_d(L: int, i: int, j: int) -> int:

@@ -785,6 +785,48 @@ int orc_invariant_all(const orc_approx *a, const int32_t *xy, int64_t n, int64_t
 }
 
 /* ------------------------------------------------------------------ */
+/* polygon-polygon join over cells (Sec. 4: blend two rasterized       */
+/* canvases, mask the cells that hold both, aggregate per pair)        */
+/* ------------------------------------------------------------------ */
+
+/* cells shared by polygon p of a and polygon q of b: per common row, the
+ * overlap of the two sorted disjoint interval lists */
+static int64_t shared_cells(const prows *x, const prows *y)
+{
+    int64_t r0 = max64(x->cj0, y->cj0), r1 = min64(x->cj1, y->cj1), n = 0;
+    if (max64(x->ci0, y->ci0) > min64(x->ci1, y->ci1)) return 0;
+    for (int64_t r = r0; r <= r1; r++) {
+        int64_t s = x->row_off[r - x->cj0], se = x->row_off[r - x->cj0 + 1];
+        int64_t t = y->row_off[r - y->cj0], te = y->row_off[r - y->cj0 + 1];
+        while (s < se && t < te) {
+            int64_t lo = max64(x->x0[s], y->x0[t]), hi = min64(x->x1[s], y->x1[t]);
+            if (hi > lo) n += hi - lo;
+            if (x->x1[s] < y->x1[t]) s++; else t++;
+        }
+    }
+    return n;
+}
+
+/* Every pair (p, q), p a polygon of a and q one of b (same cell side), whose
+ * approximations share at least one cell, with the number of shared cells,
+ * in (p, q) order.  Writes at most cap pairs; returns the number of pairs,
+ * or -1 if the cell sides differ. */
+int64_t orc_join_pairs(const orc_approx *a, const orc_approx *b, int64_t cap, int32_t *pa,
+                       int32_t *pb, int64_t *cells)
+{
+    if (a->s != b->s) return -1;
+    int64_t m = 0;
+    for (int32_t p = 0; p < a->n_polys; p++)
+        for (int32_t q = 0; q < b->n_polys; q++) {
+            int64_t n = shared_cells(&a->rows[p], &b->rows[q]);
+            if (n == 0) continue;
+            if (m < cap) { pa[m] = p; pb[m] = q; cells[m] = n; }
+            m++;
+        }
+    return m;
+}
+
+/* ------------------------------------------------------------------ */
 /* Hilbert curve (Sec. 3, dimensionality reduction)                    */
 /* ------------------------------------------------------------------ */
 

@@ -575,3 +575,97 @@ def test_centre_partition_counts_each_point_once(orc):
         assert int(cnt.sum()) == inside
         inv = C.invariant(pts)
         assert inv["far"] == 0
+
+
+# ---------------------------------------------------------------- polygon-polygon join
+#
+# Sec. 4: blending two rasterized canvases and masking the cells that hold
+# both gives the pairs of polygons whose approximations intersect, with the
+# shared cell count.  Pinned by the per-cell definition (brute membership),
+# the rectangle closed form, symmetry, the diagonal of a self-join and the
+# conservative guarantee (polygons sharing a point are always paired).
+
+def _pairs_dict(pa, pb, cells):
+    return {(int(p), int(q)): int(c) for p, q, c in zip(pa, pb, cells)}
+
+
+@pytest.mark.parametrize("s,r1,r2", [
+    (5, (0, 35, 0, 40), (20, 60, 10, 25)),      # overlapping
+    (5, (0, 35, 0, 40), (40, 60, 0, 40)),       # 5 apart: the cell rings still meet
+    (5, (0, 35, 0, 40), (45, 60, 0, 40)),       # 10 apart: one cell ring each, adjacent
+    (3, (3, 12, -9, 30), (-30, 0, 0, 3)),
+    (7, (14, 70, 7, 35), (84, 98, 35, 49))])    # corner to corner at distance 14
+def test_join_rectangles_closed_form(orc, s, r1, r2):
+    # a cell-aligned rectangle [a,b] x [c,d] covers the cells a/s-1 .. b/s and
+    # c/s-1 .. d/s; two such ranges share the product of their 1-D overlaps
+    eps = {3: 5, 5: 8, 7: 10}[s]
+    A = orc.Approx(polygons_from_rings([[np.array([[r1[0], r1[2]], [r1[1], r1[2]],
+                                                   [r1[1], r1[3]], [r1[0], r1[3]]])]]), eps)
+    B = orc.Approx(polygons_from_rings([[np.array([[r2[0], r2[2]], [r2[1], r2[2]],
+                                                   [r2[1], r2[3]], [r2[0], r2[3]]])]]), eps)
+
+    def ov(a0, a1, b0, b1):
+        return max(0, min(a1 // s, b1 // s) - max(a0 // s - 1, b0 // s - 1) + 1)
+
+    want = ov(r1[0], r1[1], r2[0], r2[1]) * ov(r1[2], r1[3], r2[2], r2[3])
+    got = _pairs_dict(*orc.join_pairs(A, B))
+    assert got == ({(0, 0): want} if want else {})
+
+
+@pytest.mark.parametrize("eps", [2, 4, 7, 13])
+def test_join_equals_definition_random_stars(orc, eps):
+    a = star_polygons(4, 9, 5.0, 60.0, 200, 4000 + eps)
+    b = star_polygons(5, 7, 5.0, 50.0, 200, 5000 + eps)
+    s = orc.cell_side(eps)
+    ia, ja, wa, ha = cell_window(a, s)
+    ib, jb, wb, hb = cell_window(b, s)
+    i0, j0 = min(ia, ib), min(ja, jb)
+    nw, nh = max(ia + wa, ib + wb) - i0, max(ja + ha, jb + hb) - j0
+    ma = orc.raster_brute(a, s, i0, j0, nw, nh) > 0
+    mb = orc.raster_brute(b, s, i0, j0, nw, nh) > 0
+    want = {}
+    for p in range(a.n_polys):
+        for q in range(b.n_polys):
+            n = int(np.count_nonzero(ma[p] & mb[q]))
+            if n:
+                want[(p, q)] = n
+    A, B = orc.Approx(a, eps), orc.Approx(b, eps)
+    assert _pairs_dict(*orc.join_pairs(A, B)) == want
+    # symmetry
+    assert _pairs_dict(*orc.join_pairs(B, A)) == {(q, p): n for (p, q), n in want.items()}
+    # centre-sampled canvases join the same way
+    mca = orc.centre_brute(a, s, i0, j0, nw, nh) > 0
+    mcb = orc.centre_brute(b, s, i0, j0, nw, nh) > 0
+    wc = {}
+    for p in range(a.n_polys):
+        for q in range(b.n_polys):
+            n = int(np.count_nonzero(mca[p] & mcb[q]))
+            if n:
+                wc[(p, q)] = n
+    got = _pairs_dict(*orc.join_pairs(orc.Approx(a, eps, centre=True),
+                                      orc.Approx(b, eps, centre=True)))
+    assert got == wc
+
+
+def test_join_self_partition_and_no_false_negatives(orc):
+    polys = voronoi_partition(20, 50000, (3, 12), seed=6, jitter_seed=7)
+    eps = 300
+    A = orc.Approx(polys, eps)
+    got = _pairs_dict(*orc.join_pairs(A, A))
+    # the diagonal is each approximation's own size
+    P, R, X0, X1 = A.intervals()
+    for p in range(polys.n_polys):
+        assert got[(p, p)] == int((X1[P == p] - X0[P == p]).sum())
+    # neighbours (a shared boundary point) are always paired; here: two
+    # polygons that hold the two ends of a short segment across their border
+    stars = star_polygons(6, 9, 100.0, 1500.0, 6000, 99)
+    S = orc.Approx(stars, 40)
+    pairs = _pairs_dict(*orc.join_pairs(S, S))
+    rng = np.random.default_rng(8)
+    pts = rng.integers(0, 6000, size=(3000, 2)).astype(np.int32)
+    for x, y in pts.tolist():
+        c, _ = S.exact(np.array([x, y], np.int32))
+        ins = np.nonzero(c)[0]
+        for p in ins:
+            for q in ins:
+                assert (int(p), int(q)) in pairs
