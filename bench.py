@@ -250,6 +250,30 @@ def pindex_bench(sba, torch, txy, tv, ro, vo, pxy, eps, res_c, res_s, scan_ms):
     return out
 
 
+def join_bench(sba, torch, a, b, eps, desc):
+    """Polygon-polygon join over cells (Sec. 4): both sets as Hilbert runs on
+    one key grid, then sba_join_pairs (synchronous) timed end to end."""
+    g = sba.key_grid_for(eps, a, b)
+    t0 = time.perf_counter()
+    A = sba.Approx.from_polygons(a, eps, kind="hilbert", key_grid=g)
+    B = sba.Approx.from_polygons(b, eps, kind="hilbert", key_grid=g)
+    t_build = 1000.0 * (time.perf_counter() - t0)
+    sba.join_pairs(A, B)
+    ts = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pa, pb, cells = sba.join_pairs(A, B)
+        ts.append(1000.0 * (time.perf_counter() - t0))
+    out = {"what": desc, "eps_units": eps, "runs": [A.info()["n_runs"], B.info()["n_runs"]],
+           "builds_ms": round(t_build, 3), "join_ms_median": round(float(np.median(ts)), 3),
+           "pairs": int(pa.numel()), "shared_cells": int(cells.sum().item())}
+    A.close()
+    B.close()
+    log(f"[bench] polygon join: {json.dumps(out)}")
+    return out
+
+
 def workload(args):
     from gen import city_points, city_polygons, quadtree_polygons, tiny_workload
     if args.workload == "tiny":
@@ -520,6 +544,14 @@ def main():
             "kernel": ch.probe_kernel(True)}
         ch.close()
         log(f"[bench] centre-sampled: {json.dumps(extra['centre_sampled'])}")
+
+    if args.workload == "city":
+        extra["polygon_join"] = join_bench(sba, torch, polys, polys, eps,
+                                           "city partition with itself")
+    if args.workload == "quadtree":
+        from gen import city_polygons
+        extra["polygon_join"] = join_bench(sba, torch, polys, city_polygons(), eps,
+                                           "40,000-cell partition with the 260-cell partition")
 
     if args.workload in ("city", "quadtree") and not args.no_pindex:
         extra["point_index"] = pindex_bench(sba, torch, txy, tv, ro, vo, pxy, eps, res_c, res_s,

@@ -268,6 +268,27 @@ const char *sba_probe_kernel(const sba_handle *h, int with_values);
  * using the handle is still queued (synchronise its streams first). */
 void sba_free(sba_handle *h);
 
+/*
+ * Polygon-polygon join over cells (Sec. 4: blend two rasterized canvases,
+ * mask the cells that hold a polygon of each): every pair (p, q), p a
+ * polygon of a and q one of b, whose approximations share at least one cell,
+ * with the number of shared cells (x s^2: an estimate of the intersection
+ * area; conservative approximations pair every two polygons that meet).
+ *   a, b     Hilbert handles with the same cell side and key grid (build
+ *            both with the same eps and opts.key_level / key_i0 / key_j0),
+ *            else SBA_EINVAL.  Either may be boundary-only or centre-sampled.
+ *   cap      capacity of the outputs, >= 0.
+ *   pa, pb   [cap] int32 DEVICE arrays: polygon of a, polygon of b.
+ *   cells    [cap] int64 DEVICE array: shared cells.
+ *   n_pairs  host; receives the number of pairs.  Pairs are written in
+ *            (p, q) order; if there are more than cap, only the first cap.
+ * Synchronous: returns after the outputs are written (it reads sizes back).
+ * Errors: SBA_EINVAL, SBA_ENOMEM, SBA_EDEVICE, SBA_ELIMIT (2^32 or more
+ * (cell interval, pair) incidences).
+ */
+int sba_join_pairs(const sba_handle *a, const sba_handle *b, int64_t cap, int32_t *pa,
+                   int32_t *pb, int64_t *cells, int64_t *n_pairs, void *stream);
+
 /* ------------------------------------------------------------ point index
  *
  * Point-side pre-aggregation (Sec. 3, point indexing): the points are

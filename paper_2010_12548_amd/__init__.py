@@ -14,7 +14,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Approx", "PointIndex", "SbaError", "lib", "library_path", "celldiv", "hilbert", "hilbert_cell",
+__all__ = ["Approx", "PointIndex", "SbaError", "join_pairs", "key_grid_for", "lib", "library_path", "celldiv", "hilbert", "hilbert_cell",
            "aggregate_batch", "bucket_points", "Task",
            "KIND_GRID", "KIND_HILBERT", "SEARCH_BINARY", "SEARCH_LEARNED"]
 
@@ -142,6 +142,8 @@ def lib():
     L.sba_pindex_aggregate.argtypes = [vp, vp, i32, vp, vp, vp]
     L.sba_pindex_free.restype = None
     L.sba_pindex_free.argtypes = [vp]
+    L.sba_join_pairs.restype = C.c_int
+    L.sba_join_pairs.argtypes = [vp, vp, i64, vp, vp, vp, C.POINTER(i64), vp]
     L.sba_debug_pindex_lb.restype = C.c_int
     L.sba_debug_pindex_lb.argtypes = [vp, vp, i64, i32, vp, C.POINTER(i64), vp]
     _lib = L
@@ -339,6 +341,45 @@ class Approx:
                 k = -2 - r
                 out.append(tuple(int(v) for v in ids[off[k]:off[k + 1]]))
         return out
+
+
+def key_grid_for(eps: int, *polysets):
+    """(level, i0, j0) of a Hilbert key grid covering the cell boxes of every
+    given polygon set (objects with an xy array) at distance bound eps, so
+    that handles built on it can be joined (join_pairs).  Host arithmetic on
+    the vertex extremes only."""
+    import math
+    s = math.isqrt(int(eps) * int(eps) // 2)
+    xs = np.concatenate([np.asarray(p.xy, np.int64).reshape(-1, 2) for p in polysets])
+    i0 = -(-int(xs[:, 0].min()) // s) - 1
+    j0 = -(-int(xs[:, 1].min()) // s) - 1
+    i1 = int(xs[:, 0].max()) // s
+    j1 = int(xs[:, 1].max()) // s
+    side = max(i1 - i0 + 1, j1 - j0 + 1)
+    level = max(1, (side - 1).bit_length())
+    return (level, i0, j0)
+
+
+def join_pairs(a: "Approx", b: "Approx", stream=None):
+    """Polygon pairs (p of a, q of b) whose approximations share cells, with
+    the shared cell counts (``sba_join_pairs``): (pa, pb, cells) int32/int32/
+    int64 GPU tensors in (p, q) order.  a and b: Hilbert handles on one key
+    grid with the same eps."""
+    torch = _torch()
+    dev = a.device
+    cap = max(1024, a.info()["n_runs"] + b.info()["n_runs"])
+    n = C.c_int64(0)
+    while True:
+        pa = torch.empty(cap, dtype=torch.int32, device=dev)
+        pb = torch.empty(cap, dtype=torch.int32, device=dev)
+        cells = torch.empty(cap, dtype=torch.int64, device=dev)
+        _check(lib().sba_join_pairs(a._h, b._h, cap, pa.data_ptr(), pb.data_ptr(),
+                                    cells.data_ptr(), C.byref(n), _stream_ptr(stream)),
+               "sba_join_pairs")
+        if n.value <= cap:
+            k = n.value
+            return pa[:k], pb[:k], cells[:k]
+        cap = n.value
 
 
 def _key_grid(g):
