@@ -495,8 +495,8 @@ def main():
         # result range [alpha - beta, alpha] (Sec. 6): beta from a
         # boundary-only approximation over the same points
         t0 = time.perf_counter()
-        bh = sba.Approx(ro, vo, pxy, eps, boundary_only=True, tile_log2=args.tile_log2,
-                        sub_log2=args.sub_log2)
+        bh = sba.Approx(ro, vo, pxy, eps, boundary_only=True, tile_log2=info["tile_log2"],
+                        sub_log2=info["sub_log2"])
         t_bb = 1000.0 * (time.perf_counter() - t0)
         bc = torch.empty_like(counts)
         bs = torch.empty_like(sums)
@@ -508,13 +508,30 @@ def main():
             bh.aggregate(txy, tv, bc, bs)
         e1.record()
         torch.cuda.synchronize()
+        beta_probe = e0.elapsed_time(e1) / 10
         beta = bc.cpu().numpy().astype(np.float64)
         alpha = res_c.astype(np.float64)
+        # alpha and beta in one pass over the points
+        a_full = sba.Approx(ro, vo, pxy, eps, **kw)
+        rr = sba.aggregate_range(a_full, bh, txy, tv)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(10):
+            rr = sba.aggregate_range(a_full, bh, txy, tv)
+        e1.record()
+        torch.cuda.synchronize()
+        one_pass = e0.elapsed_time(e1) / 10
+        same = bool(np.array_equal(rr[0].cpu().numpy().astype(np.uint64), res_c)
+                    and np.array_equal(rr[2].cpu().numpy(), bc.cpu().numpy()))
         extra["result_range"] = {
-            "beta_build_ms": round(t_bb, 3), "beta_probe_ms": round(e0.elapsed_time(e1) / 10, 4),
+            "beta_build_ms": round(t_bb, 3), "beta_probe_ms": round(beta_probe, 4),
+            "alpha_plus_beta_one_pass_ms": round(one_pass, 4),
+            "one_pass_kernel": sba.range_kernel(a_full, bh),
+            "one_pass_same_as_two": same,
             "beta_over_alpha_total": float(beta.sum() / max(alpha.sum(), 1.0)),
             "beta_over_alpha_median_polygon": float(np.median(beta / np.maximum(alpha, 1.0))),
             "kernel": bh.probe_kernel(True)}
+        a_full.close()
         bh.close()
         log(f"[bench] result range: {json.dumps(extra['result_range'])}")
 

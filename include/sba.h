@@ -182,6 +182,29 @@ int sba_aggregate_search(const int32_t *xy, const int64_t *values, int64_t n,
                          int64_t *sums, void *stream);
 
 /*
+ * Result range in one pass (Sec. 6): alpha (COUNT/SUM over A(P)) and the
+ * boundary partial beta (over B(P)) of every polygon, so that the exact
+ * answer lies in [alpha - beta, alpha] (sums: for non-negative values).
+ *   h        the full approximation; hb the boundary-only one
+ *            (opts.boundary_only) of the same polygons and eps, else
+ *            SBA_EINVAL.
+ *   counts, sums    alpha, as sba_aggregate.
+ *   bcounts, bsums  beta, as sba_aggregate (sums and bsums both or neither).
+ * When both are grid handles in the 16-bit format on the same tiles (build
+ * hb with h's tile_log2 and sub_log2, see sba_info) and both directories fit
+ * in LDS together, one kernel reads the points once and looks each cell up
+ * in both; otherwise two probes run one after the other.  Asynchronous.
+ */
+int sba_aggregate_range(const int32_t *xy, const int64_t *values, int64_t n,
+                        const sba_handle *h, const sba_handle *hb, uint64_t *counts,
+                        int64_t *sums, uint64_t *bcounts, int64_t *bsums, void *stream);
+
+/* Name of the one-pass kernel sba_aggregate_range launches for (h, hb), as
+ * profilers list it; "" when the call takes two passes.  Per-thread static
+ * storage. */
+const char *sba_range_kernel(const sba_handle *h, const sba_handle *hb, int with_values);
+
+/*
  * One aggregation task of a batch (serving: viewport queries).
  *   xy, values   the point table (as for sba_aggregate); the task reads the
  *                points with index in [lo, hi).  values may be NULL (COUNT).

@@ -14,7 +14,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Approx", "PointIndex", "SbaError", "join_pairs", "key_grid_for", "lib", "library_path", "celldiv", "hilbert", "hilbert_cell",
+__all__ = ["Approx", "PointIndex", "SbaError", "join_pairs", "key_grid_for", "aggregate_range", "lib", "library_path", "celldiv", "hilbert", "hilbert_cell",
            "aggregate_batch", "bucket_points", "Task",
            "KIND_GRID", "KIND_HILBERT", "SEARCH_BINARY", "SEARCH_LEARNED"]
 
@@ -142,6 +142,10 @@ def lib():
     L.sba_pindex_aggregate.argtypes = [vp, vp, i32, vp, vp, vp]
     L.sba_pindex_free.restype = None
     L.sba_pindex_free.argtypes = [vp]
+    L.sba_aggregate_range.restype = C.c_int
+    L.sba_aggregate_range.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
+    L.sba_range_kernel.restype = C.c_char_p
+    L.sba_range_kernel.argtypes = [vp, vp, C.c_int]
     L.sba_join_pairs.restype = C.c_int
     L.sba_join_pairs.argtypes = [vp, vp, i64, vp, vp, vp, C.POINTER(i64), vp]
     L.sba_debug_pindex_lb.restype = C.c_int
@@ -358,6 +362,34 @@ def key_grid_for(eps: int, *polysets):
     side = max(i1 - i0 + 1, j1 - j0 + 1)
     level = max(1, (side - 1).bit_length())
     return (level, i0, j0)
+
+
+def aggregate_range(alpha: "Approx", beta: "Approx", xy, values=None, stream=None):
+    """Result range in one pass (``sba_aggregate_range``): (counts, sums,
+    bcounts, bsums) as int64 GPU tensors, alpha from the full handle and beta
+    from the boundary-only one (sums None for COUNT).  Build beta with
+    alpha.info()'s tile_log2 and sub_log2 for the one-kernel path."""
+    torch = _torch()
+    if xy.dtype != torch.int32 or xy.device.type != "cuda" or not xy.is_contiguous():
+        raise ValueError("xy must be a contiguous int32 GPU tensor")
+    n = xy.numel() // 2
+    np_ = max(alpha.n_polys, 1)
+    mk = lambda: torch.empty(np_, dtype=torch.int64, device=xy.device)  # noqa: E731
+    counts, bcounts = mk(), mk()
+    sums, bsums = (mk(), mk()) if values is not None else (None, None)
+    _check(lib().sba_aggregate_range(xy.data_ptr(), values.data_ptr() if values is not None else None,
+                                     n, alpha._h, beta._h, counts.data_ptr(),
+                                     sums.data_ptr() if sums is not None else None,
+                                     bcounts.data_ptr(),
+                                     bsums.data_ptr() if bsums is not None else None,
+                                     _stream_ptr(stream)), "sba_aggregate_range")
+    k = alpha.n_polys
+    return (counts[:k], sums[:k] if sums is not None else None, bcounts[:k],
+            bsums[:k] if bsums is not None else None)
+
+
+def range_kernel(alpha: "Approx", beta: "Approx", with_values: bool = True) -> str:
+    return lib().sba_range_kernel(alpha._h, beta._h, 1 if with_values else 0).decode()
 
 
 def join_pairs(a: "Approx", b: "Approx", stream=None):

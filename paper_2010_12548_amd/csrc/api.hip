@@ -58,6 +58,18 @@ extern "C" int sba_aggregate(const int32_t *xy, const int64_t *values, int64_t n
     return probe_launch(xy, values, n, h, h->search, counts, sums, (hipStream_t)stream);
 }
 
+extern "C" int sba_aggregate_range(const int32_t *xy, const int64_t *values, int64_t n,
+                                   const sba_handle *h, const sba_handle *hb, uint64_t *counts,
+                                   int64_t *sums, uint64_t *bcounts, int64_t *bsums, void *stream)
+{
+    RC(check_probe_args(xy, values, n, h, counts));
+    RC(check_probe_args(xy, values, n, hb, bcounts));
+    if (h->n_polys != hb->n_polys || h->boundary_only || !hb->boundary_only || h->s != hb->s)
+        return SBA_EINVAL;
+    if ((sums == nullptr) != (bsums == nullptr)) return SBA_EINVAL;
+    return range_launch(xy, values, n, h, hb, counts, sums, bcounts, bsums, (hipStream_t)stream);
+}
+
 extern "C" int sba_aggregate_batch(const sba_task *tasks, int32_t n_tasks, void *stream)
 {
     if (n_tasks < 0 || (n_tasks > 0 && !tasks)) return SBA_EINVAL;

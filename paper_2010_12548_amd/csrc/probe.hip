@@ -1057,6 +1057,265 @@ static int launch_grid16(const int32_t *xy, const int64_t *values, int64_t n, co
     return hipGetLastError() != hipSuccess ? SBA_EDEVICE : 0;
 }
 
+// ---------------------------------------------------------------- result range in one pass
+//
+// The full approximation A(P) and the boundary-only B(P) of the same
+// polygons, stored on the same tiles, probed together (Sec. 6: alpha and the
+// boundary partial beta in one pass over the points): each point's cell is
+// computed once and looked up in both directories (both staged in LDS), and
+// each handle has its own LDS bins (polygons, then sets, expanded once per
+// workgroup).
+
+template <bool VALS>
+__device__ __forceinline__ void expand_set_bins(uint32_t *cnt, unsigned long long *sum,
+                                                uint32_t np, const Agg &A, int block)
+{
+    for (uint32_t k = threadIdx.x; k < A.n_sets; k += block) {
+        uint32_t c = cnt[np + k];
+        if (c == 0) continue;
+        unsigned long long sv = VALS ? sum[np + k] : 0ull;
+        for (int64_t t = A.set_off[k], e = A.set_off[k + 1]; t < e; t++) {
+            uint32_t p = (uint32_t)A.set_ids[t];
+            if (p >= np) continue;
+            atomicAdd(&cnt[p], c);
+            if (VALS) atomicAdd(&sum[p], sv);
+        }
+    }
+}
+
+template <bool VALS, bool SUB, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_probe_range16(
+    const int4 *__restrict__ xy4, const longlong2 *__restrict__ v2, const int32_t *__restrict__ xy,
+    const int64_t *__restrict__ vals, int64_t n, Grid16 ga, Grid16 gb, Agg A, Agg B,
+    uint64_t *__restrict__ counts, int64_t *__restrict__ sums, uint64_t *__restrict__ bcounts,
+    int64_t *__restrict__ bsums)
+{
+    // LDS: directory A, directory B (each nt16 u16, a multiple of 8), sums A,
+    // sums B (u64), counts A, counts B (u32)
+    extern __shared__ unsigned long long smem[];
+    const uint32_t np = ga.np;
+    const uint32_t nba = np + A.n_sets, nbb = np + B.n_sets;
+    uint16_t *dira = (uint16_t *)smem, *dirb = dira + ga.nt16;
+    Lds16 La, Lb;
+    La.dir = dira;
+    Lb.dir = dirb;
+    La.sum = smem + (ga.nt16 + gb.nt16) / 4;
+    Lb.sum = La.sum + nba;
+    La.cnt = (uint32_t *)(Lb.sum + nbb);
+    Lb.cnt = La.cnt + nba;
+    La.soff = La.sids = Lb.soff = Lb.sids = nullptr;
+    {
+        const uint4 *src = (const uint4 *)ga.dir16;
+        uint4 *dst = (uint4 *)dira;
+        for (uint32_t q = threadIdx.x; q < ga.nt16 / 8; q += BLOCK) dst[q] = src[q];
+        src = (const uint4 *)gb.dir16;
+        dst = (uint4 *)dirb;
+        for (uint32_t q = threadIdx.x; q < gb.nt16 / 8; q += BLOCK) dst[q] = src[q];
+        for (uint32_t p = threadIdx.x; p < nba; p += BLOCK) {
+            La.cnt[p] = 0;
+            La.sum[p] = 0;
+        }
+        for (uint32_t p = threadIdx.x; p < nbb; p += BLOCK) {
+            Lb.cnt[p] = 0;
+            Lb.sum[p] = 0;
+        }
+    }
+    __syncthreads();
+    const int qs = ga.tl - ga.sl;
+    const int fl = SUB ? ga.sl : ga.tl;
+    const uint32_t m = (1u << fl) - 1u, mq = (1u << qs) - 1u;
+    const int64_t npairs = n >> 1;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    const int64_t tlast = npairs - 1;
+    const uint32_t ox = (uint32_t)ga.ox, oy = (uint32_t)ga.oy;
+    for (int64_t t0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t0 < npairs;
+         t0 += stride * PROBE_UNROLL) {
+        v4i_t q[PROBE_UNROLL];
+        v2l_t vv[PROBE_UNROLL];
+        bool in[PROBE_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; u++) {
+            int64_t t = t0 + (int64_t)u * stride;
+            in[u] = t < npairs;
+            int64_t tc = in[u] ? t : tlast;
+            q[u] = __builtin_nontemporal_load((const v4i_t *)(xy4 + tc));
+            vv[u] = VALS ? __builtin_nontemporal_load((const v2l_t *)(v2 + tc)) : v2l_t{0, 0};
+        }
+        uint32_t ea[2 * PROBE_UNROLL], eb[2 * PROBE_UNROLL], lo[2 * PROBE_UNROLL],
+            sq[2 * PROBE_UNROLL];
+#pragma unroll
+        for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
+            int32_t x = (k & 1) ? q[k >> 1].z : q[k >> 1].x;
+            int32_t y = (k & 1) ? q[k >> 1].w : q[k >> 1].y;
+            uint32_t dx = (uint32_t)x - ox, dy = (uint32_t)y - oy;
+            bool ok = in[k >> 1] && dx < ga.extx && dy < ga.exty;
+            uint32_t i = __umulhi((ok ? dx : 0u) << ga.pre, ga.mag) >> ga.post;
+            uint32_t j = __umulhi((ok ? dy : 0u) << ga.pre, ga.mag) >> ga.post;
+            const uint32_t te = (j >> ga.tl) * ga.tw + (i >> ga.tl);
+            ea[k] = ok ? dira[te] : 0u;
+            eb[k] = ok ? dirb[te] : 0u;
+            lo[k] = ((j & m) << fl) | (i & m);
+            if (SUB) sq[k] = (((j >> ga.sl) & mq) << qs) | ((i >> ga.sl) & mq);
+        }
+        // both handles, the same three levels as the single probe
+        uint32_t fa[2 * PROBE_UNROLL], fbk[2 * PROBE_UNROLL], va[2 * PROBE_UNROLL],
+            vb[2 * PROBE_UNROLL];
+#pragma unroll
+        for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
+            bool ma = (ea[k] & 0x8000u) != 0, mb = (eb[k] & 0x8000u) != 0;
+            fa[k] = ma ? (ea[k] & 0x7fffu) : ~0u;
+            va[k] = ma ? 0u : ea[k];
+            fbk[k] = mb ? (eb[k] & 0x7fffu) : ~0u;
+            vb[k] = mb ? 0u : eb[k];
+        }
+        if (SUB) {
+            uint32_t sa[2 * PROBE_UNROLL], sb[2 * PROBE_UNROLL];
+#pragma unroll
+            for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
+                sa[k] = ga.sub[fa[k] != ~0u ? ((uint64_t)fa[k] << (2 * qs)) + sq[k] : 0];
+                sb[k] = gb.sub[fbk[k] != ~0u ? ((uint64_t)fbk[k] << (2 * qs)) + sq[k] : 0];
+            }
+#pragma unroll
+            for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
+                if (fa[k] != ~0u) {
+                    bool mx = (sa[k] & TILE_MIXED) != 0;
+                    va[k] = mx ? 0u : sa[k];
+                    fa[k] = mx ? (sa[k] & ~TILE_MIXED) : ~0u;
+                }
+                if (fbk[k] != ~0u) {
+                    bool mx = (sb[k] & TILE_MIXED) != 0;
+                    vb[k] = mx ? 0u : sb[k];
+                    fbk[k] = mx ? (sb[k] & ~TILE_MIXED) : ~0u;
+                }
+            }
+        }
+        uint32_t ca[2 * PROBE_UNROLL], cb[2 * PROBE_UNROLL];
+#pragma unroll
+        for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
+            ca[k] = ga.blocks16[fa[k] != ~0u ? ((uint64_t)fa[k] << (2 * fl)) + lo[k] : 0];
+            cb[k] = gb.blocks16[fbk[k] != ~0u ? ((uint64_t)fbk[k] << (2 * fl)) + lo[k] : 0];
+        }
+#pragma unroll
+        for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
+            const int64_t v = (k & 1) ? vv[k >> 1].y : vv[k >> 1].x;
+            add_short<VALS, SETS_BINS>(fa[k] != ~0u ? ca[k] : va[k], v, A, np, La);
+            add_short<VALS, SETS_BINS>(fbk[k] != ~0u ? cb[k] : vb[k], v, B, np, Lb);
+        }
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        int64_t k = n - 1;
+        const int64_t v = VALS ? vals[k] : 0;
+        add_short<VALS, SETS_BINS>(grid16_code<SUB>(ga, dira, xy[2 * k], xy[2 * k + 1]), v, A, np,
+                                   La);
+        add_short<VALS, SETS_BINS>(grid16_code<SUB>(gb, dirb, xy[2 * k], xy[2 * k + 1]), v, B, np,
+                                   Lb);
+    }
+    __syncthreads();
+    expand_set_bins<VALS>(La.cnt, La.sum, np, A, BLOCK);
+    expand_set_bins<VALS>(Lb.cnt, Lb.sum, np, B, BLOCK);
+    __syncthreads();
+    flush_bins<VALS>(La.cnt, La.sum, np, BLOCK, counts, sums);
+    flush_bins<VALS>(Lb.cnt, Lb.sum, np, BLOCK, bcounts, bsums);
+}
+
+static Grid16 grid16_of(const sba_handle *h)
+{
+    Grid16 g{};
+    g.ox = h->gi0 * h->s;
+    g.oy = h->gj0 * h->s;
+    g.extx = (uint32_t)(h->gw * h->s);
+    g.exty = (uint32_t)(h->gh * h->s);
+    g.mag = h->mag;
+    g.shift = h->shift;
+    g.pre = h->shift >= 32 ? 0u : 1u;
+    g.post = h->shift >= 32 ? (uint32_t)(h->shift - 32) : 0u;
+    g.tl = h->tile_log2;
+    g.sl = h->sub_log2;
+    g.tw = (uint32_t)h->tw;
+    g.nt16 = (uint32_t)(((h->tw * h->th) + 7) & ~(int64_t)7);
+    g.dir16 = h->dir16;
+    g.sub = h->sub;
+    g.blocks16 = h->blocks16;
+    g.np = (uint32_t)h->n_polys;
+    g.sets = SETS_BINS;
+    g.n_ids = (uint32_t)h->n_set_ids;
+    return g;
+}
+
+// LDS bytes of the one-pass range probe, or 0 when the two handles cannot
+// share it (different grids, 32-bit format, too large for LDS)
+static size_t range_lds(const sba_handle *h, const sba_handle *hb)
+{
+    if (h->kind != SBA_KIND_GRID || hb->kind != SBA_KIND_GRID || !h->compact || !hb->compact)
+        return 0;
+    if (h->s != hb->s || h->gi0 != hb->gi0 || h->gj0 != hb->gj0 || h->gw != hb->gw ||
+        h->gh != hb->gh || h->tile_log2 != hb->tile_log2 || h->sub_log2 != hb->sub_log2 ||
+        h->n_polys != hb->n_polys || h->gw == 0)
+        return 0;
+    const size_t lds = grid16_dir_lds(h) + grid16_dir_lds(hb) +
+                       ((size_t)2 * h->n_polys + h->n_sets + hb->n_sets) * 12;
+    return lds <= GRID16_LDS_MAX ? lds : 0;
+}
+
+typedef void (*range16_fn)(const int4 *, const longlong2 *, const int32_t *, const int64_t *,
+                           int64_t, Grid16, Grid16, Agg, Agg, uint64_t *, int64_t *, uint64_t *,
+                           int64_t *);
+
+template <int BLOCK>
+static range16_fn range16_pick(bool vals, bool sub)
+{
+    if (vals) return sub ? k_probe_range16<true, true, BLOCK> : k_probe_range16<true, false, BLOCK>;
+    return sub ? k_probe_range16<false, true, BLOCK> : k_probe_range16<false, false, BLOCK>;
+}
+
+int range_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
+                 const sba_handle *hb, uint64_t *counts, int64_t *sums, uint64_t *bcounts,
+                 int64_t *bsums, hipStream_t st)
+{
+    const size_t lds = n > 0 && h->n_polys > 0 ? range_lds(h, hb) : 0;
+    if (lds == 0) {  // two passes
+        RC(probe_launch(xy, values, n, h, h->search, counts, sums, st));
+        return probe_launch(xy, values, n, hb, hb->search, bcounts, bsums, st);
+    }
+    const Grid16 ga = grid16_of(h), gb = grid16_of(hb);
+    Agg A{h->set_off, h->set_ids, (uint32_t)h->n_polys, (uint32_t)h->n_sets};
+    Agg B{hb->set_off, hb->set_ids, (uint32_t)hb->n_polys, (uint32_t)hb->n_sets};
+    const int32_t np = h->n_polys;
+    const bool vals = values != nullptr && sums != nullptr && bsums != nullptr;
+    const bool sub = h->sub_log2 < h->tile_log2;
+    int block = 0, per_cu = 0;
+    grid16_shape(lds, &block, &per_cu);
+    const int64_t npairs = n >> 1;
+    int64_t nb = std::min<int64_t>((npairs + block - 1) / block, (int64_t)cu_count() * per_cu);
+    if (nb < 1) nb = 1;
+    range16_fn kern = block == 512 ? range16_pick<512>(vals, sub) : range16_pick<1024>(vals, sub);
+    (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_zero_out, dim3(grid_for(np)), dim3(256), 0, st, counts,
+                       vals ? sums : nullptr, np);
+    hipLaunchKernelGGL(k_zero_out, dim3(grid_for(np)), dim3(256), 0, st, bcounts,
+                       vals ? bsums : nullptr, np);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(block), lds, st, (const int4 *)xy,
+                       (const longlong2 *)values, xy, values, n, ga, gb, A, B, counts, sums,
+                       bcounts, bsums);
+    return hipGetLastError() != hipSuccess ? SBA_EDEVICE : 0;
+}
+
+// Name of the kernel a range call launches ("" when it takes two passes).
+extern "C" const char *sba_range_kernel(const sba_handle *h, const sba_handle *hb, int with_values)
+{
+    static thread_local char buf[96];
+    if (!h || !hb || h->n_polys == 0) return "";
+    const size_t lds = range_lds(h, hb);
+    if (lds == 0) return "";
+    int block = 0, per_cu = 0;
+    grid16_shape(lds, &block, &per_cu);
+    snprintf(buf, sizeof(buf), "k_probe_range16<%s, %s, %d>", with_values ? "true" : "false",
+             h->sub_log2 < h->tile_log2 ? "true" : "false", block);
+    return buf;
+}
+
 int probe_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
                  int32_t search, uint64_t *counts, int64_t *sums, hipStream_t st)
 {

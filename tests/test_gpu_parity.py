@@ -536,3 +536,66 @@ def test_centre_sampled_rejects_boundary_only(sba):
     polys = star_polygons(3, 8, 50.0, 200.0, 1000, 2)
     with pytest.raises(sba.SbaError):
         sba.Approx.from_polygons(polys, 10, centre_sampled=True, boundary_only=True)
+
+
+def _range(sba, A, Bh, xy, vals):
+    c, s, bc, bs = sba.aggregate_range(A, Bh, dev(xy), dev(vals) if vals is not None else None)
+    torch.cuda.synchronize()
+    f = lambda t: t.cpu().numpy() if t is not None else None  # noqa: E731
+    return f(c).astype(np.uint64), f(s), f(bc).astype(np.uint64), f(bs)
+
+
+@pytest.mark.parametrize("eps", [100, 1000, 10000])
+def test_result_range_one_pass_city(sba, orc, eps):
+    """alpha and beta from one kernel over the points equal the oracle's full
+    and boundary-only aggregates."""
+    from gen import city_polygons
+    polys = city_polygons()
+    xy, vals = city_points(1_000_001)
+    A = sba.Approx.from_polygons(polys, eps)
+    inf = A.info()
+    Bh = sba.Approx.from_polygons(polys, eps, boundary_only=True, tile_log2=inf["tile_log2"],
+                                  sub_log2=inf["sub_log2"])
+    if eps >= 1000:
+        assert sba.range_kernel(A, Bh).startswith("k_probe_range16")
+    wa_c, wa_s = orc.Approx(polys, eps).aggregate(xy, vals)
+    wb_c, wb_s = orc.Approx(polys, eps, boundary_only=True).aggregate(xy, vals)
+    c, s, bc, bs = _range(sba, A, Bh, xy, vals)
+    np.testing.assert_array_equal(c, wa_c)
+    np.testing.assert_array_equal(s, wa_s)
+    np.testing.assert_array_equal(bc, wb_c)
+    np.testing.assert_array_equal(bs, wb_s)
+    c, s, bc, bs = _range(sba, A, Bh, xy, None)
+    assert s is None and bs is None
+    np.testing.assert_array_equal(c, wa_c)
+    np.testing.assert_array_equal(bc, wb_c)
+
+
+@pytest.mark.parametrize("tl,sl", [(6, 3), (5, 5), (8, 4)])
+def test_result_range_one_pass_stars(sba, orc, tl, sl):
+    polys = star_polygons(12, 9, 20.0, 400.0, 1500, 88)
+    eps = 5
+    A = sba.Approx.from_polygons(polys, eps, tile_log2=tl, sub_log2=sl)
+    Bh = sba.Approx.from_polygons(polys, eps, boundary_only=True, tile_log2=tl, sub_log2=sl)
+    assert sba.range_kernel(A, Bh) != ""
+    rng = np.random.default_rng(tl)
+    n = 200_001
+    xy = rng.integers(-50, 1600, size=2 * n).astype(np.int32)
+    vals = rng.integers(0, 10000, size=n).astype(np.int64)
+    wa = orc.Approx(polys, eps).aggregate(xy, vals)
+    wb = orc.Approx(polys, eps, boundary_only=True).aggregate(xy, vals)
+    c, s, bc, bs = _range(sba, A, Bh, xy, vals)
+    np.testing.assert_array_equal(c, wa[0])
+    np.testing.assert_array_equal(s, wa[1])
+    np.testing.assert_array_equal(bc, wb[0])
+    np.testing.assert_array_equal(bs, wb[1])
+    # different tiles: two passes, same answer
+    B2 = sba.Approx.from_polygons(polys, eps, boundary_only=True, tile_log2=4, sub_log2=4)
+    if (tl, sl) != (4, 4):
+        assert sba.range_kernel(A, B2) == ""
+    c, s, bc, bs = _range(sba, A, B2, xy, vals)
+    np.testing.assert_array_equal(c, wa[0])
+    np.testing.assert_array_equal(bc, wb[0])
+    np.testing.assert_array_equal(bs, wb[1])
+    with pytest.raises(sba.SbaError):       # beta must be the boundary-only handle
+        _range(sba, A, A, xy, vals)
