@@ -445,6 +445,7 @@ def main():
         for v in out.values():
             v.pop("_res")
         ai = a.info()
+        fb, mm = a.learned_fallbacks(txy)
         # the same probes over the points in Hilbert order of their cells (a
         # resident layout a serving system would keep): lookups of neighbouring
         # points share cache lines; results must not change
@@ -486,6 +487,7 @@ def main():
         extra["hilbert_sorted_points"] = srt
         extra["learned_vs_binary"] = {**out, "identical": bool(same),
                                       "speedup": out["binary"]["probe_ms"] / out["learned"]["probe_ms"],
+                                      "fallbacks": fb, "learned_ne_binary": mm,
                                       "n_runs": ai["n_runs"], "max_leaf_err": ai["max_leaf_err"],
                                       "mean_leaf_err": ai["mean_leaf_err"],
                                       "leaves": 1 << ai["log2_leaves"]}

@@ -42,6 +42,16 @@ int sba_debug_grid16_sets(int mode);
  * (comparison runs); 0: default.  Process-wide, read at build time. */
 int sba_debug_force_wide_grid(int on);
 
+/* The learned run search of a Hilbert handle (built with the learned
+ * index) over the cells of n points (DEVICE xy, x,y interleaved): the host
+ * *fallbacks receives how many searches failed their bracket check and took
+ * the full binary search (an exact leaf error bound makes that 0), and
+ * *mismatches how many answers differ from the binary search's (must be 0).
+ * Points outside the key grid are skipped.  Synchronous.  Test support. */
+struct sba_handle;
+int sba_debug_learned_fallbacks(const struct sba_handle *h, const int32_t *xy, int64_t n,
+                                int64_t *fallbacks, int64_t *mismatches, void *stream);
+
 /* Lower bounds in a point index: out[k] = number of indexed points whose cell
  * key is below v[k] (0 <= v[k] <= 4^L), by binary search (search 0) or the
  * RadixSpline (search 1).  v and out are DEVICE arrays of n entries; the host

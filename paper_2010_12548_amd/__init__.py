@@ -148,6 +148,8 @@ def lib():
     L.sba_range_kernel.argtypes = [vp, vp, C.c_int]
     L.sba_join_pairs.restype = C.c_int
     L.sba_join_pairs.argtypes = [vp, vp, i64, vp, vp, vp, C.POINTER(i64), vp]
+    L.sba_debug_learned_fallbacks.restype = C.c_int
+    L.sba_debug_learned_fallbacks.argtypes = [vp, vp, i64, C.POINTER(i64), C.POINTER(i64), vp]
     L.sba_debug_pindex_lb.restype = C.c_int
     L.sba_debug_pindex_lb.argtypes = [vp, vp, i64, i32, vp, C.POINTER(i64), vp]
     _lib = L
@@ -300,6 +302,15 @@ class Approx:
                                             counts.data_ptr(), sptr, sp)
         _check(rc, "sba_aggregate")
         return counts[:self.n_polys], (sums[:self.n_polys] if values is not None else None)
+
+    def learned_fallbacks(self, xy, stream=None):
+        """Test support: (fallbacks, mismatches) of the learned run search over
+        the cells of the points xy (int32 GPU tensor [2n])."""
+        fb, mm = C.c_int64(0), C.c_int64(0)
+        _check(lib().sba_debug_learned_fallbacks(self._h, xy.data_ptr(), xy.numel() // 2,
+                                                 C.byref(fb), C.byref(mm), _stream_ptr(stream)),
+               "sba_debug_learned_fallbacks")
+        return int(fb.value), int(mm.value)
 
     def lookup(self, ij, stream=None):
         """Refs of cells (int64 GPU tensor [2n] of i,j): -1 none, p, or -2-set."""

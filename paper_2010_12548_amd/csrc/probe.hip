@@ -331,7 +331,8 @@ __device__ __forceinline__ void pred_search_var4(const uint32_t *keys, int32_t *
 // for an exact error bound).
 template <int NP>
 __device__ __forceinline__ void learned_search_n(const HilbView &v, const uint32_t *kk,
-                                                 const uint64_t *key, int64_t *q)
+                                                 const uint64_t *key, int64_t *q,
+                                                 unsigned long long *fallbacks = nullptr)
 {
     const uint32_t *keys = v.k32;
     int4 lf[NP];
@@ -367,6 +368,7 @@ __device__ __forceinline__ void learned_search_n(const HilbView &v, const uint32
     for (int k = 0; k < NP; k++) {
         bool good = first[k] <= kk[k] && (q[k] + 1 == v.n || nxt[k] > kk[k]);
         if (!good) {  // bracket missed (never for an exact error bound): full search
+            if (fallbacks) atomicAdd(fallbacks, 1ull);
             int64_t lo1[1] = {0};
             uint32_t k1[1] = {kk[k]};
             pred_search_n<uint32_t, 1>(keys, lo1, v.n, k1);
@@ -1377,6 +1379,50 @@ extern "C" const char *sba_probe_kernel(const sba_handle *h, int with_values)
     snprintf(buf, sizeof(buf), "%s<%d, %s>",
              h->n_polys <= LDS_MAX_POLYS ? "k_probe_lds" : "k_probe_items", layout, v);
     return buf;
+}
+
+// Learned run search over the cells of n points, counted: fb[0] = searches
+// whose bracket check failed (full binary search taken), fb[1] = points whose
+// learned answer differs from the binary search's.
+__global__ void k_debug_learned(HilbView v, const int32_t *xy, int64_t n, unsigned long long *fb)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int64_t dx = (int64_t)xy[2 * t] - v.ox, dy = (int64_t)xy[2 * t + 1] - v.oy;
+    if ((uint64_t)dx >= v.extx || (uint64_t)dy >= v.exty) return;
+    const uint32_t i = divmagic((uint32_t)dx, v.mag, v.shift);
+    const uint32_t j = divmagic((uint32_t)dy, v.mag, v.shift);
+    const uint64_t key[1] = {hilbert_index(v.L, i, j)};
+    const uint32_t k32[1] = {(uint32_t)key[0]};
+    int64_t q[1], qb[1] = {0};
+    learned_search_n<1>(v, k32, key, q, fb);
+    pred_search_n<uint32_t, 1>(v.k32, qb, v.n, k32);
+    if (q[0] != qb[0]) atomicAdd(&fb[1], 1ull);
+}
+
+extern "C" int sba_debug_learned_fallbacks(const sba_handle *h, const int32_t *xy, int64_t n,
+                                           int64_t *fallbacks, int64_t *mismatches, void *stream)
+{
+    if (!h || n < 0 || (n > 0 && !xy) || !fallbacks || !mismatches) return SBA_EINVAL;
+    *fallbacks = *mismatches = 0;
+    if (h->kind != SBA_KIND_HILBERT || !h->leaves || !h->starts32) return SBA_EINVAL;
+    if (n == 0 || h->n_runs == 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    GridView g;
+    HilbView hv;
+    views(h, &g, &hv);
+    Workspace ws(st);
+    unsigned long long *fb = nullptr;
+    RC(ws.alloc(&fb, 2));
+    HIP_OK(hipMemsetAsync(fb, 0, 2 * sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(k_debug_learned, dim3(grid_for(n)), dim3(256), 0, st, hv, xy, n, fb);
+    HIP_OK(hipGetLastError());
+    unsigned long long hfb[2];
+    RC(ws.read(hfb, fb, sizeof(hfb)));
+    RC(ws.sync());
+    *fallbacks = (int64_t)hfb[0];
+    *mismatches = (int64_t)hfb[1];
+    return 0;
 }
 
 extern "C" int sba_debug_grid16_sets(int mode)

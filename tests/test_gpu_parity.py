@@ -599,3 +599,25 @@ def test_result_range_one_pass_stars(sba, orc, tl, sl):
     np.testing.assert_array_equal(bs, wb[1])
     with pytest.raises(sba.SbaError):       # beta must be the boundary-only handle
         _range(sba, A, A, xy, vals)
+
+
+@pytest.mark.parametrize("log2_leaves", [4, 8, 12, 16])
+def test_learned_search_never_falls_back(sba, log2_leaves):
+    """The leaves' stored error bounds every key of their key range, so the
+    learned search's bracket check never fails and its answers equal binary
+    search for every point (in and out of the polygons)."""
+    from gen import city_polygons
+    polys = city_polygons()
+    xy, _ = city_points(1_000_000)
+    for eps in (100, 1000):
+        H = sba.Approx.from_polygons(polys, eps, kind="hilbert", search="learned",
+                                     log2_leaves=log2_leaves)
+        fb, mm = H.learned_fallbacks(dev(xy))
+        assert (fb, mm) == (0, 0)
+    rng = np.random.default_rng(log2_leaves)
+    stars = star_polygons(12, 9, 20.0, 400.0, 1500, 55)
+    pts = rng.integers(-100, 1700, size=2 * 300_000).astype(np.int32)
+    for eps in (3, 9):
+        H = sba.Approx.from_polygons(stars, eps, kind="hilbert", search="learned",
+                                     log2_leaves=log2_leaves)
+        assert H.learned_fallbacks(dev(pts)) == (0, 0)
