@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--search", default="", choices=["", "binary", "learned"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-sweep", action="store_true", help="skip the eps sweep")
+    ap.add_argument("--serial", action="store_true",
+                    help="build and probe on one stream (no overlap of step k+1's build with "
+                         "step k's probe)")
     ap.add_argument("--no-pindex", action="store_true",
                     help="skip the point-index (pre-aggregated points) measurement")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
@@ -358,31 +361,52 @@ def main():
         probe_only(args, sba, torch, txy, tv, ro, vo, pxy, eps, layout, search, n)
         return
 
+    # A step builds the approximation and probes every point with it.  The
+    # builds run on one stream and the probes on another, so the build of
+    # step k+1 (host-bound: short kernels and a few size readbacks) overlaps
+    # the probe of step k (bound by HBM bandwidth); every step still does its
+    # whole build and its whole probe.  --serial runs both on one stream.
+    import contextlib
+    bstream = None if args.serial else torch.cuda.Stream()
+    pstream = None if args.serial else torch.cuda.Stream()
+
     def step(ev=None):
-        a = sba.Approx(ro, vo, pxy, eps, **kw)
-        if ev is not None:
-            ev[0].record()
-        a.aggregate(txy, tv, counts, sums)
-        if ev is not None:
-            ev[1].record()
+        a = sba.Approx(ro, vo, pxy, eps, stream=bstream, **kw)   # returns complete
+        with (torch.cuda.stream(pstream) if pstream is not None else contextlib.nullcontext()):
+            if ev is not None:
+                ev[0].record()
+            a.aggregate(txy, tv, counts, sums, stream=pstream)
+            if ev is not None:
+                ev[1].record()
         return a
+
+    def timed_steps(k_steps):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(k_steps)]
+        hs = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(k_steps):
+            hs.append(step(evs[k]))
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, evs, hs
 
     for _ in range(args.warmup):
         step().close()
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    handles = []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        handles.append(step(evs[k]))
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
+    t_total, evs, handles = timed_steps(args.steps)
     probe_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
     info = handles[-1].info()
     kernel = handles[-1].probe_kernel(True)
     ms_step = 1000.0 * t_total / args.steps
+    # the same steps with build and probe on one stream, for comparison
+    ms_step_serial = None
+    if not args.serial:
+        bstream = pstream = None
+        t_ser, _, hs = timed_steps(args.steps)
+        ms_step_serial = 1000.0 * t_ser / args.steps
+        for h in hs:
+            h.close()
     probe_in_step = float(np.mean(probe_ms))
     alg_bytes = 16.0 * n          # 8 B x,y + 8 B value per point
     # the probe kernel's own time: back-to-back calls on the current stream
@@ -399,8 +423,8 @@ def main():
     torch.cuda.synchronize()
     probe_avg = e0.elapsed_time(e1) / reps
     achieved = alg_bytes / (probe_avg * 1e-3) / 1e9
-    # build time on its own (inside the step loop a build's first wait also
-    # covers the previous step's probe)
+    # build time on its own (in a one-stream step loop a build's first wait
+    # also covers the previous step's probe)
     iso = []
     for _ in range(5):
         torch.cuda.synchronize()
@@ -409,8 +433,10 @@ def main():
         iso.append(1000.0 * (time.perf_counter() - t0))
         a.close()
     build_iso = float(np.median(iso))
-    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, probe in step {probe_in_step:.4f} ms, "
-        f"probe back-to-back {probe_avg:.4f} ms, build alone median {build_iso:.3f} ms")
+    ser = f" (one stream: {ms_step_serial:.3f} ms/step)" if ms_step_serial else ""
+    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step{ser}, probe in step "
+        f"{probe_in_step:.4f} ms, probe back-to-back {probe_avg:.4f} ms, build alone median "
+        f"{build_iso:.3f} ms")
 
     for h in handles:
         h.close()
@@ -632,6 +658,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_serial": ms_step_serial,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -639,7 +666,10 @@ def main():
         "data": "synthetic (seeded generators stand in for the NYC taxi / census data)",
         "config": {"workload": desc, "points": n, "polygons": polys.n_polys, "eps_units": eps,
                    "layout": layout, "search": search if layout == "hilbert" else None,
-                   "step": "sba_build_approx + sba_aggregate (COUNT+SUM)"},
+                   "step": "sba_build_approx + sba_aggregate (COUNT+SUM)",
+                   "streams": ("one" if args.serial else
+                               "builds and probes on two streams: step k+1's build overlaps "
+                               "step k's probe")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_of(args.workload, eps, n, kernel),
