@@ -511,6 +511,29 @@ def main():
                                            and np.array_equal(ss.cpu().numpy(), res_s))
         del sx, sv
         extra["hilbert_sorted_points"] = srt
+        # the points as generated, partitioned into 256 coarse regions by the
+        # call itself and then probed region by region (scratch 16 B/point)
+        scratch = torch.empty(a.scratch_bytes(n), dtype=torch.uint8, device=dev)
+        part = {}
+        for srch in ("binary", "learned"):
+            cc = torch.empty_like(counts)
+            ss = torch.empty_like(sums)
+            a.aggregate_partitioned(txy, tv, cc, ss, search=srch, scratch=scratch)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(3):
+                a.aggregate_partitioned(txy, tv, cc, ss, search=srch, scratch=scratch)
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / 3
+            part[srch] = {"ms": round(t, 4), "points_per_s": n / (t * 1e-3),
+                          "same_as_direct": bool(
+                              np.array_equal(cc.cpu().numpy(), res_c.astype(np.int64))
+                              and np.array_equal(ss.cpu().numpy(), res_s))}
+        del scratch
+        extra["partitioned_probe"] = part
+        log(f"[bench] partitioned probe: {json.dumps(part)}")
         extra["learned_vs_binary"] = {**out, "identical": bool(same),
                                       "speedup": out["binary"]["probe_ms"] / out["learned"]["probe_ms"],
                                       "fallbacks": fb, "learned_ne_binary": mm,

@@ -182,6 +182,25 @@ int sba_aggregate_search(const int32_t *xy, const int64_t *values, int64_t n,
                          int64_t *sums, void *stream);
 
 /*
+ * sba_aggregate over points in no spatial order, for the layouts whose
+ * lookups search large arrays (Hilbert runs; grids with more polygons than
+ * LDS bins hold): the points and values are first partitioned into 256
+ * buckets, the level-4 Hilbert tiles of the handle's cell box, then probed
+ * bucket by bucket so each bucket's part of the structure stays in cache.
+ * The answer is sba_aggregate's (search as in sba_aggregate_search).
+ *   scratch        DEVICE buffer, 256-byte aligned, of at least
+ *                  sba_partition_scratch_bytes(n, values != NULL && sums !=
+ *                  NULL) bytes (about 16 B per point), else SBA_ELIMIT; its
+ *                  contents are overwritten.  The call allocates nothing.
+ * Inputs of fewer than 2^17 points take the direct probe.  Asynchronous.
+ */
+size_t sba_partition_scratch_bytes(int64_t n, int with_values);
+int sba_aggregate_partitioned(const int32_t *xy, const int64_t *values, int64_t n,
+                              const sba_handle *h, int32_t search, void *scratch,
+                              size_t scratch_bytes, uint64_t *counts, int64_t *sums,
+                              void *stream);
+
+/*
  * Result range in one pass (Sec. 6): alpha (COUNT/SUM over A(P)) and the
  * boundary partial beta (over B(P)) of every polygon, so that the exact
  * answer lies in [alpha - beta, alpha] (sums: for non-negative values).

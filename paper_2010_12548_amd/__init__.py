@@ -142,6 +142,10 @@ def lib():
     L.sba_pindex_aggregate.argtypes = [vp, vp, i32, vp, vp, vp]
     L.sba_pindex_free.restype = None
     L.sba_pindex_free.argtypes = [vp]
+    L.sba_partition_scratch_bytes.restype = C.c_size_t
+    L.sba_partition_scratch_bytes.argtypes = [i64, C.c_int]
+    L.sba_aggregate_partitioned.restype = C.c_int
+    L.sba_aggregate_partitioned.argtypes = [vp, vp, i64, vp, i32, vp, C.c_size_t, vp, vp, vp]
     L.sba_aggregate_range.restype = C.c_int
     L.sba_aggregate_range.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp]
     L.sba_range_kernel.restype = C.c_char_p
@@ -311,6 +315,32 @@ class Approx:
                                                  C.byref(fb), C.byref(mm), _stream_ptr(stream)),
                "sba_debug_learned_fallbacks")
         return int(fb.value), int(mm.value)
+
+    def aggregate_partitioned(self, xy, values=None, counts=None, sums=None,
+                              search: str | None = None, scratch=None, stream=None):
+        """aggregate() for points in no spatial order: points partitioned by
+        coarse region first (``sba_aggregate_partitioned``).  scratch: a uint8
+        GPU tensor of scratch_bytes(n) bytes, allocated here if None."""
+        torch = _torch()
+        n = xy.numel() // 2
+        if counts is None:
+            counts = torch.empty(max(self.n_polys, 1), dtype=torch.int64, device=xy.device)
+        if values is not None and sums is None:
+            sums = torch.empty(max(self.n_polys, 1), dtype=torch.int64, device=xy.device)
+        need = int(lib().sba_partition_scratch_bytes(n, 1 if values is not None else 0))
+        if scratch is None:
+            scratch = torch.empty(need, dtype=torch.uint8, device=xy.device)
+        code = {"binary": SEARCH_BINARY, "learned": SEARCH_LEARNED}[search or self.search]
+        rc = lib().sba_aggregate_partitioned(
+            xy.data_ptr(), values.data_ptr() if values is not None else None, n, self._h, code,
+            scratch.data_ptr(), scratch.numel(), counts.data_ptr(),
+            sums.data_ptr() if values is not None else None, _stream_ptr(stream))
+        _check(rc, "sba_aggregate_partitioned")
+        return counts[:self.n_polys], (sums[:self.n_polys] if values is not None else None)
+
+    @staticmethod
+    def scratch_bytes(n: int, with_values: bool = True) -> int:
+        return int(lib().sba_partition_scratch_bytes(int(n), 1 if with_values else 0))
 
     def lookup(self, ij, stream=None):
         """Refs of cells (int64 GPU tensor [2n] of i,j): -1 none, p, or -2-set."""

@@ -6,7 +6,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["alloc.hip", "prims.hip", "build.hip", "hilbert.hip", "probe.hip", "serve.hip", "pindex.hip",
-           "join.hip", "api.hip"]
+           "join.hip", "partition.hip", "api.hip"]
 OUT = os.path.join(HERE, "libsba.so")
 
 FLAGS = [

@@ -267,6 +267,14 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_offsets(int64_t *hist, int64_t 
     }
 }
 
+int rs_offsets_launch(int64_t *hist, int64_t nblocks, const unsigned long long *dtot,
+                      hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rs_offsets, dim3(RS_RADIX), dim3(RS_BLOCK), 0, st, hist, nblocks, dtot);
+    HIP_OK(hipGetLastError());
+    return 0;
+}
+
 template <bool HAS_VALS>
 __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const uint64_t *keys, const uint32_t *vals,
                                                          uint64_t *okeys, uint32_t *ovals,

@@ -1304,6 +1304,18 @@ int range_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_
     return hipGetLastError() != hipSuccess ? SBA_EDEVICE : 0;
 }
 
+int items_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
+                 int32_t search, uint64_t *counts, int64_t *sums, hipStream_t st)
+{
+    if (h->n_polys == 0) return 0;
+    int layout = 0;
+    if (h->kind == SBA_KIND_HILBERT) {
+        if (search == SBA_SEARCH_LEARNED && !h->leaves) return SBA_EINVAL;
+        layout = search == SBA_SEARCH_LEARNED ? 2 : 1;
+    }
+    return launch_items(xy, values, n, h, layout, counts, sums, st);
+}
+
 // Name of the kernel a range call launches ("" when it takes two passes).
 extern "C" const char *sba_range_kernel(const sba_handle *h, const sba_handle *hb, int with_values)
 {
@@ -1612,6 +1624,11 @@ __device__ __forceinline__ void table_flush(const CodeTable &H, const TaskDev &T
 // in spatial order (bucketed, Hilbert-sorted) meet few codes per item and
 // almost never reach global memory, points in no order fall back to a global
 // atomic per point once the table is full.
+// Items are dealt to the chip's 8 XCDs in contiguous eighths (workgroup b
+// runs on XCD b mod 8, the dispatcher's round robin), so the points the
+// workgroups of one XCD hold at a time come from one stretch of the input:
+// for spatially ordered or partitioned points, one region whose part of the
+// structure fits that XCD's L2.  The grid size is a multiple of 8.
 template <int LAYOUT, bool VALS>
 __global__ __launch_bounds__(PROBE_BLOCK) void k_probe_items(const TaskDev T, int64_t item,
                                                              int64_t n_items)
@@ -1628,7 +1645,10 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_probe_items(const TaskDev T, in
     }
     if (threadIdx.x == 0) s_full = 0;
     __syncthreads();
-    for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int64_t nx = gridDim.x >> 3, per = (n_items + 7) >> 3;
+    const int64_t first = (int64_t)(blockIdx.x & 7) * per;
+    const int64_t last = min(first + per, n_items);
+    for (int64_t it = first + (blockIdx.x >> 3); it < last; it += nx) {
         const int64_t lo = it * item, hi = min(lo + item, T.n);
         batch_item<LAYOUT, VALS>(T, lo, hi, H);
         __syncthreads();
@@ -1653,14 +1673,15 @@ static int launch_items(const int32_t *xy, const int64_t *values, int64_t n, con
     T.sums = vals ? (unsigned long long *)sums : nullptr;
     // about ITEMS_PER_WG items per workgroup (even sizes keep the pairs
     // aligned), so the round robin ends evenly
-    const int64_t nb = std::max<int64_t>(
+    int64_t nb = std::max<int64_t>(
         1, std::min<int64_t>((n + ITEM_MIN - 1) / ITEM_MIN, (int64_t)cu_count() * g_blocks_per_cu));
+    nb = (nb + 7) & ~(int64_t)7;  // whole rounds of the 8 XCDs
     int64_t item = (n + nb * ITEMS_PER_WG - 1) / (nb * ITEMS_PER_WG);
     item = std::max<int64_t>(ITEM_MIN, (item + 1) & ~(int64_t)1);
     const int64_t n_items = (n + item - 1) / item;
     hipLaunchKernelGGL(k_zero_out, dim3(grid_for(h->n_polys)), dim3(256), 0, st, counts,
                        vals ? sums : nullptr, h->n_polys);
-    const dim3 grid((unsigned)std::min(nb, n_items));
+    const dim3 grid((unsigned)nb);
     switch (layout * 2 + (vals ? 1 : 0)) {
     case 0: hipLaunchKernelGGL((k_probe_items<0, false>), grid, dim3(PROBE_BLOCK), 0, st, T, item, n_items); break;
     case 1: hipLaunchKernelGGL((k_probe_items<0, true>), grid, dim3(PROBE_BLOCK), 0, st, T, item, n_items); break;

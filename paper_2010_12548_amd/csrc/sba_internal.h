@@ -300,6 +300,12 @@ int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStrea
 // to it and the other buffer goes back to ws (so both must come from ws).
 int radix_sort_u64_ws(uint64_t **keys, uint32_t **vals, int64_t n, int bits, Workspace &ws);
 
+// In place: hist[d * nblocks + b] (per block b the count of digit d, 256
+// digits) becomes the position of block b's first key of digit d in the
+// output of a stable partition; dtot[d] holds the digit totals.
+int rs_offsets_launch(int64_t *hist, int64_t nblocks, const unsigned long long *dtot,
+                      hipStream_t st);
+
 // device allocation helper (persistent arrays of a handle)
 template <typename T>
 inline int dev_alloc(T **p, int64_t count)
@@ -372,6 +378,10 @@ inline unsigned grid_for(int64_t n, int block = 256)
 int probe_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
                  int32_t search, uint64_t *counts, int64_t *sums, hipStream_t st);
 int lookup_launch(const sba_handle *h, const int64_t *ij, int64_t n, int32_t *ref, hipStream_t st);
+// the probe over contiguous items of points with an LDS table of cell codes
+// (any layout; for points in spatial order)
+int items_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
+                 int32_t search, uint64_t *counts, int64_t *sums, hipStream_t st);
 int range_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
                  const sba_handle *hb, uint64_t *counts, int64_t *sums, uint64_t *bcounts,
                  int64_t *bsums, hipStream_t st);

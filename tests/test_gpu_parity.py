@@ -621,3 +621,54 @@ def test_learned_search_never_falls_back(sba, log2_leaves):
         H = sba.Approx.from_polygons(stars, eps, kind="hilbert", search="learned",
                                      log2_leaves=log2_leaves)
         assert H.learned_fallbacks(dev(pts)) == (0, 0)
+
+
+def test_partitioned_probe_equals_oracle(sba, orc):
+    """Points partitioned by coarse region, then probed: the oracle's answer
+    on every layout, with and without values, odd sizes, too-small scratch."""
+    polys = voronoi_partition(6000, 1_000_000, (2, 6), seed=31, jitter_seed=32)
+    n = 600_001
+    xy = uniform_points(n, -2000, 1_002_000, 6)
+    vals = np.random.default_rng(9).integers(-10**6, 10**6, size=n).astype(np.int64)
+    eps = 300
+    want_c, want_s = orc.Approx(polys, eps).aggregate(xy, vals)
+    handles = [sba.Approx.from_polygons(polys, eps, kind="hilbert", search="learned"),
+               sba.Approx.from_polygons(polys, eps)]
+    sba.lib().sba_debug_force_wide_grid(1)
+    try:
+        handles.append(sba.Approx.from_polygons(polys, eps))
+    finally:
+        sba.lib().sba_debug_force_wide_grid(0)
+    txy, tv = dev(xy), dev(vals)
+    for A in handles:
+        searches = ("binary", "learned") if A.kind == "hilbert" else ("binary",)
+        for search in searches:
+            c, s = A.aggregate_partitioned(txy, tv, search=search)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(c.cpu().numpy().astype(np.uint64), want_c)
+            np.testing.assert_array_equal(s.cpu().numpy(), want_s)
+            c, _ = A.aggregate_partitioned(txy, None, search=search)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(c.cpu().numpy().astype(np.uint64), want_c)
+    A = handles[0]
+    small = torch.empty(A.scratch_bytes(n) - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(sba.SbaError):
+        A.aggregate_partitioned(txy, tv, scratch=small)
+    # below the partition threshold the direct probe answers
+    c, s = A.aggregate_partitioned(txy[:2 * 1001], tv[:1001])
+    wc, ws = orc.Approx(polys, eps).aggregate(xy[:2 * 1001], vals[:1001])
+    np.testing.assert_array_equal(c.cpu().numpy().astype(np.uint64), wc)
+    np.testing.assert_array_equal(s.cpu().numpy(), ws)
+
+
+def test_partitioned_probe_city_hilbert(sba, orc):
+    from gen import city_polygons
+    polys = city_polygons()
+    xy, vals = city_points(1_000_001)
+    for eps in (100, 1000):
+        want_c, want_s = orc.Approx(polys, eps).aggregate(xy, vals)
+        A = sba.Approx.from_polygons(polys, eps, kind="hilbert", search="learned")
+        c, s = A.aggregate_partitioned(dev(xy), dev(vals))
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(c.cpu().numpy().astype(np.uint64), want_c)
+        np.testing.assert_array_equal(s.cpu().numpy(), want_s)
