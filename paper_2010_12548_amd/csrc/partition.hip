@@ -58,22 +58,76 @@ __global__ __launch_bounds__(PART_BLOCK) void k_part_hist(const int32_t *__restr
     if (c) atomicAdd(&dtot[threadIdx.x], (unsigned long long)c);
 }
 
+// Each chunk goes out in tiles of PART_TILE points: the tile is ordered by
+// bucket in LDS (a rank per point from an LDS counter, the tile's bucket
+// offsets by a scan), then written linearly, so the points of one bucket
+// leave as one contiguous run instead of scattered 8-byte stores.
+#define PART_PER 16
+#define PART_TILE (PART_BLOCK * PART_PER)
+
 template <bool VALS>
 __global__ __launch_bounds__(PART_BLOCK) void k_part_scatter(
     const int32_t *__restrict__ xy, const int64_t *__restrict__ vals, int64_t n, PartGeo g,
     const int64_t *__restrict__ off, int64_t nblocks, int2 *__restrict__ oxy,
     int64_t *__restrict__ ovals)
 {
-    __shared__ unsigned long long cur[256];
-    cur[threadIdx.x] = (unsigned long long)off[(int64_t)threadIdx.x * nblocks + blockIdx.x];
-    __syncthreads();
+    __shared__ int64_t cur[256];       // next output position of each bucket
+    __shared__ uint32_t cnt[256];      // the tile's points per bucket, then their offsets
+    __shared__ int64_t base[256];      // output position of the tile's first point of a bucket
+                                       // minus that point's position in the staged tile
+    __shared__ int2 sxy[PART_TILE];
+    __shared__ int64_t sv[VALS ? PART_TILE : 1];
+    __shared__ uint32_t wsum[PART_BLOCK / 64];
+    const int tid = threadIdx.x;
+    cur[tid] = off[(int64_t)tid * nblocks + blockIdx.x];
     const int64_t a = (int64_t)blockIdx.x * PART_CHUNK, b = min(a + (int64_t)PART_CHUNK, n);
-    for (int64_t t = a + threadIdx.x; t < b; t += PART_BLOCK) {
-        const int2 p = ((const int2 *)xy)[t];
-        const uint32_t d = part_digit(g, p.x, p.y);
-        const int64_t pos = (int64_t)atomicAdd(&cur[d], 1ull);
-        oxy[pos] = p;
-        if (VALS) ovals[pos] = vals[t];
+    for (int64_t t0 = a; t0 < b; t0 += PART_TILE) {
+        cnt[tid] = 0;
+        __syncthreads();
+        int2 p[PART_PER];
+        int64_t v[PART_PER];
+        uint32_t d[PART_PER], r[PART_PER];
+#pragma unroll
+        for (int k = 0; k < PART_PER; k++) {
+            const int64_t t = t0 + k * PART_BLOCK + tid;
+            const bool in = t < b;
+            p[k] = in ? ((const int2 *)xy)[t] : make_int2(0, 0);
+            v[k] = (VALS && in) ? vals[t] : 0;
+            d[k] = in ? part_digit(g, p[k].x, p[k].y) : 256u;
+            r[k] = in ? atomicAdd(&cnt[d[k]], 1u) : 0u;
+        }
+        __syncthreads();
+        // exclusive scan of the 256 bucket counts (one per thread)
+        const uint32_t c = cnt[tid];
+        uint32_t inc = c;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(inc, o, 64);
+            if ((tid & 63) >= o) inc += u;
+        }
+        if ((tid & 63) == 63) wsum[tid >> 6] = inc;
+        __syncthreads();
+        uint32_t excl = inc - c;
+        for (int w = 0; w < (tid >> 6); w++) excl += wsum[w];
+        base[tid] = cur[tid] - (int64_t)excl;
+        cur[tid] += c;
+        cnt[tid] = excl;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PART_PER; k++) {
+            if (d[k] >= 256u) continue;
+            const uint32_t s = cnt[d[k]] + r[k];
+            sxy[s] = p[k];
+            if (VALS) sv[s] = v[k];
+        }
+        __syncthreads();
+        const int m = (int)min((int64_t)PART_TILE, b - t0);
+        for (int s = tid; s < m; s += PART_BLOCK) {
+            const int2 q = sxy[s];
+            const int64_t pos = base[part_digit(g, q.x, q.y)] + s;
+            oxy[pos] = q;
+            if (VALS) ovals[pos] = sv[s];
+        }
+        __syncthreads();
     }
 }
 
