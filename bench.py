@@ -659,7 +659,7 @@ def main():
         t0 = time.perf_counter()
         O = oracle.Approx(polys, eps)
         tb = time.perf_counter() - t0
-        sample = min(n, 50_000_000)
+        sample = min(n, 200_000_000)
         t0 = time.perf_counter()
         oc, os_ = O.aggregate(xy[:2 * sample], vals[:sample])
         ta = time.perf_counter() - t0
