@@ -207,16 +207,20 @@ int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tota
 
 #define RS_BLOCK 256
 #define RS_WAVES (RS_BLOCK / 64)
-#define RS_ROUNDS 16
-#define RS_TILE (RS_BLOCK * RS_ROUNDS)
+// A block sorts ROUNDS x 256 keys: 16 rounds for large inputs, 4 below
+// RS_SMALL keys, so that a sort of a few hundred thousand keys still spreads
+// over every compute unit.
+#define RS_SMALL (4 << 20)
 #define RS_RADIX 256
 
 // per block and digit: count, laid out digit-major (hist[d * nblocks + b]);
 // the digit totals are summed into dtot (zeroed before the pass)
+template <int ROUNDS>
 __global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const uint64_t *keys, int64_t n, int shift,
                                                       int64_t *hist, int64_t nblocks,
                                                       unsigned long long *dtot)
 {
+    constexpr int RS_TILE = RS_BLOCK * ROUNDS;
     __shared__ uint32_t h[RS_RADIX];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -275,12 +279,13 @@ int rs_offsets_launch(int64_t *hist, int64_t nblocks, const unsigned long long *
     return 0;
 }
 
-template <bool HAS_VALS>
+template <bool HAS_VALS, int ROUNDS>
 __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const uint64_t *keys, const uint32_t *vals,
                                                          uint64_t *okeys, uint32_t *ovals,
                                                          int64_t n, int shift,
                                                          const int64_t *goff, int64_t nblocks)
 {
+    constexpr int RS_ROUNDS = ROUNDS, RS_TILE = RS_BLOCK * ROUNDS;
     __shared__ uint32_t wcnt[RS_WAVES][RS_RADIX];
     __shared__ uint32_t bdoff[RS_RADIX];
     __shared__ uint64_t skeys[RS_TILE];
@@ -355,11 +360,41 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const uint64_t *keys, c
     }
 }
 
+static int rs_rounds(int64_t n) { return n < RS_SMALL ? 4 : 16; }
+
+static int64_t rs_blocks(int64_t n) { return (n + RS_BLOCK * rs_rounds(n) - 1) / (RS_BLOCK * rs_rounds(n)); }
+
+// one pass over digit (keys >> shift) & 255
+template <int ROUNDS>
+static int rs_pass_t(const uint64_t *ka, const uint32_t *va, uint64_t *kb, uint32_t *vb, int64_t n,
+                     int shift, int64_t *goff, int64_t nblocks, unsigned long long *dtot,
+                     hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rs_hist<ROUNDS>, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st, ka, n,
+                       shift, goff, nblocks, dtot);
+    hipLaunchKernelGGL(k_rs_offsets, dim3(RS_RADIX), dim3(RS_BLOCK), 0, st, goff, nblocks, dtot);
+    if (va)
+        hipLaunchKernelGGL((k_rs_scatter<true, ROUNDS>), dim3((unsigned)nblocks), dim3(RS_BLOCK), 0,
+                           st, ka, va, kb, vb, n, shift, goff, nblocks);
+    else
+        hipLaunchKernelGGL((k_rs_scatter<false, ROUNDS>), dim3((unsigned)nblocks), dim3(RS_BLOCK), 0,
+                           st, ka, va, kb, vb, n, shift, goff, nblocks);
+    return hipGetLastError() == hipSuccess ? 0 : SBA_EDEVICE;
+}
+
+static int rs_pass(const uint64_t *ka, const uint32_t *va, uint64_t *kb, uint32_t *vb, int64_t n,
+                   int shift, int64_t *goff, int64_t nblocks, unsigned long long *dtot,
+                   hipStream_t st)
+{
+    return rs_rounds(n) == 4 ? rs_pass_t<4>(ka, va, kb, vb, n, shift, goff, nblocks, dtot, st)
+                             : rs_pass_t<16>(ka, va, kb, vb, n, shift, goff, nblocks, dtot, st);
+}
+
 int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st,
                    Workspace *ws)
 {
     if (n <= 1 || bits <= 0) return 0;
-    const int64_t nblocks = (n + RS_TILE - 1) / RS_TILE;
+    const int64_t nblocks = rs_blocks(n);
     uint64_t *k2 = nullptr;
     uint32_t *v2 = nullptr;
     int64_t *goff = nullptr;
@@ -374,19 +409,8 @@ int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStrea
     uint64_t *ka = keys, *kb = k2;
     uint32_t *va = vals, *vb = v2;
     for (int p = 0; p < passes && !rc; p++) {
-        int shift = 8 * p;
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st, ka, n, shift,
-                           goff, nblocks, dtot + RS_RADIX * p);
-        hipLaunchKernelGGL(k_rs_offsets, dim3(RS_RADIX), dim3(RS_BLOCK), 0, st, goff, nblocks,
-                           dtot + RS_RADIX * p);
-        if (hipGetLastError() != hipSuccess) { rc = SBA_EDEVICE; break; }
-        if (vals)
-            hipLaunchKernelGGL(k_rs_scatter<true>, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st, ka,
-                               va, kb, vb, n, shift, goff, nblocks);
-        else
-            hipLaunchKernelGGL(k_rs_scatter<false>, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st, ka,
-                               va, kb, vb, n, shift, goff, nblocks);
-        if (hipGetLastError() != hipSuccess) { rc = SBA_EDEVICE; break; }
+        rc = rs_pass(ka, va, kb, vb, n, 8 * p, goff, nblocks, dtot + RS_RADIX * p, st);
+        if (rc) break;
         uint64_t *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
     }
@@ -408,7 +432,7 @@ int radix_sort_u64_ws(uint64_t **keys, uint32_t **vals, int64_t n, int bits, Wor
 {
     if (n <= 1 || bits <= 0) return 0;
     hipStream_t st = ws.stream();
-    const int64_t nblocks = (n + RS_TILE - 1) / RS_TILE;
+    const int64_t nblocks = rs_blocks(n);
     uint64_t *k2 = nullptr;
     uint32_t *v2 = nullptr;
     int64_t *goff = nullptr;
@@ -422,19 +446,7 @@ int radix_sort_u64_ws(uint64_t **keys, uint32_t **vals, int64_t n, int bits, Wor
     uint64_t *ka = *keys, *kb = k2;
     uint32_t *va = vals ? *vals : nullptr, *vb = v2;
     for (int p = 0; p < passes; p++) {
-        const int shift = 8 * p;
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st, ka, n, shift,
-                           goff, nblocks, dtot + RS_RADIX * p);
-        hipLaunchKernelGGL(k_rs_offsets, dim3(RS_RADIX), dim3(RS_BLOCK), 0, st, goff, nblocks,
-                           dtot + RS_RADIX * p);
-        HIP_OK(hipGetLastError());
-        if (va)
-            hipLaunchKernelGGL(k_rs_scatter<true>, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st, ka,
-                               va, kb, vb, n, shift, goff, nblocks);
-        else
-            hipLaunchKernelGGL(k_rs_scatter<false>, dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st, ka,
-                               va, kb, vb, n, shift, goff, nblocks);
-        HIP_OK(hipGetLastError());
+        RC(rs_pass(ka, va, kb, vb, n, 8 * p, goff, nblocks, dtot + RS_RADIX * p, st));
         std::swap(ka, kb);
         std::swap(va, vb);
     }
