@@ -116,25 +116,27 @@ __global__ void k_poly_bbox(const int32_t *ring_off, const int64_t *vert_off, co
 }
 
 // union of the polygons' cell boxes (one workgroup): box = {min over p of
-// ceil(xmin/s) - 1, same for y, max over p of floor(xmax/s), same for y}
+// ceil(xmin/s) - 1, same for y, max over p of floor(xmax/s), same for y}.
+// ceil and floor are monotone, so the extremes of the coordinates are found
+// first and divided once.
 #define BOX_BLOCK 1024
 __global__ __launch_bounds__(BOX_BLOCK) void k_union_box(const int4 *bbox, int32_t n_polys,
                                                          int64_t s, int64_t *box)
 {
-    __shared__ int64_t red[4][BOX_BLOCK / 64];
-    int64_t v[4] = {INT64_MAX, INT64_MAX, INT64_MIN, INT64_MIN};
+    __shared__ int32_t red[4][BOX_BLOCK / 64];
+    int32_t v[4] = {INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN};
     for (int p = threadIdx.x; p < n_polys; p += BOX_BLOCK) {
         int4 b = bbox[p];
-        v[0] = min(v[0], ceildiv64(b.x, s) - 1);
-        v[1] = min(v[1], ceildiv64(b.y, s) - 1);
-        v[2] = max(v[2], floordiv64(b.z, s));
-        v[3] = max(v[3], floordiv64(b.w, s));
+        v[0] = min(v[0], b.x);
+        v[1] = min(v[1], b.y);
+        v[2] = max(v[2], b.z);
+        v[3] = max(v[3], b.w);
     }
     for (int o = 32; o > 0; o >>= 1) {
-        v[0] = min(v[0], (int64_t)__shfl_xor(v[0], o, 64));
-        v[1] = min(v[1], (int64_t)__shfl_xor(v[1], o, 64));
-        v[2] = max(v[2], (int64_t)__shfl_xor(v[2], o, 64));
-        v[3] = max(v[3], (int64_t)__shfl_xor(v[3], o, 64));
+        v[0] = min(v[0], __shfl_xor(v[0], o, 64));
+        v[1] = min(v[1], __shfl_xor(v[1], o, 64));
+        v[2] = max(v[2], __shfl_xor(v[2], o, 64));
+        v[3] = max(v[3], __shfl_xor(v[3], o, 64));
     }
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0)
@@ -147,7 +149,10 @@ __global__ __launch_bounds__(BOX_BLOCK) void k_union_box(const int4 *bbox, int32
             v[2] = max(v[2], red[2][q]);
             v[3] = max(v[3], red[3][q]);
         }
-        for (int k = 0; k < 4; k++) box[k] = v[k];
+        box[0] = ceildiv64(v[0], s) - 1;
+        box[1] = ceildiv64(v[1], s) - 1;
+        box[2] = floordiv64(v[2], s);
+        box[3] = floordiv64(v[3], s);
     }
 }
 
