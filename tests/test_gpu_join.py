@@ -99,3 +99,18 @@ def test_capacity_and_rejects(sba, orc):
     if (info["level"], info["gi0"], info["gj0"]) != g:
         with pytest.raises(sba.SbaError):
             sba.join_pairs(A, own_grid)
+
+
+def test_join_with_empty_sets(sba, orc):
+    from gen import polygons_from_rings
+    a = star_polygons(6, 9, 5.0, 120.0, 400, 4107)
+    empty = polygons_from_rings([])
+    far = polygons_from_rings([[np.array([[10**6, 10**6], [10**6 + 50, 10**6], [10**6, 10**6 + 50]])]])
+    eps = 7
+    g = sba.key_grid_for(eps, a)
+    A = sba.Approx.from_polygons(a, eps, kind="hilbert", key_grid=g)
+    E = sba.Approx.from_polygons(empty, eps, kind="hilbert", key_grid=g)
+    F = sba.Approx.from_polygons(far, eps, kind="hilbert", key_grid=g)   # no cell in the grid
+    for X in (E, F):
+        pa, pb, cells = sba.join_pairs(A, X)
+        assert pa.numel() == 0 and pb.numel() == 0 and cells.numel() == 0

@@ -672,3 +672,35 @@ def test_partitioned_probe_city_hilbert(sba, orc):
         torch.cuda.synchronize()
         np.testing.assert_array_equal(c.cpu().numpy().astype(np.uint64), want_c)
         np.testing.assert_array_equal(s.cpu().numpy(), want_s)
+
+
+def test_edge_sizes_of_range_and_partitioned(sba, orc):
+    """Empty and odd point counts through the one-pass range probe, and the
+    partitioned probe just above its threshold with a ragged last chunk."""
+    polys = star_polygons(12, 9, 20.0, 400.0, 1500, 88)
+    eps = 5
+    A = sba.Approx.from_polygons(polys, eps, tile_log2=6, sub_log2=3)
+    Bh = sba.Approx.from_polygons(polys, eps, boundary_only=True, tile_log2=6, sub_log2=3)
+    OA, OB = orc.Approx(polys, eps), orc.Approx(polys, eps, boundary_only=True)
+    rng = np.random.default_rng(77)
+    for n in (0, 1, 2, 1001, (1 << 17) + 3):
+        xy = rng.integers(-50, 1600, size=2 * n).astype(np.int32)
+        vals = rng.integers(-100, 10000, size=n).astype(np.int64)
+        txy = torch.from_numpy(xy).cuda() if n else torch.zeros(0, dtype=torch.int32, device="cuda")
+        tv = torch.from_numpy(vals).cuda() if n else torch.zeros(0, dtype=torch.int64, device="cuda")
+        c, s, bc, bs = sba.aggregate_range(A, Bh, txy, tv)
+        torch.cuda.synchronize()
+        wa, wb = OA.aggregate(xy, vals), OB.aggregate(xy, vals)
+        np.testing.assert_array_equal(c.cpu().numpy().astype(np.uint64), wa[0])
+        np.testing.assert_array_equal(s.cpu().numpy(), wa[1])
+        np.testing.assert_array_equal(bc.cpu().numpy().astype(np.uint64), wb[0])
+        np.testing.assert_array_equal(bs.cpu().numpy(), wb[1])
+    H = sba.Approx.from_polygons(polys, eps, kind="hilbert", search="learned")
+    for n in ((1 << 17), (1 << 17) + 1, 3 * (1 << 16) + 5):
+        xy = rng.integers(-50, 1600, size=2 * n).astype(np.int32)
+        vals = rng.integers(-100, 10000, size=n).astype(np.int64)
+        c, s = H.aggregate_partitioned(dev(xy), dev(vals))
+        torch.cuda.synchronize()
+        wa = OA.aggregate(xy, vals)
+        np.testing.assert_array_equal(c.cpu().numpy().astype(np.uint64), wa[0])
+        np.testing.assert_array_equal(s.cpu().numpy(), wa[1])
