@@ -119,7 +119,7 @@ __global__ void k_poly_bbox(const int32_t *ring_off, const int64_t *vert_off, co
 // ceil(xmin/s) - 1, same for y, max over p of floor(xmax/s), same for y}.
 // ceil and floor are monotone, so the extremes of the coordinates are found
 // first and divided once.
-#define BOX_BLOCK 1024
+#define BOX_BLOCK 256
 __global__ __launch_bounds__(BOX_BLOCK) void k_union_box(const int4 *bbox, int32_t n_polys,
                                                          int64_t s, int64_t *box)
 {
@@ -645,7 +645,7 @@ __global__ void k_flag_list(const int64_t *pos, int64_t n, int64_t total, int64_
 // squares of k_square_classify).  OUT = uint32_t full codes or uint16_t
 // short codes.
 template <typename OUT>
-__global__ void k_block_fill(const int64_t *seg_row_off, const int32_t *seg_x0,
+__global__ __launch_bounds__(256) void k_block_fill(const int64_t *seg_row_off, const int32_t *seg_x0,
                              const int32_t *seg_x1, const uint32_t *seg_code, int64_t gw,
                              int64_t gh, const int64_t *sq, int64_t nblk, const int64_t *mt,
                              int tl, int sl, int64_t tw, int side_log2, uint32_t np, OUT *blocks)
@@ -688,13 +688,19 @@ __global__ void k_block_fill(const int64_t *seg_row_off, const int32_t *seg_x0,
         if (x < gw && q >= lo && x < seg_x1[q]) v = seg_code[q];
         buf[c] = sizeof(OUT) == 2 ? (OUT)short_code(v, np) : (OUT)v;
     }
+    // constant indices only, so buf stays in registers (a dynamically
+    // indexed array would be moved to LDS, which the kernel then reserves)
     const int bytes = rlen * (int)sizeof(OUT);
     if (bytes % 16 == 0) {
         uint4 *o4 = (uint4 *)out;
         const uint4 *b4 = (const uint4 *)buf;
-        for (int k = 0; k < bytes / 16; k++) o4[k] = b4[k];
+#pragma unroll
+        for (int k = 0; k < (int)sizeof(OUT); k++)  // 16 codes = sizeof(OUT) x 16 bytes
+            if (k < bytes / 16) o4[k] = b4[k];
     } else {
-        for (int c = 0; c < rlen; c++) out[c] = buf[c];
+#pragma unroll
+        for (int c = 0; c < 16; c++)
+            if (c < rlen) out[c] = buf[c];
     }
 }
 

@@ -1470,6 +1470,7 @@ extern "C" int sba_debug_set_blocks_per_cu(int k)
 // accumulate into them.
 
 #define BATCH_ITEM (1 << 18)
+#define BATCH_PER_CU 4
 #define ITEM_MIN 4096
 #define ITEMS_PER_WG 8
 
@@ -1788,7 +1789,10 @@ int batch_launch(const sba_task *tasks, int32_t n_tasks, hipStream_t st)
         if (hipGetLastError() != hipSuccess) rc = SBA_EDEVICE;
     }
     if (!rc && n_items) {
-        int64_t nb = std::min<int64_t>(n_items, (int64_t)cu_count() * g_blocks_per_cu);
+        // at most BATCH_PER_CU persistent workgroups per CU (half its LDS and
+        // wave slots), so the builds of later queries, queued on other streams,
+        // find room to run beside the batch
+        int64_t nb = std::min<int64_t>(n_items, (int64_t)cu_count() * BATCH_PER_CU);
         hipLaunchKernelGGL(k_batch, dim3((unsigned)nb), dim3(PROBE_BLOCK), 0, st, dtasks, ditems,
                            n_items, next);
         if (hipGetLastError() != hipSuccess) rc = SBA_EDEVICE;
