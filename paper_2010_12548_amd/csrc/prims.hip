@@ -207,10 +207,12 @@ int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tota
 
 #define RS_BLOCK 256
 #define RS_WAVES (RS_BLOCK / 64)
-// A block sorts ROUNDS x 256 keys: 16 rounds for large inputs, 4 below
-// RS_SMALL keys, so that a sort of a few hundred thousand keys still spreads
-// over every compute unit.
+// A block sorts ROUNDS x 256 keys: 4 rounds below RS_SMALL keys, so that a
+// sort of a few hundred thousand keys still spreads over every compute unit;
+// 8 below RS_MID (28 KB of LDS per block, which fits beside a persistent probe
+// holding the rest of a CU); 16 for larger inputs (fewer offsets to scan).
 #define RS_SMALL (4 << 20)
+#define RS_MID (64 << 20)
 #define RS_RADIX 256
 
 // per block and digit: count, laid out digit-major (hist[d * nblocks + b]);
@@ -360,7 +362,7 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const uint64_t *keys, c
     }
 }
 
-static int rs_rounds(int64_t n) { return n < RS_SMALL ? 4 : 16; }
+static int rs_rounds(int64_t n) { return n < RS_SMALL ? 4 : (n < RS_MID ? 8 : 16); }
 
 static int64_t rs_blocks(int64_t n) { return (n + RS_BLOCK * rs_rounds(n) - 1) / (RS_BLOCK * rs_rounds(n)); }
 
@@ -386,8 +388,10 @@ static int rs_pass(const uint64_t *ka, const uint32_t *va, uint64_t *kb, uint32_
                    int shift, int64_t *goff, int64_t nblocks, unsigned long long *dtot,
                    hipStream_t st)
 {
-    return rs_rounds(n) == 4 ? rs_pass_t<4>(ka, va, kb, vb, n, shift, goff, nblocks, dtot, st)
-                             : rs_pass_t<16>(ka, va, kb, vb, n, shift, goff, nblocks, dtot, st);
+    const int r = rs_rounds(n);
+    if (r == 4) return rs_pass_t<4>(ka, va, kb, vb, n, shift, goff, nblocks, dtot, st);
+    if (r == 8) return rs_pass_t<8>(ka, va, kb, vb, n, shift, goff, nblocks, dtot, st);
+    return rs_pass_t<16>(ka, va, kb, vb, n, shift, goff, nblocks, dtot, st);
 }
 
 int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st,
