@@ -63,9 +63,9 @@ def parse():
     ap.add_argument("--search", default="", choices=["", "binary", "learned"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-sweep", action="store_true", help="skip the eps sweep")
-    ap.add_argument("--serial", action="store_true",
-                    help="build and probe on one stream (no overlap of step k+1's build with "
-                         "step k's probe)")
+    ap.add_argument("--overlap", action="store_true",
+                    help="also time the steps with builds and probes on two streams (step "
+                         "k+1's build beside step k's probe), reported separately")
     ap.add_argument("--no-pindex", action="store_true",
                     help="skip the point-index (pre-aggregated points) measurement")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
@@ -361,14 +361,14 @@ def main():
         probe_only(args, sba, torch, txy, tv, ro, vo, pxy, eps, layout, search, n)
         return
 
-    # A step builds the approximation and probes every point with it.  The
-    # builds run on one stream and the probes on another, so the build of
-    # step k+1 (host-bound: short kernels and a few size readbacks) overlaps
-    # the probe of step k (bound by HBM bandwidth); every step still does its
-    # whole build and its whole probe.  --serial runs both on one stream.
+    # A step builds the approximation and probes every point with it, both
+    # on the current stream.  --overlap also times the same steps with the
+    # builds on one stream and the probes on another (the build of step k+1,
+    # host-bound, beside the probe of step k, bound by HBM bandwidth; every
+    # step still does its whole build and its whole probe) and reports that
+    # figure separately.
     import contextlib
-    bstream = None if args.serial else torch.cuda.Stream()
-    pstream = None if args.serial else torch.cuda.Stream()
+    bstream = pstream = None
 
     def step(ev=None):
         a = sba.Approx(ro, vo, pxy, eps, stream=bstream, **kw)   # returns complete
@@ -399,14 +399,14 @@ def main():
     info = handles[-1].info()
     kernel = handles[-1].probe_kernel(True)
     ms_step = 1000.0 * t_total / args.steps
-    # the same steps with build and probe on one stream, for comparison
-    ms_step_serial = None
-    if not args.serial:
-        bstream = pstream = None
-        t_ser, _, hs = timed_steps(args.steps)
-        ms_step_serial = 1000.0 * t_ser / args.steps
+    ms_step_overlap = None
+    if args.overlap:
+        bstream, pstream = torch.cuda.Stream(), torch.cuda.Stream()
+        t_ov, _, hs = timed_steps(args.steps)
+        ms_step_overlap = 1000.0 * t_ov / args.steps
         for h in hs:
             h.close()
+        bstream = pstream = None
     probe_in_step = float(np.mean(probe_ms))
     alg_bytes = 16.0 * n          # 8 B x,y + 8 B value per point
     # the probe kernel's own time: back-to-back calls on the current stream
@@ -433,7 +433,7 @@ def main():
         iso.append(1000.0 * (time.perf_counter() - t0))
         a.close()
     build_iso = float(np.median(iso))
-    ser = f" (one stream: {ms_step_serial:.3f} ms/step)" if ms_step_serial else ""
+    ser = f" (two streams: {ms_step_overlap:.3f} ms/step)" if ms_step_overlap else ""
     log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step{ser}, probe in step "
         f"{probe_in_step:.4f} ms, probe back-to-back {probe_avg:.4f} ms, build alone median "
         f"{build_iso:.3f} ms")
@@ -681,7 +681,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
-        "ms_per_step_serial": ms_step_serial,
+        "ms_per_step_overlapped": ms_step_overlap,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -690,9 +690,7 @@ def main():
         "config": {"workload": desc, "points": n, "polygons": polys.n_polys, "eps_units": eps,
                    "layout": layout, "search": search if layout == "hilbert" else None,
                    "step": "sba_build_approx + sba_aggregate (COUNT+SUM)",
-                   "streams": ("one" if args.serial else
-                               "builds and probes on two streams: step k+1's build overlaps "
-                               "step k's probe")},
+                   "streams": "one"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_of(args.workload, eps, n, kernel),
