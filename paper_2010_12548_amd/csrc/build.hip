@@ -850,8 +850,11 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     hipLaunchKernelGGL(k_edge_counts, dim3(grid_for(nv)), dim3(256), 0, st, B.edges, B.epoly, bbox,
                        nv, s, gi0, gj0, gi1, gj1, B.centre ? 1 : 0, nb, nc);
     HIP_OK(hipGetLastError());
-    RC(scan_exclusive_i64(nb, nb, nv, tot, st, &B.ws));
-    RC(scan_exclusive_i64(nc, nc, nv, tot + 1, st, &B.ws));
+    {
+        const int64_t *in[2] = {nb, nc}, n[2] = {nv, nv};
+        int64_t *out[2] = {nb, nc}, *sum[2] = {tot, tot + 1};
+        RC(scan_exclusive_i64_multi(2, in, out, n, sum, st, &B.ws));
+    }
     RC(fetch());
     // boundary-only approximations take no row-line crossings (no interior
     // spans); centre-sampled ones no boundary cells, except as the Hilbert
@@ -961,9 +964,11 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     hipLaunchKernelGGL(k_piece_classify, dim3(grid_for(NP)), dim3(256), 0, st, dex, diff, NP, segc,
                        mm, err);
     HIP_OK(hipGetLastError());
-    RC(scan_exclusive_i64(segc, segc, NP, tot + 3, st, &B.ws));
-    RC(scan_exclusive_i64(mm, mm, NP, tot + 4, st, &B.ws));
-    RC(scan_exclusive_i64(xoff, xoff, std::max<int64_t>(NI, 1), tot + 5, st, &B.ws));
+    {
+        const int64_t *in[3] = {segc, mm, xoff}, n[3] = {NP, NP, std::max<int64_t>(NI, 1)};
+        int64_t *out[3] = {segc, mm, xoff}, *sum[3] = {tot + 3, tot + 4, tot + 5};
+        RC(scan_exclusive_i64_multi(3, in, out, n, sum, st, &B.ws));
+    }
     RC(fetch());
     const int64_t *h6 = hsc + 8;
     herr = (int)(uint32_t)hsc[0];

@@ -198,8 +198,11 @@ extern "C" int sba_join_pairs(const sba_handle *a, const sba_handle *b, int64_t 
     hipLaunchKernelGGL(k_pair_flags, dim3(grid_for(NP)), dim3(256), 0, st, pkey, pay, len, NP, pf,
                        plen);
     HIP_OK(hipGetLastError());
-    RC(scan_exclusive_i64(pf, pos, NP, tot, st, &ws));
-    RC(scan_exclusive_i64(plen, plen, NP, plen + NP, st, &ws));
+    {
+        const int64_t *in[2] = {pf, plen}, n[2] = {NP, NP};
+        int64_t *out[2] = {pos, plen}, *sum[2] = {tot, plen + NP};
+        RC(scan_exclusive_i64_multi(2, in, out, n, sum, st, &ws));
+    }
     int64_t NU = 0;
     RC(ws.read(&NU, tot, sizeof(int64_t)));
     RC(ws.sync());

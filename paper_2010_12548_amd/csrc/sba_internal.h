@@ -288,6 +288,11 @@ __device__ __forceinline__ int64_t predict_in_leaf(int4 lf, int64_t lo, int64_t 
 // Temporaries come from ws when given, else from the stream-ordered pool.
 int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, hipStream_t st,
                        Workspace *ws = nullptr);
+// m independent scans (in[k] -> out[k], total into total[k] unless null):
+// one pair of launches for up to 4 arrays of moderate size, else one by one
+int scan_exclusive_i64_multi(int m, const int64_t *const *in, int64_t *const *out,
+                             const int64_t *n, int64_t *const *total, hipStream_t st,
+                             Workspace *ws = nullptr);
 
 // LSD radix sort by the low `bits` bits of keys (bits <= 64), stable,
 // carrying the optional 32-bit values.  On return keys/vals hold the sorted
