@@ -62,6 +62,23 @@ struct sba_pindex;
 int sba_debug_pindex_lb(const struct sba_pindex *ix, const uint64_t *v, int64_t n, int32_t search,
                         int64_t *out, int64_t *fallbacks, void *stream);
 
+/* The build's stable LSD radix sort: n DEVICE keys ordered by their low
+ * `bits` bits (1..64), the optional DEVICE uint32 payload `vals` (may be
+ * null) moved with them; the result is left in keys/vals.  The passes take
+ * 8 bits each and cover ceil(bits / 8) whole bytes, so keys must be below
+ * 2^bits (as the build's are); bytes above those are ignored.  SBA_EINVAL
+ * for a bad size or bit count.  Synchronous.  Test support. */
+int sba_debug_radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int32_t bits, void *stream);
+
+/* The build's batched exclusive prefix sums: for k < m (1..8), out[k][i] =
+ * in[k][0] + ... + in[k][i-1] over n[k] entries (out[k] may be in[k]) and
+ * total[k] = the sum of all n[k].  in, out and n are HOST arrays of m
+ * entries; in[k], out[k] and total (m entries) are DEVICE memory.  Up to 4
+ * arrays of at most 2^21 entries share one pair of launches; others are
+ * scanned one by one.  Synchronous.  Test support. */
+int sba_debug_scan_multi(int32_t m, const int64_t *const *in, int64_t *const *out,
+                         const int64_t *n, int64_t *total, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

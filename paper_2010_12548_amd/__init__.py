@@ -156,6 +156,10 @@ def lib():
     L.sba_debug_learned_fallbacks.argtypes = [vp, vp, i64, C.POINTER(i64), C.POINTER(i64), vp]
     L.sba_debug_pindex_lb.restype = C.c_int
     L.sba_debug_pindex_lb.argtypes = [vp, vp, i64, i32, vp, C.POINTER(i64), vp]
+    L.sba_debug_radix_sort.restype = C.c_int
+    L.sba_debug_radix_sort.argtypes = [vp, vp, i64, i32, vp]
+    L.sba_debug_scan_multi.restype = C.c_int
+    L.sba_debug_scan_multi.argtypes = [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(i64), vp, vp]
     _lib = L
     return L
 
@@ -193,6 +197,44 @@ def celldiv(s: int, n) -> np.ndarray:
     q = np.zeros_like(n)
     _check(lib().sba_debug_celldiv(int(s), n.ctypes.data, n.shape[0], q.ctypes.data), "celldiv")
     return q
+
+
+def radix_sort(keys, vals=None, bits: int = 64, stream=None):
+    """Sort the int64 GPU tensor `keys` in place by its low `bits` bits, read
+    as unsigned, with the build's stable radix sort; the int32 GPU tensor
+    `vals` (same length) moves along.  Keys must be below 2^bits: the passes
+    cover whole bytes.  Test support."""
+    torch = _torch()
+    if keys.dtype != torch.int64 or not keys.is_cuda or not keys.is_contiguous():
+        raise ValueError("keys: contiguous int64 GPU tensor")
+    vp = None
+    if vals is not None:
+        if (vals.dtype != torch.int32 or not vals.is_cuda or not vals.is_contiguous()
+                or vals.numel() != keys.numel()):
+            raise ValueError("vals: contiguous int32 GPU tensor of the keys' length")
+        vp = vals.data_ptr() or None
+    _check(lib().sba_debug_radix_sort(keys.data_ptr() or None, vp, keys.numel(), int(bits),
+                                      _stream_ptr(stream)), "radix_sort")
+    return keys, vals
+
+
+def scan_multi(arrays, in_place: bool = False, stream=None):
+    """Exclusive prefix sums of several int64 GPU tensors by the build's
+    batched scan; returns (outputs, totals).  Test support."""
+    torch = _torch()
+    m = len(arrays)
+    for a in arrays:
+        if a.dtype != torch.int64 or not a.is_cuda or not a.is_contiguous():
+            raise ValueError("arrays: contiguous int64 GPU tensors")
+    outs = list(arrays) if in_place else [torch.empty_like(a) for a in arrays]
+    dev = arrays[0].device if m else torch.device("cuda")
+    total = torch.full((max(m, 1),), -1, dtype=torch.int64, device=dev)
+    ins = (C.c_void_p * max(m, 1))(*[a.data_ptr() or None for a in arrays])
+    ous = (C.c_void_p * max(m, 1))(*[o.data_ptr() or None for o in outs])
+    ns = (C.c_int64 * max(m, 1))(*[a.numel() for a in arrays])
+    _check(lib().sba_debug_scan_multi(m, ins, ous, ns, total.data_ptr(), _stream_ptr(stream)),
+           "scan_multi")
+    return outs, total[:m]
 
 
 def hilbert(L: int, i: int, j: int) -> int:

@@ -577,3 +577,27 @@ int radix_sort_u64_ws(uint64_t **keys, uint32_t **vals, int64_t n, int bits, Wor
     if (vals && *vals) *vals = va;
     return 0;
 }
+
+extern "C" int sba_debug_radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int32_t bits,
+                                    void *stream)
+{
+    if (n < 0 || bits < 1 || bits > 64 || (n > 0 && !keys)) return SBA_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    RC(radix_sort_u64(keys, vals, n, bits, st, nullptr));
+    HIP_OK(hipStreamSynchronize(st));
+    return 0;
+}
+
+extern "C" int sba_debug_scan_multi(int32_t m, const int64_t *const *in, int64_t *const *out,
+                                    const int64_t *n, int64_t *total, void *stream)
+{
+    if (m < 1 || m > 8 || !in || !out || !n || !total) return SBA_EINVAL;
+    for (int k = 0; k < m; k++)
+        if (n[k] < 0 || (n[k] > 0 && (!in[k] || !out[k]))) return SBA_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    int64_t *tot[8];
+    for (int k = 0; k < m; k++) tot[k] = total + k;
+    RC(scan_exclusive_i64_multi(m, in, out, n, tot, st, nullptr));
+    HIP_OK(hipStreamSynchronize(st));
+    return 0;
+}

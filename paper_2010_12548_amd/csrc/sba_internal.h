@@ -295,7 +295,9 @@ int scan_exclusive_i64_multi(int m, const int64_t *const *in, int64_t *const *ou
                              Workspace *ws = nullptr);
 
 // LSD radix sort by the low `bits` bits of keys (bits <= 64), stable,
-// carrying the optional 32-bit values.  On return keys/vals hold the sorted
+// carrying the optional 32-bit values.  The passes cover ceil(bits / 8) whole
+// bytes: keys must be below 2^bits (every caller's are), bytes above those
+// are ignored.  On return keys/vals hold the sorted
 // data (the library ping-pongs through internal temporaries).
 int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st,
                    Workspace *ws = nullptr);
