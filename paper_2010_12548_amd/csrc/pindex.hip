@@ -161,6 +161,8 @@ struct Corners {
 // leaves the band of slopes that keeps every corner since the knot within E.
 // Slopes are compared as cross products (no divisions; positive run lengths).
 // Pass 1 counts the knots, pass 2 writes them at off[c] (off[nch] = total).
+#define SPLINE_PF 8
+
 template <bool WRITE>
 __global__ void k_spline(Corners C, int64_t CHM, double E, int64_t *cnt, const int64_t *off,
                          uint64_t *kx, int64_t *ky)
@@ -210,12 +212,26 @@ __global__ void k_spline(Corners C, int64_t CHM, double E, int64_t *cnt, const i
     };
     uint64_t prev = C.D[a];
     feed(prev, y0);
-    for (int64_t m = a + 1; m < b; m++) {
-        const uint64_t d = C.D[m];
-        const int64_t p = C.P[m];
-        feed(prev + 1, p);
-        feed(d, p);
-        prev = d;
+    // the chunk's keys and positions are read SPLINE_PF at a time, all loads
+    // issued before the corridor consumes them: one memory round trip per
+    // SPLINE_PF keys instead of one per key
+    for (int64_t m0 = a + 1; m0 < b; m0 += SPLINE_PF) {
+        uint64_t dd[SPLINE_PF];
+        int64_t pp[SPLINE_PF];
+#pragma unroll
+        for (int t = 0; t < SPLINE_PF; t++) {
+            const int64_t m = m0 + t < b ? m0 + t : b - 1;
+            dd[t] = C.D[m];
+            pp[t] = C.P[m];
+        }
+#pragma unroll
+        for (int t = 0; t < SPLINE_PF; t++) {
+            if (m0 + t < b) {
+                feed(prev + 1, pp[t]);
+                feed(dd[t], pp[t]);
+                prev = dd[t];
+            }
+        }
     }
     if (b == C.M) {
         feed(prev + 1, C.n);
