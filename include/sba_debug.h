@@ -1,7 +1,9 @@
 /*
- * sba_debug.h -- host-only helpers of libsba for its own tests and tuning.
- * They expose the integer arithmetic the kernels use, evaluated on the host,
- * so that it can be checked without a GPU.  Not needed by applications.
+ * sba_debug.h -- helpers of libsba for its own tests and tuning: the integer
+ * arithmetic the kernels use, evaluated on the host so that it can be checked
+ * without a GPU; process-wide launch-shape switches; and entry points that run
+ * internal device primitives and searches on their own so that tests can check
+ * them against plain definitions.  Not needed by applications.
  */
 #ifndef SBA_DEBUG_H
 #define SBA_DEBUG_H
