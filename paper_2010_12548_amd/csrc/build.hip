@@ -353,28 +353,37 @@ __global__ void k_unique_emit(const uint64_t *keys, int64_t n, const int64_t *po
     if (t == 0 || keys[t] != keys[t - 1]) out[pos[t]] = keys[t];
 }
 
-__device__ __forceinline__ int64_t lower_bound_key(const uint64_t *a, int64_t n, uint64_t v)
+__global__ void k_iota_u32(uint32_t *v, int64_t n)
 {
-    int64_t lo = 0, hi = n;
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (a[mid] < v) lo = mid + 1; else hi = mid;
-    }
-    return lo;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) v[t] = (uint32_t)t;
+}
+
+// Index in the sorted distinct toggle positions E of every toggle: the
+// sorted copy of the toggles carries each one's original slot src[t]; a
+// sorted entry's index among the distinct keys is the number of first
+// occurrences before it (pos, exclusive), less one when it repeats the key
+// before it.
+__global__ void k_toggle_rank(const uint64_t *keys, int64_t n, const int64_t *pos,
+                              const uint32_t *src, int64_t *rank)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const bool first = t == 0 || keys[t] != keys[t - 1];
+    rank[src[t]] = pos[t] - (first ? 0 : 1);
 }
 
 // The sorted distinct toggle positions E (row << xbits | x) cut every row
 // into elementary pieces [E[k], E[k+1]) of constant polygon set.  Covered
-// interval m spans pieces [ka, kb); the depth of piece k is the number of
-// intervals spanning it (difference array, scanned later).
-__global__ void k_interval_span(const uint64_t *tkey, int64_t nint, const uint64_t *E,
-                                const int64_t *nE, int64_t *ika, int64_t *cnt, int64_t *diff)
+// interval m spans pieces [ka, kb), the indices in E of its two toggles; the
+// depth of piece k is the number of intervals spanning it (difference array,
+// scanned later).
+__global__ void k_interval_span(const int64_t *rank, int64_t nint, int64_t *ika, int64_t *cnt,
+                                int64_t *diff)
 {
     int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= nint) return;
-    int64_t ne = *nE;
-    int64_t ka = lower_bound_key(E, ne, tkey[2 * m]);
-    int64_t kb = lower_bound_key(E, ne, tkey[2 * m + 1]);
+    const int64_t ka = rank[2 * m], kb = rank[2 * m + 1];
     ika[m] = ka;
     cnt[m] = kb - ka;
     atomicAdd((unsigned long long *)&diff[ka], 1ull);
@@ -944,20 +953,33 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     RC(B.alloc(&mm, NP));
     HIP_OK(hipMemsetAsync(diff, 0, sizeof(int64_t) * (NP + 1), st));
     if (NT) {
+        if (NT >= ((int64_t)1 << 32)) return SBA_ELIMIT;
+        // sorted with each toggle's slot as payload, so that every toggle
+        // learns its index in E without a search
+        uint32_t *src = nullptr;
+        int64_t *rank = nullptr;
+        RC(B.alloc(&src, NT));
+        RC(B.alloc(&rank, NT));
         HIP_OK(hipMemcpyAsync(E, tkey, sizeof(uint64_t) * NT, hipMemcpyDeviceToDevice, st));
-        RC(radix_sort_u64_ws(&E, nullptr, NT, rxbits, B.ws));
+        hipLaunchKernelGGL(k_iota_u32, dim3(grid_for(NT)), dim3(256), 0, st, src, NT);
+        HIP_OK(hipGetLastError());
+        RC(radix_sort_u64_ws(&E, &src, NT, rxbits, B.ws));
         hipLaunchKernelGGL(k_flag_new, dim3(grid_for(NT)), dim3(256), 0, st, E, NT, pos);
         HIP_OK(hipGetLastError());
         RC(scan_exclusive_i64(pos, pos, NT, tot + 1, st, &B.ws));
         uint64_t *Eu = nullptr;
         RC(B.alloc(&Eu, NT));
         hipLaunchKernelGGL(k_unique_emit, dim3(grid_for(NT)), dim3(256), 0, st, E, NT, pos, Eu);
+        hipLaunchKernelGGL(k_toggle_rank, dim3(grid_for(NT)), dim3(256), 0, st, E, NT, pos, src,
+                           rank);
         HIP_OK(hipGetLastError());
         B.release(E);
+        B.release(src);
         E = Eu;
-        hipLaunchKernelGGL(k_interval_span, dim3(grid_for(NI)), dim3(256), 0, st, tkey, NI, E,
-                           tot + 1, ika, xoff, diff);
+        hipLaunchKernelGGL(k_interval_span, dim3(grid_for(NI)), dim3(256), 0, st, rank, NI, ika,
+                           xoff, diff);
         HIP_OK(hipGetLastError());
+        B.release(rank);
     }
     B.release(pos);
     RC(scan_exclusive_i64(diff, dex, NP, tot + 2, st, &B.ws));
