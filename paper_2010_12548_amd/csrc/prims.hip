@@ -302,23 +302,21 @@ int scan_exclusive_i64_multi(int m, const int64_t *const *in, int64_t *const *ou
 #define RS_MID (64 << 20)
 #define RS_RADIX 256
 
-// per block and digit: count, laid out digit-major (hist[d * nblocks + b]);
-// the digit totals are summed into dtot (zeroed before the pass).  A
-// workgroup counts `span` consecutive tiles, TPW at a time with every key of
-// the TPW tiles loaded before any is counted, and adds its digit totals to
-// dtot once: with 256 device-wide atomics per tile the pass read 1e8 keys at
-// about 1.5 TB/s.
+// per block and digit: count, laid out digit-major (hist[d * nblocks + b]).
+// A workgroup counts `span` consecutive tiles, TPW at a time with every key
+// of the TPW tiles loaded before any is counted.  No digit totals are formed
+// here: each row scan below leaves its digit's total, and the scatter adds
+// the totals of the lower digits itself, so the pass needs no device-wide
+// atomics and no zeroed counters.
 template <int ROUNDS>
 __global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const uint64_t *keys, int64_t n, int shift,
-                                                      int64_t *hist, int64_t nblocks, int64_t span,
-                                                      unsigned long long *dtot)
+                                                      int64_t *hist, int64_t nblocks, int64_t span)
 {
     constexpr int RS_TILE = RS_BLOCK * ROUNDS, TPW = 16 / ROUNDS;
     __shared__ uint32_t h[TPW][RS_RADIX];
     const int d = threadIdx.x;
     const int64_t bfirst = (int64_t)blockIdx.x * span;
     const int64_t blast = min(bfirst + span, nblocks);
-    unsigned long long tot = 0;
     for (int64_t b0 = bfirst; b0 < blast; b0 += TPW) {
 #pragma unroll
         for (int t = 0; t < TPW; t++) h[t][d] = 0;
@@ -336,14 +334,39 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const uint64_t *keys, int6
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < TPW; t++) {
-            if (b0 + t < blast) {
-                const uint32_t c = h[t][d];
-                hist[(int64_t)d * nblocks + b0 + t] = c;
-                tot += c;
-            }
+            if (b0 + t < blast) hist[(int64_t)d * nblocks + b0 + t] = h[t][d];
         }
     }
-    if (tot) atomicAdd(&dtot[d], tot);
+}
+
+// In place, one workgroup per digit d: the exclusive scan of digit d's block
+// counts; the digit's total goes to rowtot[d].
+__global__ __launch_bounds__(RS_BLOCK) void k_rs_rowscan(int64_t *hist, int64_t nblocks,
+                                                         int64_t *rowtot)
+{
+    const int d = blockIdx.x;
+    int64_t *row = hist + (int64_t)d * nblocks;
+    int64_t carry = 0;
+    for (int64_t c0 = 0; c0 < nblocks; c0 += RS_BLOCK * SCAN_ITEMS) {
+        const int64_t b0 = c0 + (int64_t)threadIdx.x * SCAN_ITEMS;
+        int64_t v[SCAN_ITEMS];
+        int64_t run = 0;
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; k++) {
+            v[k] = b0 + k < nblocks ? row[b0 + k] : 0;
+            run += v[k];
+        }
+        int64_t excl;
+        const int64_t tot = block_excl_scan<int64_t>(run, &excl);
+        excl += carry;
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; k++) {
+            if (b0 + k < nblocks) row[b0 + k] = excl;
+            excl += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) rowtot[d] = carry;
 }
 
 // Scatter offsets in place, one workgroup per digit d: the keys of all lower
@@ -394,15 +417,22 @@ template <bool HAS_VALS, int ROUNDS>
 __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const uint64_t *keys, const uint32_t *vals,
                                                          uint64_t *okeys, uint32_t *ovals,
                                                          int64_t n, int shift,
-                                                         const int64_t *goff, int64_t nblocks)
+                                                         const int64_t *goff, int64_t nblocks,
+                                                         const int64_t *rowtot)
 {
     constexpr int RS_ROUNDS = ROUNDS, RS_TILE = RS_BLOCK * ROUNDS;
     __shared__ uint32_t wcnt[RS_WAVES][RS_RADIX];
     __shared__ uint32_t bdoff[RS_RADIX];
+    __shared__ int64_t dbase[RS_RADIX];  // keys of all lower digits
     __shared__ uint64_t skeys[RS_TILE];
     __shared__ uint32_t svals[HAS_VALS ? RS_TILE : 1];
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    {
+        int64_t below;
+        block_excl_scan<int64_t>(rowtot[threadIdx.x], &below);
+        dbase[threadIdx.x] = below;
+    }
     for (int k = threadIdx.x; k < RS_WAVES * RS_RADIX; k += RS_BLOCK) (&wcnt[0][0])[k] = 0;
     __syncthreads();
 
@@ -465,7 +495,7 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const uint64_t *keys, c
     for (int i = threadIdx.x; i < tn; i += RS_BLOCK) {
         uint64_t key = skeys[i];
         uint32_t d = (uint32_t)(key >> shift) & 0xffu;
-        int64_t g = goff[(int64_t)d * nblocks + blockIdx.x] + (i - (int64_t)bdoff[d]);
+        int64_t g = dbase[d] + goff[(int64_t)d * nblocks + blockIdx.x] + (i - (int64_t)bdoff[d]);
         okeys[g] = key;
         if (HAS_VALS) ovals[g] = svals[i];
     }
@@ -478,33 +508,31 @@ static int64_t rs_blocks(int64_t n) { return (n + RS_BLOCK * rs_rounds(n) - 1) /
 // one pass over digit (keys >> shift) & 255
 template <int ROUNDS>
 static int rs_pass_t(const uint64_t *ka, const uint32_t *va, uint64_t *kb, uint32_t *vb, int64_t n,
-                     int shift, int64_t *goff, int64_t nblocks, unsigned long long *dtot,
-                     hipStream_t st)
+                     int shift, int64_t *goff, int64_t nblocks, int64_t *rowtot, hipStream_t st)
 {
     // tiles per counting workgroup: 16 keys a thread, and at most about 2048
     // workgroups
     constexpr int64_t TPW = 16 / ROUNDS;
     const int64_t span = TPW * std::max<int64_t>(1, (nblocks + TPW * 2048 - 1) / (TPW * 2048));
     hipLaunchKernelGGL(k_rs_hist<ROUNDS>, dim3((unsigned)((nblocks + span - 1) / span)),
-                       dim3(RS_BLOCK), 0, st, ka, n, shift, goff, nblocks, span, dtot);
-    hipLaunchKernelGGL(k_rs_offsets, dim3(RS_RADIX), dim3(RS_BLOCK), 0, st, goff, nblocks, dtot);
+                       dim3(RS_BLOCK), 0, st, ka, n, shift, goff, nblocks, span);
+    hipLaunchKernelGGL(k_rs_rowscan, dim3(RS_RADIX), dim3(RS_BLOCK), 0, st, goff, nblocks, rowtot);
     if (va)
         hipLaunchKernelGGL((k_rs_scatter<true, ROUNDS>), dim3((unsigned)nblocks), dim3(RS_BLOCK), 0,
-                           st, ka, va, kb, vb, n, shift, goff, nblocks);
+                           st, ka, va, kb, vb, n, shift, goff, nblocks, rowtot);
     else
         hipLaunchKernelGGL((k_rs_scatter<false, ROUNDS>), dim3((unsigned)nblocks), dim3(RS_BLOCK), 0,
-                           st, ka, va, kb, vb, n, shift, goff, nblocks);
+                           st, ka, va, kb, vb, n, shift, goff, nblocks, rowtot);
     return hipGetLastError() == hipSuccess ? 0 : SBA_EDEVICE;
 }
 
 static int rs_pass(const uint64_t *ka, const uint32_t *va, uint64_t *kb, uint32_t *vb, int64_t n,
-                   int shift, int64_t *goff, int64_t nblocks, unsigned long long *dtot,
-                   hipStream_t st)
+                   int shift, int64_t *goff, int64_t nblocks, int64_t *rowtot, hipStream_t st)
 {
     const int r = rs_rounds(n);
-    if (r == 4) return rs_pass_t<4>(ka, va, kb, vb, n, shift, goff, nblocks, dtot, st);
-    if (r == 8) return rs_pass_t<8>(ka, va, kb, vb, n, shift, goff, nblocks, dtot, st);
-    return rs_pass_t<16>(ka, va, kb, vb, n, shift, goff, nblocks, dtot, st);
+    if (r == 4) return rs_pass_t<4>(ka, va, kb, vb, n, shift, goff, nblocks, rowtot, st);
+    if (r == 8) return rs_pass_t<8>(ka, va, kb, vb, n, shift, goff, nblocks, rowtot, st);
+    return rs_pass_t<16>(ka, va, kb, vb, n, shift, goff, nblocks, rowtot, st);
 }
 
 int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st,
@@ -514,19 +542,16 @@ int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStrea
     const int64_t nblocks = rs_blocks(n);
     uint64_t *k2 = nullptr;
     uint32_t *v2 = nullptr;
-    int64_t *goff = nullptr;
+    int64_t *goff = nullptr, *rowtot = nullptr;
     int rc = tmp_get(ws, &k2, n, st);
     if (!rc && vals) rc = tmp_get(ws, &v2, n, st);
     if (!rc) rc = tmp_get(ws, &goff, nblocks * RS_RADIX, st);
-    int passes = (bits + 7) / 8;
-    unsigned long long *dtot = nullptr;
-    if (!rc) rc = tmp_get(ws, &dtot, (int64_t)passes * RS_RADIX, st);
-    if (!rc && hipMemsetAsync(dtot, 0, sizeof(unsigned long long) * passes * RS_RADIX, st) != hipSuccess)
-        rc = SBA_EDEVICE;
+    if (!rc) rc = tmp_get(ws, &rowtot, RS_RADIX, st);
+    const int passes = (bits + 7) / 8;
     uint64_t *ka = keys, *kb = k2;
     uint32_t *va = vals, *vb = v2;
     for (int p = 0; p < passes && !rc; p++) {
-        rc = rs_pass(ka, va, kb, vb, n, 8 * p, goff, nblocks, dtot + RS_RADIX * p, st);
+        rc = rs_pass(ka, va, kb, vb, n, 8 * p, goff, nblocks, rowtot, st);
         if (rc) break;
         uint64_t *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
@@ -541,7 +566,7 @@ int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStrea
     tmp_put(ws, k2, st);
     tmp_put(ws, v2, st);
     tmp_put(ws, goff, st);
-    tmp_put(ws, dtot, st);
+    tmp_put(ws, rowtot, st);
     return rc;
 }
 
@@ -552,18 +577,16 @@ int radix_sort_u64_ws(uint64_t **keys, uint32_t **vals, int64_t n, int bits, Wor
     const int64_t nblocks = rs_blocks(n);
     uint64_t *k2 = nullptr;
     uint32_t *v2 = nullptr;
-    int64_t *goff = nullptr;
+    int64_t *goff = nullptr, *rowtot = nullptr;
     RC(ws.alloc(&k2, n));
     if (vals && *vals) RC(ws.alloc(&v2, n));
     RC(ws.alloc(&goff, nblocks * RS_RADIX));
+    RC(ws.alloc(&rowtot, RS_RADIX));
     const int passes = (bits + 7) / 8;
-    unsigned long long *dtot = nullptr;
-    RC(ws.alloc(&dtot, (int64_t)passes * RS_RADIX));
-    HIP_OK(hipMemsetAsync(dtot, 0, sizeof(unsigned long long) * passes * RS_RADIX, st));
     uint64_t *ka = *keys, *kb = k2;
     uint32_t *va = vals ? *vals : nullptr, *vb = v2;
     for (int p = 0; p < passes; p++) {
-        RC(rs_pass(ka, va, kb, vb, n, 8 * p, goff, nblocks, dtot + RS_RADIX * p, st));
+        RC(rs_pass(ka, va, kb, vb, n, 8 * p, goff, nblocks, rowtot, st));
         std::swap(ka, kb);
         std::swap(va, vb);
     }
@@ -572,7 +595,7 @@ int radix_sort_u64_ws(uint64_t **keys, uint32_t **vals, int64_t n, int bits, Wor
     ws.put(kb);
     if (vb) ws.put(vb);
     ws.put(goff);
-    ws.put(dtot);
+    ws.put(rowtot);
     *keys = ka;
     if (vals && *vals) *vals = va;
     return 0;
