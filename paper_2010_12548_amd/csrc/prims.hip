@@ -304,15 +304,16 @@ int scan_exclusive_i64_multi(int m, const int64_t *const *in, int64_t *const *ou
 
 // per block and digit: count, laid out digit-major (hist[d * nblocks + b]).
 // A workgroup counts `span` consecutive tiles, TPW at a time with every key
-// of the TPW tiles loaded before any is counted.  No digit totals are formed
+// of the TPW tiles loaded before any is counted (one tile a workgroup for
+// small sorts).  No digit totals are formed
 // here: each row scan below leaves its digit's total, and the scatter adds
 // the totals of the lower digits itself, so the pass needs no device-wide
 // atomics and no zeroed counters.
-template <int ROUNDS>
+template <int ROUNDS, int TPW>
 __global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const uint64_t *keys, int64_t n, int shift,
                                                       int64_t *hist, int64_t nblocks, int64_t span)
 {
-    constexpr int RS_TILE = RS_BLOCK * ROUNDS, TPW = 16 / ROUNDS;
+    constexpr int RS_TILE = RS_BLOCK * ROUNDS;
     __shared__ uint32_t h[TPW][RS_RADIX];
     const int d = threadIdx.x;
     const int64_t bfirst = (int64_t)blockIdx.x * span;
@@ -510,12 +511,18 @@ template <int ROUNDS>
 static int rs_pass_t(const uint64_t *ka, const uint32_t *va, uint64_t *kb, uint32_t *vb, int64_t n,
                      int shift, int64_t *goff, int64_t nblocks, int64_t *rowtot, hipStream_t st)
 {
-    // tiles per counting workgroup: 16 keys a thread, and at most about 2048
-    // workgroups
-    constexpr int64_t TPW = 16 / ROUNDS;
-    const int64_t span = TPW * std::max<int64_t>(1, (nblocks + TPW * 2048 - 1) / (TPW * 2048));
-    hipLaunchKernelGGL(k_rs_hist<ROUNDS>, dim3((unsigned)((nblocks + span - 1) / span)),
-                       dim3(RS_BLOCK), 0, st, ka, n, shift, goff, nblocks, span);
+    // tiles per counting workgroup: one while there are at most 2048 tiles
+    // (every tile its own workgroup), else 16 keys a thread and at most about
+    // 2048 workgroups
+    if (nblocks <= 2048) {
+        hipLaunchKernelGGL((k_rs_hist<ROUNDS, 1>), dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st,
+                           ka, n, shift, goff, nblocks, (int64_t)1);
+    } else {
+        constexpr int TPW = 16 / ROUNDS;
+        const int64_t span = TPW * ((nblocks + TPW * 2048 - 1) / (TPW * 2048));
+        hipLaunchKernelGGL((k_rs_hist<ROUNDS, TPW>), dim3((unsigned)((nblocks + span - 1) / span)),
+                           dim3(RS_BLOCK), 0, st, ka, n, shift, goff, nblocks, span);
+    }
     hipLaunchKernelGGL(k_rs_rowscan, dim3(RS_RADIX), dim3(RS_BLOCK), 0, st, goff, nblocks, rowtot);
     if (va)
         hipLaunchKernelGGL((k_rs_scatter<true, ROUNDS>), dim3((unsigned)nblocks), dim3(RS_BLOCK), 0,
