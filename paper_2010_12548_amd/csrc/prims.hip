@@ -424,15 +424,20 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const uint64_t *keys, c
     constexpr int RS_ROUNDS = ROUNDS, RS_TILE = RS_BLOCK * ROUNDS;
     __shared__ uint32_t wcnt[RS_WAVES][RS_RADIX];
     __shared__ uint32_t bdoff[RS_RADIX];
-    __shared__ int64_t dbase[RS_RADIX];  // keys of all lower digits
+    // output position of the block's first key of each digit, less that
+    // key's place in the staged tile
+    __shared__ int64_t dbase[RS_RADIX];
     __shared__ uint64_t skeys[RS_TILE];
     __shared__ uint32_t svals[HAS_VALS ? RS_TILE : 1];
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // digit threadIdx.x: the block's offset within the digit, and the keys of
+    // all lower digits
+    const int64_t myoff = goff[(int64_t)threadIdx.x * nblocks + blockIdx.x];
     {
         int64_t below;
         block_excl_scan<int64_t>(rowtot[threadIdx.x], &below);
-        dbase[threadIdx.x] = below;
+        dbase[threadIdx.x] = below + myoff;
     }
     for (int k = threadIdx.x; k < RS_WAVES * RS_RADIX; k += RS_BLOCK) (&wcnt[0][0])[k] = 0;
     __syncthreads();
@@ -478,6 +483,7 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const uint64_t *keys, c
         uint32_t excl;
         block_excl_scan<uint32_t>(run, &excl);
         bdoff[d] = excl;
+        dbase[d] -= (int64_t)excl;
     }
     __syncthreads();
 #pragma unroll
@@ -496,7 +502,7 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const uint64_t *keys, c
     for (int i = threadIdx.x; i < tn; i += RS_BLOCK) {
         uint64_t key = skeys[i];
         uint32_t d = (uint32_t)(key >> shift) & 0xffu;
-        int64_t g = dbase[d] + goff[(int64_t)d * nblocks + blockIdx.x] + (i - (int64_t)bdoff[d]);
+        int64_t g = dbase[d] + i;
         okeys[g] = key;
         if (HAS_VALS) ovals[g] = svals[i];
     }
