@@ -15,6 +15,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sba_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIBRARY names another build of this source to load instead (the
+# mutation tests load deliberately broken copies built in a temporary folder)
+_LIB_OVERRIDE = os.environ.get("ORACLE_LIBRARY")
 _lib = None
 
 _i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
@@ -36,9 +39,12 @@ def lib():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB):
-        build()
-    L = C.CDLL(_LIB)
+    if _LIB_OVERRIDE:
+        L = C.CDLL(_LIB_OVERRIDE)
+    else:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
     L.orc_cell_side.restype = C.c_int64
     L.orc_cell_side.argtypes = [C.c_int64]
     L.orc_raster_brute.restype = C.c_int
@@ -71,6 +77,16 @@ def lib():
     L.orc_invariant.argtypes = [C.c_void_p, _i32p, C.c_int64, _i64p, C.c_int]
     L.orc_invariant_all.restype = C.c_int
     L.orc_invariant_all.argtypes = [C.c_void_p, _i32p, C.c_int64, _i64p]
+    L.orc_invariant_at.restype = C.c_int
+    L.orc_invariant_at.argtypes = [C.c_void_p, _i32p, C.c_int64, C.c_int64, C.c_int, _i64p,
+                                   C.c_int]
+    L.orc_invariant_all_at.restype = C.c_int
+    L.orc_invariant_all_at.argtypes = [C.c_void_p, _i32p, C.c_int64, C.c_int64, C.c_int, _i64p]
+    L.orc_seg_within.restype = C.c_int
+    L.orc_seg_within.argtypes = [C.c_int64] * 7 + [C.c_int]
+    L.orc_near_boundary.restype = C.c_int
+    L.orc_near_boundary.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_int64,
+                                    C.c_int]
     L.orc_hilbert_d.restype = C.c_uint64
     L.orc_hilbert_d.argtypes = [C.c_int, C.c_int64, C.c_int64]
     L.orc_hilbert_level.restype = C.c_int
@@ -130,6 +146,16 @@ def join_pairs(a: "Approx", b: "Approx"):
     pa, pb, cells = np.zeros(max(n, 1), np.int32), np.zeros(max(n, 1), np.int32), np.zeros(max(n, 1), np.int64)
     lib().orc_join_pairs(a._h, b._h, n, pa, pb, cells)
     return pa[:n], pb[:n], cells[:n]
+
+
+def seg_within(p, a, b, eps: int, half: bool = False) -> bool:
+    """Is point p within eps (half: eps/2) of the closed segment a-b?  Exact
+    (Sec. 2.2: the distance bound every misclassified point must meet)."""
+    r = lib().orc_seg_within(int(p[0]), int(p[1]), int(a[0]), int(a[1]), int(b[0]), int(b[1]),
+                             int(eps), 1 if half else 0)
+    if r < 0:
+        raise ValueError("coordinates or eps out of range")
+    return bool(r)
 
 
 def hilbert_d(L: int, i: int, j: int) -> int:
@@ -207,15 +233,40 @@ class Approx:
         """Exact per-polygon COUNT and SUM by the crossing-number rule."""
         return self._agg(lib().orc_exact_join, xy, vals, nthreads)
 
-    def invariant(self, xy, nthreads: int = 0, exhaustive: bool = False) -> dict:
+    def invariant(self, xy, nthreads: int = 0, exhaustive: bool = False,
+                  check_eps: int | None = None, half: bool | None = None) -> dict:
+        """Points misclassified by the approximation ("differ"), those farther
+        than the distance bound from the polygon's boundary ("far", must be 0),
+        false negatives and exact inside pairs.  The bound is the build's eps
+        (eps/2 for a centre-sampled approximation) unless check_eps / half
+        name another one."""
         xy = np.ascontiguousarray(xy, np.int32)
         out = np.zeros(4, np.int64)
-        if exhaustive:
-            lib().orc_invariant_all(self._h, xy, xy.shape[0] // 2, out)
+        n = xy.shape[0] // 2
+        if check_eps is None and half is None:
+            if exhaustive:
+                lib().orc_invariant_all(self._h, xy, n, out)
+            else:
+                lib().orc_invariant(self._h, xy, n, out, int(nthreads))
         else:
-            lib().orc_invariant(self._h, xy, xy.shape[0] // 2, out, int(nthreads))
+            ce = self.eps if check_eps is None else int(check_eps)
+            hf = (1 if self.centre else 0) if half is None else (1 if half else 0)
+            if exhaustive:
+                lib().orc_invariant_all_at(self._h, xy, n, ce, hf, out)
+            else:
+                lib().orc_invariant_at(self._h, xy, n, ce, hf, out, int(nthreads))
         return {"differ": int(out[0]), "far": int(out[1]), "false_neg": int(out[2]),
                 "inside": int(out[3])}
+
+    def near_boundary(self, p: int, x: int, y: int, eps: int | None = None,
+                      half: bool = False) -> bool:
+        """Is (x, y) within eps (default: the build's; half: eps/2) of the
+        boundary of polygon p?"""
+        r = lib().orc_near_boundary(self._h, int(p), int(x), int(y),
+                                    self.eps if eps is None else int(eps), 1 if half else 0)
+        if r < 0:
+            raise ValueError("no such polygon")
+        return bool(r)
 
     def union_box(self):
         """(i0, j0, w, h): the cell box of the union of all approximations."""

@@ -187,38 +187,40 @@ static int cell_in_boundary(const polyset *ps, int32_t p, int64_t s, int64_t i, 
     return 0;
 }
 
-/* exact: squared distance from (px,py) to the closed segment a-b is <= e2 */
-static int seg_within(int64_t px, int64_t py, int64_t ax, int64_t ay,
-                      int64_t bx, int64_t by, i128 e2)
+/* Exact test k * dist(p, [a,b])^2 <= eps^2 for the closed segment a-b, with
+ * k = 1 (distance at most eps) or k = 4 (distance at most eps/2).
+ *
+ * With v = b - a and w = p - a, the closest point of the segment is a when
+ * w.v <= 0, b when w.v >= |v|^2, and otherwise the foot of the perpendicular,
+ * at distance |v x w| / |v|.  The interior case is compared squared and
+ * multiplied out: k (v x w)^2 <= eps^2 |v|^2.  Coordinates are below 2^30 in
+ * magnitude, so every difference is below 2^31, |v x w| < 2^63,
+ * k (v x w)^2 < 2^128 and eps^2 |v|^2 < 2^56 * 2^63: both sides fit an
+ * unsigned 128-bit integer, and the endpoint cases fit int128. */
+static int seg_within_k(int64_t px, int64_t py, int64_t ax, int64_t ay,
+                        int64_t bx, int64_t by, int64_t eps, int k)
 {
+    typedef unsigned __int128 u128;
     i128 vx = bx - ax, vy = by - ay, wx = px - ax, wy = py - ay;
+    i128 e2 = (i128)eps * eps;
     i128 t = wx * vx + wy * vy;
     i128 l2 = vx * vx + vy * vy;
-    if (t <= 0) return wx * wx + wy * wy <= e2;
+    if (t <= 0) return k * (wx * wx + wy * wy) <= e2;
     if (t >= l2) {
         i128 ux = px - bx, uy = py - by;
-        return ux * ux + uy * uy <= e2;
+        return k * (ux * ux + uy * uy) <= e2;
     }
-    i128 cr = vx * wy - vy * wx;                 /* |cr| / sqrt(l2) = distance */
-    return cr * cr <= e2 * l2;
+    i128 cr = vx * wy - vy * wx;
+    u128 c = (u128)(cr < 0 ? -cr : cr);
+    return (u128)k * (c * c) <= (u128)e2 * (u128)l2;
 }
 
-static int near_boundary(const polyset *ps, int32_t p, int64_t px, int64_t py, int64_t eps)
+/* p within eps (half = 0) or eps/2 (half = 1) of some edge of polygon p */
+static int near_boundary(const polyset *ps, int32_t p, int64_t px, int64_t py, int64_t eps,
+                         int half)
 {
-    i128 e2 = (i128)eps * eps;
     FOR_EACH_EDGE(ps, p, x1, y1, x2, y2, {
-        if (seg_within(px, py, x1, y1, x2, y2, e2)) return 1;
-    })
-    return 0;
-}
-
-/* within eps/2 of the boundary: distance of the doubled point to the doubled
- * polygon within eps */
-static int near_boundary_half(const polyset *ps, int32_t p, int64_t px, int64_t py, int64_t eps)
-{
-    i128 e2 = (i128)eps * eps;
-    FOR_EACH_EDGE(ps, p, x1, y1, x2, y2, {
-        if (seg_within(2 * px, 2 * py, 2 * x1, 2 * y1, 2 * x2, 2 * y2, e2)) return 1;
+        if (seg_within_k(px, py, x1, y1, x2, y2, eps, half ? 4 : 1)) return 1;
     })
     return 0;
 }
@@ -435,7 +437,7 @@ static int build_rows(const polyset *ps, int32_t p, int64_t s, int mode, prows *
     free(cr.a);
     if (err) { free(iv.a); return -1; }
 
-    qsort(iv.a, (size_t)iv.n, sizeof(ivl), ivl_cmp);
+    if (iv.n > 1) qsort(iv.a, (size_t)iv.n, sizeof(ivl), ivl_cmp);
     int64_t nrows = out->cj1 - out->cj0 + 1;
     out->row_off = (int64_t *)calloc((size_t)nrows + 1, sizeof(int64_t));
     out->x0 = (int64_t *)malloc((size_t)(iv.n ? iv.n : 1) * sizeof(int64_t));
@@ -726,13 +728,17 @@ int orc_exact_join(const orc_approx *a, const int32_t *xy, const int64_t *vals, 
     return nt;
 }
 
-/* Invariant check over the given points.  out[0] = (point, polygon) pairs
- * where approximate and exact membership differ; out[1] = such pairs farther
- * than eps (centre-sampled: eps/2) from the boundary of P (must be 0);
- * out[2] = false negatives, i.e. p inside P with cell(p) not in the
- * approximation (must be 0 unless centre-sampled); out[3] = pairs inside P
- * (exact). */
-int orc_invariant(const orc_approx *a, const int32_t *xy, int64_t n, int64_t *out, int nthreads)
+/* Invariant check over the given points (Sec. 2.2, Hausdorff
+ * eps-approximation), with the distance bound given apart from the build:
+ * out[0] = (point, polygon) pairs where approximate and exact membership
+ * differ; out[1] = such pairs farther than check_eps (half = 1: farther than
+ * check_eps / 2) from the boundary of P; out[2] = false negatives, i.e. p
+ * inside P with cell(p) not in the approximation; out[3] = pairs inside P
+ * (exact).  Candidate polygons come from the bucket filter, which holds every
+ * polygon whose cell box contains cell(p); a point outside a polygon's cell
+ * box is outside both the polygon and its approximation. */
+int orc_invariant_at(const orc_approx *a, const int32_t *xy, int64_t n, int64_t check_eps,
+                     int half, int64_t *out, int nthreads)
 {
     int nt = nthreads_of(nthreads);
     int64_t diff = 0, far = 0, fneg = 0, ins = 0;
@@ -749,9 +755,7 @@ int orc_invariant(const orc_approx *a, const int32_t *xy, int64_t n, int64_t *ou
             ins += ex;
             if (ap != ex) {
                 diff++;
-                if (a->mode == ORC_CENTRE ? !near_boundary_half(&a->ps, p, px, py, a->eps)
-                                          : !near_boundary(&a->ps, p, px, py, a->eps))
-                    far++;
+                if (!near_boundary(&a->ps, p, px, py, check_eps, half)) far++;
                 if (ex && !ap) fneg++;
             }
         }
@@ -760,8 +764,17 @@ int orc_invariant(const orc_approx *a, const int32_t *xy, int64_t n, int64_t *ou
     return 0;
 }
 
+/* The invariant the approximation must satisfy: misclassified points within
+ * eps of the boundary (centre-sampled: within eps/2), no false negatives
+ * (centre-sampled: allowed).  out[1] must be 0; see orc_invariant_at. */
+int orc_invariant(const orc_approx *a, const int32_t *xy, int64_t n, int64_t *out, int nthreads)
+{
+    return orc_invariant_at(a, xy, n, a->eps, a->mode == ORC_CENTRE, out, nthreads);
+}
+
 /* Exhaustive version for tiny inputs: every polygon, no candidate filter. */
-int orc_invariant_all(const orc_approx *a, const int32_t *xy, int64_t n, int64_t *out)
+int orc_invariant_all_at(const orc_approx *a, const int32_t *xy, int64_t n, int64_t check_eps,
+                         int half, int64_t *out)
 {
     int64_t diff = 0, far = 0, fneg = 0, ins = 0;
     for (int64_t k = 0; k < n; k++) {
@@ -773,15 +786,41 @@ int orc_invariant_all(const orc_approx *a, const int32_t *xy, int64_t n, int64_t
             ins += ex;
             if (ap != ex) {
                 diff++;
-                if (a->mode == ORC_CENTRE ? !near_boundary_half(&a->ps, p, px, py, a->eps)
-                                          : !near_boundary(&a->ps, p, px, py, a->eps))
-                    far++;
+                if (!near_boundary(&a->ps, p, px, py, check_eps, half)) far++;
                 if (ex && !ap) fneg++;
             }
         }
     }
     out[0] = diff; out[1] = far; out[2] = fneg; out[3] = ins;
     return 0;
+}
+
+int orc_invariant_all(const orc_approx *a, const int32_t *xy, int64_t n, int64_t *out)
+{
+    return orc_invariant_all_at(a, xy, n, a->eps, a->mode == ORC_CENTRE, out);
+}
+
+/* The distance predicate itself, for its pins: 1 if (px,py) lies within eps
+ * (half = 1: eps/2) of the closed segment (ax,ay)-(bx,by), by the exact test
+ * above.  Coordinates must satisfy |c| < 2^30 and 0 <= eps <= 2^28, else -1. */
+int orc_seg_within(int64_t px, int64_t py, int64_t ax, int64_t ay, int64_t bx, int64_t by,
+                   int64_t eps, int half)
+{
+    const int64_t lim = (int64_t)1 << 30;
+    int64_t c[6] = {px, py, ax, ay, bx, by};
+    for (int t = 0; t < 6; t++)
+        if (c[t] <= -lim || c[t] >= lim) return -1;
+    if (eps < 0 || eps > ((int64_t)1 << 28)) return -1;
+    return seg_within_k(px, py, ax, ay, bx, by, eps, half ? 4 : 1);
+}
+
+/* 1 if (px,py) lies within eps (half: eps/2) of the boundary of polygon p of
+ * the approximation's polygon set (any edge of any ring), else 0. */
+int orc_near_boundary(const orc_approx *a, int32_t p, int64_t px, int64_t py, int64_t eps,
+                      int half)
+{
+    if (p < 0 || p >= a->n_polys) return -1;
+    return near_boundary(&a->ps, p, px, py, eps, half);
 }
 
 /* ------------------------------------------------------------------ */

@@ -256,10 +256,9 @@ def test_eps_invariant_stars(orc, eps):
     assert inv2 == inv
 
 
-def test_invariant_detects_planted_far_point(orc):
-    # a point farther than eps from the boundary, counted by the approximation
-    # only if the raster were wrong: shrink the polygon by hand and check that
-    # the check flags the mismatch between the two sets
+def test_invariant_counts_near_mismatch_as_near(orc):
+    # a point deep inside is not a mismatch; a point just outside the square,
+    # in a boundary cell, is a mismatch within eps (distance 3 <= 10)
     big = polygons_from_rings([[np.array([[0, 0], [100, 0], [100, 100], [0, 100]])]])
     A = orc.Approx(big, 10)
     far_in = np.array([50, 50], np.int32)
@@ -267,6 +266,215 @@ def test_invariant_detects_planted_far_point(orc):
     near_out = np.array([103, 50], np.int32)
     inv = A.invariant(near_out, exhaustive=True)
     assert inv["differ"] == 1 and inv["far"] == 0
+    # the same mismatch checked against a bound below its distance is far
+    assert A.invariant(near_out, exhaustive=True, check_eps=2)["far"] == 1
+    assert A.invariant(near_out, exhaustive=True, check_eps=3)["far"] == 0
+
+
+# ---------------------------------------------------------------- distance predicate
+#
+# The invariant's distance test (Sec. 2.2) pinned on its own: hand-derived
+# distances with ties at the bound (tests/golden/distances.yaml), and a
+# brute force by the clamped projection onto the segment in exact rationals
+# (a different formulation from the oracle's cross-product comparison).
+
+DISTANCES = os.path.join(os.path.dirname(__file__), "golden", "distances.yaml")
+
+
+def _distance_cases():
+    with open(DISTANCES) as f:
+        return yaml.safe_load(f)["cases"]
+
+
+def _d2_projection(p, a, b):
+    from fractions import Fraction
+    vx, vy = b[0] - a[0], b[1] - a[1]
+    wx, wy = p[0] - a[0], p[1] - a[1]
+    l2 = vx * vx + vy * vy
+    t = Fraction(0) if l2 == 0 else min(max(Fraction(wx * vx + wy * vy, l2), Fraction(0)), Fraction(1))
+    cx, cy = a[0] + t * vx, a[1] + t * vy
+    return (p[0] - cx) ** 2 + (p[1] - cy) ** 2
+
+
+@pytest.mark.parametrize("case", _distance_cases(), ids=lambda c: c["name"])
+def test_seg_within_hand_cases(orc, case):
+    p, a, b = case["p"], case["a"], case["b"]
+    assert _d2_projection(p, a, b) == case["d2"]          # the fixture's own derivation
+    for eps, want in case["full"]:
+        assert orc.seg_within(p, a, b, eps) is want, ("full", eps)
+        assert orc.seg_within(p, b, a, eps) is want        # orientation-free
+    for eps, want in case["half"]:
+        assert orc.seg_within(p, a, b, eps, half=True) is want, ("half", eps)
+        assert orc.seg_within(p, b, a, eps, half=True) is want
+
+
+def test_seg_within_matches_projection_brute_force(orc):
+    # random segments and points, including coordinates near +-2^30, each
+    # bound placed at the exact distance (tie) and one unit below it
+    import math
+    rng = np.random.default_rng(77)
+    lim = (1 << 30) - 1
+    n_checked = 0
+    for scale in (50, 5000, 1 << 20, lim):
+        for _ in range(300):
+            a = [int(v) for v in rng.integers(-scale, scale + 1, 2)]
+            b = [int(v) for v in rng.integers(-scale, scale + 1, 2)]
+            p = [int(v) for v in rng.integers(-scale, scale + 1, 2)]
+            d2 = _d2_projection(p, a, b)
+            for half in (False, True):
+                k = 4 if half else 1
+                # smallest integer eps with eps^2 >= k d2, and the one below
+                e = math.isqrt(int(k * d2))
+                while e * e < k * d2:
+                    e += 1
+                if e <= (1 << 28):
+                    assert orc.seg_within(p, a, b, e, half) is True
+                    n_checked += 1
+                if 1 <= e - 1 <= (1 << 28):
+                    assert orc.seg_within(p, a, b, e - 1, half) is False
+    assert n_checked > 1000
+
+
+def test_seg_within_rejects_out_of_range(orc):
+    with pytest.raises(ValueError):
+        orc.seg_within((1 << 30, 0), (0, 0), (1, 1), 5)
+    with pytest.raises(ValueError):
+        orc.seg_within((0, 0), (0, 0), (1, 1), (1 << 28) + 1)
+
+
+def _rect_dist2(x, y, x0, y0, x1, y1):
+    """Squared distance from lattice points to the boundary of the rectangle
+    [x0,x1] x [y0,y1]: clamped distance outside, nearest side inside."""
+    x = x.astype(np.int64)
+    y = y.astype(np.int64)
+    dx = np.maximum(np.maximum(x0 - x, x - x1), 0)
+    dy = np.maximum(np.maximum(y0 - y, y - y1), 0)
+    out = dx * dx + dy * dy
+    inside = (x > x0) & (x < x1) & (y > y0) & (y < y1)
+    m = np.minimum(np.minimum(x - x0, x1 - x), np.minimum(y - y0, y1 - y))
+    return np.where(inside, m * m, out)
+
+
+@pytest.mark.parametrize("check", [10, 9, 8, 7, 5, 3, 1])
+def test_invariant_far_count_rectangle_closed_form(orc, check):
+    # square [0,70]^2 at eps = 10 (s = 7): A(P) is the cells -1..10 in both
+    # axes, i.e. the points of [-7,77)^2; the exact set is [0,70)^2 (half-open
+    # crossing rule).  The mismatches are the points of the ring between, and
+    # those farther than `check` from the square's boundary are counted by
+    # the clamped distance -- none for check >= 10 (the largest is
+    # sqrt(7^2+7^2) < 10), some below
+    x0, y0, x1, y1 = 0, 0, 70, 70
+    A = orc.Approx(polygons_from_rings([[np.array([[x0, y0], [x1, y0], [x1, y1], [x0, y1]])]]), 10)
+    assert A.s == 7
+    xy = lattice(-14, 84)
+    px, py = xy[0::2], xy[1::2]
+    approx = (px >= -7) & (px < 77) & (py >= -7) & (py < 77)
+    exact = (px >= x0) & (px < x1) & (py >= y0) & (py < y1)
+    mism = approx != exact
+    d2 = _rect_dist2(px, py, x0, y0, x1, y1)
+    want_far = int(np.count_nonzero(mism & (d2 > check * check)))
+    inv = A.invariant(xy, exhaustive=True, check_eps=check)
+    assert inv["differ"] == int(np.count_nonzero(mism))
+    assert inv["far"] == want_far
+    assert inv["false_neg"] == 0
+    assert A.invariant(xy, check_eps=check) == inv           # candidate filter agrees
+    if check >= 10:
+        assert want_far == 0
+    if check <= 9:
+        assert want_far > 0                                   # the bound bites
+
+
+@pytest.mark.parametrize("check", [10, 9, 8, 6, 4, 2])
+def test_invariant_far_count_centre_rectangle_closed_form(orc, check):
+    # square [3,66]^2 at eps = 10 (s = 7), centre-sampled: the cells whose
+    # centre 7i + 3.5 lies in [3,66) are i = 0..8, i.e. the points of
+    # [0,63)^2; exact [3,66)^2.  Mismatches lie within eps/2 = 5 (the corner
+    # point (0,0) is sqrt(18) from the corner (3,3)); at bound check/2 they
+    # are counted by the clamped distance
+    x0, y0, x1, y1 = 3, 3, 66, 66
+    polys = polygons_from_rings([[np.array([[x0, y0], [x1, y0], [x1, y1], [x0, y1]])]])
+    C = orc.Approx(polys, 10, centre=True)
+    xy = lattice(-14, 84)
+    px, py = xy[0::2], xy[1::2]
+    approx = (px >= 0) & (px < 63) & (py >= 0) & (py < 63)
+    exact = (px >= x0) & (px < x1) & (py >= y0) & (py < y1)
+    mism = approx != exact
+    d2 = _rect_dist2(px, py, x0, y0, x1, y1)
+    want_far = int(np.count_nonzero(mism & (4 * d2 > check * check)))
+    inv = C.invariant(xy, exhaustive=True, check_eps=check)   # half by default here
+    assert inv["differ"] == int(np.count_nonzero(mism))
+    assert inv["far"] == want_far
+    assert inv["false_neg"] == int(np.count_nonzero(exact & ~approx))
+    if check == 10:
+        assert want_far == 0
+    if check == 8:
+        assert want_far == 1                                  # only the point (0,0)
+
+
+@pytest.mark.parametrize("eps,check", [(64, 32), (64, 16), (23, 8)])
+def test_invariant_far_count_stars_brute_force(orc, eps, check):
+    # random stars: the far mismatches at a bound below eps, counted by a
+    # floating-point distance to every edge (cases within 1e-6 of the bound
+    # are left out of the comparison and must be rare)
+    rng = np.random.default_rng(eps * 10 + check)
+    polys = star_polygons(4, 12, 30.0, 300.0, 700, 500 + eps)
+    xy = rng.integers(-300, 1000, size=2 * 8000).astype(np.int32)
+    A = orc.Approx(polys, eps)
+    inv = A.invariant(xy, exhaustive=True, check_eps=check)
+    assert A.invariant(xy, exhaustive=True)["far"] == 0
+    P, R, X0, X1 = A.intervals()
+    pts = xy.reshape(-1, 2).astype(np.float64)
+    i = np.floor_divide(xy[0::2].astype(np.int64), A.s)
+    j = np.floor_divide(xy[1::2].astype(np.int64), A.s)
+    far = amb = diff = 0
+    for p in range(polys.n_polys):
+        ring = polys.rings_of(p)[0].astype(np.float64)
+        sel = P == p
+        ap = np.zeros(len(pts), bool)
+        for r, a0, a1 in zip(R[sel], X0[sel], X1[sel]):
+            ap |= (j == r) & (i >= a0) & (i < a1)
+        # exact membership of a mismatch candidate: the oracle's exact join
+        # of that one point (the crossing rule is pinned by the closed forms
+        # above; the distance is what this test checks)
+        a_ = ring
+        b_ = np.roll(ring, -1, axis=0)
+        v = b_ - a_
+        l2 = (v * v).sum(1)
+        for k in range(len(pts)):
+            ex = A.exact(xy[2 * k:2 * k + 2])[0][p] == 1
+            if ex == ap[k]:
+                continue
+            diff += 1
+            w = pts[k] - a_
+            t = np.clip((w * v).sum(1) / np.where(l2 > 0, l2, 1), 0.0, 1.0)
+            d = np.sqrt((((a_ + t[:, None] * v) - pts[k]) ** 2).sum(1)).min()
+            if abs(d - check) < 1e-6:
+                amb += 1
+            elif d > check:
+                far += 1
+    assert amb <= 2
+    assert diff == inv["differ"]
+    assert abs(inv["far"] - far) <= amb
+    assert far > 0
+
+
+def test_centre_large_extent_within_half_eps(orc):
+    # a triangle spanning the whole accepted coordinate range, centre-sampled
+    # at a large eps: every mismatch within eps/2 (coordinates near 2^30
+    # make the squared cross products exceed 2^120)
+    lim = (1 << 30) - 1
+    tri = polygons_from_rings([[np.array([[-lim, -lim], [lim, -lim], [0, lim]])]])
+    eps = 1 << 26
+    C = orc.Approx(tri, eps, centre=True)
+    rng = np.random.default_rng(5)
+    xy = rng.integers(-lim, lim + 1, size=2 * 40000).astype(np.int32)
+    inv = C.invariant(xy, exhaustive=True)
+    assert inv["far"] == 0 and inv["differ"] > 0
+    A = orc.Approx(tri, eps)
+    inv = A.invariant(xy, exhaustive=True)
+    assert inv["far"] == 0 and inv["false_neg"] == 0 and inv["differ"] > 0
+    # at a bound of eps/8 some mismatches of the centre cells are far
+    assert C.invariant(xy, exhaustive=True, check_eps=eps // 8)["far"] > 0
 
 
 # ---------------------------------------------------------------- nested grids
@@ -553,9 +761,11 @@ def test_centre_within_half_eps(orc, eps):
     assert inv["differ"] > 0 and inv["false_neg"] > 0
     assert C.invariant(xy) == inv
     # the conservative approximation of the same polygons is further off: its
-    # misclassified points are not all within eps/2 (so the bound is a pin)
+    # misclassified points are not all within eps/2, so the check at eps/2
+    # does report far points when they exist
     A = orc.Approx(polys, eps)
     assert A.invariant(xy, exhaustive=True)["differ"] > inv["differ"]
+    assert A.invariant(xy, exhaustive=True, half=True)["far"] > 0
 
 
 def test_centre_partition_counts_each_point_once(orc):
