@@ -756,6 +756,13 @@ template <bool VALS, int SETS>
 __device__ __forceinline__ void add_short(uint32_t sc, int64_t v, const Agg &A, uint32_t np,
                                           const Lds16 &L)
 {
+    if (SETS == SETS_BINS) {
+        // polygon p has bin p and set k bin np + k: both are bin sc - 1
+        if (sc - 1u >= np + A.n_sets) return;
+        atomicAdd(&L.cnt[sc - 1], 1u);
+        if (VALS) atomicAdd(&L.sum[sc - 1], (unsigned long long)v);
+        return;
+    }
     if (sc == 0) return;
     if (sc <= np) {
         atomicAdd(&L.cnt[sc - 1], 1u);
@@ -847,29 +854,72 @@ __global__ __launch_bounds__(BLOCK) void k_probe_grid16(const int4 *__restrict__
     const uint32_t m = (1u << fl) - 1u, mq = (1u << qs) - 1u;
     const int64_t npairs = n >> 1;
     const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    const int64_t trip = stride * PROBE_UNROLL;
     const int64_t tlast = npairs - 1;
     const uint32_t ox = (uint32_t)g.ox, oy = (uint32_t)g.oy;
-    for (int64_t t0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t0 < npairs;
-         t0 += stride * PROBE_UNROLL) {
-        // loads without branches: a lane past the end re-reads the last pair
-        // (in bounds, as t0 < npairs) and drops it below
-        v4i_t q[PROBE_UNROLL];
-        v2l_t vv[PROBE_UNROLL];
-        bool in[PROBE_UNROLL];
+    // Three-stage software pipeline.  Trip r covers pairs [r trip, (r + 1) trip)
+    // of the whole grid, PROBE_UNROLL pairs per lane, and pass r of the loop
+    //   C  adds the points of trip r - 2 (their fine-block codes have arrived),
+    //   B  reads the sub-tile entries of trip r - 1 and issues its fine-block
+    //      gathers and its value loads,
+    //   A  looks up the LDS directory for trip r (its coordinates have
+    //      arrived) and issues its sub-tile gathers,
+    // and then issues the coordinate loads of trip r + 1.  Vector memory
+    // loads complete in issue order, so each pass waits once for the loads of
+    // the pass before (the coordinates last): the latencies of the stream and
+    // of both gather levels overlap instead of adding up.  Loads have no
+    // branches: a lane past the end re-reads the last pair (in bounds, as the
+    // loop runs only when npairs > 0) or element 0 of a gathered array, and
+    // drops the point.
+    // Without sub-tiles there is no stage B: the fine blocks are gathered
+    // straight after the directory, and C adds trip r - 1.
+    constexpr int K = 2 * PROBE_UNROLL;
+    constexpr int LAG = SUB ? 2 : 1;
+    const int64_t T = (npairs + trip - 1) / trip;  // trips, the same for every lane
+    const int64_t tb = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    v4i_t q[PROBE_UNROLL];                         // coordinates of trip r
+    bool in[PROBE_UNROLL];
+    uint32_t seB[K], fbB[K], vB[K], loB[K];        // trip r - 1 (seB: sub-tile entries)
+    uint32_t fC[K], fbC[K], vC[K];                 // trip r - 2 (fC: fine-block codes)
+    v2l_t valC[PROBE_UNROLL];
 #pragma unroll
-        for (int u = 0; u < PROBE_UNROLL; u++) {
-            int64_t t = t0 + (int64_t)u * stride;
-            in[u] = t < npairs;
-            int64_t tc = in[u] ? t : tlast;
-            q[u] = __builtin_nontemporal_load((const v4i_t *)(xy4 + tc));
-            vv[u] = VALS ? __builtin_nontemporal_load((const v2l_t *)(v2 + tc)) : v2l_t{0, 0};
+    for (int k = 0; k < K; k++) {
+        seB[k] = vB[k] = loB[k] = 0;
+        fC[k] = vC[k] = 0;
+        fbB[k] = fbC[k] = ~0u;
+    }
+#pragma unroll
+    for (int u = 0; u < PROBE_UNROLL; u++) {
+        valC[u] = v2l_t{0, 0};
+        int64_t t = tb + (int64_t)u * stride;
+        in[u] = t < npairs;
+        q[u] = T > 0 ? __builtin_nontemporal_load((const v4i_t *)(xy4 + (in[u] ? t : tlast)))
+                     : v4i_t{0, 0, 0, 0};
+    }
+    const int64_t passes = T > 0 ? T + LAG : 0;    // no loads at all without pairs
+    for (int64_t r = 0; r < passes; r++) {
+        // C: trip r - LAG
+        if (r >= LAG) {
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                uint32_t sc = fbC[k] != ~0u ? fC[k] : vC[k];
+                add_short<VALS, SETS>(sc, (k & 1) ? valC[k >> 1].y : valC[k >> 1].x, A, np, L);
+            }
         }
-        // level 1 from LDS; levels 2 and 3 as batched global loads (a point
-        // that needs no load there re-reads element 0, a cache hit)
-        uint32_t e[2 * PROBE_UNROLL], lo[2 * PROBE_UNROLL], sq[2 * PROBE_UNROLL];
-        bool ok[2 * PROBE_UNROLL];
+        // B: trip r - 1, after its sub-tile entries
+        if (SUB && r >= 1 && r <= T) {
 #pragma unroll
-        for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
+            for (int k = 0; k < K; k++) {
+                if (fbB[k] == ~0u) continue;
+                bool mixed = (seB[k] & TILE_MIXED) != 0;
+                vB[k] = mixed ? 0u : seB[k];
+                fbB[k] = mixed ? (seB[k] & ~TILE_MIXED) : ~0u;
+            }
+        }
+        // A: trip r, from the LDS directory
+        uint32_t fbA[K], vA[K], loA[K], sqA[K];
+#pragma unroll
+        for (int k = 0; k < K; k++) {
             int32_t x = (k & 1) ? q[k >> 1].z : q[k >> 1].x;
             int32_t y = (k & 1) ? q[k >> 1].w : q[k >> 1].y;
             // offsets from the box origin modulo 2^32: the stored box lies
@@ -878,43 +928,63 @@ __global__ __launch_bounds__(BLOCK) void k_probe_grid16(const int4 *__restrict__
             // away from a position in the box, and the wrapped offset is
             // below ext exactly when the point is in the box
             uint32_t dx = (uint32_t)x - ox, dy = (uint32_t)y - oy;
-            ok[k] = in[k >> 1] && dx < g.extx && dy < g.exty;
-            uint32_t i = __umulhi((ok[k] ? dx : 0u) << g.pre, g.mag) >> g.post;
-            uint32_t j = __umulhi((ok[k] ? dy : 0u) << g.pre, g.mag) >> g.post;
-            e[k] = ldir[(j >> g.tl) * g.tw + (i >> g.tl)];
-            lo[k] = ((j & m) << fl) | (i & m);
-            if (SUB) sq[k] = (((j >> g.sl) & mq) << qs) | ((i >> g.sl) & mq);
-            if (!ok[k]) e[k] = 0;
+            bool ok = r < T && in[k >> 1] && dx < g.extx && dy < g.exty;
+            uint32_t i = __umulhi((ok ? dx : 0u) << g.pre, g.mag) >> g.post;
+            uint32_t j = __umulhi((ok ? dy : 0u) << g.pre, g.mag) >> g.post;
+            uint32_t e = ldir[(j >> g.tl) * g.tw + (i >> g.tl)];
+            if (!ok) e = 0;
+            loA[k] = ((j & m) << fl) | (i & m);
+            sqA[k] = SUB ? (((j >> g.sl) & mq) << qs) | ((i >> g.sl) & mq) : 0u;
+            bool mixed = (e & 0x8000u) != 0;
+            fbA[k] = mixed ? (e & 0x7fffu) : ~0u;
+            vA[k] = mixed ? 0u : e;
         }
-        uint32_t fb[2 * PROBE_UNROLL];  // fine block of the point, or ~0u
-        uint32_t v[2 * PROBE_UNROLL];   // short code when no fine block is needed
+        // every load of the pass, in the order the next pass needs them
+        __builtin_amdgcn_sched_barrier(0);
+        uint32_t seA[K], fB[K];
+        v2l_t valB[PROBE_UNROLL];
+        v4i_t qn[PROBE_UNROLL];
+        bool inn[PROBE_UNROLL];
 #pragma unroll
-        for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
-            bool mixed = (e[k] & 0x8000u) != 0;
-            fb[k] = mixed ? (e[k] & 0x7fffu) : ~0u;
-            v[k] = mixed ? 0u : e[k];
+        for (int k = 0; k < K; k++)
+            seA[k] = SUB ? g.sub[fbA[k] != ~0u ? ((uint64_t)fbA[k] << (2 * qs)) + sqA[k] : 0] : 0u;
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            // without sub-tiles the fine block comes straight from the directory
+            uint32_t b = SUB ? fbB[k] : fbA[k];
+            uint32_t o = SUB ? loB[k] : loA[k];
+            fB[k] = g.blocks16[b != ~0u ? ((uint64_t)b << (2 * fl)) + o : 0];
         }
-        if (SUB) {
-            uint32_t se[2 * PROBE_UNROLL];
 #pragma unroll
-            for (int k = 0; k < 2 * PROBE_UNROLL; k++)
-                se[k] = g.sub[fb[k] != ~0u ? ((uint64_t)fb[k] << (2 * qs)) + sq[k] : 0];
-#pragma unroll
-            for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
-                if (fb[k] == ~0u) continue;
-                bool mixed = (se[k] & TILE_MIXED) != 0;
-                v[k] = mixed ? 0u : se[k];
-                fb[k] = mixed ? (se[k] & ~TILE_MIXED) : ~0u;
-            }
+        for (int u = 0; u < PROBE_UNROLL; u++) {
+            // values of the trip whose codes were just gathered
+            int64_t t = tb + (r - (LAG - 1)) * trip + (int64_t)u * stride;
+            t = t < 0 ? 0 : (t < npairs ? t : tlast);
+            valB[u] = VALS ? __builtin_nontemporal_load((const v2l_t *)(v2 + t)) : v2l_t{0, 0};
         }
-        uint32_t f[2 * PROBE_UNROLL];
 #pragma unroll
-        for (int k = 0; k < 2 * PROBE_UNROLL; k++)
-            f[k] = g.blocks16[fb[k] != ~0u ? ((uint64_t)fb[k] << (2 * fl)) + lo[k] : 0];
+        for (int u = 0; u < PROBE_UNROLL; u++) {
+            int64_t t = tb + (r + 1) * trip + (int64_t)u * stride;
+            inn[u] = t < npairs;
+            qn[u] = __builtin_nontemporal_load((const v4i_t *)(xy4 + (inn[u] ? t : tlast)));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // rotate the stages
 #pragma unroll
-        for (int k = 0; k < 2 * PROBE_UNROLL; k++) {
-            uint32_t sc = fb[k] != ~0u ? f[k] : v[k];
-            add_short<VALS, SETS>(sc, (k & 1) ? vv[k >> 1].y : vv[k >> 1].x, A, np, L);
+        for (int k = 0; k < K; k++) {
+            fC[k] = fB[k];
+            fbC[k] = SUB ? fbB[k] : fbA[k];
+            vC[k] = SUB ? vB[k] : vA[k];
+            seB[k] = seA[k];
+            fbB[k] = fbA[k];
+            vB[k] = vA[k];
+            loB[k] = loA[k];
+        }
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; u++) {
+            valC[u] = valB[u];
+            q[u] = qn[u];
+            in[u] = inn[u];
         }
     }
     if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
