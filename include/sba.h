@@ -104,6 +104,19 @@ typedef struct {
                              positives, every misclassified point within eps/2 of P's
                              boundary; on a partition every point counts once.  Not with
                              boundary_only.                                             */
+    /* Device memory of the build.  alloc == NULL: the library's own block cache
+       (hipMalloc, kept for later builds).  Otherwise every device block of the build --
+       its temporaries and the handle's arrays -- comes from alloc(bytes, alloc_ctx),
+       which returns device memory of the current device, at least `bytes` long and
+       256-byte aligned, or NULL to refuse (the build then gives back every block it
+       took and fails with SBA_ENOMEM; a misaligned block fails it with SBA_EINVAL).
+       Each block goes back through release(p, alloc_ctx): the temporaries before
+       sba_build_approx returns (their work has completed), the handle's arrays in
+       sba_free (which does not synchronise).  Both are called on the thread that
+       calls sba_build_approx / sba_free; release must be set when alloc is.       */
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*release)(void *p, void *ctx);
+    void *alloc_ctx;
 } sba_build_opts;
 
 typedef struct {
@@ -155,6 +168,28 @@ typedef struct {
  */
 int sba_build_approx(const sba_polygons *polys, int64_t eps, const sba_build_opts *opts,
                      void *stream, sba_handle **out);
+
+/*
+ * The Hilbert key grid that covers the cells of several polygon sets at
+ * distance bound eps (Sec. 2.2: cell side s = floor(eps / sqrt(2)); Sec. 3:
+ * cells linearised along one space-filling curve), so that handles built on
+ * it (sba_build_opts.key_level / key_i0 / key_j0) share one curve, as
+ * sba_join_pairs requires.  The cell box of a set is
+ * [ceil(xmin/s) - 1, floor(xmax/s)] x [ceil(ymin/s) - 1, floor(ymax/s)] over
+ * its vertices (the cells its approximations can touch); the grid is
+ * anchored at the first cell (i0, j0) of the union of the boxes and has
+ * 2^level cells a side, level the smallest in 1..21 that covers the union.
+ *   sets    HOST array of n_sets (1..64) polygon sets, each as for
+ *           sba_build_approx (DEVICE arrays); sets without polygons are skipped.
+ *   level, i0, j0  HOST pointers that receive the grid.
+ * Synchronises `stream`.  Errors: SBA_EINVAL (null pointers, bad offsets,
+ * an empty polygon, no polygon at all, eps out of range), SBA_ERANGE
+ * (|coordinate| >= 2^30), SBA_ELIMIT (more than 64 sets or polygons than
+ * sba_build_approx takes; the union wider than 2^21 cells), SBA_ENOMEM,
+ * SBA_EDEVICE.
+ */
+int sba_key_grid(const sba_polygons *sets, int32_t n_sets, int64_t eps, void *stream,
+                 int32_t *level, int64_t *i0, int64_t *j0);
 
 /*
  * Per-polygon COUNT and SUM over the points (Sec. 5: the aggregation query

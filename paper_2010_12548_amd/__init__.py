@@ -46,7 +46,63 @@ class _Opts(C.Structure):
                 ("win_y0", C.c_int32), ("win_x1", C.c_int32), ("win_y1", C.c_int32),
                 ("sub_log2", C.c_int32), ("boundary_only", C.c_int32),
                 ("key_level", C.c_int32), ("key_i0", C.c_int64), ("key_j0", C.c_int64),
-                ("centre_sampled", C.c_int32)]
+                ("centre_sampled", C.c_int32), ("alloc", C.c_void_p), ("release", C.c_void_p),
+                ("alloc_ctx", C.c_void_p)]
+
+
+# the build's device allocator callbacks (sba_build_opts.alloc / release)
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class DeviceAllocator:
+    """Device memory for builds from the caller (``sba_build_opts.alloc`` /
+    ``release``).  Subclasses implement alloc(nbytes) -> device address (int,
+    256-byte aligned) or 0 to refuse, and release(address).  An Approx built
+    with it keeps it until the handle is freed (the handle's arrays go back
+    through release in sba_free)."""
+
+    def alloc(self, nbytes: int) -> int:
+        raise NotImplementedError
+
+    def release(self, addr: int) -> None:
+        raise NotImplementedError
+
+    def _callbacks(self):
+        def a(nbytes, _ctx):
+            try:
+                return self.alloc(int(nbytes)) or None
+            except Exception:
+                return None
+
+        def r(ptr, _ctx):
+            self.release(int(ptr or 0))
+        return _ALLOC_FN(a), _RELEASE_FN(r)
+
+
+class TorchAllocator(DeviceAllocator):
+    """Builds take their device memory from torch's caching allocator on the
+    current device (so the library and torch share one pool).  ``fail_at``
+    (test support): refuse the k-th request (1-based) and count requests."""
+
+    def __init__(self, fail_at: int = 0):
+        self.fail_at = int(fail_at)
+        self.requests = 0
+        self.live = {}
+
+    def alloc(self, nbytes: int) -> int:
+        torch = _torch()
+        self.requests += 1
+        if self.fail_at and self.requests == self.fail_at:
+            return 0
+        p = torch.cuda.caching_allocator_alloc(nbytes, torch.cuda.current_device())
+        self.live[p] = nbytes
+        return p
+
+    def release(self, addr: int) -> None:
+        if addr in self.live:
+            del self.live[addr]
+            _torch().cuda.caching_allocator_delete(addr)
 
 
 class _PiOpts(C.Structure):
@@ -95,6 +151,9 @@ def lib():
     vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
     L.sba_build_approx.restype = C.c_int
     L.sba_build_approx.argtypes = [C.POINTER(_Polys), i64, C.POINTER(_Opts), vp, C.POINTER(vp)]
+    L.sba_key_grid.restype = C.c_int
+    L.sba_key_grid.argtypes = [C.POINTER(_Polys), i32, i64, vp, C.POINTER(i32), C.POINTER(i64),
+                               C.POINTER(i64)]
     L.sba_aggregate.restype = C.c_int
     L.sba_aggregate.argtypes = [vp, vp, i64, vp, vp, vp, vp]
     L.sba_aggregate_search.restype = C.c_int
@@ -265,7 +324,8 @@ class Approx:
     def __init__(self, ring_off, vert_off, xy, eps: int, kind: str = "grid",
                  search: str = "binary", log2_leaves: int = 16, tile_log2: int = 0,
                  window=None, device: str = "cuda", stream=None, sub_log2: int = 0,
-                 boundary_only: bool = False, key_grid=None, centre_sampled: bool = False):
+                 boundary_only: bool = False, key_grid=None, centre_sampled: bool = False,
+                 allocator: "DeviceAllocator | None" = None):
         torch = _torch()
         self._h = C.c_void_p(None)
         self.device = torch.device(device)
@@ -280,6 +340,13 @@ class Approx:
                      int(log2_leaves), int(tile_log2), *win, int(sub_log2),
                      1 if boundary_only else 0, *_key_grid(key_grid),
                      1 if centre_sampled else 0)
+        self._allocator = None
+        if allocator is not None:
+            cbs = allocator._callbacks()
+            opts.alloc = C.cast(cbs[0], C.c_void_p)
+            opts.release = C.cast(cbs[1], C.c_void_p)
+            # kept until sba_free has given the handle's arrays back
+            self._allocator = (allocator, cbs)
         h = C.c_void_p(None)
         with torch.cuda.device(self.device):
             rc = lib().sba_build_approx(C.byref(polys), int(eps), C.byref(opts),
@@ -303,6 +370,7 @@ class Approx:
                 _torch().cuda.synchronize(self.device)
             lib().sba_free(self._h)
             self._h = C.c_void_p(None)
+            self._allocator = None
 
     def __del__(self):
         try:
@@ -430,21 +498,26 @@ class Approx:
         return out
 
 
-def key_grid_for(eps: int, *polysets):
-    """(level, i0, j0) of a Hilbert key grid covering the cell boxes of every
-    given polygon set (objects with an xy array) at distance bound eps, so
-    that handles built on it can be joined (join_pairs).  Host arithmetic on
-    the vertex extremes only."""
-    import math
-    s = math.isqrt(int(eps) * int(eps) // 2)
-    xs = np.concatenate([np.asarray(p.xy, np.int64).reshape(-1, 2) for p in polysets])
-    i0 = -(-int(xs[:, 0].min()) // s) - 1
-    j0 = -(-int(xs[:, 1].min()) // s) - 1
-    i1 = int(xs[:, 0].max()) // s
-    j1 = int(xs[:, 1].max()) // s
-    side = max(i1 - i0 + 1, j1 - j0 + 1)
-    level = max(1, (side - 1).bit_length())
-    return (level, i0, j0)
+def key_grid_for(eps: int, *polysets, device: str = "cuda", stream=None):
+    """(level, i0, j0) of the Hilbert key grid covering the cell boxes of
+    every given polygon set (objects with ring_off / vert_off / xy arrays) at
+    distance bound eps (``sba_key_grid``), so that handles built on it can be
+    joined (join_pairs)."""
+    torch = _torch()
+    dev = torch.device(device)
+    keep, structs = [], []
+    for p in polysets:
+        ro = _dev(p.ring_off, torch.int32, dev)
+        vo = _dev(p.vert_off, torch.int64, dev)
+        pxy = _dev(p.xy, torch.int32, dev)
+        keep += [ro, vo, pxy]
+        structs.append(_Polys(int(ro.shape[0] - 1), ro.data_ptr(), vo.data_ptr(), pxy.data_ptr()))
+    arr = (_Polys * max(len(structs), 1))(*structs)
+    level, i0, j0 = C.c_int32(0), C.c_int64(0), C.c_int64(0)
+    with torch.cuda.device(dev):
+        _check(lib().sba_key_grid(arr, len(structs), int(eps), _stream_ptr(stream),
+                                  C.byref(level), C.byref(i0), C.byref(j0)), "sba_key_grid")
+    return (int(level.value), int(i0.value), int(j0.value))
 
 
 def aggregate_range(alpha: "Approx", beta: "Approx", xy, values=None, stream=None):

@@ -11,6 +11,8 @@
 // handle is freed (the caller guarantees that no queued work still reads
 // them).  Small values read back to the host go through one pinned staging
 // buffer per workspace, so a group of reads costs one synchronisation.
+// A build given a device allocator of the caller's takes every block of its
+// temporaries and of its handle from it instead, and gives each back to it.
 #include <map>
 #include <mutex>
 #include <vector>
@@ -73,7 +75,7 @@ int cache_get(size_t bytes, DevBlock *out)
         std::lock_guard<std::mutex> lk(g_cache[dev].mu);
         auto it = g_cache[dev].free_blocks.find(c);
         if (it != g_cache[dev].free_blocks.end() && !it->second.empty()) {
-            *out = DevBlock{it->second.back(), c, dev};
+            *out = DevBlock{it->second.back(), c, dev, UserAlloc{}};
             it->second.pop_back();
             return 0;
         }
@@ -87,13 +89,34 @@ int cache_get(size_t bytes, DevBlock *out)
             return SBA_ENOMEM;
         }
     }
-    *out = DevBlock{p, c, dev};
+    *out = DevBlock{p, c, dev, UserAlloc{}};
+    return 0;
+}
+
+int block_get(size_t bytes, const UserAlloc &ua, DevBlock *out)
+{
+    if (!ua.alloc) return cache_get(bytes, out);
+    int dev = 0;
+    RC(current_device(&dev));
+    const size_t c = class_size(bytes ? bytes : 1);
+    void *p = ua.alloc(c, ua.ctx);
+    if (!p) return SBA_ENOMEM;
+    if (((uintptr_t)p & 255) != 0) {  // the kernels' vector loads need the alignment
+        ua.release(p, ua.ctx);
+        return SBA_EINVAL;
+    }
+    *out = DevBlock{p, c, dev, ua};
     return 0;
 }
 
 void cache_put(const DevBlock &b)
 {
-    if (!b.p || b.dev < 0 || b.dev >= MAX_DEV) return;
+    if (!b.p) return;
+    if (b.ua.alloc) {
+        b.ua.release(b.p, b.ua.ctx);
+        return;
+    }
+    if (b.dev < 0 || b.dev >= MAX_DEV) return;
     std::lock_guard<std::mutex> lk(g_cache[b.dev].mu);
     g_cache[b.dev].free_blocks[b.cls].push_back(b.p);
 }
@@ -133,7 +156,7 @@ int Workspace::get(void **p, size_t bytes)
         }
     }
     DevBlock b{};
-    RC(cache_get(bytes, &b));
+    RC(block_get(bytes, ua_, &b));
     live_.push_back(b);
     *p = b.p;
     return 0;
@@ -192,7 +215,7 @@ int Workspace::sync()
 int handle_get(sba_handle *h, void **p, size_t bytes)
 {
     DevBlock b{};
-    RC(cache_get(bytes, &b));
+    RC(block_get(bytes, h->ua, &b));
     h->blocks_owned.push_back(b);
     h->bytes += (int64_t)bytes;
     *p = b.p;

@@ -32,6 +32,21 @@ extern "C" int sba_build_approx(const sba_polygons *polys, int64_t eps, const sb
     return SBA_OK;
 }
 
+extern "C" int sba_key_grid(const sba_polygons *sets, int32_t n_sets, int64_t eps, void *stream,
+                            int32_t *level, int64_t *i0, int64_t *j0)
+{
+    if (!sets || n_sets < 1 || !level || !i0 || !j0) return SBA_EINVAL;
+    if (n_sets > 64) return SBA_ELIMIT;
+    if (eps < 2 || eps > ((int64_t)1 << 28)) return SBA_EINVAL;
+    for (int32_t k = 0; k < n_sets; k++) {
+        const sba_polygons &P = sets[k];
+        if (P.n_polys < 0) return SBA_EINVAL;
+        if (P.n_polys > MAX_POLYS) return SBA_ELIMIT;
+        if (P.n_polys > 0 && (!P.ring_off || !P.vert_off || !P.xy)) return SBA_EINVAL;
+    }
+    return key_grid_launch(sets, n_sets, eps, (hipStream_t)stream, level, i0, j0);
+}
+
 static int check_probe_args(const int32_t *xy, const int64_t *values, int64_t n,
                             const sba_handle *h, uint64_t *counts)
 {

@@ -763,6 +763,65 @@ int pool_setup()
     return 0;
 }
 
+// Hilbert key grid covering the cell boxes of several polygon sets: each
+// set's offsets are checked and its union cell box found by the kernels of
+// the build (k_check_rings, k_check_verts, k_poly_bbox, k_union_box); the
+// grid is anchored at the first cell of the union of the boxes and has the
+// smallest level L >= 1 with 2^L cells covering the union's longer side,
+// the level the Hilbert layout takes for a stored box of that size.
+int key_grid_launch(const sba_polygons *sets, int32_t n_sets, int64_t eps, hipStream_t st,
+                    int32_t *level, int64_t *i0, int64_t *j0)
+{
+    const int64_t s = cell_side(eps);
+    constexpr int SLOTS = 8;  // per set: [0] error bits, [1..2] sizes, [3..6] cell box
+    Workspace ws(st);
+    int64_t *sc = nullptr;
+    RC(ws.alloc(&sc, (int64_t)n_sets * SLOTS));
+    HIP_OK(hipMemsetAsync(sc, 0, sizeof(int64_t) * SLOTS * n_sets, st));
+    std::vector<int4 *> bbox(n_sets, nullptr);
+    for (int32_t k = 0; k < n_sets; k++) {
+        const sba_polygons &P = sets[k];
+        const int32_t np = P.n_polys;
+        if (np == 0) continue;
+        int *err = (int *)(sc + SLOTS * k);
+        int64_t *sizes = sc + SLOTS * k + 1, *dbox = sc + SLOTS * k + 3;
+        hipLaunchKernelGGL(k_check_rings, dim3(grid_for(np + 1)), dim3(256), 0, st, P.ring_off, np,
+                           sizes, err);
+        hipLaunchKernelGGL(k_check_verts, dim3(1024), dim3(256), 0, st, P.vert_off, sizes, err);
+        RC(ws.alloc(&bbox[k], np));
+        hipLaunchKernelGGL(k_poly_bbox, dim3(grid_for((int64_t)np * 64)), dim3(256), 0, st,
+                           P.ring_off, P.vert_off, P.xy, np, bbox[k], err);
+        hipLaunchKernelGGL(k_union_box, dim3(1), dim3(BOX_BLOCK), 0, st, bbox[k], np, s, dbox);
+        HIP_OK(hipGetLastError());
+    }
+    std::vector<int64_t> hsc((size_t)SLOTS * n_sets);
+    RC(ws.read(hsc.data(), sc, sizeof(int64_t) * SLOTS * n_sets));
+    RC(ws.sync());
+    bool any = false;
+    int64_t bi0 = 0, bj0 = 0, bi1 = 0, bj1 = 0;
+    for (int32_t k = 0; k < n_sets; k++) {
+        if (sets[k].n_polys == 0) continue;
+        const int64_t *v = hsc.data() + SLOTS * k;
+        const int herr = (int)(uint32_t)v[0];
+        if (herr & 2) return SBA_EINVAL;
+        if (herr & 1) return SBA_ERANGE;
+        bi0 = any ? std::min(bi0, v[3]) : v[3];
+        bj0 = any ? std::min(bj0, v[4]) : v[4];
+        bi1 = any ? std::max(bi1, v[5]) : v[5];
+        bj1 = any ? std::max(bj1, v[6]) : v[6];
+        any = true;
+    }
+    if (!any) return SBA_EINVAL;
+    const int64_t side = std::max(bi1 - bi0 + 1, bj1 - bj0 + 1);
+    int L = 1;
+    while (L <= 21 && ((int64_t)1 << L) < side) L++;
+    if (L > 21) return SBA_ELIMIT;
+    *level = L;
+    *i0 = bi0;
+    *j0 = bj0;
+    return 0;
+}
+
 int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_handle *h,
                    BuildState &B, bool need_boundary_cells)
 {
@@ -1264,8 +1323,13 @@ int build_handle(const sba_polygons *polys, int64_t eps, const sba_build_opts *o
                  hipStream_t st, sba_handle *h)
 {
     auto t0 = std::chrono::steady_clock::now();
-    sba_build_opts o = {SBA_KIND_GRID, SBA_SEARCH_BINARY, 16, 0, 0, 0, 0, 0, 0, 0, 0};
+    sba_build_opts o{};
+    o.kind = SBA_KIND_GRID;
+    o.search = SBA_SEARCH_BINARY;
+    o.log2_leaves = 16;
     if (opts) o = *opts;
+    if ((o.alloc == nullptr) != (o.release == nullptr)) return SBA_EINVAL;
+    h->ua = UserAlloc{o.alloc, o.release, o.alloc_ctx};
     if (o.use_window && (o.win_x1 <= o.win_x0 || o.win_y1 <= o.win_y0)) return SBA_EINVAL;
     if (o.log2_leaves == 0) o.log2_leaves = 16;
     if (o.kind != SBA_KIND_GRID && o.kind != SBA_KIND_HILBERT) return SBA_EINVAL;
@@ -1291,6 +1355,7 @@ int build_handle(const sba_polygons *polys, int64_t eps, const sba_build_opts *o
         return 0;
     }
     BuildState B(st);
+    B.ws.set_allocator(h->ua);
     B.boundary_only = o.boundary_only != 0;
     h->boundary_only = o.boundary_only != 0;
     B.centre = o.centre_sampled != 0;

@@ -14,13 +14,25 @@
 
 // ---------------------------------------------------------------- device memory (alloc.hip)
 
+// A caller's device allocator (sba_build_opts.alloc / release / alloc_ctx);
+// alloc == nullptr: the library's own block cache.
+struct UserAlloc {
+    void *(*alloc)(size_t bytes, void *ctx) = nullptr;
+    void (*release)(void *p, void *ctx) = nullptr;
+    void *ctx = nullptr;
+};
+
 struct DevBlock {
     void *p;
     size_t cls;  // size of the block (its size class)
     int dev;
+    UserAlloc ua;  // the caller's allocator that gave the block, if any
 };
 
 int cache_get(size_t bytes, DevBlock *out);
+// a block from the caller's allocator when it has one, else from the cache
+int block_get(size_t bytes, const UserAlloc &ua, DevBlock *out);
+// back to the caller's allocator or to the cache
 void cache_put(const DevBlock &b);
 
 // Temporaries of one stream-ordered job; the destructor synchronises the
@@ -46,6 +58,8 @@ public:
     int read(void *host, const void *dev, size_t bytes);
     int sync();
     hipStream_t stream() const { return st_; }
+    // later blocks come from the caller's allocator (before the first get)
+    void set_allocator(const UserAlloc &ua) { ua_ = ua; }
 
 private:
     struct Read {
@@ -58,6 +72,7 @@ private:
     std::vector<Read> reads_;
     char *pinned_ = nullptr;
     size_t staged_ = 0;
+    UserAlloc ua_;
 };
 
 // ---------------------------------------------------------------- codes
@@ -142,6 +157,7 @@ struct sba_handle {
     int64_t bytes;
     double build_ms;
     int device;
+    UserAlloc ua;                        // the caller's allocator of the arrays, if any
     std::vector<DevBlock> blocks_owned;  // every device array above
 };
 
@@ -399,5 +415,7 @@ int bucket_launch(const int32_t *xy, const int64_t *values, int64_t n, int32_t x
 
 // Build entry point (build.hip).
 extern bool g_build_wide;
+int key_grid_launch(const sba_polygons *sets, int32_t n_sets, int64_t eps, hipStream_t st,
+                    int32_t *level, int64_t *i0, int64_t *j0);
 int build_handle(const sba_polygons *polys, int64_t eps, const sba_build_opts *opts,
                  hipStream_t st, sba_handle *h);
