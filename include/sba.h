@@ -82,9 +82,12 @@ typedef struct {
                              cells outside it are empty in the handle (for viewport
                              queries: the answer inside the window is unchanged)         */
     int32_t sub_log2;     /* grid: sub-tile side 2^sub_log2 cells inside mixed tiles,
-                             2..tile_log2; == tile_log2: mixed tiles are stored cell by
-                             cell (0 -> 4 for tiles of 64 cells or more, 3 for tiles of
-                             32 cells, else tile_log2)                                   */
+                             1..tile_log2; == tile_log2: mixed tiles are stored cell by
+                             cell (0 -> the smallest side whose 16-bit sub-directory fits
+                             the LDS of a compute unit beside the directory and the
+                             probe's bins, so the probe reads it there; if none fits, 4
+                             for tiles of 64 cells or more, 3 for tiles of 32 cells,
+                             else tile_log2)                                             */
     int32_t boundary_only; /* 1: store only the boundary cells B(P) of every polygon
                              (no interior cells).  sba_aggregate over such a handle gives
                              the partial count beta (and sum) over the boundary cells, so

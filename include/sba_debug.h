@@ -39,6 +39,12 @@ int sba_debug_set_grid16_per_cu(int k);
  * does not fit the LDS falls back to the next one down.  Process-wide. */
 int sba_debug_grid16_sets(int mode);
 
+/* Whether the LDS-directory grid probe may stage the sub-directory in LDS as
+ * well (16-bit entries, when they fit beside the directory and the bins):
+ * -1 when it fits (default), 0 never (read from global memory).
+ * Process-wide; for comparison runs and tests of both paths. */
+int sba_debug_grid16_lsub(int mode);
+
 /* 1: grid builds store the 32-bit format (directory read from global memory
  * by the probes) even where the 16-bit LDS-staged format would fit
  * (comparison runs); 0: default.  Process-wide, read at build time. */

@@ -187,6 +187,8 @@ def lib():
     L.sba_probe_kernel.argtypes = [C.c_void_p, C.c_int]
     L.sba_debug_grid16_sets.restype = C.c_int
     L.sba_debug_grid16_sets.argtypes = [C.c_int]
+    L.sba_debug_grid16_lsub.restype = C.c_int
+    L.sba_debug_grid16_lsub.argtypes = [C.c_int]
     L.sba_debug_set_grid16_per_cu.restype = C.c_int
     L.sba_debug_set_grid16_per_cu.argtypes = [C.c_int]
     L.sba_debug_force_wide_grid.restype = C.c_int

@@ -1197,8 +1197,9 @@ int build_grid(sba_handle *h, BuildState &B, int tile_log2, int sub_log2, hipStr
     }
     if (tl < 2 || tl > 10) return SBA_EINVAL;
     // sub-tiles of 16 x 16 cells under big tiles, of 8 x 8 under tiles of 32
+    // (until the mixed tiles are known, see below)
     int sl = sub_log2 ? sub_log2 : (tl >= 6 ? 4 : (tl == 5 ? 3 : tl));
-    if (sl < 2 || sl > tl) return SBA_EINVAL;
+    if (sl < 1 || sl > tl) return SBA_EINVAL;
     h->tile_log2 = tl;
     h->sub_log2 = sl;
     h->tw = (h->gw + (1 << tl) - 1) >> tl;
@@ -1222,6 +1223,21 @@ int build_grid(sba_handle *h, BuildState &B, int tile_log2, int sub_log2, hipStr
     const bool compact = !g_build_wide && (int64_t)np + h->n_sets < 0x8000 && nblk < 0x8000 &&
                          nt <= COMPACT_DIR_TILES_MAX;
     h->compact = compact;
+    if (sub_log2 == 0 && compact && nblk > 0) {
+        // the smallest sub-tile whose 16-bit sub-directory fits the LDS of a
+        // compute unit beside the directory and the bins: the probe then
+        // stages it there, and only points in mixed sub-tiles read a fine
+        // block from global memory
+        const int64_t dir = ((nt + 7) & ~(int64_t)7) * 2, bins = ((int64_t)np + h->n_sets) * 12;
+        for (int t = 1; t < tl; t++) {
+            const int64_t ne = ((nblk << (2 * (tl - t))) + 7) & ~(int64_t)7;
+            if (dir + ne * 2 + bins <= PROBE_LDS_BYTES) {
+                sl = t;
+                break;
+            }
+        }
+        h->sub_log2 = sl;
+    }
 
     // directory
     if (compact) {

@@ -734,7 +734,23 @@ struct Grid16 {
     uint32_t np;                  // short codes: p+1 polygon p, > np set (code - np - 1)
     uint32_t sets;                // SETS_*
     uint32_t n_ids;               // set table ids
+    uint32_t nsub16;              // sub-directory entries staged in LDS (level 2), multiple of 8
+    uint32_t nsub;                // sub-directory entries (level 2)
 };
+
+// Loads at a 32-bit byte offset from a wave-uniform base: the compiler
+// keeps the base in scalar registers and adds the offset in the load
+// (global_load ... v_off, s[base]), with no 64-bit address arithmetic.
+template <typename T>
+__device__ __forceinline__ T load_off(const void *base, uint32_t byte_off)
+{
+    return *(const T *)((const char *)base + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ T load_off_nt(const void *base, uint32_t byte_off)
+{
+    return __builtin_nontemporal_load((const T *)((const char *)base + byte_off));
+}
 
 // Workgroup-private state of the grid probe in LDS.
 struct Lds16 {
@@ -809,7 +825,10 @@ __device__ __forceinline__ uint32_t grid16_code(const Grid16 &g, const uint16_t 
     return g.blocks16[((uint64_t)b << (2 * fl)) + (((j & m) << fl) | (i & m))];
 }
 
-template <bool VALS, bool SUB, int SETS, int BLOCK>
+// LEV: 0 no sub-tiles (mixed tiles are fine blocks), 1 sub-directory read
+// from global memory, 2 sub-directory staged in LDS as 16-bit entries (short
+// code or 0x8000 | fine block), so only points in mixed sub-tiles leave LDS.
+template <bool VALS, int LEV, int SETS, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_probe_grid16(const int4 *__restrict__ xy4,
                                                         const longlong2 *__restrict__ v2,
                                                         const int32_t *__restrict__ xy,
@@ -818,18 +837,23 @@ __global__ __launch_bounds__(BLOCK) void k_probe_grid16(const int4 *__restrict__
                                                         uint64_t *__restrict__ counts,
                                                         int64_t *__restrict__ sums)
 {
-    // LDS: directory (nt16 entries, a multiple of 8), sums (u64 [nb]), counts
-    // (u32 [nb]) with nb = np (+ n_sets with SETS_BINS), then with SETS_LDS
-    // the set table (u16 [n_sets + 1], u16 [n_ids]).  Every pointer is formed
-    // by pointer arithmetic on the shared array, so the compiler keeps LDS
-    // instructions for all of them.
+    // LDS: directory (nt16 entries, a multiple of 8), with LEV 2 the
+    // sub-directory (nsub16 entries, a multiple of 8), sums (u64 [nb]),
+    // counts (u32 [nb]) with nb = np (+ n_sets with SETS_BINS), then with
+    // SETS_LDS the set table (u16 [n_sets + 1], u16 [n_ids]).  Every pointer
+    // is formed by pointer arithmetic on the shared array, so the compiler
+    // keeps LDS instructions for all of them.
+    constexpr bool SUB = LEV != 0;
+    constexpr bool GSUB = LEV == 1;
     extern __shared__ unsigned long long smem[];
     const uint32_t np = g.np;
     const uint32_t nbins = np + (SETS == SETS_BINS ? A.n_sets : 0u);
+    const uint32_t nsub16 = LEV == 2 ? g.nsub16 : 0u;
     Lds16 L;
     uint16_t *ldir = (uint16_t *)smem;
+    uint16_t *lsub = ldir + g.nt16;
     L.dir = ldir;
-    L.sum = smem + g.nt16 / 4;
+    L.sum = smem + (g.nt16 + nsub16) / 4;
     L.cnt = (uint32_t *)(L.sum + nbins);
     L.soff = (const uint16_t *)(L.cnt + nbins);
     L.sids = L.soff + A.n_sets + 1;
@@ -837,6 +861,14 @@ __global__ __launch_bounds__(BLOCK) void k_probe_grid16(const int4 *__restrict__
         const uint4 *src = (const uint4 *)g.dir16;
         uint4 *dst = (uint4 *)ldir;
         for (uint32_t q = threadIdx.x; q < g.nt16 / 8; q += BLOCK) dst[q] = src[q];
+        if (LEV == 2) {
+            // 32-bit entries (short code, or TILE_MIXED | fine block below
+            // 2^15) to 16 bits; the padding entries read as empty
+            for (uint32_t q = threadIdx.x; q < nsub16; q += BLOCK) {
+                const uint32_t se = q < g.nsub ? g.sub[q] : 0u;
+                lsub[q] = (uint16_t)((se & TILE_MIXED) ? (0x8000u | (se & 0x7fffu)) : se);
+            }
+        }
         for (uint32_t p = threadIdx.x; p < nbins; p += BLOCK) {
             L.cnt[p] = 0;
             L.sum[p] = 0;
@@ -867,125 +899,156 @@ __global__ __launch_bounds__(BLOCK) void k_probe_grid16(const int4 *__restrict__
     // and then issues the coordinate loads of trip r + 1.  Vector memory
     // loads complete in issue order, so each pass waits once for the loads of
     // the pass before (the coordinates last): the latencies of the stream and
-    // of both gather levels overlap instead of adding up.  Loads have no
-    // branches: a lane past the end re-reads the last pair (in bounds, as the
-    // loop runs only when npairs > 0) or element 0 of a gathered array, and
-    // drops the point.
-    // Without sub-tiles there is no stage B: the fine blocks are gathered
-    // straight after the directory, and C adds trip r - 1.
+    // of both gather levels overlap instead of adding up.  Without a global
+    // sub-directory (LEV 0, or LEV 2 with it in LDS) there is no stage B: A
+    // finds the fine block itself and C adds trip r - 1.
+    //
+    // Every load is a 32-bit byte offset from a scalar base: a lane's offset
+    // inside a trip is the same in every trip (only the base moves), and
+    // gathers take 32-bit offsets into arrays below 4 GB (grid16_fits).  A
+    // lane with no point (past the end) or no gather to make reads offset 0,
+    // in bounds.
     constexpr int K = 2 * PROBE_UNROLL;
-    constexpr int LAG = SUB ? 2 : 1;
+    constexpr int LAG = GSUB ? 2 : 1;
+    // A point's state between stages is one word in the sub-directory's
+    // format: a short code, or TILE_MIXED | index of the block (sub-tile
+    // entry or fine block) that holds its code.
+    struct StA {                   // trip r: coordinates
+        v4i_t q[PROBE_UNROLL];
+    };
+    struct StB {                   // trip r - 1: sub-tile entry (loaded), state, cell in block
+        uint32_t se[K], e[K], lo[K];
+    };
+    struct StC {                   // trip r - LAG: fine-block code (loaded), state, values
+        uint32_t f[K], e[K];
+        v2l_t val[PROBE_UNROLL];
+    };
     const int64_t T = (npairs + trip - 1) / trip;  // trips, the same for every lane
-    const int64_t tb = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    v4i_t q[PROBE_UNROLL];                         // coordinates of trip r
-    bool in[PROBE_UNROLL];
-    uint32_t seB[K], fbB[K], vB[K], loB[K];        // trip r - 1 (seB: sub-tile entries)
-    uint32_t fC[K], fbC[K], vC[K];                 // trip r - 2 (fC: fine-block codes)
-    v2l_t valC[PROBE_UNROLL];
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        seB[k] = vB[k] = loB[k] = 0;
-        fC[k] = vC[k] = 0;
-        fbB[k] = fbC[k] = ~0u;
-    }
-#pragma unroll
-    for (int u = 0; u < PROBE_UNROLL; u++) {
-        valC[u] = v2l_t{0, 0};
-        int64_t t = tb + (int64_t)u * stride;
-        in[u] = t < npairs;
-        q[u] = T > 0 ? __builtin_nontemporal_load((const v4i_t *)(xy4 + (in[u] ? t : tlast)))
-                     : v4i_t{0, 0, 0, 0};
-    }
     const int64_t passes = T > 0 ? T + LAG : 0;    // no loads at all without pairs
-    for (int64_t r = 0; r < passes; r++) {
+    // a lane's pairs inside a trip: tb + u stride < trip <= 2^22 (at most
+    // 1024 workgroups of 1024 lanes, 4 pairs each): 16-byte offsets fit 32 bits
+    // (whether a pair exists is compared again where it is needed rather
+    // than kept: flags kept across passes would hold scalar register pairs)
+    const uint32_t tb = blockIdx.x * BLOCK + threadIdx.x;
+    // all ones when a state word names a block, zero for a code: selects
+    // without lane masks
+    auto blk = [](uint32_t e) -> uint32_t { return (uint32_t)((int32_t)e >> 31); };
+    auto trip_pairs = [&](int64_t r) -> uint32_t {
+        const int64_t rem = npairs - r * trip;
+        return (uint32_t)(rem < trip ? rem : trip);
+    };
+    auto load_xy = [&](int64_t r, StA &a) {
+        const uint32_t mp = trip_pairs(r);
+        const void *base = xy4 + r * trip;
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; u++) {
+            const uint32_t o = tb + (uint32_t)u * (uint32_t)stride;
+            a.q[u] = load_off_nt<v4i_t>(base, o < mp ? o * 16u : 0u);
+        }
+    };
+    auto load_vals = [&](int64_t r, StC &c) {
+        const uint32_t mp = trip_pairs(r);
+        const void *base = v2 + r * trip;
+#pragma unroll
+        for (int u = 0; u < PROBE_UNROLL; u++) {
+            const uint32_t o = tb + (uint32_t)u * (uint32_t)stride;
+            c.val[u] = load_off_nt<v2l_t>(base, o < mp ? o * 16u : 0u);
+        }
+    };
+    auto pass = [&](int64_t r, const StA &ai, StA &ao, const StB &bi, StB &bo, const StC &ci,
+                    StC &co) {
         // C: trip r - LAG
         if (r >= LAG) {
 #pragma unroll
             for (int k = 0; k < K; k++) {
-                uint32_t sc = fbC[k] != ~0u ? fC[k] : vC[k];
-                add_short<VALS, SETS>(sc, (k & 1) ? valC[k >> 1].y : valC[k >> 1].x, A, np, L);
+                const uint32_t t = blk(ci.e[k]);
+                add_short<VALS, SETS>((ci.f[k] & t) | (ci.e[k] & ~t),
+                                      (k & 1) ? ci.val[k >> 1].y : ci.val[k >> 1].x, A, np, L);
             }
         }
-        // B: trip r - 1, after its sub-tile entries
-        if (SUB && r >= 1 && r <= T) {
-#pragma unroll
-            for (int k = 0; k < K; k++) {
-                if (fbB[k] == ~0u) continue;
-                bool mixed = (seB[k] & TILE_MIXED) != 0;
-                vB[k] = mixed ? 0u : seB[k];
-                fbB[k] = mixed ? (seB[k] & ~TILE_MIXED) : ~0u;
-            }
-        }
-        // A: trip r, from the LDS directory
-        uint32_t fbA[K], vA[K], loA[K], sqA[K];
+        // B: trip r - 1: a point in a mixed tile takes its sub-tile entry
+        uint32_t eB[K];
 #pragma unroll
         for (int k = 0; k < K; k++) {
-            int32_t x = (k & 1) ? q[k >> 1].z : q[k >> 1].x;
-            int32_t y = (k & 1) ? q[k >> 1].w : q[k >> 1].y;
+            const uint32_t t = GSUB ? blk(bi.e[k]) : 0u;
+            eB[k] = (bi.se[k] & t) | (bi.e[k] & ~t);
+        }
+        // A: trip r, from the LDS directory
+        uint32_t eA[K], loA[K], sqA[K];
+        const uint32_t mpA = r < T ? trip_pairs(r) : 0u;
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            int32_t x = (k & 1) ? ai.q[k >> 1].z : ai.q[k >> 1].x;
+            int32_t y = (k & 1) ? ai.q[k >> 1].w : ai.q[k >> 1].y;
             // offsets from the box origin modulo 2^32: the stored box lies
             // inside (-2^30 - 2^29, 2^30 + 2^28) (polygon coordinates below
             // 2^30 in magnitude, cells below 2^28), so no int32 point is 2^32
             // away from a position in the box, and the wrapped offset is
             // below ext exactly when the point is in the box
             uint32_t dx = (uint32_t)x - ox, dy = (uint32_t)y - oy;
-            bool ok = r < T && in[k >> 1] && dx < g.extx && dy < g.exty;
+            bool ok = tb + (uint32_t)(k >> 1) * (uint32_t)stride < mpA && dx < g.extx &&
+                      dy < g.exty;
             uint32_t i = __umulhi((ok ? dx : 0u) << g.pre, g.mag) >> g.post;
             uint32_t j = __umulhi((ok ? dy : 0u) << g.pre, g.mag) >> g.post;
             uint32_t e = ldir[(j >> g.tl) * g.tw + (i >> g.tl)];
             if (!ok) e = 0;
             loA[k] = ((j & m) << fl) | (i & m);
             sqA[k] = SUB ? (((j >> g.sl) & mq) << qs) | ((i >> g.sl) & mq) : 0u;
-            bool mixed = (e & 0x8000u) != 0;
-            fbA[k] = mixed ? (e & 0x7fffu) : ~0u;
-            vA[k] = mixed ? 0u : e;
+            if (LEV == 2) {
+                // the sub-tile entry from LDS (entry 0 for a uniform tile)
+                const uint32_t se =
+                    lsub[((e & 0x8000u) ? ((e & 0x7fffu) << (2 * qs)) + sqA[k] : 0u)];
+                e = (e & 0x8000u) ? se : e;
+            }
+            eA[k] = (e & 0x8000u) ? (TILE_MIXED | (e & 0x7fffu)) : e;
         }
         // every load of the pass, in the order the next pass needs them
         __builtin_amdgcn_sched_barrier(0);
-        uint32_t seA[K], fB[K];
-        v2l_t valB[PROBE_UNROLL];
-        v4i_t qn[PROBE_UNROLL];
-        bool inn[PROBE_UNROLL];
+        if (GSUB) {
 #pragma unroll
-        for (int k = 0; k < K; k++)
-            seA[k] = SUB ? g.sub[fbA[k] != ~0u ? ((uint64_t)fbA[k] << (2 * qs)) + sqA[k] : 0] : 0u;
+            for (int k = 0; k < K; k++)
+                bo.se[k] = load_off<uint32_t>(
+                    g.sub, ((((eA[k] & ~TILE_MIXED) << (2 * qs)) + sqA[k]) << 2) & blk(eA[k]));
+        }
 #pragma unroll
         for (int k = 0; k < K; k++) {
-            // without sub-tiles the fine block comes straight from the directory
-            uint32_t b = SUB ? fbB[k] : fbA[k];
-            uint32_t o = SUB ? loB[k] : loA[k];
-            fB[k] = g.blocks16[b != ~0u ? ((uint64_t)b << (2 * fl)) + o : 0];
+            // without a global sub-directory the fine block is known in stage A
+            const uint32_t e = GSUB ? eB[k] : eA[k];
+            const uint32_t o = GSUB ? bi.lo[k] : loA[k];
+            co.f[k] = load_off<uint16_t>(g.blocks16,
+                                         ((((e & ~TILE_MIXED) << (2 * fl)) + o) << 1) & blk(e));
         }
-#pragma unroll
-        for (int u = 0; u < PROBE_UNROLL; u++) {
-            // values of the trip whose codes were just gathered
-            int64_t t = tb + (r - (LAG - 1)) * trip + (int64_t)u * stride;
-            t = t < 0 ? 0 : (t < npairs ? t : tlast);
-            valB[u] = VALS ? __builtin_nontemporal_load((const v2l_t *)(v2 + t)) : v2l_t{0, 0};
-        }
-#pragma unroll
-        for (int u = 0; u < PROBE_UNROLL; u++) {
-            int64_t t = tb + (r + 1) * trip + (int64_t)u * stride;
-            inn[u] = t < npairs;
-            qn[u] = __builtin_nontemporal_load((const v4i_t *)(xy4 + (inn[u] ? t : tlast)));
-        }
+        // values of the trip whose codes were just gathered
+        const int64_t rv = r - (LAG - 1);
+        if (VALS && rv >= 0 && rv < T) load_vals(rv, co);
+        if (r + 1 < T) load_xy(r + 1, ao);
         __builtin_amdgcn_sched_barrier(0);
-        // rotate the stages
 #pragma unroll
         for (int k = 0; k < K; k++) {
-            fC[k] = fB[k];
-            fbC[k] = SUB ? fbB[k] : fbA[k];
-            vC[k] = SUB ? vB[k] : vA[k];
-            seB[k] = seA[k];
-            fbB[k] = fbA[k];
-            vB[k] = vA[k];
-            loB[k] = loA[k];
+            co.e[k] = GSUB ? eB[k] : eA[k];
+            bo.e[k] = eA[k];
+            bo.lo[k] = loA[k];
         }
+    };
+    StA a0, a1;
+    StB b0, b1;
+    StC c0, c1;
 #pragma unroll
-        for (int u = 0; u < PROBE_UNROLL; u++) {
-            valC[u] = valB[u];
-            q[u] = qn[u];
-            in[u] = inn[u];
-        }
+    for (int k = 0; k < K; k++) {
+        b0.se[k] = b0.e[k] = b0.lo[k] = 0;
+        c0.f[k] = c0.e[k] = 0;
+    }
+#pragma unroll
+    for (int u = 0; u < PROBE_UNROLL; u++) {
+        c0.val[u] = v2l_t{0, 0};
+        a0.q[u] = v4i_t{0, 0, 0, 0};
+    }
+    if (T > 0) load_xy(0, a0);
+    for (int64_t r = 0; r < passes; r++) {
+        pass(r, a0, a1, b0, b1, c0, c1);
+        a0 = a1;
+        b0 = b1;
+        c0 = c1;
     }
     if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
         int64_t k = n - 1;
@@ -1026,29 +1089,82 @@ static size_t grid16_dir_lds(const sba_handle *h)
 // fits, else the global table
 static int g_grid16_sets = -1;  // forced SETS_* mode (when it fits), -1: automatic
 
-static int grid16_mode(const sba_handle *h, size_t *lds)
+static int g_grid16_lsub = -1;   // 0: never stage the sub-directory in LDS, -1: when it fits
+
+// How the grid probe runs on a handle: set handling, sub-directory level and
+// LDS bytes.  In order of preference: bins for polygons and sets, the set
+// table in LDS, the global set table; for each, the sub-directory staged in
+// LDS when its 16-bit entries fit there too (every fine block index below
+// 2^15), else read from global memory.
+struct Grid16Plan {
+    int sets;         // SETS_*
+    int lev;          // 0 no sub-tiles, 1 global sub-directory, 2 sub-directory in LDS
+    uint32_t nsub, nsub16;
+    size_t lds;
+};
+
+static Grid16Plan grid16_plan(const sba_handle *h)
 {
     const size_t dir = grid16_dir_lds(h), np = (size_t)h->n_polys, ns = (size_t)h->n_sets;
+    const bool sub = h->sub_log2 < h->tile_log2;
+    Grid16Plan pl{SETS_GLOBAL, sub ? 1 : 0, 0, 0, 0};
+    size_t lsub = 0;
+    if (sub && g_grid16_lsub != 0 && h->n_sub < 0x8000) {
+        const int64_t ne = std::max<int64_t>(h->n_blocks << (2 * (h->tile_log2 - h->sub_log2)), 1);
+        if (ne < ((int64_t)1 << 24)) {
+            pl.nsub = (uint32_t)ne;
+            pl.nsub16 = (uint32_t)((ne + 7) & ~(int64_t)7);
+            lsub = (size_t)pl.nsub16 * 2;
+        }
+    }
     const int want = g_grid16_sets;
-    if ((want < 0 || want == SETS_BINS) && ns > 0 && dir + (np + ns) * 12 <= GRID16_LDS_MAX) {
-        *lds = dir + (np + ns) * 12;
-        return SETS_BINS;
-    }
     const size_t table = (ns + 1 + (size_t)h->n_set_ids) * 2;
-    if ((want < 0 || want == SETS_LDS) && ns > 0 && h->n_set_ids < 0xffff &&
-        table <= GRID16_SETS_MAX && dir + np * 12 + table <= GRID16_LDS_MAX) {
-        *lds = dir + np * 12 + table;
-        return SETS_LDS;
+    const bool bins_ok = (want < 0 || want == SETS_BINS) && ns > 0;
+    const bool table_ok = (want < 0 || want == SETS_LDS) && ns > 0 && h->n_set_ids < 0xffff &&
+                          table <= GRID16_SETS_MAX;
+    const size_t need[3] = {bins_ok ? dir + (np + ns) * 12 : SIZE_MAX,
+                            table_ok ? dir + np * 12 + table : SIZE_MAX, dir + np * 12};
+    const int modes[3] = {SETS_BINS, SETS_LDS, SETS_GLOBAL};
+    for (int t = 0; t < 3; t++) {
+        if (need[t] == SIZE_MAX) continue;
+        if (lsub && need[t] + lsub <= GRID16_LDS_MAX) {
+            pl.sets = modes[t];
+            pl.lev = 2;
+            pl.lds = need[t] + lsub;
+            return pl;
+        }
+        if (need[t] <= GRID16_LDS_MAX || t == 2) {
+            pl.sets = modes[t];
+            pl.nsub = pl.nsub16 = 0;
+            pl.lds = need[t];
+            return pl;
+        }
     }
-    *lds = dir + np * 12;
-    return SETS_GLOBAL;
+    return pl;
 }
 
-static size_t grid16_lds(const sba_handle *h)
+static size_t grid16_lds(const sba_handle *h) { return grid16_plan(h).lds; }
+
+// Byte sizes of a compact grid's sub-directory and fine blocks as the build
+// allocates them (one-element placeholders when nothing is mixed).
+static void grid16_bytes(const sba_handle *h, uint64_t *sub_b, uint64_t *blk_b)
 {
-    size_t lds = 0;
-    (void)grid16_mode(h, &lds);
-    return lds;
+    const int qs = h->tile_log2 - h->sub_log2;
+    const bool sub = qs > 0;
+    *sub_b = sub ? (uint64_t)std::max<int64_t>(h->n_blocks << (2 * qs), 1) * 4 : 4;
+    const int fl = sub ? h->sub_log2 : h->tile_log2;
+    const int64_t nfine = sub ? h->n_sub : h->n_blocks;
+    *blk_b = (uint64_t)std::max<int64_t>(nfine << (2 * fl), 1) * 2;
+}
+
+// The LDS-directory grid probe takes the handle: compact codes, directory and
+// bins within the LDS, gathered arrays addressable with 32-bit offsets.
+static bool grid16_fits(const sba_handle *h)
+{
+    if (!h->compact || grid16_lds(h) > GRID16_LDS_MAX) return false;
+    uint64_t a = 0, b = 0;
+    grid16_bytes(h, &a, &b);
+    return a <= 0xffffffffull && b <= 0xffffffffull;
 }
 
 // 16 or more waves per CU: workgroups of 512 threads when two fit in the LDS
@@ -1065,21 +1181,26 @@ static void grid16_shape(size_t lds, int *block, int *per_cu)
 typedef void (*grid16_fn)(const int4 *, const longlong2 *, const int32_t *, const int64_t *,
                           int64_t, Grid16, Agg, uint64_t *, int64_t *);
 
-template <bool VALS, bool SUB, int BLOCK>
+template <bool VALS, int LEV, int BLOCK>
 static grid16_fn grid16_pick_sets(int sets)
 {
-    if (sets == SETS_BINS) return k_probe_grid16<VALS, SUB, SETS_BINS, BLOCK>;
-    if (sets == SETS_LDS) return k_probe_grid16<VALS, SUB, SETS_LDS, BLOCK>;
-    return k_probe_grid16<VALS, SUB, SETS_GLOBAL, BLOCK>;
+    if (sets == SETS_BINS) return k_probe_grid16<VALS, LEV, SETS_BINS, BLOCK>;
+    if (sets == SETS_LDS) return k_probe_grid16<VALS, LEV, SETS_LDS, BLOCK>;
+    return k_probe_grid16<VALS, LEV, SETS_GLOBAL, BLOCK>;
+}
+
+template <bool VALS, int BLOCK>
+static grid16_fn grid16_pick_lev(int lev, int sets)
+{
+    if (lev == 2) return grid16_pick_sets<VALS, 2, BLOCK>(sets);
+    if (lev == 1) return grid16_pick_sets<VALS, 1, BLOCK>(sets);
+    return grid16_pick_sets<VALS, 0, BLOCK>(sets);
 }
 
 template <int BLOCK>
-static grid16_fn grid16_pick(bool vals, bool sub, int sets)
+static grid16_fn grid16_pick(bool vals, int lev, int sets)
 {
-    if (vals) return sub ? grid16_pick_sets<true, true, BLOCK>(sets)
-                         : grid16_pick_sets<true, false, BLOCK>(sets);
-    return sub ? grid16_pick_sets<false, true, BLOCK>(sets)
-               : grid16_pick_sets<false, false, BLOCK>(sets);
+    return vals ? grid16_pick_lev<true, BLOCK>(lev, sets) : grid16_pick_lev<false, BLOCK>(lev, sets);
 }
 
 static int launch_grid16(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
@@ -1104,20 +1225,25 @@ static int launch_grid16(const int32_t *xy, const int64_t *values, int64_t n, co
     g.sub = h->sub;
     g.blocks16 = h->blocks16;
     g.np = (uint32_t)h->n_polys;
-    size_t lds = 0;
-    g.sets = (uint32_t)grid16_mode(h, &lds);
+    const Grid16Plan pl = grid16_plan(h);
+    const size_t lds = pl.lds;
+    g.sets = (uint32_t)pl.sets;
     g.n_ids = (uint32_t)h->n_set_ids;
+    g.nsub = pl.nsub;
+    g.nsub16 = pl.nsub16;
     Agg A{h->set_off, h->set_ids, (uint32_t)h->n_polys, (uint32_t)h->n_sets};
     const int32_t np = h->n_polys;
     const bool vals = values != nullptr && sums != nullptr;
-    const bool sub = h->sub_log2 < h->tile_log2;
     int block = 0, per_cu = 0;
     grid16_shape(lds, &block, &per_cu);
     const int64_t npairs = n >> 1;
     int64_t nb = std::min<int64_t>((npairs + block - 1) / block, (int64_t)cu_count() * per_cu);
+    // the kernel's byte offsets inside a trip (16 B x PROBE_UNROLL pairs per
+    // lane of the grid) are 32-bit
+    nb = std::min<int64_t>(nb, ((int64_t)1 << 26) / ((int64_t)block * PROBE_UNROLL));
     if (nb < 1) nb = 1;
-    grid16_fn kern = block == 512 ? grid16_pick<512>(vals, sub, (int)g.sets)
-                                  : grid16_pick<1024>(vals, sub, (int)g.sets);
+    grid16_fn kern = block == 512 ? grid16_pick<512>(vals, pl.lev, pl.sets)
+                                  : grid16_pick<1024>(vals, pl.lev, pl.sets);
     // dynamic LDS above 64 KB has to be allowed explicitly
     (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
@@ -1411,8 +1537,7 @@ int probe_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_
         return 0;
     }
     if (h->kind == SBA_KIND_GRID) {
-        if (h->compact && grid16_lds(h) <= GRID16_LDS_MAX)
-            return launch_grid16(xy, values, n, h, counts, sums, st);
+        if (grid16_fits(h)) return launch_grid16(xy, values, n, h, counts, sums, st);
         return launch_layout<0>(xy, values, n, h, counts, sums, st);
     }
     if (search == SBA_SEARCH_LEARNED) {
@@ -1449,12 +1574,11 @@ extern "C" const char *sba_probe_kernel(const sba_handle *h, int with_values)
     static thread_local char buf[96];
     if (!h || h->n_polys == 0) return "";
     const char *v = with_values ? "true" : "false";
-    if (h->kind == SBA_KIND_GRID && h->compact && grid16_lds(h) <= GRID16_LDS_MAX) {
-        size_t lds = 0;
-        int sets = grid16_mode(h, &lds), block = 0, per_cu = 0;
-        grid16_shape(lds, &block, &per_cu);
-        snprintf(buf, sizeof(buf), "k_probe_grid16<%s, %s, %d, %d>", v,
-                 h->sub_log2 < h->tile_log2 ? "true" : "false", sets, block);
+    if (h->kind == SBA_KIND_GRID && grid16_fits(h)) {
+        const Grid16Plan pl = grid16_plan(h);
+        int block = 0, per_cu = 0;
+        grid16_shape(pl.lds, &block, &per_cu);
+        snprintf(buf, sizeof(buf), "k_probe_grid16<%s, %d, %d, %d>", v, pl.lev, pl.sets, block);
         return buf;
     }
     int layout = h->kind == SBA_KIND_GRID ? 0 : (h->search == SBA_SEARCH_LEARNED ? 2 : 1);
@@ -1504,6 +1628,13 @@ extern "C" int sba_debug_learned_fallbacks(const sba_handle *h, const int32_t *x
     RC(ws.sync());
     *fallbacks = (int64_t)hfb[0];
     *mismatches = (int64_t)hfb[1];
+    return 0;
+}
+
+extern "C" int sba_debug_grid16_lsub(int mode)
+{
+    if (mode != -1 && mode != 0) return SBA_EINVAL;
+    g_grid16_lsub = mode;
     return 0;
 }
 

@@ -293,7 +293,8 @@ def test_compact_and_wide_formats_agree(sba, orc, eps):
         A.close()
 
 
-@pytest.mark.parametrize("tl,sl", [(6, 2), (6, 3), (6, 4), (6, 6), (8, 4), (8, 5), (10, 4)])
+@pytest.mark.parametrize("tl,sl", [(4, 1), (6, 1), (6, 2), (6, 3), (6, 4), (6, 6), (8, 4), (8, 5),
+                                   (10, 4)])
 @pytest.mark.parametrize("wide", [0, 1])
 def test_sub_tile_levels(sba, orc, tl, sl, wide):
     """Every tile / sub-tile split, in both formats, stores the oracle's cell
@@ -322,16 +323,53 @@ def test_sub_tile_levels(sba, orc, tl, sl, wide):
     xy = rng.integers(-50, 1600, size=2 * n).astype(np.int32)
     vals = rng.integers(100, 10000, size=n).astype(np.int64)
     want_c, want_s = O.aggregate(xy, vals)
-    c, s = run_agg(A, xy, vals)
-    np.testing.assert_array_equal(c, want_c)
-    np.testing.assert_array_equal(s, want_s)
+    # the sub-directory staged in LDS where it fits, and read from global memory
+    for lsub in (-1, 0):
+        sba.lib().sba_debug_grid16_lsub(lsub)
+        try:
+            c, s = run_agg(A, xy, vals)
+        finally:
+            sba.lib().sba_debug_grid16_lsub(-1)
+        np.testing.assert_array_equal(c, want_c)
+        np.testing.assert_array_equal(s, want_s)
 
 
 def test_sub_level_rejects_bad_split(sba):
     polys = star_polygons(3, 9, 20.0, 400.0, 1500, 78)
-    for tl, sl in ((5, 6), (6, 1)):
+    for tl, sl in ((5, 6), (6, -1)):
         with pytest.raises(RuntimeError):
             sba.Approx.from_polygons(polys, 5, tile_log2=tl, sub_log2=sl)
+
+
+@pytest.mark.parametrize("eps", [100, 1000, 10000])
+def test_lds_sub_directory_city(sba, orc, eps):
+    """City partition with the automatic layout: where the 16-bit
+    sub-directory fits the LDS beside the directory and the bins (10 m, 100 m)
+    the probe stages it there (level 2 in the kernel name) and must give the
+    oracle's answer; the same handle read through the global sub-directory
+    (level 1) too."""
+    from gen import city_polygons
+    polys = city_polygons()
+    xy, vals = city_points(1_000_001)
+    want_c, want_s = orc.Approx(polys, eps).aggregate(xy, vals)
+    A = sba.Approx.from_polygons(polys, eps)
+    info = A.info()
+    kern = A.probe_kernel(True)
+    if eps >= 1000:
+        assert info["sub_log2"] < info["tile_log2"]
+        assert kern.startswith("k_probe_grid16<true, 2,"), kern
+    for lsub in (-1, 0):
+        sba.lib().sba_debug_grid16_lsub(lsub)
+        try:
+            c, s = run_agg(A, xy, vals)
+            c2, _ = run_agg(A, xy, None)
+            if lsub == 0 and info["sub_log2"] < info["tile_log2"]:
+                assert A.probe_kernel(True).startswith("k_probe_grid16<true, 1,")
+        finally:
+            sba.lib().sba_debug_grid16_lsub(-1)
+        np.testing.assert_array_equal(c, want_c)
+        np.testing.assert_array_equal(s, want_s)
+        np.testing.assert_array_equal(c2, want_c)
 
 
 @pytest.mark.parametrize("mode", [0, 1, 2])

@@ -602,6 +602,28 @@ def test_invariant_city_sample(orc, eps):
     assert int(ex.sum()) == 2_000_000           # a partition of the box
 
 
+def test_invariant_quadtree_polygons(orc):
+    """The quadtree workload's polygon set (40,000 jittered Voronoi cells, 32
+    to 675 vertices each; the analogue of Sec. 5.1's census blocks) at
+    eps = 1 m, 2M mixture points: no point farther than eps from the boundary
+    of a polygon it is wrongly counted in, no point missed, the cells a
+    partition of the box, and the check reports far points once the distance
+    bound is cut below the cell diagonal."""
+    from gen import city_points, quadtree_polygons
+    polys = quadtree_polygons()
+    xy, vals = city_points(2_000_000, config=3)
+    A = orc.Approx(polys, 100)
+    inv = A.invariant(xy)
+    assert inv["far"] == 0 and inv["false_neg"] == 0 and inv["differ"] > 0
+    ex, exs = A.exact(xy, vals)
+    ap, aps = A.aggregate(xy, vals)
+    assert int(ex.sum()) == 2_000_000           # a partition of the box
+    assert np.all(ex <= ap) and np.all(exs <= aps)
+    # the boundary cells' points lie up to a diagonal (70 sqrt 2 ~ 99 units)
+    # from the boundary; with a bound of 40 units some must be reported
+    assert A.invariant(xy, check_eps=40)["far"] > 0
+
+
 # ---------------------------------------------------------------- result range (Sec. 6)
 #
 # beta = the partial count over the boundary cells B(P); with the conservative
