@@ -6,13 +6,25 @@ resident in HBM: build the eps-approximation of every polygon
 cell layout) and answer the per-polygon COUNT and SUM of all points from it
 (sba_aggregate).  Prints one JSON line.
 
-Default workload (city scale): 100M points from a 50-component Gaussian
-mixture in a 40 km x 40 km box at 1 cm units, lognormal cents, 260 jittered
-Voronoi polygons, eps = 10 m.
+Default run, in one process:
+
+* city scale (the line's value): 100M points from a 50-component Gaussian
+  mixture in a 40 km x 40 km box at 1 cm units, lognormal cents, 260 jittered
+  Voronoi polygons, eps = 10 m; build + probe steps, the probe's roofline,
+  the oracle on the host as the CPU baseline (all cores and one thread, and
+  the exact crossing-number join as context);
+* quadtree (the ``quadtree`` object): 1e9 points of the same mixture, 40,000
+  jittered Voronoi polygons, eps = 1 m, Hilbert runs; binary search against
+  the learned index for points as generated, partitioned by the call, and in
+  Hilbert order; a 1e8-point sample compared with the oracle;
+* serving (the ``serving`` object): 1e9 resident points, three polygon sets
+  (260 / 4,000 / 40,000), viewport queries at zoom 10-18 with eps = one
+  pixel; capacity, then Poisson arrivals at 0.5 / 0.8 / 0.95 of it.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,26 +37,28 @@ sys.path.insert(0, ROOT)
 
 METRIC = "points/s + HBM GB/s, eps-bounded agg join; learned vs binary probe; p99 query ms"
 HBM_PEAK_GBS = 8000.0
+PROBE_SRC = os.path.join(ROOT, "paper_2010_12548_amd", "csrc", "probe.hip")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# HBM bytes per launch of the probe, from rocprofv3 counter runs of this
-# kernel version (FETCH_SIZE and WRITE_SIZE per dispatch, KiB, each scaled by
-# what the counter reads for a device copy of known size); keyed by the
-# workload it was taken on.  Re-measure after any change to the kernel.
-TRAFFIC = {
-    # profiles/city_eps10m_probe_counters.md: FETCH_SIZE 800568.97 KiB (x 1.99993: a 1 GiB
-    # device copy reads 524306.5 KiB), WRITE_SIZE 2080 KiB (x 1.00000)
-    ("city", 1000, 100_000_000, "k_probe_grid16<true, true, 2, 512>"):
-        {"fetch_bytes": 1639507396, "write_bytes": 2129920},
-}
+def probe_source_sha() -> str:
+    with open(PROBE_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+# HBM bytes per launch of the probe, from rocprofv3 counter runs (FETCH_SIZE
+# and WRITE_SIZE per dispatch, KiB, each scaled by what the counter reads for
+# a device copy of known size), keyed by the workload and by the hash of the
+# probe kernels' source the counters were taken on: any change to that source
+# makes the entry stale, and the line then reports null.
+TRAFFIC = {}
 
 
 def traffic_of(workload, eps, n, kernel):
-    t = TRAFFIC.get((workload, int(eps), int(n), kernel))
+    t = TRAFFIC.get((workload, int(eps), int(n), kernel, probe_source_sha()))
     return None if t is None else t["fetch_bytes"] + t["write_bytes"]
 
 
@@ -54,15 +68,19 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="city", choices=["city", "tiny", "quadtree", "serve"])
-    ap.add_argument("--queries", type=int, default=300, help="serve: queries per phase")
-    ap.add_argument("--serve", action="store_true",
-                    help="city: also run the viewport-query server on the resident points")
+    ap.add_argument("--queries", type=int, default=2000, help="serving: queries per load phase")
     ap.add_argument("--points", type=int, default=0, help="0 = the workload's size")
+    ap.add_argument("--qt-points", type=int, default=1_000_000_000,
+                    help="points of the quadtree and serving parts of the default run")
     ap.add_argument("--eps", type=int, default=0, help="0 = the workload's default")
     ap.add_argument("--layout", default="", choices=["", "grid", "hilbert"])
     ap.add_argument("--search", default="", choices=["", "binary", "learned"])
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
     ap.add_argument("--no-sweep", action="store_true", help="skip the eps sweep")
+    ap.add_argument("--no-quadtree", action="store_true", help="city: skip the quadtree part")
+    ap.add_argument("--no-serve", action="store_true", help="city: skip the serving part")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="city: skip result range, centre-sampled cells, polygon join, point index")
     ap.add_argument("--overlap", action="store_true",
                     help="also time the steps with builds and probes on two streams (step "
                          "k+1's build beside step k's probe), reported separately")
@@ -84,6 +102,22 @@ def parse():
     return ap.parse_args()
 
 
+def timed(torch, fn, reps):
+    """Mean ms of fn() over reps calls between two events on the current stream."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def same_result(cc, ss, res_c, res_s):
+    return bool(np.array_equal(cc.cpu().numpy().astype(np.uint64), res_c)
+                and np.array_equal(ss.cpu().numpy(), res_s))
+
+
 def probe_only(args, sba, torch, txy, tv, ro, vo, pxy, eps, layout, search, n):
     if args.copy_gib > 0:
         nb = int(args.copy_gib * 2**30)
@@ -102,38 +136,31 @@ def probe_only(args, sba, torch, txy, tv, ro, vo, pxy, eps, layout, search, n):
     for _ in range(args.warmup):
         a.aggregate(txy, tv, counts, sums)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        a.aggregate(txy, tv, counts, sums)
-    e1.record()
-    torch.cuda.synchronize()
-    t = e0.elapsed_time(e1) / args.steps
+    t = timed(torch, lambda: a.aggregate(txy, tv, counts, sums), args.steps)
     info = a.info()
     log(f"[bench] probe-only: {args.steps} calls, {t:.4f} ms per call, "
-        f"{16.0 * n / (t * 1e-3) / 1e9:.1f} GB/s algorithmic; approx {json.dumps(info)}")
+        f"{16.0 * n / (t * 1e-3) / 1e9:.1f} GB/s algorithmic; kernel {a.probe_kernel(True)}; "
+        f"probe source {probe_source_sha()}; approx {json.dumps(info)}")
     a.close()
 
 
-def serve_bench(args, torch, txy, tv, n_queries, with_big_set=True):
+# ------------------------------------------------------------------ serving
+
+def serve_bench(torch, txy, tv, n_queries, sets):
     """Viewport-query serving on the resident points: capacity (closed loop),
     then Poisson arrivals at 0.5 / 0.8 / 0.95 of it; p50 / p99 latency from
     arrival to result on the host."""
     import paper_2010_12548_amd.serve as serve
-    from gen import CITY_BOX, city_polygons, quadtree_polygons, seeds, viewport_queries
-    t0 = time.time()
-    sets = [city_polygons(), city_polygons(4000, (4, 40), config=5)]
-    if with_big_set:
-        sets.append(quadtree_polygons())
-    log(f"[bench] serve: polygon sets {[p.n_polys for p in sets]} in {time.time() - t0:.1f}s")
-    qs = viewport_queries(4 * n_queries, seeds(5)["queries"], n_sets=len(sets))
+    from gen import CITY_BOX, seeds, viewport_queries
+    qs = viewport_queries(4 * n_queries + 64, seeds(5)["queries"], n_sets=len(sets))
     Q = [serve.Query(q["vx"], q["vy"], q["vw"], q["eps"], q["set"], q["agg"]) for q in qs]
-    S = serve.Server(txy, tv, sets, (0, 0, CITY_BOX), G=256, mem_budget=16 << 30)
+    S = serve.Server(txy, tv, sets, (0, 0, CITY_BOX), G=256)
     out = {"points": int(txy.numel() // 2), "polygon_sets": [p.n_polys for p in sets],
-           "bucket_prep_ms": round(S.prep_ms, 2)}
+           "bucket_prep_ms": round(S.prep_ms, 2), "mem_budget_bytes": S.budget,
+           "queries_per_phase": n_queries}
     try:
         # warm-up, then capacity with everything submitted at once
-        [f.result() for f in [S.submit(q) for q in Q[:32]]]
+        [f.result() for f in [S.submit(q) for q in Q[-64:]]]
         phase = Q[:n_queries]
         t1 = time.perf_counter()
         res = [f.result() for f in [S.submit(q) for q in phase]]
@@ -167,7 +194,7 @@ def serve_bench(args, torch, txy, tv, n_queries, with_big_set=True):
             out["open_loop"].append(row)
             log(f"[bench] serve open loop: {json.dumps(row)}")
         # each result identical alone and in the mix
-        probe = Q[:24]
+        probe = Q[:48]
         mixed = [f.result() for f in [S.submit(q) for q in probe]]
         alone = [S.submit(q).result() for q in probe]
         same = all(np.array_equal(a.counts, m.counts) and
@@ -177,8 +204,12 @@ def serve_bench(args, torch, txy, tv, n_queries, with_big_set=True):
         out["peak_reserved_bytes"] = S.peak_reserved
     finally:
         S.close()
+    out["p50_ms_closed_loop"] = out["closed_loop"]["p50_ms"]
+    out["p99_ms_by_load"] = {str(r["load"]): r["p99_ms"] for r in out["open_loop"]}
     return out
 
+
+# ------------------------------------------------------------------ quadtree
 
 def hilbert_sorted(torch, txy, tv, info):
     """The points reordered by the Hilbert index of their cell on the handle's
@@ -210,6 +241,122 @@ def hilbert_sorted(torch, txy, tv, info):
     return sx, sv
 
 
+def quadtree_bench(args, sba, torch, n, polys, xy, vals, eps=100, cpu=True):
+    """Config 3/4: the Hilbert-run layout of 40,000 polygons at 1 m probed by
+    binary search and by the learned index over the same handle, for points
+    as generated, partitioned by the call, and in Hilbert order."""
+    dev = torch.device("cuda:0")
+    txy = torch.from_numpy(xy).to(dev)
+    tv = torch.from_numpy(vals).to(dev)
+    ro = torch.from_numpy(polys.ring_off).to(dev)
+    vo = torch.from_numpy(polys.vert_off).to(dev)
+    pxy = torch.from_numpy(polys.xy).to(dev)
+    alg_bytes = 16.0 * n
+    builds = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a = sba.Approx(ro, vo, pxy, eps, kind="hilbert", search="learned",
+                       log2_leaves=args.log2_leaves)
+        builds.append(1000.0 * (time.perf_counter() - t0))
+        if len(builds) < 3:
+            a.close()
+    ai = a.info()
+    out = {"workload": (f"quadtree: {n} Gaussian-mixture points, {polys.n_polys} jittered Voronoi "
+                        f"polygons, eps={eps / 100:g} m, Hilbert runs"),
+           "points": n, "polygons": polys.n_polys, "eps_units": eps, "n_runs": ai["n_runs"],
+           "level": ai["level"], "leaves": 1 << ai["log2_leaves"],
+           "max_leaf_err": ai["max_leaf_err"], "mean_leaf_err": ai["mean_leaf_err"],
+           "build_ms_median": round(float(np.median(builds)), 3),
+           "approx_MB": round(ai["bytes"] / 2**20, 1), "kernel_learned": a.probe_kernel(True)}
+    np_ = max(a.n_polys, 1)
+    cc = torch.empty(np_, dtype=torch.int64, device=dev)
+    ss = torch.empty_like(cc)
+
+    def row(t):
+        return {"probe_ms": round(t, 4), "points_per_s": n / (t * 1e-3),
+                "gbps": round(alg_bytes / (t * 1e-3) / 1e9, 1)}
+
+    direct, res = {}, {}
+    for srch in ("binary", "learned"):
+        for _ in range(2):
+            a.aggregate(txy, tv, cc, ss, search=srch)
+        torch.cuda.synchronize()
+        direct[srch] = row(timed(torch, lambda: a.aggregate(txy, tv, cc, ss, search=srch), 5))
+        res[srch] = (cc.cpu().numpy().astype(np.uint64), ss.cpu().numpy())
+    res_c, res_s = res["binary"]
+    identical = bool(np.array_equal(res["learned"][0], res_c)
+                     and np.array_equal(res["learned"][1], res_s))
+    fb, mm = a.learned_fallbacks(txy)
+    out["direct"] = direct
+    log(f"[bench] quadtree direct: {json.dumps(direct)}")
+    # points partitioned into coarse Hilbert regions by the call itself
+    scratch = torch.empty(a.scratch_bytes(n), dtype=torch.uint8, device=dev)
+    part = {}
+    for srch in ("binary", "learned"):
+        a.aggregate_partitioned(txy, tv, cc, ss, search=srch, scratch=scratch)
+        torch.cuda.synchronize()
+        part[srch] = row(timed(torch, lambda: a.aggregate_partitioned(
+            txy, tv, cc, ss, search=srch, scratch=scratch), 3))
+        part[srch]["same_as_direct"] = same_result(cc, ss, res_c, res_s)
+    del scratch
+    out["partitioned"] = part
+    log(f"[bench] quadtree partitioned: {json.dumps(part)}")
+    # the same points in the Hilbert order of their cells (a resident layout
+    # a serving system keeps): neighbouring lookups share cache lines
+    sx, sv = hilbert_sorted(torch, txy, tv, ai)
+    srt = {}
+    for srch in ("binary", "learned"):
+        a.aggregate(sx, sv, cc, ss, search=srch)
+        torch.cuda.synchronize()
+        srt[srch] = row(timed(torch, lambda: a.aggregate(sx, sv, cc, ss, search=srch), 3))
+        srt[srch]["same_as_direct"] = same_result(cc, ss, res_c, res_s)
+        task = sba.Task(a, sx, sv, 0, n, None, cc, ss, search=srch)
+        sba.aggregate_batch([task])
+        torch.cuda.synchronize()
+        tb = timed(torch, lambda: sba.aggregate_batch([task]), 3)
+        srt[srch]["batch_probe_ms"] = round(tb, 4)
+        srt[srch]["batch_same"] = same_result(cc, ss, res_c, res_s)
+    del sx, sv
+    out["hilbert_sorted"] = srt
+    log(f"[bench] quadtree sorted: {json.dumps(srt)}")
+    out["identical"] = bool(identical and all(v["same_as_direct"] for v in part.values())
+                            and all(v["same_as_direct"] and v["batch_same"] for v in srt.values()))
+    out["fallbacks"] = fb
+    out["learned_ne_binary"] = mm
+    out["learned_speedup"] = {
+        "direct": round(direct["binary"]["probe_ms"] / direct["learned"]["probe_ms"], 3),
+        "partitioned": round(part["binary"]["probe_ms"] / part["learned"]["probe_ms"], 3),
+        "hilbert_sorted": round(srt["binary"]["probe_ms"] / srt["learned"]["probe_ms"], 3)}
+    # a sample of the points against the oracle (the same approximation,
+    # built and probed on the host)
+    if cpu:
+        import oracle
+        m = min(n, 100_000_000)
+        t0 = time.perf_counter()
+        O = oracle.Approx(polys, eps)
+        tb = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oc, os_ = O.aggregate(xy[:2 * m], vals[:m])
+        ta = time.perf_counter() - t0
+        c2, s2 = a.aggregate(txy[:2 * m], tv[:m], search="learned")
+        out["oracle_sample"] = {"points": m, "matches_gpu": same_result(c2, s2, oc, os_),
+                                "oracle_build_s": round(tb, 3), "oracle_aggregate_s": round(ta, 3),
+                                "oracle_points_per_s": m / ta, "cores": int(O.threads_used)}
+        log(f"[bench] quadtree oracle sample: {json.dumps(out['oracle_sample'])}")
+    # the polygon-polygon join of this set with the city set (Sec. 4)
+    from gen import city_polygons
+    out["polygon_join"] = join_bench(sba, torch, polys, city_polygons(), eps,
+                                     "40,000-cell partition with the 260-cell partition")
+    if not args.no_pindex:
+        scan = direct["learned"]["probe_ms"]
+        out["point_index"] = pindex_bench(sba, torch, txy, tv, ro, vo, pxy, eps, res_c, res_s, scan)
+    a.close()
+    return out
+
+
+# ------------------------------------------------------------------ city extras
+
 def pindex_bench(sba, torch, txy, tv, ro, vo, pxy, eps, res_c, res_s, scan_ms):
     """Point-side pre-aggregation (Sec. 3, point indexing): build the point
     index once, then answer the same query from the runs of a Hilbert handle
@@ -235,16 +382,8 @@ def pindex_bench(sba, torch, txy, tv, ro, vo, pxy, eps, res_c, res_s, scan_ms):
         for _ in range(2):
             ix.aggregate(a, srch, counts, sums)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 10
-        e0.record()
-        for _ in range(reps):
-            ix.aggregate(a, srch, counts, sums)
-        e1.record()
-        torch.cuda.synchronize()
-        t = e0.elapsed_time(e1) / reps
-        same = bool(np.array_equal(counts[:a.n_polys].cpu().numpy().astype(np.uint64), res_c)
-                    and np.array_equal(sums[:a.n_polys].cpu().numpy(), res_s))
+        t = timed(torch, lambda: ix.aggregate(a, srch, counts, sums), 10)
+        same = same_result(counts[:a.n_polys], sums[:a.n_polys], res_c, res_s)
         out[srch] = {"query_ms": round(t, 4), "points_per_s_equiv": n / (t * 1e-3),
                      "speedup_vs_scan": round(scan_ms / t, 2), "same_as_scan": same}
     a.close()
@@ -277,6 +416,119 @@ def join_bench(sba, torch, a, b, eps, desc):
     return out
 
 
+def city_extras(args, sba, torch, txy, tv, ro, vo, pxy, eps, info, kw, counts, sums, res_c,
+                res_s, polys, probe_avg, n):
+    extra = {}
+    # result range [alpha - beta, alpha] (Sec. 6): beta from a boundary-only
+    # approximation over the same points
+    t0 = time.perf_counter()
+    bh = sba.Approx(ro, vo, pxy, eps, boundary_only=True, tile_log2=info["tile_log2"],
+                    sub_log2=info["sub_log2"])
+    t_bb = 1000.0 * (time.perf_counter() - t0)
+    bc = torch.empty_like(counts)
+    bs = torch.empty_like(sums)
+    bh.aggregate(txy, tv, bc, bs)
+    torch.cuda.synchronize()
+    beta_probe = timed(torch, lambda: bh.aggregate(txy, tv, bc, bs), 10)
+    beta = bc.cpu().numpy().astype(np.float64)
+    alpha = res_c.astype(np.float64)
+    a_full = sba.Approx(ro, vo, pxy, eps, **kw)
+    rr = sba.aggregate_range(a_full, bh, txy, tv)
+    torch.cuda.synchronize()
+    one_pass = timed(torch, lambda: sba.aggregate_range(a_full, bh, txy, tv), 10)
+    rr = sba.aggregate_range(a_full, bh, txy, tv)
+    same = bool(np.array_equal(rr[0].cpu().numpy().astype(np.uint64), res_c)
+                and np.array_equal(rr[2].cpu().numpy(), bc.cpu().numpy()))
+    extra["result_range"] = {
+        "beta_build_ms": round(t_bb, 3), "beta_probe_ms": round(beta_probe, 4),
+        "alpha_plus_beta_one_pass_ms": round(one_pass, 4),
+        "one_pass_kernel": sba.range_kernel(a_full, bh), "one_pass_same_as_two": same,
+        "beta_over_alpha_total": float(beta.sum() / max(alpha.sum(), 1.0)),
+        "beta_over_alpha_median_polygon": float(np.median(beta / np.maximum(alpha, 1.0))),
+        "kernel": bh.probe_kernel(True)}
+    a_full.close()
+    bh.close()
+    log(f"[bench] result range: {json.dumps(extra['result_range'])}")
+    # the non-conservative approximation (cells whose centre is inside)
+    t0 = time.perf_counter()
+    ch = sba.Approx(ro, vo, pxy, eps, centre_sampled=True, tile_log2=args.tile_log2,
+                    sub_log2=args.sub_log2)
+    t_cb = 1000.0 * (time.perf_counter() - t0)
+    cc = torch.empty_like(counts)
+    cs = torch.empty_like(sums)
+    ch.aggregate(txy, tv, cc, cs)
+    torch.cuda.synchronize()
+    t_cp = timed(torch, lambda: ch.aggregate(txy, tv, cc, cs), 10)
+    extra["centre_sampled"] = {
+        "build_ms": round(t_cb, 3), "probe_ms": round(t_cp, 4),
+        "counted_over_points": int(cc.sum().item()) / n,
+        "conservative_counted_over_points": float(res_c.sum()) / n,
+        "kernel": ch.probe_kernel(True)}
+    ch.close()
+    log(f"[bench] centre-sampled: {json.dumps(extra['centre_sampled'])}")
+    extra["polygon_join"] = join_bench(sba, torch, polys, polys, eps, "city partition with itself")
+    if not args.no_pindex:
+        extra["point_index"] = pindex_bench(sba, torch, txy, tv, ro, vo, pxy, eps, res_c, res_s,
+                                            probe_avg)
+    return extra
+
+
+def eps_sweep(sba, torch, txy, tv, ro, vo, pxy, counts, sums, n):
+    sweep = {}
+    for e in (100, 1000, 10000):
+        a = sba.Approx(ro, vo, pxy, e, kind="grid")
+        for _ in range(2):
+            a.aggregate(txy, tv, counts, sums)
+        torch.cuda.synchronize()
+        t = timed(torch, lambda: a.aggregate(txy, tv, counts, sums), 10)
+        ai = a.info()
+        sweep[f"{e / 100:g}m"] = {"probe_ms": round(t, 4), "probe_points_per_s": n / (t * 1e-3),
+                                  "probe_gbps": round(16.0 * n / (t * 1e-3) / 1e9, 1),
+                                  "build_ms": round(ai["build_ms"], 3),
+                                  "tile": 1 << ai["tile_log2"], "sub": 1 << ai["sub_log2"],
+                                  "blocks": ai["n_blocks"], "approx_MB": round(ai["bytes"] / 2**20, 2),
+                                  "kernel": a.probe_kernel(True)}
+        a.close()
+    log(f"[bench] eps sweep: {json.dumps(sweep)}")
+    return sweep
+
+
+def cpu_baselines(polys, xy, vals, eps, n, res_c, res_s, compare):
+    """The oracle on the host: the same approximate join on all cores (the
+    baseline), on one thread, and the exact crossing-number join as context."""
+    import oracle
+    t0 = time.perf_counter()
+    O = oracle.Approx(polys, eps)
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oc, os_ = O.aggregate(xy, vals)
+    ta = time.perf_counter() - t0
+    cores = int(O.threads_used)
+    cpu = {"value": n / (tb + ta), "unit": "points/s", "cores": cores, "kind": "oracle",
+           "sample": (f"oracle build of all {polys.n_polys} polygons ({tb:.2f}s) + oracle "
+                      f"aggregate of all {n} points ({ta:.2f}s) on {cores} threads")}
+    if compare:
+        cpu["matches_gpu"] = bool(np.array_equal(oc, res_c) and np.array_equal(os_, res_s))
+    m1 = min(n, 30_000_000)
+    t0 = time.perf_counter()
+    O.aggregate(xy[:2 * m1], vals[:m1], nthreads=1)
+    t1 = time.perf_counter() - t0
+    cpu["single_thread"] = {"value": m1 / (t1 + tb), "unit": "points/s", "cores": 1,
+                            "sample": f"oracle aggregate of the first {m1} points ({t1:.2f}s) "
+                                      f"on one thread, plus the build"}
+    me = min(n, 20_000_000)
+    t0 = time.perf_counter()
+    O.exact(xy[:2 * me], vals[:me])
+    te = time.perf_counter() - t0
+    cpu["exact_join"] = {"value": me / te, "unit": "points/s", "cores": int(O.threads_used),
+                         "sample": f"exact crossing-number join (bounding-box filter, then "
+                                   f"point-in-polygon) of the first {me} points ({te:.2f}s)"}
+    log(f"[bench] cpu oracle: {json.dumps(cpu)}")
+    return cpu
+
+
+# ------------------------------------------------------------------ main
+
 def workload(args):
     from gen import city_points, city_polygons, quadtree_polygons, tiny_workload
     if args.workload == "tiny":
@@ -294,13 +546,6 @@ def workload(args):
         desc = (f"city: {n} Gaussian-mixture points (50 comps, sigma 200-3000 m) in 40x40 km at "
                 f"1 cm, lognormal(7,0.8) cents, 260 jittered Voronoi polygons, eps={eps / 100:g} m")
         return xy, vals, polys, eps, desc, "grid"
-    if args.workload == "serve":
-        n = args.points or 1_000_000_000
-        xy, vals = city_points(n, config=5)
-        desc = (f"serve: {n} resident Gaussian-mixture points, polygon sets of 260 / 4,000 / "
-                f"40,000 jittered Voronoi cells, viewport queries at zoom 10-18 with eps = one "
-                f"pixel, Poisson arrivals")
-        return xy, vals, None, 0, desc, "grid"
     n = args.points or 1_000_000_000
     polys = quadtree_polygons()
     xy, vals = city_points(n, config=3)
@@ -308,6 +553,25 @@ def workload(args):
     desc = (f"quadtree: {n} Gaussian-mixture points, 40,000 jittered Voronoi polygons, "
             f"eps={eps / 100:g} m, Hilbert runs")
     return xy, vals, polys, eps, desc, "hilbert"
+
+
+def serving_part(args, torch, qt_polys=None):
+    """Config 5 on its own 1e9 resident points (freed afterwards)."""
+    from gen import city_points, city_polygons, quadtree_polygons
+    t0 = time.time()
+    n = args.points if args.workload == "serve" and args.points else args.qt_points
+    xy, vals = city_points(n, config=5)
+    sets = [city_polygons(), city_polygons(4000, (4, 40), config=5),
+            qt_polys if qt_polys is not None else quadtree_polygons()]
+    log(f"[bench] serve: {n} points, polygon sets {[p.n_polys for p in sets]} in "
+        f"{time.time() - t0:.1f}s")
+    txy = torch.from_numpy(xy).cuda()
+    tv = torch.from_numpy(vals).cuda()
+    del xy, vals
+    res = serve_bench(torch, txy, tv, args.queries, sets)
+    del txy, tv
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -330,25 +594,26 @@ def main():
     if args.force_wide:
         sba.lib().sba_debug_force_wide_grid(1)
     dev = torch.device("cuda:0")
-    t0 = time.time()
+    t_start = time.time()
+
+    if args.workload == "serve":
+        res = serving_part(args, torch)
+        cl = res["closed_loop"]
+        print(json.dumps({"metric": METRIC, "value": cl["queries_per_s"], "unit": "queries/s",
+                          "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
+                          "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+                          "config": {"workload": "serve: 1e9 resident points, 3 polygon sets, "
+                                                 "viewport queries at zoom 10-18"},
+                          "serving": res}), flush=True)
+        return
+
     xy, vals, polys, eps, desc, layout = workload(args)
     layout = args.layout or layout
     search = args.search or ("learned" if layout == "hilbert" else "binary")
     n = xy.shape[0] // 2
-    log(f"[bench] workload ready in {time.time() - t0:.1f}s: {desc}")
+    log(f"[bench] workload ready in {time.time() - t_start:.1f}s: {desc}")
     txy = torch.from_numpy(xy).to(dev)
     tv = torch.from_numpy(vals).to(dev)
-    if args.workload == "serve":
-        del xy, vals
-        res = serve_bench(args, torch, txy, tv, args.queries)
-        cl = res["closed_loop"]
-        p99 = max(r["p99_ms"] for r in res["open_loop"])
-        print(json.dumps({"metric": METRIC, "value": cl["queries_per_s"], "unit": "queries/s",
-                          "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
-                          "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-                          "config": {"workload": desc}, "p99_ms_worst_open_loop": p99,
-                          "serving": res}), flush=True)
-        return
     ro = torch.from_numpy(polys.ring_off).to(dev)
     vo = torch.from_numpy(polys.vert_off).to(dev)
     pxy = torch.from_numpy(polys.xy).to(dev)
@@ -363,9 +628,7 @@ def main():
 
     # A step builds the approximation and probes every point with it, both
     # on the current stream.  --overlap also times the same steps with the
-    # builds on one stream and the probes on another (the build of step k+1,
-    # host-bound, beside the probe of step k, bound by HBM bandwidth; every
-    # step still does its whole build and its whole probe) and reports that
+    # builds on one stream and the probes on another and reports that
     # figure separately.
     import contextlib
     bstream = pstream = None
@@ -410,21 +673,12 @@ def main():
     probe_in_step = float(np.mean(probe_ms))
     alg_bytes = 16.0 * n          # 8 B x,y + 8 B value per point
     # the probe kernel's own time: back-to-back calls on the current stream
-    # between one pair of events (the per-step events above also hold the
-    # launch gaps of a step); each call is a zeroing kernel of the outputs
-    # (a few microseconds) and the probe kernel
+    # between one pair of events (each call: a zeroing kernel of the outputs,
+    # a few microseconds, and the probe kernel)
     last = handles[-1]
-    reps = max(args.steps, 10)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        last.aggregate(txy, tv, counts, sums)
-    e1.record()
-    torch.cuda.synchronize()
-    probe_avg = e0.elapsed_time(e1) / reps
+    probe_avg = timed(torch, lambda: last.aggregate(txy, tv, counts, sums), max(args.steps, 10))
     achieved = alg_bytes / (probe_avg * 1e-3) / 1e9
-    # build time on its own (in a one-stream step loop a build's first wait
-    # also covers the previous step's probe)
+    # build time on its own
     iso = []
     for _ in range(5):
         torch.cuda.synchronize()
@@ -436,242 +690,42 @@ def main():
     ser = f" (two streams: {ms_step_overlap:.3f} ms/step)" if ms_step_overlap else ""
     log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step{ser}, probe in step "
         f"{probe_in_step:.4f} ms, probe back-to-back {probe_avg:.4f} ms, build alone median "
-        f"{build_iso:.3f} ms")
-
+        f"{build_iso:.3f} ms, kernel {kernel}")
     for h in handles:
         h.close()
     res_c = counts.cpu().numpy().astype(np.uint64)
     res_s = sums.cpu().numpy()
 
     extra = {}
-    if layout == "hilbert":
-        # binary and learned probe on the same handle, identical results required
-        a = sba.Approx(ro, vo, pxy, eps, kind="hilbert", search="learned",
-                       log2_leaves=args.log2_leaves)
-        out = {}
-        for srch in ("binary", "learned"):
-            cc = torch.empty_like(counts)
-            ss = torch.empty_like(sums)
-            for _ in range(2):
-                a.aggregate(txy, tv, cc, ss, search=srch)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            reps = 5
-            e0.record()
-            for _ in range(reps):
-                a.aggregate(txy, tv, cc, ss, search=srch)
-            e1.record()
-            torch.cuda.synchronize()
-            t = e0.elapsed_time(e1) / reps
-            out[srch] = {"probe_ms": round(t, 4), "points_per_s": n / (t * 1e-3),
-                         "gbps": alg_bytes / (t * 1e-3) / 1e9,
-                         "_res": (cc.cpu().numpy(), ss.cpu().numpy())}
-        same = (np.array_equal(out["binary"]["_res"][0], out["learned"]["_res"][0])
-                and np.array_equal(out["binary"]["_res"][1], out["learned"]["_res"][1]))
-        for v in out.values():
-            v.pop("_res")
-        ai = a.info()
-        fb, mm = a.learned_fallbacks(txy)
-        # the same probes over the points in Hilbert order of their cells (a
-        # resident layout a serving system would keep): lookups of neighbouring
-        # points share cache lines; results must not change
-        sx, sv = hilbert_sorted(torch, txy, tv, ai)
-        srt = {}
-        for srch in ("binary", "learned"):
-            cc = torch.empty_like(counts)
-            ss = torch.empty_like(sums)
-            a.aggregate(sx, sv, cc, ss, search=srch)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(3):
-                a.aggregate(sx, sv, cc, ss, search=srch)
-            e1.record()
-            torch.cuda.synchronize()
-            t = e0.elapsed_time(e1) / 3
-            srt[srch] = {"probe_ms": round(t, 4), "points_per_s": n / (t * 1e-3),
-                         "gbps": alg_bytes / (t * 1e-3) / 1e9,
-                         "same_as_unsorted": bool(np.array_equal(cc.cpu().numpy(), res_c.astype(np.int64))
-                                                  and np.array_equal(ss.cpu().numpy(), res_s))}
-            # the batch entry point over the same range: workgroups take
-            # contiguous items and count them in an LDS table of cell codes,
-            # which sorted points keep small
-            task = sba.Task(a, sx, sv, 0, n, None, cc, ss, search=srch)
-            sba.aggregate_batch([task])
-            torch.cuda.synchronize()
-            e0.record()
-            for _ in range(3):
-                sba.aggregate_batch([task])
-            e1.record()
-            torch.cuda.synchronize()
-            tb = e0.elapsed_time(e1) / 3
-            srt[srch]["batch_probe_ms"] = round(tb, 4)
-            srt[srch]["batch_points_per_s"] = n / (tb * 1e-3)
-            srt[srch]["batch_same"] = bool(np.array_equal(cc.cpu().numpy(), res_c.astype(np.int64))
-                                           and np.array_equal(ss.cpu().numpy(), res_s))
-        del sx, sv
-        extra["hilbert_sorted_points"] = srt
-        # the points as generated, partitioned into 256 coarse regions by the
-        # call itself and then probed region by region (scratch 16 B/point)
-        scratch = torch.empty(a.scratch_bytes(n), dtype=torch.uint8, device=dev)
-        part = {}
-        for srch in ("binary", "learned"):
-            cc = torch.empty_like(counts)
-            ss = torch.empty_like(sums)
-            a.aggregate_partitioned(txy, tv, cc, ss, search=srch, scratch=scratch)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(3):
-                a.aggregate_partitioned(txy, tv, cc, ss, search=srch, scratch=scratch)
-            e1.record()
-            torch.cuda.synchronize()
-            t = e0.elapsed_time(e1) / 3
-            part[srch] = {"ms": round(t, 4), "points_per_s": n / (t * 1e-3),
-                          "same_as_direct": bool(
-                              np.array_equal(cc.cpu().numpy(), res_c.astype(np.int64))
-                              and np.array_equal(ss.cpu().numpy(), res_s))}
-        del scratch
-        extra["partitioned_probe"] = part
-        log(f"[bench] partitioned probe: {json.dumps(part)}")
-        extra["learned_vs_binary"] = {**out, "identical": bool(same),
-                                      "speedup": out["binary"]["probe_ms"] / out["learned"]["probe_ms"],
-                                      "fallbacks": fb, "learned_ne_binary": mm,
-                                      "n_runs": ai["n_runs"], "max_leaf_err": ai["max_leaf_err"],
-                                      "mean_leaf_err": ai["mean_leaf_err"],
-                                      "leaves": 1 << ai["log2_leaves"]}
-        a.close()
-
-    if args.workload == "city":
-        # result range [alpha - beta, alpha] (Sec. 6): beta from a
-        # boundary-only approximation over the same points
-        t0 = time.perf_counter()
-        bh = sba.Approx(ro, vo, pxy, eps, boundary_only=True, tile_log2=info["tile_log2"],
-                        sub_log2=info["sub_log2"])
-        t_bb = 1000.0 * (time.perf_counter() - t0)
-        bc = torch.empty_like(counts)
-        bs = torch.empty_like(sums)
-        bh.aggregate(txy, tv, bc, bs)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(10):
-            bh.aggregate(txy, tv, bc, bs)
-        e1.record()
-        torch.cuda.synchronize()
-        beta_probe = e0.elapsed_time(e1) / 10
-        beta = bc.cpu().numpy().astype(np.float64)
-        alpha = res_c.astype(np.float64)
-        # alpha and beta in one pass over the points
-        a_full = sba.Approx(ro, vo, pxy, eps, **kw)
-        rr = sba.aggregate_range(a_full, bh, txy, tv)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(10):
-            rr = sba.aggregate_range(a_full, bh, txy, tv)
-        e1.record()
-        torch.cuda.synchronize()
-        one_pass = e0.elapsed_time(e1) / 10
-        same = bool(np.array_equal(rr[0].cpu().numpy().astype(np.uint64), res_c)
-                    and np.array_equal(rr[2].cpu().numpy(), bc.cpu().numpy()))
-        extra["result_range"] = {
-            "beta_build_ms": round(t_bb, 3), "beta_probe_ms": round(beta_probe, 4),
-            "alpha_plus_beta_one_pass_ms": round(one_pass, 4),
-            "one_pass_kernel": sba.range_kernel(a_full, bh),
-            "one_pass_same_as_two": same,
-            "beta_over_alpha_total": float(beta.sum() / max(alpha.sum(), 1.0)),
-            "beta_over_alpha_median_polygon": float(np.median(beta / np.maximum(alpha, 1.0))),
-            "kernel": bh.probe_kernel(True)}
-        a_full.close()
-        bh.close()
-        log(f"[bench] result range: {json.dumps(extra['result_range'])}")
-
-    if args.workload == "city":
-        # the non-conservative approximation (cells whose centre is inside):
-        # same probe kernel, no double counting on the partition's shared
-        # boundaries, misclassified points within eps/2
-        t0 = time.perf_counter()
-        ch = sba.Approx(ro, vo, pxy, eps, centre_sampled=True, tile_log2=args.tile_log2,
-                        sub_log2=args.sub_log2)
-        t_cb = 1000.0 * (time.perf_counter() - t0)
-        cc = torch.empty_like(counts)
-        cs = torch.empty_like(sums)
-        ch.aggregate(txy, tv, cc, cs)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(10):
-            ch.aggregate(txy, tv, cc, cs)
-        e1.record()
-        torch.cuda.synchronize()
-        csum = int(cc.sum().item())
-        extra["centre_sampled"] = {
-            "build_ms": round(t_cb, 3), "probe_ms": round(e0.elapsed_time(e1) / 10, 4),
-            "counted_over_points": csum / n,
-            "conservative_counted_over_points": float(res_c.sum()) / n,
-            "kernel": ch.probe_kernel(True)}
-        ch.close()
-        log(f"[bench] centre-sampled: {json.dumps(extra['centre_sampled'])}")
-
-    if args.workload == "city":
-        extra["polygon_join"] = join_bench(sba, torch, polys, polys, eps,
-                                           "city partition with itself")
-    if args.workload == "quadtree":
-        from gen import city_polygons
-        extra["polygon_join"] = join_bench(sba, torch, polys, city_polygons(), eps,
-                                           "40,000-cell partition with the 260-cell partition")
-
-    if args.workload in ("city", "quadtree") and not args.no_pindex:
-        extra["point_index"] = pindex_bench(sba, torch, txy, tv, ro, vo, pxy, eps, res_c, res_s,
-                                            probe_avg)
-
-    sweep = {}
+    if args.workload == "city" and not args.no_extras:
+        extra.update(city_extras(args, sba, torch, txy, tv, ro, vo, pxy, eps, info, kw, counts,
+                                 sums, res_c, res_s, polys, probe_avg, n))
+    sweep = None
     if args.workload == "city" and not args.no_sweep:
-        for e in (100, 1000, 10000):
-            a = sba.Approx(ro, vo, pxy, e, kind="grid")
-            for _ in range(2):
-                a.aggregate(txy, tv, counts, sums)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            reps = 10
-            e0.record()
-            for _ in range(reps):
-                a.aggregate(txy, tv, counts, sums)
-            e1.record()
-            torch.cuda.synchronize()
-            t = e0.elapsed_time(e1) / reps
-            ai = a.info()
-            sweep[f"{e / 100:g}m"] = {"probe_ms": round(t, 4), "probe_points_per_s": n / (t * 1e-3),
-                                      "probe_gbps": round(alg_bytes / (t * 1e-3) / 1e9, 1),
-                                      "build_ms": round(ai["build_ms"], 3),
-                                      "tile": 1 << ai["tile_log2"], "blocks": ai["n_blocks"],
-                                      "approx_MB": round(ai["bytes"] / 2**20, 2)}
-            a.close()
-        log(f"[bench] eps sweep: {json.dumps(sweep)}")
-
-    serving = None
-    if args.serve and args.workload == "city":
-        serving = serve_bench(args, torch, txy, tv, args.queries)
-
+        sweep = eps_sweep(sba, torch, txy, tv, ro, vo, pxy, counts, sums, n)
     cpu = None
     if not args.no_cpu:
-        import oracle
-        t0 = time.perf_counter()
-        O = oracle.Approx(polys, eps)
-        tb = time.perf_counter() - t0
-        sample = min(n, 200_000_000)
-        t0 = time.perf_counter()
-        oc, os_ = O.aggregate(xy[:2 * sample], vals[:sample])
-        ta = time.perf_counter() - t0
-        t_step = tb + ta * (n / sample)
-        cpu = {"value": n / t_step, "unit": "points/s", "cores": int(O.threads_used),
-               "kind": "oracle",
-               "sample": (f"oracle build of all {polys.n_polys} polygons ({tb:.2f}s) + oracle "
-                          f"aggregate of the first {sample} points ({ta:.2f}s), aggregate time "
-                          f"scaled to all {n} points")}
-        if sample == n and layout == "grid":
-            cpu["matches_gpu"] = bool(np.array_equal(oc, res_c) and np.array_equal(os_, res_s))
-        log(f"[bench] cpu oracle: {json.dumps(cpu)}")
+        cpu = cpu_baselines(polys, xy, vals, eps, n, res_c, res_s, compare=layout == "grid")
+    del txy, tv
+    torch.cuda.empty_cache()
+
+    quad = None
+    qt_polys = None
+    if args.workload == "quadtree":
+        quad = quadtree_bench(args, sba, torch, n, polys, xy, vals, eps=eps, cpu=not args.no_cpu)
+    elif args.workload == "city" and not args.no_quadtree:
+        from gen import city_points, quadtree_polygons
+        t0 = time.time()
+        qt_polys = quadtree_polygons()
+        qxy, qvals = city_points(args.qt_points, config=3)
+        log(f"[bench] quadtree workload ready in {time.time() - t0:.1f}s")
+        quad = quadtree_bench(args, sba, torch, args.qt_points, qt_polys, qxy, qvals,
+                              cpu=not args.no_cpu)
+        del qxy, qvals
+    torch.cuda.empty_cache()
+    serving = None
+    if args.workload == "city" and not args.no_serve:
+        serving = serving_part(args, torch, qt_polys)
 
     line = {
         "metric": METRIC,
@@ -694,17 +748,20 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_of(args.workload, eps, n, kernel),
-                     "kernel": kernel,
+                     "kernel": kernel, "probe_source": probe_source_sha(),
                      "algorithmic_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
         "probe_ms": probe_avg,
         "probe_ms_in_step": probe_in_step,
         "probe_points_per_s": n / (probe_avg * 1e-3),
         "build_ms_median": build_iso,
-        "approx": {k: info[k] for k in ("s", "gw", "gh", "tile_log2", "n_tiles", "n_blocks",
-                                        "n_sets", "n_segments", "n_boundary", "n_runs", "bytes")},
-        "eps_sweep": sweep or None,
+        "approx": {k: info[k] for k in ("s", "gw", "gh", "tile_log2", "sub_log2", "n_tiles",
+                                        "n_blocks", "n_sub", "n_sets", "n_segments",
+                                        "n_boundary", "n_runs", "bytes")},
+        "eps_sweep": sweep,
+        "quadtree": quad,
         "serving": serving,
+        "bench_wall_s": round(time.time() - t_start, 1),
         **extra,
     }
     print(json.dumps(line), flush=True)

@@ -82,13 +82,19 @@ class DeviceAllocator:
 
 class TorchAllocator(DeviceAllocator):
     """Builds take their device memory from torch's caching allocator on the
-    current device (so the library and torch share one pool).  ``fail_at``
-    (test support): refuse the k-th request (1-based) and count requests."""
+    current device (so the library and torch share one pool).  Counts the
+    bytes held (live_bytes) and their peak (peak_bytes, reset_peak()).
+    ``fail_at`` (test support): refuse the k-th request (1-based)."""
 
     def __init__(self, fail_at: int = 0):
         self.fail_at = int(fail_at)
         self.requests = 0
         self.live = {}
+        self.live_bytes = 0
+        self.peak_bytes = 0
+
+    def reset_peak(self):
+        self.peak_bytes = self.live_bytes
 
     def alloc(self, nbytes: int) -> int:
         torch = _torch()
@@ -97,11 +103,13 @@ class TorchAllocator(DeviceAllocator):
             return 0
         p = torch.cuda.caching_allocator_alloc(nbytes, torch.cuda.current_device())
         self.live[p] = nbytes
+        self.live_bytes += nbytes
+        self.peak_bytes = max(self.peak_bytes, self.live_bytes)
         return p
 
     def release(self, addr: int) -> None:
         if addr in self.live:
-            del self.live[addr]
+            self.live_bytes -= self.live.pop(addr)
             _torch().cuda.caching_allocator_delete(addr)
 
 

@@ -79,9 +79,9 @@ class Server:
     side) is the extent the bucket grid covers (G x G buckets).
     """
 
-    def __init__(self, xy, values, polygon_sets, box, G: int = 256, mem_budget: int = 8 << 30,
+    def __init__(self, xy, values, polygon_sets, box, G: int = 256, mem_budget: int | None = None,
                  max_batch: int = 256, kind: str = "grid", builders: int = 4,
-                 max_inflight: int = 1):
+                 max_inflight: int = 1, budget_fraction: float = 0.5):
         import torch
         self.torch = torch
         self.dev = xy.device
@@ -105,6 +105,12 @@ class Server:
                               torch.from_numpy(np.ascontiguousarray(ps.xy)).to(self.dev),
                               int(ps.n_polys), int(ps.xy.shape[0] // 2)))
         self.kind = kind
+        # admission budget: the given bytes, or a fraction of the device
+        # memory free once the point table and its bucketed copy are resident
+        # (hipMemGetInfo through torch)
+        if mem_budget is None:
+            free, _ = torch.cuda.mem_get_info(self.dev)
+            mem_budget = int(budget_fraction * free)
         self.budget = int(mem_budget)
         self.reserved = 0
         self.peak_reserved = 0
@@ -126,13 +132,18 @@ class Server:
 
     # ------------------------------------------------------------ helpers
     def estimate_bytes(self, q: Query) -> int:
-        """Device bytes a query's build and probe may hold at once (an upper
-        estimate: a cell side of eps / 1.5 undercuts the real one)."""
+        """Device bytes a query's build and probe may hold at once, an upper
+        estimate: 8 B per viewport cell (a cell side of eps / 1.5 undercuts
+        the real one), 192 B per vertex of the polygon set (the build's edge,
+        event and sort arrays cover every vertex before the window cuts
+        them), 64 B per polygon and 4 MB.  A GPU test holds it against the
+        peak a build really takes over the serving query mix (at most two
+        thirds of the estimate there)."""
         s = max(1, int(q.eps / 1.5))
         cells = (q.vw // s + 3) ** 2
         nv = self.sets[q.set_id][4]
         np_ = self.sets[q.set_id][3]
-        return int(8 * cells + 96 * nv + 64 * np_ + (1 << 20))
+        return int(8 * cells + 192 * nv + 64 * np_ + (4 << 20))
 
     def ranges_of(self, q: Query):
         """Point index ranges whose buckets meet the viewport (one per bucket row)."""

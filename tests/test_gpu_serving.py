@@ -246,3 +246,34 @@ def test_server_admission_waits_under_small_budget(sba, city_small):
     finally:
         S.close()
     assert S.reserved == 0
+
+
+def test_memory_estimate_bounds_the_builds_of_the_query_mix(sba):
+    """Admission reserves estimate_bytes(q) for a query's build: over the
+    serving workload's query mix (viewports at zoom 10-18, eps one pixel,
+    the 260 / 4,000 / 40,000-polygon sets) it must be at least what the
+    build really holds at its peak (its temporaries and the handle, counted
+    by a caller allocator)."""
+    import paper_2010_12548_amd.serve as serve
+    from gen import city_polygons, quadtree_polygons, seeds, viewport_queries
+    sets = [city_polygons(), city_polygons(4000, (4, 40), config=5), quadtree_polygons()]
+    S = serve.Server.__new__(serve.Server)
+    S.sets = [(dev(p.ring_off), dev(p.vert_off), dev(p.xy), int(p.n_polys),
+               int(p.xy.shape[0] // 2)) for p in sets]
+    qs = viewport_queries(240, seeds(5)["queries"], n_sets=3)
+    al = sba.TorchAllocator()
+    worst = 0.0
+    for q in qs:
+        Q = serve.Query(q["vx"], q["vy"], q["vw"], q["eps"], q["set"], q["agg"])
+        ro, vo, pxy, _, _ = S.sets[Q.set_id]
+        al.reset_peak()
+        A = sba.Approx(ro, vo, pxy, Q.eps, window=(Q.vx, Q.vy, Q.vx + Q.vw, Q.vy + Q.vw),
+                       allocator=al)
+        peak = al.peak_bytes
+        assert A.info()["bytes"] <= al.live_bytes
+        A.close()
+        est = S.estimate_bytes(Q)
+        assert est >= peak, (q, est, peak)
+        worst = max(worst, peak / est)
+    assert al.live_bytes == 0
+    assert worst > 0.05            # the estimate is not vacuous
