@@ -296,6 +296,27 @@ typedef struct {
 int sba_aggregate_batch(const sba_task *tasks, int32_t n_tasks, void *stream);
 
 /*
+ * sba_aggregate_batch without any device allocation, for callers that cannot
+ * allocate (code under graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The same tasks, semantics and results; the tasks'
+ * descriptors, their items of at most 2^18 points and the work counter go to
+ * a fixed scratch array in the library's device memory of
+ * sba_batch_noalloc_bytes() bytes (4 MB) on each device the library runs on,
+ * held until the process ends.  A batch that needs more
+ * (sba_batch_scratch_bytes) fails with SBA_ELIMIT and leaves the outputs
+ * untouched.  Every call on one device uses that device's array, so calls
+ * that overlap on a device (other streams, other host threads) race: the
+ * caller orders them.  The array's address is looked up on the first call
+ * on each device.  Errors: as sba_aggregate_batch, and SBA_ELIMIT.
+ */
+int sba_aggregate_batch_noalloc(const sba_task *tasks, int32_t n_tasks, void *stream);
+
+/* Scratch bytes a batch needs (-1 for invalid arguments), and the size of the
+ * no-allocation entry point's array. */
+int64_t sba_batch_scratch_bytes(const sba_task *tasks, int32_t n_tasks);
+size_t sba_batch_noalloc_bytes(void);
+
+/*
  * Reorder a point table into G x G buckets of `cell` x `cell` units,
  * row-major, anchored at (x0, y0) (points outside the bucket grid go to the
  * nearest border bucket), so that the points of a viewport are a few

@@ -168,6 +168,12 @@ def lib():
     L.sba_aggregate_search.argtypes = [vp, vp, i64, vp, i32, vp, vp, vp]
     L.sba_aggregate_batch.restype = C.c_int
     L.sba_aggregate_batch.argtypes = [C.POINTER(_Task), i32, vp]
+    L.sba_aggregate_batch_noalloc.restype = C.c_int
+    L.sba_aggregate_batch_noalloc.argtypes = [C.POINTER(_Task), i32, vp]
+    L.sba_batch_scratch_bytes.restype = C.c_int64
+    L.sba_batch_scratch_bytes.argtypes = [C.POINTER(_Task), i32]
+    L.sba_batch_noalloc_bytes.restype = C.c_size_t
+    L.sba_batch_noalloc_bytes.argtypes = []
     L.sba_bucket_points.restype = C.c_int
     L.sba_bucket_points.argtypes = [vp, vp, i64, i32, i32, i32, i32, vp, vp, vp, vp]
     L.sba_lookup_cells.restype = C.c_int
@@ -702,11 +708,26 @@ class Task:
                      self.sums.data_ptr() if self.sums is not None else None)
 
 
-def aggregate_batch(tasks, stream=None):
-    """Run ``sba_aggregate_batch`` over a list of Task objects (asynchronous)."""
+def aggregate_batch(tasks, stream=None, no_alloc: bool = False):
+    """Run ``sba_aggregate_batch`` over a list of Task objects (asynchronous);
+    no_alloc: ``sba_aggregate_batch_noalloc`` (scratch in the library's fixed
+    device array, no allocation)."""
     arr = (_Task * max(len(tasks), 1))(*[t._c() for t in tasks])
-    _check(lib().sba_aggregate_batch(arr, len(tasks), _stream_ptr(stream)), "sba_aggregate_batch")
+    fn = lib().sba_aggregate_batch_noalloc if no_alloc else lib().sba_aggregate_batch
+    _check(fn(arr, len(tasks), _stream_ptr(stream)),
+           "sba_aggregate_batch_noalloc" if no_alloc else "sba_aggregate_batch")
     return tasks
+
+
+def batch_scratch_bytes(tasks) -> int:
+    """Device scratch bytes the batch of Task objects needs."""
+    arr = (_Task * max(len(tasks), 1))(*[t._c() for t in tasks])
+    return int(lib().sba_batch_scratch_bytes(arr, len(tasks)))
+
+
+def batch_noalloc_bytes() -> int:
+    """Size of the no-allocation batch entry point's scratch array."""
+    return int(lib().sba_batch_noalloc_bytes())
 
 
 def bucket_points(xy, values, x0: int, y0: int, cell: int, G: int, stream=None):

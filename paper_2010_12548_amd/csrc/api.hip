@@ -85,7 +85,7 @@ extern "C" int sba_aggregate_range(const int32_t *xy, const int64_t *values, int
     return range_launch(xy, values, n, h, hb, counts, sums, bcounts, bsums, (hipStream_t)stream);
 }
 
-extern "C" int sba_aggregate_batch(const sba_task *tasks, int32_t n_tasks, void *stream)
+static int check_tasks(const sba_task *tasks, int32_t n_tasks)
 {
     if (n_tasks < 0 || (n_tasks > 0 && !tasks)) return SBA_EINVAL;
     for (int32_t k = 0; k < n_tasks; k++) {
@@ -97,7 +97,19 @@ extern "C" int sba_aggregate_batch(const sba_task *tasks, int32_t n_tasks, void 
         if (t.search == SBA_SEARCH_LEARNED && t.h->kind == SBA_KIND_HILBERT && !t.h->leaves)
             return SBA_EINVAL;
     }
+    return 0;
+}
+
+extern "C" int sba_aggregate_batch(const sba_task *tasks, int32_t n_tasks, void *stream)
+{
+    RC(check_tasks(tasks, n_tasks));
     return batch_launch(tasks, n_tasks, (hipStream_t)stream);
+}
+
+extern "C" int sba_aggregate_batch_noalloc(const sba_task *tasks, int32_t n_tasks, void *stream)
+{
+    RC(check_tasks(tasks, n_tasks));
+    return batch_launch_noalloc(tasks, n_tasks, (hipStream_t)stream);
 }
 
 extern "C" int sba_bucket_points(const int32_t *xy, const int64_t *values, int64_t n, int32_t x0,

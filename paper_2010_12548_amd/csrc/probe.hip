@@ -21,6 +21,7 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "sba_internal.h"
@@ -1946,16 +1947,17 @@ __global__ void k_batch_zero(const TaskDev *__restrict__ tasks, int32_t n_tasks,
     }
 }
 
-int batch_launch(const sba_task *tasks, int32_t n_tasks, hipStream_t st)
+// The tasks and items of a batch on the host (ItemDev ranges of at most
+// BATCH_ITEM points).
+static void batch_prepare(const sba_task *tasks, int32_t n_tasks, std::vector<TaskDev> &td,
+                          std::vector<ItemDev> &items)
 {
-    if (n_tasks <= 0) return 0;
-    std::vector<TaskDev> td(n_tasks);
-    std::vector<ItemDev> items;
+    td.assign(n_tasks, TaskDev{});
+    items.clear();
     for (int32_t k = 0; k < n_tasks; k++) {
         const sba_task &q = tasks[k];
         const sba_handle *h = q.h;
         TaskDev &T = td[k];
-        T = TaskDev{};
         views(h, &T.g, &T.hv);
         T.A = Agg{h->set_off, h->set_ids, (uint32_t)h->n_polys, (uint32_t)h->n_sets};
         T.layout = h->kind == SBA_KIND_GRID ? 0 : (q.search == SBA_SEARCH_LEARNED ? 2 : 1);
@@ -1972,34 +1974,117 @@ int batch_launch(const sba_task *tasks, int32_t n_tasks, hipStream_t st)
         for (int64_t a = q.lo; a < q.hi; a += BATCH_ITEM)
             items.push_back(ItemDev{a, std::min<int64_t>(q.hi, a + BATCH_ITEM), k, 0});
     }
+}
+
+// bytes of device scratch a batch needs: tasks, items (+1), the item counter
+static size_t batch_bytes(int32_t n_tasks, size_t n_items)
+{
+    return sizeof(TaskDev) * n_tasks + sizeof(ItemDev) * (n_items + 1) + 64;
+}
+
+// Copies the tasks and items into buf (batch_bytes long, device memory) and
+// launches the batch on st.
+static int batch_run(const std::vector<TaskDev> &td, const std::vector<ItemDev> &items,
+                     char *buf, hipStream_t st)
+{
+    const int32_t n_tasks = (int32_t)td.size();
     const int32_t n_items = (int32_t)items.size();
     const size_t tbytes = sizeof(TaskDev) * n_tasks, ibytes = sizeof(ItemDev) * (n_items + 1);
-    char *buf = nullptr;
-    RC(tmp_alloc(&buf, (int64_t)(tbytes + ibytes + 64), st));
     TaskDev *dtasks = (TaskDev *)buf;
     ItemDev *ditems = (ItemDev *)(buf + tbytes);
     int *next = (int *)(buf + tbytes + ibytes);
-    int rc = 0;
     if (hipMemcpyAsync(dtasks, td.data(), tbytes, hipMemcpyHostToDevice, st) != hipSuccess ||
         (n_items && hipMemcpyAsync(ditems, items.data(), sizeof(ItemDev) * n_items,
                                    hipMemcpyHostToDevice, st) != hipSuccess))
-        rc = SBA_EDEVICE;
-    if (!rc) {
-        hipLaunchKernelGGL(k_batch_zero, dim3((unsigned)n_tasks), dim3(256), 0, st, dtasks, n_tasks,
-                           next);
-        if (hipGetLastError() != hipSuccess) rc = SBA_EDEVICE;
-    }
-    if (!rc && n_items) {
+        return SBA_EDEVICE;
+    // zeroes the outputs and the item counter
+    hipLaunchKernelGGL(k_batch_zero, dim3((unsigned)n_tasks), dim3(256), 0, st, dtasks, n_tasks,
+                       next);
+    if (hipGetLastError() != hipSuccess) return SBA_EDEVICE;
+    if (n_items) {
         // at most BATCH_PER_CU persistent workgroups per CU (half its LDS and
         // wave slots), so the builds of later queries, queued on other streams,
         // find room to run beside the batch
         int64_t nb = std::min<int64_t>(n_items, (int64_t)cu_count() * BATCH_PER_CU);
         hipLaunchKernelGGL(k_batch, dim3((unsigned)nb), dim3(PROBE_BLOCK), 0, st, dtasks, ditems,
                            n_items, next);
-        if (hipGetLastError() != hipSuccess) rc = SBA_EDEVICE;
+        if (hipGetLastError() != hipSuccess) return SBA_EDEVICE;
     }
+    return 0;
+}
+
+int batch_launch(const sba_task *tasks, int32_t n_tasks, hipStream_t st)
+{
+    if (n_tasks <= 0) return 0;
+    std::vector<TaskDev> td;
+    std::vector<ItemDev> items;
+    batch_prepare(tasks, n_tasks, td, items);
+    char *buf = nullptr;
+    RC(tmp_alloc(&buf, (int64_t)batch_bytes(n_tasks, items.size()), st));
+    const int rc = batch_run(td, items, buf, st);
     tmp_free(buf, st);
     return rc;
+}
+
+// ---------------------------------------------------------------- batches without allocation
+//
+// The same batch with its tasks, items and counter in a fixed device array of
+// the library (BATCH_SCRATCH_BYTES on every device it runs on, held until the
+// process ends) instead of memory taken per call.  In host code the array's
+// name does not stand for its device address: that address is looked up once
+// per device (hipGetSymbolAddress, with the device current) and only the
+// looked-up pointer is used.  Calls on one device share the array: calls
+// that overlap on a device (different streams, or host threads) race.
+
+#define BATCH_SCRATCH_BYTES (4u << 20)
+static __device__ __align__(256) unsigned char batch_scratch[BATCH_SCRATCH_BYTES];
+
+static int batch_scratch_ptr(char **out)
+{
+    constexpr int MAX_DEV = 64;
+    static std::mutex mu;
+    static char *ptr[MAX_DEV] = {};
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEV) {
+        (void)hipGetLastError();
+        return SBA_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(batch_scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return SBA_EDEVICE;
+        }
+        ptr[dev] = (char *)p;
+    }
+    *out = ptr[dev];
+    return 0;
+}
+
+int batch_launch_noalloc(const sba_task *tasks, int32_t n_tasks, hipStream_t st)
+{
+    if (n_tasks <= 0) return 0;
+    std::vector<TaskDev> td;
+    std::vector<ItemDev> items;
+    batch_prepare(tasks, n_tasks, td, items);
+    if (batch_bytes(n_tasks, items.size()) > BATCH_SCRATCH_BYTES) return SBA_ELIMIT;
+    char *buf = nullptr;
+    RC(batch_scratch_ptr(&buf));
+    return batch_run(td, items, buf, st);
+}
+
+extern "C" size_t sba_batch_noalloc_bytes(void) { return BATCH_SCRATCH_BYTES; }
+
+extern "C" int64_t sba_batch_scratch_bytes(const sba_task *tasks, int32_t n_tasks)
+{
+    if (n_tasks < 0 || (n_tasks > 0 && !tasks)) return -1;
+    int64_t n_items = 0;
+    for (int32_t k = 0; k < n_tasks; k++) {
+        if (tasks[k].hi < tasks[k].lo) return -1;
+        n_items += (tasks[k].hi - tasks[k].lo + BATCH_ITEM - 1) / BATCH_ITEM;
+    }
+    return (int64_t)batch_bytes(n_tasks, (size_t)n_items);
 }
 
 extern "C" int sba_debug_force_wide_grid(int on)

@@ -409,6 +409,7 @@ int range_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_
                  const sba_handle *hb, uint64_t *counts, int64_t *sums, uint64_t *bcounts,
                  int64_t *bsums, hipStream_t st);
 int batch_launch(const sba_task *tasks, int32_t n_tasks, hipStream_t st);
+int batch_launch_noalloc(const sba_task *tasks, int32_t n_tasks, hipStream_t st);
 int bucket_launch(const int32_t *xy, const int64_t *values, int64_t n, int32_t x0, int32_t y0,
                   int32_t cell, int32_t G, int32_t *out_xy, int64_t *out_values, int64_t *off,
                   hipStream_t st);
