@@ -22,6 +22,10 @@ int sba_debug_celldiv(int64_t s, const uint32_t *n, int64_t count, uint32_t *q);
 /* Hilbert index of cell (i, j) at level L (Sec. 3 linearisation), and its
  * inverse, exactly as the kernels compute them. */
 uint64_t sba_debug_hilbert(int L, uint32_t i, uint32_t j);
+/* The probes' Hilbert encoder that takes four levels at a time through a
+ * table (built from the one-level step), host copy; L <= 16. */
+uint64_t sba_debug_hilbert_tab(int L, uint32_t i, uint32_t j);
+
 void sba_debug_hilbert_cell(int L, uint64_t d, uint32_t *i, uint32_t *j);
 
 /* Workgroups per compute unit of the streaming probes (default 8, 1..64).

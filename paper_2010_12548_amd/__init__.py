@@ -194,6 +194,8 @@ def lib():
     L.sba_debug_celldiv.argtypes = [i64, vp, i64, vp]
     L.sba_debug_hilbert.restype = C.c_uint64
     L.sba_debug_hilbert.argtypes = [C.c_int, C.c_uint32, C.c_uint32]
+    L.sba_debug_hilbert_tab.restype = C.c_uint64
+    L.sba_debug_hilbert_tab.argtypes = [C.c_int, C.c_uint32, C.c_uint32]
     L.sba_debug_hilbert_cell.restype = None
     L.sba_debug_hilbert_cell.argtypes = [C.c_int, C.c_uint64, C.POINTER(C.c_uint32),
                                          C.POINTER(C.c_uint32)]

@@ -239,6 +239,19 @@ extern "C" int sba_debug_celldiv(int64_t s, const uint32_t *n, int64_t count, ui
 // Host-side Hilbert index and its inverse as used by the kernels.  Test support.
 extern "C" uint64_t sba_debug_hilbert(int L, uint32_t i, uint32_t j) { return hilbert_index(L, i, j); }
 
+// the probes' four-levels-at-a-time encoder (host copy of its table), L <= 16
+extern "C" uint64_t sba_debug_hilbert_tab(int L, uint32_t i, uint32_t j)
+{
+    static uint16_t tab[HILBERT_TAB];
+    static bool ready = false;
+    if (!ready) {
+        for (uint32_t e = 0; e < HILBERT_TAB; e++) tab[e] = hilbert_tab_entry(e);
+        ready = true;
+    }
+    if (L < 0 || L > 16) return ~(uint64_t)0;
+    return hilbert_index_tab(L, i, j, tab);
+}
+
 extern "C" void sba_debug_hilbert_cell(int L, uint64_t d, uint32_t *i, uint32_t *j)
 {
     hilbert_cell(L, d, i, j);

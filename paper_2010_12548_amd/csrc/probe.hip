@@ -62,7 +62,22 @@ struct HilbView {
     uint32_t nl;
     const int4 *leaves;
     const int32_t *leaf_lo;
+    const uint16_t *tab;   // Hilbert table in LDS (set by the kernel) or NULL
 };
+
+// the Hilbert key of cell (i, j) of the view's grid
+__device__ __forceinline__ uint64_t hkey(const HilbView &v, uint32_t i, uint32_t j)
+{
+    return (v.tab && v.L <= 16) ? (uint64_t)hilbert_index_tab(v.L, i, j, v.tab)
+                                : hilbert_index(v.L, i, j);
+}
+
+// fills an LDS copy of the Hilbert table (all threads of the workgroup;
+// the caller synchronises before use)
+__device__ __forceinline__ void hilbert_tab_fill(uint16_t *tab, int nthreads)
+{
+    for (int e = threadIdx.x; e < HILBERT_TAB; e += nthreads) tab[e] = hilbert_tab_entry((uint32_t)e);
+}
 
 // short code (compact format) -> cell code
 __device__ __forceinline__ uint32_t full_code(uint32_t sc, uint32_t np)
@@ -144,7 +159,7 @@ __device__ __forceinline__ uint32_t hilbert_code(const HilbView &v, int32_t x, i
     if ((uint64_t)dx >= v.extx || (uint64_t)dy >= v.exty) return 0;
     uint32_t i = divmagic((uint32_t)dx, v.mag, v.shift);
     uint32_t j = divmagic((uint32_t)dy, v.mag, v.shift);
-    uint64_t key = hilbert_index(v.L, i, j);
+    uint64_t key = hkey(v, i, j);
     int64_t q;
     if (v.k32) {
         q = SEARCH ? learned_search<uint32_t>(v, v.k32, (uint32_t)key)
@@ -395,7 +410,7 @@ __device__ __forceinline__ void hilbert_codes(const HilbView &v, const int32_t *
         ok[k] = (uint64_t)dx < v.extx && (uint64_t)dy < v.exty;
         uint32_t i = divmagic(ok[k] ? (uint32_t)dx : 0u, v.mag, v.shift);
         uint32_t j = divmagic(ok[k] ? (uint32_t)dy : 0u, v.mag, v.shift);
-        key[k] = hilbert_index(v.L, i, j);
+        key[k] = hkey(v, i, j);
     }
     int64_t q[NP];
     if (v.k32) {
@@ -421,12 +436,126 @@ __device__ __forceinline__ void hilbert_codes(const HilbView &v, const int32_t *
     for (int k = 0; k < NP; k++) c[k] = ok[k] ? r[k] : 0u;
 }
 
+// Wave-bracketed Hilbert lookups for points in spatial order.  The NP
+// points of every lane of the wave (all lanes take part: the caller keeps
+// the wave together) have keys in [kmin, kmax]; two searches with those
+// wave-uniform keys -- binary search or the learned index, as the handle
+// is searched -- give the runs qlo and qhi that hold them.  When the
+// bracket spans at most 64 runs, the wave reads the bracket's starts and
+// codes once (a lane each) and every point finds its run by a binary search
+// over the lanes' registers: no memory access per point.  A wider bracket
+// (points in no order) takes the per-point search.  Exact either way: the
+// run of every key lies in [qlo, qhi].
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+template <int SEARCH, int NP>
+__device__ __forceinline__ void hilbert_codes_wave(const HilbView &v, const int32_t *xs,
+                                                   const int32_t *ys, uint32_t *c)
+{
+    if (v.extx == 0 || !v.k32) {  // empty handle; 64-bit keys take the plain path
+        hilbert_codes<SEARCH, NP>(v, xs, ys, c);
+        return;
+    }
+    bool ok[NP];
+    uint32_t key[NP];
+    uint32_t kmin = 0xffffffffu, kmax = 0u;
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        int64_t dx = (int64_t)xs[k] - v.ox, dy = (int64_t)ys[k] - v.oy;
+        ok[k] = (uint64_t)dx < v.extx && (uint64_t)dy < v.exty;
+        uint32_t i = divmagic(ok[k] ? (uint32_t)dx : 0u, v.mag, v.shift);
+        uint32_t j = divmagic(ok[k] ? (uint32_t)dy : 0u, v.mag, v.shift);
+        key[k] = (uint32_t)hkey(v, i, j);
+        kmin = ok[k] ? min(kmin, key[k]) : kmin;
+        kmax = ok[k] ? max(kmax, key[k]) : kmax;
+    }
+    kmin = wave_min_u32(kmin);
+    kmax = wave_max_u32(kmax);
+    if (kmax < kmin) {  // no point of the wave lies in the stored box
+#pragma unroll
+        for (int k = 0; k < NP; k++) c[k] = 0;
+        return;
+    }
+    // runs expected in [kmin, kmax] if they were spread evenly over the
+    // 4^L keys: far more than a wave holds means points in no spatial order
+    // (or spread over a partition region), where the bracket searches would
+    // only add to the per-point ones
+    if (((uint64_t)(kmax - kmin) * (uint64_t)v.n) >> (2 * v.L) > 1024) {
+        hilbert_codes<SEARCH, NP>(v, xs, ys, c);
+        return;
+    }
+    const int64_t qlo = SEARCH ? learned_search<uint32_t>(v, v.k32, kmin)
+                               : pred_search<uint32_t>(v.k32, 0, v.n, kmin);
+    const int64_t qhi = SEARCH ? learned_search<uint32_t>(v, v.k32, kmax)
+                               : pred_search<uint32_t>(v.k32, 0, v.n, kmax);
+    const int32_t w = (int32_t)__builtin_amdgcn_readfirstlane((int)(qhi - qlo + 1));
+    if (qhi - qlo + 1 > 64) {
+        // per point, a binary search restricted to the bracket; a learned
+        // index searches a bracket of more than 4096 runs through its own
+        // windows instead
+        int64_t q[NP];
+        if (SEARCH && qhi - qlo + 1 > 4096) {
+            uint64_t k64[NP];
+#pragma unroll
+            for (int k = 0; k < NP; k++) k64[k] = key[k];
+            learned_search_n<NP>(v, key, k64, q);
+        } else {
+#pragma unroll
+            for (int k = 0; k < NP; k++) q[k] = qlo;
+            pred_search_n<uint32_t, NP>(v.k32, q, qhi - qlo + 1, key);
+        }
+        uint32_t r[NP];
+#pragma unroll
+        for (int k = 0; k < NP; k++) r[k] = v.code[q[k]];
+#pragma unroll
+        for (int k = 0; k < NP; k++) c[k] = ok[k] ? r[k] : 0u;
+        return;
+    }
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t mine = qlo + (lane < w ? lane : w - 1);
+    const uint32_t wstart = v.k32[mine];
+    const uint32_t wcode = v.code[mine];
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        // last lane l < w with wstart(l) <= key: keys[qlo] <= kmin <= key
+        int lo = 0, len = w;
+        while (len > 1) {
+            const int half = len >> 1;
+            const uint32_t sv = (uint32_t)__shfl((int)wstart, lo + half, 64);
+            lo = sv <= key[k] ? lo + half : lo;
+            len -= half;
+        }
+        const uint32_t cv = (uint32_t)__shfl((int)wcode, lo, 64);
+        c[k] = ok[k] ? cv : 0u;
+    }
+}
+
 template <int LAYOUT, int NP>
 __device__ __forceinline__ void codes_of(const GridView &g, const HilbView &hv, const int32_t *xs,
                                          const int32_t *ys, uint32_t *c)
 {
     if (LAYOUT == 0) grid_codes<NP>(g, xs, ys, c);
     else hilbert_codes<LAYOUT == 2 ? 1 : 0, NP>(hv, xs, ys, c);
+}
+
+// As codes_of, with the wave-bracketed lookups for the Hilbert layouts; every
+// lane of the wave must call it.
+template <int LAYOUT, int NP>
+__device__ __forceinline__ void codes_of_wave(const GridView &g, const HilbView &hv,
+                                              const int32_t *xs, const int32_t *ys, uint32_t *c)
+{
+    if (LAYOUT == 0) grid_codes<NP>(g, xs, ys, c);
+    else hilbert_codes_wave<LAYOUT == 2 ? 1 : 0, NP>(hv, xs, ys, c);
 }
 
 struct Agg {
@@ -517,11 +646,16 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_probe_lds(const int4 *__restric
                                                            int64_t *__restrict__ sums)
 {
     extern __shared__ unsigned long long smem[];
+    __shared__ uint16_t s_htab[LAYOUT ? HILBERT_TAB : 1];
     unsigned long long *lsum = smem;
     uint32_t *lcnt = (uint32_t *)(smem + np);
     for (int p = threadIdx.x; p < np; p += PROBE_BLOCK) {
         lcnt[p] = 0;
         lsum[p] = 0;
+    }
+    if (LAYOUT) {
+        hilbert_tab_fill(s_htab, PROBE_BLOCK);
+        hv.tab = s_htab;
     }
     __syncthreads();
     const int64_t npairs = n >> 1;
@@ -1761,12 +1895,21 @@ __device__ __forceinline__ void batch_item(const TaskDev &T, int64_t lo, int64_t
     const int4 *xy4 = (const int4 *)T.xy;
     const longlong2 *v2 = (const longlong2 *)T.vals;
     const int64_t pb = b >> 1;
-    for (int64_t t0 = (a >> 1) + threadIdx.x; t0 < pb; t0 += (int64_t)PROBE_BLOCK * PROBE_UNROLL) {
+    // Each wave takes blocks of 64 PROBE_UNROLL consecutive pairs (the
+    // waves of the workgroup in turn), so the points of one wave's trip are
+    // neighbours in the input, and in space when the input is in spatial
+    // order.  The lanes of a wave leave the loop together (the lookups work
+    // across the wave): a wave runs while its block starts before the end,
+    // and lanes past the end take a point no cell holds.
+    constexpr int64_t WB = 64 * PROBE_UNROLL;
+    const int64_t nw = PROBE_BLOCK / 64;
+    const int64_t lane = (int64_t)(threadIdx.x & 63u);
+    for (int64_t w0 = (a >> 1) + (int64_t)(threadIdx.x >> 6) * WB; w0 < pb; w0 += nw * WB) {
         int4 q[PROBE_UNROLL];
         longlong2 vv[PROBE_UNROLL];
 #pragma unroll
         for (int u = 0; u < PROBE_UNROLL; u++) {
-            int64_t t = t0 + (int64_t)u * PROBE_BLOCK;
+            int64_t t = w0 + (int64_t)u * 64 + lane;
             q[u] = t < pb ? xy4[t] : make_int4(INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN);
             vv[u] = (VALS && t < pb) ? v2[t] : make_longlong2(0, 0);
         }
@@ -1781,7 +1924,7 @@ __device__ __forceinline__ void batch_item(const TaskDev &T, int64_t lo, int64_t
             ys[2 * u + 1] = k1 ? q[u].w : INT32_MIN;
         }
         uint32_t c[2 * PROBE_UNROLL];
-        codes_of<LAYOUT, 2 * PROBE_UNROLL>(T.g, T.hv, xs, ys, c);
+        codes_of_wave<LAYOUT, 2 * PROBE_UNROLL>(T.g, T.hv, xs, ys, c);
 #pragma unroll
         for (int u = 0; u < PROBE_UNROLL; u++) {
             table_add<VALS>(H, c[2 * u], vv[u].x, T);
@@ -1833,13 +1976,14 @@ __device__ __forceinline__ void table_flush(const CodeTable &H, const TaskDev &T
 // for spatially ordered or partitioned points, one region whose part of the
 // structure fits that XCD's L2.  The grid size is a multiple of 8.
 template <int LAYOUT, bool VALS>
-__global__ __launch_bounds__(PROBE_BLOCK) void k_probe_items(const TaskDev T, int64_t item,
+__global__ __launch_bounds__(PROBE_BLOCK) void k_probe_items(const TaskDev T0, int64_t item,
                                                              int64_t n_items)
 {
     __shared__ uint32_t s_key[BATCH_SLOTS];
     __shared__ uint32_t s_cnt[BATCH_SLOTS];
     __shared__ unsigned long long s_sum[BATCH_SLOTS];
     __shared__ int s_full;
+    __shared__ uint16_t s_htab[LAYOUT ? HILBERT_TAB : 1];
     const CodeTable H{s_key, s_cnt, s_sum, &s_full};
     for (int k = threadIdx.x; k < BATCH_SLOTS; k += PROBE_BLOCK) {
         s_key[k] = BATCH_EMPTY;
@@ -1847,6 +1991,11 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_probe_items(const TaskDev T, in
         s_sum[k] = 0;
     }
     if (threadIdx.x == 0) s_full = 0;
+    TaskDev T = T0;
+    if (LAYOUT) {
+        hilbert_tab_fill(s_htab, PROBE_BLOCK);
+        T.hv.tab = s_htab;
+    }
     __syncthreads();
     const int64_t nx = gridDim.x >> 3, per = (n_items + 7) >> 3;
     const int64_t first = (int64_t)(blockIdx.x & 7) * per;
@@ -1905,6 +2054,7 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_batch(const TaskDev *__restrict
     __shared__ uint32_t s_cnt[BATCH_SLOTS];
     __shared__ unsigned long long s_sum[BATCH_SLOTS];
     __shared__ int s_item, s_full;
+    __shared__ uint16_t s_htab[HILBERT_TAB];
     const CodeTable H{s_key, s_cnt, s_sum, &s_full};
     for (int k = threadIdx.x; k < BATCH_SLOTS; k += PROBE_BLOCK) {
         s_key[k] = BATCH_EMPTY;
@@ -1912,6 +2062,7 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_batch(const TaskDev *__restrict
         s_sum[k] = 0;
     }
     if (threadIdx.x == 0) s_full = 0;
+    hilbert_tab_fill(s_htab, PROBE_BLOCK);
     while (true) {
         if (threadIdx.x == 0) s_item = atomicAdd(next, 1);
         __syncthreads();
@@ -1919,7 +2070,8 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_batch(const TaskDev *__restrict
         __syncthreads();
         if (it >= n_items) break;  // every wave of the workgroup leaves here together
         const ItemDev I = items[it];
-        const TaskDev T = tasks[I.task];
+        TaskDev T = tasks[I.task];
+        T.hv.tab = s_htab;
         const bool vals = T.vals != nullptr && T.sums != nullptr;
         switch (T.layout * 2 + (vals ? 1 : 0)) {
         case 0: batch_item<0, false>(T, I.lo, I.hi, H); break;

@@ -221,20 +221,62 @@ inline int64_t cell_side(int64_t eps)
 // consecutive indices are edge-adjacent (Sec. 3, linearisation of cells).
 // Processed one level at a time from the top; the orientation state is kept
 // as a transpose flag and a reflection flag instead of rewriting i and j.
+//
+// One level: the quadrant digit of cell bits (bi, bj) in the current frame,
+// and the frame of the next level.
+__host__ __device__ inline uint32_t hilbert_level(uint32_t bi, uint32_t bj, uint32_t *swap,
+                                                  uint32_t *flip)
+{
+    uint32_t x = (*swap ? bj : bi) ^ *flip;
+    uint32_t y = (*swap ? bi : bj) ^ *flip;
+    uint32_t q = (3u * x) ^ y;  // 0:(0,0) 1:(0,1) 2:(1,1) 3:(1,0)
+    if (y == 0) {               // lower quadrants are transposed,
+        if (x == 1) *flip ^= 1u;  // the lower-right one also complemented
+        *swap ^= 1u;
+    }
+    return q;
+}
+
 __host__ __device__ inline uint64_t hilbert_index(int L, uint32_t i, uint32_t j)
 {
     uint64_t d = 0;
     uint32_t swap = 0, flip = 0;  // current frame: transpose, then complement
-    for (int lev = L - 1; lev >= 0; --lev) {
-        uint32_t bi = (i >> lev) & 1u, bj = (j >> lev) & 1u;
-        uint32_t x = (swap ? bj : bi) ^ flip;
-        uint32_t y = (swap ? bi : bj) ^ flip;
-        uint32_t q = (3u * x) ^ y;  // 0:(0,0) 1:(0,1) 2:(1,1) 3:(1,0)
-        d = (d << 2) | q;
-        if (y == 0) {             // lower quadrants are transposed,
-            if (x == 1) flip ^= 1u;  // the lower-right one also complemented
-            swap ^= 1u;
-        }
+    for (int lev = L - 1; lev >= 0; --lev)
+        d = (d << 2) | hilbert_level((i >> lev) & 1u, (j >> lev) & 1u, &swap, &flip);
+    return d;
+}
+
+// The same index four levels at a time through a table (kept in LDS by the
+// probes).  Entry (frame << 8) | (i4 << 4) | j4 holds the 8 index bits of
+// four levels of cell bits i4, j4 entered in frame (bit 0 transpose, bit 1
+// complement) and, in bits 8-9, the frame they leave; hilbert_tab_entry
+// builds it from hilbert_level, so both give the same index.
+#define HILBERT_TAB 1024
+
+__host__ __device__ inline uint16_t hilbert_tab_entry(uint32_t e)
+{
+    uint32_t swap = (e >> 8) & 1u, flip = (e >> 9) & 1u, d = 0;
+    for (int lev = 3; lev >= 0; --lev)
+        d = (d << 2) | hilbert_level((e >> (4 + lev)) & 1u, (e >> lev) & 1u, &swap, &flip);
+    return (uint16_t)(d | (swap << 8) | (flip << 9));
+}
+
+// L <= 16: the levels above the last multiple of four one at a time, then
+// four at a time
+__host__ __device__ inline uint32_t hilbert_index_tab(int L, uint32_t i, uint32_t j,
+                                                      const uint16_t *tab)
+{
+    uint32_t d = 0, swap = 0, flip = 0;
+    int lev = L;
+    while (lev & 3) {
+        --lev;
+        d = (d << 2) | hilbert_level((i >> lev) & 1u, (j >> lev) & 1u, &swap, &flip);
+    }
+    uint32_t fr = swap | (flip << 1);
+    for (; lev > 0; lev -= 4) {
+        const uint32_t e = tab[(fr << 8) | (((i >> (lev - 4)) & 15u) << 4) | ((j >> (lev - 4)) & 15u)];
+        d = (d << 8) | (e & 255u);
+        fr = e >> 8;
     }
     return d;
 }

@@ -115,3 +115,20 @@ def test_struct_layouts_match_header(sba, tmp_path):
         assert int(out[cname]) == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert int(out[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+@pytest.mark.parametrize("L", [0, 1, 2, 3, 4, 5, 7, 8, 11, 12, 15, 16])
+def test_hilbert_table_encoder_matches_oracle(sba, orc, L):
+    """The probes' encoder that takes four levels at a time through a table
+    gives the oracle's Hilbert index (every cell for small L, samples and
+    the corners otherwise)."""
+    lib = sba.lib()
+    side = 1 << L
+    if side <= 64:
+        cells = [(i, j) for i in range(side) for j in range(side)]
+    else:
+        rng = np.random.default_rng(100 + L)
+        cells = [tuple(map(int, c)) for c in rng.integers(0, side, size=(4000, 2))]
+        cells += [(0, 0), (side - 1, 0), (0, side - 1), (side - 1, side - 1)]
+    for i, j in cells:
+        assert lib.sba_debug_hilbert_tab(L, i, j) == orc.hilbert_d(L, i, j), (L, i, j)
