@@ -589,13 +589,14 @@ __device__ __forceinline__ void add_lds(uint32_t code, int64_t val, const Agg &A
 
 template <bool VALS>
 __device__ __forceinline__ void add_global(uint32_t code, int64_t val, const Agg &A,
-                                           unsigned long long *cnt, unsigned long long *sum)
+                                           unsigned long long *cnt, unsigned long long *sum,
+                                           unsigned long long n = 1)
 {
     if (code == 0) return;
     if (code < CODE_SET_BASE) {
         uint32_t p = code - 1u;
         if (p >= A.np) return;
-        atomicAdd(&cnt[p], 1ull);
+        atomicAdd(&cnt[p], n);
         if (VALS) atomicAdd(&sum[p], (unsigned long long)val);
     } else {
         uint32_t k = code - CODE_SET_BASE;
@@ -603,7 +604,7 @@ __device__ __forceinline__ void add_global(uint32_t code, int64_t val, const Agg
         for (int64_t t = A.set_off[k], e = A.set_off[k + 1]; t < e; t++) {
             uint32_t p = (uint32_t)A.set_ids[t];
             if (p >= A.np) continue;
-            atomicAdd(&cnt[p], 1ull);
+            atomicAdd(&cnt[p], n);
             if (VALS) atomicAdd(&sum[p], (unsigned long long)val);
         }
     }
@@ -1840,38 +1841,47 @@ __device__ __forceinline__ bool in_view(const TaskDev &T, int32_t x, int32_t y)
 // open addressing in LDS): the serving loop keeps its points bucketed, so the
 // points of one item come from a small area and meet few codes; a code that
 // finds no free slot within BATCH_PROBES steps goes to the outputs directly.
-#define BATCH_SLOTS 2048
+// The item probe's table has ITEM_SLOTS slots (its items may hold points
+// in no order); the batch's has BATCH_SLOTS (bucketed points), which keeps
+// a batch workgroup's LDS small enough for several per compute unit.
+#define ITEM_SLOTS_LOG2 11
+#define BATCH_SLOTS_LOG2 10
+#define ITEM_SLOTS (1 << ITEM_SLOTS_LOG2)
+#define BATCH_SLOTS (1 << BATCH_SLOTS_LOG2)
 #define BATCH_PROBES 16
 #define BATCH_EMPTY 0xffffffffu
 
 struct CodeTable {
-    uint32_t *key;                 // [BATCH_SLOTS] code or BATCH_EMPTY
-    uint32_t *cnt;                 // [BATCH_SLOTS]
-    unsigned long long *sum;       // [BATCH_SLOTS]
+    uint32_t *key;                 // [2^bits] code or BATCH_EMPTY
+    uint32_t *cnt;                 // [2^bits]
+    unsigned long long *sum;       // [2^bits]
     int *full;                     // set once a code found no slot: later codes
                                    // look at one slot only (points in no
                                    // spatial order meet more codes than fit)
+    int bits;
 };
 
+// n points of one code, v the sum of their values
 template <bool VALS>
 __device__ __forceinline__ void table_add(const CodeTable &H, uint32_t code, int64_t v,
-                                          const TaskDev &T)
+                                          const TaskDev &T, uint32_t n = 1)
 {
     if (code == 0) return;
-    uint32_t h = (code * 2654435761u) >> (32 - 11);  // BATCH_SLOTS = 2^11
+    uint32_t h = (code * 2654435761u) >> (32 - H.bits);
+    const uint32_t mask = (1u << H.bits) - 1u;
     const int probes = *H.full ? 1 : BATCH_PROBES;
     for (int k = 0; k < probes; k++) {
         uint32_t old = H.key[h];
         if (old == BATCH_EMPTY) old = atomicCAS(&H.key[h], BATCH_EMPTY, code);
         if (old == BATCH_EMPTY || old == code) {
-            atomicAdd(&H.cnt[h], 1u);
+            atomicAdd(&H.cnt[h], n);
             if (VALS) atomicAdd(&H.sum[h], (unsigned long long)v);
             return;
         }
-        h = (h + 1) & (BATCH_SLOTS - 1);
+        h = (h + 1) & mask;
     }
     if (probes > 1) *H.full = 1;
-    add_global<VALS>(code, v, T.A, T.counts, T.sums);
+    add_global<VALS>(code, v, T.A, T.counts, T.sums, n);
 }
 
 template <int LAYOUT, bool VALS>
@@ -1925,11 +1935,24 @@ __device__ __forceinline__ void batch_item(const TaskDev &T, int64_t lo, int64_t
         }
         uint32_t c[2 * PROBE_UNROLL];
         codes_of_wave<LAYOUT, 2 * PROBE_UNROLL>(T.g, T.hv, xs, ys, c);
+        // a lane's points of the trip (pairs 64 apart) often share their code
+        // when the input is in spatial order: runs of one code take one add
+        uint32_t cur = c[0], run = 1;
+        int64_t rs = vv[0].x;
 #pragma unroll
-        for (int u = 0; u < PROBE_UNROLL; u++) {
-            table_add<VALS>(H, c[2 * u], vv[u].x, T);
-            table_add<VALS>(H, c[2 * u + 1], vv[u].y, T);
+        for (int k = 1; k < 2 * PROBE_UNROLL; k++) {
+            const int64_t v = (k & 1) ? vv[k >> 1].y : vv[k >> 1].x;
+            if (c[k] == cur) {
+                run++;
+                rs += v;
+            } else {
+                table_add<VALS>(H, cur, rs, T, run);
+                cur = c[k];
+                run = 1;
+                rs = v;
+            }
         }
+        table_add<VALS>(H, cur, rs, T, run);
     }
 }
 
@@ -1937,7 +1960,7 @@ __device__ __forceinline__ void batch_item(const TaskDev &T, int64_t lo, int64_t
 // table back to empty
 __device__ __forceinline__ void table_flush(const CodeTable &H, const TaskDev &T, bool vals)
 {
-    for (int k = threadIdx.x; k < BATCH_SLOTS; k += PROBE_BLOCK) {
+    for (int k = threadIdx.x; k < (1 << H.bits); k += PROBE_BLOCK) {
         const uint32_t code = H.key[k];
         if (code == BATCH_EMPTY) continue;
         const unsigned long long c = H.cnt[k], sv = H.sum[k];
@@ -1979,13 +2002,13 @@ template <int LAYOUT, bool VALS>
 __global__ __launch_bounds__(PROBE_BLOCK) void k_probe_items(const TaskDev T0, int64_t item,
                                                              int64_t n_items)
 {
-    __shared__ uint32_t s_key[BATCH_SLOTS];
-    __shared__ uint32_t s_cnt[BATCH_SLOTS];
-    __shared__ unsigned long long s_sum[BATCH_SLOTS];
+    __shared__ uint32_t s_key[ITEM_SLOTS];
+    __shared__ uint32_t s_cnt[ITEM_SLOTS];
+    __shared__ unsigned long long s_sum[ITEM_SLOTS];
     __shared__ int s_full;
     __shared__ uint16_t s_htab[LAYOUT ? HILBERT_TAB : 1];
-    const CodeTable H{s_key, s_cnt, s_sum, &s_full};
-    for (int k = threadIdx.x; k < BATCH_SLOTS; k += PROBE_BLOCK) {
+    const CodeTable H{s_key, s_cnt, s_sum, &s_full, ITEM_SLOTS_LOG2};
+    for (int k = threadIdx.x; k < ITEM_SLOTS; k += PROBE_BLOCK) {
         s_key[k] = BATCH_EMPTY;
         s_cnt[k] = 0;
         s_sum[k] = 0;
@@ -2046,6 +2069,9 @@ static int launch_items(const int32_t *xy, const int64_t *values, int64_t n, con
     return 0;
 }
 
+// Items of one layout (each layout its own launch, so that the grid
+// probe's workgroups are not sized by the Hilbert searches' registers).
+template <int LAYOUT>
 __global__ __launch_bounds__(PROBE_BLOCK) void k_batch(const TaskDev *__restrict__ tasks,
                                                        const ItemDev *__restrict__ items,
                                                        int32_t n_items, int *__restrict__ next)
@@ -2054,15 +2080,15 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_batch(const TaskDev *__restrict
     __shared__ uint32_t s_cnt[BATCH_SLOTS];
     __shared__ unsigned long long s_sum[BATCH_SLOTS];
     __shared__ int s_item, s_full;
-    __shared__ uint16_t s_htab[HILBERT_TAB];
-    const CodeTable H{s_key, s_cnt, s_sum, &s_full};
+    __shared__ uint16_t s_htab[LAYOUT ? HILBERT_TAB : 1];
+    const CodeTable H{s_key, s_cnt, s_sum, &s_full, BATCH_SLOTS_LOG2};
     for (int k = threadIdx.x; k < BATCH_SLOTS; k += PROBE_BLOCK) {
         s_key[k] = BATCH_EMPTY;
         s_cnt[k] = 0;
         s_sum[k] = 0;
     }
     if (threadIdx.x == 0) s_full = 0;
-    hilbert_tab_fill(s_htab, PROBE_BLOCK);
+    if (LAYOUT) hilbert_tab_fill(s_htab, PROBE_BLOCK);
     while (true) {
         if (threadIdx.x == 0) s_item = atomicAdd(next, 1);
         __syncthreads();
@@ -2071,26 +2097,21 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_batch(const TaskDev *__restrict
         if (it >= n_items) break;  // every wave of the workgroup leaves here together
         const ItemDev I = items[it];
         TaskDev T = tasks[I.task];
-        T.hv.tab = s_htab;
+        if (LAYOUT) T.hv.tab = s_htab;
         const bool vals = T.vals != nullptr && T.sums != nullptr;
-        switch (T.layout * 2 + (vals ? 1 : 0)) {
-        case 0: batch_item<0, false>(T, I.lo, I.hi, H); break;
-        case 1: batch_item<0, true>(T, I.lo, I.hi, H); break;
-        case 2: batch_item<1, false>(T, I.lo, I.hi, H); break;
-        case 3: batch_item<1, true>(T, I.lo, I.hi, H); break;
-        case 4: batch_item<2, false>(T, I.lo, I.hi, H); break;
-        default: batch_item<2, true>(T, I.lo, I.hi, H); break;
-        }
+        if (vals) batch_item<LAYOUT, true>(T, I.lo, I.hi, H);
+        else batch_item<LAYOUT, false>(T, I.lo, I.hi, H);
         __syncthreads();
         table_flush(H, T, vals);
         __syncthreads();
     }
 }
 
+// next: one item counter per layout
 __global__ void k_batch_zero(const TaskDev *__restrict__ tasks, int32_t n_tasks, int *next)
 {
     const int t = blockIdx.x;
-    if (t == 0 && threadIdx.x == 0) *next = 0;
+    if (t == 0 && threadIdx.x < 3) next[threadIdx.x] = 0;
     if (t >= n_tasks) return;
     const TaskDev &T = tasks[t];
     for (int p = threadIdx.x; p < T.np; p += blockDim.x) {
@@ -2100,12 +2121,14 @@ __global__ void k_batch_zero(const TaskDev *__restrict__ tasks, int32_t n_tasks,
 }
 
 // The tasks and items of a batch on the host (ItemDev ranges of at most
-// BATCH_ITEM points).
+// BATCH_ITEM points), the items grouped by layout: n_layout[l] items of
+// layout l, layout 0 first.
 static void batch_prepare(const sba_task *tasks, int32_t n_tasks, std::vector<TaskDev> &td,
-                          std::vector<ItemDev> &items)
+                          std::vector<ItemDev> &items, int64_t n_layout[3])
 {
     td.assign(n_tasks, TaskDev{});
     items.clear();
+    std::vector<ItemDev> by[3];
     for (int32_t k = 0; k < n_tasks; k++) {
         const sba_task &q = tasks[k];
         const sba_handle *h = q.h;
@@ -2124,11 +2147,16 @@ static void batch_prepare(const sba_task *tasks, int32_t n_tasks, std::vector<Ta
         T.counts = (unsigned long long *)q.counts;
         T.sums = (unsigned long long *)q.sums;
         for (int64_t a = q.lo; a < q.hi; a += BATCH_ITEM)
-            items.push_back(ItemDev{a, std::min<int64_t>(q.hi, a + BATCH_ITEM), k, 0});
+            by[T.layout].push_back(ItemDev{a, std::min<int64_t>(q.hi, a + BATCH_ITEM), k, 0});
+    }
+    for (int l = 0; l < 3; l++) {
+        n_layout[l] = (int64_t)by[l].size();
+        items.insert(items.end(), by[l].begin(), by[l].end());
     }
 }
 
-// bytes of device scratch a batch needs: tasks, items (+1), the item counter
+// bytes of device scratch a batch needs: tasks, items (+1), the item
+// counters
 static size_t batch_bytes(int32_t n_tasks, size_t n_items)
 {
     return sizeof(TaskDev) * n_tasks + sizeof(ItemDev) * (n_items + 1) + 64;
@@ -2137,7 +2165,7 @@ static size_t batch_bytes(int32_t n_tasks, size_t n_items)
 // Copies the tasks and items into buf (batch_bytes long, device memory) and
 // launches the batch on st.
 static int batch_run(const std::vector<TaskDev> &td, const std::vector<ItemDev> &items,
-                     char *buf, hipStream_t st)
+                     const int64_t n_layout[3], char *buf, hipStream_t st)
 {
     const int32_t n_tasks = (int32_t)td.size();
     const int32_t n_items = (int32_t)items.size();
@@ -2149,20 +2177,32 @@ static int batch_run(const std::vector<TaskDev> &td, const std::vector<ItemDev> 
         (n_items && hipMemcpyAsync(ditems, items.data(), sizeof(ItemDev) * n_items,
                                    hipMemcpyHostToDevice, st) != hipSuccess))
         return SBA_EDEVICE;
-    // zeroes the outputs and the item counter
+    // zeroes the outputs and the item counters
     hipLaunchKernelGGL(k_batch_zero, dim3((unsigned)n_tasks), dim3(256), 0, st, dtasks, n_tasks,
                        next);
     if (hipGetLastError() != hipSuccess) return SBA_EDEVICE;
-    if (n_items) {
-        // at most BATCH_PER_CU persistent workgroups per CU (half its LDS and
-        // wave slots), so the builds of later queries, queued on other streams,
-        // find room to run beside the batch
-        int64_t nb = std::min<int64_t>(n_items, (int64_t)cu_count() * BATCH_PER_CU);
-        hipLaunchKernelGGL(k_batch, dim3((unsigned)nb), dim3(PROBE_BLOCK), 0, st, dtasks, ditems,
-                           n_items, next);
+    int64_t first = 0;
+    for (int l = 0; l < 3; l++) {
+        const int64_t ni = n_layout[l];
+        if (ni == 0) continue;
+        // at most BATCH_PER_CU persistent workgroups per CU (part of its LDS
+        // and wave slots), so the builds of later queries, queued on other
+        // streams, find room to run beside the batch
+        const dim3 grid((unsigned)std::min<int64_t>(ni, (int64_t)cu_count() * BATCH_PER_CU));
+        const ItemDev *it = ditems + first;
+        if (l == 0)
+            hipLaunchKernelGGL(k_batch<0>, grid, dim3(PROBE_BLOCK), 0, st, dtasks, it, (int32_t)ni,
+                               next);
+        else if (l == 1)
+            hipLaunchKernelGGL(k_batch<1>, grid, dim3(PROBE_BLOCK), 0, st, dtasks, it, (int32_t)ni,
+                               next + 1);
+        else
+            hipLaunchKernelGGL(k_batch<2>, grid, dim3(PROBE_BLOCK), 0, st, dtasks, it, (int32_t)ni,
+                               next + 2);
         if (hipGetLastError() != hipSuccess) return SBA_EDEVICE;
+        first += ni;
     }
-    return 0;
+    return first == n_items ? 0 : SBA_EDEVICE;
 }
 
 int batch_launch(const sba_task *tasks, int32_t n_tasks, hipStream_t st)
@@ -2170,10 +2210,11 @@ int batch_launch(const sba_task *tasks, int32_t n_tasks, hipStream_t st)
     if (n_tasks <= 0) return 0;
     std::vector<TaskDev> td;
     std::vector<ItemDev> items;
-    batch_prepare(tasks, n_tasks, td, items);
+    int64_t n_layout[3];
+    batch_prepare(tasks, n_tasks, td, items, n_layout);
     char *buf = nullptr;
     RC(tmp_alloc(&buf, (int64_t)batch_bytes(n_tasks, items.size()), st));
-    const int rc = batch_run(td, items, buf, st);
+    const int rc = batch_run(td, items, n_layout, buf, st);
     tmp_free(buf, st);
     return rc;
 }
@@ -2219,11 +2260,12 @@ int batch_launch_noalloc(const sba_task *tasks, int32_t n_tasks, hipStream_t st)
     if (n_tasks <= 0) return 0;
     std::vector<TaskDev> td;
     std::vector<ItemDev> items;
-    batch_prepare(tasks, n_tasks, td, items);
+    int64_t n_layout[3];
+    batch_prepare(tasks, n_tasks, td, items, n_layout);
     if (batch_bytes(n_tasks, items.size()) > BATCH_SCRATCH_BYTES) return SBA_ELIMIT;
     char *buf = nullptr;
     RC(batch_scratch_ptr(&buf));
-    return batch_run(td, items, buf, st);
+    return batch_run(td, items, n_layout, buf, st);
 }
 
 extern "C" size_t sba_batch_noalloc_bytes(void) { return BATCH_SCRATCH_BYTES; }

@@ -50,7 +50,8 @@ def check_sort(sba, keys, bits, with_vals=True):
 
 
 @pytest.mark.parametrize("kind", ["random", "equal", "sorted", "reverse", "few"])
-@pytest.mark.parametrize("n", [0, 1, 2, 1000, 1024 * 4 * 4 + 3, 300_001, (4 << 20) + 17])
+@pytest.mark.parametrize("n", [0, 1, 2, 1000, 1024 * 4 * 4 + 3, 262_145, 300_001, (2 << 20) + 1,
+                               (4 << 20) + 17])
 def test_radix_sort(sba, kind, n):
     rng = np.random.default_rng(n * 7 + len(kind))
     keys = keys_of(kind, n, rng)
@@ -111,5 +112,22 @@ def test_scan_multi(sba, sizes, in_place):
     tot = total.cpu().numpy()
     for k, h in enumerate(host):
         want = np.concatenate([[0], np.cumsum(h)[:-1]]) if h.size else h
+        np.testing.assert_array_equal(outs[k].cpu().numpy(), want)
+        assert tot[k] == h.sum()
+
+
+def test_scan_multi_wide_values(sba):
+    # tile sums far beyond 32 bits and of either sign (the build scans
+    # packed counts): every bit of a tile sum must arrive
+    rng = np.random.default_rng(5)
+    sizes = [1 << 21, 300_001, 4097]
+    host = [rng.integers(-2**40, 2**40, n, dtype=np.int64) for n in sizes]
+    host[1] = np.abs(host[1]) << 2                       # sums near 2^60
+    arrs = [torch.from_numpy(h).cuda() for h in host]
+    outs, total = sba.scan_multi(arrs)
+    torch.cuda.synchronize()
+    tot = total.cpu().numpy()
+    for k, h in enumerate(host):
+        want = np.concatenate([[0], np.cumsum(h)[:-1]])
         np.testing.assert_array_equal(outs[k].cpu().numpy(), want)
         assert tot[k] == h.sum()
