@@ -85,6 +85,31 @@ __device__ __forceinline__ uint32_t full_code(uint32_t sc, uint32_t np)
     return sc <= np ? sc : CODE_SET_BASE + (sc - np - 1);
 }
 
+// Loads and adds through pointers that address device memory.  A pointer
+// the kernel reads from memory (a batch task's) is generic to the compiler,
+// which would emit flat accesses: they also count against the LDS wait
+// counter, so each would wait out the LDS operations in flight as well.
+// (The host pass only checks these; it never runs them.)
+template <typename T>
+__device__ __forceinline__ T gld(const T *p)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return *(const __attribute__((address_space(1))) T *)p;
+#else
+    return *p;
+#endif
+}
+
+__device__ __forceinline__ void gadd(unsigned long long *p, unsigned long long v)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    __hip_atomic_fetch_add((__attribute__((address_space(1))) unsigned long long *)p, v,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#else
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#endif
+}
+
 __device__ __forceinline__ uint32_t grid_code(const GridView &g, int32_t x, int32_t y)
 {
     int64_t dx = (int64_t)x - g.ox, dy = (int64_t)y - g.oy;
@@ -95,11 +120,11 @@ __device__ __forceinline__ uint32_t grid_code(const GridView &g, int32_t x, int3
     uint32_t e, b;
     bool mixed;
     if (g.compact) {
-        e = g.dir16[ti];
+        e = gld(g.dir16 + ti);
         mixed = (e & 0x8000u) != 0;
         b = e & 0x7fffu;
     } else {
-        e = g.dir[ti];
+        e = gld(g.dir + ti);
         mixed = (e & TILE_MIXED) != 0;
         b = e & ~TILE_MIXED;
     }
@@ -109,8 +134,8 @@ __device__ __forceinline__ uint32_t grid_code(const GridView &g, int32_t x, int3
     if (g.sl < g.tl) {
         const int qs = g.tl - g.sl;
         const uint32_t mq = (1u << qs) - 1u;
-        uint32_t se = g.sub[((uint64_t)b << (2 * qs)) + ((((j >> g.sl) & mq) << qs) |
-                                                           ((i >> g.sl) & mq))];
+        uint32_t se = gld(g.sub + ((uint64_t)b << (2 * qs)) + ((((j >> g.sl) & mq) << qs) |
+                                                                ((i >> g.sl) & mq)));
         if (!(se & TILE_MIXED)) return g.compact ? full_code(se, g.np) : se;
         b = se & ~TILE_MIXED;
         fl = g.sl;
@@ -118,7 +143,7 @@ __device__ __forceinline__ uint32_t grid_code(const GridView &g, int32_t x, int3
     if (b >= g.nfine) return 0;
     const uint32_t m = (1u << fl) - 1u;
     uint64_t idx = ((uint64_t)b << (2 * fl)) + ((j & m) << fl) + (i & m);
-    return g.compact ? full_code(g.blocks16[idx], g.np) : g.blocks[idx];
+    return g.compact ? full_code(gld(g.blocks16 + idx), g.np) : gld(g.blocks + idx);
 }
 
 // last q with keys[q] <= key; keys[0] == 0 <= key
@@ -178,10 +203,12 @@ __device__ __forceinline__ uint32_t hilbert_code(const HilbView &v, int32_t x, i
 // a uniform tile re-reads the first block word, a cache hit), so one
 // iteration pays two memory latencies instead of 2*NP.
 
-template <int NP>
+// FMT: 0 the handle's format read from g.compact, 1 compact, 2 32-bit
+template <int NP, int FMT = 0>
 __device__ __forceinline__ void grid_codes(const GridView &g, const int32_t *xs, const int32_t *ys,
                                            uint32_t *c)
 {
+    const bool cpt = FMT == 0 ? g.compact != 0 : FMT == 1;
     if (g.extx == 0) {  // empty handle (a clip window that holds no cell)
 #pragma unroll
         for (int k = 0; k < NP; k++) c[k] = 0;
@@ -208,18 +235,19 @@ __device__ __forceinline__ void grid_codes(const GridView &g, const int32_t *xs,
     bool mix[NP];
 #pragma unroll
     for (int k = 0; k < NP; k++) {
-        uint32_t e = g.compact ? (uint32_t)g.dir16[ti[k]] : g.dir[ti[k]];
-        mix[k] = g.compact ? (e & 0x8000u) != 0 : (e & TILE_MIXED) != 0;
-        b[k] = g.compact ? (e & 0x7fffu) : (e & ~TILE_MIXED);
+        uint32_t e = cpt ? (uint32_t)gld(g.dir16 + ti[k]) : gld(g.dir + ti[k]);
+        mix[k] = cpt ? (e & 0x8000u) != 0 : (e & TILE_MIXED) != 0;
+        b[k] = cpt ? (e & 0x7fffu) : (e & ~TILE_MIXED);
         mix[k] = mix[k] && b[k] < g.nblocks;
-        v[k] = mix[k] ? 0u : (g.compact ? full_code(e, g.np) : e);
+        v[k] = mix[k] ? 0u : (cpt ? full_code(e, g.np) : e);
         if (!ok[k]) { mix[k] = false; v[k] = 0; }
     }
     // level 2: sub-directory entry of mixed tiles
     if (two) {
         uint32_t se[NP];
 #pragma unroll
-        for (int k = 0; k < NP; k++) se[k] = g.sub[mix[k] ? ((uint64_t)b[k] << (2 * qs)) + sq[k] : 0];
+        for (int k = 0; k < NP; k++)
+            se[k] = gld(g.sub + (mix[k] ? ((uint64_t)b[k] << (2 * qs)) + sq[k] : 0));
 #pragma unroll
         for (int k = 0; k < NP; k++) {
             if (!mix[k]) continue;
@@ -227,7 +255,7 @@ __device__ __forceinline__ void grid_codes(const GridView &g, const int32_t *xs,
                 b[k] = se[k] & ~TILE_MIXED;
                 mix[k] = b[k] < g.nfine;
             } else {
-                v[k] = g.compact ? full_code(se[k], g.np) : se[k];
+                v[k] = cpt ? full_code(se[k], g.np) : se[k];
                 mix[k] = false;
             }
         }
@@ -237,10 +265,10 @@ __device__ __forceinline__ void grid_codes(const GridView &g, const int32_t *xs,
 #pragma unroll
     for (int k = 0; k < NP; k++) {
         uint64_t idx = mix[k] ? ((uint64_t)b[k] << (2 * fl)) + lo[k] : 0;
-        f[k] = g.compact ? (uint32_t)g.blocks16[idx] : g.blocks[idx];
+        f[k] = cpt ? (uint32_t)gld(g.blocks16 + idx) : gld(g.blocks + idx);
     }
 #pragma unroll
-    for (int k = 0; k < NP; k++) c[k] = mix[k] ? (g.compact ? full_code(f[k], g.np) : f[k]) : v[k];
+    for (int k = 0; k < NP; k++) c[k] = mix[k] ? (cpt ? full_code(f[k], g.np) : f[k]) : v[k];
 }
 
 // NP predecessor searches in lockstep over keys[lo[k] .. lo[k]+len): the
@@ -596,16 +624,16 @@ __device__ __forceinline__ void add_global(uint32_t code, int64_t val, const Agg
     if (code < CODE_SET_BASE) {
         uint32_t p = code - 1u;
         if (p >= A.np) return;
-        atomicAdd(&cnt[p], n);
-        if (VALS) atomicAdd(&sum[p], (unsigned long long)val);
+        gadd(&cnt[p], n);
+        if (VALS) gadd(&sum[p], (unsigned long long)val);
     } else {
         uint32_t k = code - CODE_SET_BASE;
         if (k >= A.n_sets) return;
-        for (int64_t t = A.set_off[k], e = A.set_off[k + 1]; t < e; t++) {
-            uint32_t p = (uint32_t)A.set_ids[t];
+        for (int64_t t = gld(A.set_off + k), e = gld(A.set_off + k + 1); t < e; t++) {
+            uint32_t p = (uint32_t)gld(A.set_ids + t);
             if (p >= A.np) continue;
-            atomicAdd(&cnt[p], n);
-            if (VALS) atomicAdd(&sum[p], (unsigned long long)val);
+            gadd(&cnt[p], n);
+            if (VALS) gadd(&sum[p], (unsigned long long)val);
         }
     }
 }
@@ -1821,7 +1849,7 @@ struct TaskDev {
     const int32_t *xy;
     const int64_t *vals;
     int32_t filt;
-    int64_t vx0, vy0, vx1, vy1;  // viewport [vx0, vx1) x [vy0, vy1)
+    int32_t vx0, vy0, vx1, vy1;  // viewport [vx0, vx1] x [vy0, vy1] (inclusive)
     unsigned long long *counts;
     unsigned long long *sums;
 };
@@ -1834,7 +1862,7 @@ struct ItemDev {
 
 __device__ __forceinline__ bool in_view(const TaskDev &T, int32_t x, int32_t y)
 {
-    return !T.filt || (x >= T.vx0 && x < T.vx1 && y >= T.vy0 && y < T.vy1);
+    return !T.filt || (x >= T.vx0 && x <= T.vx1 && y >= T.vy0 && y <= T.vy1);
 }
 
 // Per-workgroup table of the codes an item meets (polygon or polygon set,
@@ -1884,7 +1912,8 @@ __device__ __forceinline__ void table_add(const CodeTable &H, uint32_t code, int
     add_global<VALS>(code, v, T.A, T.counts, T.sums, n);
 }
 
-template <int LAYOUT, bool VALS>
+// FMT (grid layout): the handle's format, as for grid_codes
+template <int LAYOUT, bool VALS, int FMT = 0>
 __device__ __forceinline__ void batch_item(const TaskDev &T, int64_t lo, int64_t hi,
                                            const CodeTable &H)
 {
@@ -1920,8 +1949,8 @@ __device__ __forceinline__ void batch_item(const TaskDev &T, int64_t lo, int64_t
 #pragma unroll
         for (int u = 0; u < PROBE_UNROLL; u++) {
             int64_t t = w0 + (int64_t)u * 64 + lane;
-            q[u] = t < pb ? xy4[t] : make_int4(INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN);
-            vv[u] = (VALS && t < pb) ? v2[t] : make_longlong2(0, 0);
+            q[u] = t < pb ? gld(xy4 + t) : make_int4(INT32_MIN, INT32_MIN, INT32_MIN, INT32_MIN);
+            vv[u] = (VALS && t < pb) ? gld(v2 + t) : make_longlong2(0, 0);
         }
         // points outside the viewport become a coordinate no cell holds
         int32_t xs[2 * PROBE_UNROLL], ys[2 * PROBE_UNROLL];
@@ -1934,7 +1963,10 @@ __device__ __forceinline__ void batch_item(const TaskDev &T, int64_t lo, int64_t
             ys[2 * u + 1] = k1 ? q[u].w : INT32_MIN;
         }
         uint32_t c[2 * PROBE_UNROLL];
-        codes_of_wave<LAYOUT, 2 * PROBE_UNROLL>(T.g, T.hv, xs, ys, c);
+        if (LAYOUT == 0)
+            grid_codes<2 * PROBE_UNROLL, FMT>(T.g, xs, ys, c);
+        else
+            codes_of_wave<LAYOUT, 2 * PROBE_UNROLL>(T.g, T.hv, xs, ys, c);
         // a lane's points of the trip (pairs 64 apart) often share their code
         // when the input is in spatial order: runs of one code take one add
         uint32_t cur = c[0], run = 1;
@@ -1971,16 +2003,16 @@ __device__ __forceinline__ void table_flush(const CodeTable &H, const TaskDev &T
         if (code < CODE_SET_BASE) {
             const uint32_t p = code - 1u;
             if (p >= T.A.np) continue;
-            atomicAdd(&T.counts[p], c);
-            if (vals) atomicAdd(&T.sums[p], sv);
+            gadd(&T.counts[p], c);
+            if (vals) gadd(&T.sums[p], sv);
         } else {
             const uint32_t ks = code - CODE_SET_BASE;
             if (ks >= T.A.n_sets) continue;
-            for (int64_t t = T.A.set_off[ks], e = T.A.set_off[ks + 1]; t < e; t++) {
-                const uint32_t p = (uint32_t)T.A.set_ids[t];
+            for (int64_t t = gld(T.A.set_off + ks), e = gld(T.A.set_off + ks + 1); t < e; t++) {
+                const uint32_t p = (uint32_t)gld(T.A.set_ids + t);
                 if (p >= T.A.np) continue;
-                atomicAdd(&T.counts[p], c);
-                if (vals) atomicAdd(&T.sums[p], sv);
+                gadd(&T.counts[p], c);
+                if (vals) gadd(&T.sums[p], sv);
             }
         }
     }
@@ -2099,8 +2131,18 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_batch(const TaskDev *__restrict
         TaskDev T = tasks[I.task];
         if (LAYOUT) T.hv.tab = s_htab;
         const bool vals = T.vals != nullptr && T.sums != nullptr;
-        if (vals) batch_item<LAYOUT, true>(T, I.lo, I.hi, H);
-        else batch_item<LAYOUT, false>(T, I.lo, I.hi, H);
+        if constexpr (LAYOUT == 0) {
+            // one code path per format keeps the other format's pointers out
+            // of the registers
+            const int f = T.g.compact ? 1 : 2;
+            if (vals && f == 1) batch_item<0, true, 1>(T, I.lo, I.hi, H);
+            else if (vals) batch_item<0, true, 2>(T, I.lo, I.hi, H);
+            else if (f == 1) batch_item<0, false, 1>(T, I.lo, I.hi, H);
+            else batch_item<0, false, 2>(T, I.lo, I.hi, H);
+        } else {
+            if (vals) batch_item<LAYOUT, true>(T, I.lo, I.hi, H);
+            else batch_item<LAYOUT, false>(T, I.lo, I.hi, H);
+        }
         __syncthreads();
         table_flush(H, T, vals);
         __syncthreads();
@@ -2140,10 +2182,11 @@ static void batch_prepare(const sba_task *tasks, int32_t n_tasks, std::vector<Ta
         T.xy = q.xy;
         T.vals = q.values;
         T.filt = (q.vw > 0 && q.vh > 0) ? 1 : 0;
+        // the last coordinate inside, clamped to the int32 coordinates
         T.vx0 = q.vx;
         T.vy0 = q.vy;
-        T.vx1 = (int64_t)q.vx + q.vw;
-        T.vy1 = (int64_t)q.vy + q.vh;
+        T.vx1 = (int32_t)std::min<int64_t>((int64_t)q.vx + q.vw - 1, INT32_MAX);
+        T.vy1 = (int32_t)std::min<int64_t>((int64_t)q.vy + q.vh - 1, INT32_MAX);
         T.counts = (unsigned long long *)q.counts;
         T.sums = (unsigned long long *)q.sums;
         for (int64_t a = q.lo; a < q.hi; a += BATCH_ITEM)
