@@ -421,7 +421,25 @@ __device__ __forceinline__ void learned_search_n(const HilbView &v, const uint32
     }
 }
 
-template <int SEARCH, int NP>
+// The same, NP/2 points at a time when NP >= 8 (unless FULL): each lookup
+// holds a leaf, its range and its bracket, and the learned probe runs with
+// more waves (more points in flight on the chip) when half of them are held
+// at once.  FULL keeps all NP in flight per wave: points in no order within
+// their region (the partitioned probe) take this search for nearly every
+// point and gain more from the loads in flight than from the waves.
+template <int NP, bool FULL = false>
+__device__ __forceinline__ void learned_search_halves(const HilbView &v, const uint32_t *kk,
+                                                      const uint64_t *key, int64_t *q)
+{
+    if constexpr (NP >= 8 && !FULL) {
+        learned_search_n<NP / 2>(v, kk, key, q);
+        learned_search_n<NP / 2>(v, kk + NP / 2, key + NP / 2, q + NP / 2);
+    } else {
+        learned_search_n<NP>(v, kk, key, q);
+    }
+}
+
+template <int SEARCH, int NP, bool FULL = false>
 __device__ __forceinline__ void hilbert_codes(const HilbView &v, const int32_t *xs, const int32_t *ys,
                                               uint32_t *c)
 {
@@ -446,7 +464,7 @@ __device__ __forceinline__ void hilbert_codes(const HilbView &v, const int32_t *
 #pragma unroll
         for (int k = 0; k < NP; k++) k32[k] = (uint32_t)key[k];
         if (SEARCH) {
-            learned_search_n<NP>(v, k32, key, q);
+            learned_search_halves<NP, FULL>(v, k32, key, q);
         } else {
 #pragma unroll
             for (int k = 0; k < NP; k++) q[k] = 0;
@@ -486,12 +504,12 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
-template <int SEARCH, int NP>
+template <int SEARCH, int NP, bool FULL = false>
 __device__ __forceinline__ void hilbert_codes_wave(const HilbView &v, const int32_t *xs,
                                                    const int32_t *ys, uint32_t *c)
 {
     if (v.extx == 0 || !v.k32) {  // empty handle; 64-bit keys take the plain path
-        hilbert_codes<SEARCH, NP>(v, xs, ys, c);
+        hilbert_codes<SEARCH, NP, FULL>(v, xs, ys, c);
         return;
     }
     bool ok[NP];
@@ -519,7 +537,7 @@ __device__ __forceinline__ void hilbert_codes_wave(const HilbView &v, const int3
     // (or spread over a partition region), where the bracket searches would
     // only add to the per-point ones
     if (((uint64_t)(kmax - kmin) * (uint64_t)v.n) >> (2 * v.L) > 1024) {
-        hilbert_codes<SEARCH, NP>(v, xs, ys, c);
+        hilbert_codes<SEARCH, NP, FULL>(v, xs, ys, c);
         return;
     }
     const int64_t qlo = SEARCH ? learned_search<uint32_t>(v, v.k32, kmin)
@@ -536,7 +554,7 @@ __device__ __forceinline__ void hilbert_codes_wave(const HilbView &v, const int3
             uint64_t k64[NP];
 #pragma unroll
             for (int k = 0; k < NP; k++) k64[k] = key[k];
-            learned_search_n<NP>(v, key, k64, q);
+            learned_search_halves<NP, FULL>(v, key, k64, q);
         } else {
 #pragma unroll
             for (int k = 0; k < NP; k++) q[k] = qlo;
@@ -578,12 +596,12 @@ __device__ __forceinline__ void codes_of(const GridView &g, const HilbView &hv, 
 
 // As codes_of, with the wave-bracketed lookups for the Hilbert layouts; every
 // lane of the wave must call it.
-template <int LAYOUT, int NP>
+template <int LAYOUT, int NP, bool FULL = false>
 __device__ __forceinline__ void codes_of_wave(const GridView &g, const HilbView &hv,
                                               const int32_t *xs, const int32_t *ys, uint32_t *c)
 {
     if (LAYOUT == 0) grid_codes<NP>(g, xs, ys, c);
-    else hilbert_codes_wave<LAYOUT == 2 ? 1 : 0, NP>(hv, xs, ys, c);
+    else hilbert_codes_wave<LAYOUT == 2 ? 1 : 0, NP, FULL>(hv, xs, ys, c);
 }
 
 struct Agg {
@@ -828,7 +846,7 @@ static void views(const sba_handle *h, GridView *g, HilbView *hv)
 static int g_blocks_per_cu = 8;
 
 static int launch_items(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
-                        int layout, uint64_t *counts, int64_t *sums, hipStream_t st);
+                        int layout, bool part, uint64_t *counts, int64_t *sums, hipStream_t st);
 
 
 template <int LAYOUT>
@@ -861,7 +879,7 @@ static int launch_layout(const int32_t *xy, const int64_t *values, int64_t n, co
         HIP_OK(hipGetLastError());
         return 0;
     }
-    return launch_items(xy, values, n, h, LAYOUT, counts, sums, st);
+    return launch_items(xy, values, n, h, LAYOUT, false, counts, sums, st);
 }
 
 
@@ -1673,7 +1691,7 @@ int items_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_
         if (search == SBA_SEARCH_LEARNED && !h->leaves) return SBA_EINVAL;
         layout = search == SBA_SEARCH_LEARNED ? 2 : 1;
     }
-    return launch_items(xy, values, n, h, layout, counts, sums, st);
+    return launch_items(xy, values, n, h, layout, true, counts, sums, st);
 }
 
 // Name of the kernel a range call launches ("" when it takes two passes).
@@ -1746,8 +1764,10 @@ extern "C" const char *sba_probe_kernel(const sba_handle *h, int with_values)
         return buf;
     }
     int layout = h->kind == SBA_KIND_GRID ? 0 : (h->search == SBA_SEARCH_LEARNED ? 2 : 1);
-    snprintf(buf, sizeof(buf), "%s<%d, %s>",
-             h->n_polys <= LDS_MAX_POLYS ? "k_probe_lds" : "k_probe_items", layout, v);
+    if (h->n_polys <= LDS_MAX_POLYS)
+        snprintf(buf, sizeof(buf), "k_probe_lds<%d, %s>", layout, v);
+    else
+        snprintf(buf, sizeof(buf), "k_probe_items<%d, %s, false>", layout, v);
     return buf;
 }
 
@@ -1912,8 +1932,9 @@ __device__ __forceinline__ void table_add(const CodeTable &H, uint32_t code, int
     add_global<VALS>(code, v, T.A, T.counts, T.sums, n);
 }
 
-// FMT (grid layout): the handle's format, as for grid_codes
-template <int LAYOUT, bool VALS, int FMT = 0>
+// FMT (grid layout): the handle's format, as for grid_codes; FULL: as for
+// the learned search
+template <int LAYOUT, bool VALS, int FMT = 0, bool FULL = false>
 __device__ __forceinline__ void batch_item(const TaskDev &T, int64_t lo, int64_t hi,
                                            const CodeTable &H)
 {
@@ -1966,7 +1987,7 @@ __device__ __forceinline__ void batch_item(const TaskDev &T, int64_t lo, int64_t
         if (LAYOUT == 0)
             grid_codes<2 * PROBE_UNROLL, FMT>(T.g, xs, ys, c);
         else
-            codes_of_wave<LAYOUT, 2 * PROBE_UNROLL>(T.g, T.hv, xs, ys, c);
+            codes_of_wave<LAYOUT, 2 * PROBE_UNROLL, FULL>(T.g, T.hv, xs, ys, c);
         // a lane's points of the trip (pairs 64 apart) often share their code
         // when the input is in spatial order: runs of one code take one add
         uint32_t cur = c[0], run = 1;
@@ -2030,8 +2051,13 @@ __device__ __forceinline__ void table_flush(const CodeTable &H, const TaskDev &T
 // workgroups of one XCD hold at a time come from one stretch of the input:
 // for spatially ordered or partitioned points, one region whose part of the
 // structure fits that XCD's L2.  The grid size is a multiple of 8.
-template <int LAYOUT, bool VALS>
-__global__ __launch_bounds__(PROBE_BLOCK) void k_probe_items(const TaskDev T0, int64_t item,
+// PART: the points come partitioned by region but in no order inside one
+// (the partitioned probe): nearly every lookup takes the plain search,
+// which keeps all its loads in flight per wave; otherwise the workgroup is
+// held to 4 waves per SIMD worth of registers, which points in spatial
+// order (bracketed lookups) turn into throughput.
+template <int LAYOUT, bool VALS, bool PART>
+__global__ __launch_bounds__(PROBE_BLOCK, PART ? 1 : 4) void k_probe_items(const TaskDev T0, int64_t item,
                                                              int64_t n_items)
 {
     __shared__ uint32_t s_key[ITEM_SLOTS];
@@ -2057,7 +2083,7 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_probe_items(const TaskDev T0, i
     const int64_t last = min(first + per, n_items);
     for (int64_t it = first + (blockIdx.x >> 3); it < last; it += nx) {
         const int64_t lo = it * item, hi = min(lo + item, T.n);
-        batch_item<LAYOUT, VALS>(T, lo, hi, H);
+        batch_item<LAYOUT, VALS, 0, PART>(T, lo, hi, H);
         __syncthreads();
         table_flush(H, T, VALS);
         __syncthreads();
@@ -2065,7 +2091,7 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_probe_items(const TaskDev T0, i
 }
 
 static int launch_items(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
-                        int layout, uint64_t *counts, int64_t *sums, hipStream_t st)
+                        int layout, bool part, uint64_t *counts, int64_t *sums, hipStream_t st)
 {
     const bool vals = values != nullptr && sums != nullptr;
     TaskDev T{};
@@ -2089,14 +2115,23 @@ static int launch_items(const int32_t *xy, const int64_t *values, int64_t n, con
     hipLaunchKernelGGL(k_zero_out, dim3(grid_for(h->n_polys)), dim3(256), 0, st, counts,
                        vals ? sums : nullptr, h->n_polys);
     const dim3 grid((unsigned)nb);
-    switch (layout * 2 + (vals ? 1 : 0)) {
-    case 0: hipLaunchKernelGGL((k_probe_items<0, false>), grid, dim3(PROBE_BLOCK), 0, st, T, item, n_items); break;
-    case 1: hipLaunchKernelGGL((k_probe_items<0, true>), grid, dim3(PROBE_BLOCK), 0, st, T, item, n_items); break;
-    case 2: hipLaunchKernelGGL((k_probe_items<1, false>), grid, dim3(PROBE_BLOCK), 0, st, T, item, n_items); break;
-    case 3: hipLaunchKernelGGL((k_probe_items<1, true>), grid, dim3(PROBE_BLOCK), 0, st, T, item, n_items); break;
-    case 4: hipLaunchKernelGGL((k_probe_items<2, false>), grid, dim3(PROBE_BLOCK), 0, st, T, item, n_items); break;
-    default: hipLaunchKernelGGL((k_probe_items<2, true>), grid, dim3(PROBE_BLOCK), 0, st, T, item, n_items); break;
+#define ITEMS_CASE(L, V, P)                                                                        \
+    hipLaunchKernelGGL((k_probe_items<L, V, P>), grid, dim3(PROBE_BLOCK), 0, st, T, item, n_items)
+    switch (layout * 4 + (vals ? 2 : 0) + (part ? 1 : 0)) {
+    case 0: ITEMS_CASE(0, false, false); break;
+    case 1: ITEMS_CASE(0, false, true); break;
+    case 2: ITEMS_CASE(0, true, false); break;
+    case 3: ITEMS_CASE(0, true, true); break;
+    case 4: ITEMS_CASE(1, false, false); break;
+    case 5: ITEMS_CASE(1, false, true); break;
+    case 6: ITEMS_CASE(1, true, false); break;
+    case 7: ITEMS_CASE(1, true, true); break;
+    case 8: ITEMS_CASE(2, false, false); break;
+    case 9: ITEMS_CASE(2, false, true); break;
+    case 10: ITEMS_CASE(2, true, false); break;
+    default: ITEMS_CASE(2, true, true); break;
     }
+#undef ITEMS_CASE
     HIP_OK(hipGetLastError());
     return 0;
 }
@@ -2104,7 +2139,7 @@ static int launch_items(const int32_t *xy, const int64_t *values, int64_t n, con
 // Items of one layout (each layout its own launch, so that the grid
 // probe's workgroups are not sized by the Hilbert searches' registers).
 template <int LAYOUT>
-__global__ __launch_bounds__(PROBE_BLOCK) void k_batch(const TaskDev *__restrict__ tasks,
+__global__ __launch_bounds__(PROBE_BLOCK, 4) void k_batch(const TaskDev *__restrict__ tasks,
                                                        const ItemDev *__restrict__ items,
                                                        int32_t n_items, int *__restrict__ next)
 {
