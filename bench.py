@@ -54,7 +54,13 @@ def probe_source_sha() -> str:
 # a device copy of known size), keyed by the workload and by the hash of the
 # probe kernels' source the counters were taken on: any change to that source
 # makes the entry stale, and the line then reports null.
-TRAFFIC = {}
+TRAFFIC = {
+    # profiles/city_eps10m_probe_counters.md: FETCH_SIZE 898,897 KiB and
+    # WRITE_SIZE 1,040 KiB per dispatch (mean of 6); the 1 GiB copy read
+    # 524,318 / wrote 1,048,576 KiB (factors 1.99989 and 1.0)
+    ("city", 1000, 100_000_000, "k_probe_grid16<true, 2, 2, 1024>", "aa0dfb478ee6c192"):
+        {"fetch_bytes": 1840835723, "write_bytes": 1064960},
+}
 
 
 def traffic_of(workload, eps, n, kernel):
@@ -69,6 +75,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="city", choices=["city", "tiny", "quadtree", "serve"])
     ap.add_argument("--queries", type=int, default=2000, help="serving: queries per load phase")
+    ap.add_argument("--batch-rounds", type=int, default=0,
+                    help="serving: instead of the load phases, time the batch probe alone: per "
+                         "round, build --queries queries with the server paused, then run "
+                         "their batches")
     ap.add_argument("--points", type=int, default=0, help="0 = the workload's size")
     ap.add_argument("--qt-points", type=int, default=1_000_000_000,
                     help="points of the quadtree and serving parts of the default run")
@@ -145,6 +155,44 @@ def probe_only(args, sba, torch, txy, tv, ro, vo, pxy, eps, layout, search, n):
 
 
 # ------------------------------------------------------------------ serving
+
+def serve_batches_only(torch, txy, tv, n_queries, rounds, sets):
+    """The batch probe without the builds beside it: per round the server
+    builds the approximations of n_queries queries while paused, then runs
+    their batches; points scanned per second over the batch phases."""
+    import paper_2010_12548_amd.serve as serve
+    from gen import CITY_BOX, seeds, viewport_queries
+    qs = viewport_queries(n_queries * rounds + 64, seeds(5)["queries"], n_sets=len(sets))
+    Q = [serve.Query(q["vx"], q["vy"], q["vw"], q["eps"], q["set"], q["agg"]) for q in qs]
+    S = serve.Server(txy, tv, sets, (0, 0, CITY_BOX), G=256)
+    out = {"rounds": []}
+    try:
+        [f.result() for f in [S.submit(q) for q in Q[-64:]]]
+        t_all, p_all = 0.0, 0
+        for r in range(rounds):
+            S.pause()
+            futs = [S.submit(q) for q in Q[r * n_queries:(r + 1) * n_queries]]
+            t_wait = time.perf_counter()
+            while S.n_ready() < n_queries and time.perf_counter() - t_wait < 60:
+                time.sleep(0.005)
+            ready = S.n_ready()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            S.resume()
+            res = [f.result() for f in futs]
+            dt = time.perf_counter() - t0
+            pts = sum(x.points_scanned for x in res)
+            t_all += dt
+            p_all += pts
+            row = {"queries": n_queries, "built_before_batches": ready,
+                   "queries_per_s": n_queries / dt, "points_per_s": pts / dt}
+            out["rounds"].append(row)
+            log(f"[bench] serve batches only: {json.dumps(row)}")
+        out["points_per_s"] = p_all / t_all
+    finally:
+        S.close()
+    return out
+
 
 def serve_bench(torch, txy, tv, n_queries, sets):
     """Viewport-query serving on the resident points: capacity (closed loop),
@@ -568,7 +616,10 @@ def serving_part(args, torch, qt_polys=None):
     txy = torch.from_numpy(xy).cuda()
     tv = torch.from_numpy(vals).cuda()
     del xy, vals
-    res = serve_bench(torch, txy, tv, args.queries, sets)
+    if args.batch_rounds:
+        res = serve_batches_only(torch, txy, tv, args.queries, args.batch_rounds, sets)
+    else:
+        res = serve_bench(torch, txy, tv, args.queries, sets)
     del txy, tv
     torch.cuda.empty_cache()
     return res
@@ -598,6 +649,14 @@ def main():
 
     if args.workload == "serve":
         res = serving_part(args, torch)
+        if args.batch_rounds:
+            print(json.dumps({"metric": "serving batch probe points/s", "value": res["points_per_s"],
+                              "unit": "points/s", "n_gpus": 1, "higher_is_better": True,
+                              "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+                              "data": "synthetic",
+                              "config": {"workload": "serve: batches of paused queries"},
+                              "serving": res}), flush=True)
+            return
         cl = res["closed_loop"]
         print(json.dumps({"metric": METRIC, "value": cl["queries_per_s"], "unit": "queries/s",
                           "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
