@@ -131,6 +131,27 @@ __global__ __launch_bounds__(PART_BLOCK) void k_part_scatter(
     }
 }
 
+// The runs that hold each bucket's keys when the buckets are the top 8 bits
+// of a Hilbert handle's 2L-bit keys (bucket b: keys b << bshift ..): bq[b] =
+// the run holding key b << bshift, bq[256] = the last run.
+__global__ void k_part_bq(const uint32_t *k32, int64_t nr, int bshift, int64_t *bq)
+{
+    const int b = threadIdx.x;
+    if (b > 256) return;
+    if (b == 256) {
+        bq[256] = nr - 1;
+        return;
+    }
+    const uint32_t key = (uint32_t)((uint64_t)b << bshift);
+    int64_t lo = 0, len = nr;
+    while (len > 1) {
+        const int64_t half = len >> 1;
+        lo = k32[lo + half] <= key ? lo + half : lo;
+        len -= half;
+    }
+    bq[b] = lo;
+}
+
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 extern "C" size_t sba_partition_scratch_bytes(int64_t n, int with_values)
@@ -138,7 +159,7 @@ extern "C" size_t sba_partition_scratch_bytes(int64_t n, int with_values)
     if (n <= 0) return 256;
     const int64_t nblocks = (n + PART_CHUNK - 1) / PART_CHUNK;
     return align256((size_t)n * 8) + (with_values ? align256((size_t)n * 8) : 0) +
-           align256((size_t)nblocks * 256 * 8) + align256(256 * 8);
+           align256((size_t)nblocks * 256 * 8) + align256(256 * 8) + align256(257 * 8);
 }
 
 extern "C" int sba_aggregate_partitioned(const int32_t *xy, const int64_t *values, int64_t n,
@@ -170,6 +191,8 @@ extern "C" int sba_aggregate_partitioned(const int32_t *xy, const int64_t *value
     int64_t *hist = (int64_t *)p;
     p += align256((size_t)nblocks * 256 * 8);
     unsigned long long *dtot = (unsigned long long *)p;
+    p += align256(256 * 8);
+    int64_t *bq = (int64_t *)p;
 
     PartGeo g{};
     g.ox = h->gi0 * h->s;
@@ -194,6 +217,17 @@ extern "C" int sba_aggregate_partitioned(const int32_t *xy, const int64_t *value
         hipLaunchKernelGGL(k_part_scatter<false>, dim3((unsigned)nblocks), dim3(PART_BLOCK), 0, st,
                            xy, values, n, g, hist, nblocks, oxy, ovals);
     HIP_OK(hipGetLastError());
-    return items_launch((const int32_t *)oxy, ovals, n, h, search, counts, vals ? sums : nullptr,
-                        st);
+    // the binary search of a Hilbert handle whose buckets are the top 8 bits
+    // of its keys searches each item's region (its buckets' runs) only
+    PartRegions reg{}, *regp = nullptr;
+    if (h->kind == SBA_KIND_HILBERT && search == SBA_SEARCH_BINARY && h->starts32 &&
+        h->level >= 4 && lb == h->level && h->n_runs > 0) {
+        reg = PartRegions{bq, hist, nblocks, 2 * h->level - 8};
+        hipLaunchKernelGGL(k_part_bq, dim3(1), dim3(320), 0, st, h->starts32, h->n_runs,
+                           reg.bshift, bq);
+        HIP_OK(hipGetLastError());
+        regp = &reg;
+    }
+    return items_launch((const int32_t *)oxy, ovals, n, h, search, regp, counts,
+                        vals ? sums : nullptr, st);
 }

@@ -63,6 +63,11 @@ struct HilbView {
     const int4 *leaves;
     const int32_t *leaf_lo;
     const uint16_t *tab;   // Hilbert table in LDS (set by the kernel) or NULL
+    // Region of a partitioned item (set by the kernel, NULL otherwise): runs
+    // sq0 .. sq1 hold every key of the item's points, and samp (in LDS) holds
+    // every sS-th of their starts, sn of them: samp[j] = k32[sq0 + j * sS].
+    const uint32_t *samp;
+    int32_t sq0, sq1, sS, sn;
 };
 
 // the Hilbert key of cell (i, j) of the view's grid
@@ -504,6 +509,36 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
+// Binary search through a partitioned item's region: the last sample
+// start <= key in LDS, then the at most sS runs after it in global memory
+// (one or two cache lines) instead of a search over every run.
+template <int NP>
+__device__ __forceinline__ void hilbert_codes_region(const HilbView &v, const uint32_t *key,
+                                                     const bool *ok, uint32_t *c)
+{
+    int32_t j[NP];
+#pragma unroll
+    for (int k = 0; k < NP; k++) j[k] = 0;
+    for (int32_t len = v.sn; len > 1;) {
+        const int32_t half = len >> 1;
+#pragma unroll
+        for (int k = 0; k < NP; k++) j[k] = v.samp[j[k] + half] <= key[k] ? j[k] + half : j[k];
+        len -= half;
+    }
+    int32_t lo[NP], len[NP];
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        lo[k] = v.sq0 + j[k] * v.sS;
+        len[k] = min(v.sS, v.sq1 + 1 - lo[k]);
+    }
+    pred_search_var4<NP>(v.k32, lo, len, key);
+    uint32_t r[NP];
+#pragma unroll
+    for (int k = 0; k < NP; k++) r[k] = v.code[lo[k]];
+#pragma unroll
+    for (int k = 0; k < NP; k++) c[k] = ok[k] ? r[k] : 0u;
+}
+
 template <int SEARCH, int NP, bool FULL = false>
 __device__ __forceinline__ void hilbert_codes_wave(const HilbView &v, const int32_t *xs,
                                                    const int32_t *ys, uint32_t *c)
@@ -524,6 +559,12 @@ __device__ __forceinline__ void hilbert_codes_wave(const HilbView &v, const int3
         key[k] = (uint32_t)hkey(v, i, j);
         kmin = ok[k] ? min(kmin, key[k]) : kmin;
         kmax = ok[k] ? max(kmax, key[k]) : kmax;
+    }
+    if constexpr (FULL && !SEARCH) {
+        if (v.samp) {  // a partitioned item's region
+            hilbert_codes_region<NP>(v, key, ok, c);
+            return;
+        }
     }
     kmin = wave_min_u32(kmin);
     kmax = wave_max_u32(kmax);
@@ -846,7 +887,8 @@ static void views(const sba_handle *h, GridView *g, HilbView *hv)
 static int g_blocks_per_cu = 8;
 
 static int launch_items(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
-                        int layout, bool part, uint64_t *counts, int64_t *sums, hipStream_t st);
+                        int layout, bool part, uint64_t *counts, int64_t *sums, hipStream_t st,
+                        const PartRegions *regions = nullptr);
 
 
 template <int LAYOUT>
@@ -1683,7 +1725,8 @@ int range_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_
 }
 
 int items_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
-                 int32_t search, uint64_t *counts, int64_t *sums, hipStream_t st)
+                 int32_t search, const PartRegions *regions, uint64_t *counts, int64_t *sums,
+                 hipStream_t st)
 {
     if (h->n_polys == 0) return 0;
     int layout = 0;
@@ -1691,7 +1734,8 @@ int items_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_
         if (search == SBA_SEARCH_LEARNED && !h->leaves) return SBA_EINVAL;
         layout = search == SBA_SEARCH_LEARNED ? 2 : 1;
     }
-    return launch_items(xy, values, n, h, layout, true, counts, sums, st);
+    return launch_items(xy, values, n, h, layout, true, counts, sums, st,
+                        layout == 1 ? regions : nullptr);
 }
 
 // Name of the kernel a range call launches ("" when it takes two passes).
@@ -1872,6 +1916,7 @@ struct TaskDev {
     int32_t vx0, vy0, vx1, vy1;  // viewport [vx0, vx1] x [vy0, vy1] (inclusive)
     unsigned long long *counts;
     unsigned long long *sums;
+    PartRegions reg;             // the items kernel over partitioned points (bq NULL: none)
 };
 
 struct ItemDev {
@@ -2051,6 +2096,42 @@ __device__ __forceinline__ void table_flush(const CodeTable &H, const TaskDev &T
 // workgroups of one XCD hold at a time come from one stretch of the input:
 // for spatially ordered or partitioned points, one region whose part of the
 // structure fits that XCD's L2.  The grid size is a multiple of 8.
+// The region of a partitioned item [lo, hi): the buckets of its first and
+// last points, the runs that hold their keys, and every S-th start of those
+// runs in LDS (S the smallest step that fits ITEM_SAMPLES of them).  Every
+// thread of the workgroup calls it; it returns after a barrier.
+#define ITEM_SAMPLES 4096
+__device__ __forceinline__ void stage_region(const TaskDev &T, int64_t lo, int64_t hi,
+                                             uint32_t *samp, int32_t *reg)
+{
+    if (threadIdx.x == 0) {
+        // last bucket b with start <= p: buckets may be empty, so this is
+        // the bucket that holds point p
+        auto bucket_of = [&](int64_t p) {
+            int32_t b = 0, len = 256;
+            while (len > 1) {
+                const int32_t half = len >> 1;
+                b = gld(T.reg.bstart + (int64_t)(b + half) * T.reg.bstride) <= p ? b + half : b;
+                len -= half;
+            }
+            return b;
+        };
+        const int32_t b0 = bucket_of(lo), b1 = bucket_of(hi - 1);
+        const int64_t q0 = gld(T.reg.bq + b0), q1 = gld(T.reg.bq + b1 + 1);
+        const int64_t m = q1 - q0 + 1;
+        const int64_t step = (m + ITEM_SAMPLES - 1) / ITEM_SAMPLES;
+        reg[0] = (int32_t)q0;
+        reg[1] = (int32_t)q1;
+        reg[2] = (int32_t)step;
+        reg[3] = (int32_t)((m + step - 1) / step);
+    }
+    __syncthreads();
+    const int32_t q0 = reg[0], step = reg[2], ns = reg[3];
+    for (int32_t j = threadIdx.x; j < ns; j += PROBE_BLOCK)
+        samp[j] = gld(T.hv.k32 + q0 + (int64_t)j * step);
+    __syncthreads();
+}
+
 // PART: the points come partitioned by region but in no order inside one
 // (the partitioned probe): nearly every lookup takes the plain search,
 // which keeps all its loads in flight per wave; otherwise the workgroup is
@@ -2065,6 +2146,9 @@ __global__ __launch_bounds__(PROBE_BLOCK, PART ? 1 : 4) void k_probe_items(const
     __shared__ unsigned long long s_sum[ITEM_SLOTS];
     __shared__ int s_full;
     __shared__ uint16_t s_htab[LAYOUT ? HILBERT_TAB : 1];
+    constexpr bool REGIONS = PART && LAYOUT == 1;
+    __shared__ uint32_t s_samp[REGIONS ? ITEM_SAMPLES : 1];
+    __shared__ int32_t s_reg[4];
     const CodeTable H{s_key, s_cnt, s_sum, &s_full, ITEM_SLOTS_LOG2};
     for (int k = threadIdx.x; k < ITEM_SLOTS; k += PROBE_BLOCK) {
         s_key[k] = BATCH_EMPTY;
@@ -2083,6 +2167,16 @@ __global__ __launch_bounds__(PROBE_BLOCK, PART ? 1 : 4) void k_probe_items(const
     const int64_t last = min(first + per, n_items);
     for (int64_t it = first + (blockIdx.x >> 3); it < last; it += nx) {
         const int64_t lo = it * item, hi = min(lo + item, T.n);
+        if constexpr (REGIONS) {
+            if (T.reg.bq) {
+                stage_region(T, lo, hi, s_samp, s_reg);
+                T.hv.samp = s_samp;
+                T.hv.sq0 = s_reg[0];
+                T.hv.sq1 = s_reg[1];
+                T.hv.sS = s_reg[2];
+                T.hv.sn = s_reg[3];
+            }
+        }
         batch_item<LAYOUT, VALS, 0, PART>(T, lo, hi, H);
         __syncthreads();
         table_flush(H, T, VALS);
@@ -2091,7 +2185,8 @@ __global__ __launch_bounds__(PROBE_BLOCK, PART ? 1 : 4) void k_probe_items(const
 }
 
 static int launch_items(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
-                        int layout, bool part, uint64_t *counts, int64_t *sums, hipStream_t st)
+                        int layout, bool part, uint64_t *counts, int64_t *sums, hipStream_t st,
+                        const PartRegions *regions)
 {
     const bool vals = values != nullptr && sums != nullptr;
     TaskDev T{};
@@ -2104,6 +2199,7 @@ static int launch_items(const int32_t *xy, const int64_t *values, int64_t n, con
     T.vals = vals ? values : nullptr;
     T.counts = (unsigned long long *)counts;
     T.sums = vals ? (unsigned long long *)sums : nullptr;
+    if (regions && layout == 1 && h->starts32) T.reg = *regions;
     // about ITEMS_PER_WG items per workgroup (even sizes keep the pairs
     // aligned), so the round robin ends evenly
     int64_t nb = std::max<int64_t>(

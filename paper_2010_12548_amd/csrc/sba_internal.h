@@ -445,8 +445,22 @@ int probe_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_
 int lookup_launch(const sba_handle *h, const int64_t *ij, int64_t n, int32_t *ref, hipStream_t st);
 // the probe over contiguous items of points with an LDS table of cell codes
 // (any layout; for points in spatial order)
+// Points partitioned into 256 buckets by the top 8 bits of their Hilbert
+// keys (2L-bit keys, bucket = key >> bshift): bucket b starts at
+// bstart[b * bstride] of the partitioned array, and runs bq[b] .. bq[b + 1]
+// hold every key of bucket b (bq has 257 entries, on the device).
+struct PartRegions {
+    const int64_t *bq;
+    const int64_t *bstart;
+    int64_t bstride;
+    int32_t bshift;
+};
+
+// The item probe over partitioned points (regions: NULL, or the buckets of a
+// Hilbert handle's points for its binary search).
 int items_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
-                 int32_t search, uint64_t *counts, int64_t *sums, hipStream_t st);
+                 int32_t search, const PartRegions *regions, uint64_t *counts, int64_t *sums,
+                 hipStream_t st);
 int range_launch(const int32_t *xy, const int64_t *values, int64_t n, const sba_handle *h,
                  const sba_handle *hb, uint64_t *counts, int64_t *sums, uint64_t *bcounts,
                  int64_t *bsums, hipStream_t st);
