@@ -99,7 +99,9 @@ def parse():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--grid16-per-cu", type=int, default=0,
                     help="cap on workgroups per CU of the LDS-directory grid probe (0 = none)")
-    ap.add_argument("--log2-leaves", type=int, default=16, help="learned index leaves (log2)")
+    ap.add_argument("--log2-leaves", type=int, default=20,
+                    help="learned index leaves (log2); 2^20 keeps the quadtree leaves' error "
+                         "below 56 runs (2^16: 238)")
     ap.add_argument("--tile-log2", type=int, default=0, help="grid tile side log2 (0 = auto)")
     ap.add_argument("--sub-log2", type=int, default=0, help="grid sub-tile side log2 (0 = auto)")
     ap.add_argument("--force-wide", action="store_true",
