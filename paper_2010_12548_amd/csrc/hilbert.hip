@@ -262,16 +262,33 @@ __device__ __forceinline__ int64_t lower_bound_u64(const uint64_t *a, int64_t n,
     return lo;
 }
 
-// one wavefront per leaf: key range, least-squares fit, exact error bound
-__global__ void k_leaf_fit(const uint64_t *starts, int64_t n, float a, uint32_t nl, uint64_t total,
-                           int4 *leaves, int32_t *leaf_lo, unsigned long long *err_stats)
+// first q >= from with a[q] >= v (a[from - 1] < v when from > 0): doubling
+// steps from `from`, then a binary search in the last step (a leaf holds a
+// few dozen runs, so this takes a few loads where a search over all runs
+// would take about 25)
+__device__ __forceinline__ int64_t lower_bound_from(const uint64_t *a, int64_t n, int64_t from,
+                                                    uint64_t v)
 {
-    int64_t l = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    int lane = threadIdx.x & 63;
-    if (l >= nl) return;
-    uint64_t K0 = leaf_first_key((uint32_t)l, a, nl, total);
-    uint64_t K1 = (l + 1 < nl) ? leaf_first_key((uint32_t)l + 1, a, nl, total) : total;
-    int64_t lo = lower_bound_u64(starts, n, K0), hi = lower_bound_u64(starts, n, K1);
+    if (from >= n || a[from] >= v) return from;
+    int64_t base = from, step = 1;  // a[base] < v
+    while (base + step < n && a[base + step] < v) {
+        base += step;
+        step <<= 1;
+    }
+    int64_t lo = base + 1, hi = min(base + step, n);  // the answer is in [lo, hi]
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// The fit of leaf l over the run starts [lo, hi) of its keys [K0, K1) by one
+// wavefront; returns its error bound (every lane).
+__device__ int64_t leaf_fit_one(const uint64_t *starts, int64_t n, uint32_t nl, uint32_t l,
+                                uint64_t K0, uint64_t K1, int64_t lo, int64_t hi, int lane,
+                                int4 *leaves, int32_t *leaf_lo)
+{
     // least squares of y = q - lo against x = starts[q] - K0 over q in [lo, hi)
     double sx = 0, sy = 0, sxx = 0, sxy = 0;
     for (int64_t q = lo + lane; q < hi; q += 64) {
@@ -322,10 +339,43 @@ __global__ void k_leaf_fit(const uint64_t *starts, int64_t n, float a, uint32_t 
         leaves[l] = make_int4(lf.x, lf.y, lf.z, (int)err);
         leaf_lo[l] = (int32_t)lo;
         if (l == nl - 1) leaf_lo[nl] = (int32_t)n;
-        atomicMax(&err_stats[0], (unsigned long long)err);
-        atomicAdd(&err_stats[1], (unsigned long long)err);
+    }
+    return err;
+}
+
+// Each wavefront fits a contiguous chunk of leaves: key range, least-squares
+// fit, exact error bound.  A leaf's end (key and run position) is the next
+// leaf's start, found from it by doubling steps, and the wave adds the
+// largest and the summed error of its leaves to err_stats once.
+__global__ void k_leaf_fit(const uint64_t *starts, int64_t n, float a, uint32_t nl, uint64_t total,
+                           int4 *leaves, int32_t *leaf_lo, unsigned long long *err_stats)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t chunk = ((int64_t)nl + waves - 1) / waves;
+    const int64_t l0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * chunk;
+    const int64_t l1 = min(l0 + chunk, (int64_t)nl);
+    unsigned long long emax = 0, esum = 0;
+    if (l0 < l1) {
+        uint64_t K0 = leaf_first_key((uint32_t)l0, a, nl, total);
+        int64_t lo = lower_bound_u64(starts, n, K0);
+        for (int64_t l = l0; l < l1; l++) {
+            const uint64_t K1 = (l + 1 < nl) ? leaf_first_key((uint32_t)l + 1, a, nl, total) : total;
+            const int64_t hi = lower_bound_from(starts, n, lo, K1);
+            const int64_t err =
+                leaf_fit_one(starts, n, nl, (uint32_t)l, K0, K1, lo, hi, lane, leaves, leaf_lo);
+            emax = max(emax, (unsigned long long)err);
+            esum += (unsigned long long)err;
+            K0 = K1;
+            lo = hi;
+        }
+    }
+    if (lane == 0 && esum + emax > 0) {
+        atomicMax(&err_stats[0], emax);
+        atomicAdd(&err_stats[1], esum);
     }
 }
+
 
 int hilbert_finish(BuildState &B, sba_handle *h, const sba_build_opts &o, hipStream_t st)
 {
@@ -389,7 +439,8 @@ int hilbert_finish(BuildState &B, sba_handle *h, const sba_build_opts &o, hipStr
         HIP_OK(hipMemsetAsync(stats, 0, 2 * sizeof(unsigned long long), st));
         RC(handle_alloc(h, &h->leaves, nl));
         RC(handle_alloc(h, &h->leaf_lo, (int64_t)nl + 1));
-        hipLaunchKernelGGL(k_leaf_fit, dim3(grid_for((int64_t)nl * 64)), dim3(256), 0, st, h->starts,
+        const int64_t fit_blocks = std::min<int64_t>(grid_for((int64_t)nl * 64), 4096);
+        hipLaunchKernelGGL(k_leaf_fit, dim3((unsigned)fit_blocks), dim3(256), 0, st, h->starts,
                            nr, h->root_a, nl, total, h->leaves, h->leaf_lo, stats);
         HIP_OK(hipGetLastError());
         unsigned long long hs[2];
