@@ -77,9 +77,11 @@ int sba_debug_pindex_lb(const struct sba_pindex *ix, const uint64_t *v, int64_t 
 /* The build's stable LSD radix sort: n DEVICE keys ordered by their low
  * `bits` bits (1..64), the optional DEVICE uint32 payload `vals` (may be
  * null) moved with them; the result is left in keys/vals.  The passes take
- * 8 bits each and cover ceil(bits / 8) whole bytes, so keys must be below
- * 2^bits (as the build's are); bytes above those are ignored.  SBA_EINVAL
- * for a bad size or bit count.  Synchronous.  Test support. */
+ * 8-bit digits, or 9-bit ones for fewer than 4,194,304 keys where
+ * ceil(bits / 9) < ceil(bits / 8), and cover whole digits, so keys must be
+ * below 2^bits (as the build's are); bits above the last digit are ignored
+ * (for a multiple of 8 bits: the bytes above them).  SBA_EINVAL for a bad
+ * size or bit count.  Synchronous.  Test support. */
 int sba_debug_radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int32_t bits, void *stream);
 
 /* The build's batched exclusive prefix sums: for k < m (1..8), out[k][i] =

@@ -280,7 +280,8 @@ def radix_sort(keys, vals=None, bits: int = 64, stream=None):
     """Sort the int64 GPU tensor `keys` in place by its low `bits` bits, read
     as unsigned, with the build's stable radix sort; the int32 GPU tensor
     `vals` (same length) moves along.  Keys must be below 2^bits: the passes
-    cover whole bytes.  Test support."""
+    cover whole digits (8 bits, or 9 for small sorts where that saves a
+    pass).  Test support."""
     torch = _torch()
     if keys.dtype != torch.int64 or not keys.is_cuda or not keys.is_contiguous():
         raise ValueError("keys: contiguous int64 GPU tensor")

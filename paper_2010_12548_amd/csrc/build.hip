@@ -313,17 +313,30 @@ __global__ void k_ev_values(const uint32_t *kind, int64_t n, int64_t *v)
 // flag[t] = 1 when t is the last event of its (polygon, row, x) group and
 // the polygon's membership at x differs from its membership just before x
 // (a toggle).  Toggles of one (polygon, row) alternate on/off, starting with
-// on, so consecutive pairs are the maximal covered intervals [a, b).
-__global__ void k_toggle_flags(const uint64_t *key, const uint32_t *kind, const int64_t *cex,
-                               int64_t n, int xbits, int64_t *flag, int *err)
+// on, so consecutive pairs are the maximal covered intervals [a, b).  The
+// group's first event comes from a ballot of the wavefront's group heads; only
+// a group that began in an earlier wavefront is walked back in memory.
+__global__ __launch_bounds__(256) void k_toggle_flags(const uint64_t *key, const uint32_t *kind,
+                                                      const int64_t *cex, int64_t n, int xbits,
+                                                      int64_t *flag, int *err)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    uint64_t k = key[t];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool in = t < n;
+    const uint64_t k = in ? key[t] : 0;
+    const bool head = in && (t == 0 || key[t - 1] != k);
+    const uint64_t heads = __ballot(head);
+    if (!in) return;
     int64_t f = 0;
     if (t + 1 == n || key[t + 1] != k) {
-        int64_t a = t;
-        while (a > 0 && key[a - 1] == k) a--;
+        // heads at or before this lane (2 << 63 wraps to 0: all lanes)
+        const uint64_t le = heads & ((2ull << lane) - 1);
+        int64_t a = t - lane;
+        if (le) {
+            a += 63 - __clzll(le);
+        } else {
+            while (a > 0 && key[a - 1] == k) a--;
+        }
         uint64_t g = k >> xbits;
         int64_t before = (a > 0 && (key[a - 1] >> xbits) == g) ? cov_after(cex, kind, a - 1) : 0;
         int64_t after = cov_after(cex, kind, t);
@@ -346,48 +359,53 @@ __global__ void k_toggle_emit(const uint64_t *key, const int64_t *toff, int64_t 
     tpoly[o] = (int32_t)(k >> rxbits);
 }
 
-__global__ void k_unique_emit(const uint64_t *keys, int64_t n, const int64_t *pos, uint64_t *out)
-{
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    if (t == 0 || keys[t] != keys[t - 1]) out[pos[t]] = keys[t];
-}
-
 __global__ void k_iota_u32(uint32_t *v, int64_t n)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) v[t] = (uint32_t)t;
 }
 
-// Index in the sorted distinct toggle positions E of every toggle: the
-// sorted copy of the toggles carries each one's original slot src[t]; a
-// sorted entry's index among the distinct keys is the number of first
-// occurrences before it (pos, exclusive), less one when it repeats the key
-// before it.
-__global__ void k_toggle_rank(const uint64_t *keys, int64_t n, const int64_t *pos,
-                              const uint32_t *src, int64_t *rank)
+// One pass over the toggles sorted by position (row << xbits | x), each
+// carrying its original slot src[t] (slot 2m opens covered interval m, slot
+// 2m + 1 closes it).  pos is the exclusive count of first occurrences, nu
+// its total (the number of distinct positions).  Writes
+//  * E: the sorted distinct positions, which cut every row into elementary
+//    pieces [E[k], E[k+1]) of constant polygon set;
+//  * rank[slot]: the index in E of every toggle;
+//  * diff[k]: intervals opening at E[k] less intervals closing there (the
+//    depth of piece k is the prefix sum), formed by the first toggle of each
+//    distinct position over its run of equal positions; entries nu..n are
+//    zeroed here.
+__global__ void k_unique_rank(const uint64_t *keys, int64_t n, const int64_t *pos,
+                              const int64_t *nu_p, const uint32_t *src, uint64_t *E,
+                              int64_t *rank, int64_t *diff)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
-    const bool first = t == 0 || keys[t] != keys[t - 1];
-    rank[src[t]] = pos[t] - (first ? 0 : 1);
+    const uint64_t k = keys[t];
+    const bool first = t == 0 || k != keys[t - 1];
+    const int64_t r = pos[t] - (first ? 0 : 1);
+    rank[src[t]] = r;
+    if (first) {
+        E[r] = k;
+        int64_t d = 0;
+        for (int64_t u = t; u < n && keys[u] == k; u++) d += (src[u] & 1u) ? -1 : 1;
+        diff[r] = d;
+    }
+    const int64_t nu = *nu_p;
+    if (t >= nu) diff[t] = 0;
+    if (t == n - 1) diff[n] = 0;
 }
 
-// The sorted distinct toggle positions E (row << xbits | x) cut every row
-// into elementary pieces [E[k], E[k+1]) of constant polygon set.  Covered
-// interval m spans pieces [ka, kb), the indices in E of its two toggles; the
-// depth of piece k is the number of intervals spanning it (difference array,
-// scanned later).
-__global__ void k_interval_span(const int64_t *rank, int64_t nint, int64_t *ika, int64_t *cnt,
-                                int64_t *diff)
+// Covered interval m spans pieces [ka, kb), the indices in E of its two
+// toggles.
+__global__ void k_interval_span(const int64_t *rank, int64_t nint, int64_t *ika, int64_t *cnt)
 {
     int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= nint) return;
     const int64_t ka = rank[2 * m], kb = rank[2 * m + 1];
     ika[m] = ka;
     cnt[m] = kb - ka;
-    atomicAdd((unsigned long long *)&diff[ka], 1ull);
-    atomicAdd((unsigned long long *)&diff[kb], ~0ull);
 }
 
 // per piece: packed counters (non-empty << 32 | multi) and multi member count
@@ -1010,33 +1028,28 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     RC(B.alloc(&dex, NP));
     RC(B.alloc(&segc, NP));
     RC(B.alloc(&mm, NP));
-    HIP_OK(hipMemsetAsync(diff, 0, sizeof(int64_t) * (NP + 1), st));
+    if (NT == 0) HIP_OK(hipMemsetAsync(diff, 0, sizeof(int64_t) * (NP + 1), st));
     if (NT) {
         if (NT >= ((int64_t)1 << 32)) return SBA_ELIMIT;
         // sorted with each toggle's slot as payload, so that every toggle
-        // learns its index in E without a search
+        // learns its index in E without a search (the toggle keys are not
+        // needed in slot order afterwards)
         uint32_t *src = nullptr;
         int64_t *rank = nullptr;
         RC(B.alloc(&src, NT));
         RC(B.alloc(&rank, NT));
-        HIP_OK(hipMemcpyAsync(E, tkey, sizeof(uint64_t) * NT, hipMemcpyDeviceToDevice, st));
         hipLaunchKernelGGL(k_iota_u32, dim3(grid_for(NT)), dim3(256), 0, st, src, NT);
         HIP_OK(hipGetLastError());
-        RC(radix_sort_u64_ws(&E, &src, NT, rxbits, B.ws));
-        hipLaunchKernelGGL(k_flag_new, dim3(grid_for(NT)), dim3(256), 0, st, E, NT, pos);
+        RC(radix_sort_u64_ws(&tkey, &src, NT, rxbits, B.ws));
+        hipLaunchKernelGGL(k_flag_new, dim3(grid_for(NT)), dim3(256), 0, st, tkey, NT, pos);
         HIP_OK(hipGetLastError());
         RC(scan_exclusive_i64(pos, pos, NT, tot + 1, st, &B.ws));
-        uint64_t *Eu = nullptr;
-        RC(B.alloc(&Eu, NT));
-        hipLaunchKernelGGL(k_unique_emit, dim3(grid_for(NT)), dim3(256), 0, st, E, NT, pos, Eu);
-        hipLaunchKernelGGL(k_toggle_rank, dim3(grid_for(NT)), dim3(256), 0, st, E, NT, pos, src,
-                           rank);
+        hipLaunchKernelGGL(k_unique_rank, dim3(grid_for(NT)), dim3(256), 0, st, tkey, NT, pos,
+                           tot + 1, src, E, rank, diff);
         HIP_OK(hipGetLastError());
-        B.release(E);
         B.release(src);
-        E = Eu;
         hipLaunchKernelGGL(k_interval_span, dim3(grid_for(NI)), dim3(256), 0, st, rank, NI, ika,
-                           xoff, diff);
+                           xoff);
         HIP_OK(hipGetLastError());
         B.release(rank);
     }

@@ -285,12 +285,13 @@ int scan_exclusive_i64_multi(int m, const int64_t *const *in, int64_t *const *ou
 
 // ---------------------------------------------------------------- radix sort
 //
-// One pass per 8-bit digit, least significant first.  A block sorts a tile
-// of RS_TILE keys: each of its 4 waves owns a contiguous quarter and walks it
-// 64 keys at a time; lanes with equal digits find each other with 8 ballots,
-// so the rank of a key among equal digits before it is a popcount and the
-// pass is stable.  Keys are staged in LDS in digit order and written out in
-// runs, which keeps the global writes coalesced.
+// One pass per digit of RB = 8 bits (9 bits for sorts under RS_SMALL keys
+// whose key width then needs one pass fewer), least significant first.  A
+// block sorts a tile of RS_TILE keys: each of its 4 waves owns a contiguous
+// quarter and walks it 64 keys at a time; lanes with equal digits find each
+// other with RB ballots, so the rank of a key among equal digits before it is
+// a popcount and the pass is stable.  Keys are staged in LDS in digit order
+// and written out in runs, which keeps the global writes coalesced.
 
 #define RS_BLOCK 256
 #define RS_WAVES (RS_BLOCK / 64)
@@ -300,7 +301,7 @@ int scan_exclusive_i64_multi(int m, const int64_t *const *in, int64_t *const *ou
 // holding the rest of a CU); 16 for larger inputs (fewer offsets to scan).
 #define RS_SMALL (4 << 20)
 #define RS_MID (64 << 20)
-#define RS_RADIX 256
+#define RS_RADIX 256       // digits of an 8-bit pass (the partition pass uses these offsets)
 
 // per block and digit: count, laid out digit-major (hist[d * nblocks + b]).
 // A workgroup counts `span` consecutive tiles, TPW at a time with every key
@@ -309,33 +310,36 @@ int scan_exclusive_i64_multi(int m, const int64_t *const *in, int64_t *const *ou
 // here: each row scan below leaves its digit's total, and the scatter adds
 // the totals of the lower digits itself, so the pass needs no device-wide
 // atomics and no zeroed counters.
-template <int ROUNDS, int TPW>
+template <int ROUNDS, int TPW, int RB>
 __global__ __launch_bounds__(RS_BLOCK) void k_rs_hist(const uint64_t *keys, int64_t n, int shift,
                                                       int64_t *hist, int64_t nblocks, int64_t span)
 {
-    constexpr int RS_TILE = RS_BLOCK * ROUNDS;
-    __shared__ uint32_t h[TPW][RS_RADIX];
-    const int d = threadIdx.x;
+    constexpr int RS_TILE = RS_BLOCK * ROUNDS, RADIX = 1 << RB;
+    __shared__ uint32_t h[TPW][RADIX];
     const int64_t bfirst = (int64_t)blockIdx.x * span;
     const int64_t blast = min(bfirst + span, nblocks);
     for (int64_t b0 = bfirst; b0 < blast; b0 += TPW) {
 #pragma unroll
-        for (int t = 0; t < TPW; t++) h[t][d] = 0;
+        for (int t = 0; t < TPW; t++)
+            for (int d = threadIdx.x; d < RADIX; d += RS_BLOCK) h[t][d] = 0;
         __syncthreads();
         uint32_t dg[TPW * ROUNDS];
 #pragma unroll
         for (int k = 0; k < TPW * ROUNDS; k++) {
             const int64_t idx = b0 * RS_TILE + (int64_t)k * RS_BLOCK + threadIdx.x;
-            dg[k] = (idx < n && b0 + k / ROUNDS < blast) ? (uint32_t)(keys[idx] >> shift) & 0xffu
-                                                         : RS_RADIX;
+            dg[k] = (idx < n && b0 + k / ROUNDS < blast)
+                        ? (uint32_t)(keys[idx] >> shift) & (uint32_t)(RADIX - 1)
+                        : RADIX;
         }
 #pragma unroll
         for (int k = 0; k < TPW * ROUNDS; k++)
-            if (dg[k] < RS_RADIX) atomicAdd(&h[k / ROUNDS][dg[k]], 1u);
+            if (dg[k] < RADIX) atomicAdd(&h[k / ROUNDS][dg[k]], 1u);
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < TPW; t++) {
-            if (b0 + t < blast) hist[(int64_t)d * nblocks + b0 + t] = h[t][d];
+            if (b0 + t < blast)
+                for (int d = threadIdx.x; d < RADIX; d += RS_BLOCK)
+                    hist[(int64_t)d * nblocks + b0 + t] = h[t][d];
         }
     }
 }
@@ -414,32 +418,44 @@ int rs_offsets_launch(int64_t *hist, int64_t nblocks, const unsigned long long *
     return 0;
 }
 
-template <bool HAS_VALS, int ROUNDS>
+template <bool HAS_VALS, int ROUNDS, int RB>
 __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const uint64_t *keys, const uint32_t *vals,
                                                          uint64_t *okeys, uint32_t *ovals,
                                                          int64_t n, int shift,
                                                          const int64_t *goff, int64_t nblocks,
                                                          const int64_t *rowtot)
 {
-    constexpr int RS_ROUNDS = ROUNDS, RS_TILE = RS_BLOCK * ROUNDS;
-    __shared__ uint32_t wcnt[RS_WAVES][RS_RADIX];
-    __shared__ uint32_t bdoff[RS_RADIX];
+    constexpr int RS_ROUNDS = ROUNDS, RS_TILE = RS_BLOCK * ROUNDS, RADIX = 1 << RB;
+    constexpr int DPT = RADIX / RS_BLOCK;  // digits per thread, consecutive
+    constexpr uint32_t DMASK = RADIX - 1;
+    __shared__ uint32_t wcnt[RS_WAVES][RADIX];
+    __shared__ uint32_t bdoff[RADIX];
     // output position of the block's first key of each digit, less that
     // key's place in the staged tile
-    __shared__ int64_t dbase[RS_RADIX];
+    __shared__ int64_t dbase[RADIX];
     __shared__ uint64_t skeys[RS_TILE];
     __shared__ uint32_t svals[HAS_VALS ? RS_TILE : 1];
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    // digit threadIdx.x: the block's offset within the digit, and the keys of
-    // all lower digits
-    const int64_t myoff = goff[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+    const int d0 = threadIdx.x * DPT;
+    // digits d0 .. d0 + DPT - 1: the block's offset within each digit, and
+    // the keys of all lower digits
     {
+        int64_t rt[DPT], run = 0;
+#pragma unroll
+        for (int j = 0; j < DPT; j++) {
+            rt[j] = rowtot[d0 + j];
+            run += rt[j];
+        }
         int64_t below;
-        block_excl_scan<int64_t>(rowtot[threadIdx.x], &below);
-        dbase[threadIdx.x] = below + myoff;
+        block_excl_scan<int64_t>(run, &below);
+#pragma unroll
+        for (int j = 0; j < DPT; j++) {
+            dbase[d0 + j] = below + goff[(int64_t)(d0 + j) * nblocks + blockIdx.x];
+            below += rt[j];
+        }
     }
-    for (int k = threadIdx.x; k < RS_WAVES * RS_RADIX; k += RS_BLOCK) (&wcnt[0][0])[k] = 0;
+    for (int k = threadIdx.x; k < RS_WAVES * RADIX; k += RS_BLOCK) (&wcnt[0][0])[k] = 0;
     __syncthreads();
 
     const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
@@ -455,10 +471,10 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const uint64_t *keys, c
         uint64_t key = valid ? keys[idx] : 0;
         kk[q] = key;
         if (HAS_VALS) vv[q] = valid ? vals[idx] : 0;
-        uint32_t d = (uint32_t)(key >> shift) & 0xffu;
+        uint32_t d = (uint32_t)(key >> shift) & DMASK;
         uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; b++) {
+        for (int b = 0; b < RB; b++) {
             uint64_t bal = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? bal : ~bal;
         }
@@ -470,27 +486,36 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const uint64_t *keys, c
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    // digit d = threadIdx.x: totals, wave prefixes, block-wide digit offsets
+    // digits d0 ..: totals, wave prefixes, block-wide digit offsets
     {
-        const int d = threadIdx.x;
-        uint32_t run = 0;
+        uint32_t cnt[DPT], run = 0;
 #pragma unroll
-        for (int k = 0; k < RS_WAVES; k++) {
-            uint32_t c = wcnt[k][d];
-            wcnt[k][d] = run;
-            run += c;
+        for (int j = 0; j < DPT; j++) {
+            uint32_t r = 0;
+#pragma unroll
+            for (int k = 0; k < RS_WAVES; k++) {
+                uint32_t c = wcnt[k][d0 + j];
+                wcnt[k][d0 + j] = r;
+                r += c;
+            }
+            cnt[j] = r;
+            run += r;
         }
         uint32_t excl;
         block_excl_scan<uint32_t>(run, &excl);
-        bdoff[d] = excl;
-        dbase[d] -= (int64_t)excl;
+#pragma unroll
+        for (int j = 0; j < DPT; j++) {
+            bdoff[d0 + j] = excl;
+            dbase[d0 + j] -= (int64_t)excl;
+            excl += cnt[j];
+        }
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < RS_ROUNDS; q++) {
         int64_t idx = wbase + q * 64 + lane;
         if (idx < n) {
-            uint32_t d = (uint32_t)(kk[q] >> shift) & 0xffu;
+            uint32_t d = (uint32_t)(kk[q] >> shift) & DMASK;
             uint32_t p = bdoff[d] + wcnt[w][d] + loc[q];
             skeys[p] = kk[q];
             if (HAS_VALS) svals[p] = vv[q];
@@ -501,7 +526,7 @@ __global__ __launch_bounds__(RS_BLOCK) void k_rs_scatter(const uint64_t *keys, c
     if (tn > RS_TILE) tn = RS_TILE;
     for (int i = threadIdx.x; i < tn; i += RS_BLOCK) {
         uint64_t key = skeys[i];
-        uint32_t d = (uint32_t)(key >> shift) & 0xffu;
+        uint32_t d = (uint32_t)(key >> shift) & DMASK;
         int64_t g = dbase[d] + i;
         okeys[g] = key;
         if (HAS_VALS) ovals[g] = svals[i];
@@ -512,8 +537,15 @@ static int rs_rounds(int64_t n) { return n < RS_SMALL ? 4 : (n < RS_MID ? 8 : 16
 
 static int64_t rs_blocks(int64_t n) { return (n + RS_BLOCK * rs_rounds(n) - 1) / (RS_BLOCK * rs_rounds(n)); }
 
-// one pass over digit (keys >> shift) & 255
-template <int ROUNDS>
+// digit width of a sort of n keys of `bits` bits: 9 where that saves a pass
+// for the small sorts (the build's), else 8
+static int rs_digit_bits(int64_t n, int bits)
+{
+    return (n < RS_SMALL && (bits + 8) / 9 < (bits + 7) / 8) ? 9 : 8;
+}
+
+// one pass over digit (keys >> shift) & (2^RB - 1)
+template <int ROUNDS, int RB>
 static int rs_pass_t(const uint64_t *ka, const uint32_t *va, uint64_t *kb, uint32_t *vb, int64_t n,
                      int shift, int64_t *goff, int64_t nblocks, int64_t *rowtot, hipStream_t st)
 {
@@ -521,31 +553,35 @@ static int rs_pass_t(const uint64_t *ka, const uint32_t *va, uint64_t *kb, uint3
     // (every tile its own workgroup), else 16 keys a thread and at most about
     // 2048 workgroups
     if (nblocks <= 2048) {
-        hipLaunchKernelGGL((k_rs_hist<ROUNDS, 1>), dim3((unsigned)nblocks), dim3(RS_BLOCK), 0, st,
-                           ka, n, shift, goff, nblocks, (int64_t)1);
+        hipLaunchKernelGGL((k_rs_hist<ROUNDS, 1, RB>), dim3((unsigned)nblocks), dim3(RS_BLOCK), 0,
+                           st, ka, n, shift, goff, nblocks, (int64_t)1);
     } else {
         constexpr int TPW = 16 / ROUNDS;
         const int64_t span = TPW * ((nblocks + TPW * 2048 - 1) / (TPW * 2048));
-        hipLaunchKernelGGL((k_rs_hist<ROUNDS, TPW>), dim3((unsigned)((nblocks + span - 1) / span)),
-                           dim3(RS_BLOCK), 0, st, ka, n, shift, goff, nblocks, span);
+        hipLaunchKernelGGL((k_rs_hist<ROUNDS, TPW, RB>),
+                           dim3((unsigned)((nblocks + span - 1) / span)), dim3(RS_BLOCK), 0, st, ka,
+                           n, shift, goff, nblocks, span);
     }
-    hipLaunchKernelGGL(k_rs_rowscan, dim3(RS_RADIX), dim3(RS_BLOCK), 0, st, goff, nblocks, rowtot);
+    hipLaunchKernelGGL(k_rs_rowscan, dim3(1u << RB), dim3(RS_BLOCK), 0, st, goff, nblocks, rowtot);
     if (va)
-        hipLaunchKernelGGL((k_rs_scatter<true, ROUNDS>), dim3((unsigned)nblocks), dim3(RS_BLOCK), 0,
-                           st, ka, va, kb, vb, n, shift, goff, nblocks, rowtot);
+        hipLaunchKernelGGL((k_rs_scatter<true, ROUNDS, RB>), dim3((unsigned)nblocks),
+                           dim3(RS_BLOCK), 0, st, ka, va, kb, vb, n, shift, goff, nblocks, rowtot);
     else
-        hipLaunchKernelGGL((k_rs_scatter<false, ROUNDS>), dim3((unsigned)nblocks), dim3(RS_BLOCK), 0,
-                           st, ka, va, kb, vb, n, shift, goff, nblocks, rowtot);
+        hipLaunchKernelGGL((k_rs_scatter<false, ROUNDS, RB>), dim3((unsigned)nblocks),
+                           dim3(RS_BLOCK), 0, st, ka, va, kb, vb, n, shift, goff, nblocks, rowtot);
     return hipGetLastError() == hipSuccess ? 0 : SBA_EDEVICE;
 }
 
 static int rs_pass(const uint64_t *ka, const uint32_t *va, uint64_t *kb, uint32_t *vb, int64_t n,
-                   int shift, int64_t *goff, int64_t nblocks, int64_t *rowtot, hipStream_t st)
+                   int shift, int rb, int64_t *goff, int64_t nblocks, int64_t *rowtot,
+                   hipStream_t st)
 {
     const int r = rs_rounds(n);
-    if (r == 4) return rs_pass_t<4>(ka, va, kb, vb, n, shift, goff, nblocks, rowtot, st);
-    if (r == 8) return rs_pass_t<8>(ka, va, kb, vb, n, shift, goff, nblocks, rowtot, st);
-    return rs_pass_t<16>(ka, va, kb, vb, n, shift, goff, nblocks, rowtot, st);
+    if (r == 4)
+        return rb == 9 ? rs_pass_t<4, 9>(ka, va, kb, vb, n, shift, goff, nblocks, rowtot, st)
+                       : rs_pass_t<4, 8>(ka, va, kb, vb, n, shift, goff, nblocks, rowtot, st);
+    if (r == 8) return rs_pass_t<8, 8>(ka, va, kb, vb, n, shift, goff, nblocks, rowtot, st);
+    return rs_pass_t<16, 8>(ka, va, kb, vb, n, shift, goff, nblocks, rowtot, st);
 }
 
 int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStream_t st,
@@ -558,13 +594,14 @@ int radix_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, hipStrea
     int64_t *goff = nullptr, *rowtot = nullptr;
     int rc = tmp_get(ws, &k2, n, st);
     if (!rc && vals) rc = tmp_get(ws, &v2, n, st);
-    if (!rc) rc = tmp_get(ws, &goff, nblocks * RS_RADIX, st);
-    if (!rc) rc = tmp_get(ws, &rowtot, RS_RADIX, st);
-    const int passes = (bits + 7) / 8;
+    const int rb = rs_digit_bits(n, bits);
+    if (!rc) rc = tmp_get(ws, &goff, nblocks << rb, st);
+    if (!rc) rc = tmp_get(ws, &rowtot, (int64_t)1 << rb, st);
+    const int passes = (bits + rb - 1) / rb;
     uint64_t *ka = keys, *kb = k2;
     uint32_t *va = vals, *vb = v2;
     for (int p = 0; p < passes && !rc; p++) {
-        rc = rs_pass(ka, va, kb, vb, n, 8 * p, goff, nblocks, rowtot, st);
+        rc = rs_pass(ka, va, kb, vb, n, rb * p, rb, goff, nblocks, rowtot, st);
         if (rc) break;
         uint64_t *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
@@ -593,13 +630,14 @@ int radix_sort_u64_ws(uint64_t **keys, uint32_t **vals, int64_t n, int bits, Wor
     int64_t *goff = nullptr, *rowtot = nullptr;
     RC(ws.alloc(&k2, n));
     if (vals && *vals) RC(ws.alloc(&v2, n));
-    RC(ws.alloc(&goff, nblocks * RS_RADIX));
-    RC(ws.alloc(&rowtot, RS_RADIX));
-    const int passes = (bits + 7) / 8;
+    const int rb = rs_digit_bits(n, bits);
+    RC(ws.alloc(&goff, nblocks << rb));
+    RC(ws.alloc(&rowtot, (int64_t)1 << rb));
+    const int passes = (bits + rb - 1) / rb;
     uint64_t *ka = *keys, *kb = k2;
     uint32_t *va = vals ? *vals : nullptr, *vb = v2;
     for (int p = 0; p < passes; p++) {
-        RC(rs_pass(ka, va, kb, vb, n, 8 * p, goff, nblocks, rowtot, st));
+        RC(rs_pass(ka, va, kb, vb, n, rb * p, rb, goff, nblocks, rowtot, st));
         std::swap(ka, kb);
         std::swap(va, vb);
     }

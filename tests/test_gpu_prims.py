@@ -58,13 +58,24 @@ def test_radix_sort(sba, kind, n):
     check_sort(sba, keys, 64 if kind == "random" else 48)
 
 
-@pytest.mark.parametrize("bits", [1, 7, 8, 9, 21, 33, 63, 64])
+@pytest.mark.parametrize("bits", [1, 7, 8, 9, 17, 21, 26, 33, 35, 63, 64])
 def test_radix_sort_bits(sba, bits):
     # keys below 2^bits, as every caller's are
     rng = np.random.default_rng(bits)
     keys = rng.integers(-2**63, 2**63 - 1, 200_003, dtype=np.int64)
     keys = (keys.view(np.uint64) & np.uint64(2**bits - 1)).view(np.int64)
     check_sort(sba, keys, bits)
+
+
+@pytest.mark.parametrize("kind", ["random", "equal", "sorted", "reverse", "few"])
+@pytest.mark.parametrize("n", [1000, 1024 * 4 * 4 + 3, 300_001])
+def test_radix_sort_nine_bit_digits(sba, kind, n):
+    # 35-bit keys (the build's event keys at city sizes) take four 9-bit
+    # passes instead of five 8-bit ones
+    rng = np.random.default_rng(n * 11 + len(kind))
+    keys = keys_of(kind, n, rng)
+    keys = (keys.view(np.uint64) & np.uint64(2**35 - 1)).view(np.int64)
+    check_sort(sba, keys, 35)
 
 
 @pytest.mark.parametrize("nbytes", [1, 3, 5, 7])
