@@ -711,7 +711,13 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(k_steps):
-            hs.append(step(evs[k]))
+            a = step(evs[k])
+            if pstream is None and hs:
+                # on one stream the build just made has synchronised it, so
+                # the previous step's probe is done: its approximation goes
+                # back to the library's memory cache for the next build
+                hs[-1].close(sync=False)
+            hs.append(a)
         torch.cuda.synchronize()
         return time.perf_counter() - t0, evs, hs
 

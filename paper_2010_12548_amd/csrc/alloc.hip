@@ -10,9 +10,17 @@
 // build.  Handle arrays come from the same cache and return to it when the
 // handle is freed (the caller guarantees that no queued work still reads
 // them).  Small values read back to the host go through one pinned staging
-// buffer per workspace, so a group of reads costs one synchronisation.
+// buffer per workspace, so a group of reads costs one synchronisation: one
+// small kernel copies them into the (coherent) staging buffer and then raises
+// a flag there, which the host polls for a short while before it falls back
+// to a blocking stream synchronisation.  A build makes several such reads, and
+// the poll returns in a few microseconds where waking from a blocking wait
+// and a copy-engine transfer take tens.
 // A build given a device allocator of the caller's takes every block of its
 // temporaries and of its handle from it instead, and gives each back to it.
+#include <atomic>
+#include <chrono>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -32,6 +40,12 @@ struct DevCache {
 DevCache g_cache[MAX_DEV];
 
 constexpr size_t PINNED_BYTES = 4096;
+// the staged values sit below FLAG_OFF; the flag word (a number unique to
+// each sync) above it
+constexpr size_t FLAG_OFF = PINNED_BYTES - 64;
+// how long the host polls the flag before it blocks on the stream
+constexpr double POLL_US = 300.0;
+std::atomic<uint32_t> g_read_seq{0};
 
 size_t class_size(size_t bytes)
 {
@@ -175,6 +189,38 @@ void Workspace::put(void *p)
     }
 }
 
+// Copies the queued reads into the staging buffer (one workgroup; sizes and
+// offsets in bytes, 8-byte words where both ends allow), then makes them
+// visible to the host before it writes `seq` to the flag word.
+struct ReadSet {
+    const unsigned char *src[WS_MAX_READS];
+    uint32_t off[WS_MAX_READS], bytes[WS_MAX_READS];
+    int n;
+    unsigned char *dst;  // device address of the staging buffer
+    uint32_t seq;
+};
+
+__global__ __launch_bounds__(64) void k_readback(ReadSet R)
+{
+    for (int r = 0; r < R.n; r++) {
+        const unsigned char *src = R.src[r];
+        unsigned char *dst = R.dst + R.off[r];
+        const uint32_t nb = R.bytes[r];
+        if ((((uintptr_t)src | (uintptr_t)dst | nb) & 7) == 0) {
+            for (uint32_t k = threadIdx.x; k < nb / 8; k += 64)
+                ((uint64_t *)dst)[k] = ((const uint64_t *)src)[k];
+        } else {
+            for (uint32_t k = threadIdx.x; k < nb; k += 64) dst[k] = src[k];
+        }
+    }
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence_system();
+        *(volatile uint32_t *)(R.dst + FLAG_OFF) = R.seq;
+    }
+}
+
 int Workspace::read(void *host, const void *dev, size_t bytes)
 {
     if (dev_ < 0) return SBA_EDEVICE;
@@ -186,24 +232,61 @@ int Workspace::read(void *host, const void *dev, size_t bytes)
                 g_cache[dev_].pinned.pop_back();
             }
         }
-        if (!pinned_ && hipHostMalloc((void **)&pinned_, PINNED_BYTES, hipHostMallocDefault) !=
-                            hipSuccess) {
-            (void)hipGetLastError();
-            pinned_ = nullptr;
-            return SBA_ENOMEM;
+        if (!pinned_) {
+            if (hipHostMalloc((void **)&pinned_, PINNED_BYTES, hipHostMallocCoherent) !=
+                hipSuccess) {
+                (void)hipGetLastError();
+                pinned_ = nullptr;
+                return SBA_ENOMEM;
+            }
+            *(volatile uint32_t *)(pinned_ + FLAG_OFF) = 0;
         }
+        void *dp = nullptr;
+        if (hipHostGetDevicePointer(&dp, pinned_, 0) != hipSuccess || !dp) {
+            (void)hipGetLastError();
+            return SBA_EDEVICE;
+        }
+        pinned_dev_ = (char *)dp;
     }
     size_t off = (staged_ + 15) & ~(size_t)15;
-    if (off + bytes > PINNED_BYTES) return SBA_ELIMIT;
-    HIP_OK(hipMemcpyAsync(pinned_ + off, dev, bytes, hipMemcpyDeviceToHost, st_));
-    reads_.push_back(Read{host, off, bytes});
+    if (off + bytes > FLAG_OFF || reads_.size() >= WS_MAX_READS) return SBA_ELIMIT;
+    reads_.push_back(Read{host, dev, off, bytes});
     staged_ = off + bytes;
     return 0;
 }
 
 int Workspace::sync()
 {
-    HIP_OK(hipStreamSynchronize(st_));
+    if (reads_.empty()) {
+        HIP_OK(hipStreamSynchronize(st_));
+        return 0;
+    }
+    ReadSet R{};
+    for (size_t k = 0; k < reads_.size(); k++) {
+        R.src[k] = (const unsigned char *)reads_[k].dev;
+        R.off[k] = (uint32_t)reads_[k].off;
+        R.bytes[k] = (uint32_t)reads_[k].bytes;
+    }
+    R.n = (int)reads_.size();
+    R.dst = (unsigned char *)pinned_dev_;
+    uint32_t seq = g_read_seq.fetch_add(1) + 1;
+    if (seq == 0) seq = g_read_seq.fetch_add(1) + 1;  // 0 marks a fresh buffer
+    R.seq = seq;
+    hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, st_, R);
+    HIP_OK(hipGetLastError());
+    volatile uint32_t *flag = (volatile uint32_t *)(pinned_ + FLAG_OFF);
+    const auto t0 = std::chrono::steady_clock::now();
+    while (*flag != seq) {
+        if (std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0)
+                .count() > POLL_US) {
+            // a long stretch of work ahead of the reads: block instead (the
+            // kernel has ended, and its writes are visible, once this returns)
+            HIP_OK(hipStreamSynchronize(st_));
+            if (*flag != seq) return SBA_EDEVICE;
+            break;
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
     for (const Read &r : reads_) memcpy(r.host, pinned_ + r.off, r.bytes);
     reads_.clear();
     staged_ = 0;

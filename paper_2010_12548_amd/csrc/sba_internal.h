@@ -37,6 +37,9 @@ void cache_put(const DevBlock &b);
 
 // Temporaries of one stream-ordered job; the destructor synchronises the
 // stream and returns every block to the device's cache.
+// reads queued for one Workspace::sync
+#define WS_MAX_READS 8
+
 class Workspace {
 public:
     explicit Workspace(hipStream_t st);
@@ -64,13 +67,15 @@ public:
 private:
     struct Read {
         void *host;
+        const void *dev;
         size_t off, bytes;
     };
     hipStream_t st_;
     int dev_ = -1;
     std::vector<DevBlock> live_, spare_;
     std::vector<Read> reads_;
-    char *pinned_ = nullptr;
+    char *pinned_ = nullptr;      // staging buffer (host address)
+    char *pinned_dev_ = nullptr;  // its device address
     size_t staged_ = 0;
     UserAlloc ua_;
 };
