@@ -199,7 +199,9 @@ def serve_batches_only(torch, txy, tv, n_queries, rounds, sets):
 def serve_bench(torch, txy, tv, n_queries, sets):
     """Viewport-query serving on the resident points: capacity (closed loop),
     then Poisson arrivals at 0.5 / 0.8 / 0.95 of it; p50 / p99 latency from
-    arrival to result on the host."""
+    arrival to result on the host.  Every load phase replays the same queries
+    with the same arrival pattern, scaled to its rate, so that the phases
+    differ in load only (not in their mix of cheap and costly viewports)."""
     import paper_2010_12548_amd.serve as serve
     from gen import CITY_BOX, seeds, viewport_queries
     qs = viewport_queries(4 * n_queries + 64, seeds(5)["queries"], n_sets=len(sets))
@@ -222,10 +224,11 @@ def serve_bench(torch, txy, tv, n_queries, sets):
         log(f"[bench] serve closed loop: {json.dumps(out['closed_loop'])}")
         rng = np.random.default_rng(seeds(5)["queries"] + 1)
         out["open_loop"] = []
-        for k, frac in enumerate((0.5, 0.8, 0.95)):
+        qs_k = Q[n_queries:2 * n_queries]
+        unit_gaps = rng.exponential(1.0, size=len(qs_k))
+        for frac in (0.5, 0.8, 0.95):
             lam = frac * cap
-            qs_k = Q[n_queries * (k + 1):n_queries * (k + 2)]
-            gaps = rng.exponential(1.0 / lam, size=len(qs_k))
+            gaps = unit_gaps / lam
             futs = []
             t_start = time.perf_counter()
             due = t_start
