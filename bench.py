@@ -125,6 +125,28 @@ def timed(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def stream_read_rate(sba, torch, txy, tv, reps):
+    """The yardstick beside the peak: the read rate of the library's plain
+    streaming-read kernel (16-byte non-temporal loads, XOR-folded, nothing
+    written) over the probe's own inputs (x, y and values: the same bytes in
+    the same place, both streams in one launch), best over a few launch
+    shapes."""
+    out = torch.empty(1, dtype=torch.int32, device=txy.device)
+    nbytes = txy.numel() * txy.element_size() + tv.numel() * tv.element_size()
+    best = None
+    for blocks, threads in ((256, 512), (256, 1024), (512, 512), (1024, 256), (2048, 256)):
+        def run():
+            sba.stream_read(txy, tv, blocks=blocks, threads=threads, out=out)
+        run()
+        ms = timed(torch, run, reps)
+        gbps = nbytes / (ms * 1e-3) / 1e9
+        if best is None or gbps > best["gbps"]:
+            best = {"gbps": gbps, "ms": ms, "blocks": blocks, "threads": threads,
+                    "bytes": nbytes, "kernel": "k_stream_read"}
+    log(f"[bench] streaming read of the probe's inputs: {json.dumps(best)}")
+    return best
+
+
 def same_result(cc, ss, res_c, res_s):
     return bool(np.array_equal(cc.cpu().numpy().astype(np.uint64), res_c)
                 and np.array_equal(ss.cpu().numpy(), res_s))
@@ -748,6 +770,7 @@ def main():
     last = handles[-1]
     probe_avg = timed(torch, lambda: last.aggregate(txy, tv, counts, sums), max(args.steps, 10))
     achieved = alg_bytes / (probe_avg * 1e-3) / 1e9
+    read_rate = stream_read_rate(sba, torch, txy, tv, max(args.steps, 10))
     # build time on its own
     iso = []
     for _ in range(5):
@@ -819,7 +842,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_of(args.workload, eps, n, kernel),
                      "kernel": kernel, "probe_source": probe_source_sha(),
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "read_stream": read_rate,
+                     "frac_of_read_stream": achieved / read_rate["gbps"]},
         "cpu_baseline": cpu,
         "probe_ms": probe_avg,
         "probe_ms_in_step": probe_in_step,

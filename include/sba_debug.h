@@ -84,6 +84,18 @@ int sba_debug_pindex_lb(const struct sba_pindex *ix, const uint64_t *v, int64_t 
  * size or bit count.  Synchronous.  Test support. */
 int sba_debug_radix_sort(uint64_t *keys, uint32_t *vals, int64_t n, int32_t bits, void *stream);
 
+/* A plain streaming read of `bytes` DEVICE bytes at `a` and, unless `b` is
+ * null, as many at `b` (the probe's two input streams; sizes and addresses
+ * multiples of 16, SBA_EINVAL otherwise, or for blocks outside 1..65536 or
+ * threads not a multiple of 64 in 64..1024): `blocks` workgroups of
+ * `threads` lanes read the buffers in 16-byte non-temporal loads and leave
+ * the XOR of all their 32-bit words in the DEVICE word *xor_out (zeroed
+ * first).  It measures the read rate a kernel that only reads its input can
+ * reach, the yardstick of the probes' fraction of peak.  Asynchronous on
+ * `stream`.  Test and benchmark support. */
+int sba_debug_stream_read(const void *a, const void *b, int64_t bytes, int32_t blocks,
+                          int32_t threads, uint32_t *xor_out, void *stream);
+
 /* The build's batched exclusive prefix sums: for k < m (1..8), out[k][i] =
  * in[k][0] + ... + in[k][i-1] over n[k] entries (out[k] may be in[k]) and
  * total[k] = the sum of all n[k].  in, out and n are HOST arrays of m

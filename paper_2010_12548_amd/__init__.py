@@ -235,6 +235,8 @@ def lib():
     L.sba_debug_pindex_lb.argtypes = [vp, vp, i64, i32, vp, C.POINTER(i64), vp]
     L.sba_debug_radix_sort.restype = C.c_int
     L.sba_debug_radix_sort.argtypes = [vp, vp, i64, i32, vp]
+    L.sba_debug_stream_read.restype = C.c_int
+    L.sba_debug_stream_read.argtypes = [vp, vp, i64, i32, i32, vp, vp]
     L.sba_debug_scan_multi.restype = C.c_int
     L.sba_debug_scan_multi.argtypes = [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(i64), vp, vp]
     _lib = L
@@ -294,6 +296,28 @@ def radix_sort(keys, vals=None, bits: int = 64, stream=None):
     _check(lib().sba_debug_radix_sort(keys.data_ptr() or None, vp, keys.numel(), int(bits),
                                       _stream_ptr(stream)), "radix_sort")
     return keys, vals
+
+
+def stream_read(a, b=None, blocks: int = 256, threads: int = 512, out=None, stream=None):
+    """Read the contiguous GPU tensor `a` and, if given, `b` (the same size in
+    bytes, a multiple of 16) with the library's plain streaming-read kernel
+    (`blocks` workgroups of `threads` lanes); returns the one-element int32
+    GPU tensor that receives the XOR of all their 32-bit words.  Benchmark and
+    test support (the read rate a kernel that only reads can reach)."""
+    torch = _torch()
+    nbytes = a.numel() * a.element_size()
+    for t in (a, b):
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("a, b: contiguous GPU tensors")
+    if b is not None and b.numel() * b.element_size() != nbytes:
+        raise ValueError("b: as many bytes as a")
+    if out is None:
+        out = torch.empty(1, dtype=torch.int32, device=a.device)
+    _check(lib().sba_debug_stream_read(a.data_ptr() or None,
+                                       None if b is None else (b.data_ptr() or None), nbytes,
+                                       int(blocks), int(threads), out.data_ptr(),
+                                       _stream_ptr(stream)), "stream_read")
+    return out
 
 
 def scan_multi(arrays, in_place: bool = False, stream=None):

@@ -675,3 +675,58 @@ extern "C" int sba_debug_scan_multi(int32_t m, const int64_t *const *in, int64_t
     HIP_OK(hipStreamSynchronize(st));
     return 0;
 }
+
+// ---------------------------------------------------------------- read rate
+//
+// The plain streaming read that bounds what a kernel which only reads its
+// input can reach on the device: each lane walks one or two equally long
+// buffers (the probe's two input streams) in 16-byte non-temporal loads, four
+// per buffer in flight, and folds them into an XOR (one atomic per
+// wavefront), so that no load can be dropped and nothing is written but one
+// word.
+
+typedef uint32_t rd4_t __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(1024) void k_stream_read(const rd4_t *p, const rd4_t *q, int64_t n16,
+                                                      unsigned int *out)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t acc = 0;
+    auto fold = [](rd4_t v) { return v.x ^ v.y ^ v.z ^ v.w; };
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        rd4_t a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) a[u] = __builtin_nontemporal_load(p + i + u * stride);
+        if (q) {
+#pragma unroll
+            for (int u = 0; u < 4; u++) b[u] = __builtin_nontemporal_load(q + i + u * stride);
+#pragma unroll
+            for (int u = 0; u < 4; u++) acc ^= fold(b[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) acc ^= fold(a[u]);
+    }
+    for (; i < n16; i += stride) {
+        acc ^= fold(__builtin_nontemporal_load(p + i));
+        if (q) acc ^= fold(__builtin_nontemporal_load(q + i));
+    }
+    for (int o = 32; o > 0; o >>= 1) acc ^= (uint32_t)__shfl_xor((int)acc, o, 64);
+    if ((threadIdx.x & 63) == 0) atomicXor(out, acc);
+}
+
+extern "C" int sba_debug_stream_read(const void *a, const void *b, int64_t bytes, int32_t blocks,
+                                     int32_t threads, uint32_t *xor_out, void *stream)
+{
+    if (bytes < 0 || (bytes & 15) || ((uintptr_t)a & 15) || ((uintptr_t)b & 15) ||
+        (bytes > 0 && !a) || !xor_out || blocks < 1 || blocks > 65536 || threads < 64 ||
+        threads > 1024 || (threads & 63))
+        return SBA_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_OK(hipMemsetAsync(xor_out, 0, sizeof(uint32_t), st));
+    if (bytes)
+        hipLaunchKernelGGL(k_stream_read, dim3((unsigned)blocks), dim3((unsigned)threads), 0, st,
+                           (const rd4_t *)a, (const rd4_t *)b, bytes / 16, xor_out);
+    HIP_OK(hipGetLastError());
+    return 0;
+}

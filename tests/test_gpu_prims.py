@@ -142,3 +142,37 @@ def test_scan_multi_wide_values(sba):
         want = np.concatenate([[0], np.cumsum(h)[:-1]])
         np.testing.assert_array_equal(outs[k].cpu().numpy(), want)
         assert tot[k] == h.sum()
+
+
+@pytest.mark.parametrize("nbytes", [0, 16, 4096 + 48, 64 * 1024 * 1024 + 16 * 7])
+@pytest.mark.parametrize("blocks,threads", [(1, 64), (512, 512), (256, 1024)])
+@pytest.mark.parametrize("two", [False, True])
+def test_stream_read_reads_every_word(sba, nbytes, blocks, threads, two):
+    # the streaming-read yardstick folds every 32-bit word of its buffers into
+    # one XOR: any skipped or repeated 16-byte load changes it
+    rng = np.random.default_rng(nbytes + blocks + 7 * two)
+    words = rng.integers(0, 2**32, (2 if two else 1) * (nbytes // 4),
+                         dtype=np.uint64).astype(np.uint32)
+    data = torch.from_numpy(words.view(np.int32)).cuda()
+    n = nbytes // 4
+    if two:
+        out = sba.stream_read(data[:n], data[n:], blocks=blocks, threads=threads)
+    else:
+        out = sba.stream_read(data, blocks=blocks, threads=threads)
+    torch.cuda.synchronize()
+    want = np.bitwise_xor.reduce(words) if words.size else np.uint32(0)
+    assert np.uint32(out.cpu().numpy().view(np.uint32)[0]) == want
+
+
+def test_stream_read_rejects(sba):
+    data = torch.zeros(16, dtype=torch.int32, device="cuda")
+    with pytest.raises(RuntimeError):
+        sba.stream_read(data[1:5])                 # not 16-byte aligned
+    with pytest.raises(RuntimeError):
+        sba.stream_read(data[:6])                  # 24 bytes
+    with pytest.raises(RuntimeError):
+        sba.stream_read(data, blocks=0)
+    with pytest.raises(RuntimeError):
+        sba.stream_read(data, threads=96)
+    with pytest.raises(ValueError):
+        sba.stream_read(data[:8], data[:4])        # unequal sizes
