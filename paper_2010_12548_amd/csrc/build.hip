@@ -278,6 +278,162 @@ __global__ void k_emit_cross(const int4 *edges, const int32_t *epoly, int64_t n_
     evpay[t] = EV_CROSS;
 }
 
+// ------------------------------------------------ events sorted per polygon
+//
+// The events come out of the emit kernels grouped by polygon (edges are
+// numbered polygon by polygon): the boundary events of polygon p, in edge
+// order, and further on its crossings.  Ordering them by (polygon, row, x)
+// therefore only needs each polygon's events ordered by (row, x), which one
+// workgroup does in LDS when the polygon has at most SEG_CAP events: the
+// (row, x) key and the 2-bit kind packed in 32 bits, sorted by an LSD radix
+// sort of 7-bit digits over the packed word (the order among events of equal
+// (row, x) is not used: the coverage test reads only whole groups).  The
+// polygon's sorted events land where a sort of all events by (polygon, row,
+// x) puts them: after the events of the polygons before it.
+
+#define SEG_BLOCK 1024
+#define SEG_ROUNDS 16
+#define SEG_CAP (SEG_BLOCK * SEG_ROUNDS)
+#define SEG_DBITS 7
+#define SEG_RADIX (1 << SEG_DBITS)
+#define SEG_WAVES (SEG_BLOCK / 64)
+
+struct EventSegs {
+    const int32_t *ring_off;
+    const int64_t *vert_off;
+    const int64_t *boff, *coff;  // exclusive scans of the per-edge boundary items and crossings
+    const int64_t *tot;          // tot[0], tot[1]: their totals
+    int64_t nv;                  // edges
+    int use_b, use_c;            // boundary events / crossings among the sorted events
+    int64_t cbase;               // where the crossings start in the event arrays
+};
+
+// polygon p: its sorted events' first input slot of each kind, their counts,
+// and its first output slot
+__device__ __forceinline__ void event_seg(const EventSegs &S, int p, int64_t *ib, int64_t *nbv,
+                                          int64_t *ic, int64_t *ncv, int64_t *o0)
+{
+    const int64_t e0 = S.vert_off[S.ring_off[p]], e1 = S.vert_off[S.ring_off[p + 1]];
+    const int64_t b0 = e0 < S.nv ? S.boff[e0] : S.tot[0], b1 = e1 < S.nv ? S.boff[e1] : S.tot[0];
+    const int64_t c0 = e0 < S.nv ? S.coff[e0] : S.tot[1], c1 = e1 < S.nv ? S.coff[e1] : S.tot[1];
+    *ib = 2 * b0;
+    *nbv = S.use_b ? 2 * (b1 - b0) : 0;
+    *ic = S.cbase + c0;
+    *ncv = S.use_c ? c1 - c0 : 0;
+    *o0 = (S.use_b ? 2 * b0 : 0) + (S.use_c ? c0 : 0);
+}
+
+// the largest polygon's event count, into *mx (zeroed before)
+__global__ void k_event_seg_max(EventSegs S, int32_t np, unsigned long long *mx)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    int64_t ib, nbv, ic, ncv, o0;
+    event_seg(S, p, &ib, &nbv, &ic, &ncv, &o0);
+    atomicMax(mx, (unsigned long long)(nbv + ncv));
+}
+
+// one workgroup per polygon; dynamic LDS: two buffers of `cap` words (the
+// largest polygon's event count rounded up to whole waves' rounds, at most
+// SEG_CAP) and the per-wave digit counts
+__global__ __launch_bounds__(SEG_BLOCK) void k_event_seg_sort(EventSegs S, const uint64_t *evkey,
+                                                              const uint32_t *evpay, int rxbits,
+                                                              int cap, uint64_t *okey,
+                                                              uint32_t *opay)
+{
+    extern __shared__ uint32_t seg_lds[];
+    uint32_t *src = seg_lds, *dst = seg_lds + cap;
+    uint32_t *wcnt = seg_lds + 2 * cap;  // [SEG_WAVES][SEG_RADIX]
+    __shared__ uint32_t doff[SEG_RADIX];
+    __shared__ uint32_t wtot[SEG_RADIX / 64];
+    const int p = blockIdx.x;
+    int64_t ib, nbv, ic, ncv, o0;
+    event_seg(S, p, &ib, &nbv, &ic, &ncv, &o0);
+    const int n = (int)(nbv + ncv);  // <= cap (checked by the host)
+    const uint64_t rxm = (1ull << rxbits) - 1;
+    for (int i = threadIdx.x; i < n; i += SEG_BLOCK) {
+        const int64_t at = i < nbv ? ib + i : ic + (i - nbv);
+        src[i] = (uint32_t)(((evkey[at] & rxm) << 2) | evpay[at]);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int kbits = rxbits + 2;
+    for (int shift = 0; shift < kbits; shift += SEG_DBITS) {
+        for (int k = threadIdx.x; k < SEG_WAVES * SEG_RADIX; k += SEG_BLOCK) wcnt[k] = 0;
+        __syncthreads();
+        // wave w ranks its own SEG_ROUNDS x 64 consecutive words, 64 at a
+        // time: equal digits find each other with SEG_DBITS ballots, so the
+        // order is stable
+        uint32_t kk[SEG_ROUNDS], loc[SEG_ROUNDS];
+#pragma unroll
+        for (int q = 0; q < SEG_ROUNDS; q++) {
+            // rounds past the polygon's events are skipped (uniform per wave)
+            if (w * (64 * SEG_ROUNDS) + q * 64 >= n) break;
+            const int idx = w * (64 * SEG_ROUNDS) + q * 64 + lane;
+            const bool valid = idx < n;
+            const uint32_t key = valid ? src[idx] : 0u;
+            kk[q] = key;
+            const uint32_t d = (key >> shift) & (SEG_RADIX - 1);
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < SEG_DBITS; b++) {
+                const uint64_t bal = __ballot((d >> b) & 1u);
+                peers &= ((d >> b) & 1u) ? bal : ~bal;
+            }
+            const uint32_t old = wcnt[w * SEG_RADIX + d];
+            loc[q] = old + (uint32_t)__popcll(peers & lt);
+            __builtin_amdgcn_wave_barrier();
+            if (valid && (peers & lt) == 0) wcnt[w * SEG_RADIX + d] = old + (uint32_t)__popcll(peers);
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        // digit d = threadIdx.x: offsets of the waves within the digit, then
+        // the digit's first slot
+        uint32_t run = 0, incl = 0;
+        if (threadIdx.x < SEG_RADIX) {
+            const int d = threadIdx.x;
+#pragma unroll
+            for (int k = 0; k < SEG_WAVES; k++) {
+                const uint32_t c = wcnt[k * SEG_RADIX + d];
+                wcnt[k * SEG_RADIX + d] = run;
+                run += c;
+            }
+            incl = run;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
+                if (lane >= o) incl += u;
+            }
+            if (lane == 63) wtot[w] = incl;
+        }
+        __syncthreads();
+        if (threadIdx.x < SEG_RADIX) {
+            uint32_t before = 0;
+            for (int k = 0; k < w; k++) before += wtot[k];
+            doff[threadIdx.x] = before + incl - run;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < SEG_ROUNDS; q++) {
+            const int idx = w * (64 * SEG_ROUNDS) + q * 64 + lane;
+            if (idx < n) {
+                const uint32_t d = (kk[q] >> shift) & (SEG_RADIX - 1);
+                dst[doff[d] + wcnt[w * SEG_RADIX + d] + loc[q]] = kk[q];
+            }
+        }
+        __syncthreads();
+        uint32_t *t = src;
+        src = dst;
+        dst = t;
+    }
+    const uint64_t pk = (uint64_t)p << rxbits;
+    for (int i = threadIdx.x; i < n; i += SEG_BLOCK) {
+        const uint32_t v = src[i];
+        okey[o0 + i] = pk | (uint64_t)(v >> 2);
+        opay[o0 + i] = v & 3u;
+    }
+}
+
 // ------------------------------------------------ coverage of each row
 //
 // Events carry the key (polygon, row, x) and one of three kinds: the start
@@ -941,7 +1097,15 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
         int64_t *out[2] = {nb, nc}, *sum[2] = {tot, tot + 1};
         RC(scan_exclusive_i64_multi(2, in, out, n, sum, st, &B.ws));
     }
+    // the events of the coverage, polygon by polygon: the largest polygon's
+    // count decides whether they are sorted per polygon in LDS
+    EventSegs S{polys->ring_off, polys->vert_off, nb, nc, tot, nv, B.centre ? 0 : 1,
+                B.boundary_only ? 0 : 1, 0};
+    hipLaunchKernelGGL(k_event_seg_max, dim3(grid_for(np)), dim3(256), 0, st, S, np,
+                       (unsigned long long *)(B.sc + SC_SEG_MAX));
+    HIP_OK(hipGetLastError());
     RC(fetch());
+    const int64_t seg_max = hsc[SC_SEG_MAX];
     // boundary-only approximations take no row-line crossings (no interior
     // spans); centre-sampled ones no boundary cells, except as the Hilbert
     // layout's candidate keys (where the cell sets can change along the curve)
@@ -969,8 +1133,6 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
                            nc, NC, s, gi0, gj0, gi1, B.centre ? 1 : 0, B.xbits, B.rbits, ckey,
                            cpay);
     HIP_OK(hipGetLastError());
-    B.release(nb);
-    B.release(nc);
 
     // the Hilbert layout needs the boundary cells before the events are sorted
     if (B.on_boundary_events) RC(B.on_boundary_events(B, h, st));
@@ -985,7 +1147,30 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     // polygon's coverage count at every event, whose changes (toggles) are
     // the maximal covered intervals of each polygon in each row.
     const int rxbits = B.rbits + B.xbits;
-    RC(radix_sort_u64_ws(&B.evkey, &B.evpay, NE, pbits + rxbits, B.ws));
+    if (NE > 0 && seg_max <= SEG_CAP && rxbits + 2 <= 32) {
+        uint64_t *k2 = nullptr;
+        uint32_t *v2 = nullptr;
+        RC(B.alloc(&k2, NE));
+        RC(B.alloc(&v2, NE));
+        S.cbase = B.centre ? 0 : 2 * NB;
+        const int cap = (int)std::max<int64_t>(64, (seg_max + 63) & ~(int64_t)63);
+        const int lds = (2 * cap + SEG_WAVES * SEG_RADIX) * (int)sizeof(uint32_t);
+        (void)hipFuncSetAttribute((const void *)k_event_seg_sort,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (2 * SEG_CAP + SEG_WAVES * SEG_RADIX) * (int)sizeof(uint32_t));
+        (void)hipGetLastError();
+        hipLaunchKernelGGL(k_event_seg_sort, dim3((unsigned)np), dim3(SEG_BLOCK), lds, st, S,
+                           B.evkey, B.evpay, rxbits, cap, k2, v2);
+        HIP_OK(hipGetLastError());
+        B.release(B.evkey);
+        B.release(B.evpay);
+        B.evkey = k2;
+        B.evpay = v2;
+    } else {
+        RC(radix_sort_u64_ws(&B.evkey, &B.evpay, NE, pbits + rxbits, B.ws));
+    }
+    B.release(nb);
+    B.release(nc);
     int64_t *cex = nullptr, *tf = nullptr;
     RC(B.alloc(&cex, NE));
     RC(B.alloc(&tf, NE));

@@ -9,6 +9,8 @@
 
 #define SC_SLOTS 32
 #define SC_READ 20
+// slot of the largest polygon's event count (read with the edge totals)
+#define SC_SEG_MAX 14
 
 struct BuildState {
     explicit BuildState(hipStream_t s) : st(s), ws(s) {}
