@@ -289,7 +289,12 @@ __global__ void k_emit_cross(const int4 *edges, const int32_t *epoly, int64_t n_
 // sort of 7-bit digits over the packed word (the order among events of equal
 // (row, x) is not used: the coverage test reads only whole groups).  The
 // polygon's sorted events land where a sort of all events by (polygon, row,
-// x) puts them: after the events of the polygons before it.
+// x) puts them: after the events of the polygons before it.  The same
+// workgroup then takes the coverage step for its polygon: the prefix sums of
+// the event values over the polygon (its rows are balanced, so this equals
+// the prefix over all events), each (row, x) group's toggle flag, and the
+// toggle's index among the polygon's toggles; a scan of the per-polygon
+// toggle counts places every toggle.
 
 #define SEG_BLOCK 1024
 #define SEG_ROUNDS 16
@@ -333,19 +338,52 @@ __global__ void k_event_seg_max(EventSegs S, int32_t np, unsigned long long *mx)
     atomicMax(mx, (unsigned long long)(nbv + ncv));
 }
 
+// exclusive scan across a workgroup of SEG_BLOCK lanes (wsum: SEG_WAVES words)
+__device__ __forceinline__ uint32_t seg_excl_scan(uint32_t v, uint32_t *wsum)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int k = 0; k < w; k++) before += wsum[k];
+    __syncthreads();
+    return before + incl - v;
+}
+
+// event value in 32 bits: starts and ends add +1 / -1 to the count of open
+// boundary intervals (bits 0-30, at most the polygon's event count), a
+// crossing flips bit 31 (the parity of the crossings so far)
+__device__ __forceinline__ uint32_t ev_word(uint32_t kind)
+{
+    return kind == EV_CROSS ? 0x80000000u : (kind == EV_OPEN ? 1u : 0xffffffffu);
+}
+
+__device__ __forceinline__ uint32_t cov_of(uint32_t P) { return (P & 0x7fffffffu) + (P >> 31); }
+
 // one workgroup per polygon; dynamic LDS: two buffers of `cap` words (the
 // largest polygon's event count rounded up to whole waves' rounds, at most
-// SEG_CAP) and the per-wave digit counts
+// SEG_CAP) and the per-wave digit counts.  Out: the sorted events (kind in
+// bits 0-1 of opay, bit 2 set on a toggle), each event's index among the
+// polygon's toggles before it (otl), the polygon's toggle count (ptot[p]),
+// and error bit 2 when a row ends inside the polygon
 __global__ __launch_bounds__(SEG_BLOCK) void k_event_seg_sort(EventSegs S, const uint64_t *evkey,
                                                               const uint32_t *evpay, int rxbits,
-                                                              int cap, uint64_t *okey,
-                                                              uint32_t *opay)
+                                                              int xbits, int cap, uint64_t *okey,
+                                                              uint32_t *opay, int32_t *otl,
+                                                              int64_t *ptot, int *err)
 {
     extern __shared__ uint32_t seg_lds[];
     uint32_t *src = seg_lds, *dst = seg_lds + cap;
     uint32_t *wcnt = seg_lds + 2 * cap;  // [SEG_WAVES][SEG_RADIX]
     __shared__ uint32_t doff[SEG_RADIX];
     __shared__ uint32_t wtot[SEG_RADIX / 64];
+    __shared__ uint32_t wsum[SEG_WAVES];
     const int p = blockIdx.x;
     int64_t ib, nbv, ic, ncv, o0;
     event_seg(S, p, &ib, &nbv, &ic, &ncv, &o0);
@@ -426,12 +464,73 @@ __global__ __launch_bounds__(SEG_BLOCK) void k_event_seg_sort(EventSegs S, const
         src = dst;
         dst = t;
     }
+    // coverage: each lane takes `per` consecutive sorted events; dst gets
+    // the inclusive prefix words
+    const int per = (n + SEG_BLOCK - 1) / SEG_BLOCK;
+    const int i0 = threadIdx.x * per, i1 = min(i0 + per, n);
+    uint32_t sum = 0;
+    for (int i = i0; i < i1; i++) sum += ev_word(src[i] & 3u);
+    uint32_t run = seg_excl_scan(sum, wsum);
+    for (int i = i0; i < i1; i++) {
+        run += ev_word(src[i] & 3u);
+        dst[i] = run;
+    }
+    __syncthreads();
+    // toggles: the last event of a (row, x) group where membership changes
+    // from just before the group to just after it
+    uint32_t fbits = 0, cnt = 0;
+    for (int k = 0; k < per; k++) {
+        const int i = i0 + k;
+        if (i >= n) break;
+        const uint32_t key = src[i] >> 2;
+        if (i + 1 < n && (src[i + 1] >> 2) == key) continue;
+        int a = i;
+        while (a > 0 && (src[a - 1] >> 2) == key) a--;
+        const uint32_t row = key >> xbits;
+        const uint32_t before =
+            (a > 0 && ((src[a - 1] >> 2) >> xbits) == row) ? cov_of(dst[a - 1]) : 0u;
+        const uint32_t after = cov_of(dst[i]);
+        if ((before > 0) != (after > 0)) {
+            fbits |= 1u << k;
+            cnt++;
+        }
+        if ((i + 1 == n || ((src[i + 1] >> 2) >> xbits) != row) && after != 0) atomicOr(err, 2);
+    }
+    const uint32_t tex = seg_excl_scan(cnt, wsum);
+    if (threadIdx.x == SEG_BLOCK - 1) ptot[p] = tex + cnt;
+    // dst (the prefix words, no longer needed) takes each event's toggle
+    // index and flag, so the outputs below leave in coalesced stores
+    uint32_t t = tex;
+    for (int k = 0; k < per; k++) {
+        const int i = i0 + k;
+        if (i >= n) break;
+        const uint32_t f = (fbits >> k) & 1u;
+        dst[i] = t | (f << 31);
+        t += f;
+    }
+    __syncthreads();
     const uint64_t pk = (uint64_t)p << rxbits;
     for (int i = threadIdx.x; i < n; i += SEG_BLOCK) {
-        const uint32_t v = src[i];
+        const uint32_t v = src[i], tl = dst[i];
         okey[o0 + i] = pk | (uint64_t)(v >> 2);
-        opay[o0 + i] = v & 3u;
+        opay[o0 + i] = (v & 3u) | ((tl >> 31) << 2);
+        otl[o0 + i] = (int32_t)(tl & 0x7fffffffu);
     }
+}
+
+// toggles of the per-polygon path: event t with its toggle bit set goes to
+// slot ptoff[polygon] + otl[t]
+__global__ void k_toggle_emit_seg(const uint64_t *key, const uint32_t *pay, const int32_t *otl,
+                                  const int64_t *ptoff, int64_t n, int rxbits, uint64_t *tkey,
+                                  int32_t *tpoly)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n || !(pay[t] & 4u)) return;
+    const uint64_t k = key[t];
+    const int32_t p = (int32_t)(k >> rxbits);
+    const int64_t o = ptoff[p] + otl[t];
+    tkey[o] = k & ((1ull << rxbits) - 1);
+    tpoly[o] = p;
 }
 
 // ------------------------------------------------ coverage of each row
@@ -1147,11 +1246,21 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     // polygon's coverage count at every event, whose changes (toggles) are
     // the maximal covered intervals of each polygon in each row.
     const int rxbits = B.rbits + B.xbits;
+    int64_t NT = 0;
+    uint64_t *tkey = nullptr, *E = nullptr;
+    int32_t *tpoly = nullptr;
+    int64_t *tf = nullptr;
     if (NE > 0 && seg_max <= SEG_CAP && rxbits + 2 <= 32) {
+        // per polygon in LDS: sort, coverage and toggle flags in one launch
         uint64_t *k2 = nullptr;
         uint32_t *v2 = nullptr;
+        int32_t *tl = nullptr;
+        int64_t *ptot = nullptr, *ptoff = nullptr;
         RC(B.alloc(&k2, NE));
         RC(B.alloc(&v2, NE));
+        RC(B.alloc(&tl, NE));
+        RC(B.alloc(&ptot, np));
+        RC(B.alloc(&ptoff, np));
         S.cbase = B.centre ? 0 : 2 * NB;
         const int cap = (int)std::max<int64_t>(64, (seg_max + 63) & ~(int64_t)63);
         const int lds = (2 * cap + SEG_WAVES * SEG_RADIX) * (int)sizeof(uint32_t);
@@ -1160,40 +1269,53 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
                                   (2 * SEG_CAP + SEG_WAVES * SEG_RADIX) * (int)sizeof(uint32_t));
         (void)hipGetLastError();
         hipLaunchKernelGGL(k_event_seg_sort, dim3((unsigned)np), dim3(SEG_BLOCK), lds, st, S,
-                           B.evkey, B.evpay, rxbits, cap, k2, v2);
+                           B.evkey, B.evpay, rxbits, B.xbits, cap, k2, v2, tl, ptot, err);
         HIP_OK(hipGetLastError());
+        B.release(nb);  // the edge offsets: read by the launch above, free after it in stream order
+        B.release(nc);
         B.release(B.evkey);
         B.release(B.evpay);
         B.evkey = k2;
         B.evpay = v2;
+        RC(scan_exclusive_i64(ptot, ptoff, np, tot, st, &B.ws));
+        RC(fetch());
+        NT = hsc[8];
+        herr = (int)(uint32_t)hsc[0];
+        if (herr || (NT & 1)) return SBA_EDEVICE;
+        RC(B.alloc(&tkey, std::max<int64_t>(NT, 1)));
+        RC(B.alloc(&tpoly, std::max<int64_t>(NT, 1)));
+        hipLaunchKernelGGL(k_toggle_emit_seg, dim3(grid_for(NE)), dim3(256), 0, st, B.evkey,
+                           B.evpay, tl, ptoff, NE, rxbits, tkey, tpoly);
+        HIP_OK(hipGetLastError());
+        B.release(tl);
+        B.release(ptot);
+        B.release(ptoff);
     } else {
+        B.release(nb);
+        B.release(nc);
         RC(radix_sort_u64_ws(&B.evkey, &B.evpay, NE, pbits + rxbits, B.ws));
+        int64_t *cex = nullptr;
+        RC(B.alloc(&cex, NE));
+        RC(B.alloc(&tf, NE));
+        hipLaunchKernelGGL(k_ev_values, dim3(grid_for(NE)), dim3(256), 0, st, B.evpay, NE, cex);
+        HIP_OK(hipGetLastError());
+        RC(scan_exclusive_i64(cex, cex, NE, tot, st, &B.ws));
+        hipLaunchKernelGGL(k_toggle_flags, dim3(grid_for(NE)), dim3(256), 0, st, B.evkey,
+                           B.evpay, cex, NE, B.xbits, tf, err);
+        HIP_OK(hipGetLastError());
+        RC(scan_exclusive_i64(tf, tf, NE, tot, st, &B.ws));
+        RC(fetch());
+        NT = hsc[8];
+        herr = (int)(uint32_t)hsc[0];
+        if (herr || (NT & 1)) return SBA_EDEVICE;
+        B.release(cex);
+        RC(B.alloc(&tkey, std::max<int64_t>(NT, 1)));
+        RC(B.alloc(&tpoly, std::max<int64_t>(NT, 1)));
+        hipLaunchKernelGGL(k_toggle_emit, dim3(grid_for(NE)), dim3(256), 0, st, B.evkey, tf, NE,
+                           NT, rxbits, tkey, tpoly);
+        HIP_OK(hipGetLastError());
     }
-    B.release(nb);
-    B.release(nc);
-    int64_t *cex = nullptr, *tf = nullptr;
-    RC(B.alloc(&cex, NE));
-    RC(B.alloc(&tf, NE));
-    hipLaunchKernelGGL(k_ev_values, dim3(grid_for(NE)), dim3(256), 0, st, B.evpay, NE, cex);
-    HIP_OK(hipGetLastError());
-    RC(scan_exclusive_i64(cex, cex, NE, tot, st, &B.ws));
-    hipLaunchKernelGGL(k_toggle_flags, dim3(grid_for(NE)), dim3(256), 0, st, B.evkey, B.evpay, cex,
-                       NE, B.xbits, tf, err);
-    HIP_OK(hipGetLastError());
-    RC(scan_exclusive_i64(tf, tf, NE, tot, st, &B.ws));
-    RC(fetch());
-    const int64_t NT = hsc[8];
-    herr = (int)(uint32_t)hsc[0];
-    if (herr || (NT & 1)) return SBA_EDEVICE;
-    B.release(cex);
-    uint64_t *tkey = nullptr, *E = nullptr;
-    int32_t *tpoly = nullptr;
-    RC(B.alloc(&tkey, std::max<int64_t>(NT, 1)));
-    RC(B.alloc(&tpoly, std::max<int64_t>(NT, 1)));
-    hipLaunchKernelGGL(k_toggle_emit, dim3(grid_for(NE)), dim3(256), 0, st, B.evkey, tf, NE, NT,
-                       rxbits, tkey, tpoly);
-    HIP_OK(hipGetLastError());
-    B.release(tf);
+    if (tf) B.release(tf);
     B.release(B.evkey);
     B.evkey = nullptr;
     B.release(B.evpay);
