@@ -328,11 +328,15 @@ __device__ __forceinline__ void event_seg(const EventSegs &S, int p, int64_t *ib
     *o0 = (S.use_b ? 2 * b0 : 0) + (S.use_c ? c0 : 0);
 }
 
-// the largest polygon's event count, into *mx (zeroed before)
-__global__ void k_event_seg_max(EventSegs S, int32_t np, unsigned long long *mx)
+// the largest polygon's event count, into *mx (zeroed before); also zeroes
+// the per-row toggle counters rowcnt[0..gh]
+__global__ void k_event_seg_max(EventSegs S, int32_t np, unsigned long long *mx,
+                                unsigned long long *rowcnt, int64_t gh)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t <= gh) rowcnt[t] = 0;
+    const int p = (int)t;
+    if (t >= np) return;
     int64_t ib, nbv, ic, ncv, o0;
     event_seg(S, p, &ib, &nbv, &ic, &ncv, &o0);
     atomicMax(mx, (unsigned long long)(nbv + ncv));
@@ -376,7 +380,8 @@ __global__ __launch_bounds__(SEG_BLOCK) void k_event_seg_sort(EventSegs S, const
                                                               const uint32_t *evpay, int rxbits,
                                                               int xbits, int cap, uint64_t *okey,
                                                               uint32_t *opay, int32_t *otl,
-                                                              int64_t *ptot, int *err)
+                                                              int64_t *ptot, int *err,
+                                                              unsigned long long *rowcnt)
 {
     extern __shared__ uint32_t seg_lds[];
     uint32_t *src = seg_lds, *dst = seg_lds + cap;
@@ -493,6 +498,7 @@ __global__ __launch_bounds__(SEG_BLOCK) void k_event_seg_sort(EventSegs S, const
         if ((before > 0) != (after > 0)) {
             fbits |= 1u << k;
             cnt++;
+            if (rowcnt) atomicAdd(rowcnt + row, 1ull);
         }
         if ((i + 1 == n || ((src[i + 1] >> 2) >> xbits) != row) && after != 0) atomicOr(err, 2);
     }
@@ -519,18 +525,120 @@ __global__ __launch_bounds__(SEG_BLOCK) void k_event_seg_sort(EventSegs S, const
 }
 
 // toggles of the per-polygon path: event t with its toggle bit set goes to
-// slot ptoff[polygon] + otl[t]
+// slot o = ptoff[polygon] + otl[t] (polygon, then row and x order); with row
+// buckets, (x << 32 | o) also goes to the bucket of its row, in no order
+// (rowcnt: fill counters, zero on entry)
 __global__ void k_toggle_emit_seg(const uint64_t *key, const uint32_t *pay, const int32_t *otl,
-                                  const int64_t *ptoff, int64_t n, int rxbits, uint64_t *tkey,
-                                  int32_t *tpoly)
+                                  const int64_t *ptoff, int64_t n, int rxbits, int xbits,
+                                  uint64_t *tkey, int32_t *tpoly, const int64_t *rowoff,
+                                  unsigned long long *rowcnt, uint64_t *rb)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n || !(pay[t] & 4u)) return;
     const uint64_t k = key[t];
     const int32_t p = (int32_t)(k >> rxbits);
     const int64_t o = ptoff[p] + otl[t];
-    tkey[o] = k & ((1ull << rxbits) - 1);
+    const uint64_t rx = k & ((1ull << rxbits) - 1);
+    if (tkey) tkey[o] = rx;
     tpoly[o] = p;
+    if (rb) {
+        const uint64_t row = rx >> xbits, x = rx & ((1ull << xbits) - 1);
+        const int64_t at = rowoff[row] + (int64_t)atomicAdd(rowcnt + row, 1ull);
+        rb[at] = (x << 32) | (uint64_t)o;
+    }
+}
+
+// One workgroup: row offsets of the toggle buckets (exclusive scan of
+// rowcnt[0..gh) into rowoff[0..gh], total at rowoff[gh]), the largest row's
+// count into *mx, and rowcnt zeroed again for use as fill counters.
+__global__ __launch_bounds__(SEG_BLOCK) void k_row_scan_max(unsigned long long *rowcnt, int64_t gh,
+                                                            int64_t *rowoff,
+                                                            unsigned long long *mx)
+{
+    __shared__ uint32_t wsum[SEG_WAVES];
+    __shared__ unsigned long long smax;
+    if (threadIdx.x == 0) smax = 0;
+    const int64_t per = (gh + SEG_BLOCK - 1) / SEG_BLOCK;
+    const int64_t r0 = threadIdx.x * per, r1 = min(r0 + per, gh);
+    uint32_t sum = 0;
+    unsigned long long m = 0;
+    for (int64_t r = r0; r < r1; r++) {
+        const unsigned long long c = rowcnt[r];
+        sum += (uint32_t)c;
+        m = c > m ? c : m;
+    }
+    __syncthreads();
+    atomicMax(&smax, m);
+    uint32_t run = seg_excl_scan(sum, wsum);
+    for (int64_t r = r0; r < r1; r++) {
+        rowoff[r] = run;
+        run += (uint32_t)rowcnt[r];
+        rowcnt[r] = 0;
+    }
+    if (threadIdx.x == SEG_BLOCK - 1) rowoff[gh] = run;
+    __syncthreads();
+    if (threadIdx.x == 0) *mx = smax;
+}
+
+// Rows of at most ROW_CAP toggles: one wavefront per row ranks the row's
+// (x, slot) words in LDS (a word's rank is the number of smaller words:
+// slots are distinct), then walks them in order.  The distinct positions of
+// row r take indices rowoff[r] + 0, 1, ... (a row's toggle count bounds its
+// distinct positions; the indices left over up to rowoff[r + 1] stay holes
+// of depth 0, which no piece reads), and each toggle learns its index.
+#define ROW_CAP 512
+#define ROW_WAVES 4
+__global__ __launch_bounds__(64 * ROW_WAVES) void k_row_pieces(const uint64_t *rb,
+                                                                const int64_t *rowoff, int64_t gh,
+                                                                int xbits, int64_t nt, uint64_t *E,
+                                                                int64_t *rank, int64_t *diff)
+{
+    __shared__ uint64_t raw[ROW_WAVES][ROW_CAP];
+    __shared__ uint64_t sorted[ROW_WAVES][ROW_CAP];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t r = (int64_t)blockIdx.x * ROW_WAVES + wv;
+    if (r >= gh) return;  // whole wavefronts leave; no workgroup barrier below
+    const int64_t base = rowoff[r];
+    const int c = (int)(rowoff[r + 1] - base);  // <= ROW_CAP (checked by the host)
+    uint64_t *w = raw[wv], *s = sorted[wv];
+    for (int i = lane; i < c; i += 64) w[i] = rb[base + i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int i = lane; i < c; i += 64) {
+        const uint64_t v = w[i];
+        int rk = 0;
+        for (int j = 0; j < c; j++) rk += w[j] < v ? 1 : 0;
+        s[rk] = v;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int64_t nd = 0;  // distinct positions so far
+    for (int q0 = 0; q0 < c; q0 += 64) {
+        const int q = q0 + lane;
+        const bool valid = q < c;
+        const uint64_t v = valid ? s[q] : 0ull;
+        const uint32_t x = (uint32_t)(v >> 32);
+        const bool first = valid && (q == 0 || (uint32_t)(s[q - 1] >> 32) != x);
+        const uint64_t fb = __ballot(first);
+        const uint64_t le = fb & ((2ull << lane) - 1);
+        const int64_t idx = base + nd + __popcll(le) - 1;
+        if (valid) {
+            const uint32_t slot = (uint32_t)v;
+            rank[slot] = idx;
+            if (first) {
+                E[idx] = ((uint64_t)r << xbits) | x;
+                int64_t d = 0;
+                for (int u = q; u < c && (uint32_t)(s[u] >> 32) == x; u++)
+                    d += ((uint32_t)s[u] & 1u) ? -1 : 1;
+                diff[idx] = d;
+            }
+        }
+        nd += __popcll(fb);
+    }
+    for (int64_t q = nd + lane; q < c; q += 64) diff[base + q] = 0;
+    if (r == gh - 1 && lane == 0) diff[nt] = 0;
 }
 
 // ------------------------------------------------ coverage of each row
@@ -1200,8 +1308,11 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     // count decides whether they are sorted per polygon in LDS
     EventSegs S{polys->ring_off, polys->vert_off, nb, nc, tot, nv, B.centre ? 0 : 1,
                 B.boundary_only ? 0 : 1, 0};
-    hipLaunchKernelGGL(k_event_seg_max, dim3(grid_for(np)), dim3(256), 0, st, S, np,
-                       (unsigned long long *)(B.sc + SC_SEG_MAX));
+    // per-row toggle counters of the row-bucket path, zeroed by the same launch
+    unsigned long long *rowcnt = nullptr;
+    RC(B.alloc(&rowcnt, gh + 1));
+    hipLaunchKernelGGL(k_event_seg_max, dim3(grid_for(std::max<int64_t>(np, gh + 1))), dim3(256), 0,
+                       st, S, np, (unsigned long long *)(B.sc + SC_SEG_MAX), rowcnt, gh);
     HIP_OK(hipGetLastError());
     RC(fetch());
     const int64_t seg_max = hsc[SC_SEG_MAX];
@@ -1250,6 +1361,11 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     uint64_t *tkey = nullptr, *E = nullptr;
     int32_t *tpoly = nullptr;
     int64_t *tf = nullptr;
+    // row buckets of the toggles (per-polygon path, rows of at most ROW_CAP
+    // toggles): each row's distinct positions are found in one wavefront
+    bool rows = false;
+    uint64_t *rb = nullptr;
+    int64_t *rowoff = nullptr;
     if (NE > 0 && seg_max <= SEG_CAP && rxbits + 2 <= 32) {
         // per polygon in LDS: sort, coverage and toggle flags in one launch
         uint64_t *k2 = nullptr;
@@ -1269,7 +1385,11 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
                                   (2 * SEG_CAP + SEG_WAVES * SEG_RADIX) * (int)sizeof(uint32_t));
         (void)hipGetLastError();
         hipLaunchKernelGGL(k_event_seg_sort, dim3((unsigned)np), dim3(SEG_BLOCK), lds, st, S,
-                           B.evkey, B.evpay, rxbits, B.xbits, cap, k2, v2, tl, ptot, err);
+                           B.evkey, B.evpay, rxbits, B.xbits, cap, k2, v2, tl, ptot, err, rowcnt);
+        HIP_OK(hipGetLastError());
+        RC(B.alloc(&rowoff, gh + 1));
+        hipLaunchKernelGGL(k_row_scan_max, dim3(1), dim3(SEG_BLOCK), 0, st, rowcnt, gh, rowoff,
+                           (unsigned long long *)(B.sc + SC_ROW_MAX));
         HIP_OK(hipGetLastError());
         B.release(nb);  // the edge offsets: read by the launch above, free after it in stream order
         B.release(nc);
@@ -1282,10 +1402,13 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
         NT = hsc[8];
         herr = (int)(uint32_t)hsc[0];
         if (herr || (NT & 1)) return SBA_EDEVICE;
-        RC(B.alloc(&tkey, std::max<int64_t>(NT, 1)));
+        rows = hsc[SC_ROW_MAX] <= ROW_CAP;
+        if (!rows) RC(B.alloc(&tkey, std::max<int64_t>(NT, 1)));
+        if (rows) RC(B.alloc(&rb, std::max<int64_t>(NT, 1)));
         RC(B.alloc(&tpoly, std::max<int64_t>(NT, 1)));
         hipLaunchKernelGGL(k_toggle_emit_seg, dim3(grid_for(NE)), dim3(256), 0, st, B.evkey,
-                           B.evpay, tl, ptoff, NE, rxbits, tkey, tpoly);
+                           B.evpay, tl, ptoff, NE, rxbits, B.xbits, tkey, tpoly,
+                           rows ? rowoff : nullptr, rowcnt, rb);
         HIP_OK(hipGetLastError());
         B.release(tl);
         B.release(ptot);
@@ -1336,7 +1459,18 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     RC(B.alloc(&segc, NP));
     RC(B.alloc(&mm, NP));
     if (NT == 0) HIP_OK(hipMemsetAsync(diff, 0, sizeof(int64_t) * (NP + 1), st));
-    if (NT) {
+    if (NT && rows) {
+        int64_t *rank = nullptr;
+        RC(B.alloc(&rank, NT));
+        hipLaunchKernelGGL(k_row_pieces, dim3((unsigned)((gh + ROW_WAVES - 1) / ROW_WAVES)),
+                           dim3(64 * ROW_WAVES), 0, st, rb, rowoff, gh, B.xbits, NT, E, rank,
+                           diff);
+        HIP_OK(hipGetLastError());
+        hipLaunchKernelGGL(k_interval_span, dim3(grid_for(NI)), dim3(256), 0, st, rank, NI, ika,
+                           xoff);
+        HIP_OK(hipGetLastError());
+        B.release(rank);
+    } else if (NT) {
         if (NT >= ((int64_t)1 << 32)) return SBA_ELIMIT;
         // sorted with each toggle's slot as payload, so that every toggle
         // learns its index in E without a search (the toggle keys are not
@@ -1361,6 +1495,9 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
         B.release(rank);
     }
     B.release(pos);
+    B.release(rb);
+    B.release(rowoff);
+    B.release(rowcnt);
     RC(scan_exclusive_i64(diff, dex, NP, tot + 2, st, &B.ws));
     hipLaunchKernelGGL(k_piece_classify, dim3(grid_for(NP)), dim3(256), 0, st, dex, diff, NP, segc,
                        mm, err);

@@ -11,6 +11,8 @@
 #define SC_READ 20
 // slot of the largest polygon's event count (read with the edge totals)
 #define SC_SEG_MAX 14
+// slot of the largest row's toggle count (read with the toggle total)
+#define SC_ROW_MAX 15
 
 struct BuildState {
     explicit BuildState(hipStream_t s) : st(s), ws(s) {}
