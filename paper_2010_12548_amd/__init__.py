@@ -235,6 +235,10 @@ def lib():
     L.sba_debug_pindex_lb.argtypes = [vp, vp, i64, i32, vp, C.POINTER(i64), vp]
     L.sba_debug_radix_sort.restype = C.c_int
     L.sba_debug_radix_sort.argtypes = [vp, vp, i64, i32, vp]
+    L.sba_debug_build_paths.restype = C.c_int
+    L.sba_debug_build_paths.argtypes = [C.c_int]
+    L.sba_debug_last_build_paths.restype = C.c_int
+    L.sba_debug_last_build_paths.argtypes = []
     L.sba_debug_stream_read.restype = C.c_int
     L.sba_debug_stream_read.argtypes = [vp, vp, i64, i32, i32, vp, vp]
     L.sba_debug_scan_multi.restype = C.c_int

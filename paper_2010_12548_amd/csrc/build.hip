@@ -25,6 +25,7 @@
 //   6. the segments are written into the chosen layout: a two-level tiled
 //      grid (uniform tiles stored once in a directory, mixed tiles as fine
 //      blocks) or, in hilbert.hip, the runs of the Hilbert order.
+#include <atomic>
 #include <chrono>
 #include <vector>
 
@@ -1203,6 +1204,20 @@ int key_grid_launch(const sba_polygons *sets, int32_t n_sets, int64_t eps, hipSt
     return 0;
 }
 
+// paths of the coverage stages: bits set in g_build_paths_off turn a path
+// off (1: the per-polygon event sort, 2: the toggle row buckets); the last
+// build's paths taken, same bits (tests of both sides of each choice)
+static std::atomic<int> g_build_paths_off{0}, g_build_paths_last{0};
+
+extern "C" int sba_debug_build_paths(int off)
+{
+    if (off < 0 || off > 3) return SBA_EINVAL;
+    g_build_paths_off = off;
+    return 0;
+}
+
+extern "C" int sba_debug_last_build_paths(void) { return g_build_paths_last.load(); }
+
 int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_handle *h,
                    BuildState &B, bool need_boundary_cells)
 {
@@ -1363,11 +1378,13 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     int64_t *tf = nullptr;
     // row buckets of the toggles (per-polygon path, rows of at most ROW_CAP
     // toggles): each row's distinct positions are found in one wavefront
-    bool rows = false;
+    bool rows = false, seg_path = false;
     uint64_t *rb = nullptr;
     int64_t *rowoff = nullptr;
-    if (NE > 0 && seg_max <= SEG_CAP && rxbits + 2 <= 32) {
+    const int paths_off = g_build_paths_off.load();
+    if (NE > 0 && seg_max <= SEG_CAP && rxbits + 2 <= 32 && !(paths_off & 1)) {
         // per polygon in LDS: sort, coverage and toggle flags in one launch
+        seg_path = true;
         uint64_t *k2 = nullptr;
         uint32_t *v2 = nullptr;
         int32_t *tl = nullptr;
@@ -1402,7 +1419,7 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
         NT = hsc[8];
         herr = (int)(uint32_t)hsc[0];
         if (herr || (NT & 1)) return SBA_EDEVICE;
-        rows = hsc[SC_ROW_MAX] <= ROW_CAP;
+        rows = hsc[SC_ROW_MAX] <= ROW_CAP && !(paths_off & 2);
         if (!rows) RC(B.alloc(&tkey, std::max<int64_t>(NT, 1)));
         if (rows) RC(B.alloc(&rb, std::max<int64_t>(NT, 1)));
         RC(B.alloc(&tpoly, std::max<int64_t>(NT, 1)));
@@ -1498,6 +1515,7 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     B.release(rb);
     B.release(rowoff);
     B.release(rowcnt);
+    g_build_paths_last = (seg_path ? 1 : 0) | (rows ? 2 : 0);
     RC(scan_exclusive_i64(diff, dex, NP, tot + 2, st, &B.ws));
     hipLaunchKernelGGL(k_piece_classify, dim3(grid_for(NP)), dim3(256), 0, st, dex, diff, NP, segc,
                        mm, err);

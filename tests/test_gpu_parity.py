@@ -742,3 +742,50 @@ def test_edge_sizes_of_range_and_partitioned(sba, orc):
         wa = OA.aggregate(xy, vals)
         np.testing.assert_array_equal(c.cpu().numpy().astype(np.uint64), wa[0])
         np.testing.assert_array_equal(s.cpu().numpy(), wa[1])
+
+
+# --------------------------------------------------------------- build paths
+
+@pytest.mark.parametrize("case", ["city_grid", "city_hilbert", "city_centre", "city_boundary",
+                                  "stars_grid"])
+def test_every_build_path_gives_the_oracles_answer(sba, orc, case):
+    """The coverage stages choose between per-polygon work in LDS (each
+    polygon's events sorted and scanned by one workgroup; each row's toggles
+    ranked by one wavefront) and global radix sorts and scans.  Every
+    combination, forced through the debug switch, stores the oracle's cell
+    sets and gives its aggregates; the default takes both LDS paths here."""
+    from gen import city_polygons
+    if case.startswith("city"):
+        polys, eps = city_polygons(), 1000
+        xy, vals = city_points(400_000)
+    else:
+        polys, eps = star_polygons(12, 9, 20.0, 400.0, 1500, 77), 5
+        rng = np.random.default_rng(91)
+        xy = rng.integers(-50, 1600, size=2 * 400_001).astype(np.int32)
+        vals = rng.integers(100, 10000, size=400_001).astype(np.int64)
+    kw = {"kind": "hilbert"} if case == "city_hilbert" else {}
+    okw = {}
+    if case == "city_centre":
+        kw["centre_sampled"] = okw["centre"] = True
+    if case == "city_boundary":
+        kw["boundary_only"] = okw["boundary_only"] = True
+    O = orc.Approx(polys, eps, **okw)
+    want_c, want_s = O.aggregate(xy, vals)
+    got = {}
+    try:
+        for off in (0, 1, 2, 3):
+            assert sba.lib().sba_debug_build_paths(off) == 0
+            A = sba.Approx.from_polygons(polys, eps, **kw)
+            taken = sba.lib().sba_debug_last_build_paths()
+            # bit 2 (row buckets) exists only on the per-polygon path
+            assert taken == {0: 3, 1: 0, 2: 1, 3: 0}[off], (off, taken)
+            c, s = run_agg(A, xy, vals)
+            np.testing.assert_array_equal(c, want_c)
+            np.testing.assert_array_equal(s, want_s)
+            info = A.info()
+            got[off] = {k: info[k] for k in ("n_runs", "n_segments", "n_sets", "n_blocks",
+                                             "n_sub", "bytes")}
+            A.close()
+    finally:
+        sba.lib().sba_debug_build_paths(0)
+    assert all(g == got[0] for g in got.values()), got
