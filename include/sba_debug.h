@@ -54,7 +54,8 @@ int sba_debug_grid16_lsub(int mode);
  * LDS (fused with the coverage step), so that all events take the global
  * radix sort and scans; 2 = bucketing the toggles by row, so that they take
  * the global radix sort.  0 (default) takes each path wherever it applies
- * (polygons of at most 16,384 events, rows of at most 512 toggles).
+ * (builds without a clip window, polygons of at most 16,384 events, rows of
+ * at most 512 toggles).
  * SBA_EINVAL outside 0..3.  For tests of both sides of each choice. */
 int sba_debug_build_paths(int off);
 

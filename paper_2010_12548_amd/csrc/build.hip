@@ -1382,7 +1382,12 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     uint64_t *rb = nullptr;
     int64_t *rowoff = nullptr;
     const int paths_off = g_build_paths_off.load();
-    if (NE > 0 && seg_max <= SEG_CAP && rxbits + 2 <= 32 && !(paths_off & 1)) {
+    // Clip-window builds (viewport queries) keep the global sorts: they run
+    // beside persistent probe kernels that hold most of every compute unit's
+    // wave slots and registers, where the per-polygon workgroups of 1024
+    // lanes would wait for those kernels to end; their event counts are
+    // small, so the global passes cost little there.
+    if (NE > 0 && seg_max <= SEG_CAP && rxbits + 2 <= 32 && !(paths_off & 1) && !B.window) {
         // per polygon in LDS: sort, coverage and toggle flags in one launch
         seg_path = true;
         uint64_t *k2 = nullptr;
