@@ -395,13 +395,66 @@ __global__ __launch_bounds__(SEG_BLOCK) void k_event_seg_sort(EventSegs S, const
     event_seg(S, p, &ib, &nbv, &ic, &ncv, &o0);
     const int n = (int)(nbv + ncv);  // <= cap (checked by the host)
     const uint64_t rxm = (1ull << rxbits) - 1;
-    for (int i = threadIdx.x; i < n; i += SEG_BLOCK) {
-        const int64_t at = i < nbv ? ib + i : ic + (i - nbv);
-        src[i] = (uint32_t)(((evkey[at] & rxm) << 2) | evpay[at]);
+    {
+        // every load of the lane issued before the first LDS store (a
+        // load-store loop would wait for each load in turn)
+        uint64_t kq[SEG_ROUNDS];
+        uint32_t pq[SEG_ROUNDS];
+#pragma unroll
+        for (int q = 0; q < SEG_ROUNDS; q++) {
+            const int i = q * SEG_BLOCK + threadIdx.x;
+            if (i < n) {
+                const int64_t at = i < nbv ? ib + i : ic + (i - nbv);
+                kq[q] = evkey[at];
+                pq[q] = evpay[at];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < SEG_ROUNDS; q++) {
+            const int i = q * SEG_BLOCK + threadIdx.x;
+            if (i < n) src[i] = (uint32_t)(((kq[q] & rxm) << 2) | pq[q]);
+        }
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    const int kbits = rxbits + 2;
+    // the polygon's own row and column range: keys re-based to it need fewer
+    // bits, so fewer passes (a polygon spans a few hundred rows and columns)
+    __shared__ uint32_t rng[4];
+    if (threadIdx.x < 4) rng[threadIdx.x] = (threadIdx.x & 1) ? 0u : 0xffffffffu;
+    __syncthreads();
+    const uint32_t xmask = (1u << xbits) - 1;
+    {
+        uint32_t r0 = 0xffffffffu, r1 = 0, x0 = 0xffffffffu, x1 = 0;
+        for (int i = threadIdx.x; i < n; i += SEG_BLOCK) {
+            const uint32_t rx = src[i] >> 2, r = rx >> xbits, x = rx & xmask;
+            r0 = min(r0, r);
+            r1 = max(r1, r);
+            x0 = min(x0, x);
+            x1 = max(x1, x);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            r0 = min(r0, (uint32_t)__shfl_xor((int)r0, o, 64));
+            r1 = max(r1, (uint32_t)__shfl_xor((int)r1, o, 64));
+            x0 = min(x0, (uint32_t)__shfl_xor((int)x0, o, 64));
+            x1 = max(x1, (uint32_t)__shfl_xor((int)x1, o, 64));
+        }
+        if (lane == 0) {
+            atomicMin(&rng[0], r0);
+            atomicMax(&rng[1], r1);
+            atomicMin(&rng[2], x0);
+            atomicMax(&rng[3], x1);
+        }
+    }
+    __syncthreads();
+    const uint32_t rmin = rng[0], xmin = rng[2];
+    const int xw = n ? 32 - __clz((int)(rng[3] - xmin)) : 0;
+    const int rw = n ? 32 - __clz((int)(rng[1] - rmin)) : 0;
+    for (int i = threadIdx.x; i < n; i += SEG_BLOCK) {
+        const uint32_t v = src[i], rx = v >> 2;
+        src[i] = ((((rx >> xbits) - rmin) << xw | ((rx & xmask) - xmin)) << 2) | (v & 3u);
+    }
+    __syncthreads();
+    const int kbits = n ? rw + xw + 2 : 0;
     for (int shift = 0; shift < kbits; shift += SEG_DBITS) {
         for (int k = threadIdx.x; k < SEG_WAVES * SEG_RADIX; k += SEG_BLOCK) wcnt[k] = 0;
         __syncthreads();
@@ -488,20 +541,20 @@ __global__ __launch_bounds__(SEG_BLOCK) void k_event_seg_sort(EventSegs S, const
     for (int k = 0; k < per; k++) {
         const int i = i0 + k;
         if (i >= n) break;
-        const uint32_t key = src[i] >> 2;
+        const uint32_t key = src[i] >> 2;  // re-based (row, x): row above bit xw
         if (i + 1 < n && (src[i + 1] >> 2) == key) continue;
         int a = i;
         while (a > 0 && (src[a - 1] >> 2) == key) a--;
-        const uint32_t row = key >> xbits;
+        const uint32_t row = key >> xw;
         const uint32_t before =
-            (a > 0 && ((src[a - 1] >> 2) >> xbits) == row) ? cov_of(dst[a - 1]) : 0u;
+            (a > 0 && ((src[a - 1] >> 2) >> xw) == row) ? cov_of(dst[a - 1]) : 0u;
         const uint32_t after = cov_of(dst[i]);
         if ((before > 0) != (after > 0)) {
             fbits |= 1u << k;
             cnt++;
-            if (rowcnt) atomicAdd(rowcnt + row, 1ull);
+            if (rowcnt) atomicAdd(rowcnt + rmin + row, 1ull);
         }
-        if ((i + 1 == n || ((src[i + 1] >> 2) >> xbits) != row) && after != 0) atomicOr(err, 2);
+        if ((i + 1 == n || ((src[i + 1] >> 2) >> xw) != row) && after != 0) atomicOr(err, 2);
     }
     const uint32_t tex = seg_excl_scan(cnt, wsum);
     if (threadIdx.x == SEG_BLOCK - 1) ptot[p] = tex + cnt;
@@ -517,9 +570,11 @@ __global__ __launch_bounds__(SEG_BLOCK) void k_event_seg_sort(EventSegs S, const
     }
     __syncthreads();
     const uint64_t pk = (uint64_t)p << rxbits;
+    const uint32_t lxm = (1u << xw) - 1;
     for (int i = threadIdx.x; i < n; i += SEG_BLOCK) {
-        const uint32_t v = src[i], tl = dst[i];
-        okey[o0 + i] = pk | (uint64_t)(v >> 2);
+        const uint32_t v = src[i], tl = dst[i], key = v >> 2;
+        const uint32_t rx = (((key >> xw) + rmin) << xbits) | ((key & lxm) + xmin);
+        okey[o0 + i] = pk | (uint64_t)rx;
         opay[o0 + i] = (v & 3u) | ((tl >> 31) << 2);
         otl[o0 + i] = (int32_t)(tl & 0x7fffffffu);
     }
@@ -602,7 +657,15 @@ __global__ __launch_bounds__(64 * ROW_WAVES) void k_row_pieces(const uint64_t *r
     const int64_t base = rowoff[r];
     const int c = (int)(rowoff[r + 1] - base);  // <= ROW_CAP (checked by the host)
     uint64_t *w = raw[wv], *s = sorted[wv];
-    for (int i = lane; i < c; i += 64) w[i] = rb[base + i];
+    {
+        uint64_t v[ROW_CAP / 64];
+#pragma unroll
+        for (int q = 0; q < ROW_CAP / 64; q++)
+            if (q * 64 + lane < c) v[q] = rb[base + q * 64 + lane];
+#pragma unroll
+        for (int q = 0; q < ROW_CAP / 64; q++)
+            if (q * 64 + lane < c) w[q * 64 + lane] = v[q];
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
