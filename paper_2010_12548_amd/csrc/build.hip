@@ -606,34 +606,41 @@ __global__ void k_toggle_emit_seg(const uint64_t *key, const uint32_t *pay, cons
 
 // One workgroup: row offsets of the toggle buckets (exclusive scan of
 // rowcnt[0..gh) into rowoff[0..gh], total at rowoff[gh]), the largest row's
-// count into *mx, and rowcnt zeroed again for use as fill counters.
+// count into *mx, and rowcnt zeroed again for use as fill counters.  The
+// rows go by in chunks of one count per lane, the next chunk's counts loaded
+// while the current one is scanned.
 __global__ __launch_bounds__(SEG_BLOCK) void k_row_scan_max(unsigned long long *rowcnt, int64_t gh,
                                                             int64_t *rowoff,
                                                             unsigned long long *mx)
 {
     __shared__ uint32_t wsum[SEG_WAVES];
-    __shared__ unsigned long long smax;
+    __shared__ uint32_t chunk_tot, smax;
     if (threadIdx.x == 0) smax = 0;
-    const int64_t per = (gh + SEG_BLOCK - 1) / SEG_BLOCK;
-    const int64_t r0 = threadIdx.x * per, r1 = min(r0 + per, gh);
-    uint32_t sum = 0;
-    unsigned long long m = 0;
-    for (int64_t r = r0; r < r1; r++) {
-        const unsigned long long c = rowcnt[r];
-        sum += (uint32_t)c;
-        m = c > m ? c : m;
-    }
     __syncthreads();
-    atomicMax(&smax, m);
-    uint32_t run = seg_excl_scan(sum, wsum);
-    for (int64_t r = r0; r < r1; r++) {
-        rowoff[r] = run;
-        run += (uint32_t)rowcnt[r];
-        rowcnt[r] = 0;
+    uint32_t carry = 0, m = 0;
+    uint32_t next = threadIdx.x < gh ? (uint32_t)rowcnt[threadIdx.x] : 0u;
+    for (int64_t c0 = 0; c0 < gh; c0 += SEG_BLOCK) {
+        const int64_t r = c0 + threadIdx.x;
+        const uint32_t cur = next;  // 0 past the last row
+        next = r + SEG_BLOCK < gh ? (uint32_t)rowcnt[r + SEG_BLOCK] : 0u;
+        m = max(m, cur);
+        const uint32_t ex = seg_excl_scan(cur, wsum);
+        if (r < gh) {
+            rowoff[r] = carry + ex;
+            rowcnt[r] = 0;
+        }
+        if (threadIdx.x == SEG_BLOCK - 1) chunk_tot = ex + cur;
+        __syncthreads();
+        carry += chunk_tot;
+        __syncthreads();
     }
-    if (threadIdx.x == SEG_BLOCK - 1) rowoff[gh] = run;
+    for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(&smax, m);
     __syncthreads();
-    if (threadIdx.x == 0) *mx = smax;
+    if (threadIdx.x == 0) {
+        rowoff[gh] = carry;
+        *mx = smax;
+    }
 }
 
 // Rows of at most ROW_CAP toggles: one wavefront per row ranks the row's
@@ -1128,19 +1135,48 @@ __global__ __launch_bounds__(256) void k_block_fill(const int64_t *seg_row_off, 
         int64_t mid = (a + e) >> 1;
         if (seg_x0[mid] <= xa) a = mid + 1; else e = mid;
     }
-    int64_t q = a - 1;  // last segment starting at or before xa (lo-1 if none)
+    const int64_t q0 = a - 1;  // last segment starting at or before xa (lo-1 if none)
     // the run's codes go to registers first and leave in 16-byte stores (a
     // run starts at a multiple of 16 bytes: blocks and rows are multiples of
     // 8 bytes long and runs of 16 codes are 32 or 64 bytes)
     OUT buf[16] __attribute__((aligned(16)));
+    // Segments q0 .. q0 + 3 are loaded at once (no chain of dependent loads
+    // along the row); they cover the run unless segment q0 + 4 starts inside
+    // it, and then the run walks the row's segments one by one.  Segments of
+    // a row are disjoint, so at most one holds a cell.
+    constexpr int W = 4;
+    int32_t wx0[W], wx1[W];
+    uint32_t wc[W];
 #pragma unroll
-    for (int c = 0; c < 16; c++) {
-        if (c >= rlen) break;
-        int32_t x = xa + c;
-        while (q + 1 < hi && seg_x0[q + 1] <= x) q++;
-        uint32_t v = 0;
-        if (x < gw && q >= lo && x < seg_x1[q]) v = seg_code[q];
-        buf[c] = sizeof(OUT) == 2 ? (OUT)short_code(v, np) : (OUT)v;
+    for (int j = 0; j < W; j++) {
+        const int64_t q = q0 + j;
+        const bool in = q >= lo && q < hi;
+        wx0[j] = in ? seg_x0[q] : INT32_MAX;
+        wx1[j] = in ? seg_x1[q] : INT32_MIN;
+        wc[j] = in ? seg_code[q] : 0u;
+    }
+    if (!(q0 + W < hi && seg_x0[q0 + W] < xa + rlen)) {
+#pragma unroll
+        for (int c = 0; c < 16; c++) {
+            if (c >= rlen) break;
+            const int32_t x = xa + c;
+            uint32_t v = 0;
+#pragma unroll
+            for (int j = 0; j < W; j++) v = (wx0[j] <= x && x < wx1[j]) ? wc[j] : v;
+            if (x >= gw) v = 0;
+            buf[c] = sizeof(OUT) == 2 ? (OUT)short_code(v, np) : (OUT)v;
+        }
+    } else {
+        int64_t q = q0;
+#pragma unroll
+        for (int c = 0; c < 16; c++) {
+            if (c >= rlen) break;
+            int32_t x = xa + c;
+            while (q + 1 < hi && seg_x0[q + 1] <= x) q++;
+            uint32_t v = 0;
+            if (x < gw && q >= lo && x < seg_x1[q]) v = seg_code[q];
+            buf[c] = sizeof(OUT) == 2 ? (OUT)short_code(v, np) : (OUT)v;
+        }
     }
     // constant indices only, so buf stays in registers (a dynamically
     // indexed array would be moved to LDS, which the kernel then reserves)

@@ -789,3 +789,21 @@ def test_every_build_path_gives_the_oracles_answer(sba, orc, case):
     finally:
         sba.lib().sba_debug_build_paths(0)
     assert all(g == got[0] for g in got.values()), got
+
+
+@pytest.mark.parametrize("eps", [2000, 2800, 4000, 5500, 8000])
+def test_row_buckets_across_grid_heights(sba, orc, eps):
+    """The toggle row buckets' offsets are scanned in chunks of 1024 rows;
+    grid heights from about 700 to 2,800 rows end those chunks at different
+    places.  Both LDS paths are taken and the answer is the oracle's."""
+    from gen import city_polygons
+    polys = city_polygons()
+    xy, vals = city_points(300_000)
+    want_c, want_s = orc.Approx(polys, eps).aggregate(xy, vals)
+    A = sba.Approx.from_polygons(polys, eps)
+    assert sba.lib().sba_debug_last_build_paths() == 3
+    assert A.info()["gh"] % 1024 != 0
+    c, s = run_agg(A, xy, vals)
+    np.testing.assert_array_equal(c, want_c)
+    np.testing.assert_array_equal(s, want_s)
+    A.close()
