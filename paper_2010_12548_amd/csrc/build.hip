@@ -286,14 +286,17 @@ __global__ void k_emit_cross(const int4 *edges, const int32_t *epoly, int64_t n_
 // order, and further on its crossings.  Ordering them by (polygon, row, x)
 // therefore only needs each polygon's events ordered by (row, x), which one
 // workgroup does in LDS when the polygon has at most SEG_CAP events: the
-// (row, x) key and the 2-bit kind packed in 32 bits, sorted by an LSD radix
-// sort of 7-bit digits over the packed word (the order among events of equal
-// (row, x) is not used: the coverage test reads only whole groups).  The
+// (row, x) key, re-based to the polygon's own row and column range, and the
+// 2-bit kind packed in 32 bits, sorted by an LSD radix sort of 7-bit digits
+// over the packed word (the order among events of equal (row, x) is not
+// used: the coverage test reads only whole groups).  The
 // polygon's sorted events land where a sort of all events by (polygon, row,
 // x) puts them: after the events of the polygons before it.  The same
 // workgroup then takes the coverage step for its polygon: the prefix sums of
-// the event values over the polygon (its rows are balanced, so this equals
-// the prefix over all events), each (row, x) group's toggle flag, and the
+// the event values over the polygon (the rows before any event are balanced:
+// matched starts and ends, an even number of crossings, so this gives the
+// same coverage as the prefix over all events), each (row, x) group's toggle
+// flag, and the
 // toggle's index among the polygon's toggles; a scan of the per-polygon
 // toggle counts places every toggle.
 
