@@ -49,18 +49,20 @@ int sba_debug_grid16_sets(int mode);
  * Process-wide; for comparison runs and tests of both paths. */
 int sba_debug_grid16_lsub(int mode);
 
-/* Build paths of the coverage stages, process-wide, read at build time.
- * Bits set in `off` turn a path off: 1 = sorting each polygon's events in
- * LDS (fused with the coverage step), so that all events take the global
- * radix sort and scans; 2 = bucketing the toggles by row, so that they take
- * the global radix sort.  0 (default) takes each path wherever it applies
- * (builds without a clip window, polygons of at most 16,384 events, rows of
- * at most 512 toggles).
- * SBA_EINVAL outside 0..3.  For tests of both sides of each choice. */
+/* Build paths, process-wide, read at build time.  Bits set in `off` turn a
+ * path off: 1 = sorting each polygon's events in LDS (fused with the
+ * coverage step), so that all events take the global radix sort and scans;
+ * 2 = bucketing the toggles by row, so that they take the global radix sort;
+ * 4 = collecting the distinct polygon sets through a hash table and numbering
+ * them in one workgroup, so that all multi-polygon segments take the global
+ * radix sort.  0 (default) takes each path wherever it applies (builds
+ * without a clip window, polygons of at most 16,384 events, rows of at most
+ * 512 toggles; set keys below 2^31 and at most 8,192 distinct sets).
+ * SBA_EINVAL outside 0..7.  For tests of both sides of each choice. */
 int sba_debug_build_paths(int off);
 
 /* The paths the last build in the process took, same bits (1: per-polygon
- * event sort, 2: toggle row buckets).  Test support. */
+ * event sort, 2: toggle row buckets, 4: hashed set table).  Test support. */
 int sba_debug_last_build_paths(void);
 
 /* 1: grid builds store the 32-bit format (directory read from global memory

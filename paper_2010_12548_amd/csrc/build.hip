@@ -374,102 +374,32 @@ __device__ __forceinline__ uint32_t ev_word(uint32_t kind)
 
 __device__ __forceinline__ uint32_t cov_of(uint32_t P) { return (P & 0x7fffffffu) + (P >> 31); }
 
-// one workgroup per polygon; dynamic LDS: two buffers of `cap` words (the
-// largest polygon's event count rounded up to whole waves' rounds, at most
-// SEG_CAP) and the per-wave digit counts.  Out: the sorted events (kind in
-// bits 0-1 of opay, bit 2 set on a toggle), each event's index among the
-// polygon's toggles before it (otl), the polygon's toggle count (ptot[p]),
-// and error bit 2 when a row ends inside the polygon
-__global__ __launch_bounds__(SEG_BLOCK) void k_event_seg_sort(EventSegs S, const uint64_t *evkey,
-                                                              const uint32_t *evpay, int rxbits,
-                                                              int xbits, int cap, uint64_t *okey,
-                                                              uint32_t *opay, int32_t *otl,
-                                                              int64_t *ptot, int *err,
-                                                              unsigned long long *rowcnt)
+// Stable LSD radix sort, by one workgroup of SEG_BLOCK lanes, of n <= SEG_CAP
+// 32-bit words in LDS by their bits [0, kbits): 7-bit digits; wave w ranks
+// its own rpw x 64 consecutive words (rpw = the fewest rounds that spread
+// the words over every wave), 64 at a time, equal digits finding each other
+// with SEG_DBITS ballots.  The words end in *src (the two buffers swap once
+// per pass); wcnt holds SEG_WAVES x SEG_RADIX counters.
+__device__ __forceinline__ void lds_radix_u32(uint32_t *&src, uint32_t *&dst, int n, int kbits,
+                                              uint32_t *wcnt, uint32_t *doff, uint32_t *wtot)
 {
-    extern __shared__ uint32_t seg_lds[];
-    uint32_t *src = seg_lds, *dst = seg_lds + cap;
-    uint32_t *wcnt = seg_lds + 2 * cap;  // [SEG_WAVES][SEG_RADIX]
-    __shared__ uint32_t doff[SEG_RADIX];
-    __shared__ uint32_t wtot[SEG_RADIX / 64];
-    __shared__ uint32_t wsum[SEG_WAVES];
-    const int p = blockIdx.x;
-    int64_t ib, nbv, ic, ncv, o0;
-    event_seg(S, p, &ib, &nbv, &ic, &ncv, &o0);
-    const int n = (int)(nbv + ncv);  // <= cap (checked by the host)
-    const uint64_t rxm = (1ull << rxbits) - 1;
-    {
-        // every load of the lane issued before the first LDS store (a
-        // load-store loop would wait for each load in turn)
-        uint64_t kq[SEG_ROUNDS];
-        uint32_t pq[SEG_ROUNDS];
-#pragma unroll
-        for (int q = 0; q < SEG_ROUNDS; q++) {
-            const int i = q * SEG_BLOCK + threadIdx.x;
-            if (i < n) {
-                const int64_t at = i < nbv ? ib + i : ic + (i - nbv);
-                kq[q] = evkey[at];
-                pq[q] = evpay[at];
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < SEG_ROUNDS; q++) {
-            const int i = q * SEG_BLOCK + threadIdx.x;
-            if (i < n) src[i] = (uint32_t)(((kq[q] & rxm) << 2) | pq[q]);
-        }
-    }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    // the polygon's own row and column range: keys re-based to it need fewer
-    // bits, so fewer passes (a polygon spans a few hundred rows and columns)
-    __shared__ uint32_t rng[4];
-    if (threadIdx.x < 4) rng[threadIdx.x] = (threadIdx.x & 1) ? 0u : 0xffffffffu;
-    __syncthreads();
-    const uint32_t xmask = (1u << xbits) - 1;
-    {
-        uint32_t r0 = 0xffffffffu, r1 = 0, x0 = 0xffffffffu, x1 = 0;
-        for (int i = threadIdx.x; i < n; i += SEG_BLOCK) {
-            const uint32_t rx = src[i] >> 2, r = rx >> xbits, x = rx & xmask;
-            r0 = min(r0, r);
-            r1 = max(r1, r);
-            x0 = min(x0, x);
-            x1 = max(x1, x);
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-            r0 = min(r0, (uint32_t)__shfl_xor((int)r0, o, 64));
-            r1 = max(r1, (uint32_t)__shfl_xor((int)r1, o, 64));
-            x0 = min(x0, (uint32_t)__shfl_xor((int)x0, o, 64));
-            x1 = max(x1, (uint32_t)__shfl_xor((int)x1, o, 64));
-        }
-        if (lane == 0) {
-            atomicMin(&rng[0], r0);
-            atomicMax(&rng[1], r1);
-            atomicMin(&rng[2], x0);
-            atomicMax(&rng[3], x1);
-        }
-    }
-    __syncthreads();
-    const uint32_t rmin = rng[0], xmin = rng[2];
-    const int xw = n ? 32 - __clz((int)(rng[3] - xmin)) : 0;
-    const int rw = n ? 32 - __clz((int)(rng[1] - rmin)) : 0;
-    for (int i = threadIdx.x; i < n; i += SEG_BLOCK) {
-        const uint32_t v = src[i], rx = v >> 2;
-        src[i] = ((((rx >> xbits) - rmin) << xw | ((rx & xmask) - xmin)) << 2) | (v & 3u);
-    }
-    __syncthreads();
-    const int kbits = n ? rw + xw + 2 : 0;
+    const int rpw = (n + SEG_BLOCK - 1) / SEG_BLOCK;  // <= SEG_ROUNDS
+    const int wbase = w * 64 * rpw;
     for (int shift = 0; shift < kbits; shift += SEG_DBITS) {
         for (int k = threadIdx.x; k < SEG_WAVES * SEG_RADIX; k += SEG_BLOCK) wcnt[k] = 0;
         __syncthreads();
-        // wave w ranks its own SEG_ROUNDS x 64 consecutive words, 64 at a
-        // time: equal digits find each other with SEG_DBITS ballots, so the
-        // order is stable
+        // wave w ranks its own rpw x 64 consecutive words, 64 at a time:
+        // equal digits find each other with SEG_DBITS ballots, so the order
+        // is stable
         uint32_t kk[SEG_ROUNDS], loc[SEG_ROUNDS];
 #pragma unroll
         for (int q = 0; q < SEG_ROUNDS; q++) {
-            // rounds past the polygon's events are skipped (uniform per wave)
-            if (w * (64 * SEG_ROUNDS) + q * 64 >= n) break;
-            const int idx = w * (64 * SEG_ROUNDS) + q * 64 + lane;
+            // rounds past the wave's share or past the words are skipped
+            // (uniform per wave)
+            if (q >= rpw || wbase + q * 64 >= n) break;
+            const int idx = wbase + q * 64 + lane;
             const bool valid = idx < n;
             const uint32_t key = valid ? src[idx] : 0u;
             kk[q] = key;
@@ -515,8 +445,8 @@ __global__ __launch_bounds__(SEG_BLOCK) void k_event_seg_sort(EventSegs S, const
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < SEG_ROUNDS; q++) {
-            const int idx = w * (64 * SEG_ROUNDS) + q * 64 + lane;
-            if (idx < n) {
+            const int idx = wbase + q * 64 + lane;
+            if (q < rpw && idx < n) {
                 const uint32_t d = (kk[q] >> shift) & (SEG_RADIX - 1);
                 dst[doff[d] + wcnt[w * SEG_RADIX + d] + loc[q]] = kk[q];
             }
@@ -526,6 +456,92 @@ __global__ __launch_bounds__(SEG_BLOCK) void k_event_seg_sort(EventSegs S, const
         src = dst;
         dst = t;
     }
+}
+
+// one workgroup per polygon; dynamic LDS: two buffers of `cap` words (the
+// largest polygon's event count rounded up to whole waves' rounds, at most
+// SEG_CAP) and the per-wave digit counts.  Out: the sorted events (kind in
+// bits 0-1 of opay, bit 2 set on a toggle), each event's index among the
+// polygon's toggles before it (otl), the polygon's toggle count (ptot[p]),
+// and error bit 2 when a row ends inside the polygon
+__global__ __launch_bounds__(SEG_BLOCK) void k_event_seg_sort(EventSegs S, const uint64_t *evkey,
+                                                              const uint32_t *evpay, int rxbits,
+                                                              int xbits, int cap, uint64_t *okey,
+                                                              uint32_t *opay, int32_t *otl,
+                                                              int64_t *ptot, int *err,
+                                                              unsigned long long *rowcnt)
+{
+    extern __shared__ uint32_t seg_lds[];
+    uint32_t *src = seg_lds, *dst = seg_lds + cap;
+    uint32_t *wcnt = seg_lds + 2 * cap;  // [SEG_WAVES][SEG_RADIX]
+    __shared__ uint32_t doff[SEG_RADIX];
+    __shared__ uint32_t wtot[SEG_RADIX / 64];
+    __shared__ uint32_t wsum[SEG_WAVES];
+    const int p = blockIdx.x;
+    int64_t ib, nbv, ic, ncv, o0;
+    event_seg(S, p, &ib, &nbv, &ic, &ncv, &o0);
+    const int n = (int)(nbv + ncv);  // <= cap (checked by the host)
+    const uint64_t rxm = (1ull << rxbits) - 1;
+    {
+        // every load of the lane issued before the first LDS store (a
+        // load-store loop would wait for each load in turn)
+        uint64_t kq[SEG_ROUNDS];
+        uint32_t pq[SEG_ROUNDS];
+#pragma unroll
+        for (int q = 0; q < SEG_ROUNDS; q++) {
+            const int i = q * SEG_BLOCK + threadIdx.x;
+            if (i < n) {
+                const int64_t at = i < nbv ? ib + i : ic + (i - nbv);
+                kq[q] = evkey[at];
+                pq[q] = evpay[at];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < SEG_ROUNDS; q++) {
+            const int i = q * SEG_BLOCK + threadIdx.x;
+            if (i < n) src[i] = (uint32_t)(((kq[q] & rxm) << 2) | pq[q]);
+        }
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // the polygon's own row and column range: keys re-based to it need fewer
+    // bits, so fewer passes (a polygon spans a few hundred rows and columns)
+    __shared__ uint32_t rng[4];
+    if (threadIdx.x < 4) rng[threadIdx.x] = (threadIdx.x & 1) ? 0u : 0xffffffffu;
+    __syncthreads();
+    const uint32_t xmask = (1u << xbits) - 1;
+    {
+        uint32_t r0 = 0xffffffffu, r1 = 0, x0 = 0xffffffffu, x1 = 0;
+        for (int i = threadIdx.x; i < n; i += SEG_BLOCK) {
+            const uint32_t rx = src[i] >> 2, r = rx >> xbits, x = rx & xmask;
+            r0 = min(r0, r);
+            r1 = max(r1, r);
+            x0 = min(x0, x);
+            x1 = max(x1, x);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            r0 = min(r0, (uint32_t)__shfl_xor((int)r0, o, 64));
+            r1 = max(r1, (uint32_t)__shfl_xor((int)r1, o, 64));
+            x0 = min(x0, (uint32_t)__shfl_xor((int)x0, o, 64));
+            x1 = max(x1, (uint32_t)__shfl_xor((int)x1, o, 64));
+        }
+        if (lane == 0) {
+            atomicMin(&rng[0], r0);
+            atomicMax(&rng[1], r1);
+            atomicMin(&rng[2], x0);
+            atomicMax(&rng[3], x1);
+        }
+    }
+    __syncthreads();
+    const uint32_t rmin = rng[0], xmin = rng[2];
+    const int xw = n ? 32 - __clz((int)(rng[3] - xmin)) : 0;
+    const int rw = n ? 32 - __clz((int)(rng[1] - rmin)) : 0;
+    for (int i = threadIdx.x; i < n; i += SEG_BLOCK) {
+        const uint32_t v = src[i], rx = v >> 2;
+        src[i] = ((((rx >> xbits) - rmin) << xw | ((rx & xmask) - xmin)) << 2) | (v & 3u);
+    }
+    __syncthreads();
+    const int kbits = n ? rw + xw + 2 : 0;
+    lds_radix_u32(src, dst, n, kbits, wcnt, doff, wtot);
     // coverage: each lane takes `per` consecutive sorted events; dst gets
     // the inclusive prefix words
     const int per = (n + SEG_BLOCK - 1) / SEG_BLOCK;
@@ -987,6 +1003,136 @@ __global__ void k_set_fill(const uint64_t *key, const uint32_t *val, const int64
     seg_code[multi_seg[m]] = CODE_SET_BASE + (uint32_t)g;
 }
 
+// Sets of at most SET_CAP distinct keys (keys below 2^31) take a shorter
+// path than the global sort of all NM keys: a hash table collects the
+// distinct keys (each first insert appends its key to a list), one workgroup
+// sorts the list in LDS, numbers the sets in key order (the numbering the
+// global sort gives), lays out and fills the set table and records each
+// key's number in a table beside the hash, and one lookup per multi segment
+// writes its code.
+#define SET_CAP 8192
+#define SET_EMPTY 0xffffffffu
+
+__device__ __forceinline__ uint32_t set_slot(uint32_t k, int hb)
+{
+    return (k * 2654435761u) >> (32 - hb);
+}
+
+__global__ void k_set_insert(const uint64_t *key, int64_t n, uint32_t *tab, int hb,
+                             uint32_t *list, unsigned long long *cnt)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    const uint32_t k = (uint32_t)key[m], mask = (1u << hb) - 1u;
+    // neighbouring multi segments mostly share their set: only the first of
+    // a run of equal keys inserts it
+    if (m > 0 && (uint32_t)key[m - 1] == k) return;
+    uint32_t s = set_slot(k, hb);
+    // the table has at least twice as many slots as keys: a free slot is
+    // always ahead; a slot already holding the key is seen without an atomic
+    while (true) {
+        const uint32_t seen = tab[s];
+        if (seen == k) return;
+        if (seen != SET_EMPTY) {
+            s = (s + 1) & mask;
+            continue;
+        }
+        const uint32_t prev = atomicCAS(tab + s, SET_EMPTY, k);
+        if (prev == SET_EMPTY) {
+            const unsigned long long at = atomicAdd(cnt, 1ull);
+            if (at < SET_CAP) list[at] = k;
+            return;
+        }
+        if (prev == k) return;
+        s = (s + 1) & mask;
+    }
+}
+
+__device__ __forceinline__ uint32_t set_find(const uint32_t *tab, uint32_t k, int hb)
+{
+    const uint32_t mask = (1u << hb) - 1u;
+    uint32_t s = set_slot(k, hb);
+    while (tab[s] != k) s = (s + 1) & mask;
+    return s;
+}
+
+// members of the set with key k: fb-bit fields of id + 1 (ascending ids) for
+// sets of 2 or 3, else the members of multi segment k - 2^(3 fb)
+__device__ __forceinline__ int64_t set_members(uint32_t k, int fb, const int64_t *multi_mem,
+                                               int64_t n_multi, int64_t n_mem, int64_t *a)
+{
+    if (k < (1u << (3 * fb))) {
+        const uint32_t fm = (1u << fb) - 1u;
+        *a = -1;
+        return ((k & fm) != 0) + (((k >> fb) & fm) != 0) + (((k >> (2 * fb)) & fm) != 0);
+    }
+    const int64_t m = (int64_t)(k - (1u << (3 * fb)));
+    *a = multi_mem[m];
+    return ((m + 1 < n_multi) ? multi_mem[m + 1] : n_mem) - *a;
+}
+
+// one workgroup; dynamic LDS: two buffers of SET_CAP words and the digit
+// counters.  Leaves at once when the list overflowed (the host then takes
+// the global sort).  Out: set_off[0..nd], set_ids, rank[slot] for every
+// key's slot, *nids = the total member count.
+__global__ __launch_bounds__(SEG_BLOCK) void k_set_table(const uint32_t *list,
+                                                         const unsigned long long *cnt,
+                                                         const uint32_t *tab, int hb, int kbits,
+                                                         int fb, const int64_t *multi_mem,
+                                                         int64_t n_multi, int64_t n_mem,
+                                                         const int32_t *mem_ids, uint32_t *rank,
+                                                         int64_t *set_off, int32_t *set_ids,
+                                                         unsigned long long *nids)
+{
+    extern __shared__ uint32_t set_lds[];
+    uint32_t *src = set_lds, *dst = set_lds + SET_CAP;
+    uint32_t *wcnt = set_lds + 2 * SET_CAP;
+    __shared__ uint32_t doff[SEG_RADIX];
+    __shared__ uint32_t wtot[SEG_RADIX / 64];
+    __shared__ uint32_t wsum[SEG_WAVES];
+    const unsigned long long nd = *cnt;
+    if (nd > SET_CAP) return;
+    const int n = (int)nd;
+    for (int i = threadIdx.x; i < n; i += SEG_BLOCK) src[i] = list[i];
+    __syncthreads();
+    lds_radix_u32(src, dst, n, kbits, wcnt, doff, wtot);
+    // set r = src[r]: sizes, offsets (each lane `per` consecutive sets)
+    const int per = (n + SEG_BLOCK - 1) / SEG_BLOCK;
+    const int i0 = threadIdx.x * per, i1 = min(i0 + per, n);
+    uint32_t sum = 0;
+    int64_t a;
+    for (int i = i0; i < i1; i++) sum += (uint32_t)set_members(src[i], fb, multi_mem, n_multi, n_mem, &a);
+    uint32_t off = seg_excl_scan(sum, wsum);
+    for (int i = i0; i < i1; i++) {
+        const uint32_t k = src[i];
+        const int64_t c = set_members(k, fb, multi_mem, n_multi, n_mem, &a);
+        set_off[i] = off;
+        if (a < 0) {
+            const uint32_t fm = (1u << fb) - 1u;
+            for (int64_t t = 0; t < c; t++) set_ids[off + t] = (int32_t)(((k >> (fb * t)) & fm) - 1);
+        } else {
+            for (int64_t t = 0; t < c; t++) set_ids[off + t] = mem_ids[a + t];
+        }
+        rank[set_find(tab, k, hb)] = (uint32_t)i;
+        off += (uint32_t)c;
+    }
+    if (threadIdx.x == SEG_BLOCK - 1) {
+        set_off[n] = off;
+        *nids = off;
+    }
+}
+
+// code of every multi segment: its key's set number
+__global__ void k_set_codes(const uint64_t *key, int64_t n, const unsigned long long *cnt,
+                            const uint32_t *tab, int hb, const uint32_t *rank,
+                            const int64_t *multi_seg, uint32_t *seg_code)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n || *cnt > SET_CAP) return;
+    const uint32_t g = rank[set_find(tab, (uint32_t)key[m], hb)];
+    seg_code[multi_seg[m]] = CODE_SET_BASE + g;
+}
+
 // ------------------------------------------------ segment lookups
 
 __device__ __forceinline__ uint32_t seg_code_at(const int64_t *seg_row_off, const int32_t *seg_x0,
@@ -1307,13 +1453,14 @@ int key_grid_launch(const sba_polygons *sets, int32_t n_sets, int64_t eps, hipSt
 }
 
 // paths of the coverage stages: bits set in g_build_paths_off turn a path
-// off (1: the per-polygon event sort, 2: the toggle row buckets); the last
-// build's paths taken, same bits (tests of both sides of each choice)
+// off (1: the per-polygon event sort, 2: the toggle row buckets, 4: the set
+// table through a hash); the last build's paths taken, same bits (tests of
+// both sides of each choice)
 static std::atomic<int> g_build_paths_off{0}, g_build_paths_last{0};
 
 extern "C" int sba_debug_build_paths(int off)
 {
-    if (off < 0 || off > 3) return SBA_EINVAL;
+    if (off < 0 || off > 7) return SBA_EINVAL;
     g_build_paths_off = off;
     return 0;
 }
@@ -1677,49 +1824,90 @@ int build_segments(const sba_polygons *polys, int64_t eps, hipStream_t st, sba_h
     // 5: deduplicate the sets of multi-polygon segments
     h->n_sets = 0;
     h->n_set_ids = 0;
+    bool set_path = false;
     if (NM > 0) {
         uint64_t *mkey = nullptr;
         uint32_t *mval = nullptr;
-        int64_t *g = nullptr, *set_sz = nullptr;
         RC(B.alloc(&mkey, NM));
         RC(B.alloc(&mval, NM));
-        RC(B.alloc(&g, NM + 1));
         const int fb = std::min(pbits + 1, 21);  // ids + 1 < 2^21
         const int kbits = std::max(3 * fb + 1, bits_for(((uint64_t)1 << (3 * fb)) | (uint64_t)NM));
         if (kbits > 64) return SBA_ELIMIT;
         hipLaunchKernelGGL(k_multi_keys, dim3(grid_for(NM)), dim3(256), 0, st, multi_mem, NM, NMEM,
                            mem_ids, fb, mkey, mval);
         HIP_OK(hipGetLastError());
-        RC(radix_sort_u64_ws(&mkey, &mval, NM, kbits, B.ws));
-        hipLaunchKernelGGL(k_flag_new, dim3(grid_for(NM)), dim3(256), 0, st, mkey, NM, g);
-        HIP_OK(hipGetLastError());
-        RC(scan_exclusive_i64(g, g, NM, tot, st, &B.ws));
         // sizes are bounded by the multi segments (NM sets, NMEM ids), so the
         // set table is laid out before its counts reach the host
-        RC(B.alloc(&set_sz, NM + 1));
-        HIP_OK(hipMemsetAsync(set_sz, 0, sizeof(int64_t) * (NM + 1), st));
-        hipLaunchKernelGGL(k_set_sizes, dim3(grid_for(NM)), dim3(256), 0, st, mkey, mval, g, NM,
-                           multi_mem, NM, NMEM, set_sz);
-        HIP_OK(hipGetLastError());
         RC(handle_alloc(h, &h->set_off, NM + 1));
-        RC(scan_exclusive_i64(set_sz, h->set_off, NM, h->set_off + NM, st, &B.ws));
         RC(handle_alloc(h, &h->set_ids, NMEM));
-        hipLaunchKernelGGL(k_set_fill, dim3(grid_for(NM)), dim3(256), 0, st, mkey, mval, g, NM,
-                           multi_mem, NM, NMEM, mem_ids, h->set_off, h->set_ids, multi_seg,
-                           B.seg_code);
-        HIP_OK(hipGetLastError());
-        int64_t nids = 0;
-        RC(B.ws.read(hsc, B.sc, sizeof(hsc)));
-        RC(B.ws.read(&nids, h->set_off + NM, sizeof(int64_t)));
-        RC(B.ws.sync());
-        const int64_t nsets = hsc[8];
-        h->n_sets = nsets;
-        h->n_set_ids = nids;
+        if (kbits <= 31 && !(g_build_paths_off.load() & 4)) {
+            // distinct keys through a hash table, sorted by one workgroup
+            int hb = 1;
+            while (((int64_t)1 << hb) < 2 * NM) hb++;
+            if (hb > 31) return SBA_ELIMIT;
+            uint32_t *tab = nullptr, *rank = nullptr, *list = nullptr;
+            RC(B.alloc(&tab, (int64_t)1 << hb));
+            RC(B.alloc(&rank, (int64_t)1 << hb));
+            RC(B.alloc(&list, SET_CAP));
+            HIP_OK(hipMemsetAsync(tab, 0xff, sizeof(uint32_t) << hb, st));
+            unsigned long long *nd = (unsigned long long *)(B.sc + SC_SET_N);
+            unsigned long long *nids = (unsigned long long *)(B.sc + SC_SET_IDS);
+            hipLaunchKernelGGL(k_set_insert, dim3(grid_for(NM)), dim3(256), 0, st, mkey, NM, tab, hb,
+                               list, nd);
+            HIP_OK(hipGetLastError());
+            constexpr int lds = (2 * SET_CAP + SEG_WAVES * SEG_RADIX) * (int)sizeof(uint32_t);
+            (void)hipFuncSetAttribute((const void *)k_set_table,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            (void)hipGetLastError();
+            hipLaunchKernelGGL(k_set_table, dim3(1), dim3(SEG_BLOCK), lds, st, list, nd, tab, hb,
+                               kbits, fb, multi_mem, NM, NMEM, mem_ids, rank, h->set_off,
+                               h->set_ids, nids);
+            HIP_OK(hipGetLastError());
+            hipLaunchKernelGGL(k_set_codes, dim3(grid_for(NM)), dim3(256), 0, st, mkey, NM, nd, tab,
+                               hb, rank, multi_seg, B.seg_code);
+            HIP_OK(hipGetLastError());
+            RC(B.ws.read(hsc, B.sc, sizeof(hsc)));
+            RC(B.ws.sync());
+            B.release(tab);
+            B.release(rank);
+            B.release(list);
+            if (hsc[SC_SET_N] <= SET_CAP) {
+                set_path = true;
+                h->n_sets = hsc[SC_SET_N];
+                h->n_set_ids = hsc[SC_SET_IDS];
+            }
+        }
+        if (!set_path) {
+            // all keys through the global radix sort
+            int64_t *g = nullptr, *set_sz = nullptr;
+            RC(B.alloc(&g, NM + 1));
+            RC(radix_sort_u64_ws(&mkey, &mval, NM, kbits, B.ws));
+            hipLaunchKernelGGL(k_flag_new, dim3(grid_for(NM)), dim3(256), 0, st, mkey, NM, g);
+            HIP_OK(hipGetLastError());
+            RC(scan_exclusive_i64(g, g, NM, tot, st, &B.ws));
+            RC(B.alloc(&set_sz, NM + 1));
+            HIP_OK(hipMemsetAsync(set_sz, 0, sizeof(int64_t) * (NM + 1), st));
+            hipLaunchKernelGGL(k_set_sizes, dim3(grid_for(NM)), dim3(256), 0, st, mkey, mval, g, NM,
+                               multi_mem, NM, NMEM, set_sz);
+            HIP_OK(hipGetLastError());
+            RC(scan_exclusive_i64(set_sz, h->set_off, NM, h->set_off + NM, st, &B.ws));
+            hipLaunchKernelGGL(k_set_fill, dim3(grid_for(NM)), dim3(256), 0, st, mkey, mval, g, NM,
+                               multi_mem, NM, NMEM, mem_ids, h->set_off, h->set_ids, multi_seg,
+                               B.seg_code);
+            HIP_OK(hipGetLastError());
+            int64_t nids = 0;
+            RC(B.ws.read(hsc, B.sc, sizeof(hsc)));
+            RC(B.ws.read(&nids, h->set_off + NM, sizeof(int64_t)));
+            RC(B.ws.sync());
+            h->n_sets = hsc[8];
+            h->n_set_ids = nids;
+            B.release(g);
+            B.release(set_sz);
+        }
         B.release(mkey);
         B.release(mval);
-        B.release(g);
-        B.release(set_sz);
     }
+    g_build_paths_last = g_build_paths_last.load() | (set_path ? 4 : 0);
     B.release(multi_seg);
     B.release(multi_mem);
     B.release(mem_ids);

@@ -13,6 +13,9 @@
 #define SC_SEG_MAX 14
 // slot of the largest row's toggle count (read with the toggle total)
 #define SC_ROW_MAX 15
+// slots of the set table path: distinct sets, total member ids
+#define SC_SET_N 18
+#define SC_SET_IDS 19
 
 struct BuildState {
     explicit BuildState(hipStream_t s) : st(s), ws(s) {}

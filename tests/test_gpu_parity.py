@@ -749,11 +749,13 @@ def test_edge_sizes_of_range_and_partitioned(sba, orc):
 @pytest.mark.parametrize("case", ["city_grid", "city_hilbert", "city_centre", "city_boundary",
                                   "stars_grid"])
 def test_every_build_path_gives_the_oracles_answer(sba, orc, case):
-    """The coverage stages choose between per-polygon work in LDS (each
-    polygon's events sorted and scanned by one workgroup; each row's toggles
-    ranked by one wavefront) and global radix sorts and scans.  Every
-    combination, forced through the debug switch, stores the oracle's cell
-    sets and gives its aggregates; the default takes both LDS paths here."""
+    """The build stages choose between work in LDS (each polygon's events
+    sorted and scanned by one workgroup; each row's toggles ranked by one
+    wavefront; the distinct polygon sets collected by a hash and numbered by
+    one workgroup) and global radix sorts and scans.  Every combination,
+    forced through the debug switch, stores the oracle's cell sets and gives
+    its aggregates with the same structures; the default takes every LDS path
+    here."""
     from gen import city_polygons
     if case.startswith("city"):
         polys, eps = city_polygons(), 1000
@@ -773,12 +775,14 @@ def test_every_build_path_gives_the_oracles_answer(sba, orc, case):
     want_c, want_s = O.aggregate(xy, vals)
     got = {}
     try:
-        for off in (0, 1, 2, 3):
+        for off in range(8):
             assert sba.lib().sba_debug_build_paths(off) == 0
             A = sba.Approx.from_polygons(polys, eps, **kw)
             taken = sba.lib().sba_debug_last_build_paths()
-            # bit 2 (row buckets) exists only on the per-polygon path
-            assert taken == {0: 3, 1: 0, 2: 1, 3: 0}[off], (off, taken)
+            # bit 2 (row buckets) exists only on the per-polygon path; bit 4
+            # (hashed set table) wherever there are polygon sets
+            assert taken & 3 == {0: 3, 1: 0, 2: 1, 3: 0}[off & 3], (off, taken)
+            assert bool(taken & 4) == (not off & 4 and A.info()["n_sets"] > 0), (off, taken)
             c, s = run_agg(A, xy, vals)
             np.testing.assert_array_equal(c, want_c)
             np.testing.assert_array_equal(s, want_s)
@@ -801,7 +805,7 @@ def test_row_buckets_across_grid_heights(sba, orc, eps):
     xy, vals = city_points(300_000)
     want_c, want_s = orc.Approx(polys, eps).aggregate(xy, vals)
     A = sba.Approx.from_polygons(polys, eps)
-    assert sba.lib().sba_debug_last_build_paths() == 3
+    assert sba.lib().sba_debug_last_build_paths() & 3 == 3
     assert A.info()["gh"] % 1024 != 0
     c, s = run_agg(A, xy, vals)
     np.testing.assert_array_equal(c, want_c)
