@@ -811,3 +811,31 @@ def test_row_buckets_across_grid_heights(sba, orc, eps):
     np.testing.assert_array_equal(c, want_c)
     np.testing.assert_array_equal(s, want_s)
     A.close()
+
+
+def test_more_polygon_sets_than_the_hashed_table_takes(sba, orc):
+    """500 overlapping stars at eps 5 make about 14,700 distinct polygon sets
+    (at most 13 polygons on a cell), more than the one-workgroup set table
+    sorts (8,192): the build finds that at its readback and takes the global
+    sort instead, with the oracle's answer."""
+    polys = star_polygons(500, 12, 40.0, 200.0, 2000, 5)
+    eps = 5
+    O = orc.Approx(polys, eps)
+    rng = np.random.default_rng(55)
+    n = 300_001
+    xy = rng.integers(-50, 2050, size=2 * n).astype(np.int32)
+    vals = rng.integers(100, 10000, size=n).astype(np.int64)
+    want_c, want_s = O.aggregate(xy, vals)
+    A = sba.Approx.from_polygons(polys, eps)
+    assert A.info()["n_sets"] > 8192
+    assert not sba.lib().sba_debug_last_build_paths() & 4
+    c, s = run_agg(A, xy, vals)
+    np.testing.assert_array_equal(c, want_c)
+    np.testing.assert_array_equal(s, want_s)
+    i0, j0, nw, nh = window_of(polys, O.s, pad=1)
+    cells = [(i0 + i, j0 + j) for j in range(0, nh, 7) for i in range(0, nw, 7)]
+    want = expected_sets(O, polys.n_polys, i0, j0, nw, nh)
+    got = gpu_sets(A, cells)
+    bad = [k for k in cells if got[k] != want[k]]
+    assert not bad, (len(bad), bad[:5])
+    A.close()
